@@ -1,0 +1,196 @@
+/*
+ * asora.h -- C ABI of the MI355X (gfx950) ASORA ray-tracing library.
+ *
+ * The library computes, for a set of point sources on a periodic cubic grid,
+ * the hydrogen photoionization rate Gamma of every cell (eq. gamma / eq. sugg
+ * of Section 2.2, summed over sources as in the multi-source paragraph of
+ * Section 2.2), with the neutral-hydrogen column densities obtained by short
+ * characteristics (Section 3.1) swept outward in octahedral shells
+ * (Section 3.3, Appendix A), and the adjoint of that map.
+ *
+ * Conventions shared by every entry point:
+ *   - Grids are N^3, C order [i][j][k] with k fastest, cell index
+ *     (i*N + j)*N + k.  Units: cm, cm^-3, photons/s, s^-1, cm^-2.
+ *   - "device" pointers are HIP device memory of the device given to
+ *     asora_init; "host" pointers are ordinary host memory.  The caller owns
+ *     every buffer it passes; the library only reads inputs and writes outputs
+ *     and keeps no reference after the call returns.  The library owns its
+ *     context, copies of the tables and its scratch memory.
+ *   - Work is enqueued on the HIP stream passed as `stream` (a hipStream_t;
+ *     NULL = the default stream) and is asynchronous: outputs are valid once
+ *     that stream has reached the call.  A context must not be used from two
+ *     streams or threads at the same time.
+ *   - Argument errors are detected before anything is enqueued and returned
+ *     as ASORA_EINVAL; nothing is written then.  Errors seen by the kernels
+ *     (a source radius above the bound given to the call) are recorded in the
+ *     context and reported by asora_check.  asora_last_error describes the
+ *     most recent failure.
+ */
+#ifndef ASORA_H
+#define ASORA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct asora_ctx asora_ctx;
+
+typedef enum {
+    ASORA_OK = 0,
+    ASORA_EINVAL = -1,    /* invalid argument                                   */
+    ASORA_ENOMEM = -2,    /* device or host allocation failed                   */
+    ASORA_EHIP = -3,      /* a HIP runtime call failed                           */
+    ASORA_ESTATE = -4,    /* context not usable (NULL, freed, wrong device)      */
+    ASORA_ERANGE = -5,    /* a kernel met a source outside the call's bounds    */
+    ASORA_ENOSYS = -6     /* combination of options not supported               */
+} asora_status;
+
+/* asora_init flags */
+#define ASORA_INIT_SOURCE_HALFPATH_SCALAR 0x1u
+/*   Column that a cell interpolating from the source cell sees for it.
+ *   Default (flag clear): the exit column of the source cell along the cell's
+ *   own ray, n_HI(s) alpha ds / 2 (exact on axes and diagonals).  With the
+ *   flag: the scalar n_HI(s) alpha / 2.  The source cell itself always has
+ *   entry column 0, path half a cell and volume alpha^3. */
+
+/* asora_raytrace / asora_raytrace_backward flags */
+#define ASORA_ACCUMULATE 0x1u  /* gamma += result (forward); gradients += (backward) */
+#define ASORA_PLAIN      0x2u  /* one kernel launch per source, in input order: the
+                                  unbatched baseline form (Section 3.3, one block per
+                                  source).  Default: all sources in one persistent
+                                  launch per piece kind, longest first.  Results are
+                                  the same up to the order of floating-point sums.   */
+
+/*
+ * asora_init -- create a context for one grid and one photoionization table.
+ *
+ * The table is P(tau) = gamma(tau/sigma0)/gamma(0), the number of ionizing
+ * photons per second that survive an optical depth tau at the threshold
+ * frequency, normalised to P(0) = 1 (eq. tables, Section 2.2), and its
+ * derivative dP/dtau.  It is sampled on n_tab nodes uniform in log10 tau from
+ * lg_tau_lo to lg_tau_hi.  Between nodes the library uses the cubic Hermite
+ * spline of ln P in ln tau with node slopes tau P'/P ("a simple
+ * interpolation", Section 2.2); below the first node the tangent line at the
+ * first node; above the last node the constant P(tau_hi) (nothing absorbed
+ * beyond the table).
+ *
+ *   out          host, receives the new context.
+ *   N            grid size (cells per side), 1 <= N <= 2048.
+ *   cell_cm      cell size alpha in cm (> 0).
+ *   sigma0_cm2   HI cross-section at the threshold (> 0); tau = sigma0 N_HI.
+ *   lg_tau_lo, lg_tau_hi   log10 tau of the first and last node (lo < hi).
+ *   n_tab        number of nodes, 2 <= n_tab <= 4096.
+ *   P, dPdtau    host arrays of n_tab doubles; copied.  P must be positive,
+ *                finite, non-increasing and representable as a normal FP32
+ *                number (>= 1.2e-38); dPdtau finite and <= 0.
+ *   tau_weight_floor   optical-depth floor of the interpolation weights
+ *                w = s / max(sigma0 M, floor) (0.6 is the customary value);
+ *                +INFINITY or 0 selects purely geometric weights.
+ *   flags        ASORA_INIT_* flags.
+ *   device       HIP device ordinal.
+ * Allocates about 12 N^3 bytes of device memory (FP64 rate accumulator and
+ * FP32 n_HI).  Returns ASORA_OK, ASORA_EINVAL, ASORA_ENOMEM or ASORA_EHIP.
+ */
+asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, double sigma0_cm2,
+                        double lg_tau_lo, double lg_tau_hi, int32_t n_tab, const double *P,
+                        const double *dPdtau, double tau_weight_floor, uint32_t flags,
+                        int32_t device);
+
+/*
+ * asora_raytrace -- photoionization rate of all cells from n_src sources.
+ *
+ * For each source s and each cell p with |p - s|^2 <= R_s^2 (in cells, the
+ * hard photon radius of Section 3.2/3.3) inside the periodic extent
+ * (Appendix A: at most N/2 cells on the negative and N/2-1 on the positive
+ * side of the source on an even mesh, (N-1)/2 on both sides on an odd mesh):
+ * interpolate the column N_in up to the entry face of p from the exit columns
+ * of its four neighbours one layer closer to the source along the dominant
+ * axis (eq. raga, eq. interp; bilinear geometric weights times optical-depth
+ * weights), add the in-cell column n_HI alpha ds with ds = r/m (Section 3.1),
+ * and add Gamma_p = Q_s [P(sigma0 N_in) - P(sigma0 N_out)] /
+ * (n_HI V_shell), V_shell = 4 pi (alpha r)^2 alpha ds (eq. sugg), to gamma[p].
+ * Cells are swept in shells of equal L1 distance from the source
+ * (Section 3.3), which is a causal order for the interpolation.
+ *
+ *   n_H, x_HI    device, N^3 floats: total hydrogen density (cm^-3) and neutral
+ *                fraction; n_HI = n_H x_HI.
+ *   n_src        number of sources (>= 0; 0 writes zeros / leaves gamma).
+ *   src_ijk      device, n_src x 3 int32 cell indices in [0, N).
+ *   src_Q        device, n_src doubles, ionizing photons per second (>= 0).
+ *   src_R        device, n_src floats, radius in cells; NULL = R_max for all.
+ *   R_max        host, an upper bound of every src_R (cells, 0 <= R_max <=
+ *                4096).  Used to size on-chip buffers; a source with a larger
+ *                radius is skipped and flagged (asora_check returns ERANGE).
+ *   gamma        device, N^3 floats, output (s^-1); overwritten unless
+ *                ASORA_ACCUMULATE.  Summation runs in FP64 and is rounded once.
+ *   coldens_in   device, N^3 doubles or NULL.  Only with n_src == 1: receives
+ *                N_in (cm^-2) for every cell of the ball, 0 elsewhere.
+ *   flags        ASORA_ACCUMULATE | ASORA_PLAIN.
+ *   stream       hipStream_t.
+ */
+asora_status asora_raytrace(asora_ctx *ctx, const float *n_H, const float *x_HI, int64_t n_src,
+                            const int32_t *src_ijk, const double *src_Q, const float *src_R,
+                            float R_max, float *gamma, double *coldens_in, uint32_t flags,
+                            void *stream);
+
+/*
+ * asora_raytrace_backward -- adjoint of asora_raytrace.
+ *
+ * Given dL/dgamma, computes dL/dn_H, dL/dx_HI and dL/dQ of the forward map
+ * with the same inputs.  The shells of each source are swept from the
+ * outermost inward; the column densities of a source are recomputed into
+ * scratch memory before its reverse sweep, so no forward state is kept
+ * between the calls.  Same argument conventions as asora_raytrace.
+ *
+ *   dL_dgamma    device, N^3 floats.
+ *   dL_dnH, dL_dxHI   device, N^3 floats, outputs (overwritten unless
+ *                ASORA_ACCUMULATE).
+ *   dL_dQ        device, n_src doubles, output (overwritten unless ACCUMULATE).
+ * Cells with n_HI = 0 use the limit of the rate for a vanishing in-cell
+ * optical depth.
+ */
+asora_status asora_raytrace_backward(asora_ctx *ctx, const float *n_H, const float *x_HI,
+                                     int64_t n_src, const int32_t *src_ijk, const double *src_Q,
+                                     const float *src_R, float R_max, const float *dL_dgamma,
+                                     float *dL_dnH, float *dL_dxHI, double *dL_dQ,
+                                     uint32_t flags, void *stream);
+
+/*
+ * asora_table_blackbody -- build P(tau) and dP/dtau for a black-body source of
+ * temperature T_bb (K) behind a power-law cross-section sigma0 (nu/nu_th)^-index
+ * (Section 4.1, Test 3), threshold h nu_th = 13.6 eV, on n nodes uniform in
+ * log10 tau in [lg_lo, lg_hi]:
+ *   P(tau)   = int_x0^inf phi(x) exp(-tau (x/x0)^-index) dx / int_x0^inf phi(x) dx
+ *   P'(tau)  = -int_x0^inf phi(x) (x/x0)^-index exp(..) dx / (same)
+ * with phi(x) = x^2/(e^x - 1) and x0 = 13.6 eV / (k T_bb).  Host only (no
+ * GPU use); P, dPdtau are host arrays of n doubles.  Relative accuracy ~1e-12.
+ */
+asora_status asora_table_blackbody(double T_bb, double index, int32_t n, double lg_lo,
+                                   double lg_hi, double *P, double *dPdtau);
+
+/* asora_table_grey -- P = exp(-tau), dP/dtau = -exp(-tau) (grey opacity). */
+asora_status asora_table_grey(int32_t n, double lg_lo, double lg_hi, double *P, double *dPdtau);
+
+/*
+ * asora_check -- wait for `stream` and report errors recorded by kernels since
+ * the previous check (ASORA_ERANGE: a source radius exceeded the R_max of its
+ * call, or a source index was outside the grid; that source was skipped).
+ * Clears the record.
+ */
+asora_status asora_check(asora_ctx *ctx, void *stream);
+
+/* asora_last_error -- text of the most recent error on ctx (or of the most
+ * recent failed asora_init when ctx is NULL).  Owned by the library. */
+const char *asora_last_error(const asora_ctx *ctx);
+
+/* asora_free -- release the context and its device memory (waits for the
+ * device).  NULL is accepted. */
+asora_status asora_free(asora_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ASORA_H */

@@ -1,0 +1,211 @@
+"""ASORA ray tracing on MI355X (gfx950): Python binding of libasora.so.
+
+The binding only marshals arguments: every step of the ray-tracing step runs
+in the HIP kernels of libasora.so, behind the C ABI of include/asora.h.
+PyTorch supplies device memory and streams.  If the library is missing the
+import fails; there is no CPU fallback.
+
+    import paper_2311_01492_amd as asora
+    P, dP = asora.table_blackbody(5e4)                 # host float64 arrays
+    ctx = asora.Asora(N, cell_cm, P, dP)
+    gamma = ctx.raytrace(n_H, x_HI, ijk, Q, R)         # torch tensors on cuda
+    gamma = asora.raytrace(ctx, n_H, x_HI, ijk, Q, R)  # differentiable version
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+import torch  # loads the HIP runtime that libasora.so binds to
+
+__all__ = ["Asora", "AsoraError", "raytrace", "table_blackbody", "table_grey", "lib_path",
+           "SIGMA0", "ACCUMULATE", "PLAIN", "HALFPATH_SCALAR"]
+
+SIGMA0 = 6.3e-18          # HI cross-section at 13.6 eV, cm^2
+ACCUMULATE, PLAIN = 0x1, 0x2
+HALFPATH_SCALAR = 0x1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libasora.so")
+
+if not os.path.exists(_LIB_PATH):
+    raise ImportError(f"{_LIB_PATH} is not built; run `python __graft_entry__.py` or "
+                      f"`python -m paper_2311_01492_amd.build` first (there is no CPU fallback)")
+_lib = ctypes.CDLL(_LIB_PATH)
+
+_c_int, _c_i64, _c_u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+_c_d, _c_f, _p = ctypes.c_double, ctypes.c_float, ctypes.c_void_p
+
+_lib.asora_init.restype = _c_int
+_lib.asora_init.argtypes = [ctypes.POINTER(_p), _c_int, _c_d, _c_d, _c_d, _c_d, _c_int, _p, _p,
+                            _c_d, _c_u32, _c_int]
+_lib.asora_raytrace.restype = _c_int
+_lib.asora_raytrace.argtypes = [_p, _p, _p, _c_i64, _p, _p, _p, _c_f, _p, _p, _c_u32, _p]
+_lib.asora_raytrace_backward.restype = _c_int
+_lib.asora_raytrace_backward.argtypes = [_p, _p, _p, _c_i64, _p, _p, _p, _c_f, _p, _p, _p, _p,
+                                         _c_u32, _p]
+_lib.asora_table_blackbody.restype = _c_int
+_lib.asora_table_blackbody.argtypes = [_c_d, _c_d, _c_int, _c_d, _c_d, _p, _p]
+_lib.asora_table_grey.restype = _c_int
+_lib.asora_table_grey.argtypes = [_c_int, _c_d, _c_d, _p, _p]
+_lib.asora_check.restype = _c_int
+_lib.asora_check.argtypes = [_p, _p]
+_lib.asora_last_error.restype = ctypes.c_char_p
+_lib.asora_last_error.argtypes = [_p]
+_lib.asora_free.restype = _c_int
+_lib.asora_free.argtypes = [_p]
+
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ERANGE",
+           -6: "ENOSYS"}
+
+
+class AsoraError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def _raise(st: int, ctx_ptr=None):
+    if st != 0:
+        msg = _lib.asora_last_error(ctx_ptr)
+        raise AsoraError(st, msg.decode() if msg else "")
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(_p)
+
+
+def _dptr(t):
+    return None if t is None else _p(t.data_ptr())
+
+
+def table_blackbody(T_bb: float = 5e4, index: float = 2.8, n: int = 2000, lg_lo: float = -20.0,
+                    lg_hi: float = 4.0):
+    """(P, dP/dtau) as float64 numpy arrays for a black body behind a power-law
+    cross-section; built by the library on the host."""
+    P, dP = np.empty(n), np.empty(n)
+    _raise(_lib.asora_table_blackbody(T_bb, index, n, lg_lo, lg_hi, _np_ptr(P), _np_ptr(dP)))
+    return P, dP
+
+
+def table_grey(n: int = 2000, lg_lo: float = -20.0, lg_hi: float = math.log10(80.0)):
+    P, dP = np.empty(n), np.empty(n)
+    _raise(_lib.asora_table_grey(n, lg_lo, lg_hi, _np_ptr(P), _np_ptr(dP)))
+    return P, dP
+
+
+def _stream_ptr(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return _p(s.cuda_stream)
+
+
+class Asora:
+    """One grid (N, cell size) and one photoionization table on one device."""
+
+    def __init__(self, N: int, cell_cm: float, P, dPdtau, lg_lo: float = -20.0, lg_hi: float = 4.0,
+                 sigma0: float = SIGMA0, tau_w: float = 0.6, halfpath_scalar: bool = False,
+                 device: int | None = None):
+        if not torch.cuda.is_available():
+            raise AsoraError(-4, "no HIP device available (the library has no CPU path)")
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        P = np.ascontiguousarray(P, dtype=np.float64)
+        dP = np.ascontiguousarray(dPdtau, dtype=np.float64)
+        self.N, self.cell_cm, self.sigma0 = int(N), float(cell_cm), float(sigma0)
+        h = _p()
+        st = _lib.asora_init(ctypes.byref(h), self.N, self.cell_cm, self.sigma0, float(lg_lo),
+                             float(lg_hi), int(P.size), _np_ptr(P), _np_ptr(dP), float(tau_w),
+                             HALFPATH_SCALAR if halfpath_scalar else 0, self.device)
+        _raise(st)
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.asora_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- argument checks shared by forward and backward ----------------------
+    def _prep(self, n_H, x_HI, ijk, Q, R, R_max):
+        dev = torch.device("cuda", self.device)
+        for name, t, dt in (("n_H", n_H, torch.float32), ("x_HI", x_HI, torch.float32)):
+            if t.dtype != dt or t.device != dev or not t.is_contiguous() or t.numel() != self.N ** 3:
+                raise AsoraError(-1, f"{name} must be a contiguous float32 cuda tensor of N^3 cells")
+        ijk = ijk.to(dev, torch.int32).contiguous()
+        Q = Q.to(dev, torch.float64).contiguous()
+        if R is not None and not torch.is_tensor(R):
+            R = torch.full((ijk.shape[0],), float(R), dtype=torch.float32, device=dev)
+        if R is not None:
+            R = R.to(dev, torch.float32).contiguous()
+        if R_max is None:
+            R_max = float(R.max().item()) if (R is not None and R.numel()) else 0.0
+        n = ijk.shape[0] if ijk.dim() == 2 else 0
+        if ijk.numel() != 3 * n or Q.numel() != n or (R is not None and R.numel() != n):
+            raise AsoraError(-1, "ijk must be [n,3], Q and R [n]")
+        return ijk, Q, R, float(R_max), n
+
+    def raytrace(self, n_H, x_HI, ijk, Q, R=None, R_max=None, plain=False, coldens=False,
+                 out=None, accumulate=False, stream=None):
+        """Gamma (float32 cuda, N^3) for the sources; with coldens=True (one
+        source) also the entry column N_in (float64, N^3)."""
+        ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
+        dev = n_H.device
+        gamma = out if out is not None else torch.empty(self.N ** 3, dtype=torch.float32, device=dev)
+        cd = torch.empty(self.N ** 3, dtype=torch.float64, device=dev) if coldens else None
+        flags = (PLAIN if plain else 0) | (ACCUMULATE if accumulate else 0)
+        st = _lib.asora_raytrace(self._h, _dptr(n_H), _dptr(x_HI), n, _dptr(ijk), _dptr(Q),
+                                 _dptr(R), R_max, _dptr(gamma), _dptr(cd), flags,
+                                 _stream_ptr(stream))
+        _raise(st, self._h)
+        shape = (self.N,) * 3
+        return (gamma.view(shape), cd.view(shape)) if coldens else gamma.view(shape)
+
+    def backward(self, n_H, x_HI, ijk, Q, R, dL_dgamma, R_max=None, stream=None):
+        """(dL/dn_H, dL/dx_HI, dL/dQ) for the given dL/dgamma."""
+        ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
+        dev = n_H.device
+        g = dL_dgamma.to(dev, torch.float32).contiguous()
+        dn = torch.empty(self.N ** 3, dtype=torch.float32, device=dev)
+        dx = torch.empty_like(dn)
+        dq = torch.empty(n, dtype=torch.float64, device=dev)
+        st = _lib.asora_raytrace_backward(self._h, _dptr(n_H), _dptr(x_HI), n, _dptr(ijk),
+                                          _dptr(Q), _dptr(R), R_max, _dptr(g), _dptr(dn),
+                                          _dptr(dx), _dptr(dq), 0, _stream_ptr(stream))
+        _raise(st, self._h)
+        shape = (self.N,) * 3
+        return dn.view(shape), dx.view(shape), dq
+
+    def check(self, stream=None):
+        """Wait for the stream; raise if a kernel flagged a source."""
+        _raise(_lib.asora_check(self._h, _stream_ptr(stream)), self._h)
+
+
+class _RaytraceFn(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, ctx: Asora, n_H, x_HI, ijk, Q, R, R_max):
+        fctx.save_for_backward(n_H, x_HI, ijk, Q, R if R is not None else torch.empty(0))
+        fctx.asora, fctx.R_max, fctx.has_R = ctx, R_max, R is not None
+        return ctx.raytrace(n_H.detach(), x_HI.detach(), ijk, Q.detach(), R, R_max=R_max)
+
+    @staticmethod
+    def backward(fctx, g):
+        n_H, x_HI, ijk, Q, R = fctx.saved_tensors
+        R = R if fctx.has_R else None
+        dn, dx, dq = fctx.asora.backward(n_H.detach(), x_HI.detach(), ijk, Q.detach(), R,
+                                         g.contiguous(), R_max=fctx.R_max)
+        return None, dn, dx, None, dq.to(Q.dtype), None, None
+
+
+def raytrace(ctx: Asora, n_H, x_HI, ijk, Q, R=None, R_max=None):
+    """Differentiable Gamma(n_H, x_HI, Q): backward runs the adjoint kernels."""
+    return _RaytraceFn.apply(ctx, n_H, x_HI, ijk, Q, R, R_max)

@@ -1,0 +1,383 @@
+// asora_api.hip -- the C ABI declared in include/asora.h: argument checks,
+// context and scratch memory, table preparation, launch planning.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/asora.h"
+#include "asora_internal.h"
+
+using namespace asora;
+
+struct PlanKey {
+    int type, Rsq;
+    bool operator<(const PlanKey &o) const { return type != o.type ? type < o.type : Rsq < o.Rsq; }
+};
+
+struct Plan {
+    int ring_cap, row_cap, Qmax;
+    size_t lds;
+    int grid;
+};
+
+struct asora_ctx {
+    int magic;
+    int device;
+    int N;
+    double alpha, sigma0, tau_w;
+    uint32_t flags;
+    int reading;
+    TabParams tp;
+    TabNode *d_tab;
+    float *d_nhi;
+    double *d_gacc;
+    int *d_ctl;
+    int *d_err;
+    int *d_keys;
+    int *d_order;
+    long src_cap;
+    int n_cu;
+    size_t max_lds;
+    float R_whole, R_oct;   // radius thresholds of the piece types
+    std::map<PlanKey, Plan> plans;
+    std::string err;
+};
+
+static const int kMagic = 0x4153524f;
+static std::string g_init_err;
+static std::mutex g_init_mu;
+
+static asora_status fail(asora_ctx *c, asora_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    else {
+        std::lock_guard<std::mutex> g(g_init_mu);
+        g_init_err = buf;
+    }
+    return st;
+}
+
+#define HIPCHK(ctx, expr)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? ASORA_ENOMEM : ASORA_EHIP, "%s: %s", \
+                        #expr, hipGetErrorString(e_));                                        \
+    } while (0)
+
+static bool ctx_ok(const asora_ctx *c) { return c && c->magic == kMagic; }
+
+// ---------------------------------------------------------------------------
+extern "C" asora_status asora_table_blackbody(double T_bb, double index, int32_t n, double lg_lo,
+                                              double lg_hi, double *P, double *dPdtau)
+{
+    if (table_blackbody(T_bb, index, n, lg_lo, lg_hi, P, dPdtau) != 0)
+        return fail(nullptr, ASORA_EINVAL, "asora_table_blackbody: invalid argument");
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_table_grey(int32_t n, double lg_lo, double lg_hi, double *P,
+                                         double *dPdtau)
+{
+    if (n < 2 || !(lg_hi > lg_lo) || !P || !dPdtau)
+        return fail(nullptr, ASORA_EINVAL, "asora_table_grey: invalid argument");
+    for (int t = 0; t < n; ++t) {
+        const double tau = std::pow(10.0, lg_lo + (lg_hi - lg_lo) * t / (double)(n - 1));
+        P[t] = std::exp(-tau);
+        dPdtau[t] = -std::exp(-tau);
+    }
+    return ASORA_OK;
+}
+
+// ---------------------------------------------------------------------------
+extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, double sigma0_cm2,
+                                   double lg_tau_lo, double lg_tau_hi, int32_t n_tab,
+                                   const double *P, const double *dPdtau,
+                                   double tau_weight_floor, uint32_t flags, int32_t device)
+{
+    if (!out) return fail(nullptr, ASORA_EINVAL, "asora_init: out is NULL");
+    *out = nullptr;
+    if (N < 1 || N > 2048) return fail(nullptr, ASORA_EINVAL, "asora_init: N=%d out of [1,2048]", N);
+    if (!(cell_cm > 0) || !std::isfinite(cell_cm))
+        return fail(nullptr, ASORA_EINVAL, "asora_init: cell size must be positive and finite");
+    if (!(sigma0_cm2 > 0) || !std::isfinite(sigma0_cm2))
+        return fail(nullptr, ASORA_EINVAL, "asora_init: sigma0 must be positive and finite");
+    if (!(lg_tau_hi > lg_tau_lo) || !std::isfinite(lg_tau_lo) || !std::isfinite(lg_tau_hi))
+        return fail(nullptr, ASORA_EINVAL, "asora_init: table range must satisfy lo < hi");
+    if (n_tab < 2 || n_tab > 4096)
+        return fail(nullptr, ASORA_EINVAL, "asora_init: n_tab=%d out of [2,4096]", n_tab);
+    if (!P || !dPdtau) return fail(nullptr, ASORA_EINVAL, "asora_init: table pointer is NULL");
+    for (int k = 0; k < n_tab; ++k) {
+        if (!std::isfinite(P[k]) || !(P[k] >= 1.2e-38) || !std::isfinite(dPdtau[k]) ||
+            dPdtau[k] > 0 || (k > 0 && P[k] > P[k - 1]))
+            return fail(nullptr, ASORA_EINVAL,
+                        "asora_init: table node %d invalid (P must be positive, >= 1.2e-38, "
+                        "non-increasing; dP/dtau finite and <= 0)", k);
+    }
+    if (std::isnan(tau_weight_floor) || tau_weight_floor < 0)
+        return fail(nullptr, ASORA_EINVAL, "asora_init: tau_weight_floor must be >= 0 or +inf");
+    if (flags & ~ASORA_INIT_SOURCE_HALFPATH_SCALAR)
+        return fail(nullptr, ASORA_EINVAL, "asora_init: unknown flags 0x%x", flags);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(nullptr, ASORA_EINVAL, "asora_init: device %d not available", device);
+
+    asora_ctx *c = new asora_ctx();
+    c->magic = kMagic;
+    c->device = device;
+    c->N = N;
+    c->alpha = cell_cm;
+    c->sigma0 = sigma0_cm2;
+    c->tau_w = (tau_weight_floor > 0 && std::isfinite(tau_weight_floor)) ? tau_weight_floor : 0.0;
+    c->flags = flags;
+    c->reading = (flags & ASORA_INIT_SOURCE_HALFPATH_SCALAR) ? 1 : 0;
+    c->R_whole = 10.f;
+    c->R_oct = 30.f;
+
+    // table in the kernels' form
+    std::vector<TabNode> nodes(n_tab);
+    prepare_table(n_tab, lg_tau_lo, lg_tau_hi, P, dPdtau, &c->tp, nodes.data());
+
+    auto bail = [&](asora_status st) {
+        asora_free(c);
+        return st;
+    };
+    if (hipSetDevice(device) != hipSuccess)
+        return bail(fail(nullptr, ASORA_EHIP, "asora_init: hipSetDevice(%d) failed", device));
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+        return bail(fail(nullptr, ASORA_EHIP, "asora_init: hipGetDeviceProperties failed"));
+    c->n_cu = prop.multiProcessorCount;
+    c->max_lds = prop.sharedMemPerBlock;
+    int lds_optin = 0;
+    if (hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, device) ==
+            hipSuccess && lds_optin > (int)c->max_lds)
+        c->max_lds = lds_optin;
+    const long n3 = (long)N * N * N;
+    if (hipMalloc(&c->d_tab, sizeof(TabNode) * n_tab) != hipSuccess ||
+        hipMalloc(&c->d_nhi, sizeof(float) * n3) != hipSuccess ||
+        hipMalloc(&c->d_gacc, sizeof(double) * n3) != hipSuccess ||
+        hipMalloc(&c->d_ctl, sizeof(int) * kCtlSize) != hipSuccess ||
+        hipMalloc(&c->d_err, sizeof(int)) != hipSuccess)
+        return bail(fail(nullptr, ASORA_ENOMEM, "asora_init: device allocation of %.1f MB failed",
+                         12.0 * n3 / 1e6));
+    if (hipMemcpy(c->d_tab, nodes.data(), sizeof(TabNode) * n_tab, hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemset(c->d_err, 0, sizeof(int)) != hipSuccess ||
+        hipMemset(c->d_ctl, 0, sizeof(int) * kCtlSize) != hipSuccess)
+        return bail(fail(nullptr, ASORA_EHIP, "asora_init: copy to device failed"));
+    if (fwd_configure(c->max_lds) != hipSuccess)
+        return bail(fail(nullptr, ASORA_EHIP, "asora_init: kernel attribute setup failed"));
+    *out = c;
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_free(asora_ctx *c)
+{
+    if (!c) return ASORA_OK;
+    if (c->magic != kMagic) return ASORA_ESTATE;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(c->d_tab);
+    (void)hipFree(c->d_nhi);
+    (void)hipFree(c->d_gacc);
+    (void)hipFree(c->d_ctl);
+    (void)hipFree(c->d_err);
+    (void)hipFree(c->d_keys);
+    (void)hipFree(c->d_order);
+    c->magic = 0;
+    delete c;
+    return ASORA_OK;
+}
+
+extern "C" const char *asora_last_error(const asora_ctx *c)
+{
+    if (!c) {
+        std::lock_guard<std::mutex> g(g_init_mu);
+        return g_init_err.c_str();
+    }
+    return c->err.c_str();
+}
+
+extern "C" asora_status asora_check(asora_ctx *c, void *stream)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    int e = 0;
+    HIPCHK(c, hipMemcpy(&e, c->d_err, sizeof(int), hipMemcpyDeviceToHost));
+    if (e) {
+        HIPCHK(c, hipMemset(c->d_err, 0, sizeof(int)));
+        return fail(c, ASORA_ERANGE,
+                    "a source had a radius above the call's R_max (or was outside the grid) and "
+                    "was skipped");
+    }
+    return ASORA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launch planning: on-chip buffer sizes of one piece type for radii <= R_cap.
+static int type_of(const asora_ctx *c, float R)
+{
+    return R <= c->R_whole ? 0 : (R <= c->R_oct ? 1 : 2);
+}
+
+static asora_status get_plan(asora_ctx *c, int type, float R_cap, Plan *out)
+{
+    const int Rsq = (int)std::floor((double)R_cap * (double)R_cap);
+    const PlanKey key{type, Rsq};
+    auto it = c->plans.find(key);
+    if (it != c->plans.end()) {
+        *out = it->second;
+        return ASORA_OK;
+    }
+    const Extent ex = make_extent(c->N);
+    const int Qmax = max_shell(Rsq, ex);
+    int ring = 1;
+    for (int p = 0; p < pieces_of_type(type); ++p) {
+        const Piece pc = make_piece(type, p);
+        for (int q = 1; q <= Qmax; ++q) {
+            int tot = 0;
+            for (int r = 0; r < pc.n_oct * (q + 1); ++r) {
+                int blo, cnt;
+                row_range(pc, ex, Rsq, q, r, &blo, &cnt);
+                tot += cnt;
+            }
+            ring = tot > ring ? tot : ring;
+        }
+    }
+    Plan P;
+    P.ring_cap = ring;
+    P.row_cap = (type == 0 ? 8 : 1) * (Qmax + 1);
+    P.Qmax = Qmax;
+    P.lds = fwd_lds_bytes(c->tp.n, P.ring_cap, P.row_cap);
+    if (P.lds > c->max_lds)
+        return fail(c, ASORA_ENOSYS,
+                    "R_max=%.1f needs %zu bytes of LDS per work-group (limit %zu) for this table "
+                    "and grid", R_cap, P.lds, c->max_lds);
+    int bpc = 0;
+    HIPCHK(c, fwd_occupancy(P.lds, &bpc));
+    P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
+    c->plans[key] = P;
+    *out = P;
+    return ASORA_OK;
+}
+
+static asora_status ensure_src_cap(asora_ctx *c, long n)
+{
+    if (n <= c->src_cap) return ASORA_OK;
+    long cap = c->src_cap ? c->src_cap : 1024;
+    while (cap < n) cap *= 2;
+    (void)hipFree(c->d_keys);
+    (void)hipFree(c->d_order);
+    c->d_keys = c->d_order = nullptr;
+    c->src_cap = 0;
+    HIPCHK(c, hipMalloc(&c->d_keys, sizeof(int) * cap));
+    HIPCHK(c, hipMalloc(&c->d_order, sizeof(int) * cap));
+    c->src_cap = cap;
+    return ASORA_OK;
+}
+
+static asora_status check_common(asora_ctx *c, const float *n_H, const float *x_HI, int64_t n_src,
+                                 const int32_t *ijk, const double *Q, float R_max)
+{
+    if (!n_H || !x_HI) return fail(c, ASORA_EINVAL, "n_H and x_HI must not be NULL");
+    if (n_src < 0 || n_src > (int64_t)1 << 30) return fail(c, ASORA_EINVAL, "n_src out of range");
+    if (n_src > 0 && (!ijk || !Q)) return fail(c, ASORA_EINVAL, "source arrays must not be NULL");
+    if (!(R_max >= 0.f) || !(R_max <= 4096.f))
+        return fail(c, ASORA_EINVAL, "R_max must be in [0, 4096]");
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const float *x_HI,
+                                       int64_t n_src, const int32_t *src_ijk, const double *src_Q,
+                                       const float *src_R, float R_max, float *gamma,
+                                       double *coldens_in, uint32_t flags, void *stream)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    asora_status st = check_common(c, n_H, x_HI, n_src, src_ijk, src_Q, R_max);
+    if (st) return st;
+    if (!gamma) return fail(c, ASORA_EINVAL, "gamma must not be NULL");
+    if (coldens_in && n_src != 1) return fail(c, ASORA_EINVAL, "coldens_in requires n_src == 1");
+    if (flags & ~(ASORA_ACCUMULATE | ASORA_PLAIN)) return fail(c, ASORA_EINVAL, "unknown flags");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const long n3 = (long)c->N * c->N * c->N;
+    const int tmax = type_of(c, R_max);
+    Plan plans[3];
+    for (int t = 0; t <= tmax; ++t) {
+        const float cap = t == tmax ? R_max : (t == 0 ? c->R_whole : c->R_oct);
+        if ((st = get_plan(c, t, cap, &plans[t]))) return st;
+    }
+    if ((st = ensure_src_cap(c, n_src))) return st;
+
+    FwdLaunch F;
+    F.N = c->N;
+    F.alpha = c->alpha;
+    F.sigma0 = c->sigma0;
+    F.tau_w = (float)c->tau_w;
+    F.reading = c->reading;
+    F.tp = c->tp;
+    F.tab = c->d_tab;
+    F.nHI = c->d_nhi;
+    F.gacc = c->d_gacc;
+    F.coldens = coldens_in;
+    F.ijk = src_ijk;
+    F.Q = src_Q;
+    F.R = src_R;
+    F.order = c->d_order;
+    F.ctl = c->d_ctl;
+    F.err = c->d_err;
+
+    HIPCHK(c, launch_prologue(s, n_H, x_HI, c->d_nhi, c->d_gacc, coldens_in, n3, c->d_ctl,
+                              kCtlSize, c->n_cu));
+    if (n_src > 0) {
+        if (flags & ASORA_PLAIN) {
+            F.type = tmax;
+            F.R_cap = R_max;
+            F.ring_cap = plans[tmax].ring_cap;
+            F.row_cap = plans[tmax].row_cap;
+            for (long k = 0; k < n_src; ++k) HIPCHK(c, launch_fwd_plain(s, F, (int)k));
+        } else {
+            HIPCHK(c, launch_bucketing(s, src_R, src_ijk, n_src, c->N, R_max, c->R_whole, c->R_oct,
+                                       c->d_keys, c->d_ctl, c->d_order, c->d_err));
+            for (int t = tmax; t >= 0; --t) {
+                F.type = t;
+                F.R_cap = t == tmax ? R_max : (t == 0 ? c->R_whole : c->R_oct);
+                F.ring_cap = plans[t].ring_cap;
+                F.row_cap = plans[t].row_cap;
+                HIPCHK(c, launch_fwd_persistent(s, F, plans[t].grid));
+            }
+        }
+    }
+    HIPCHK(c, launch_finalize(s, c->d_gacc, gamma, n3, (flags & ASORA_ACCUMULATE) ? 1 : 0,
+                              c->n_cu));
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, const float *x_HI,
+                                                int64_t n_src, const int32_t *src_ijk,
+                                                const double *src_Q, const float *src_R,
+                                                float R_max, const float *dL_dgamma,
+                                                float *dL_dnH, float *dL_dxHI, double *dL_dQ,
+                                                uint32_t flags, void *stream)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    asora_status st = check_common(c, n_H, x_HI, n_src, src_ijk, src_Q, R_max);
+    if (st) return st;
+    (void)src_R; (void)dL_dgamma; (void)dL_dnH; (void)dL_dxHI; (void)dL_dQ; (void)flags;
+    (void)stream;
+    return fail(c, ASORA_ENOSYS, "asora_raytrace_backward: not built yet");
+}

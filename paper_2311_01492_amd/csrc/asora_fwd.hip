@@ -1,0 +1,384 @@
+// asora_fwd.hip -- forward ray-tracing kernels for gfx950.
+//
+// One work-group sweeps one piece of one source (see asora_dev.h): shell by
+// shell in L1 distance q (Section 3.3), with the exit columns of the last
+// four shells in an LDS ring (FP64), the photoionization table in LDS, and
+// the rate of every owned cell added to an FP64 N^3 accumulator with one
+// hardware atomic per source-cell.  The persistent kernel pulls
+// (source, piece) items from a global counter, largest radius first.
+#include "asora_dev.h"
+#include "asora_internal.h"
+
+namespace asora {
+
+constexpr int kWG = 256;
+
+struct FwdArgs {
+    int N;
+    Extent ex;
+    double alpha, sigma0;
+    float alpha_f, sig_f;   // FP32 copies for the weights and the in-cell column
+    float tau_w;            // weight floor, <= 0: geometric weights
+    int reading;            // 0: directional source half path, 1: scalar
+    TabParams tp;
+    const TabNode *tab;
+    const float *nHI;
+    double *gacc;
+    double *coldens;
+    const int32_t *ijk;
+    const double *Q;
+    const float *R;         // may be NULL: every source has R = R_cap
+    float R_cap;
+    const int *order;       // sources sorted by type and decreasing radius
+    const int *seg;         // seg[t] .. seg[t+1]: sources of type t in order[]
+    int type, n_pieces;
+    int *counter;
+    int *err;
+    int ring_cap, row_cap;
+    int plain_src;          // >= 0: non-persistent launch for this source
+};
+
+struct Lds {
+    TabNode *tab;
+    double *ring;      // [4][ring_cap]
+    int *rowbase;      // [4][row_cap]: slot of (row, B) = rowbase[row] + B
+    int *rowstart;     // [row_cap + 1] of the current shell
+};
+
+// Sweep one piece of one source.  Called by all threads of the work-group.
+__device__ void sweep_piece(const FwdArgs &A, const Lds &L, int src, int p, int *sh_total)
+{
+    const int tid = threadIdx.x;
+    const int N = A.N;
+    const int si = A.ijk[3 * src], sj = A.ijk[3 * src + 1], sk = A.ijk[3 * src + 2];
+    const float R = A.R ? A.R[src] : A.R_cap;
+    if (!(R >= 0.f && R <= A.R_cap) || si < 0 || si >= N || sj < 0 || sj >= N || sk < 0 ||
+        sk >= N) {
+        if (tid == 0) atomicOr(A.err, 1);
+        return;
+    }
+    const double Q = A.Q[src];
+    const int Rsq = (int)floor((double)R * (double)R);
+    const Piece pc = make_piece(A.type, p);
+    const int Qmax = max_shell(Rsq, A.ex);
+    const long cs = ((long)si * N + sj) * N + sk;
+    const float n_s = A.nHI[cs];
+
+    CellCtx X;
+    X.pc = pc;
+    X.N = N;
+    X.si = si;
+    X.sj = sj;
+    X.sk = sk;
+    X.reading = A.reading;
+    X.tau_w = A.tau_w;
+    X.sig_f = A.sig_f;
+    X.alpha_f = A.alpha_f;
+    X.sigma0 = A.sigma0;
+    X.half_col = (double)n_s * A.alpha * 0.5;
+    X.coef = Q * A.sigma0 / (4.0 * M_PI * A.alpha * A.alpha);
+    X.tab = L.tab;
+    X.tp = A.tp;
+    X.ring = L.ring;
+    X.rowbase = L.rowbase;
+    X.ring_cap = A.ring_cap;
+    X.row_cap = A.row_cap;
+    X.nHI = A.nHI;
+
+    const bool src_owner = (pc.kind == 0) || (pc.oct == 0 && (pc.dom < 0 || pc.dom == 2));
+    if (src_owner && tid == 0) {
+        const double G = source_cell_rate(L.tab, A.tp, A.sigma0, A.alpha, Q, n_s);
+        if (G != 0.0) unsafeAtomicAdd(&A.gacc[cs], G);
+        if (A.coldens) A.coldens[cs] = 0.0;
+    }
+
+    for (int q = 1; q <= Qmax; ++q) {
+        const int slot = q & 3;
+        const int nrows = pc.n_oct * (q + 1);
+        // ---- row table of shell q (wave 0): counts, exclusive scan, bases
+        if (tid < 64) {
+            const int c = (nrows + 63) >> 6;
+            const int r0 = tid * c;
+            int sum = 0;
+            for (int k = 0; k < c; ++k) {
+                const int r = r0 + k;
+                if (r < nrows) {
+                    int blo, cnt;
+                    row_range(pc, A.ex, Rsq, q, r, &blo, &cnt);
+                    sum += cnt;
+                }
+            }
+            int incl = sum;
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const int t = __shfl_up(incl, off, 64);
+                if (tid >= off) incl += t;
+            }
+            int run = incl - sum;
+            for (int k = 0; k < c; ++k) {
+                const int r = r0 + k;
+                if (r < nrows) {
+                    int blo, cnt;
+                    row_range(pc, A.ex, Rsq, q, r, &blo, &cnt);
+                    L.rowstart[r] = run;
+                    L.rowbase[slot * A.row_cap + r] = run - blo;
+                    run += cnt;
+                }
+            }
+            if (tid == 63) {
+                L.rowstart[nrows] = incl;
+                *sh_total = incl;
+            }
+        }
+        __syncthreads();
+        const int total = *sh_total;
+        const int *rb_q = L.rowbase + slot * A.row_cap;
+        double *ring_q = L.ring + slot * A.ring_cap;
+        for (int g = tid; g < total; g += kWG) {
+            const int row = find_row(L.rowstart, nrows, g);
+            CellOut co;
+            cell_update(X, q, g, row, rb_q[row], co);
+            ring_q[g] = co.Nout;
+            if (co.owned) {
+                if (co.G != 0.0) unsafeAtomicAdd(&A.gacc[co.cp], co.G);
+                if (A.coldens) A.coldens[co.cp] = co.Nin;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__device__ Lds carve_lds(char *smem, const FwdArgs &A)
+{
+    Lds L;
+    L.tab = (TabNode *)smem;
+    L.ring = (double *)(smem + (size_t)A.tp.n * sizeof(TabNode));
+    L.rowbase = (int *)(L.ring + 4 * (size_t)A.ring_cap);
+    L.rowstart = L.rowbase + 4 * A.row_cap;
+    return L;
+}
+
+__device__ void load_table(const FwdArgs &A, TabNode *dst)
+{
+    const int4 *s = (const int4 *)A.tab;
+    int4 *d = (int4 *)dst;
+    for (int k = threadIdx.x; k < A.tp.n; k += kWG) d[k] = s[k];
+}
+
+__global__ __launch_bounds__(kWG) void fwd_persistent(FwdArgs A)
+{
+    extern __shared__ __align__(16) char smem[];
+    __shared__ int sh_item, sh_total;
+    const Lds L = carve_lds(smem, A);
+    load_table(A, L.tab);
+    const int base = A.seg[A.type];
+    const long nitems = (long)(A.seg[A.type + 1] - base) * A.n_pieces;
+    __syncthreads();
+    for (;;) {
+        if (threadIdx.x == 0) sh_item = atomicAdd(A.counter, 1);
+        __syncthreads();
+        const long item = sh_item;
+        if (item >= nitems) break;
+        const int src = A.order[base + (int)(item / A.n_pieces)];
+        const int p = (int)(item % A.n_pieces);
+        sweep_piece(A, L, src, p, &sh_total);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kWG) void fwd_plain(FwdArgs A)
+{
+    extern __shared__ __align__(16) char smem[];
+    __shared__ int sh_total;
+    const Lds L = carve_lds(smem, A);
+    load_table(A, L.tab);
+    __syncthreads();
+    sweep_piece(A, L, A.plain_src, blockIdx.x, &sh_total);
+}
+
+// ---- small kernels: n_HI, accumulators, bucketing, final conversion --------
+
+__global__ void prologue_kernel(const float *__restrict__ nH, const float *__restrict__ xHI,
+                                float *__restrict__ nHI, double *__restrict__ gacc,
+                                double *__restrict__ coldens, long n3, int *ctl, int nctl)
+{
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < n3; c += stride) {
+        nHI[c] = nH[c] * xHI[c];
+        gacc[c] = 0.0;
+        if (coldens) coldens[c] = 0.0;
+    }
+    if (blockIdx.x == 0)
+        for (int k = threadIdx.x; k < nctl; k += blockDim.x) ctl[k] = 0;
+}
+
+__global__ void classify_kernel(const float *R, const int32_t *ijk, long nsrc, int N, float R_max,
+                                float R_whole, float R_oct, int *keys, int *hist, int *err)
+{
+    const long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (s >= nsrc) return;
+    const float r = R ? R[s] : R_max;
+    const int i = ijk[3 * s], j = ijk[3 * s + 1], k = ijk[3 * s + 2];
+    int key;
+    if (!(r >= 0.f && r <= R_max) || i < 0 || i >= N || j < 0 || j >= N || k < 0 || k >= N) {
+        atomicOr(err, 1);
+        key = 3 * kRBins;   // not scheduled
+    } else {
+        const int type = r <= R_whole ? 0 : (r <= R_oct ? 1 : 2);
+        int bin = R_max > 0.f ? (int)(r / R_max * (float)(kRBins - 1)) : 0;
+        bin = bin < 0 ? 0 : (bin > kRBins - 1 ? kRBins - 1 : bin);
+        key = type * kRBins + (kRBins - 1 - bin);
+        atomicAdd(&hist[key], 1);
+    }
+    keys[s] = key;
+}
+
+// Exclusive scan of the 3*kRBins histogram (one work-group); offsets and
+// per-type segment starts.
+__global__ void scan_kernel(const int *hist, int *offs, int *seg)
+{
+    constexpr int n = 3 * kRBins;
+    __shared__ int buf[n];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) buf[k] = hist[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int k = 0; k < n; ++k) {
+            const int v = buf[k];
+            buf[k] = run;
+            run += v;
+        }
+        for (int t = 0; t < 3; ++t) seg[t] = buf[t * kRBins];
+        seg[3] = run;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += blockDim.x) offs[k] = buf[k];
+}
+
+__global__ void scatter_kernel(const int *keys, long nsrc, int *offs, int *order)
+{
+    const long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
+    if (s >= nsrc) return;
+    const int key = keys[s];
+    if (key >= 3 * kRBins) return;
+    const int pos = atomicAdd(&offs[key], 1);
+    order[pos] = (int)s;
+}
+
+__global__ void finalize_kernel(const double *__restrict__ gacc, float *__restrict__ gamma, long n3,
+                                int accumulate)
+{
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < n3; c += stride) {
+        const float v = (float)gacc[c];
+        gamma[c] = accumulate ? gamma[c] + v : v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (called from the C ABI in asora_api.hip)
+// ---------------------------------------------------------------------------
+hipError_t launch_prologue(hipStream_t st, const float *nH, const float *xHI, float *nHI,
+                           double *gacc, double *coldens, long n3, int *ctl, int nctl, int n_cu)
+{
+    const int blocks = n_cu * 8;
+    hipLaunchKernelGGL(prologue_kernel, dim3(blocks), dim3(256), 0, st, nH, xHI, nHI, gacc,
+                       coldens, n3, ctl, nctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_bucketing(hipStream_t st, const float *R, const int32_t *ijk, long nsrc, int N,
+                            float R_max, float R_whole, float R_oct, int *keys, int *ctl,
+                            int *order, int *err)
+{
+    int *hist = ctl + kCtlHist, *offs = ctl + kCtlOffs, *seg = ctl + kCtlSeg;
+    const int b = (int)((nsrc + 255) / 256);
+    if (nsrc > 0) {
+        hipLaunchKernelGGL(classify_kernel, dim3(b), dim3(256), 0, st, R, ijk, nsrc, N, R_max,
+                           R_whole, R_oct, keys, hist, err);
+    }
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(256), 0, st, hist, offs, seg);
+    if (nsrc > 0)
+        hipLaunchKernelGGL(scatter_kernel, dim3(b), dim3(256), 0, st, keys, nsrc, offs, order);
+    return hipGetLastError();
+}
+
+static FwdArgs make_args(const FwdLaunch &F)
+{
+    FwdArgs A;
+    A.N = F.N;
+    A.ex = make_extent(F.N);
+    A.alpha = F.alpha;
+    A.sigma0 = F.sigma0;
+    A.alpha_f = (float)F.alpha;
+    A.sig_f = (float)F.sigma0;
+    A.tau_w = F.tau_w;
+    A.reading = F.reading;
+    A.tp = F.tp;
+    A.tab = F.tab;
+    A.nHI = F.nHI;
+    A.gacc = F.gacc;
+    A.coldens = F.coldens;
+    A.ijk = F.ijk;
+    A.Q = F.Q;
+    A.R = F.R;
+    A.R_cap = F.R_cap;
+    A.order = F.order;
+    A.seg = F.ctl + kCtlSeg;
+    A.type = F.type;
+    A.n_pieces = pieces_of_type(F.type);
+    A.counter = F.ctl + kCtlCounter + F.type;
+    A.err = F.err;
+    A.ring_cap = F.ring_cap;
+    A.row_cap = F.row_cap;
+    A.plain_src = -1;
+    return A;
+}
+
+size_t fwd_lds_bytes(int n_tab, int ring_cap, int row_cap)
+{
+    return (size_t)n_tab * sizeof(TabNode) + 4 * (size_t)ring_cap * sizeof(double) +
+           (4 * (size_t)row_cap + row_cap + 1) * sizeof(int);
+}
+
+hipError_t fwd_configure(size_t max_lds)
+{
+    hipError_t e = hipFuncSetAttribute((const void *)fwd_persistent,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)fwd_plain, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)max_lds);
+}
+
+hipError_t fwd_occupancy(size_t lds, int *blocks_per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)fwd_persistent,
+                                                        kWG, lds);
+}
+
+hipError_t launch_fwd_persistent(hipStream_t st, const FwdLaunch &F, int grid)
+{
+    const FwdArgs A = make_args(F);
+    const size_t lds = fwd_lds_bytes(F.tp.n, F.ring_cap, F.row_cap);
+    hipLaunchKernelGGL(fwd_persistent, dim3(grid), dim3(kWG), lds, st, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd_plain(hipStream_t st, const FwdLaunch &F, int src)
+{
+    FwdArgs A = make_args(F);
+    A.plain_src = src;
+    const size_t lds = fwd_lds_bytes(F.tp.n, F.ring_cap, F.row_cap);
+    hipLaunchKernelGGL(fwd_plain, dim3(A.n_pieces), dim3(kWG), lds, st, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(hipStream_t st, const double *gacc, float *gamma, long n3, int accumulate,
+                           int n_cu)
+{
+    hipLaunchKernelGGL(finalize_kernel, dim3(n_cu * 8), dim3(256), 0, st, gacc, gamma, n3,
+                       accumulate);
+    return hipGetLastError();
+}
+
+}  // namespace asora

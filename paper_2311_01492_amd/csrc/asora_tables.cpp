@@ -1,0 +1,116 @@
+// asora_tables.cpp -- host construction of the photoionization tables
+// P(tau) = gamma(tau/sigma0)/gamma(0) and dP/dtau (eq. tables, Section 2.2)
+// for a black-body spectrum behind a power-law cross-section (Section 4.1).
+//
+// Integration: x = h nu / k T from x0 = 13.6 eV / kT to 800 (the integrand is
+// below e^-790 of its peak beyond), substituted x = x0 + u^2 so that panels
+// crowd towards the threshold, and a composite 20-point Gauss-Legendre rule
+// on 240 panels in u.  The Legendre nodes are found by Newton's method on the
+// three-term recurrence.
+#include <cmath>
+#include <vector>
+
+#include "asora_dev.h"
+
+namespace asora {
+
+namespace {
+
+constexpr double kBoltzmannEv = 8.617333262e-5;   // eV / K
+constexpr double kThresholdEv = 13.6;             // hydrogen ionization threshold
+constexpr int kGL = 20;
+constexpr int kPanels = 240;
+constexpr double kXUpper = 800.0;
+
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = 0.0;
+            for (int k = 1; k <= n; ++k) {
+                const double p2 = p1;
+                p1 = p0;
+                p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+            }
+            dp = n * (z * p0 - p1) / (z * z - 1.0);
+            const double dz = p0 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        x[i] = -z;
+        x[n - 1 - i] = z;
+        w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+}  // namespace
+
+int table_blackbody(double T_bb, double index, int n, double lg_lo, double lg_hi, double *P,
+                    double *dP)
+{
+    if (!(T_bb > 0) || !(n >= 2) || !(lg_hi > lg_lo) || !P || !dP) return -1;
+    const double x0 = kThresholdEv / (kBoltzmannEv * T_bb);
+    if (!(x0 < kXUpper)) return -1;
+    std::vector<double> gx, gw;
+    gauss_legendre(kGL, gx, gw);
+    // quadrature points in x with weights including the Jacobian dx = 2u du,
+    // the photon spectrum phi(x) = x^2/(e^x-1) and the cross-section shape
+    const double u_hi = std::sqrt(kXUpper - x0);
+    const double du = u_hi / kPanels;
+    const int npts = kGL * kPanels;
+    std::vector<double> wphi(npts), shape(npts);
+    double norm = 0.0;
+    for (int p = 0; p < kPanels; ++p) {
+        const double c = (p + 0.5) * du;
+        for (int k = 0; k < kGL; ++k) {
+            const double u = c + 0.5 * du * gx[k];
+            const double x = x0 + u * u;
+            const double phi = x * x * std::exp(-x) / -std::expm1(-x);
+            const int i = p * kGL + k;
+            wphi[i] = 0.5 * du * gw[k] * 2.0 * u * phi;
+            shape[i] = std::pow(x / x0, -index);
+            norm += wphi[i];
+        }
+    }
+    for (int t = 0; t < n; ++t) {
+        const double tau = std::pow(10.0, lg_lo + (lg_hi - lg_lo) * t / (double)(n - 1));
+        double s0 = 0.0, s1 = 0.0;
+        for (int i = 0; i < npts; ++i) {
+            const double e = wphi[i] * std::exp(-tau * shape[i]);
+            s0 += e;
+            s1 += e * shape[i];
+        }
+        P[t] = s0 / norm;
+        dP[t] = -s1 / norm;
+    }
+    return 0;
+}
+
+// The table in the form the kernels read (see TabNode): node values ln P,
+// log-log slopes tau P'/P, FP32 P, and the parameters of the node grid.
+void prepare_table(int n, double lg_lo, double lg_hi, const double *P, const double *dP,
+                   TabParams *tp, TabNode *nodes)
+{
+    const double ln10 = std::log(10.0);
+    tp->n = n;
+    tp->x_lo = lg_lo * ln10;
+    const double h = (lg_hi - lg_lo) * ln10 / (double)(n - 1);
+    tp->inv_h = 1.0 / h;
+    tp->h = (float)h;
+    tp->inv_hf = (float)(1.0 / h);
+    tp->tau_lo = std::exp(tp->x_lo);
+    tp->tau_hi = std::exp(tp->x_lo + h * (n - 1));
+    tp->dP0 = (float)dP[0];
+    for (int k = 0; k < n; ++k) {
+        const double tk = std::exp(tp->x_lo + h * k);
+        nodes[k].y = std::log(P[k]);
+        nodes[k].m = (float)(tk * dP[k] / P[k]);
+        nodes[k].P = (float)P[k];
+    }
+}
+
+}  // namespace asora

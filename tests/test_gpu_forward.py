@@ -1,0 +1,166 @@
+"""GPU parity of the forward ray tracing (HIP kernels through the C ABI)
+against the FP64 oracle.  Bar: max relative error 1e-5 on Gamma and on the
+column density over cells above 1e-20 of the maximum (tests/parity.py);
+exact zeros where the oracle is zero."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.parity import assert_parity, floored_rel
+from workloads import make_workload
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def asora():
+    import paper_2311_01492_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def bb():
+    return oracle.blackbody_table()
+
+
+def _ctx(asora, w, table, **kw):
+    return asora.Asora(w.N, w.cell_cm, table.P, table.dP, table.lg_lo, table.lg_hi, **kw)
+
+
+def _dev(w):
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    return t(w.n_H), t(w.x_HI)
+
+
+def _gpu(ctx, w, src=None, **kw):
+    src = src or w.src
+    nH, xH = _dev(w)
+    out = ctx.raytrace(nH, xH, torch.from_numpy(src.ijk), torch.from_numpy(src.Q),
+                       torch.from_numpy(src.R), **kw)
+    ctx.check()
+    if isinstance(out, tuple):
+        return tuple(o.cpu().numpy().astype(np.float64) for o in out)
+    return out.cpu().numpy().astype(np.float64)
+
+
+def _orc(w, table, src=None, **kw):
+    src = src or w.src
+    return oracle.raytrace(w.N, w.cell_cm, table, w.n_H, w.x_HI, src.ijk, src.Q, src.R, **kw)
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_c1_gamma_and_column(asora, bb, plain):
+    w = make_workload("c1")
+    print("case c1 plain", plain, flush=True)
+    o, ocd = _orc(w, bb, coldens=True)
+    g, cd = _gpu(_ctx(asora, w, bb), w, coldens=True, plain=plain)
+    assert_parity(g, o, TOL)
+    assert_parity(cd, ocd, TOL, what="coldens")
+    assert np.count_nonzero(cd) == 14147 - 1
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_uneven_radii_all_piece_kinds(asora, bb, plain):
+    """Radii 2..40 cover the whole-source, octant and pyramid pieces."""
+    w = make_workload("c2", N=48, n_src=40, R=(2.0, 40.0))
+    print("case uneven N=48 n_src=40 plain", plain, flush=True)
+    o = _orc(w, bb)
+    g = _gpu(_ctx(asora, w, bb), w, plain=plain)
+    assert_parity(g, o, TOL)
+
+
+def test_c2_subset(asora, bb):
+    w = make_workload("c2")
+    sub = w.src.subset(np.arange(60))
+    print("case c2 subset 60", flush=True)
+    o = _orc(w, bb, src=sub)
+    g = _gpu(_ctx(asora, w, bb), w, src=sub)
+    assert_parity(g, o, TOL)
+
+
+def test_c2_full_by_superposition(asora, bb):
+    """All 1000 C2 sources in one launch equal the sum of ten 100-source
+    launches (Gamma is additive over sources); one chunk is checked against
+    the oracle in test_c2_subset's way."""
+    w = make_workload("c2")
+    print("case c2 full superposition", flush=True)
+    ctx = _ctx(asora, w, bb)
+    full = _gpu(ctx, w)
+    parts = sum(_gpu(ctx, w, src=w.src.subset(np.arange(k, k + 100))) for k in range(0, 1000, 100))
+    rel, small, n = floored_rel(full, parts)
+    assert rel < 1e-6 and small < 1e-6
+    o = _orc(w, bb, src=w.src.subset(np.arange(900, 920)))
+    g = _gpu(ctx, w, src=w.src.subset(np.arange(900, 920)))
+    assert_parity(g, o, TOL)
+
+
+def test_c3_shape_subset(asora, bb):
+    """250^3 grid, radii U[5,50]: a 120-source subset against the oracle."""
+    w = make_workload("c3", n_src=120)
+    print("case c3 subset 120", flush=True)
+    o = _orc(w, bb)
+    g = _gpu(_ctx(asora, w, bb), w)
+    assert_parity(g, o, TOL)
+
+
+@pytest.mark.parametrize("tau_w,scalar", [(math.inf, False), (0.6, True)])
+def test_weighting_and_source_readings(asora, bb, tau_w, scalar):
+    w = make_workload("c2", N=32, n_src=12, R=(3.0, 20.0))
+    print("case readings", tau_w, scalar, flush=True)
+    o = _orc(w, bb, tau_w=tau_w, reading=1 if scalar else 0)
+    g = _gpu(_ctx(asora, w, bb, tau_w=tau_w, halfpath_scalar=scalar), w)
+    assert_parity(g, o, TOL)
+
+
+def test_grey_table_and_zero_density(asora):
+    gt = oracle.grey_table()
+    w = make_workload("c2", N=24, n_src=5, R=(2.0, 12.0))
+    w.n_H = (w.n_H * 2e-3).astype(np.float32)
+    print("case grey", flush=True)
+    assert_parity(_gpu(_ctx(asora, w, gt), w), _orc(w, gt), TOL)
+    w.n_H = np.zeros_like(w.n_H)
+    bb = oracle.blackbody_table()
+    assert_parity(_gpu(_ctx(asora, w, bb), w), _orc(w, bb), TOL)
+
+
+def test_edges_odd_grid_wrap_and_clip(asora, bb):
+    """Odd N, sources on the faces and corners of the box (periodic wrap),
+    radii beyond half the box (extent clip), a duplicate source, R = 0."""
+    w = make_workload("c2", N=19, n_src=6, R=(3.0, 17.0))
+    w.src.ijk[:] = [[0, 0, 0], [18, 18, 18], [0, 9, 18], [5, 5, 5], [5, 5, 5], [12, 0, 7]]
+    w.src.R[:] = [17.0, 9.5, 12.0, 4.0, 4.0, 0.0]
+    print("case edges", flush=True)
+    assert_parity(_gpu(_ctx(asora, w, bb), w), _orc(w, bb), TOL)
+
+
+def test_empty_and_accumulate(asora, bb):
+    w = make_workload("c2", N=20, n_src=3, R=(4.0, 8.0))
+    ctx = _ctx(asora, w, bb)
+    nH, xH = _dev(w)
+    e = torch.empty(0, 3, dtype=torch.int32)
+    g0 = ctx.raytrace(nH, xH, e, torch.empty(0, dtype=torch.float64), torch.empty(0), R_max=0.0)
+    assert float(g0.abs().max()) == 0.0
+    g1 = _gpu(ctx, w)
+    acc = torch.from_numpy(g1.astype(np.float32).reshape(-1)).cuda()
+    ctx.raytrace(nH, xH, torch.from_numpy(w.src.ijk), torch.from_numpy(w.src.Q),
+                 torch.from_numpy(w.src.R), out=acc, accumulate=True)
+    np.testing.assert_allclose(acc.cpu().numpy().reshape(g1.shape), 2 * g1, rtol=1e-6, atol=0)
+
+
+def test_radius_above_bound_is_flagged(asora, bb):
+    w = make_workload("c2", N=20, n_src=3, R=(4.0, 8.0))
+    ctx = _ctx(asora, w, bb)
+    nH, xH = _dev(w)
+    ctx.raytrace(nH, xH, torch.from_numpy(w.src.ijk), torch.from_numpy(w.src.Q),
+                 torch.from_numpy(w.src.R), R_max=3.0)
+    with pytest.raises(asora.AsoraError) as e:
+        ctx.check()
+    assert e.value.status == -5
+    ctx.check()   # cleared
+    with pytest.raises(asora.AsoraError):
+        ctx.raytrace(nH, xH, torch.from_numpy(w.src.ijk), torch.from_numpy(w.src.Q),
+                     torch.from_numpy(w.src.R), coldens=True)

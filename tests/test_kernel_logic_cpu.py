@@ -1,0 +1,126 @@
+"""The library's per-cell code (cell update, row enumeration, rate numerics
+from csrc/asora_dev.h) compiled for the CPU and driven serially, against the
+FP64 oracle.  Checks the logic the GPU kernels run -- piece decomposition,
+compact shell indexing, neighbour slots, interpolation, divided differences
+-- without a GPU.  The parallel driver (wave scan, barriers, atomics) is
+covered by the GPU tests."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.native import hostsweep
+from tests.parity import assert_parity
+from workloads import make_workload
+
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def bb():
+    return oracle.blackbody_table()
+
+
+@pytest.mark.parametrize("type_force", [0, 1, 2])
+def test_c1_all_piece_kinds(bb, type_force):
+    w = make_workload("c1")
+    o, ocd = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R, coldens=True)
+    g, cd = hostsweep.raytrace(w.N, w.cell_cm, oracle.SIGMA0, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
+                               w.src.R, type_force=type_force, coldens=True)
+    assert_parity(g, o, TOL)
+    assert_parity(cd, ocd, TOL, what="coldens")
+    assert np.count_nonzero(cd) == 14147 - 1
+
+
+@pytest.mark.parametrize("type_force", [-1, 0, 1, 2])
+@pytest.mark.parametrize("tau_w,reading", [(0.6, 0), (math.inf, 0), (0.6, 1)])
+def test_lognormal_sources(bb, type_force, tau_w, reading):
+    w = make_workload("c2", N=36, n_src=9, R=(3.0, 21.0))
+    o = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R,
+                        tau_w=tau_w, reading=reading)
+    g = hostsweep.raytrace(w.N, w.cell_cm, oracle.SIGMA0, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
+                           w.src.R, tau_w=tau_w, reading=reading, type_force=type_force)
+    assert_parity(g, o, TOL)
+
+
+def test_odd_grid_large_radius_extent_clip(bb):
+    """R larger than the box: the periodic extent clips the ball (odd N)."""
+    w = make_workload("c2", N=21, n_src=3, R=(14.0, 19.0))
+    o = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
+    for tf in (0, 1, 2):
+        g = hostsweep.raytrace(w.N, w.cell_cm, oracle.SIGMA0, bb, w.n_H, w.x_HI, w.src.ijk,
+                               w.src.Q, w.src.R, type_force=tf)
+        assert_parity(g, o, TOL)
+
+
+def test_grey_and_thin(bb):
+    gt = oracle.grey_table()
+    w = make_workload("c2", N=24, n_src=4, R=(5.0, 11.0))
+    nH = (w.n_H * 2e-3).astype(np.float32)          # a few optical depths per cell (grey)
+    o = oracle.raytrace(w.N, w.cell_cm, gt, nH, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
+    g = hostsweep.raytrace(w.N, w.cell_cm, oracle.SIGMA0, gt, nH, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
+    assert_parity(g, o, TOL)
+    thin = (w.n_H * 1e-9).astype(np.float32)        # tau per cell ~ 3e-6
+    o = oracle.raytrace(w.N, w.cell_cm, bb, thin, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
+    g = hostsweep.raytrace(w.N, w.cell_cm, oracle.SIGMA0, bb, thin, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
+    assert_parity(g, o, TOL)
+    zero = np.zeros_like(w.n_H)
+    o = oracle.raytrace(w.N, w.cell_cm, bb, zero, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
+    g = hostsweep.raytrace(w.N, w.cell_cm, oracle.SIGMA0, bb, zero, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
+    assert_parity(g, o, TOL)
+
+
+def test_divided_difference_regimes(bb):
+    """-[P(a+dt)-P(a)]/dt of the library's log-space evaluation against the
+    oracle's FP64 difference of its own interpolant, over the regimes: both
+    ends in one node interval, neighbouring intervals, many intervals, across
+    the first node, across the last node, zero width."""
+    rng = np.random.default_rng(0)
+    a = 10 ** rng.uniform(-6, 4.2, 4000)
+    rel = 10 ** rng.uniform(-5, 3, 4000)
+    dt = a * rel
+    a = np.concatenate([a, [0.0, 0.0, 1e-21, 9999.0, 9990.0, 3.0]])
+    dt = np.concatenate([dt, [1e-3, 2.7e3, 5e-21, 5.0, 0.5, 0.0]])
+    got = hostsweep.neg_divdiff(bb, a, dt)
+    Pa, d1a, _ = oracle.table_eval(bb, a)
+    Pb, _, _ = oracle.table_eval(bb, a + dt)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        want = np.where(dt > 0, -(Pb - Pa) / dt, -d1a)
+    # below the first node the interpolant is linear: its difference quotient is
+    # the slope there (FP64 cannot resolve 1 - P at tau ~ 1e-21)
+    lin = a + dt < 1e-20
+    want[lin] = -bb.dP[0]
+    ok = want > 0
+    # the oracle's FP64 difference itself loses digits when P(a+dt) ~ P(a)
+    cond = np.where((dt > 0) & ~lin, np.abs(Pa) * 2.2e-16 / np.maximum(np.abs(Pb - Pa), 1e-300), 0)
+    err = np.abs(got[ok] - want[ok]) / want[ok]
+    assert np.all(err <= 2e-6 + 4 * cond[ok]), err.max()
+    assert np.all(got[~ok] == 0)
+
+
+@pytest.mark.parametrize("N", [16, 17])
+def test_row_enumeration_matches_brute_force(N):
+    """Union of the rows of all pieces of a type = the shell's cells in the
+    ball and the periodic extent, each owned once."""
+    rng = np.random.default_rng(N)
+    off, sh = oracle.shell_order(N, 9.3)
+    Rsq = int(math.floor(9.3 * 9.3))
+    for q in rng.choice(np.arange(1, sh.max() + 1), 6, replace=False):
+        want = {tuple(d) for d, s in zip(off, sh) if s == q}
+        for type_ in (0, 1, 2):
+            npieces = (1, 8, 24)[type_]
+            got = []
+            for p in range(npieces):
+                blo, cnt = hostsweep.rows(N, type_, p, Rsq, int(q))
+                for r in range(len(cnt)):
+                    os_, A = divmod(r, int(q) + 1)
+                    o = os_ if type_ == 0 else (p if type_ == 1 else p // 3)
+                    for B in range(blo[r], blo[r] + cnt[r]):
+                        C = q - A - B
+                        d = (-A if o & 1 else A, -B if o & 2 else B, -C if o & 4 else C)
+                        got.append(d)
+            if type_ == 0:
+                assert sorted(got) == sorted(want)
+            else:
+                assert set(got) == want          # ghosts duplicate cells, nothing missing or extra
