@@ -90,8 +90,9 @@ typedef enum {
  *                +INFINITY or 0 selects purely geometric weights.
  *   flags        ASORA_INIT_* flags.
  *   device       HIP device ordinal.
- * Allocates about 12 N^3 bytes of device memory (FP64 rate accumulator and
- * FP32 n_HI).  Returns ASORA_OK, ASORA_EINVAL, ASORA_ENOMEM or ASORA_EHIP.
+ * Allocates about 16 N^3 bytes of device memory (FP64 rate accumulator and
+ * FP64 n_HI, the exact product of the FP32 inputs).  Returns ASORA_OK,
+ * ASORA_EINVAL, ASORA_ENOMEM or ASORA_EHIP.
  */
 asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, double sigma0_cm2,
                         double lg_tau_lo, double lg_tau_hi, int32_t n_tab, const double *P,

@@ -36,7 +36,7 @@ struct asora_ctx {
     int reading;
     TabParams tp;
     TabNode *d_tab;
-    float *d_nhi;
+    double *d_nhi;
     double *d_gacc;
     int *d_ctl;
     int *d_err;
@@ -161,18 +161,14 @@ extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, d
         return bail(fail(nullptr, ASORA_EHIP, "asora_init: hipGetDeviceProperties failed"));
     c->n_cu = prop.multiProcessorCount;
     c->max_lds = prop.sharedMemPerBlock;
-    int lds_optin = 0;
-    if (hipDeviceGetAttribute(&lds_optin, hipDeviceAttributeSharedMemPerBlockOptin, device) ==
-            hipSuccess && lds_optin > (int)c->max_lds)
-        c->max_lds = lds_optin;
     const long n3 = (long)N * N * N;
     if (hipMalloc(&c->d_tab, sizeof(TabNode) * n_tab) != hipSuccess ||
-        hipMalloc(&c->d_nhi, sizeof(float) * n3) != hipSuccess ||
+        hipMalloc(&c->d_nhi, sizeof(double) * n3) != hipSuccess ||
         hipMalloc(&c->d_gacc, sizeof(double) * n3) != hipSuccess ||
         hipMalloc(&c->d_ctl, sizeof(int) * kCtlSize) != hipSuccess ||
         hipMalloc(&c->d_err, sizeof(int)) != hipSuccess)
         return bail(fail(nullptr, ASORA_ENOMEM, "asora_init: device allocation of %.1f MB failed",
-                         12.0 * n3 / 1e6));
+                         16.0 * n3 / 1e6));
     if (hipMemcpy(c->d_tab, nodes.data(), sizeof(TabNode) * n_tab, hipMemcpyHostToDevice) !=
             hipSuccess ||
         hipMemset(c->d_err, 0, sizeof(int)) != hipSuccess ||
@@ -263,7 +259,7 @@ static asora_status get_plan(asora_ctx *c, int type, float R_cap, Plan *out)
     P.row_cap = (type == 0 ? 8 : 1) * (Qmax + 1);
     P.Qmax = Qmax;
     P.lds = fwd_lds_bytes(c->tp.n, P.ring_cap, P.row_cap);
-    if (P.lds > c->max_lds)
+    if (P.lds + 64 > c->max_lds)
         return fail(c, ASORA_ENOSYS,
                     "R_max=%.1f needs %zu bytes of LDS per work-group (limit %zu) for this table "
                     "and grid", R_cap, P.lds, c->max_lds);

@@ -24,13 +24,13 @@ __host__ __device__ __forceinline__ float rcp_nr(float x)
     return r * (2.f - x * r);
 }
 
-// 1/x in FP64 for a positive normal FP32 x: FP32 estimate and one FP64 Newton
-// step (relative error ~1e-14).
-__host__ __device__ __forceinline__ double rcp_f64(float x)
+// 1/x in FP64 for positive x within the FP32 range: FP32 estimate and one
+// FP64 Newton step (relative error ~1e-14, far cheaper than a full FP64
+// division).
+__host__ __device__ __forceinline__ double rcp_f64(double x)
 {
-    const double r = (double)rcp_approx(x);
-    const double xd = (double)x;
-    return r * (2.0 - xd * r);
+    const double r = (double)rcp_approx((float)x);
+    return r * (2.0 - x * r);
 }
 
 // --------------------------------------------------------------------------
@@ -283,8 +283,7 @@ struct CellCtx {
     int N, si, sj, sk;
     int reading;           // 0: directional source half path, 1: scalar
     float tau_w;           // <= 0: geometric weights
-    float sig_f, alpha_f;
-    double sigma0;
+    double sigma0, alpha;
     double half_col;       // n_HI(s) alpha / 2
     double coef;           // Q sigma0 / (4 pi alpha^2)
     const TabNode *tab;
@@ -292,7 +291,7 @@ struct CellCtx {
     const double *ring;    // [4][ring_cap] exit columns of shells q-1..q-3
     const int *rowbase;    // [4][row_cap]
     int ring_cap, row_cap;
-    const float *nHI;
+    const double *nHI;     // n_H x_HI, exact product of the FP32 inputs
 };
 
 struct CellOut {
@@ -319,7 +318,7 @@ __host__ __device__ __forceinline__ void cell_update(const CellCtx &X, int q, in
     const int dk = (o & 4) ? -cC : cC;
     const int N = X.N;
     const long cp = ((long)wrap(X.si + di, N) * N + wrap(X.sj + dj, N)) * N + wrap(X.sk + dk, N);
-    const float nhi = X.nHI[cp];
+    const double nhi = X.nHI[cp];
 
     // geometry: dominant axis, bilinear weights, path length
     const int m = cA > cB ? (cA > cC ? cA : cC) : (cB > cC ? cB : cC);
@@ -328,24 +327,23 @@ __host__ __device__ __forceinline__ void cell_update(const CellCtx &X, int q, in
     // the other two axes, in the order (i, j), (i, k), (j, k)
     const int cu = dd == 0 ? cB : cA;
     const int cv = dd == 2 ? cB : cC;
-    const float inv_m = rcp_approx((float)m);
+    const double inv_m = rcp_f64((double)m);
     // a = 1 (b = 1) must be exact: the weights of neighbours that leave the
     // dominant-axis layer then vanish exactly
-    const float a = cu == m ? 1.f : (float)cu * inv_m;
-    const float b = cv == m ? 1.f : (float)cv * inv_m;
+    const double a = cu == m ? 1.0 : (double)cu * inv_m;
+    const double b = cv == m ? 1.0 : (double)cv * inv_m;
     const int r2 = cA * cA + cB * cB + cC * cC;
-    const float ds = sqrtf((float)r2) * inv_m;
-    const float sw[4] = {(1.f - a) * (1.f - b), a * (1.f - b), (1.f - a) * b, a * b};
+    const double ds = sqrt((double)r2) * inv_m;
+    const double sw[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
 
-    // interpolate the entry column from the (up to) four neighbours:
-    // N_in = sum w M / sum w, a ratio of sums of non-negative FP64 terms, so
-    // the FP32 weights (relative error ~1e-7) bound its relative error by a
-    // few 1e-7 however different the neighbour columns are
-    double num = 0.0;
-    float W = 0.f;
+    // interpolate the entry column from the (up to) four neighbours,
+    // N_in = sum w M / sum w, in FP64: the column is carried along every
+    // characteristic, and at optical depths of 10^3 the rate moves ten times
+    // faster than the column, so the weights must not leave FP32 rounding in it
+    double num = 0.0, W = 0.0;
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
-        if (!(sw[n] > 0.f)) continue;
+        if (!(sw[n] > 0.0)) continue;
         // offsets: the dominant axis always, u for n = 1, 3 and v for n = 2, 3
         const int su = n & 1, sv = (n >> 1) & 1;
         const int eA = cA - (dd == 0 ? 1 : 0) - (su & (dd != 0 ? 1 : 0));
@@ -354,7 +352,7 @@ __host__ __device__ __forceinline__ void cell_update(const CellCtx &X, int q, in
         const int qn = q - 1 - su - sv;
         double M;
         if (qn == 0) {
-            M = X.reading == 0 ? X.half_col * (double)ds : X.half_col;
+            M = X.reading == 0 ? X.half_col * ds : X.half_col;
         } else {
             int o2 = o;
             if (X.pc.kind == 0) {   // half-open octants: zero planes live in the + octant
@@ -367,14 +365,14 @@ __host__ __device__ __forceinline__ void cell_update(const CellCtx &X, int q, in
             const int nrow = ord * (qn + 1) + eA;
             M = X.ring[sl * X.ring_cap + X.rowbase[sl * X.row_cap + nrow] + eB];
         }
-        float wn = sw[n];
-        if (X.tau_w > 0.f) wn *= rcp_nr(fmaxf(X.sig_f * (float)M, X.tau_w));
-        num += (double)wn * M;
+        double wn = sw[n];
+        if (X.tau_w > 0.f) wn *= rcp_f64(fmax(X.sigma0 * M, (double)X.tau_w));
+        num += wn * M;
         W += wn;
     }
     const double Nin = num * rcp_f64(W);
-    const float dN = nhi * X.alpha_f * ds;
-    const double Nout = Nin + (double)dN;
+    const double dN = nhi * X.alpha * ds;
+    const double Nout = Nin + dN;
 
     // ownership: ghosts of a closed octant, tied cells of a pyramid
     bool owned = true;
@@ -386,7 +384,7 @@ __host__ __device__ __forceinline__ void cell_update(const CellCtx &X, int q, in
     if (owned) {
         const double ta = X.sigma0 * Nin;
         if (ta < X.tp.tau_hi) {
-            const float nd = neg_divdiff(X.tab, X.tp, ta, X.sigma0 * (double)dN);
+            const float nd = neg_divdiff(X.tab, X.tp, ta, X.sigma0 * dN);
             if (nd > 0.f) G = X.coef * (double)(nd * rcp_approx((float)r2));
         }
     }
@@ -401,9 +399,9 @@ __host__ __device__ __forceinline__ void cell_update(const CellCtx &X, int q, in
 // alpha^3.
 __host__ __device__ __forceinline__ double source_cell_rate(const TabNode *T, const TabParams &tp,
                                                             double sigma0, double alpha, double Q,
-                                                            float n_s)
+                                                            double n_s)
 {
-    const double tau_s = sigma0 * (double)n_s * alpha * 0.5;
+    const double tau_s = sigma0 * n_s * alpha * 0.5;
     const float nd = neg_divdiff(T, tp, 0.0, tau_s);
     return Q * sigma0 / (2.0 * alpha * alpha) * (double)nd;
 }

@@ -17,12 +17,11 @@ struct FwdArgs {
     int N;
     Extent ex;
     double alpha, sigma0;
-    float alpha_f, sig_f;   // FP32 copies for the weights and the in-cell column
     float tau_w;            // weight floor, <= 0: geometric weights
     int reading;            // 0: directional source half path, 1: scalar
     TabParams tp;
     const TabNode *tab;
-    const float *nHI;
+    const double *nHI;
     double *gacc;
     double *coldens;
     const int32_t *ijk;
@@ -62,7 +61,7 @@ __device__ void sweep_piece(const FwdArgs &A, const Lds &L, int src, int p, int 
     const Piece pc = make_piece(A.type, p);
     const int Qmax = max_shell(Rsq, A.ex);
     const long cs = ((long)si * N + sj) * N + sk;
-    const float n_s = A.nHI[cs];
+    const double n_s = A.nHI[cs];
 
     CellCtx X;
     X.pc = pc;
@@ -72,10 +71,9 @@ __device__ void sweep_piece(const FwdArgs &A, const Lds &L, int src, int p, int 
     X.sk = sk;
     X.reading = A.reading;
     X.tau_w = A.tau_w;
-    X.sig_f = A.sig_f;
-    X.alpha_f = A.alpha_f;
     X.sigma0 = A.sigma0;
-    X.half_col = (double)n_s * A.alpha * 0.5;
+    X.alpha = A.alpha;
+    X.half_col = n_s * A.alpha * 0.5;
     X.coef = Q * A.sigma0 / (4.0 * M_PI * A.alpha * A.alpha);
     X.tab = L.tab;
     X.tp = A.tp;
@@ -199,12 +197,12 @@ __global__ __launch_bounds__(kWG) void fwd_plain(FwdArgs A)
 // ---- small kernels: n_HI, accumulators, bucketing, final conversion --------
 
 __global__ void prologue_kernel(const float *__restrict__ nH, const float *__restrict__ xHI,
-                                float *__restrict__ nHI, double *__restrict__ gacc,
+                                double *__restrict__ nHI, double *__restrict__ gacc,
                                 double *__restrict__ coldens, long n3, int *ctl, int nctl)
 {
     const long stride = (long)gridDim.x * blockDim.x;
     for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < n3; c += stride) {
-        nHI[c] = nH[c] * xHI[c];
+        nHI[c] = (double)nH[c] * (double)xHI[c];   // exact
         gacc[c] = 0.0;
         if (coldens) coldens[c] = 0.0;
     }
@@ -278,7 +276,7 @@ __global__ void finalize_kernel(const double *__restrict__ gacc, float *__restri
 // ---------------------------------------------------------------------------
 // Host-side launchers (called from the C ABI in asora_api.hip)
 // ---------------------------------------------------------------------------
-hipError_t launch_prologue(hipStream_t st, const float *nH, const float *xHI, float *nHI,
+hipError_t launch_prologue(hipStream_t st, const float *nH, const float *xHI, double *nHI,
                            double *gacc, double *coldens, long n3, int *ctl, int nctl, int n_cu)
 {
     const int blocks = n_cu * 8;
@@ -310,8 +308,6 @@ static FwdArgs make_args(const FwdLaunch &F)
     A.ex = make_extent(F.N);
     A.alpha = F.alpha;
     A.sigma0 = F.sigma0;
-    A.alpha_f = (float)F.alpha;
-    A.sig_f = (float)F.sigma0;
     A.tau_w = F.tau_w;
     A.reading = F.reading;
     A.tp = F.tp;
@@ -343,11 +339,15 @@ size_t fwd_lds_bytes(int n_tab, int ring_cap, int row_cap)
 
 hipError_t fwd_configure(size_t max_lds)
 {
-    hipError_t e = hipFuncSetAttribute((const void *)fwd_persistent,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)max_lds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void *)fwd_plain, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)max_lds);
+    // Best effort: the dynamic LDS limit of a kernel defaults to what the device
+    // offers; raising it explicitly is only an opt-in where a runtime needs it.
+    const int dyn = (int)max_lds - 64;   // leave room for the static LDS words
+    (void)hipFuncSetAttribute((const void *)fwd_persistent,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)fwd_plain, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              dyn);
+    (void)hipGetLastError();
+    return hipSuccess;
 }
 
 hipError_t fwd_occupancy(size_t lds, int *blocks_per_cu)

@@ -23,7 +23,7 @@ struct FwdLaunch {
     int reading;
     TabParams tp;
     const TabNode *tab;
-    const float *nHI;
+    const double *nHI;
     double *gacc;
     double *coldens;
     const int32_t *ijk;
@@ -37,7 +37,7 @@ struct FwdLaunch {
     int ring_cap, row_cap;
 };
 
-hipError_t launch_prologue(hipStream_t st, const float *nH, const float *xHI, float *nHI,
+hipError_t launch_prologue(hipStream_t st, const float *nH, const float *xHI, double *nHI,
                            double *gacc, double *coldens, long n3, int *ctl, int nctl, int n_cu);
 hipError_t launch_bucketing(hipStream_t st, const float *R, const int32_t *ijk, long nsrc, int N,
                             float R_max, float R_whole, float R_oct, int *keys, int *ctl,

@@ -54,8 +54,8 @@ extern "C" int hc_raytrace(int N, double alpha, double sigma0, int n, double lg_
     std::vector<TabNode> T(n);
     prepare_table(n, lg_lo, lg_hi, P, dP, &tp, T.data());
     const long n3 = (long)N * N * N;
-    std::vector<float> nhi(n3);
-    for (long c = 0; c < n3; ++c) nhi[c] = nH[c] * xHI[c];
+    std::vector<double> nhi(n3);
+    for (long c = 0; c < n3; ++c) nhi[c] = (double)nH[c] * (double)xHI[c];
     const Extent ex = make_extent(N);
     for (long s = 0; s < nsrc; ++s) {
         const float Rs = R[s];
@@ -85,10 +85,9 @@ extern "C" int hc_raytrace(int N, double alpha, double sigma0, int n, double lg_
             X.sk = sk;
             X.reading = reading;
             X.tau_w = (float)(tau_w > 0 && std::isfinite(tau_w) ? tau_w : 0.0);
-            X.sig_f = (float)sigma0;
-            X.alpha_f = (float)alpha;
             X.sigma0 = sigma0;
-            X.half_col = (double)nhi[cs] * alpha * 0.5;
+            X.alpha = alpha;
+            X.half_col = nhi[cs] * alpha * 0.5;
             X.coef = Q[s] * sigma0 / (4.0 * M_PI * alpha * alpha);
             X.tab = T.data();
             X.tp = tp;
