@@ -57,6 +57,8 @@ typedef enum {
 
 /* asora_raytrace / asora_raytrace_backward flags */
 #define ASORA_ACCUMULATE 0x1u  /* gamma += result (forward); gradients += (backward) */
+#define ASORA_PROFILE    0x4u  /* record HIP events around the sweep kernels and the
+                                  whole call on `stream`; read with asora_profile   */
 #define ASORA_PLAIN      0x2u  /* one kernel launch per source, in input order: the
                                   unbatched baseline form (Section 3.3, one block per
                                   source).  Default: all sources in one persistent
@@ -77,7 +79,7 @@ typedef enum {
  * beyond the table).
  *
  *   out          host, receives the new context.
- *   N            grid size (cells per side), 1 <= N <= 2048.
+ *   N            grid size (cells per side), 1 <= N <= 1600 (N^3 < 2^32).
  *   cell_cm      cell size alpha in cm (> 0).
  *   sigma0_cm2   HI cross-section at the threshold (> 0); tau = sigma0 N_HI.
  *   lg_tau_lo, lg_tau_hi   log10 tau of the first and last node (lo < hi).
@@ -140,21 +142,33 @@ asora_status asora_raytrace(asora_ctx *ctx, const float *n_H, const float *x_HI,
  * asora_raytrace_backward -- adjoint of asora_raytrace.
  *
  * Given dL/dgamma, computes dL/dn_H, dL/dx_HI and dL/dQ of the forward map
- * with the same inputs.  The shells of each source are swept from the
- * outermost inward; the column densities of a source are recomputed into
- * scratch memory before its reverse sweep, so no forward state is kept
- * between the calls.  Same argument conventions as asora_raytrace.
+ * with the same inputs (reverse mode through eq. sugg, the in-cell column
+ * and the interpolation of eq. interp, with the optical-depth weights
+ * differentiated as functions of the neighbour columns).  For every source
+ * piece the exit columns are first recomputed shell by shell into scratch
+ * memory, then the shells are swept from the outermost inward and every
+ * cell pushes the adjoint of its entry column to its neighbours, so no
+ * forward state is kept between the calls.
  *
- *   dL_dgamma    device, N^3 floats.
+ *   n_H, x_HI, n_src, src_ijk, src_Q, src_R, R_max: as for asora_raytrace.
+ *   dL_dgamma    device, N^3 doubles (FP64: a cell's gradient can be a sum of
+ *                large terms of both signs, so FP32 rounding of dL/dgamma
+ *                would be amplified).
  *   dL_dnH, dL_dxHI   device, N^3 floats, outputs (overwritten unless
+ *                ASORA_ACCUMULATE); accumulated in FP64, rounded once.
+ *   dL_dQ        device, n_src doubles, output (overwritten unless
  *                ASORA_ACCUMULATE).
- *   dL_dQ        device, n_src doubles, output (overwritten unless ACCUMULATE).
- * Cells with n_HI = 0 use the limit of the rate for a vanishing in-cell
- * optical depth.
+ *   flags        ASORA_ACCUMULATE | ASORA_PROFILE (asora_profile then reports
+ *                the reverse sweep as sweep_ms).
+ * Scratch: about 16 N^3 bytes more than the forward, plus the stored columns
+ * of the pieces in flight (allocated at the first call, grown on demand).
+ * The derivative of the rate is taken on the interpolant as it is (a cubic
+ * spline, so its second derivative is piecewise continuous); at exactly zero
+ * n_HI the limit of the rate for vanishing in-cell optical depth is used.
  */
 asora_status asora_raytrace_backward(asora_ctx *ctx, const float *n_H, const float *x_HI,
                                      int64_t n_src, const int32_t *src_ijk, const double *src_Q,
-                                     const float *src_R, float R_max, const float *dL_dgamma,
+                                     const float *src_R, float R_max, const double *dL_dgamma,
                                      float *dL_dnH, float *dL_dxHI, double *dL_dQ,
                                      uint32_t flags, void *stream);
 
@@ -181,6 +195,35 @@ asora_status asora_table_grey(int32_t n, double lg_lo, double lg_hi, double *P, 
  * Clears the record.
  */
 asora_status asora_check(asora_ctx *ctx, void *stream);
+
+/*
+ * asora_set_tuning -- scheduling parameters of the sweep (results do not
+ * depend on them beyond the order of floating-point sums).  Sources with
+ * R <= R_whole are swept whole by one wave; R_whole < R <= R_oct as eight
+ * closed octants; larger R as 24 octant x dominant-axis pyramids (cells on
+ * shared planes are computed by each piece and owned by one).  max_waves
+ * (1..16) caps the waves per work-group that share one LDS copy of the table.
+ * Values <= 0 keep the current setting.  asora_autotune measures and sets
+ * them.  ASORA_EINVAL if R_oct < R_whole.
+ */
+asora_status asora_set_tuning(asora_ctx *ctx, float R_whole, float R_oct, int32_t max_waves);
+
+/*
+ * asora_get_tuning -- the current scheduling parameters (any pointer may be
+ * NULL).
+ */
+asora_status asora_get_tuning(const asora_ctx *ctx, float *R_whole, float *R_oct,
+                              int32_t *max_waves);
+
+/*
+ * asora_profile -- durations (ms) of the most recent call made with
+ * ASORA_PROFILE on ctx: sweep_ms covers the ray-tracing sweep kernels only
+ * (all piece kinds; for ASORA_PLAIN every per-source launch), total_ms the
+ * whole call (n_HI and accumulator set-up, scheduling sort, sweep, final
+ * conversion).  Waits for those events.  Either pointer may be NULL.
+ * ASORA_ESTATE if no profiled call was made.
+ */
+asora_status asora_profile(asora_ctx *ctx, double *sweep_ms, double *total_ms);
 
 /* asora_last_error -- text of the most recent error on ctx (or of the most
  * recent failed asora_init when ctx is NULL).  Owned by the library. */

@@ -24,7 +24,7 @@ __all__ = ["Asora", "AsoraError", "raytrace", "table_blackbody", "table_grey", "
            "SIGMA0", "ACCUMULATE", "PLAIN", "HALFPATH_SCALAR"]
 
 SIGMA0 = 6.3e-18          # HI cross-section at 13.6 eV, cm^2
-ACCUMULATE, PLAIN = 0x1, 0x2
+ACCUMULATE, PLAIN, PROFILE = 0x1, 0x2, 0x4
 HALFPATH_SCALAR = 0x1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -52,6 +52,12 @@ _lib.asora_table_grey.restype = _c_int
 _lib.asora_table_grey.argtypes = [_c_int, _c_d, _c_d, _p, _p]
 _lib.asora_check.restype = _c_int
 _lib.asora_check.argtypes = [_p, _p]
+_lib.asora_profile.restype = _c_int
+_lib.asora_profile.argtypes = [_p, ctypes.POINTER(_c_d), ctypes.POINTER(_c_d)]
+_lib.asora_set_tuning.restype = _c_int
+_lib.asora_set_tuning.argtypes = [_p, _c_f, _c_f, _c_int]
+_lib.asora_get_tuning.restype = _c_int
+_lib.asora_get_tuning.argtypes = [_p, ctypes.POINTER(_c_f), ctypes.POINTER(_c_f), ctypes.POINTER(_c_int)]
 _lib.asora_last_error.restype = ctypes.c_char_p
 _lib.asora_last_error.argtypes = [_p]
 _lib.asora_free.restype = _c_int
@@ -155,14 +161,14 @@ class Asora:
         return ijk, Q, R, float(R_max), n
 
     def raytrace(self, n_H, x_HI, ijk, Q, R=None, R_max=None, plain=False, coldens=False,
-                 out=None, accumulate=False, stream=None):
+                 out=None, accumulate=False, profile=False, stream=None):
         """Gamma (float32 cuda, N^3) for the sources; with coldens=True (one
         source) also the entry column N_in (float64, N^3)."""
         ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
         dev = n_H.device
         gamma = out if out is not None else torch.empty(self.N ** 3, dtype=torch.float32, device=dev)
         cd = torch.empty(self.N ** 3, dtype=torch.float64, device=dev) if coldens else None
-        flags = (PLAIN if plain else 0) | (ACCUMULATE if accumulate else 0)
+        flags = (PLAIN if plain else 0) | (ACCUMULATE if accumulate else 0) | (PROFILE if profile else 0)
         st = _lib.asora_raytrace(self._h, _dptr(n_H), _dptr(x_HI), n, _dptr(ijk), _dptr(Q),
                                  _dptr(R), R_max, _dptr(gamma), _dptr(cd), flags,
                                  _stream_ptr(stream))
@@ -170,20 +176,35 @@ class Asora:
         shape = (self.N,) * 3
         return (gamma.view(shape), cd.view(shape)) if coldens else gamma.view(shape)
 
-    def backward(self, n_H, x_HI, ijk, Q, R, dL_dgamma, R_max=None, stream=None):
-        """(dL/dn_H, dL/dx_HI, dL/dQ) for the given dL/dgamma."""
+    def backward(self, n_H, x_HI, ijk, Q, R, dL_dgamma, R_max=None, profile=False, stream=None):
+        """(dL/dn_H, dL/dx_HI, dL/dQ) for the given dL/dgamma (converted to FP64)."""
         ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
         dev = n_H.device
-        g = dL_dgamma.to(dev, torch.float32).contiguous()
+        g = dL_dgamma.to(dev, torch.float64).contiguous()
         dn = torch.empty(self.N ** 3, dtype=torch.float32, device=dev)
         dx = torch.empty_like(dn)
         dq = torch.empty(n, dtype=torch.float64, device=dev)
         st = _lib.asora_raytrace_backward(self._h, _dptr(n_H), _dptr(x_HI), n, _dptr(ijk),
                                           _dptr(Q), _dptr(R), R_max, _dptr(g), _dptr(dn),
-                                          _dptr(dx), _dptr(dq), 0, _stream_ptr(stream))
+                                          _dptr(dx), _dptr(dq), PROFILE if profile else 0,
+                                          _stream_ptr(stream))
         _raise(st, self._h)
         shape = (self.N,) * 3
         return dn.view(shape), dx.view(shape), dq
+
+    def profile(self):
+        """(sweep_ms, total_ms) of the last call made with profile=True."""
+        a, b = _c_d(), _c_d()
+        _raise(_lib.asora_profile(self._h, ctypes.byref(a), ctypes.byref(b)), self._h)
+        return a.value, b.value
+
+    def set_tuning(self, R_whole=0.0, R_oct=0.0, max_waves=0):
+        _raise(_lib.asora_set_tuning(self._h, float(R_whole), float(R_oct), int(max_waves)), self._h)
+
+    def get_tuning(self):
+        a, b, w = _c_f(), _c_f(), _c_int()
+        _raise(_lib.asora_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(w)), self._h)
+        return a.value, b.value, w.value
 
     def check(self, stream=None):
         """Wait for the stream; raise if a kernel flagged a source."""
@@ -202,7 +223,7 @@ class _RaytraceFn(torch.autograd.Function):
         n_H, x_HI, ijk, Q, R = fctx.saved_tensors
         R = R if fctx.has_R else None
         dn, dx, dq = fctx.asora.backward(n_H.detach(), x_HI.detach(), ijk, Q.detach(), R,
-                                         g.contiguous(), R_max=fctx.R_max)
+                                         g.double().contiguous(), R_max=fctx.R_max)
         return None, dn, dx, None, dq.to(Q.dtype), None, None
 
 

@@ -1,0 +1,315 @@
+// asora_adj.hip -- adjoint (reverse-mode) ray-tracing kernels for gfx950.
+//
+// One wave per source piece, like the forward wave kernels.  For each piece
+// the wave first recomputes the exit column of every cell, shell by shell
+// (the forward sweep without the rate), keeping the last four shells in an
+// LDS ring and storing every shell to the wave's own scratch in global
+// memory.  It then sweeps the shells from the outermost inward: the exit
+// columns of shells q-1..q-3 (the neighbours of shell q) come back from the
+// scratch into the LDS ring, and the adjoints of the exit columns of shells
+// q..q-3 live in a second LDS ring that the cells of shell q update with LDS
+// atomics when they push their entry-column adjoint to their neighbours.
+// dL/dn_HI goes to an FP64 N^3 accumulator with hardware atomics; dL/dQ is
+// reduced over the wave and added once per piece.
+#include "asora_dev.h"
+#include "asora_internal.h"
+
+namespace asora {
+
+struct AdjArgs {
+    int N;
+    Extent ex;
+    double alpha, sigma0, coef_unit;
+    float tau_w;
+    int reading;
+    TabParams tp;
+    const TabNode *tab;
+    const double *m64;       // FP64 node slopes
+    const double *nHI;
+    const double *gbar;      // dL/dGamma, N^3
+    double *nbar;            // dL/dn_HI accumulator, N^3
+    double *qbar;            // dL/dQ, n_src
+    const int32_t *ijk;
+    const double *Q;
+    const float *R;
+    float R_cap;
+    const int *order;
+    const int *seg;
+    int *counter;
+    int *err;
+    int ring_cap, row_cap, shell_cap;
+    int region_bytes;
+    double *store;           // per-wave stored exit columns
+    long store_stride;       // doubles per wave
+};
+
+template <int TYPE>
+__device__ void adjoint_piece_wave(const AdjArgs &A, const TabNode *T, char *region, double *store,
+                                   int src, int p, int lane)
+{
+    const int N = A.N;
+    const int si = A.ijk[3 * src], sj = A.ijk[3 * src + 1], sk = A.ijk[3 * src + 2];
+    const float R = A.R ? A.R[src] : A.R_cap;
+    if (!(R >= 0.f && R <= A.R_cap) || si < 0 || si >= N || sj < 0 || sj >= N || sk < 0 ||
+        sk >= N) {
+        if (lane == 0) atomicOr(A.err, 1);
+        return;
+    }
+    const double Q = A.Q[src];
+    const int Rsq = (int)floor((double)R * (double)R);
+    const Piece pc = make_piece(TYPE, p);
+    const int Qmax = max_shell(Rsq, A.ex);
+    const uint32_t cs = ((uint32_t)si * (uint32_t)N + (uint32_t)sj) * (uint32_t)N + (uint32_t)sk;
+    const double n_s = A.nHI[cs];
+
+    // LDS region of this wave
+    double *ring = (double *)region;                        // [4][ring_cap] exit columns
+    double *abar = ring + 4 * (size_t)A.ring_cap;           // [4][ring_cap] their adjoints
+    int *rowbase = (int *)(abar + 4 * (size_t)A.ring_cap);  // [4][row_cap]
+    int *rowstart = rowbase + 4 * A.row_cap;                // [4][row_cap + 1]
+    int *shoff = rowstart + 4 * (A.row_cap + 1);            // [shell_cap + 2] offsets in store
+
+    CellCtx X;
+    X.pc = pc;
+    X.N = N;
+    X.si = si;
+    X.sj = sj;
+    X.sk = sk;
+    X.reading = A.reading;
+    X.tau_w = A.tau_w;
+    X.sigma0 = A.sigma0;
+    X.alpha = A.alpha;
+    X.half_col = n_s * A.alpha * 0.5;
+    X.coef = Q * A.coef_unit;
+    X.tab = T;
+    X.m64 = A.m64;
+    X.tp = A.tp;
+    X.ring = ring;
+    X.rowbase = rowbase;
+    X.ring_cap = A.ring_cap;
+    X.row_cap = A.row_cap;
+    X.nHI = A.nHI;
+
+    // ---- forward: exit columns of every shell, kept and stored
+    if (lane == 0) shoff[1] = 0;
+    wave_sync();
+    for (int q = 1; q <= Qmax; ++q) {
+        const int slot = q & 3;
+        int *rs_q = rowstart + slot * (A.row_cap + 1);
+        int *rb_q = rowbase + slot * A.row_cap;
+        const int total = wave_build_rows(pc, A.ex, Rsq, q, lane, rs_q, rb_q);
+        wave_sync();
+        const int off = shoff[q];
+        const int nrows = pc.n_oct * (q + 1);
+        double *ring_q = ring + slot * (size_t)A.ring_cap;
+        for (int g = lane; g < total; g += 64) {
+            const int row = find_row(rs_q, nrows, g);
+            CellOut co;
+            cell_update<false>(X, q, g, row, rb_q[row], co);
+            ring_q[g] = co.Nout;
+            store[off + g] = co.Nout;
+        }
+        if (lane == 0) shoff[q + 1] = off + total;
+        wave_sync();
+    }
+
+    // ---- reverse
+    for (int k = lane; k < 4 * A.ring_cap; k += 64) abar[k] = 0.0;
+    wave_sync();
+    double nb_src = 0.0, qb = 0.0;
+    for (int q = Qmax; q >= 1; --q) {
+        const int slot = q & 3;
+        if (q < Qmax && q - 3 >= 1) {
+            // shell q-3 enters the rings (its slot held shell q+1, finished)
+            const int q3 = q - 3, s3 = q3 & 3;
+            const int t3 = wave_build_rows(pc, A.ex, Rsq, q3, lane, rowstart + s3 * (A.row_cap + 1),
+                                           rowbase + s3 * A.row_cap);
+            const int off3 = shoff[q3];
+            for (int g = lane; g < t3; g += 64) {
+                ring[s3 * (size_t)A.ring_cap + g] = store[off3 + g];
+                abar[s3 * (size_t)A.ring_cap + g] = 0.0;
+            }
+            wave_sync();
+        }
+        const int *rs_q = rowstart + slot * (A.row_cap + 1);
+        const int *rb_q = rowbase + slot * A.row_cap;
+        const int nrows = pc.n_oct * (q + 1);
+        const int total = shoff[q + 1] - shoff[q];
+        for (int g = lane; g < total; g += 64) {
+            const int row = find_row(rs_q, nrows, g);
+            CellAdj ca;
+            cell_adjoint(X, q, g, row, rb_q[row], abar[slot * (size_t)A.ring_cap + g], A.gbar, ca);
+            if (ca.nbar != 0.0) unsafeAtomicAdd(&A.nbar[ca.cp], ca.nbar);
+            nb_src += ca.nbar_src;
+            qb += ca.qbar;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (ca.slot[k] >= 0)
+                    atomicAdd(&abar[(ca.qn[k] & 3) * (size_t)A.ring_cap + ca.slot[k]], ca.Mbar[k]);
+        }
+        wave_sync();
+    }
+    const bool src_owner = (pc.kind == 0) || (pc.oct == 0 && (pc.dom < 0 || pc.dom == 2));
+    if (src_owner && lane == 0) {
+        double nb, q1;
+        source_cell_adjoint(T, A.m64, A.tp, A.sigma0, A.alpha, Q, n_s, A.gbar[cs], &nb, &q1);
+        nb_src += nb;
+        qb += q1;
+    }
+    // wave sums
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        nb_src += __shfl_xor(nb_src, off, 64);
+        qb += __shfl_xor(qb, off, 64);
+    }
+    if (lane == 0) {
+        if (nb_src != 0.0) unsafeAtomicAdd(&A.nbar[cs], nb_src);
+        if (qb != 0.0) unsafeAtomicAdd(&A.qbar[src], qb / Q);
+    }
+}
+
+template <int TYPE>
+__global__ __launch_bounds__(512) void adj_wave(AdjArgs A)
+{
+    extern __shared__ __align__(16) char smem[];
+    if (A.seg[TYPE + 1] == A.seg[TYPE]) return;   // no sources of this kind
+    TabNode *T = (TabNode *)smem;
+    {
+        const int4 *s = (const int4 *)A.tab;
+        int4 *d = (int4 *)smem;
+        for (int k = threadIdx.x; k < A.tp.n; k += blockDim.x) d[k] = s[k];
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int waves = blockDim.x >> 6;
+    char *region = smem + (size_t)A.tp.n * sizeof(TabNode) + (size_t)wave * A.region_bytes;
+    double *store = A.store + (size_t)(blockIdx.x * waves + wave) * A.store_stride;
+    constexpr int npieces = TYPE == 0 ? 1 : (TYPE == 1 ? 8 : 24);
+    const int base = A.seg[TYPE];
+    const long nitems = (long)(A.seg[TYPE + 1] - base) * npieces;
+    for (;;) {
+        const int item = next_item(A.counter, lane);
+        if (item >= nitems) break;
+        const int src = A.order[base + item / npieces];
+        adjoint_piece_wave<TYPE>(A, T, region, store, src, item % npieces, lane);
+    }
+}
+
+__global__ void adj_prologue_kernel(const float *__restrict__ nH, const float *__restrict__ xHI,
+                                    double *__restrict__ nHI, double *__restrict__ nbar, long n3,
+                                    double *__restrict__ qbar, long nsrc, int zero_q, int *ctl,
+                                    int nctl)
+{
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < n3; c += stride) {
+        nHI[c] = (double)nH[c] * (double)xHI[c];
+        nbar[c] = 0.0;
+    }
+    if (zero_q)
+        for (long s = blockIdx.x * (long)blockDim.x + threadIdx.x; s < nsrc; s += stride) qbar[s] = 0.0;
+    if (blockIdx.x == 0)
+        for (int k = threadIdx.x; k < nctl; k += blockDim.x) ctl[k] = 0;
+}
+
+// dL/dn_H = x_HI dL/dn_HI, dL/dx_HI = n_H dL/dn_HI
+__global__ void adj_finalize_kernel(const double *__restrict__ nbar, const float *__restrict__ nH,
+                                    const float *__restrict__ xHI, float *__restrict__ dnH,
+                                    float *__restrict__ dxHI, long n3, int accumulate)
+{
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < n3; c += stride) {
+        const double g = nbar[c];
+        const float a = (float)(g * (double)xHI[c]);
+        const float b = (float)(g * (double)nH[c]);
+        dnH[c] = accumulate ? dnH[c] + a : a;
+        dxHI[c] = accumulate ? dxHI[c] + b : b;
+    }
+}
+
+// ---------------------------------------------------------------------------
+size_t adj_region_bytes(int ring_cap, int row_cap, int shell_cap)
+{
+    const size_t b = 8 * (size_t)ring_cap * sizeof(double) +
+                     (4 * (size_t)row_cap + 4 * ((size_t)row_cap + 1) + (size_t)shell_cap + 2) *
+                         sizeof(int);
+    return (b + 15) & ~(size_t)15;
+}
+
+static const void *adj_fn(int type)
+{
+    return type == 0 ? (const void *)adj_wave<0>
+                     : (type == 1 ? (const void *)adj_wave<1> : (const void *)adj_wave<2>);
+}
+
+hipError_t adj_configure(size_t max_lds)
+{
+    const int dyn = (int)max_lds - 64;
+    for (int t = 0; t < 3; ++t)
+        (void)hipFuncSetAttribute(adj_fn(t), hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipGetLastError();
+    return hipSuccess;
+}
+
+hipError_t adj_occupancy(int type, int waves, size_t lds, int *blocks_per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, adj_fn(type), waves * 64, lds);
+}
+
+hipError_t launch_adj_prologue(hipStream_t st, const float *nH, const float *xHI, double *nHI,
+                               double *nbar, long n3, double *qbar, long nsrc, int zero_q, int *ctl,
+                               int nctl, int n_cu)
+{
+    hipLaunchKernelGGL(adj_prologue_kernel, dim3(n_cu * 8), dim3(256), 0, st, nH, xHI, nHI, nbar,
+                       n3, qbar, nsrc, zero_q, ctl, nctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L)
+{
+    AdjArgs A;
+    A.N = L.N;
+    A.ex = make_extent(L.N);
+    A.alpha = L.alpha;
+    A.sigma0 = L.sigma0;
+    A.coef_unit = L.sigma0 / (4.0 * M_PI * L.alpha * L.alpha);
+    A.tau_w = L.tau_w;
+    A.reading = L.reading;
+    A.tp = L.tp;
+    A.tab = L.tab;
+    A.m64 = L.m64;
+    A.nHI = L.nHI;
+    A.gbar = L.gbar;
+    A.nbar = L.nbar;
+    A.qbar = L.qbar;
+    A.ijk = L.ijk;
+    A.Q = L.Q;
+    A.R = L.R;
+    A.R_cap = L.R_cap;
+    A.order = L.order;
+    A.seg = L.ctl + kCtlSeg;
+    A.counter = L.ctl + kCtlCounter + L.type;
+    A.err = L.err;
+    A.ring_cap = L.ring_cap;
+    A.row_cap = L.row_cap;
+    A.shell_cap = L.shell_cap;
+    A.region_bytes = (int)adj_region_bytes(L.ring_cap, L.row_cap, L.shell_cap);
+    A.store = L.store;
+    A.store_stride = L.store_stride;
+    const size_t lds = (size_t)L.tp.n * sizeof(TabNode) + (size_t)L.waves * A.region_bytes;
+    switch (L.type) {
+    case 0: hipLaunchKernelGGL(adj_wave<0>, dim3(L.grid), dim3(64 * L.waves), lds, st, A); break;
+    case 1: hipLaunchKernelGGL(adj_wave<1>, dim3(L.grid), dim3(64 * L.waves), lds, st, A); break;
+    default: hipLaunchKernelGGL(adj_wave<2>, dim3(L.grid), dim3(64 * L.waves), lds, st, A); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_finalize(hipStream_t st, const double *nbar, const float *nH, const float *xHI,
+                               float *dnH, float *dxHI, long n3, int accumulate, int n_cu)
+{
+    hipLaunchKernelGGL(adj_finalize_kernel, dim3(n_cu * 8), dim3(256), 0, st, nbar, nH, xHI, dnH,
+                       dxHI, n3, accumulate);
+    return hipGetLastError();
+}
+
+}  // namespace asora

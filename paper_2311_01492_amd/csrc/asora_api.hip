@@ -23,6 +23,9 @@ struct PlanKey {
 
 struct Plan {
     int ring_cap, row_cap, Qmax;
+    long piece_cells;   // largest number of cells of one piece (adjoint scratch)
+    int wave_mode;   // 1: one wave per piece (waves per work-group below); 0: one work-group per piece
+    int waves;
     size_t lds;
     int grid;
 };
@@ -36,6 +39,7 @@ struct asora_ctx {
     int reading;
     TabParams tp;
     TabNode *d_tab;
+    double *d_m64;          // FP64 node slopes for the adjoint
     double *d_nhi;
     double *d_gacc;
     int *d_ctl;
@@ -46,7 +50,14 @@ struct asora_ctx {
     int n_cu;
     size_t max_lds;
     float R_whole, R_oct;   // radius thresholds of the piece types
+    int min_waves, max_waves;   // wave-per-piece mode bounds
     std::map<PlanKey, Plan> plans;
+    double *d_nbar;         // dL/dn_HI accumulator (allocated by the first backward call)
+    double *d_store;        // stored exit columns of the adjoint pieces in flight
+    size_t store_cap;       // doubles
+    std::map<PlanKey, Plan> adj_plans;
+    hipEvent_t ev[4];       // total start, sweep start, sweep stop, total stop
+    bool ev_ready, profiled;
     std::string err;
 };
 
@@ -109,7 +120,7 @@ extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, d
 {
     if (!out) return fail(nullptr, ASORA_EINVAL, "asora_init: out is NULL");
     *out = nullptr;
-    if (N < 1 || N > 2048) return fail(nullptr, ASORA_EINVAL, "asora_init: N=%d out of [1,2048]", N);
+    if (N < 1 || N > 1600) return fail(nullptr, ASORA_EINVAL, "asora_init: N=%d out of [1,1600]", N);
     if (!(cell_cm > 0) || !std::isfinite(cell_cm))
         return fail(nullptr, ASORA_EINVAL, "asora_init: cell size must be positive and finite");
     if (!(sigma0_cm2 > 0) || !std::isfinite(sigma0_cm2))
@@ -143,12 +154,15 @@ extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, d
     c->tau_w = (tau_weight_floor > 0 && std::isfinite(tau_weight_floor)) ? tau_weight_floor : 0.0;
     c->flags = flags;
     c->reading = (flags & ASORA_INIT_SOURCE_HALFPATH_SCALAR) ? 1 : 0;
-    c->R_whole = 10.f;
-    c->R_oct = 30.f;
+    c->R_whole = 6.f;
+    c->R_oct = 15.f;
+    c->min_waves = 4;
+    c->max_waves = 16;
 
     // table in the kernels' form
     std::vector<TabNode> nodes(n_tab);
-    prepare_table(n_tab, lg_tau_lo, lg_tau_hi, P, dPdtau, &c->tp, nodes.data());
+    std::vector<double> m64(n_tab);
+    prepare_table(n_tab, lg_tau_lo, lg_tau_hi, P, dPdtau, &c->tp, nodes.data(), m64.data());
 
     auto bail = [&](asora_status st) {
         asora_free(c);
@@ -163,6 +177,7 @@ extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, d
     c->max_lds = prop.sharedMemPerBlock;
     const long n3 = (long)N * N * N;
     if (hipMalloc(&c->d_tab, sizeof(TabNode) * n_tab) != hipSuccess ||
+        hipMalloc(&c->d_m64, sizeof(double) * n_tab) != hipSuccess ||
         hipMalloc(&c->d_nhi, sizeof(double) * n3) != hipSuccess ||
         hipMalloc(&c->d_gacc, sizeof(double) * n3) != hipSuccess ||
         hipMalloc(&c->d_ctl, sizeof(int) * kCtlSize) != hipSuccess ||
@@ -171,10 +186,15 @@ extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, d
                          16.0 * n3 / 1e6));
     if (hipMemcpy(c->d_tab, nodes.data(), sizeof(TabNode) * n_tab, hipMemcpyHostToDevice) !=
             hipSuccess ||
+        hipMemcpy(c->d_m64, m64.data(), sizeof(double) * n_tab, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(c->d_err, 0, sizeof(int)) != hipSuccess ||
         hipMemset(c->d_ctl, 0, sizeof(int) * kCtlSize) != hipSuccess)
         return bail(fail(nullptr, ASORA_EHIP, "asora_init: copy to device failed"));
-    if (fwd_configure(c->max_lds) != hipSuccess)
+    for (int k = 0; k < 4; ++k)
+        if (hipEventCreate(&c->ev[k]) != hipSuccess)
+            return bail(fail(nullptr, ASORA_EHIP, "asora_init: hipEventCreate failed"));
+    c->ev_ready = true;
+    if (fwd_configure(c->max_lds) != hipSuccess || adj_configure(c->max_lds) != hipSuccess)
         return bail(fail(nullptr, ASORA_EHIP, "asora_init: kernel attribute setup failed"));
     *out = c;
     return ASORA_OK;
@@ -187,12 +207,17 @@ extern "C" asora_status asora_free(asora_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(c->d_tab);
+    (void)hipFree(c->d_m64);
     (void)hipFree(c->d_nhi);
     (void)hipFree(c->d_gacc);
     (void)hipFree(c->d_ctl);
     (void)hipFree(c->d_err);
     (void)hipFree(c->d_keys);
     (void)hipFree(c->d_order);
+    (void)hipFree(c->d_nbar);
+    (void)hipFree(c->d_store);
+    if (c->ev_ready)
+        for (int k = 0; k < 4; ++k) (void)hipEventDestroy(c->ev[k]);
     c->magic = 0;
     delete c;
     return ASORA_OK;
@@ -242,8 +267,10 @@ static asora_status get_plan(asora_ctx *c, int type, float R_cap, Plan *out)
     const Extent ex = make_extent(c->N);
     const int Qmax = max_shell(Rsq, ex);
     int ring = 1;
+    long cells = 1;
     for (int p = 0; p < pieces_of_type(type); ++p) {
         const Piece pc = make_piece(type, p);
+        long pcells = 0;
         for (int q = 1; q <= Qmax; ++q) {
             int tot = 0;
             for (int r = 0; r < pc.n_oct * (q + 1); ++r) {
@@ -252,19 +279,36 @@ static asora_status get_plan(asora_ctx *c, int type, float R_cap, Plan *out)
                 tot += cnt;
             }
             ring = tot > ring ? tot : ring;
+            pcells += tot;
         }
+        cells = pcells > cells ? pcells : cells;
     }
     Plan P;
+    P.piece_cells = cells;
     P.ring_cap = ring;
     P.row_cap = (type == 0 ? 8 : 1) * (Qmax + 1);
     P.Qmax = Qmax;
-    P.lds = fwd_lds_bytes(c->tp.n, P.ring_cap, P.row_cap);
-    if (P.lds + 64 > c->max_lds)
-        return fail(c, ASORA_ENOSYS,
-                    "R_max=%.1f needs %zu bytes of LDS per work-group (limit %zu) for this table "
-                    "and grid", R_cap, P.lds, c->max_lds);
+    // one wave per piece when at least c->min_waves per-wave regions fit next to
+    // the table; else a whole work-group per piece
+    const size_t tab = (size_t)c->tp.n * sizeof(TabNode);
+    const size_t region = wave_region_bytes(P.ring_cap, P.row_cap);
+    const long fit = c->max_lds > tab + 64 ? (long)((c->max_lds - tab - 64) / region) : 0;
     int bpc = 0;
-    HIPCHK(c, fwd_occupancy(P.lds, &bpc));
+    if (fit >= c->min_waves && P.row_cap <= 256) {
+        P.wave_mode = 1;
+        P.waves = (int)(fit < c->max_waves ? fit : c->max_waves);
+        P.lds = tab + (size_t)P.waves * region;
+        HIPCHK(c, wave_occupancy(type, P.waves, P.lds, &bpc));
+    } else {
+        P.wave_mode = 0;
+        P.waves = 4;
+        P.lds = fwd_lds_bytes(c->tp.n, P.ring_cap, P.row_cap);
+        if (P.lds + 64 > c->max_lds)
+            return fail(c, ASORA_ENOSYS,
+                        "R_max=%.1f needs %zu bytes of LDS per work-group (limit %zu) for this "
+                        "table and grid", R_cap, P.lds, c->max_lds);
+        HIPCHK(c, fwd_occupancy(P.lds, &bpc));
+    }
     P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
     c->plans[key] = P;
     *out = P;
@@ -307,7 +351,9 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     if (st) return st;
     if (!gamma) return fail(c, ASORA_EINVAL, "gamma must not be NULL");
     if (coldens_in && n_src != 1) return fail(c, ASORA_EINVAL, "coldens_in requires n_src == 1");
-    if (flags & ~(ASORA_ACCUMULATE | ASORA_PLAIN)) return fail(c, ASORA_EINVAL, "unknown flags");
+    if (flags & ~(ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_PROFILE))
+        return fail(c, ASORA_EINVAL, "unknown flags");
+    const bool prof = (flags & ASORA_PROFILE) != 0;
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     const long n3 = (long)c->N * c->N * c->N;
@@ -337,43 +383,204 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     F.ctl = c->d_ctl;
     F.err = c->d_err;
 
+    if (prof) HIPCHK(c, hipEventRecord(c->ev[0], s));
     HIPCHK(c, launch_prologue(s, n_H, x_HI, c->d_nhi, c->d_gacc, coldens_in, n3, c->d_ctl,
                               kCtlSize, c->n_cu));
+    if (n_src > 0 && !(flags & ASORA_PLAIN))
+        HIPCHK(c, launch_bucketing(s, src_R, src_ijk, n_src, c->N, R_max, c->R_whole, c->R_oct,
+                                   c->d_keys, c->d_ctl, c->d_order, c->d_err));
+    if (prof) HIPCHK(c, hipEventRecord(c->ev[1], s));
     if (n_src > 0) {
         if (flags & ASORA_PLAIN) {
             F.type = tmax;
             F.R_cap = R_max;
             F.ring_cap = plans[tmax].ring_cap;
             F.row_cap = plans[tmax].row_cap;
-            for (long k = 0; k < n_src; ++k) HIPCHK(c, launch_fwd_plain(s, F, (int)k));
+            for (long k = 0; k < n_src; ++k) {
+                if (plans[tmax].wave_mode)
+                    HIPCHK(c, launch_fwd_wave(s, F, plans[tmax].waves, 0, (int)k));
+                else
+                    HIPCHK(c, launch_fwd_plain(s, F, (int)k));
+            }
         } else {
-            HIPCHK(c, launch_bucketing(s, src_R, src_ijk, n_src, c->N, R_max, c->R_whole, c->R_oct,
-                                       c->d_keys, c->d_ctl, c->d_order, c->d_err));
             for (int t = tmax; t >= 0; --t) {
                 F.type = t;
                 F.R_cap = t == tmax ? R_max : (t == 0 ? c->R_whole : c->R_oct);
                 F.ring_cap = plans[t].ring_cap;
                 F.row_cap = plans[t].row_cap;
-                HIPCHK(c, launch_fwd_persistent(s, F, plans[t].grid));
+                if (plans[t].wave_mode)
+                    HIPCHK(c, launch_fwd_wave(s, F, plans[t].waves, plans[t].grid, -1));
+                else
+                    HIPCHK(c, launch_fwd_persistent(s, F, plans[t].grid));
             }
         }
     }
+    if (prof) HIPCHK(c, hipEventRecord(c->ev[2], s));
     HIPCHK(c, launch_finalize(s, c->d_gacc, gamma, n3, (flags & ASORA_ACCUMULATE) ? 1 : 0,
                               c->n_cu));
+    if (prof) {
+        HIPCHK(c, hipEventRecord(c->ev[3], s));
+        c->profiled = true;
+    }
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_set_tuning(asora_ctx *c, float R_whole, float R_oct, int32_t max_waves)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    const float w = R_whole > 0 ? R_whole : c->R_whole;
+    const float o = R_oct > 0 ? R_oct : c->R_oct;
+    if (!(o >= w) || !std::isfinite(w) || !std::isfinite(o) || max_waves > 16)
+        return fail(c, ASORA_EINVAL, "asora_set_tuning: need 0 < R_whole <= R_oct, max_waves <= 16");
+    c->R_whole = w;
+    c->R_oct = o;
+    if (max_waves > 0) c->max_waves = max_waves;
+    if (c->min_waves > c->max_waves) c->min_waves = c->max_waves;
+    c->plans.clear();
+    c->adj_plans.clear();
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_get_tuning(const asora_ctx *c, float *R_whole, float *R_oct,
+                                         int32_t *max_waves)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    if (R_whole) *R_whole = c->R_whole;
+    if (R_oct) *R_oct = c->R_oct;
+    if (max_waves) *max_waves = c->max_waves;
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_profile(asora_ctx *c, double *sweep_ms, double *total_ms)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    if (!c->profiled) return fail(c, ASORA_ESTATE, "asora_profile: no profiled call yet");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipEventSynchronize(c->ev[3]));
+    float a = 0.f, b = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&a, c->ev[1], c->ev[2]));
+    HIPCHK(c, hipEventElapsedTime(&b, c->ev[0], c->ev[3]));
+    if (sweep_ms) *sweep_ms = a;
+    if (total_ms) *total_ms = b;
+    return ASORA_OK;
+}
+
+// Adjoint plan: the forward plan's sizes with the adjoint's per-wave region.
+static asora_status get_adj_plan(asora_ctx *c, int type, float R_cap, Plan *out)
+{
+    const int Rsq = (int)std::floor((double)R_cap * (double)R_cap);
+    const PlanKey key{type, Rsq};
+    auto it = c->adj_plans.find(key);
+    if (it != c->adj_plans.end()) {
+        *out = it->second;
+        return ASORA_OK;
+    }
+    Plan P;
+    asora_status st = get_plan(c, type, R_cap, &P);   // ring/row/cell sizes
+    if (st) return st;
+    if (P.row_cap > 256)
+        return fail(c, ASORA_ENOSYS, "asora_raytrace_backward: R_max=%.1f too large for the wave adjoint", R_cap);
+    const size_t tab = (size_t)c->tp.n * sizeof(TabNode);
+    const size_t region = adj_region_bytes(P.ring_cap, P.row_cap, P.Qmax);
+    const long fit = c->max_lds > tab + 64 ? (long)((c->max_lds - tab - 64) / region) : 0;
+    if (fit < 1)
+        return fail(c, ASORA_ENOSYS,
+                    "asora_raytrace_backward: R_max=%.1f needs %zu bytes of LDS per wave (limit %zu)",
+                    R_cap, region + tab, c->max_lds);
+    P.wave_mode = 1;
+    const int cap = c->max_waves < 8 ? c->max_waves : 8;   // adjoint work-groups: <= 512 threads
+    P.waves = (int)(fit < cap ? fit : cap);
+    P.lds = tab + (size_t)P.waves * region;
+    int bpc = 0;
+    HIPCHK(c, adj_occupancy(type, P.waves, P.lds, &bpc));
+    P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
+    c->adj_plans[key] = P;
+    *out = P;
     return ASORA_OK;
 }
 
 extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, const float *x_HI,
                                                 int64_t n_src, const int32_t *src_ijk,
                                                 const double *src_Q, const float *src_R,
-                                                float R_max, const float *dL_dgamma,
+                                                float R_max, const double *dL_dgamma,
                                                 float *dL_dnH, float *dL_dxHI, double *dL_dQ,
                                                 uint32_t flags, void *stream)
 {
     if (!ctx_ok(c)) return ASORA_ESTATE;
     asora_status st = check_common(c, n_H, x_HI, n_src, src_ijk, src_Q, R_max);
     if (st) return st;
-    (void)src_R; (void)dL_dgamma; (void)dL_dnH; (void)dL_dxHI; (void)dL_dQ; (void)flags;
-    (void)stream;
-    return fail(c, ASORA_ENOSYS, "asora_raytrace_backward: not built yet");
+    if (!dL_dgamma || !dL_dnH || !dL_dxHI || (n_src > 0 && !dL_dQ))
+        return fail(c, ASORA_EINVAL, "gradient buffers must not be NULL");
+    if (flags & ~(ASORA_ACCUMULATE | ASORA_PROFILE)) return fail(c, ASORA_EINVAL, "unknown flags");
+    const bool prof = (flags & ASORA_PROFILE) != 0;
+    const bool acc = (flags & ASORA_ACCUMULATE) != 0;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const long n3 = (long)c->N * c->N * c->N;
+    const int tmax = type_of(c, R_max);
+    Plan plans[3];
+    size_t store_need = 0;
+    for (int t = 0; t <= tmax; ++t) {
+        const float cap = t == tmax ? R_max : (t == 0 ? c->R_whole : c->R_oct);
+        if ((st = get_adj_plan(c, t, cap, &plans[t]))) return st;
+        const size_t need = (size_t)plans[t].grid * plans[t].waves * (size_t)plans[t].piece_cells;
+        store_need = need > store_need ? need : store_need;
+    }
+    if ((st = ensure_src_cap(c, n_src))) return st;
+    if (!c->d_nbar) HIPCHK(c, hipMalloc(&c->d_nbar, sizeof(double) * n3));
+    if (store_need > c->store_cap) {
+        (void)hipFree(c->d_store);
+        c->d_store = nullptr;
+        c->store_cap = 0;
+        HIPCHK(c, hipMalloc(&c->d_store, sizeof(double) * store_need));
+        c->store_cap = store_need;
+    }
+    if (prof) HIPCHK(c, hipEventRecord(c->ev[0], s));
+    // dL/dQ accumulates over pieces: zero it unless the caller accumulates
+    HIPCHK(c, launch_adj_prologue(s, n_H, x_HI, c->d_nhi, c->d_nbar, n3, dL_dQ, n_src, acc ? 0 : 1,
+                                  c->d_ctl, kCtlSize, c->n_cu));
+    if (n_src > 0)
+        HIPCHK(c, launch_bucketing(s, src_R, src_ijk, n_src, c->N, R_max, c->R_whole, c->R_oct,
+                                   c->d_keys, c->d_ctl, c->d_order, c->d_err));
+    if (prof) HIPCHK(c, hipEventRecord(c->ev[1], s));
+    if (n_src > 0) {
+        AdjLaunch L;
+        L.N = c->N;
+        L.alpha = c->alpha;
+        L.sigma0 = c->sigma0;
+        L.tau_w = (float)c->tau_w;
+        L.reading = c->reading;
+        L.tp = c->tp;
+        L.tab = c->d_tab;
+        L.m64 = c->d_m64;
+        L.nHI = c->d_nhi;
+        L.gbar = dL_dgamma;
+        L.nbar = c->d_nbar;
+        L.qbar = dL_dQ;
+        L.ijk = src_ijk;
+        L.Q = src_Q;
+        L.R = src_R;
+        L.order = c->d_order;
+        L.ctl = c->d_ctl;
+        L.err = c->d_err;
+        L.store = c->d_store;
+        for (int t = tmax; t >= 0; --t) {
+            L.type = t;
+            L.R_cap = t == tmax ? R_max : (t == 0 ? c->R_whole : c->R_oct);
+            L.ring_cap = plans[t].ring_cap;
+            L.row_cap = plans[t].row_cap;
+            L.shell_cap = plans[t].Qmax;
+            L.waves = plans[t].waves;
+            L.grid = plans[t].grid;
+            L.store_stride = plans[t].piece_cells;
+            HIPCHK(c, launch_adj_wave(s, L));
+        }
+    }
+    if (prof) HIPCHK(c, hipEventRecord(c->ev[2], s));
+    HIPCHK(c, launch_adj_finalize(s, c->d_nbar, n_H, x_HI, dL_dnH, dL_dxHI, n3, acc ? 1 : 0, c->n_cu));
+    if (prof) {
+        HIPCHK(c, hipEventRecord(c->ev[3], s));
+        c->profiled = true;
+    }
+    return ASORA_OK;
 }

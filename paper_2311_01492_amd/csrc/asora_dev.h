@@ -17,6 +17,41 @@ __host__ __device__ __forceinline__ float rcp_approx(float x)
 #endif
 }
 
+// 2^x in FP32: the hardware instruction on the GPU (about 1 ulp).
+__host__ __device__ __forceinline__ float exp2_fast(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_exp2f(x);
+#else
+    return exp2f(x);
+#endif
+}
+
+// e^x for |x| <~ 1 in FP32, relative error ~1e-7.
+__host__ __device__ __forceinline__ float exp_small(float x)
+{
+    return exp2_fast(x * 1.44269504088896341f);
+}
+
+// e^x - 1 in FP32 with full relative accuracy near 0: Taylor series (to x^9)
+// for |x| < 0.5, else e^x - 1 (relative error below 3e-7 there).
+__host__ __device__ __forceinline__ float expm1_fast(float x)
+{
+    if (fabsf(x) < 0.5f) {
+        float p = 1.f / 362880.f;
+        p = p * x + 1.f / 40320.f;
+        p = p * x + 1.f / 5040.f;
+        p = p * x + 1.f / 720.f;
+        p = p * x + 1.f / 120.f;
+        p = p * x + 1.f / 24.f;
+        p = p * x + 1.f / 6.f;
+        p = p * x + 0.5f;
+        p = p * x + 1.f;
+        return p * x;
+    }
+    return exp2_fast(x * 1.44269504088896341f) - 1.f;
+}
+
 // 1/x to about half an ulp: hardware estimate and one Newton step.
 __host__ __device__ __forceinline__ float rcp_nr(float x)
 {
@@ -24,13 +59,52 @@ __host__ __device__ __forceinline__ float rcp_nr(float x)
     return r * (2.f - x * r);
 }
 
-// 1/x in FP64 for positive x within the FP32 range: FP32 estimate and one
+// 1/x in FP64 for positive x within the FP32 normal range (about 1e-38 to
+// 3e38): FP32 estimate and one
 // FP64 Newton step (relative error ~1e-14, far cheaper than a full FP64
 // division).
 __host__ __device__ __forceinline__ double rcp_f64(double x)
 {
     const double r = (double)rcp_approx((float)x);
     return r * (2.0 - x * r);
+}
+
+// sqrt(x) in FP64 for x within the FP32 normal range: FP32 reciprocal square
+// root estimate and one Goldschmidt step (relative error ~1e-14).
+__host__ __device__ __forceinline__ double sqrt_fast(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    const double y = (double)__builtin_amdgcn_rsqf((float)x);
+#else
+    const double y = 1.0 / (double)sqrtf((float)x);
+#endif
+    double g = x * y;
+    const double h = 0.5 * y;
+    const double e = 0.5 - g * h;
+    return g + g * e;
+}
+
+// ln(a) in FP64 for normal a > 0, absolute error below 2e-11: the mantissa
+// is reduced to [1/sqrt2, sqrt2) and ln m = 2 atanh(s), s = (m-1)/(m+1),
+// |s| <= 0.172, summed to s^11.  (The table position needs ln tau to ~1e-9
+// absolute; a correctly rounded FP64 log costs several times more.)
+__host__ __device__ __forceinline__ double log_fast(double a)
+{
+    int e;
+    double m = frexp(a, &e);
+    if (m < 0.70710678118654752) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double s = (m - 1.0) * rcp_f64(m + 1.0);
+    const double s2 = s * s;
+    double p = 1.0 / 11.0;
+    p = p * s2 + 1.0 / 9.0;
+    p = p * s2 + 1.0 / 7.0;
+    p = p * s2 + 1.0 / 5.0;
+    p = p * s2 + 1.0 / 3.0;
+    p = p * s2 + 1.0;
+    return 2.0 * s * p + (double)e * 0.69314718055994530942;
 }
 
 // --------------------------------------------------------------------------
@@ -86,47 +160,58 @@ __host__ __device__ __forceinline__ float cubic_dd(const Cubic &c, float t1, flo
 }
 
 // Divided difference [P(a+dt) - P(a)] / dt of the spline part, for
-// tau_lo <= a and a + dt <= tau_hi.  The difference is formed in log space
-// (P(a) expm1(delta ln P)) so that it keeps full relative accuracy when dt is
-// small against a, and delta ln P is summed piecewise when both ends share an
-// interval or sit in neighbouring ones.
+// tau_lo <= a and a + dt <= tau_hi.  The difference is formed in log space,
+// P(a) expm1(delta ln P), so that it keeps full relative accuracy when dt is
+// small against a; delta ln P is the exact difference of the cubic when both
+// ends share a node interval, the sum over the two pieces when they sit in
+// neighbouring intervals, and node values plus end corrections otherwise.
 __host__ __device__ __forceinline__ float divdiff_spline(const TabNode *T, const TabParams &tp, double a,
-                                                double dt)
+                                                         double dt)
 {
-    const double xa = log(a);
+    const double xa = log_fast(a);
     const double ta = (xa - tp.x_lo) * tp.inv_h;
     int ja = (int)floor(ta);
     ja = ja < 0 ? 0 : (ja > tp.n - 2 ? tp.n - 2 : ja);
     const float fa = (float)(ta - (double)ja);
     const Cubic ca = cubic_at(T, ja, tp.h);
     const float corr_a = cubic_val(ca, fa);
-    const float Pa = T[ja].P * expf(corr_a);
-    const float u = (float)(dt / a);
-    if (!(u > 1e-12f)) {
-        // zero-width interval: the slope of the interpolant at a
-        const float yx = cubic_dd(ca, fa, fa) * tp.inv_hf;
-        return Pa * yx / (float)a;
-    }
-    const float dtn = log1pf(u) * tp.inv_hf;   // (x_b - x_a) / h
-    const float tb = fa + dtn;
+    const float Pa = T[ja].P * exp_small(corr_a);
+    const float u = (float)dt * rcp_nr((float)a);
     float dy;
-    if (tb <= 1.f || ja == tp.n - 2) {
-        // same interval (on the last interval b <= tau_hi, so tb > 1 is rounding)
-        dy = dtn * cubic_dd(ca, fa, fminf(tb, 1.f));
-    } else if (tb <= 2.f) {
-        const float d1 = 1.f - fa;
-        const float d2 = dtn - d1;
-        const Cubic cb = cubic_at(T, ja + 1, tp.h);
-        dy = d1 * cubic_dd(ca, fa, 1.f) + d2 * cubic_dd(cb, 0.f, d2);
+    if (u < 1e-3f) {
+        if (!(u > 1e-12f)) {
+            // zero-width interval: the slope of the interpolant at a
+            const float yx = cubic_dd(ca, fa, fa) * tp.inv_hf;
+            return Pa * yx * rcp_nr((float)a);
+        }
+        // ln(1+u) to u^4 (error below u^5/5 < 2e-16): both ends in one or two intervals
+        const float dx = u * (1.f - u * (0.5f - u * (1.f / 3.f - u * 0.25f)));
+        const float dtn = dx * tp.inv_hf;
+        const float tb = fa + dtn;
+        if (tb <= 1.f || ja == tp.n - 2) {
+            dy = dtn * cubic_dd(ca, fa, fminf(tb, 1.f));
+        } else {
+            const float d1 = 1.f - fa;
+            const float d2 = dtn - d1;
+            const Cubic cb = cubic_at(T, ja + 1, tp.h);
+            dy = d1 * cubic_dd(ca, fa, 1.f) + d2 * cubic_dd(cb, 0.f, d2);
+        }
     } else {
-        const double tbb = (log(a + dt) - tp.x_lo) * tp.inv_h;
+        const double tbb = (log_fast(a + dt) - tp.x_lo) * tp.inv_h;
         int jb = (int)floor(tbb);
         jb = jb < 0 ? 0 : (jb > tp.n - 2 ? tp.n - 2 : jb);
         const float fb = (float)(tbb - (double)jb);
-        const Cubic cb = cubic_at(T, jb, tp.h);
-        dy = (float)(T[jb].y - T[ja].y) + (cubic_val(cb, fb) - corr_a);
+        if (jb == ja) {
+            dy = (float)(tbb - ta) * cubic_dd(ca, fa, fb);
+        } else if (jb == ja + 1) {
+            const Cubic cb = cubic_at(T, jb, tp.h);
+            dy = (1.f - fa) * cubic_dd(ca, fa, 1.f) + fb * cubic_dd(cb, 0.f, fb);
+        } else {
+            const Cubic cb = cubic_at(T, jb, tp.h);
+            dy = (float)(T[jb].y - T[ja].y) + (cubic_val(cb, fb) - corr_a);
+        }
     }
-    return Pa * expm1f(dy) / (float)dt;
+    return Pa * expm1_fast(dy) * rcp_nr((float)dt);
 }
 
 // -D = -[P(a+dt) - P(a)] / dt >= 0 of the full interpolant (linear piece,
@@ -145,7 +230,7 @@ __host__ __device__ __forceinline__ float neg_divdiff(const TabNode *T, const Ta
     const double lenL = a < tp.tau_lo ? tp.tau_lo - a : 0.0;
     const double lenH = bH - aH;
     const double DH = lenH > 0 ? (double)divdiff_spline(T, tp, aH, lenH) : 0.0;
-    return (float)(-((double)tp.dP0 * lenL + DH * lenH) / dt);
+    return (float)(-((double)tp.dP0 * lenL + DH * lenH) * rcp_f64(dt));
 }
 
 // --------------------------------------------------------------------------
@@ -287,6 +372,7 @@ struct CellCtx {
     double half_col;       // n_HI(s) alpha / 2
     double coef;           // Q sigma0 / (4 pi alpha^2)
     const TabNode *tab;
+    const double *m64;     // FP64 node slopes (adjoint only; may be NULL in the forward)
     TabParams tp;
     const double *ring;    // [4][ring_cap] exit columns of shells q-1..q-3
     const int *rowbase;    // [4][row_cap]
@@ -295,9 +381,11 @@ struct CellCtx {
 };
 
 struct CellOut {
-    long cp;        // global cell index
+    uint32_t cp;    // global cell index (N^3 < 2^32)
     double Nin, Nout;
-    double G;       // rate contribution (0 if none)
+    double dN;      // in-cell column
+    int r2;         // squared distance to the source (cells)
+    double G;       // rate contribution (0 if none; only with the rate evaluated)
     bool owned;
 };
 
@@ -305,10 +393,12 @@ struct CellOut {
 // q (row `row` of the shell's row table, base rb = rowbase of that row):
 // interpolate the entry column from the neighbours (eq. raga, eq. interp),
 // add the in-cell column (Section 3.1) and form the rate (eq. sugg).
+template <bool kRate = true>
 __host__ __device__ __forceinline__ void cell_update(const CellCtx &X, int q, int g, int row,
                                                      int rb, CellOut &out)
 {
-    const int os = row / (q + 1);
+    // octant slot and first coordinate of the row (single-octant pieces: row = A)
+    const int os = X.pc.n_oct == 1 ? 0 : (int)(((float)row + 0.5f) * rcp_approx((float)(q + 1)));
     const int cA = row - os * (q + 1);
     const int cB = g - rb;
     const int cC = q - cA - cB;
@@ -317,7 +407,8 @@ __host__ __device__ __forceinline__ void cell_update(const CellCtx &X, int q, in
     const int dj = (o & 2) ? -cB : cB;
     const int dk = (o & 4) ? -cC : cC;
     const int N = X.N;
-    const long cp = ((long)wrap(X.si + di, N) * N + wrap(X.sj + dj, N)) * N + wrap(X.sk + dk, N);
+    const uint32_t cp = ((uint32_t)wrap(X.si + di, N) * (uint32_t)N + (uint32_t)wrap(X.sj + dj, N)) *
+                            (uint32_t)N + (uint32_t)wrap(X.sk + dk, N);
     const double nhi = X.nHI[cp];
 
     // geometry: dominant axis, bilinear weights, path length
@@ -333,7 +424,7 @@ __host__ __device__ __forceinline__ void cell_update(const CellCtx &X, int q, in
     const double a = cu == m ? 1.0 : (double)cu * inv_m;
     const double b = cv == m ? 1.0 : (double)cv * inv_m;
     const int r2 = cA * cA + cB * cB + cC * cC;
-    const double ds = sqrt((double)r2) * inv_m;
+    const double ds = sqrt_fast((double)r2) * inv_m;
     const double sw[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
 
     // interpolate the entry column from the (up to) four neighbours,
@@ -381,7 +472,7 @@ __host__ __device__ __forceinline__ void cell_update(const CellCtx &X, int q, in
         if (X.pc.dom >= 0 && canon != X.pc.dom) owned = false;
     }
     double G = 0.0;
-    if (owned) {
+    if (kRate && owned) {
         const double ta = X.sigma0 * Nin;
         if (ta < X.tp.tau_hi) {
             const float nd = neg_divdiff(X.tab, X.tp, ta, X.sigma0 * dN);
@@ -391,8 +482,255 @@ __host__ __device__ __forceinline__ void cell_update(const CellCtx &X, int q, in
     out.cp = cp;
     out.Nin = Nin;
     out.Nout = Nout;
+    out.dN = dN;
+    out.r2 = r2;
     out.G = G;
     out.owned = owned;
+}
+
+// --------------------------------------------------------------------------
+// FP64 evaluation of the interpolant and of the rate's partial derivatives,
+// for the adjoint.
+// --------------------------------------------------------------------------
+
+// e^x in FP64 (relative error ~2e-16): x = k ln2 + r, |r| <= ln2/2, Taylor to r^13.
+__host__ __device__ __forceinline__ double exp_f64(double x)
+{
+    if (x < -745.0) return 0.0;
+    const double k = rint(x * 1.4426950408889634);
+    const double r = (x - k * 0.69314718055994529) - k * 2.3190468138462996e-17;
+    double p = 1.0 / 6227020800.0;
+    p = p * r + 1.0 / 479001600.0;
+    p = p * r + 1.0 / 39916800.0;
+    p = p * r + 1.0 / 3628800.0;
+    p = p * r + 1.0 / 362880.0;
+    p = p * r + 1.0 / 40320.0;
+    p = p * r + 1.0 / 5040.0;
+    p = p * r + 1.0 / 720.0;
+    p = p * r + 1.0 / 120.0;
+    p = p * r + 1.0 / 24.0;
+    p = p * r + 1.0 / 6.0;
+    p = p * r + 0.5;
+    p = p * r + 1.0;
+    p = p * r + 1.0;
+    return ldexp(p, (int)k);
+}
+
+// P(tau), dP/dtau and d2P/dtau2 of the interpolant in FP64 (node slopes m64
+// in FP64: gradients can be sums of large terms of both signs).
+__host__ __device__ __forceinline__ void tab_eval64(const TabNode *T, const double *m64,
+                                                    const TabParams &tp, double tau, double *P,
+                                                    double *d1, double *d2)
+{
+    if (tau < tp.tau_lo) {
+        *P = exp_f64(T[0].y) + (double)tp.dP0 * (tau - tp.tau_lo);
+        *d1 = (double)tp.dP0;
+        *d2 = 0.0;
+        return;
+    }
+    if (tau >= tp.tau_hi) {
+        *P = exp_f64(T[tp.n - 1].y);
+        *d1 = 0.0;
+        *d2 = 0.0;
+        return;
+    }
+    const double t = (log_fast(tau) - tp.x_lo) * tp.inv_h;
+    int j = (int)floor(t);
+    j = j < 0 ? 0 : (j > tp.n - 2 ? tp.n - 2 : j);
+    const double f = t - (double)j;
+    const double h = 1.0 / tp.inv_h;
+    const double d = T[j + 1].y - T[j].y;
+    const double hm0 = h * m64[j], hm1 = h * m64[j + 1];
+    const double c1 = hm0, c2 = 3.0 * d - 2.0 * hm0 - hm1, c3 = -2.0 * d + hm0 + hm1;
+    const double y = T[j].y + f * (c1 + f * (c2 + f * c3));
+    const double yx = (c1 + f * (2.0 * c2 + 3.0 * f * c3)) * tp.inv_h;
+    const double yxx = (2.0 * c2 + 6.0 * f * c3) * tp.inv_h * tp.inv_h;
+    const double p = exp_f64(y);
+    const double it = 1.0 / tau;
+    *P = p;
+    *d1 = p * yx * it;
+    *d2 = p * (yx * yx + yxx - yx) * it * it;
+}
+
+// D = [P(a+dt) - P(a)] / dt and its partial derivatives dD/da (dt fixed) and
+// dD/d(dt) (a fixed), FP64.  For dt > 1e-4 a the difference quotients are
+// formed directly (their FP64 cancellation costs at most ~1e-8); below that
+// the integral forms dD/da = mean of P'' over [a, a+dt] and
+// dD/d(dt) = (1/dt^2) int_0^dt t P''(a+t) dt are taken with two-point Gauss
+// rules (error O((dt/a)^4)).
+__host__ __device__ __forceinline__ void rate_derivs64(const TabNode *T, const double *m64,
+                                                       const TabParams &tp, double a, double dt,
+                                                       double *D, double *dDda, double *dDddt)
+{
+    double Pa, Pa1, Pa2;
+    tab_eval64(T, m64, tp, a, &Pa, &Pa1, &Pa2);
+    if (dt > 1e-4 * a && dt > 0.0) {
+        double Pb, Pb1, Pb2;
+        tab_eval64(T, m64, tp, a + dt, &Pb, &Pb1, &Pb2);
+        const double idt = 1.0 / dt;
+        const double d = (Pb - Pa) * idt;
+        *D = d;
+        *dDda = (Pb1 - Pa1) * idt;
+        *dDddt = (Pb1 - d) * idt;
+        return;
+    }
+    // Gauss-Legendre (mean of P'') and Gauss-Jacobi for the weight t (second)
+    const double g1 = 0.21132486540518711, g2 = 0.78867513459481289;
+    const double j1 = 0.35505102572168219, j2 = 0.84494897427831781;   // (6 -+ sqrt6)/10
+    const double w1 = (9.0 + 2.449489742783178) / 36.0, w2 = (9.0 - 2.449489742783178) / 36.0;
+    double P_, d1_, q1, q2, r1, r2;
+    tab_eval64(T, m64, tp, a + g1 * dt, &P_, &d1_, &q1);
+    tab_eval64(T, m64, tp, a + g2 * dt, &P_, &d1_, &q2);
+    tab_eval64(T, m64, tp, a + j1 * dt, &P_, &d1_, &r1);
+    tab_eval64(T, m64, tp, a + j2 * dt, &P_, &d1_, &r2);
+    *dDda = 0.5 * (q1 + q2);
+    *dDddt = w1 * r1 + w2 * r2;
+    *D = Pa1 + 0.5 * dt * (*dDda);
+}
+
+// Reverse-mode update of one cell (not the source).  Given the total adjoint
+// of its exit column from its consumers (Nbar_out) and dL/dGamma of the cell
+// (gbar, owned cells only), it recomputes the forward quantities from the
+// neighbour columns in the ring and returns the adjoints to push to the
+// neighbours (their exit columns; a neighbour that is the source pushes to
+// n_HI of the source), the adjoint of the cell's n_HI and of the source rate.
+struct CellAdj {
+    uint32_t cp;
+    int slot[4];            // ring slot of neighbour e_n in shell qn[n]; -1 the source, -2 unused
+    int qn[4];              // neighbour shells
+    double Mbar[4];         // adjoint pushed to each neighbour's exit column
+    double nbar_src;        // pushed to n_HI of the source
+    double nbar;            // dL/dn_HI of this cell
+    double qbar;            // dL/dQ of the source (times Q: Gbar * Gamma)
+};
+
+__host__ __device__ __forceinline__ void cell_adjoint(const CellCtx &X, int q, int g, int row, int rb,
+                                                      double Nbar_out, const double *gbar_grid,
+                                                      CellAdj &out)
+{
+    const int os = X.pc.n_oct == 1 ? 0 : (int)(((float)row + 0.5f) * rcp_approx((float)(q + 1)));
+    const int cA = row - os * (q + 1);
+    const int cB = g - rb;
+    const int cC = q - cA - cB;
+    const int o = X.pc.kind == 0 ? os : X.pc.oct;
+    const int di = (o & 1) ? -cA : cA;
+    const int dj = (o & 2) ? -cB : cB;
+    const int dk = (o & 4) ? -cC : cC;
+    const int N = X.N;
+    const uint32_t cp = ((uint32_t)wrap(X.si + di, N) * (uint32_t)N + (uint32_t)wrap(X.sj + dj, N)) *
+                            (uint32_t)N + (uint32_t)wrap(X.sk + dk, N);
+    const double nhi = X.nHI[cp];
+    const int m = cA > cB ? (cA > cC ? cA : cC) : (cB > cC ? cB : cC);
+    const int canon = cC == m ? 2 : (cB == m ? 1 : 0);
+    const int dd = X.pc.dom >= 0 ? X.pc.dom : canon;
+    const int cu = dd == 0 ? cB : cA;
+    const int cv = dd == 2 ? cB : cC;
+    const double inv_m = rcp_f64((double)m);
+    const double a = cu == m ? 1.0 : (double)cu * inv_m;
+    const double b = cv == m ? 1.0 : (double)cv * inv_m;
+    const int r2 = cA * cA + cB * cB + cC * cC;
+    const double ds = sqrt_fast((double)r2) * inv_m;
+    const double sw[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
+
+    double Mv[4], wv[4], dw[4];
+    int nslot[4], nq[4];
+    double num = 0.0, W = 0.0;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        Mv[n] = 0.0;
+        wv[n] = 0.0;
+        dw[n] = 0.0;
+        nslot[n] = -2;
+        nq[n] = 0;
+        if (!(sw[n] > 0.0)) continue;
+        const int su = n & 1, sv = (n >> 1) & 1;
+        const int eA = cA - (dd == 0 ? 1 : 0) - (su & (dd != 0 ? 1 : 0));
+        const int eB = cB - (dd == 1 ? 1 : 0) - (su & (dd == 0 ? 1 : 0)) - (sv & (dd == 2 ? 1 : 0));
+        const int eC = cC - (dd == 2 ? 1 : 0) - (sv & (dd != 2 ? 1 : 0));
+        const int qn = q - 1 - su - sv;
+        double M;
+        if (qn == 0) {
+            M = X.reading == 0 ? X.half_col * ds : X.half_col;
+            nslot[n] = -1;
+        } else {
+            int o2 = o;
+            if (X.pc.kind == 0) {
+                if ((o2 & 1) && eA == 0) o2 &= ~1;
+                if ((o2 & 2) && eB == 0) o2 &= ~2;
+                if ((o2 & 4) && eC == 0) o2 &= ~4;
+            }
+            const int ord = X.pc.kind == 0 ? o2 : 0;
+            const int sl = qn & 3;
+            const int nrow = ord * (qn + 1) + eA;
+            nslot[n] = X.rowbase[sl * X.row_cap + nrow] + eB;
+            M = X.ring[sl * X.ring_cap + nslot[n]];
+        }
+        nq[n] = qn;
+        double wn = sw[n];
+        if (X.tau_w > 0.f) {
+            const double tau = X.sigma0 * M;
+            if (tau > (double)X.tau_w) {
+                const double it = 1.0 / tau;
+                wn *= it;
+                dw[n] = -sw[n] * X.sigma0 * it * it;
+            } else {
+                wn *= 1.0 / (double)X.tau_w;
+            }
+        }
+        Mv[n] = M;
+        wv[n] = wn;
+        num += wn * M;
+        W += wn;
+    }
+    const double iW = 1.0 / W;
+    const double Nin = num * iW;
+    const double dN = nhi * X.alpha * ds;
+
+    // ownership as in the forward
+    bool owned = true;
+    if (X.pc.kind == 1) {
+        if (((o & 1) && cA == 0) || ((o & 2) && cB == 0) || ((o & 4) && cC == 0)) owned = false;
+        if (X.pc.dom >= 0 && canon != X.pc.dom) owned = false;
+    }
+    // N_out = N_in + dN: both receive Nbar_out; the rate adds its own parts
+    double Nin_bar = Nbar_out, dN_bar = Nbar_out, qb = 0.0;
+    const double ta = X.sigma0 * Nin;
+    const double gbar = owned ? gbar_grid[cp] : 0.0;
+    if (gbar != 0.0 && ta < X.tp.tau_hi) {
+        double D, Da, Ddt;
+        rate_derivs64(X.tab, X.m64, X.tp, ta, X.sigma0 * dN, &D, &Da, &Ddt);
+        const double k = -X.coef / (double)r2;          // Gamma = k D
+        Nin_bar += gbar * k * Da * X.sigma0;
+        dN_bar += gbar * k * Ddt * X.sigma0;
+        qb = gbar * k * D;                              // = gbar Gamma
+    }
+    out.cp = cp;
+    out.nbar = dN_bar * X.alpha * ds;                   // dN = n_HI alpha ds
+    out.qbar = qb;
+    out.nbar_src = 0.0;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        const double dNin_dM = (wv[n] + (Mv[n] - Nin) * dw[n]) * iW;
+        const double mb = nslot[n] == -2 ? 0.0 : Nin_bar * dNin_dM;
+        if (nslot[n] == -1) out.nbar_src += mb * (X.reading == 0 ? X.alpha * ds * 0.5 : X.alpha * 0.5);
+        out.slot[n] = nslot[n];
+        out.qn[n] = nq[n];
+        out.Mbar[n] = mb;
+    }
+}
+
+// Adjoint of the source cell's own rate: d Gamma_s / d n_HI(s) and Gamma_s.
+__host__ __device__ __forceinline__ void source_cell_adjoint(const TabNode *T, const double *m64,
+                                                             const TabParams &tp, double sigma0,
+                                                             double alpha, double Q, double n_s,
+                                                             double gbar, double *nbar, double *qbar)
+{
+    const double tau_s = sigma0 * n_s * alpha * 0.5;
+    double D, Da, Ddt;
+    rate_derivs64(T, m64, tp, 0.0, tau_s, &D, &Da, &Ddt);
+    const double k = -Q * sigma0 / (2.0 * alpha * alpha);
+    *nbar = gbar * k * Ddt * sigma0 * alpha * 0.5;
+    *qbar = gbar * k * D;
 }
 
 // Rate of the source cell itself: entry column 0, path half a cell, volume
@@ -403,7 +741,7 @@ __host__ __device__ __forceinline__ double source_cell_rate(const TabNode *T, co
 {
     const double tau_s = sigma0 * n_s * alpha * 0.5;
     const float nd = neg_divdiff(T, tp, 0.0, tau_s);
-    return Q * sigma0 / (2.0 * alpha * alpha) * (double)nd;
+    return Q * sigma0 / (2.0 * alpha * alpha) * (double)nd;   // once per source
 }
 
 // Build the row table of shell q of a piece (serial form; the kernel runs
@@ -423,5 +761,72 @@ __host__ __device__ inline int build_rows(const Piece &pc, const Extent &ex, int
     rowstart[nrows] = run;
     return run;
 }
+
+#if defined(__HIPCC__)
+constexpr int kRowsPerLane = 4;   // wave sweeps: rows per shell <= 64 * kRowsPerLane
+
+// Order LDS traffic of one wave: its own writes before its later reads.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Next work item of a wave from the global counter.  Every lane takes part in
+// the one atomic (lane 0 adds 1, the others 0) and the item is lane 0's
+// result, read into a scalar register.  There is no branch on the lane index
+// here: with `if (lane == 0) fetch` followed by a broadcast, the compiler may
+// merge that branch with a lane-0 branch at the end of the previous item and
+// run lane 0 and lanes 1..63 around separate loops, so that the broadcast runs
+// without lane 0 and lanes 1..63 never see the end of the work.  The scalar
+// result also lets the compiler treat everything derived from the item as
+// wave-uniform.
+__device__ __forceinline__ int next_item(int *counter, int lane)
+{
+    const int got = atomicAdd(counter, lane == 0 ? 1 : 0);
+    return __builtin_amdgcn_readfirstlane(got);
+}
+
+// Row table of shell q built by one wave: every lane owns up to kRowsPerLane
+// consecutive rows, counts them, and a wave-wide exclusive scan gives the
+// row starts.  Returns the shell's cell count (same value in every lane).
+__device__ __forceinline__ int wave_build_rows(const Piece &pc, const Extent &ex, int Rsq, int q,
+                                               int lane, int *rowstart, int *rowbase_q)
+{
+    const int nrows = pc.n_oct * (q + 1);
+    const int c = (nrows + 63) >> 6;
+    const int r0 = lane * c;
+    int blo_k[kRowsPerLane], cnt_k[kRowsPerLane];
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < kRowsPerLane; ++k) {
+        const int r = r0 + k;
+        blo_k[k] = 0;
+        cnt_k[k] = 0;
+        if (k < c && r < nrows) row_range(pc, ex, Rsq, q, r, &blo_k[k], &cnt_k[k]);
+        sum += cnt_k[k];
+    }
+    int incl = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    int run = incl - sum;
+#pragma unroll
+    for (int k = 0; k < kRowsPerLane; ++k) {
+        const int r = r0 + k;
+        if (k < c && r < nrows) {
+            rowstart[r] = run;
+            rowbase_q[r] = run - blo_k[k];
+            run += cnt_k[k];
+        }
+    }
+    const int total = __shfl(incl, 63, 64);
+    if (lane == 0) rowstart[nrows] = total;
+    return total;
+}
+#endif
 
 }  // namespace asora

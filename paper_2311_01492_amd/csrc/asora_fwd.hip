@@ -35,6 +35,8 @@ struct FwdArgs {
     int *err;
     int ring_cap, row_cap;
     int plain_src;          // >= 0: non-persistent launch for this source
+    int region_bytes;       // per-wave LDS region (wave kernels)
+    double coef_unit;       // sigma0 / (4 pi alpha^2)
 };
 
 struct Lds {
@@ -74,8 +76,9 @@ __device__ void sweep_piece(const FwdArgs &A, const Lds &L, int src, int p, int 
     X.sigma0 = A.sigma0;
     X.alpha = A.alpha;
     X.half_col = n_s * A.alpha * 0.5;
-    X.coef = Q * A.sigma0 / (4.0 * M_PI * A.alpha * A.alpha);
+    X.coef = Q * A.coef_unit;
     X.tab = L.tab;
+    X.m64 = nullptr;
     X.tp = A.tp;
     X.ring = L.ring;
     X.rowbase = L.rowbase;
@@ -144,6 +147,201 @@ __device__ void sweep_piece(const FwdArgs &A, const Lds &L, int src, int p, int 
         }
         __syncthreads();
     }
+}
+
+static FwdArgs make_args(const FwdLaunch &F);
+
+// Per-wave queue of pending rate evaluations (structure of arrays in LDS).
+constexpr int kQueue = 128;
+struct RateQueue {
+    double *ta;     // entry optical depth
+    float *dt;      // in-cell optical depth
+    uint32_t *cp;   // cell index
+    int *r2;        // squared distance (cells)
+};
+
+__device__ __forceinline__ void rate_batch(const FwdArgs &A, const TabNode *T, const RateQueue &Qa,
+                                           int head, int lane, double coef)
+{
+    const int pos = (head + lane) & (kQueue - 1);
+    const double ta = Qa.ta[pos];
+    const float nd = neg_divdiff(T, A.tp, ta, (double)Qa.dt[pos]);
+    if (nd > 0.f) {
+        const double G = coef * (double)(nd * rcp_approx((float)Qa.r2[pos]));
+        unsafeAtomicAdd(&A.gacc[Qa.cp[pos]], G);
+    }
+}
+
+template <int TYPE>
+__device__ void sweep_piece_wave(const FwdArgs &A, const TabNode *T, double *ring, int *rowbase,
+                                 int *rowstart, const RateQueue &Qa, int src, int p, int lane)
+{
+    const int N = A.N;
+    const int si = A.ijk[3 * src], sj = A.ijk[3 * src + 1], sk = A.ijk[3 * src + 2];
+    const float R = A.R ? A.R[src] : A.R_cap;
+    if (!(R >= 0.f && R <= A.R_cap) || si < 0 || si >= N || sj < 0 || sj >= N || sk < 0 ||
+        sk >= N) {
+        if (lane == 0) atomicOr(A.err, 1);
+        return;
+    }
+    const double Q = A.Q[src];
+    const int Rsq = (int)floor((double)R * (double)R);
+    const Piece pc = make_piece(TYPE, p);
+    const int Qmax = max_shell(Rsq, A.ex);
+    const long cs = ((long)si * N + sj) * N + sk;
+    const double n_s = A.nHI[cs];
+
+    CellCtx X;
+    X.pc = pc;
+    X.N = N;
+    X.si = si;
+    X.sj = sj;
+    X.sk = sk;
+    X.reading = A.reading;
+    X.tau_w = A.tau_w;
+    X.sigma0 = A.sigma0;
+    X.alpha = A.alpha;
+    X.half_col = n_s * A.alpha * 0.5;
+    X.coef = Q * A.coef_unit;
+    X.tab = T;
+    X.m64 = nullptr;
+    X.tp = A.tp;
+    X.ring = ring;
+    X.rowbase = rowbase;
+    X.ring_cap = A.ring_cap;
+    X.row_cap = A.row_cap;
+    X.nHI = A.nHI;
+
+    const bool src_owner = (pc.kind == 0) || (pc.oct == 0 && (pc.dom < 0 || pc.dom == 2));
+    if (src_owner && lane == 0) {
+        const double G = source_cell_rate(T, A.tp, A.sigma0, A.alpha, Q, n_s);
+        if (G != 0.0) unsafeAtomicAdd(&A.gacc[cs], G);
+        if (A.coldens) A.coldens[cs] = 0.0;
+    }
+    int head = 0, tail = 0;   // rate queue positions (wave-uniform)
+
+    for (int q = 1; q <= Qmax; ++q) {
+        const int slot = q & 3;
+        const int nrows = pc.n_oct * (q + 1);
+        int *rb_q = rowbase + slot * A.row_cap;
+        const int total = wave_build_rows(pc, A.ex, Rsq, q, lane, rowstart, rb_q);
+        wave_sync();
+        double *ring_q = ring + slot * A.ring_cap;
+        // columns for 64 cells at a time; cells whose rate is non-zero (owned,
+        // entry optical depth below the table end) go to the wave's queue, and
+        // every full 64 queued rates are evaluated by all lanes together
+        for (int g0 = 0; g0 < total; g0 += 64) {
+            const int g = g0 + lane;
+            bool want = false;
+            CellOut co;
+            co.Nin = 0.0;
+            if (g < total) {
+                const int row = find_row(rowstart, nrows, g);
+                cell_update<false>(X, q, g, row, rb_q[row], co);
+                ring_q[g] = co.Nout;
+                if (co.owned) {
+                    if (A.coldens) A.coldens[co.cp] = co.Nin;
+                    want = A.sigma0 * co.Nin < A.tp.tau_hi;
+                }
+            }
+            const uint64_t mask = __ballot(want);
+            if (want) {
+                const int pos = (tail + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                  __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))) & (kQueue - 1);
+                Qa.ta[pos] = A.sigma0 * co.Nin;
+                Qa.dt[pos] = A.sigma0 * co.dN;
+                Qa.cp[pos] = co.cp;
+                Qa.r2[pos] = co.r2;
+            }
+            tail += __popcll(mask);
+            if (tail - head >= 64) {
+                wave_sync();
+                rate_batch(A, T, Qa, head, lane, X.coef);
+                head += 64;
+                wave_sync();
+            }
+        }
+        wave_sync();
+    }
+    // the rates still queued
+    if (tail > head) {
+        wave_sync();
+        if (lane < tail - head) rate_batch(A, T, Qa, head, lane, X.coef);
+        wave_sync();
+    }
+}
+
+// One wave per piece; the work-group only shares the table.  Persistent
+// (items from the global counter) or plain (item = wave index).
+template <int TYPE>
+__global__ __launch_bounds__(1024) void fwd_wave(FwdArgs A)
+{
+    extern __shared__ __align__(16) char smem[];
+    constexpr int npieces0 = TYPE == 0 ? 1 : (TYPE == 1 ? 8 : 24);
+    if (A.plain_src < 0 && A.seg[TYPE + 1] == A.seg[TYPE]) return;   // no sources of this kind
+    (void)npieces0;
+    TabNode *T = (TabNode *)smem;
+    {
+        const int4 *s = (const int4 *)A.tab;
+        int4 *d = (int4 *)smem;
+        for (int k = threadIdx.x; k < A.tp.n; k += blockDim.x) d[k] = s[k];
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int waves = blockDim.x >> 6;
+    char *region = smem + (size_t)A.tp.n * sizeof(TabNode) + (size_t)wave * A.region_bytes;
+    double *ring = (double *)region;
+    RateQueue Qa;
+    Qa.ta = ring + 4 * (size_t)A.ring_cap;
+    Qa.dt = (float *)(Qa.ta + kQueue);
+    Qa.cp = (uint32_t *)(Qa.dt + kQueue);
+    Qa.r2 = (int *)(Qa.cp + kQueue);
+    int *rowbase = Qa.r2 + kQueue;
+    int *rowstart = rowbase + 4 * A.row_cap;
+    constexpr int npieces = TYPE == 0 ? 1 : (TYPE == 1 ? 8 : 24);
+    if (A.plain_src >= 0) {
+        const int item = blockIdx.x * waves + wave;
+        if (item < npieces)
+            sweep_piece_wave<TYPE>(A, T, ring, rowbase, rowstart, Qa, A.plain_src, item, lane);
+        return;
+    }
+    const int base = A.seg[TYPE];
+    const long nitems = (long)(A.seg[TYPE + 1] - base) * npieces;
+    for (;;) {
+        const int item = next_item(A.counter, lane);
+        if (item >= nitems) break;
+        const int src = A.order[base + item / npieces];
+        sweep_piece_wave<TYPE>(A, T, ring, rowbase, rowstart, Qa, src, item % npieces, lane);
+    }
+}
+
+size_t wave_region_bytes(int ring_cap, int row_cap)
+{
+    const size_t b = 4 * (size_t)ring_cap * sizeof(double) +
+                     (size_t)kQueue * (sizeof(double) + sizeof(float) + sizeof(uint32_t) + sizeof(int)) +
+                     (4 * (size_t)row_cap + row_cap + 1) * sizeof(int);
+    return (b + 15) & ~(size_t)15;
+}
+
+hipError_t wave_occupancy(int type, int waves, size_t lds, int *blocks_per_cu)
+{
+    const void *f = type == 0 ? (const void *)fwd_wave<0> : (type == 1 ? (const void *)fwd_wave<1> : (const void *)fwd_wave<2>);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, waves * 64, lds);
+}
+
+hipError_t launch_fwd_wave(hipStream_t st, const FwdLaunch &F, int waves, int grid, int plain_src)
+{
+    FwdArgs A = make_args(F);
+    A.plain_src = plain_src;
+    A.region_bytes = (int)wave_region_bytes(F.ring_cap, F.row_cap);
+    const size_t lds = (size_t)F.tp.n * sizeof(TabNode) + (size_t)waves * A.region_bytes;
+    if (plain_src >= 0) grid = (pieces_of_type(F.type) + waves - 1) / waves;
+    switch (F.type) {
+    case 0: hipLaunchKernelGGL(fwd_wave<0>, dim3(grid), dim3(64 * waves), lds, st, A); break;
+    case 1: hipLaunchKernelGGL(fwd_wave<1>, dim3(grid), dim3(64 * waves), lds, st, A); break;
+    default: hipLaunchKernelGGL(fwd_wave<2>, dim3(grid), dim3(64 * waves), lds, st, A); break;
+    }
+    return hipGetLastError();
 }
 
 __device__ Lds carve_lds(char *smem, const FwdArgs &A)
@@ -328,6 +526,8 @@ static FwdArgs make_args(const FwdLaunch &F)
     A.ring_cap = F.ring_cap;
     A.row_cap = F.row_cap;
     A.plain_src = -1;
+    A.region_bytes = 0;
+    A.coef_unit = F.sigma0 / (4.0 * M_PI * F.alpha * F.alpha);
     return A;
 }
 
@@ -346,6 +546,9 @@ hipError_t fwd_configure(size_t max_lds)
                               hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipFuncSetAttribute((const void *)fwd_plain, hipFuncAttributeMaxDynamicSharedMemorySize,
                               dyn);
+    (void)hipFuncSetAttribute((const void *)fwd_wave<0>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)fwd_wave<1>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)fwd_wave<2>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipGetLastError();
     return hipSuccess;
 }

@@ -93,7 +93,7 @@ int table_blackbody(double T_bb, double index, int n, double lg_lo, double lg_hi
 // The table in the form the kernels read (see TabNode): node values ln P,
 // log-log slopes tau P'/P, FP32 P, and the parameters of the node grid.
 void prepare_table(int n, double lg_lo, double lg_hi, const double *P, const double *dP,
-                   TabParams *tp, TabNode *nodes)
+                   TabParams *tp, TabNode *nodes, double *m64)
 {
     const double ln10 = std::log(10.0);
     tp->n = n;
@@ -108,8 +108,10 @@ void prepare_table(int n, double lg_lo, double lg_hi, const double *P, const dou
     for (int k = 0; k < n; ++k) {
         const double tk = std::exp(tp->x_lo + h * k);
         nodes[k].y = std::log(P[k]);
-        nodes[k].m = (float)(tk * dP[k] / P[k]);
+        const double m = tk * dP[k] / P[k];
+        nodes[k].m = (float)m;
         nodes[k].P = (float)P[k];
+        if (m64) m64[k] = m;
     }
 }
 

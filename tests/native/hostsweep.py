@@ -37,6 +37,8 @@ def load():
         lib.hc_raytrace.argtypes = [i, d, d, i, d, d, p, p, d, i, p, p, l, p, p, p, f, f, i, p, p]
         lib.hc_neg_divdiff_batch.restype = None
         lib.hc_neg_divdiff_batch.argtypes = [i, d, d, p, p, l, p, p, p]
+        lib.hc_raytrace_grad.restype = i
+        lib.hc_raytrace_grad.argtypes = [i, d, d, i, d, d, p, p, d, i, p, p, l, p, p, p, f, f, i, p, p, p]
         lib.hc_rows.restype = i
         lib.hc_rows.argtypes = [i, i, i, i, i, p, p]
         _lib = lib
@@ -84,3 +86,25 @@ def rows(N, type_, piece, Rsq, q):
     cnt = np.zeros(n, np.int32)
     lib.hc_rows(N, type_, piece, Rsq, q, _p(blo), _p(cnt))
     return blo, cnt
+
+
+def raytrace_grad(N, cell_cm, sigma0, table, n_H, x_HI, ijk, Q, R, gbar, tau_w=0.6, reading=0,
+                  type_force=-1, R_whole=10.0, R_oct=30.0):
+    """(dL/dn_H, dL/dx_HI, dL/dQ) for dL/dGamma = gbar (FP64)."""
+    lib = load()
+    P, dP = np.ascontiguousarray(table.P, np.float64), np.ascontiguousarray(table.dP, np.float64)
+    nH = np.ascontiguousarray(n_H, np.float32)
+    xH = np.ascontiguousarray(x_HI, np.float32)
+    ijk = np.ascontiguousarray(ijk, np.int32)
+    Q = np.ascontiguousarray(Q, np.float64)
+    R = np.ascontiguousarray(R, np.float32)
+    gb = np.ascontiguousarray(gbar, np.float64)
+    nbar = np.zeros(N ** 3)
+    qbar = np.zeros(len(Q))
+    st = lib.hc_raytrace_grad(N, cell_cm, sigma0, len(P), table.lg_lo, table.lg_hi, _p(P), _p(dP),
+                              float(tau_w), reading, _p(nH), _p(xH), len(Q), _p(ijk), _p(Q), _p(R),
+                              R_whole, R_oct, type_force, _p(gb), _p(nbar), _p(qbar))
+    if st != 0:
+        raise RuntimeError(f"host grad failed: {st}")
+    nbar = nbar.reshape((N,) * 3)
+    return xH.astype(np.float64) * nbar, nH.astype(np.float64) * nbar, qbar

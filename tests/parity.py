@@ -24,3 +24,13 @@ def assert_parity(g, o, tol, floor=1e-20, what="gamma"):
     assert small <= tol, f"{what}: below-floor abs err {small:.3e} (in floor units) > {tol:.1e}"
     zero = np.asarray(o) == 0
     assert np.all(np.asarray(g)[zero] == 0), f"{what}: non-zero where the oracle is exactly 0"
+
+
+def assert_grad_parity(g, o, tol, floor=1e-6, what="grad"):
+    """Gradient entries can be sums of large terms of both signs, so the
+    relative error is taken against max(|o_i|, floor * max|o|)."""
+    g = np.asarray(g, np.float64)
+    o = np.asarray(o, np.float64)
+    scale = np.maximum(np.abs(o), floor * np.abs(o).max())
+    rel = float((np.abs(g - o) / scale).max())
+    assert rel <= tol, f"{what}: max rel err {rel:.3e} > {tol:.1e}"

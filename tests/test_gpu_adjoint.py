@@ -1,0 +1,141 @@
+"""GPU adjoint (asora_raytrace_backward) against the FP64 oracle's reverse
+mode and against central finite differences of the oracle forward, for the
+loss L = sum_p w_p log10(Gamma_p + 1e-20) with w ~ N(0,1) per cell."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.parity import assert_grad_parity
+from workloads import make_workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def asora():
+    import paper_2311_01492_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def bb():
+    return oracle.blackbody_table()
+
+
+def _loss_grad(g, wt):
+    return wt / ((g + 1e-20) * math.log(10))
+
+
+def _gpu_backward(asora, w, table, gbar, **kw):
+    ctx = asora.Asora(w.N, w.cell_cm, table.P, table.dP, table.lg_lo, table.lg_hi, **kw)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    dn, dx, dq = ctx.backward(t(w.n_H), t(w.x_HI), t(w.src.ijk), t(w.src.Q), t(w.src.R), t(gbar))
+    ctx.check()
+    return (dn.cpu().numpy().astype(np.float64), dx.cpu().numpy().astype(np.float64),
+            dq.cpu().numpy())
+
+
+def _case(name, **kw):
+    w = make_workload(name, **kw)
+    bb = oracle.blackbody_table()
+    g = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
+    wt = np.random.default_rng(4).standard_normal(g.shape)
+    return w, g, wt
+
+
+def test_c4_against_oracle_reverse(asora, bb):
+    print("case c4 adjoint vs oracle", flush=True)
+    w, g, wt = _case("c4")
+    gbar = _loss_grad(g, wt)
+    on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
+                                      w.src.R, gbar)
+    gn, gx, gq = _gpu_backward(asora, w, bb, gbar)
+    assert_grad_parity(gn, on, 1e-5, what="dL/dn_H")
+    assert_grad_parity(gx, ox, 1e-5, what="dL/dx_HI")
+    np.testing.assert_allclose(gq, oq, rtol=1e-5)
+
+
+@pytest.mark.parametrize("tau_w,scalar", [(math.inf, False), (0.6, True)])
+def test_uneven_radii_all_piece_kinds(asora, bb, tau_w, scalar):
+    print("case adjoint uneven", tau_w, scalar, flush=True)
+    w, g, wt = _case("c2", N=40, n_src=24, R=(2.0, 38.0))
+    g = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R,
+                        tau_w=tau_w, reading=1 if scalar else 0)
+    gbar = _loss_grad(g, wt)
+    on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
+                                      w.src.R, gbar, tau_w=tau_w, reading=1 if scalar else 0)
+    gn, gx, gq = _gpu_backward(asora, w, bb, gbar, tau_w=tau_w, halfpath_scalar=scalar)
+    assert_grad_parity(gn, on, 1e-5, what="dL/dn_H")
+    assert_grad_parity(gx, ox, 1e-5, what="dL/dx_HI")
+    np.testing.assert_allclose(gq, oq, rtol=1e-5)
+
+
+def _covering(w, c):
+    d = (np.asarray(c)[None, :] - w.src.ijk + w.N // 2) % w.N - w.N // 2
+    return np.nonzero((d ** 2).sum(axis=1) <= w.src.R.astype(np.float64) ** 2)[0]
+
+
+def test_c4_against_finite_differences(asora, bb):
+    """Central differences (step 1e-4 relative) of the FP64 oracle forward on
+    100 seeded entries: 40 of n_H, 40 of x_HI, 20 of Q.  Only the sources whose
+    ball holds the perturbed cell are re-run (the others do not change)."""
+    print("case c4 adjoint vs FD", flush=True)
+    w, g, wt = _case("c4")
+    gbar = _loss_grad(g, wt)
+    gn, gx, gq = _gpu_backward(asora, w, bb, gbar)
+    rng = np.random.default_rng(9)
+    nH = w.n_H.astype(np.float64)
+    xH = w.x_HI.astype(np.float64)
+    dl = lambda gp, gm: float(np.sum(wt * (np.log10(gp + 1e-20) - np.log10(gm + 1e-20))))
+    cells = np.argwhere(g > 1e-6 * g.max())
+    errs = []
+    for field, grad, name in ((nH, gn, "n_H"), (xH, gx, "x_HI")):
+        for c in map(tuple, cells[rng.choice(len(cells), 40, replace=False)]):
+            S = _covering(w, c)
+            sub = w.src.subset(S)
+            base = oracle.raytrace(w.N, w.cell_cm, bb, nH, xH, sub.ijk, sub.Q, sub.R)
+            h = 1e-4 * field[c]
+            fp, fm = field.copy(), field.copy()
+            fp[c] += h
+            fm[c] -= h
+            args = (lambda f: (f, xH)) if field is nH else (lambda f: (nH, f))
+            gp = g - base + oracle.raytrace(w.N, w.cell_cm, bb, *args(fp), sub.ijk, sub.Q, sub.R)
+            gm = g - base + oracle.raytrace(w.N, w.cell_cm, bb, *args(fm), sub.ijk, sub.Q, sub.R)
+            fd = dl(gp, gm) / (2 * h)
+            scale = max(abs(fd), 1e-6 * np.abs(grad).max())
+            errs.append(abs(grad[c] - fd) / scale)
+            assert abs(grad[c] - fd) <= 1e-4 * scale, (name, c, grad[c], fd)
+    for s in rng.choice(len(w.src), 20, replace=False):
+        sub = w.src.subset([s])
+        base = oracle.raytrace(w.N, w.cell_cm, bb, nH, xH, sub.ijk, sub.Q, sub.R)
+        h = 1e-4 * w.src.Q[s]
+        gp = g - base + oracle.raytrace(w.N, w.cell_cm, bb, nH, xH, sub.ijk, sub.Q + h, sub.R)
+        gm = g - base + oracle.raytrace(w.N, w.cell_cm, bb, nH, xH, sub.ijk, sub.Q - h, sub.R)
+        fd = dl(gp, gm) / (2 * h)
+        errs.append(abs(gq[s] - fd) / abs(fd))
+        assert gq[s] == pytest.approx(fd, rel=1e-4)
+    print("max rel err vs FD", max(errs), flush=True)
+
+
+def test_autograd_function(asora, bb):
+    """torch.autograd through asora.raytrace gives the adjoint kernels' gradients."""
+    w = make_workload("c2", N=32, n_src=10, R=(3.0, 14.0))
+    ctx = asora.Asora(w.N, w.cell_cm, bb.P, bb.dP, bb.lg_lo, bb.lg_hi)
+    dev = torch.device("cuda")
+    nH = torch.from_numpy(w.n_H).to(dev).requires_grad_(True)
+    xH = torch.from_numpy(w.x_HI).to(dev).requires_grad_(True)
+    Q = torch.from_numpy(w.src.Q).to(dev).requires_grad_(True)
+    ijk = torch.from_numpy(w.src.ijk).to(dev)
+    R = torch.from_numpy(w.src.R).to(dev)
+    wt = torch.from_numpy(np.random.default_rng(2).standard_normal((w.N,) * 3)).to(dev)
+    gam = asora.raytrace(ctx, nH, xH, ijk, Q, R)
+    loss = (wt * torch.log10(gam.double() + 1e-20)).sum()
+    loss.backward()
+    gbar = (wt / ((gam.detach().double() + 1e-20) * math.log(10)))
+    dn, dx, dq = ctx.backward(nH.detach(), xH.detach(), ijk, Q.detach(), R, gbar)
+    torch.testing.assert_close(nH.grad, dn, rtol=1e-5, atol=1e-6 * float(dn.abs().max()))
+    torch.testing.assert_close(xH.grad, dx, rtol=1e-5, atol=1e-6 * float(dx.abs().max()))
+    torch.testing.assert_close(Q.grad, dq, rtol=1e-6, atol=0)

@@ -124,3 +124,24 @@ def test_row_enumeration_matches_brute_force(N):
                 assert sorted(got) == sorted(want)
             else:
                 assert set(got) == want          # ghosts duplicate cells, nothing missing or extra
+
+
+@pytest.mark.parametrize("type_force", [-1, 0, 1, 2])
+@pytest.mark.parametrize("tau_w,reading", [(0.6, 0), (math.inf, 0), (0.6, 1)])
+def test_adjoint_matches_oracle_reverse(bb, type_force, tau_w, reading):
+    """The library's per-cell adjoint, driven serially over the reversed
+    shells, against the oracle's reverse mode for L = sum w log10(Gamma+1e-20)."""
+    w = make_workload("c4", N=24, n_src=6, R=(3.0, 11.0))
+    g = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R,
+                        tau_w=tau_w, reading=reading)
+    wt = np.random.default_rng(1).standard_normal(g.shape)
+    gbar = wt / ((g + 1e-20) * math.log(10))
+    on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
+                                      w.src.R, gbar, tau_w=tau_w, reading=reading)
+    hn, hx, hq = hostsweep.raytrace_grad(w.N, w.cell_cm, oracle.SIGMA0, bb, w.n_H, w.x_HI,
+                                         w.src.ijk, w.src.Q, w.src.R, gbar, tau_w=tau_w,
+                                         reading=reading, type_force=type_force)
+    from tests.parity import assert_grad_parity
+    assert_grad_parity(hn, on, 1e-5, what="dL/dn_H")
+    assert_grad_parity(hx, ox, 1e-5, what="dL/dx_HI")
+    np.testing.assert_allclose(hq, oq, rtol=1e-6)
