@@ -1,17 +1,28 @@
-"""Benchmark of the ASORA ray-tracing step on one MI355X.
+"""Benchmark of the ASORA ray-tracing step (forward and adjoint) on one MI355X.
 
-A step is one asora_raytrace call over the whole source list of the
-workload (n_HI and accumulator set-up, scheduling sort, persistent sweep,
-FP32 conversion), inputs resident in HBM.  The metric is the paper's
-time per source per voxel, t / sum_s (4/3) pi R_s^3 (Section 4.2), in ns.
+A step is one pass of the whole hot path over the workload's source list:
+the forward sweep (asora_raytrace: n_HI and accumulator set-up, scheduling
+sort, persistent sweep over all source pieces, FP32 conversion of Gamma)
+followed by the adjoint (asora_raytrace_backward: the same set-up, per-piece
+recomputation of the columns, reverse sweep, dL/dn_H and dL/dx_HI
+conversion) for a fixed dL/dGamma, all inputs resident in HBM.  The metric
+is the paper's time per source per voxel, t / sum_s (4/3) pi R_s^3
+(Section 4.2), in ns: `value` is the forward+adjoint step; the batched
+forward alone and the plain form (one launch per source) are reported beside
+it.
 
-Default workload: 128^3 grid, 1.4 Mpc cells, lognormal density with
-ionized bubbles, 1000 sources, R = 30 cells (FP32 in, FP64 columns).
-Prints one JSON line.
+Default workload: 128^3 grid, 1.4 Mpc cells, lognormal density with ionized
+bubbles, 1000 sources, R = 30 cells.  Prints one JSON line.
+
+`--reduce-pmc DIR` turns rocprofv3 counter runs (CSV output) of this script
+into the per-launch HBM traffic file read here (see the design doc for the
+commands).
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
 import hashlib
 import json
 import math
@@ -24,9 +35,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ns per source-voxel (ASORA fwd, fwd+adjoint), batched vs plain, at 1e-5 rel err"
 HBM_PEAK_GBS = 8000.0
-ALG_BYTES_PER_SV = 16.0   # n_H + x_HI gather (2 x FP32) + rate read-modify-write (2 x FP32)
-KERNEL_SOURCES = ["paper_2311_01492_amd/csrc/asora_dev.h", "paper_2311_01492_amd/csrc/asora_fwd.hip"]
-PMC_FILE = os.path.join(ROOT, "profiles", "fwd_persistent_c2_pmc.json")
+# algorithmic HBM bytes per source-voxel
+FWD_BYTES_PER_SV = 16.0   # n_H + x_HI reads (2 x FP32), Gamma read-modify-write (2 x FP32)
+ADJ_BYTES_PER_SV = 32.0   # n_H + x_HI (2 x FP32), dL/dGamma (FP64), dL/dn_HI read-modify-write (2 x FP64)
+KERNEL_SOURCES = ["paper_2311_01492_amd/csrc/asora_dev.h", "paper_2311_01492_amd/csrc/asora_fwd.hip",
+                  "paper_2311_01492_amd/csrc/asora_adj.hip"]
+KERNELS = {"fwd": "fwd_wave", "adj": "adj_wave"}
 
 WORKLOADS = {
     "c2": dict(name="c2", kw={}, plain_src=1000,
@@ -47,26 +61,110 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
+def pmc_file(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
+
+
+# ---------------------------------------------------------------------------
+def _read_counter_csv(path):
+    """{kernel name: {counter: [value per dispatch]}} from a rocprofv3
+    counter_collection.csv."""
+    out = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            name = row.get("Kernel_Name", "")
+            ctr = row.get("Counter_Name", "")
+            val = float(row.get("Counter_Value", "nan"))
+            out.setdefault(name, {}).setdefault(ctr, []).append(val)
+    return out
+
+
+def _per_dispatch(table, kernel_substr, counter):
+    vals = [v for name, c in table.items() if kernel_substr in name for v in c.get(counter, [])]
+    return sum(vals) / len(vals) if vals else None
+
+
+def reduce_pmc(directory: str, workload: str):
+    """Combine four rocprofv3 --pmc runs (CSV) found under `directory`:
+    fetch/ and write/ (FETCH_SIZE, WRITE_SIZE of this benchmark), and
+    copy_fetch/ and copy_write/ (the same counters for `--copy-calibration`,
+    a 1 GiB device copy).  Each counter is scaled by known bytes / counted
+    bytes of the copy, per launch of each sweep kernel."""
+    def load(sub):
+        files = glob.glob(os.path.join(directory, sub, "**", "*counter_collection.csv"), recursive=True)
+        if not files:
+            raise SystemExit(f"no counter_collection.csv under {directory}/{sub}")
+        t = {}
+        for p in files:
+            for k, v in _read_counter_csv(p).items():
+                for c, vals in v.items():
+                    t.setdefault(k, {}).setdefault(c, []).extend(vals)
+        return t
+    fetch, write, cf, cw = load("fetch"), load("write"), load("copy_fetch"), load("copy_write")
+    copy_bytes = float(1 << 30)
+    # the copy kernel is the largest single dispatch of the calibration run
+    cf_kib = max(sum(v) / len(v) for k in cf.values() for c, v in k.items() if c == "FETCH_SIZE")
+    cw_kib = max(sum(v) / len(v) for k in cw.values() for c, v in k.items() if c == "WRITE_SIZE")
+    f_read = copy_bytes / (cf_kib * 1024.0)
+    f_write = copy_bytes / (cw_kib * 1024.0)
+    res = {"kernel_sha": kernel_sha(), "workload": workload,
+           "calibration": {"copy_bytes": copy_bytes, "fetch_kib": cf_kib, "write_kib": cw_kib,
+                           "read_factor": f_read, "write_factor": f_write},
+           "kernels": {}}
+    for key, sub in KERNELS.items():
+        if _per_dispatch(fetch, sub, "FETCH_SIZE") is None or _per_dispatch(write, sub, "WRITE_SIZE") is None:
+            continue
+        # one dispatch per piece kind up to the largest radius in each call (the
+        # kinds without sources return at once), so the per-call sum over the
+        # kinds is what one call moves; kind 0 is launched once per call
+        nf = sum(len(c.get("FETCH_SIZE", [])) for n, c in fetch.items() if sub in n)
+        calls = sum(len(c.get("FETCH_SIZE", [])) for n, c in fetch.items() if sub + "<0>" in n)
+        calls_w = sum(len(c.get("WRITE_SIZE", [])) for n, c in write.items() if sub + "<0>" in n)
+        if calls == 0 or calls != calls_w:
+            raise SystemExit(f"{sub}: {calls} / {calls_w} calls in the two counter runs")
+        fsum = sum(v for n, c in fetch.items() if sub in n for v in c.get("FETCH_SIZE", []))
+        wsum = sum(v for n, c in write.items() if sub in n for v in c.get("WRITE_SIZE", []))
+        res["kernels"][key] = {
+            "kernel": sub,
+            "fetch_bytes_per_call": fsum / calls * 1024.0 * f_read,
+            "write_bytes_per_call": wsum / calls * 1024.0 * f_write,
+            "hbm_bytes_per_call": (fsum * f_read + wsum * f_write) / calls * 1024.0,
+            "dispatches": nf, "calls": calls,
+        }
+    os.makedirs(os.path.dirname(pmc_file(workload)), exist_ok=True)
+    with open(pmc_file(workload), "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res))
+
+
+# ---------------------------------------------------------------------------
 def cpu_baseline(w, budget_s: float = 12.0):
-    """The FP64 oracle as it stands, single-threaded, on the first sources of
+    """The FP64 oracle as it stands (forward, then reverse for
+    L = sum w log10(Gamma + 1e-20)), single-threaded, on the first sources of
     the same workload until about budget_s of CPU time."""
     import numpy as np
 
     import oracle
     tb = oracle.blackbody_table()
+    rng = np.random.default_rng(7)
     oracle.raytrace(w.N, w.cell_cm, tb, w.n_H, w.x_HI, w.src.ijk[:1], w.src.Q[:1], w.src.R[:1])
     done, work, t = 0, 0.0, 0.0
-    chunk = 8
+    chunk = 4
     while t < budget_s and done < len(w.src):
         sl = slice(done, min(done + chunk, len(w.src)))
+        ijk, Q, R = w.src.ijk[sl], w.src.Q[sl], w.src.R[sl]
         t0 = time.perf_counter()
-        oracle.raytrace(w.N, w.cell_cm, tb, w.n_H, w.x_HI, w.src.ijk[sl], w.src.Q[sl], w.src.R[sl])
+        g = oracle.raytrace(w.N, w.cell_cm, tb, w.n_H, w.x_HI, ijk, Q, R)
         t += time.perf_counter() - t0
-        work += float(np.sum(4.0 / 3.0 * math.pi * w.src.R[sl].astype(np.float64) ** 3))
+        gbar = rng.standard_normal(g.shape) / ((g + 1e-20) * math.log(10))
+        t0 = time.perf_counter()
+        oracle.raytrace_grad(w.N, w.cell_cm, tb, w.n_H, w.x_HI, ijk, Q, R, gbar)
+        t += time.perf_counter() - t0
+        work += float(np.sum(4.0 / 3.0 * math.pi * R.astype(np.float64) ** 3))
         done = sl.stop
     return {"value": t / work * 1e9, "unit": "ns per source-voxel", "cores": 1, "kind": "oracle",
-            "sample": f"first {done} of {len(w.src)} sources of the same workload "
-                      f"({t:.1f} s, one thread, FP64)"}
+            "sample": f"forward + reverse of the first {done} of {len(w.src)} sources of the same "
+                      f"workload ({t:.1f} s, one thread, FP64)"}
 
 
 def main():
@@ -79,12 +177,16 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-source form")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--reduce-pmc", metavar="DIR", help="reduce rocprofv3 counter CSVs and exit")
     args = ap.parse_args()
+    if args.reduce_pmc:
+        reduce_pmc(args.reduce_pmc, args.workload)
+        return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(sources would shard over GPUs with one all-reduce of Gamma, not built here)",
-              file=sys.stderr)
+        print(f"bench.py: one GPU only; --gpus {args.gpus} is not supported (sources would shard "
+              f"over GPUs with one all-reduce of Gamma, which is not built)", file=sys.stderr)
         sys.exit(2)
+    args.steps = max(1, min(args.steps, 32))   # the library keeps events of the last 64 calls
 
     import numpy as np
     import torch
@@ -93,7 +195,7 @@ def main():
         n = 1 << 28
         a = torch.ones(n, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
-        for _ in range(5):
+        for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read_per_launch": 4 * n, "copy_bytes_written_per_launch": 4 * n}))
@@ -115,66 +217,98 @@ def main():
     R = torch.from_numpy(w.src.R).to(dev)
     R_max = float(w.src.R.max())
     work = w.work_sphere
-    gamma = torch.empty(w.N ** 3, dtype=torch.float32, device=dev)
+    n3 = w.N ** 3
+    gamma = torch.empty(n3, dtype=torch.float32, device=dev)
+    dn = torch.empty(n3, dtype=torch.float32, device=dev)
+    dx = torch.empty(n3, dtype=torch.float32, device=dev)
+    dq = torch.empty(len(w.src), dtype=torch.float64, device=dev)
 
-    def step(plain=False, n=None, profile=False):
+    # dL/dGamma of L = sum w log10(Gamma + 1e-20), w ~ N(0,1) seeded, at this Gamma
+    ctx.raytrace(nH, xH, ijk, Q, R, R_max=R_max, out=gamma)
+    wt = torch.from_numpy(np.random.default_rng(w.seed + 1).standard_normal(n3)).to(dev)
+    gbar = (wt / ((gamma.double() + 1e-20) * math.log(10))).contiguous()
+
+    def fwd(profile=False, plain=False, n=None):
         s = slice(0, n)
         ctx.raytrace(nH, xH, ijk[s], Q[s], R[s], R_max=R_max, out=gamma, plain=plain, profile=profile)
 
+    def adj(profile=False):
+        ctx.backward(nH, xH, ijk, Q, R, gbar, R_max=R_max, profile=profile, out=(dn, dx, dq))
+
+    # ---- the step: forward + adjoint, sweep kernels timed with HIP events
     for _ in range(args.warmup):
-        step()
+        fwd()
+        adj()
     torch.cuda.synchronize()
+    ctx.profile_read()
     print(f"[bench] warmup done, timing {args.steps} steps", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        fwd(profile=True)
+        adj(profile=True)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) / args.steps * 1e3
     ctx.check()
-    ns_sv = ms * 1e6 / work
+    prof = ctx.profile_read()
+    assert len(prof) == 2 * args.steps, len(prof)
+    fwd_sweep_ms = float(np.mean([p[0] for p in prof[0::2]]))
+    adj_sweep_ms = float(np.mean([p[0] for p in prof[1::2]]))
+    fwd_call_ms = float(np.mean([p[1] for p in prof[0::2]]))
+    adj_call_ms = float(np.mean([p[1] for p in prof[1::2]]))
 
-    # the dominant kernel (the persistent sweep), timed with HIP events on the
-    # stream it runs on, over the same number of steps
-    sweep = []
+    # ---- batched forward alone
+    print("[bench] batched forward", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(profile=True)
-        sweep.append(ctx.profile()[0])
-    sweep_ms = float(np.mean(sweep))
-    achieved = ALG_BYTES_PER_SV * work / (sweep_ms * 1e-3) / 1e9
+        fwd()
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t0) / args.steps * 1e3
 
-    traffic = None
-    if os.path.exists(PMC_FILE):
-        pmc = json.load(open(PMC_FILE))
+    traffic = {}
+    if os.path.exists(pmc_file(args.workload)):
+        pmc = json.load(open(pmc_file(args.workload)))
         if pmc.get("kernel_sha") == kernel_sha() and pmc.get("workload") == args.workload:
-            traffic = pmc.get("hbm_bytes_per_launch")
+            traffic = {k: v.get("hbm_bytes_per_call") for k, v in pmc.get("kernels", {}).items()}
+
+    def roof(bytes_per_sv, sweep_ms, kernel, key):
+        achieved = bytes_per_sv * work / (sweep_ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic.get(key),
+                "kernel": kernel, "launch_ms": sweep_ms,
+                "alg_bytes_per_source_voxel": bytes_per_sv, "source_voxels_per_launch": work}
 
     out = {
-        "metric": METRIC, "value": ns_sv, "unit": "ns per source-voxel", "n_gpus": 1,
+        "metric": METRIC, "value": ms * 1e6 / work, "unit": "ns per source-voxel", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64/f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {spec['desc']}", "grid": w.N,
                    "n_sources": len(w.src), "source_voxels": work, "seed": w.seed,
-                   "mode": "batched persistent"},
-        "sweep_ms": sweep_ms,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "fwd_persistent", "alg_bytes_per_source_voxel": ALG_BYTES_PER_SV},
+                   "step": "batched forward + adjoint (recompute)"},
+        # the adjoint sweep dominates the step
+        "roofline": roof(ADJ_BYTES_PER_SV, adj_sweep_ms, "adj_wave", "adj"),
+        "fwd": {"ns_per_source_voxel": fwd_ms * 1e6 / work, "ms_per_call": fwd_ms,
+                "roofline": roof(FWD_BYTES_PER_SV, fwd_sweep_ms, "fwd_wave", "fwd")},
+        "adjoint": {"ns_per_source_voxel": (ms - fwd_ms) * 1e6 / work,
+                    "sweep_ms": adj_sweep_ms, "call_ms": adj_call_ms},
+        "fwd_call_ms_in_step": fwd_call_ms,
     }
 
     if not args.no_plain:
         n = min(spec["plain_src"], len(w.src))
         sub_work = float(np.sum(4.0 / 3.0 * math.pi * w.src.R[:n].astype(np.float64) ** 3))
-        step(plain=True, n=n)
+        print(f"[bench] plain forward, {n} launches", file=sys.stderr, flush=True)
+        fwd(plain=True, n=n)
         torch.cuda.synchronize()
         reps = 2
         t0 = time.perf_counter()
         for _ in range(reps):
-            step(plain=True, n=n)
+            fwd(plain=True, n=n)
         torch.cuda.synchronize()
         pms = (time.perf_counter() - t0) / reps * 1e3
         out["plain"] = {"ns_per_source_voxel": pms * 1e6 / sub_work, "sources": n,
-                        "ms_per_call": pms, "plain_over_batched": (pms * 1e6 / sub_work) / ns_sv}
-    out["paper_context"] = {"value": 3.156, "unit": "ns per source-voxel",
+                        "ms_per_call": pms,
+                        "plain_over_batched_fwd": (pms * 1e6 / sub_work) / out["fwd"]["ns_per_source_voxel"]}
+    out["paper_context"] = {"value": 3.156, "unit": "ns per source-voxel (forward)",
                             "hardware": "1x NVIDIA Tesla P100, FP64 grid data",
                             "workload": "250^3, R in {10,30,50,100}, up to 1e6 sources (asymptote)"}
     if not args.no_cpu:

@@ -58,7 +58,8 @@ typedef enum {
 /* asora_raytrace / asora_raytrace_backward flags */
 #define ASORA_ACCUMULATE 0x1u  /* gamma += result (forward); gradients += (backward) */
 #define ASORA_PROFILE    0x4u  /* record HIP events around the sweep kernels and the
-                                  whole call on `stream`; read with asora_profile   */
+                                  whole call on `stream`; read with asora_profile or
+                                  asora_profile_read                                */
 #define ASORA_PLAIN      0x2u  /* one kernel launch per source, in input order: the
                                   unbatched baseline form (Section 3.3, one block per
                                   source).  Default: all sources in one persistent
@@ -224,6 +225,20 @@ asora_status asora_get_tuning(const asora_ctx *ctx, float *R_whole, float *R_oct
  * ASORA_ESTATE if no profiled call was made.
  */
 asora_status asora_profile(asora_ctx *ctx, double *sweep_ms, double *total_ms);
+
+/*
+ * asora_profile_read -- the same two durations (ms) for every call made with
+ * ASORA_PROFILE since the previous asora_profile_read, oldest first, into the
+ * host arrays sweep_ms[max_calls] and total_ms[max_calls].  The library keeps
+ * the events of the 64 most recent profiled calls; when more calls are pending
+ * than max_calls (or than 64), the most recent ones are returned.  *n_calls
+ * (may be NULL) receives the count written.  Waits for those events, so a
+ * timed loop of profiled calls can be read once at its end without a wait per
+ * call.  Afterwards no call is pending.  ASORA_EINVAL if max_calls < 0, or
+ * max_calls > 0 with a NULL array.
+ */
+asora_status asora_profile_read(asora_ctx *ctx, int32_t max_calls, int32_t *n_calls,
+                                double *sweep_ms, double *total_ms);
 
 /* asora_last_error -- text of the most recent error on ctx (or of the most
  * recent failed asora_init when ctx is NULL).  Owned by the library. */

@@ -32,7 +32,7 @@ _LIB_PATH = os.path.join(_HERE, "libasora.so")
 
 if not os.path.exists(_LIB_PATH):
     raise ImportError(f"{_LIB_PATH} is not built; run `python __graft_entry__.py` or "
-                      f"`python -m paper_2311_01492_amd.build` first (there is no CPU fallback)")
+                      f"`python paper_2311_01492_amd/build.py` first (there is no CPU fallback)")
 _lib = ctypes.CDLL(_LIB_PATH)
 
 _c_int, _c_i64, _c_u32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
@@ -54,6 +54,8 @@ _lib.asora_check.restype = _c_int
 _lib.asora_check.argtypes = [_p, _p]
 _lib.asora_profile.restype = _c_int
 _lib.asora_profile.argtypes = [_p, ctypes.POINTER(_c_d), ctypes.POINTER(_c_d)]
+_lib.asora_profile_read.restype = _c_int
+_lib.asora_profile_read.argtypes = [_p, _c_int, ctypes.POINTER(_c_int), _p, _p]
 _lib.asora_set_tuning.restype = _c_int
 _lib.asora_set_tuning.argtypes = [_p, _c_f, _c_f, _c_int]
 _lib.asora_get_tuning.restype = _c_int
@@ -176,14 +178,23 @@ class Asora:
         shape = (self.N,) * 3
         return (gamma.view(shape), cd.view(shape)) if coldens else gamma.view(shape)
 
-    def backward(self, n_H, x_HI, ijk, Q, R, dL_dgamma, R_max=None, profile=False, stream=None):
-        """(dL/dn_H, dL/dx_HI, dL/dQ) for the given dL/dgamma (converted to FP64)."""
+    def backward(self, n_H, x_HI, ijk, Q, R, dL_dgamma, R_max=None, profile=False, stream=None,
+                 out=None):
+        """(dL/dn_H, dL/dx_HI, dL/dQ) for the given dL/dgamma (converted to FP64).
+        out: optional (dn [N^3 float32], dx [N^3 float32], dq [n float64]) to fill."""
         ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
         dev = n_H.device
         g = dL_dgamma.to(dev, torch.float64).contiguous()
-        dn = torch.empty(self.N ** 3, dtype=torch.float32, device=dev)
-        dx = torch.empty_like(dn)
-        dq = torch.empty(n, dtype=torch.float64, device=dev)
+        if out is not None:
+            dn, dx, dq = out
+            for t, dt, m in ((dn, torch.float32, self.N ** 3), (dx, torch.float32, self.N ** 3),
+                             (dq, torch.float64, n)):
+                if t.dtype != dt or t.device != dev or not t.is_contiguous() or t.numel() != m:
+                    raise AsoraError(-1, "backward out buffers: contiguous cuda (N^3 f32, N^3 f32, n f64)")
+        else:
+            dn = torch.empty(self.N ** 3, dtype=torch.float32, device=dev)
+            dx = torch.empty_like(dn)
+            dq = torch.empty(n, dtype=torch.float64, device=dev)
         st = _lib.asora_raytrace_backward(self._h, _dptr(n_H), _dptr(x_HI), n, _dptr(ijk),
                                           _dptr(Q), _dptr(R), R_max, _dptr(g), _dptr(dn),
                                           _dptr(dx), _dptr(dq), PROFILE if profile else 0,
@@ -197,6 +208,16 @@ class Asora:
         a, b = _c_d(), _c_d()
         _raise(_lib.asora_profile(self._h, ctypes.byref(a), ctypes.byref(b)), self._h)
         return a.value, b.value
+
+    def profile_read(self, max_calls: int = 64):
+        """[(sweep_ms, total_ms), ...] of the profiled calls since the previous
+        read, oldest first (at most the last 64)."""
+        a = np.zeros(max_calls)
+        b = np.zeros(max_calls)
+        n = _c_int()
+        _raise(_lib.asora_profile_read(self._h, int(max_calls), ctypes.byref(n), _np_ptr(a),
+                                       _np_ptr(b)), self._h)
+        return list(zip(a[:n.value].tolist(), b[:n.value].tolist()))
 
     def set_tuning(self, R_whole=0.0, R_oct=0.0, max_waves=0):
         _raise(_lib.asora_set_tuning(self._h, float(R_whole), float(R_oct), int(max_waves)), self._h)

@@ -30,6 +30,8 @@ struct Plan {
     int grid;
 };
 
+static const int kProfSlots = 64;
+
 struct asora_ctx {
     int magic;
     int device;
@@ -56,8 +58,11 @@ struct asora_ctx {
     double *d_store;        // stored exit columns of the adjoint pieces in flight
     size_t store_cap;       // doubles
     std::map<PlanKey, Plan> adj_plans;
-    hipEvent_t ev[4];       // total start, sweep start, sweep stop, total stop
-    bool ev_ready, profiled;
+    // profiling: a ring of event quadruples (call start, sweep start, sweep
+    // stop, call stop), one per call made with ASORA_PROFILE
+    hipEvent_t pev[kProfSlots][4];
+    long prof_count;        // profiled calls so far
+    int prof_pending;       // profiled calls since the last summary reset (<= kProfSlots)
     std::string err;
 };
 
@@ -190,10 +195,10 @@ extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, d
         hipMemset(c->d_err, 0, sizeof(int)) != hipSuccess ||
         hipMemset(c->d_ctl, 0, sizeof(int) * kCtlSize) != hipSuccess)
         return bail(fail(nullptr, ASORA_EHIP, "asora_init: copy to device failed"));
-    for (int k = 0; k < 4; ++k)
-        if (hipEventCreate(&c->ev[k]) != hipSuccess)
-            return bail(fail(nullptr, ASORA_EHIP, "asora_init: hipEventCreate failed"));
-    c->ev_ready = true;
+    for (int sl = 0; sl < kProfSlots; ++sl)
+        for (int k = 0; k < 4; ++k)
+            if (hipEventCreate(&c->pev[sl][k]) != hipSuccess)
+                return bail(fail(nullptr, ASORA_EHIP, "asora_init: hipEventCreate failed"));
     if (fwd_configure(c->max_lds) != hipSuccess || adj_configure(c->max_lds) != hipSuccess)
         return bail(fail(nullptr, ASORA_EHIP, "asora_init: kernel attribute setup failed"));
     *out = c;
@@ -216,8 +221,9 @@ extern "C" asora_status asora_free(asora_ctx *c)
     (void)hipFree(c->d_order);
     (void)hipFree(c->d_nbar);
     (void)hipFree(c->d_store);
-    if (c->ev_ready)
-        for (int k = 0; k < 4; ++k) (void)hipEventDestroy(c->ev[k]);
+    for (int sl = 0; sl < kProfSlots; ++sl)
+        for (int k = 0; k < 4; ++k)
+            if (c->pev[sl][k]) (void)hipEventDestroy(c->pev[sl][k]);
     c->magic = 0;
     delete c;
     return ASORA_OK;
@@ -354,6 +360,7 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     if (flags & ~(ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_PROFILE))
         return fail(c, ASORA_EINVAL, "unknown flags");
     const bool prof = (flags & ASORA_PROFILE) != 0;
+    hipEvent_t *ev = c->pev[c->prof_count % kProfSlots];
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     const long n3 = (long)c->N * c->N * c->N;
@@ -383,13 +390,13 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     F.ctl = c->d_ctl;
     F.err = c->d_err;
 
-    if (prof) HIPCHK(c, hipEventRecord(c->ev[0], s));
+    if (prof) HIPCHK(c, hipEventRecord(ev[0], s));
     HIPCHK(c, launch_prologue(s, n_H, x_HI, c->d_nhi, c->d_gacc, coldens_in, n3, c->d_ctl,
                               kCtlSize, c->n_cu));
     if (n_src > 0 && !(flags & ASORA_PLAIN))
         HIPCHK(c, launch_bucketing(s, src_R, src_ijk, n_src, c->N, R_max, c->R_whole, c->R_oct,
                                    c->d_keys, c->d_ctl, c->d_order, c->d_err));
-    if (prof) HIPCHK(c, hipEventRecord(c->ev[1], s));
+    if (prof) HIPCHK(c, hipEventRecord(ev[1], s));
     if (n_src > 0) {
         if (flags & ASORA_PLAIN) {
             F.type = tmax;
@@ -415,12 +422,13 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
             }
         }
     }
-    if (prof) HIPCHK(c, hipEventRecord(c->ev[2], s));
+    if (prof) HIPCHK(c, hipEventRecord(ev[2], s));
     HIPCHK(c, launch_finalize(s, c->d_gacc, gamma, n3, (flags & ASORA_ACCUMULATE) ? 1 : 0,
                               c->n_cu));
     if (prof) {
-        HIPCHK(c, hipEventRecord(c->ev[3], s));
-        c->profiled = true;
+        HIPCHK(c, hipEventRecord(ev[3], s));
+        c->prof_count++;
+        if (c->prof_pending < kProfSlots) c->prof_pending++;
     }
     return ASORA_OK;
 }
@@ -454,14 +462,37 @@ extern "C" asora_status asora_get_tuning(const asora_ctx *c, float *R_whole, flo
 extern "C" asora_status asora_profile(asora_ctx *c, double *sweep_ms, double *total_ms)
 {
     if (!ctx_ok(c)) return ASORA_ESTATE;
-    if (!c->profiled) return fail(c, ASORA_ESTATE, "asora_profile: no profiled call yet");
+    if (c->prof_count == 0) return fail(c, ASORA_ESTATE, "asora_profile: no profiled call yet");
     HIPCHK(c, hipSetDevice(c->device));
-    HIPCHK(c, hipEventSynchronize(c->ev[3]));
+    hipEvent_t *ev = c->pev[(c->prof_count - 1) % kProfSlots];
+    HIPCHK(c, hipEventSynchronize(ev[3]));
     float a = 0.f, b = 0.f;
-    HIPCHK(c, hipEventElapsedTime(&a, c->ev[1], c->ev[2]));
-    HIPCHK(c, hipEventElapsedTime(&b, c->ev[0], c->ev[3]));
+    HIPCHK(c, hipEventElapsedTime(&a, ev[1], ev[2]));
+    HIPCHK(c, hipEventElapsedTime(&b, ev[0], ev[3]));
     if (sweep_ms) *sweep_ms = a;
     if (total_ms) *total_ms = b;
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_profile_read(asora_ctx *c, int32_t max_calls, int32_t *n_calls,
+                                           double *sweep_ms, double *total_ms)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    if (max_calls < 0 || (max_calls > 0 && (!sweep_ms || !total_ms)))
+        return fail(c, ASORA_EINVAL, "asora_profile_read: need max_calls >= 0 and both arrays");
+    HIPCHK(c, hipSetDevice(c->device));
+    const int n = c->prof_pending < max_calls ? c->prof_pending : max_calls;
+    for (int i = 0; i < n; ++i) {   // output i = the (n-1-i)-th most recent call
+        hipEvent_t *ev = c->pev[(c->prof_count - n + i) % kProfSlots];
+        HIPCHK(c, hipEventSynchronize(ev[3]));
+        float a = 0.f, b = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&a, ev[1], ev[2]));
+        HIPCHK(c, hipEventElapsedTime(&b, ev[0], ev[3]));
+        sweep_ms[i] = a;
+        total_ms[i] = b;
+    }
+    if (n_calls) *n_calls = n;
+    c->prof_pending = 0;
     return ASORA_OK;
 }
 
@@ -514,6 +545,7 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
     if (flags & ~(ASORA_ACCUMULATE | ASORA_PROFILE)) return fail(c, ASORA_EINVAL, "unknown flags");
     const bool prof = (flags & ASORA_PROFILE) != 0;
     const bool acc = (flags & ASORA_ACCUMULATE) != 0;
+    hipEvent_t *ev = c->pev[c->prof_count % kProfSlots];
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     const long n3 = (long)c->N * c->N * c->N;
@@ -535,14 +567,14 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
         HIPCHK(c, hipMalloc(&c->d_store, sizeof(double) * store_need));
         c->store_cap = store_need;
     }
-    if (prof) HIPCHK(c, hipEventRecord(c->ev[0], s));
+    if (prof) HIPCHK(c, hipEventRecord(ev[0], s));
     // dL/dQ accumulates over pieces: zero it unless the caller accumulates
     HIPCHK(c, launch_adj_prologue(s, n_H, x_HI, c->d_nhi, c->d_nbar, n3, dL_dQ, n_src, acc ? 0 : 1,
                                   c->d_ctl, kCtlSize, c->n_cu));
     if (n_src > 0)
         HIPCHK(c, launch_bucketing(s, src_R, src_ijk, n_src, c->N, R_max, c->R_whole, c->R_oct,
                                    c->d_keys, c->d_ctl, c->d_order, c->d_err));
-    if (prof) HIPCHK(c, hipEventRecord(c->ev[1], s));
+    if (prof) HIPCHK(c, hipEventRecord(ev[1], s));
     if (n_src > 0) {
         AdjLaunch L;
         L.N = c->N;
@@ -576,11 +608,12 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
             HIPCHK(c, launch_adj_wave(s, L));
         }
     }
-    if (prof) HIPCHK(c, hipEventRecord(c->ev[2], s));
+    if (prof) HIPCHK(c, hipEventRecord(ev[2], s));
     HIPCHK(c, launch_adj_finalize(s, c->d_nbar, n_H, x_HI, dL_dnH, dL_dxHI, n3, acc ? 1 : 0, c->n_cu));
     if (prof) {
-        HIPCHK(c, hipEventRecord(c->ev[3], s));
-        c->profiled = true;
+        HIPCHK(c, hipEventRecord(ev[3], s));
+        c->prof_count++;
+        if (c->prof_pending < kProfSlots) c->prof_pending++;
     }
     return ASORA_OK;
 }
