@@ -202,19 +202,23 @@ asora_status asora_check(asora_ctx *ctx, void *stream);
  * depend on them beyond the order of floating-point sums).  Sources with
  * R <= R_whole are swept whole by one wave; R_whole < R <= R_oct as eight
  * closed octants; larger R as 24 octant x dominant-axis pyramids (cells on
- * shared planes are computed by each piece and owned by one).  max_waves
- * (1..16) caps the waves per work-group that share one LDS copy of the table.
- * Values <= 0 keep the current setting.  asora_autotune measures and sets
- * them.  ASORA_EINVAL if R_oct < R_whole.
+ * shared planes are computed by each piece and owned by one).  Those
+ * pyramids are swept either shell by shell in L1 distance (pyramid_sweep 2)
+ * or layer by layer along their dominant axis with memory-contiguous tiles
+ * (pyramid_sweep 3, the default), in the forward and in the adjoint.
+ * max_waves (1..16) caps the waves per work-group that share one LDS copy of
+ * the table.  Values <= 0 keep the current setting.  ASORA_EINVAL if
+ * R_oct < R_whole, max_waves > 16 or pyramid_sweep is not 0, 2 or 3.
  */
-asora_status asora_set_tuning(asora_ctx *ctx, float R_whole, float R_oct, int32_t max_waves);
+asora_status asora_set_tuning(asora_ctx *ctx, float R_whole, float R_oct, int32_t max_waves,
+                              int32_t pyramid_sweep);
 
 /*
  * asora_get_tuning -- the current scheduling parameters (any pointer may be
  * NULL).
  */
 asora_status asora_get_tuning(const asora_ctx *ctx, float *R_whole, float *R_oct,
-                              int32_t *max_waves);
+                              int32_t *max_waves, int32_t *pyramid_sweep);
 
 /*
  * asora_profile -- durations (ms) of the most recent call made with

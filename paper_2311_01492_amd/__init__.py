@@ -57,9 +57,10 @@ _lib.asora_profile.argtypes = [_p, ctypes.POINTER(_c_d), ctypes.POINTER(_c_d)]
 _lib.asora_profile_read.restype = _c_int
 _lib.asora_profile_read.argtypes = [_p, _c_int, ctypes.POINTER(_c_int), _p, _p]
 _lib.asora_set_tuning.restype = _c_int
-_lib.asora_set_tuning.argtypes = [_p, _c_f, _c_f, _c_int]
+_lib.asora_set_tuning.argtypes = [_p, _c_f, _c_f, _c_int, _c_int]
 _lib.asora_get_tuning.restype = _c_int
-_lib.asora_get_tuning.argtypes = [_p, ctypes.POINTER(_c_f), ctypes.POINTER(_c_f), ctypes.POINTER(_c_int)]
+_lib.asora_get_tuning.argtypes = [_p, ctypes.POINTER(_c_f), ctypes.POINTER(_c_f), ctypes.POINTER(_c_int),
+                                  ctypes.POINTER(_c_int)]
 _lib.asora_last_error.restype = ctypes.c_char_p
 _lib.asora_last_error.argtypes = [_p]
 _lib.asora_free.restype = _c_int
@@ -219,13 +220,16 @@ class Asora:
                                        _np_ptr(b)), self._h)
         return list(zip(a[:n.value].tolist(), b[:n.value].tolist()))
 
-    def set_tuning(self, R_whole=0.0, R_oct=0.0, max_waves=0):
-        _raise(_lib.asora_set_tuning(self._h, float(R_whole), float(R_oct), int(max_waves)), self._h)
+    def set_tuning(self, R_whole=0.0, R_oct=0.0, max_waves=0, pyramid_sweep=0):
+        """Scheduling parameters; pyramid_sweep 2 = shells, 3 = layers (forward)."""
+        _raise(_lib.asora_set_tuning(self._h, float(R_whole), float(R_oct), int(max_waves),
+                                     int(pyramid_sweep)), self._h)
 
     def get_tuning(self):
-        a, b, w = _c_f(), _c_f(), _c_int()
-        _raise(_lib.asora_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(w)), self._h)
-        return a.value, b.value, w.value
+        a, b, w, k = _c_f(), _c_f(), _c_int(), _c_int()
+        _raise(_lib.asora_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(w),
+                                     ctypes.byref(k)), self._h)
+        return a.value, b.value, w.value, k.value
 
     def check(self, stream=None):
         """Wait for the stream; raise if a kernel flagged a source."""

@@ -4,7 +4,9 @@
 // the wave first recomputes the exit column of every cell, shell by shell
 // (the forward sweep without the rate), keeping the last four shells in an
 // LDS ring and storing every shell to the wave's own scratch in global
-// memory.  It then sweeps the shells from the outermost inward: the exit
+// memory together with its in-cell columns (so that the reverse pass reads
+// them back in order instead of gathering n_HI again).  It then sweeps the
+// shells from the outermost inward: the exit
 // columns of shells q-1..q-3 (the neighbours of shell q) come back from the
 // scratch into the LDS ring, and the adjoints of the exit columns of shells
 // q..q-3 live in a second LDS ring that the cells of shell q update with LDS
@@ -39,14 +41,20 @@ struct AdjArgs {
     int *err;
     int ring_cap, row_cap, shell_cap;
     int region_bytes;
-    double *store;           // per-wave stored exit columns
-    long store_stride;       // doubles per wave
+    double *store;           // per wave: stored exit columns, then in-cell columns
+    long store_stride;       // doubles per wave (twice the largest piece's cell count)
+    // layer pieces
+    const double *nHI_T;     // [k][i][j] copies for pyramids with dominant axis k
+    const double *gbar_T;
+    double *nbar_T;
+    int Mcap, lay_S;         // largest layer index, row stride of the layer buffers
 };
 
 template <int TYPE>
 __device__ void adjoint_piece_wave(const AdjArgs &A, const TabNode *T, char *region, double *store,
                                    int src, int p, int lane)
 {
+    double *store_dN = store + A.store_stride / 2;   // in-cell columns, same indexing as store
     const int N = A.N;
     const int si = A.ijk[3 * src], sj = A.ijk[3 * src + 1], sk = A.ijk[3 * src + 2];
     const float R = A.R ? A.R[src] : A.R_cap;
@@ -108,6 +116,7 @@ __device__ void adjoint_piece_wave(const AdjArgs &A, const TabNode *T, char *reg
             cell_update<false>(X, q, g, row, rb_q[row], co);
             ring_q[g] = co.Nout;
             store[off + g] = co.Nout;
+            store_dN[off + g] = co.dN;
         }
         if (lane == 0) shoff[q + 1] = off + total;
         wave_sync();
@@ -138,7 +147,8 @@ __device__ void adjoint_piece_wave(const AdjArgs &A, const TabNode *T, char *reg
         for (int g = lane; g < total; g += 64) {
             const int row = find_row(rs_q, nrows, g);
             CellAdj ca;
-            cell_adjoint(X, q, g, row, rb_q[row], abar[slot * (size_t)A.ring_cap + g], A.gbar, ca);
+            cell_adjoint(X, q, g, row, rb_q[row], abar[slot * (size_t)A.ring_cap + g],
+                         store_dN[shoff[q] + g], A.gbar, ca);
             if (ca.nbar != 0.0) unsafeAtomicAdd(&A.nbar[ca.cp], ca.nbar);
             nb_src += ca.nbar_src;
             qb += ca.qbar;
@@ -186,12 +196,240 @@ __global__ __launch_bounds__(512) void adj_wave(AdjArgs A)
     double *store = A.store + (size_t)(blockIdx.x * waves + wave) * A.store_stride;
     constexpr int npieces = TYPE == 0 ? 1 : (TYPE == 1 ? 8 : 24);
     const int base = A.seg[TYPE];
-    const long nitems = (long)(A.seg[TYPE + 1] - base) * npieces;
+    const int nitems = (A.seg[TYPE + 1] - base) * npieces;
+    const int home = (int)(blockIdx.x % kXcds);
+    int chunk = home;
     for (;;) {
-        const int item = next_item(A.counter, lane);
+        const int item = next_item(A.counter, nitems, home, chunk, lane);
         if (item >= nitems) break;
         const int src = A.order[base + item / npieces];
         adjoint_piece_wave<TYPE>(A, T, region, store, src, item % npieces, lane);
+    }
+}
+
+// ---- layer pieces --------------------------------------------------------
+// One wave per pyramid.  Forward pass: the columns layer by layer, in place in
+// the LDS buffer `cols` (as in the forward kernel), every layer's exit and
+// in-cell columns stored to the wave's scratch at [m][u][v].  Reverse pass,
+// from the outermost layer inward: layer m - 1's exit columns come back from
+// the scratch into `cols`; the cells of layer m, in increasing u band then
+// increasing v (so that every slot they push to belongs to an already
+// finished cell), take their exit-column adjoint from `abar`, clear it, and
+// add their entry-column adjoint to the slots of their layer m - 1 neighbours
+// with LDS atomics.
+template <int TV>
+__device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *cols, double *abar,
+                                    double *store, int src, int p, int lane)
+{
+    constexpr int TU = 64 / TV;
+    const int N = A.N;
+    const int si = A.ijk[3 * src], sj = A.ijk[3 * src + 1], sk = A.ijk[3 * src + 2];
+    const float R = A.R ? A.R[src] : A.R_cap;
+    if (!(R >= 0.f && R <= A.R_cap) || si < 0 || si >= N || sj < 0 || sj >= N || sk < 0 ||
+        sk >= N) {
+        if (lane == 0) atomicOr(A.err, 1);
+        return;
+    }
+    const double Q = A.Q[src];
+    const int Rsq = (int)floor((double)R * (double)R);
+    const LayerPiece L = make_layer_piece(p, si, sj, sk, N, A.ex);
+    const uint32_t cs = ((uint32_t)si * (uint32_t)N + (uint32_t)sj) * (uint32_t)N + (uint32_t)sk;
+    const double n_s = A.nHI[cs];
+    LayerX X;
+    X.N = N;
+    X.reading = A.reading;
+    X.tau_w = A.tau_w;
+    X.sigma0 = A.sigma0;
+    X.alpha = A.alpha;
+    X.half_col = n_s * A.alpha * 0.5;
+    X.nHI = L.transposed ? A.nHI_T : A.nHI;
+    const double *gbar = L.transposed ? A.gbar_T : A.gbar;
+    double *nbar = L.transposed ? A.nbar_T : A.nbar;
+    const double coef = Q * A.coef_unit;
+    const int S = A.lay_S;
+    const size_t SS = (size_t)(A.Mcap + 1) * S;       // doubles per stored layer
+    double *st_N = store, *st_dN = store + (size_t)(A.Mcap + 1) * SS;
+    const int Mx = min(isqrt_floor(Rsq), L.ext_d);
+
+    // ---- forward: columns of every layer, kept in place and stored
+    for (int k = lane; k < (Mx + 1) * S; k += 64) cols[k] = 0.0;
+    wave_sync();
+    for (int m = 1; m <= Mx; ++m) {
+        const int rem = Rsq - m * m;
+        const int umax = min(min(m, L.ext_u), isqrt_floor(rem));
+        const int vcap = min(m, L.ext_v);
+        for (int tu = umax / TU; tu >= 0; --tu) {
+            const int u0 = tu * TU;
+            const int vmax = min(vcap, isqrt_floor(rem - u0 * u0));
+            for (int tv = vmax / TV; tv >= 0; --tv) {
+                const int u = u0 + lane / TV, v = tv * TV + lane % TV;
+                const bool act = u <= umax && v <= vcap && u * u + v * v <= rem;
+                LayerCell lc;
+                if (act) layer_cell(L, X, m, u, v, cols, S, lc);
+                wave_sync();
+                if (act) {
+                    cols[u * S + v] = lc.Nout;
+                    st_N[m * SS + u * S + v] = lc.Nout;
+                    st_dN[m * SS + u * S + v] = lc.dN;
+                }
+                wave_sync();
+            }
+        }
+    }
+
+    // ---- reverse
+    for (int k = lane; k < (Mx + 1) * S; k += 64) abar[k] = 0.0;
+    double nb_src = 0.0, qb = 0.0;
+    for (int m = Mx; m >= 1; --m) {
+        if (m >= 2) {   // exit columns of layer m - 1 back into cols
+            const int mp = m - 1, remp = Rsq - mp * mp;
+            const int umaxp = min(min(mp, L.ext_u), isqrt_floor(remp));
+            const int vcapp = min(mp, L.ext_v);
+            for (int tu = 0; tu <= umaxp / TU; ++tu) {
+                const int u0 = tu * TU;
+                const int vmax = min(vcapp, isqrt_floor(remp - u0 * u0));
+                for (int tv = 0; tv <= vmax / TV; ++tv) {
+                    const int u = u0 + lane / TV, v = tv * TV + lane % TV;
+                    if (u <= umaxp && v <= vcapp && u * u + v * v <= remp)
+                        cols[u * S + v] = st_N[mp * SS + u * S + v];
+                }
+            }
+        }
+        wave_sync();
+        const int rem = Rsq - m * m;
+        const int umax = min(min(m, L.ext_u), isqrt_floor(rem));
+        const int vcap = min(m, L.ext_v);
+        for (int tu = 0; tu <= umax / TU; ++tu) {
+            const int u0 = tu * TU;
+            const int vmax = min(vcap, isqrt_floor(rem - u0 * u0));
+            for (int tv = 0; tv <= vmax / TV; ++tv) {
+                const int u = u0 + lane / TV, v = tv * TV + lane % TV;
+                const bool act = u <= umax && v <= vcap && u * u + v * v <= rem;
+                LayerAdj la;
+                if (act)
+                    layer_cell_adjoint(L, X, T, A.m64, A.tp, coef, m, u, v, cols, S, abar[u * S + v],
+                                       st_dN[m * SS + u * S + v], gbar, la);
+                wave_sync();
+                if (act) abar[u * S + v] = 0.0;
+                wave_sync();
+                if (act) {
+                    if (m >= 2) {
+#pragma unroll
+                        for (int n = 0; n < 4; ++n)
+                            if (la.Mbar[n] != 0.0)
+                                atomicAdd(&abar[(u - (n & 1)) * S + (v - (n >> 1))], la.Mbar[n]);
+                    }
+                    if (la.nbar != 0.0) unsafeAtomicAdd(&nbar[la.cp], la.nbar);
+                    nb_src += la.nbar_src;
+                    qb += la.qbar;
+                }
+                wave_sync();
+            }
+        }
+    }
+    if (p == 3 * 0 + 2 && lane == 0) {   // the source cell, once per source
+        double nb, q1;
+        source_cell_adjoint(T, A.m64, A.tp, A.sigma0, A.alpha, Q, n_s, A.gbar[cs], &nb, &q1);
+        nb_src += nb;
+        qb += q1;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        nb_src += __shfl_xor(nb_src, off, 64);
+        qb += __shfl_xor(qb, off, 64);
+    }
+    if (lane == 0) {
+        if (nb_src != 0.0) unsafeAtomicAdd(&A.nbar[cs], nb_src);
+        if (qb != 0.0) unsafeAtomicAdd(&A.qbar[src], qb / Q);
+    }
+}
+
+template <int TV>
+__global__ __launch_bounds__(512) void adj_layer(AdjArgs A)
+{
+    extern __shared__ __align__(16) char smem[];
+    constexpr int TYPE = 3, npieces = 24;
+    if (A.seg[TYPE + 1] == A.seg[TYPE]) return;   // no sources of this kind
+    TabNode *T = (TabNode *)smem;
+    {
+        const int4 *s = (const int4 *)A.tab;
+        int4 *d = (int4 *)smem;
+        for (int k = threadIdx.x; k < A.tp.n; k += blockDim.x) d[k] = s[k];
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int waves = blockDim.x >> 6;
+    double *cols = (double *)(smem + (size_t)A.tp.n * sizeof(TabNode) + (size_t)wave * A.region_bytes);
+    double *abar = cols + (size_t)(A.Mcap + 1) * A.lay_S;
+    double *store = A.store + (size_t)(blockIdx.x * waves + wave) * A.store_stride;
+    const int base = A.seg[TYPE];
+    const int nitems = (A.seg[TYPE + 1] - base) * npieces;
+    const int home = (int)(blockIdx.x % kXcds);
+    int chunk = home;
+    for (;;) {
+        const int item = next_item(A.counter, nitems, home, chunk, lane);
+        if (item >= nitems) break;
+        const int src = A.order[base + item / npieces];
+        adjoint_layer_piece<TV>(A, T, cols, abar, store, src, item % npieces, lane);
+    }
+}
+
+// dL/dn_HI of the layer pieces with dominant axis k is accumulated in the
+// [k][i][j] layout; this kernel builds that layout's n_HI and dL/dGamma and
+// zeroes its accumulator (one 32 x 32 (j, k) tile of one i plane per
+// work-group).
+constexpr int kTile = 32;
+__global__ __launch_bounds__(256) void adj_transpose_prologue_kernel(
+    const float *__restrict__ nH, const float *__restrict__ xHI, const double *__restrict__ gbar,
+    double *__restrict__ nHI_T, double *__restrict__ gbar_T, double *__restrict__ nbar_T, int N)
+{
+    __shared__ double tn[kTile][kTile + 1], tg[kTile][kTile + 1];
+    const int k0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile, i = blockIdx.z;
+    const int tx = threadIdx.x & (kTile - 1), ty = threadIdx.x / kTile;
+    for (int jj = ty; jj < kTile; jj += 8) {
+        const int j = j0 + jj, k = k0 + tx;
+        if (j < N && k < N) {
+            const size_t c = ((size_t)i * N + j) * N + k;
+            tn[jj][tx] = (double)nH[c] * (double)xHI[c];
+            tg[jj][tx] = gbar[c];
+        }
+    }
+    __syncthreads();
+    for (int kk = ty; kk < kTile; kk += 8) {
+        const int k = k0 + kk, j = j0 + tx;
+        if (j < N && k < N) {
+            const size_t t = ((size_t)k * N + i) * N + j;
+            nHI_T[t] = tn[tx][kk];
+            gbar_T[t] = tg[tx][kk];
+            nbar_T[t] = 0.0;
+        }
+    }
+}
+
+// dL/dn_H = x_HI g, dL/dx_HI = n_H g with g = dL/dn_HI from both layouts.
+__global__ __launch_bounds__(256) void adj_transpose_finalize_kernel(
+    const double *__restrict__ nbar, const double *__restrict__ nbar_T, const float *__restrict__ nH,
+    const float *__restrict__ xHI, float *__restrict__ dnH, float *__restrict__ dxHI, int N,
+    int accumulate)
+{
+    __shared__ double tile[kTile][kTile + 1];
+    const int k0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile, i = blockIdx.z;
+    const int tx = threadIdx.x & (kTile - 1), ty = threadIdx.x / kTile;
+    for (int kk = ty; kk < kTile; kk += 8) {
+        const int k = k0 + kk, j = j0 + tx;
+        if (j < N && k < N) tile[kk][tx] = nbar_T[((size_t)k * N + i) * N + j];
+    }
+    __syncthreads();
+    for (int jj = ty; jj < kTile; jj += 8) {
+        const int j = j0 + jj, k = k0 + tx;
+        if (j < N && k < N) {
+            const size_t c = ((size_t)i * N + j) * N + k;
+            const double g = nbar[c] + tile[tx][jj];
+            const float a = (float)(g * (double)xHI[c]);
+            const float b = (float)(g * (double)nH[c]);
+            dnH[c] = accumulate ? dnH[c] + a : a;
+            dxHI[c] = accumulate ? dxHI[c] + b : b;
+        }
     }
 }
 
@@ -246,6 +484,8 @@ hipError_t adj_configure(size_t max_lds)
     const int dyn = (int)max_lds - 64;
     for (int t = 0; t < 3; ++t)
         (void)hipFuncSetAttribute(adj_fn(t), hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)adj_layer<8>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)adj_layer<16>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipGetLastError();
     return hipSuccess;
 }
@@ -264,7 +504,7 @@ hipError_t launch_adj_prologue(hipStream_t st, const float *nH, const float *xHI
     return hipGetLastError();
 }
 
-hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L)
+static AdjArgs make_adj_args(const AdjLaunch &L)
 {
     AdjArgs A;
     A.N = L.N;
@@ -287,20 +527,75 @@ hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L)
     A.R_cap = L.R_cap;
     A.order = L.order;
     A.seg = L.ctl + kCtlSeg;
-    A.counter = L.ctl + kCtlCounter + L.type;
+    A.counter = L.ctl + kCtlCounter + kXcds * L.type;
     A.err = L.err;
     A.ring_cap = L.ring_cap;
     A.row_cap = L.row_cap;
     A.shell_cap = L.shell_cap;
-    A.region_bytes = (int)adj_region_bytes(L.ring_cap, L.row_cap, L.shell_cap);
+    A.region_bytes = 0;
     A.store = L.store;
     A.store_stride = L.store_stride;
+    A.nHI_T = L.nHI_T;
+    A.gbar_T = L.gbar_T;
+    A.nbar_T = L.nbar_T;
+    A.Mcap = 0;
+    A.lay_S = 0;
+    return A;
+}
+
+hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L)
+{
+    AdjArgs A = make_adj_args(L);
+    A.region_bytes = (int)adj_region_bytes(L.ring_cap, L.row_cap, L.shell_cap);
     const size_t lds = (size_t)L.tp.n * sizeof(TabNode) + (size_t)L.waves * A.region_bytes;
     switch (L.type) {
     case 0: hipLaunchKernelGGL(adj_wave<0>, dim3(L.grid), dim3(64 * L.waves), lds, st, A); break;
     case 1: hipLaunchKernelGGL(adj_wave<1>, dim3(L.grid), dim3(64 * L.waves), lds, st, A); break;
     default: hipLaunchKernelGGL(adj_wave<2>, dim3(L.grid), dim3(64 * L.waves), lds, st, A); break;
     }
+    return hipGetLastError();
+}
+
+size_t adj_layer_region_bytes(int Mcap, int S)
+{
+    return ((size_t)2 * (Mcap + 1) * S * sizeof(double) + 15) & ~(size_t)15;
+}
+
+hipError_t adj_layer_occupancy(int tv, int waves, size_t lds, int *blocks_per_cu)
+{
+    const void *f = tv == 8 ? (const void *)adj_layer<8> : (const void *)adj_layer<16>;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, waves * 64, lds);
+}
+
+hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int tv, int Mcap)
+{
+    AdjArgs A = make_adj_args(L);
+    A.Mcap = Mcap;
+    A.lay_S = Mcap + 1;
+    A.region_bytes = (int)adj_layer_region_bytes(Mcap, A.lay_S);
+    const size_t lds = (size_t)L.tp.n * sizeof(TabNode) + (size_t)L.waves * A.region_bytes;
+    if (tv == 8) hipLaunchKernelGGL(adj_layer<8>, dim3(L.grid), dim3(64 * L.waves), lds, st, A);
+    else hipLaunchKernelGGL(adj_layer<16>, dim3(L.grid), dim3(64 * L.waves), lds, st, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_transpose_prologue(hipStream_t st, const float *nH, const float *xHI,
+                                         const double *gbar, double *nHI_T, double *gbar_T,
+                                         double *nbar_T, int N)
+{
+    const dim3 grid((N + kTile - 1) / kTile, (N + kTile - 1) / kTile, N);
+    hipLaunchKernelGGL(adj_transpose_prologue_kernel, grid, dim3(256), 0, st, nH, xHI, gbar, nHI_T,
+                       gbar_T, nbar_T, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_transpose_finalize(hipStream_t st, const double *nbar, const double *nbar_T,
+                                         const float *nH, const float *xHI, float *dnH, float *dxHI,
+                                         int N, int accumulate)
+{
+    const dim3 grid((N + kTile - 1) / kTile, (N + kTile - 1) / kTile, N);
+    hipLaunchKernelGGL(adj_transpose_finalize_kernel, grid, dim3(256), 0, st, nbar, nbar_T, nH, xHI,
+                       dnH, dxHI, N, accumulate);
     return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@ struct PlanKey {
 struct Plan {
     int ring_cap, row_cap, Qmax;
     long piece_cells;   // largest number of cells of one piece (adjoint scratch)
+    int Mcap, tv;       // layer pieces: largest layer index, tile width along v
     int wave_mode;   // 1: one wave per piece (waves per work-group below); 0: one work-group per piece
     int waves;
     size_t lds;
@@ -54,6 +55,11 @@ struct asora_ctx {
     float R_whole, R_oct;   // radius thresholds of the piece types
     int min_waves, max_waves;   // wave-per-piece mode bounds
     std::map<PlanKey, Plan> plans;
+    int big_kind;           // piece kind of the forward above R_oct: 2 shell pyramids, 3 layer pyramids
+    double *d_nhi_T;        // [k][i][j] copies for the layer pieces (allocated on first use)
+    double *d_gacc_T;
+    double *d_gbar_T;       // adjoint: dL/dGamma and dL/dn_HI in the [k][i][j] layout
+    double *d_nbar_T;
     double *d_nbar;         // dL/dn_HI accumulator (allocated by the first backward call)
     double *d_store;        // stored exit columns of the adjoint pieces in flight
     size_t store_cap;       // doubles
@@ -163,6 +169,7 @@ extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, d
     c->R_oct = 15.f;
     c->min_waves = 4;
     c->max_waves = 16;
+    c->big_kind = 3;
 
     // table in the kernels' form
     std::vector<TabNode> nodes(n_tab);
@@ -219,6 +226,10 @@ extern "C" asora_status asora_free(asora_ctx *c)
     (void)hipFree(c->d_err);
     (void)hipFree(c->d_keys);
     (void)hipFree(c->d_order);
+    (void)hipFree(c->d_nhi_T);
+    (void)hipFree(c->d_gacc_T);
+    (void)hipFree(c->d_gbar_T);
+    (void)hipFree(c->d_nbar_T);
     (void)hipFree(c->d_nbar);
     (void)hipFree(c->d_store);
     for (int sl = 0; sl < kProfSlots; ++sl)
@@ -261,8 +272,11 @@ static int type_of(const asora_ctx *c, float R)
     return R <= c->R_whole ? 0 : (R <= c->R_oct ? 1 : 2);
 }
 
+static asora_status get_layer_plan(asora_ctx *c, float R_cap, Plan *out);
+
 static asora_status get_plan(asora_ctx *c, int type, float R_cap, Plan *out)
 {
+    if (type == 3) return get_layer_plan(c, R_cap, out);
     const int Rsq = (int)std::floor((double)R_cap * (double)R_cap);
     const PlanKey key{type, Rsq};
     auto it = c->plans.find(key);
@@ -321,6 +335,55 @@ static asora_status get_plan(asora_ctx *c, int type, float R_cap, Plan *out)
     return ASORA_OK;
 }
 
+// Layer pieces: one wave per pyramid, the wave's LDS holds one layer.
+static asora_status get_layer_plan(asora_ctx *c, float R_cap, Plan *out)
+{
+    const int Rsq = (int)std::floor((double)R_cap * (double)R_cap);
+    const PlanKey key{3, Rsq};
+    auto it = c->plans.find(key);
+    if (it != c->plans.end()) {
+        *out = it->second;
+        return ASORA_OK;
+    }
+    const Extent ex = make_extent(c->N);
+    Plan P = Plan();
+    int r = (int)std::floor(std::sqrt((double)Rsq));
+    while ((long)r * r > Rsq) --r;
+    while ((long)(r + 1) * (r + 1) <= Rsq) ++r;
+    P.Mcap = r < ex.neg ? r : ex.neg;
+    if (P.Mcap < 1) P.Mcap = 1;
+    P.tv = P.Mcap + 1 > 8 ? 16 : 8;
+    P.wave_mode = 1;
+    const size_t tab = (size_t)c->tp.n * sizeof(TabNode);
+    const size_t region = layer_region_bytes(P.Mcap, P.Mcap + 1);
+    const long fit = c->max_lds > tab + 64 ? (long)((c->max_lds - tab - 64) / region) : 0;
+    if (fit < 1)
+        return fail(c, ASORA_ENOSYS,
+                    "R_max=%.1f needs %zu bytes of LDS per wave (limit %zu) for this table and grid",
+                    R_cap, region + tab, c->max_lds);
+    P.waves = (int)(fit < c->max_waves ? fit : c->max_waves);
+    P.lds = tab + (size_t)P.waves * region;
+    int bpc = 0;
+    HIPCHK(c, layer_occupancy(P.tv, P.waves, P.lds, &bpc));
+    P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
+    c->plans[key] = P;
+    *out = P;
+    return ASORA_OK;
+}
+
+static asora_status ensure_layer_buffers(asora_ctx *c)
+{
+    if (c->d_nhi_T) return ASORA_OK;
+    const size_t n3 = (size_t)c->N * c->N * c->N;
+    HIPCHK(c, hipMalloc(&c->d_nhi_T, sizeof(double) * n3));
+    if (hipMalloc(&c->d_gacc_T, sizeof(double) * n3) != hipSuccess) {
+        (void)hipFree(c->d_nhi_T);
+        c->d_nhi_T = nullptr;
+        return fail(c, ASORA_ENOMEM, "allocation of the transposed field copies failed");
+    }
+    return ASORA_OK;
+}
+
 static asora_status ensure_src_cap(asora_ctx *c, long n)
 {
     if (n <= c->src_cap) return ASORA_OK;
@@ -364,13 +427,18 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     const long n3 = (long)c->N * c->N * c->N;
-    const int tmax = type_of(c, R_max);
-    Plan plans[3];
+    // piece kinds in use: 0 and 1 up to R_oct, then the large kind (2 or 3)
+    const int tbig = type_of(c, R_max);
+    const int tmax = tbig == 2 ? c->big_kind : tbig;
+    const bool layers = tmax == 3;
+    Plan plans[4];
     for (int t = 0; t <= tmax; ++t) {
+        if (t == 2 && tmax == 3) continue;
         const float cap = t == tmax ? R_max : (t == 0 ? c->R_whole : c->R_oct);
         if ((st = get_plan(c, t, cap, &plans[t]))) return st;
     }
     if ((st = ensure_src_cap(c, n_src))) return st;
+    if (layers && (st = ensure_layer_buffers(c))) return st;
 
     FwdLaunch F;
     F.N = c->N;
@@ -389,13 +457,16 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     F.order = c->d_order;
     F.ctl = c->d_ctl;
     F.err = c->d_err;
+    F.nHI_T = c->d_nhi_T;
+    F.gacc_T = c->d_gacc_T;
 
     if (prof) HIPCHK(c, hipEventRecord(ev[0], s));
     HIPCHK(c, launch_prologue(s, n_H, x_HI, c->d_nhi, c->d_gacc, coldens_in, n3, c->d_ctl,
                               kCtlSize, c->n_cu));
+    if (layers) HIPCHK(c, launch_transpose_prologue(s, n_H, x_HI, c->d_nhi_T, c->d_gacc_T, c->N));
     if (n_src > 0 && !(flags & ASORA_PLAIN))
         HIPCHK(c, launch_bucketing(s, src_R, src_ijk, n_src, c->N, R_max, c->R_whole, c->R_oct,
-                                   c->d_keys, c->d_ctl, c->d_order, c->d_err));
+                                   tmax == 3 ? 3 : 2, c->d_keys, c->d_ctl, c->d_order, c->d_err));
     if (prof) HIPCHK(c, hipEventRecord(ev[1], s));
     if (n_src > 0) {
         if (flags & ASORA_PLAIN) {
@@ -404,18 +475,25 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
             F.ring_cap = plans[tmax].ring_cap;
             F.row_cap = plans[tmax].row_cap;
             for (long k = 0; k < n_src; ++k) {
-                if (plans[tmax].wave_mode)
+                if (tmax == 3)
+                    HIPCHK(c, launch_fwd_layer(s, F, plans[3].tv, plans[3].Mcap, plans[3].waves, 0,
+                                               (int)k));
+                else if (plans[tmax].wave_mode)
                     HIPCHK(c, launch_fwd_wave(s, F, plans[tmax].waves, 0, (int)k));
                 else
                     HIPCHK(c, launch_fwd_plain(s, F, (int)k));
             }
         } else {
             for (int t = tmax; t >= 0; --t) {
+                if (t == 2 && tmax == 3) continue;
                 F.type = t;
                 F.R_cap = t == tmax ? R_max : (t == 0 ? c->R_whole : c->R_oct);
                 F.ring_cap = plans[t].ring_cap;
                 F.row_cap = plans[t].row_cap;
-                if (plans[t].wave_mode)
+                if (t == 3)
+                    HIPCHK(c, launch_fwd_layer(s, F, plans[3].tv, plans[3].Mcap, plans[3].waves,
+                                               plans[3].grid, -1));
+                else if (plans[t].wave_mode)
                     HIPCHK(c, launch_fwd_wave(s, F, plans[t].waves, plans[t].grid, -1));
                 else
                     HIPCHK(c, launch_fwd_persistent(s, F, plans[t].grid));
@@ -423,8 +501,12 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
         }
     }
     if (prof) HIPCHK(c, hipEventRecord(ev[2], s));
-    HIPCHK(c, launch_finalize(s, c->d_gacc, gamma, n3, (flags & ASORA_ACCUMULATE) ? 1 : 0,
-                              c->n_cu));
+    if (layers)
+        HIPCHK(c, launch_transpose_finalize(s, c->d_gacc, c->d_gacc_T, gamma, c->N,
+                                            (flags & ASORA_ACCUMULATE) ? 1 : 0));
+    else
+        HIPCHK(c, launch_finalize(s, c->d_gacc, gamma, n3, (flags & ASORA_ACCUMULATE) ? 1 : 0,
+                                  c->n_cu));
     if (prof) {
         HIPCHK(c, hipEventRecord(ev[3], s));
         c->prof_count++;
@@ -433,29 +515,34 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     return ASORA_OK;
 }
 
-extern "C" asora_status asora_set_tuning(asora_ctx *c, float R_whole, float R_oct, int32_t max_waves)
+extern "C" asora_status asora_set_tuning(asora_ctx *c, float R_whole, float R_oct, int32_t max_waves,
+                                         int32_t pyramid_sweep)
 {
     if (!ctx_ok(c)) return ASORA_ESTATE;
     const float w = R_whole > 0 ? R_whole : c->R_whole;
     const float o = R_oct > 0 ? R_oct : c->R_oct;
-    if (!(o >= w) || !std::isfinite(w) || !std::isfinite(o) || max_waves > 16)
-        return fail(c, ASORA_EINVAL, "asora_set_tuning: need 0 < R_whole <= R_oct, max_waves <= 16");
+    if (!(o >= w) || !std::isfinite(w) || !std::isfinite(o) || max_waves > 16 ||
+        !(pyramid_sweep == 0 || pyramid_sweep == 2 || pyramid_sweep == 3))
+        return fail(c, ASORA_EINVAL,
+                    "asora_set_tuning: need 0 < R_whole <= R_oct, max_waves <= 16, pyramid_sweep 0/2/3");
     c->R_whole = w;
     c->R_oct = o;
     if (max_waves > 0) c->max_waves = max_waves;
     if (c->min_waves > c->max_waves) c->min_waves = c->max_waves;
+    if (pyramid_sweep) c->big_kind = pyramid_sweep;
     c->plans.clear();
     c->adj_plans.clear();
     return ASORA_OK;
 }
 
 extern "C" asora_status asora_get_tuning(const asora_ctx *c, float *R_whole, float *R_oct,
-                                         int32_t *max_waves)
+                                         int32_t *max_waves, int32_t *pyramid_sweep)
 {
     if (!ctx_ok(c)) return ASORA_ESTATE;
     if (R_whole) *R_whole = c->R_whole;
     if (R_oct) *R_oct = c->R_oct;
     if (max_waves) *max_waves = c->max_waves;
+    if (pyramid_sweep) *pyramid_sweep = c->big_kind;
     return ASORA_OK;
 }
 
@@ -510,7 +597,8 @@ static asora_status get_adj_plan(asora_ctx *c, int type, float R_cap, Plan *out)
     asora_status st = get_plan(c, type, R_cap, &P);   // ring/row/cell sizes
     if (st) return st;
     if (P.row_cap > 256)
-        return fail(c, ASORA_ENOSYS, "asora_raytrace_backward: R_max=%.1f too large for the wave adjoint", R_cap);
+        return fail(c, ASORA_ENOSYS,
+                    "asora_raytrace_backward: R_max=%.1f too large for the shell adjoint", R_cap);
     const size_t tab = (size_t)c->tp.n * sizeof(TabNode);
     const size_t region = adj_region_bytes(P.ring_cap, P.row_cap, P.Qmax);
     const long fit = c->max_lds > tab + 64 ? (long)((c->max_lds - tab - 64) / region) : 0;
@@ -527,6 +615,55 @@ static asora_status get_adj_plan(asora_ctx *c, int type, float R_cap, Plan *out)
     P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
     c->adj_plans[key] = P;
     *out = P;
+    return ASORA_OK;
+}
+
+// Adjoint layer pieces: two layer buffers per wave in LDS, every layer's
+// columns in the wave's scratch.
+static asora_status get_adj_layer_plan(asora_ctx *c, float R_cap, Plan *out)
+{
+    const int Rsq = (int)std::floor((double)R_cap * (double)R_cap);
+    const PlanKey key{3, Rsq};
+    auto it = c->adj_plans.find(key);
+    if (it != c->adj_plans.end()) {
+        *out = it->second;
+        return ASORA_OK;
+    }
+    Plan P;
+    asora_status st = get_layer_plan(c, R_cap, &P);   // Mcap, tile width
+    if (st) return st;
+    const size_t tab = (size_t)c->tp.n * sizeof(TabNode);
+    const size_t region = adj_layer_region_bytes(P.Mcap, P.Mcap + 1);
+    const long fit = c->max_lds > tab + 64 ? (long)((c->max_lds - tab - 64) / region) : 0;
+    if (fit < 1)
+        return fail(c, ASORA_ENOSYS,
+                    "asora_raytrace_backward: R_max=%.1f needs %zu bytes of LDS per wave (limit %zu)",
+                    R_cap, region + tab, c->max_lds);
+    const int cap = c->max_waves < 8 ? c->max_waves : 8;   // adjoint work-groups: <= 512 threads
+    P.waves = (int)(fit < cap ? fit : cap);
+    P.lds = tab + (size_t)P.waves * region;
+    int bpc = 0;
+    HIPCHK(c, adj_layer_occupancy(P.tv, P.waves, P.lds, &bpc));
+    P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
+    const long S = P.Mcap + 1;
+    P.piece_cells = (long)(P.Mcap + 1) * (P.Mcap + 1) * S;   // dense [m][u][v] per stored array
+    c->adj_plans[key] = P;
+    *out = P;
+    return ASORA_OK;
+}
+
+static asora_status ensure_adj_layer_buffers(asora_ctx *c)
+{
+    asora_status st = ensure_layer_buffers(c);
+    if (st) return st;
+    if (c->d_gbar_T) return ASORA_OK;
+    const size_t n3 = (size_t)c->N * c->N * c->N;
+    HIPCHK(c, hipMalloc(&c->d_gbar_T, sizeof(double) * n3));
+    if (hipMalloc(&c->d_nbar_T, sizeof(double) * n3) != hipSuccess) {
+        (void)hipFree(c->d_gbar_T);
+        c->d_gbar_T = nullptr;
+        return fail(c, ASORA_ENOMEM, "allocation of the transposed adjoint buffers failed");
+    }
     return ASORA_OK;
 }
 
@@ -549,16 +686,21 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     const long n3 = (long)c->N * c->N * c->N;
-    const int tmax = type_of(c, R_max);
-    Plan plans[3];
+    const int tbig = type_of(c, R_max);
+    const int tmax = tbig == 2 ? c->big_kind : tbig;
+    const bool layers = tmax == 3;
+    Plan plans[4];
     size_t store_need = 0;
     for (int t = 0; t <= tmax; ++t) {
+        if (t == 2 && layers) continue;
         const float cap = t == tmax ? R_max : (t == 0 ? c->R_whole : c->R_oct);
-        if ((st = get_adj_plan(c, t, cap, &plans[t]))) return st;
-        const size_t need = (size_t)plans[t].grid * plans[t].waves * (size_t)plans[t].piece_cells;
+        if ((st = t == 3 ? get_adj_layer_plan(c, cap, &plans[t]) : get_adj_plan(c, t, cap, &plans[t])))
+            return st;
+        const size_t need = (size_t)plans[t].grid * plans[t].waves * 2 * (size_t)plans[t].piece_cells;
         store_need = need > store_need ? need : store_need;
     }
     if ((st = ensure_src_cap(c, n_src))) return st;
+    if (layers && (st = ensure_adj_layer_buffers(c))) return st;
     if (!c->d_nbar) HIPCHK(c, hipMalloc(&c->d_nbar, sizeof(double) * n3));
     if (store_need > c->store_cap) {
         (void)hipFree(c->d_store);
@@ -571,9 +713,12 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
     // dL/dQ accumulates over pieces: zero it unless the caller accumulates
     HIPCHK(c, launch_adj_prologue(s, n_H, x_HI, c->d_nhi, c->d_nbar, n3, dL_dQ, n_src, acc ? 0 : 1,
                                   c->d_ctl, kCtlSize, c->n_cu));
+    if (layers)
+        HIPCHK(c, launch_adj_transpose_prologue(s, n_H, x_HI, dL_dgamma, c->d_nhi_T, c->d_gbar_T,
+                                                c->d_nbar_T, c->N));
     if (n_src > 0)
         HIPCHK(c, launch_bucketing(s, src_R, src_ijk, n_src, c->N, R_max, c->R_whole, c->R_oct,
-                                   c->d_keys, c->d_ctl, c->d_order, c->d_err));
+                                   layers ? 3 : 2, c->d_keys, c->d_ctl, c->d_order, c->d_err));
     if (prof) HIPCHK(c, hipEventRecord(ev[1], s));
     if (n_src > 0) {
         AdjLaunch L;
@@ -596,7 +741,11 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
         L.ctl = c->d_ctl;
         L.err = c->d_err;
         L.store = c->d_store;
+        L.nHI_T = c->d_nhi_T;
+        L.gbar_T = c->d_gbar_T;
+        L.nbar_T = c->d_nbar_T;
         for (int t = tmax; t >= 0; --t) {
+            if (t == 2 && layers) continue;
             L.type = t;
             L.R_cap = t == tmax ? R_max : (t == 0 ? c->R_whole : c->R_oct);
             L.ring_cap = plans[t].ring_cap;
@@ -604,12 +753,18 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
             L.shell_cap = plans[t].Qmax;
             L.waves = plans[t].waves;
             L.grid = plans[t].grid;
-            L.store_stride = plans[t].piece_cells;
-            HIPCHK(c, launch_adj_wave(s, L));
+            L.store_stride = 2 * plans[t].piece_cells;
+            if (t == 3) HIPCHK(c, launch_adj_layer(s, L, plans[3].tv, plans[3].Mcap));
+            else HIPCHK(c, launch_adj_wave(s, L));
         }
     }
     if (prof) HIPCHK(c, hipEventRecord(ev[2], s));
-    HIPCHK(c, launch_adj_finalize(s, c->d_nbar, n_H, x_HI, dL_dnH, dL_dxHI, n3, acc ? 1 : 0, c->n_cu));
+    if (layers)
+        HIPCHK(c, launch_adj_transpose_finalize(s, c->d_nbar, c->d_nbar_T, n_H, x_HI, dL_dnH, dL_dxHI,
+                                                c->N, acc ? 1 : 0));
+    else
+        HIPCHK(c, launch_adj_finalize(s, c->d_nbar, n_H, x_HI, dL_dnH, dL_dxHI, n3, acc ? 1 : 0,
+                                      c->n_cu));
     if (prof) {
         HIPCHK(c, hipEventRecord(ev[3], s));
         c->prof_count++;

@@ -7,6 +7,8 @@
 
 namespace asora {
 
+constexpr int kXcds = 8;   // accelerator dies (XCDs) of the MI355X, each with its own L2
+
 // Approximate reciprocal (about 1 ulp): the hardware instruction on the GPU.
 __host__ __device__ __forceinline__ float rcp_approx(float x)
 {
@@ -589,8 +591,9 @@ __host__ __device__ __forceinline__ void rate_derivs64(const TabNode *T, const d
 }
 
 // Reverse-mode update of one cell (not the source).  Given the total adjoint
-// of its exit column from its consumers (Nbar_out) and dL/dGamma of the cell
-// (gbar, owned cells only), it recomputes the forward quantities from the
+// of its exit column from its consumers (Nbar_out), its in-cell column dN as
+// the forward computed it, and dL/dGamma of the cell (gbar, owned cells
+// only), it recomputes the forward quantities from the
 // neighbour columns in the ring and returns the adjoints to push to the
 // neighbours (their exit columns; a neighbour that is the source pushes to
 // n_HI of the source), the adjoint of the cell's n_HI and of the source rate.
@@ -605,8 +608,8 @@ struct CellAdj {
 };
 
 __host__ __device__ __forceinline__ void cell_adjoint(const CellCtx &X, int q, int g, int row, int rb,
-                                                      double Nbar_out, const double *gbar_grid,
-                                                      CellAdj &out)
+                                                      double Nbar_out, double dN,
+                                                      const double *gbar_grid, CellAdj &out)
 {
     const int os = X.pc.n_oct == 1 ? 0 : (int)(((float)row + 0.5f) * rcp_approx((float)(q + 1)));
     const int cA = row - os * (q + 1);
@@ -619,7 +622,6 @@ __host__ __device__ __forceinline__ void cell_adjoint(const CellCtx &X, int q, i
     const int N = X.N;
     const uint32_t cp = ((uint32_t)wrap(X.si + di, N) * (uint32_t)N + (uint32_t)wrap(X.sj + dj, N)) *
                             (uint32_t)N + (uint32_t)wrap(X.sk + dk, N);
-    const double nhi = X.nHI[cp];
     const int m = cA > cB ? (cA > cC ? cA : cC) : (cB > cC ? cB : cC);
     const int canon = cC == m ? 2 : (cB == m ? 1 : 0);
     const int dd = X.pc.dom >= 0 ? X.pc.dom : canon;
@@ -684,7 +686,6 @@ __host__ __device__ __forceinline__ void cell_adjoint(const CellCtx &X, int q, i
     }
     const double iW = 1.0 / W;
     const double Nin = num * iW;
-    const double dN = nhi * X.alpha * ds;
 
     // ownership as in the forward
     bool owned = true;
@@ -695,8 +696,9 @@ __host__ __device__ __forceinline__ void cell_adjoint(const CellCtx &X, int q, i
     // N_out = N_in + dN: both receive Nbar_out; the rate adds its own parts
     double Nin_bar = Nbar_out, dN_bar = Nbar_out, qb = 0.0;
     const double ta = X.sigma0 * Nin;
-    const double gbar = owned ? gbar_grid[cp] : 0.0;
-    if (gbar != 0.0 && ta < X.tp.tau_hi) {
+    // dL/dGamma is read only where the rate can be non-zero
+    const double gbar = (owned && ta < X.tp.tau_hi) ? gbar_grid[cp] : 0.0;
+    if (gbar != 0.0) {
         double D, Da, Ddt;
         rate_derivs64(X.tab, X.m64, X.tp, ta, X.sigma0 * dN, &D, &Da, &Ddt);
         const double k = -X.coef / (double)r2;          // Gamma = k D
@@ -744,6 +746,253 @@ __host__ __device__ __forceinline__ double source_cell_rate(const TabNode *T, co
     return Q * sigma0 / (2.0 * alpha * alpha) * (double)nd;   // once per source
 }
 
+// --------------------------------------------------------------------------
+// Layer pieces.  Within one octant, the cells of a source whose dominant axis
+// (largest |d|, ties included) is d form a pyramid; every non-zero-weight
+// neighbour of such a cell lies in the same pyramid, one step closer along d
+// (the neighbour set of Section 3.1, eq. 11).  The pyramid can therefore be
+// swept layer by layer, m = |d_d| = 1, 2, ...: a cell of layer m reads only
+// layer m - 1.  In layer m a cell is (u, v) = (|d_u|, |d_v|) in [0, m]^2, for
+// the two other axes u, v.  v is the axis that is contiguous in memory: k
+// for d = i or j in the field layout [i][j][k]; j for d = k, which reads and
+// accumulates in a transposed copy laid out [k][i][j].  A wave's cells are
+// then runs of neighbouring addresses, so its gathers and atomics coalesce.
+// Pieces are numbered p = 3 * octant + d, octant bits as for Piece.
+// --------------------------------------------------------------------------
+struct LayerPiece {
+    int d, au, av;             // dominant axis and the (u, v) axes (0 = i, 1 = j, 2 = k)
+    int oct;                   // octant bits: 1 = i negative, 2 = j negative, 4 = k negative
+    int sd, su, sv;            // +1 / -1: direction of the offsets along d, u, v
+    int ext_d, ext_u, ext_v;   // periodic extents in those directions
+    int c_d, c_u, c_v;         // source coordinates along d, u, v
+    uint32_t st_d, st_u;       // memory strides of d and u (v has stride 1)
+    bool transposed;           // the piece uses the [k][i][j] copies
+};
+
+__host__ __device__ __forceinline__ int axis_sign(int oct, int ax) { return ((oct >> ax) & 1) ? -1 : 1; }
+
+__host__ __device__ inline LayerPiece make_layer_piece(int p, int si, int sj, int sk, int N,
+                                                       const Extent &ex)
+{
+    LayerPiece L;
+    L.oct = p / 3;
+    L.d = p % 3;
+    L.au = L.d == 0 ? 1 : 0;
+    L.av = L.d == 2 ? 1 : 2;
+    L.transposed = L.d == 2;
+    L.sd = axis_sign(L.oct, L.d);
+    L.su = axis_sign(L.oct, L.au);
+    L.sv = axis_sign(L.oct, L.av);
+    L.ext_d = L.sd < 0 ? ex.neg : ex.pos;
+    L.ext_u = L.su < 0 ? ex.neg : ex.pos;
+    L.ext_v = L.sv < 0 ? ex.neg : ex.pos;
+    // (selects rather than indexed arrays: no private memory on the GPU)
+    L.c_d = L.d == 0 ? si : (L.d == 1 ? sj : sk);
+    L.c_u = L.au == 0 ? si : sj;
+    L.c_v = L.av == 1 ? sj : sk;
+    const uint32_t n = (uint32_t)N;
+    // standard [i][j][k]: strides N^2, N, 1; transposed [k][i][j]: i N, j 1, k N^2
+    if (L.transposed) {          // d = k, u = i, v = j
+        L.st_d = n * n;
+        L.st_u = n;
+    } else if (L.d == 0) {       // u = j, v = k
+        L.st_d = n * n;
+        L.st_u = n;
+    } else {                     // d = j, u = i, v = k
+        L.st_d = n;
+        L.st_u = n * n;
+    }
+    return L;
+}
+
+// Largest r with r * r <= x (0 <= x < 2^24).
+__host__ __device__ __forceinline__ int isqrt_floor(int x)
+{
+    int r = (int)sqrtf((float)x);
+    if (r * r > x) --r;
+    else if ((r + 1) * (r + 1) <= x) ++r;
+    return r;
+}
+
+// Everything one layer-cell update needs that is uniform over a piece.
+struct LayerX {
+    int N;
+    int reading;           // 0: directional source half path, 1: scalar
+    float tau_w;           // <= 0: geometric weights
+    double sigma0, alpha;
+    double half_col;       // n_HI(s) alpha / 2
+    const double *nHI;     // n_HI in the piece's layout
+};
+
+struct LayerCell {
+    uint32_t cp;    // cell index in the piece's layout
+    double Nin, Nout, dN;
+    int r2;
+    bool owned;
+};
+
+// The short-characteristics update of cell (u, v) of layer m of a pyramid:
+// entry column interpolated from the four neighbours in layer m - 1 (eqs.
+// 11-12; for m = 1 the only neighbour of non-zero weight is the source),
+// in-cell column (eqs. 9-10), ownership.  lay holds layer m - 1 as
+// lay[u * S + v].  The arithmetic is the same as cell_update's.
+__host__ __device__ __forceinline__ void layer_cell(const LayerPiece &L, const LayerX &X, int m,
+                                                    int u, int v, const double *lay, int S,
+                                                    LayerCell &out)
+{
+    const int N = X.N;
+    const uint32_t cp = (uint32_t)wrap(L.c_d + L.sd * m, N) * L.st_d +
+                        (uint32_t)wrap(L.c_u + L.su * u, N) * L.st_u +
+                        (uint32_t)wrap(L.c_v + L.sv * v, N);
+    const double nhi = X.nHI[cp];
+    const double inv_m = rcp_f64((double)m);
+    // a = 1 (b = 1) must be exact: the weights of neighbours that leave the
+    // pyramid then vanish exactly
+    const double a = u == m ? 1.0 : (double)u * inv_m;
+    const double b = v == m ? 1.0 : (double)v * inv_m;
+    const int r2 = m * m + u * u + v * v;
+    const double ds = sqrt_fast((double)r2) * inv_m;
+    double Nin;
+    if (m == 1) {
+        Nin = X.reading == 0 ? X.half_col * ds : X.half_col;
+    } else {
+        const double sw[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
+        double num = 0.0, W = 0.0;
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            if (!(sw[n] > 0.0)) continue;
+            const double M = lay[(u - (n & 1)) * S + (v - (n >> 1))];
+            double wn = sw[n];
+            if (X.tau_w > 0.f) wn *= rcp_f64(fmax(X.sigma0 * M, (double)X.tau_w));
+            num += wn * M;
+            W += wn;
+        }
+        Nin = num * rcp_f64(W);
+    }
+    const double dN = nhi * X.alpha * ds;
+    // ownership: zero planes of negative axes belong to the neighbouring
+    // octant; a tied cell to the first dominant axis in the order k, j, i
+    bool owned = !((((L.oct >> L.au) & 1) && u == 0) || (((L.oct >> L.av) & 1) && v == 0));
+    int canon = 0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int t = ax == L.d ? m : (ax == L.au ? u : v);
+        if (t == m) canon = ax;   // the last tied axis in i, j, k order = the first in k, j, i
+    }
+    owned = owned && canon == L.d;
+    out.cp = cp;
+    out.Nin = Nin;
+    out.Nout = Nin + dN;
+    out.dN = dN;
+    out.r2 = r2;
+    out.owned = owned;
+}
+
+// Cell (i, j, k) of layer cell (m, u, v), in the standard layout.
+__host__ __device__ __forceinline__ uint32_t layer_std_index(const LayerPiece &L, int N, int m, int u,
+                                                             int v)
+{
+    const int cd = wrap(L.c_d + L.sd * m, N), cu = wrap(L.c_u + L.su * u, N),
+              cv = wrap(L.c_v + L.sv * v, N);
+    const int ci = L.d == 0 ? cd : cu;                      // u is i unless d = i
+    const int cj = L.d == 1 ? cd : (L.d == 0 ? cu : cv);
+    const int ck = L.d == 2 ? cd : cv;                      // v is k unless d = k
+    return ((uint32_t)ci * (uint32_t)N + (uint32_t)cj) * (uint32_t)N + (uint32_t)ck;
+}
+
+// Reverse-mode update of layer cell (u, v) of layer m (the layer form of
+// cell_adjoint, same arithmetic).  Nbar_out: total adjoint of the cell's
+// exit column from its consumers in layer m + 1; dN: its in-cell column as
+// the forward computed it; cols: exit columns of layer m - 1 (unused for
+// m = 1); gbar_grid: dL/dGamma in the piece's layout.  Returns the adjoints
+// to push to the four neighbours of layer m - 1 (Mbar[n], for neighbour
+// (u - (n & 1), v - (n >> 1)); zero where the weight is zero; for m = 1 the
+// source takes them through nbar_src), dL/dn_HI of the cell and gbar * Gamma.
+struct LayerAdj {
+    uint32_t cp;
+    double Mbar[4];
+    double nbar_src;
+    double nbar;
+    double qbar;
+};
+
+__host__ __device__ __forceinline__ void layer_cell_adjoint(const LayerPiece &L, const LayerX &X,
+                                                            const TabNode *T, const double *m64,
+                                                            const TabParams &tp, double coef, int m,
+                                                            int u, int v, const double *cols, int S,
+                                                            double Nbar_out, double dN,
+                                                            const double *gbar_grid, LayerAdj &out)
+{
+    const int N = X.N;
+    const uint32_t cp = (uint32_t)wrap(L.c_d + L.sd * m, N) * L.st_d +
+                        (uint32_t)wrap(L.c_u + L.su * u, N) * L.st_u +
+                        (uint32_t)wrap(L.c_v + L.sv * v, N);
+    const double inv_m = rcp_f64((double)m);
+    const double a = u == m ? 1.0 : (double)u * inv_m;
+    const double b = v == m ? 1.0 : (double)v * inv_m;
+    const int r2 = m * m + u * u + v * v;
+    const double ds = sqrt_fast((double)r2) * inv_m;
+    const double sw[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
+    double Mv[4], wv[4], dw[4];
+    double num = 0.0, W = 0.0;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        Mv[n] = 0.0;
+        wv[n] = 0.0;
+        dw[n] = 0.0;
+        if (!(sw[n] > 0.0)) continue;
+        const double M = m == 1 ? (X.reading == 0 ? X.half_col * ds : X.half_col)
+                                : cols[(u - (n & 1)) * S + (v - (n >> 1))];
+        double wn = sw[n];
+        if (X.tau_w > 0.f) {
+            const double tau = X.sigma0 * M;
+            if (tau > (double)X.tau_w) {
+                const double it = 1.0 / tau;
+                wn *= it;
+                dw[n] = -sw[n] * X.sigma0 * it * it;
+            } else {
+                wn *= 1.0 / (double)X.tau_w;
+            }
+        }
+        Mv[n] = M;
+        wv[n] = wn;
+        num += wn * M;
+        W += wn;
+    }
+    const double iW = 1.0 / W;
+    const double Nin = num * iW;
+    bool owned = !((((L.oct >> L.au) & 1) && u == 0) || (((L.oct >> L.av) & 1) && v == 0));
+    int canon = 0;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+        const int t = ax == L.d ? m : (ax == L.au ? u : v);
+        if (t == m) canon = ax;
+    }
+    owned = owned && canon == L.d;
+    double Nin_bar = Nbar_out, dN_bar = Nbar_out, qb = 0.0;
+    const double ta = X.sigma0 * Nin;
+    // dL/dGamma is read only where the rate can be non-zero
+    const double gbar = (owned && ta < tp.tau_hi) ? gbar_grid[cp] : 0.0;
+    if (gbar != 0.0) {
+        double D, Da, Ddt;
+        rate_derivs64(T, m64, tp, ta, X.sigma0 * dN, &D, &Da, &Ddt);
+        const double k = -coef / (double)r2;          // Gamma = k D
+        Nin_bar += gbar * k * Da * X.sigma0;
+        dN_bar += gbar * k * Ddt * X.sigma0;
+        qb = gbar * k * D;                            // = gbar Gamma
+    }
+    out.cp = cp;
+    out.nbar = dN_bar * X.alpha * ds;                 // dN = n_HI alpha ds
+    out.qbar = qb;
+    out.nbar_src = 0.0;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        const double mb = sw[n] > 0.0 ? Nin_bar * (wv[n] + (Mv[n] - Nin) * dw[n]) * iW : 0.0;
+        out.Mbar[n] = m == 1 ? 0.0 : mb;
+        if (m == 1) out.nbar_src += mb * (X.reading == 0 ? X.alpha * ds * 0.5 : X.alpha * 0.5);
+    }
+}
+
 // Build the row table of shell q of a piece (serial form; the kernel runs
 // the same per-row computation in parallel with a wave-wide scan).
 __host__ __device__ inline int build_rows(const Piece &pc, const Extent &ex, int Rsq, int q,
@@ -773,19 +1022,31 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Next work item of a wave from the global counter.  Every lane takes part in
-// the one atomic (lane 0 adds 1, the others 0) and the item is lane 0's
-// result, read into a scalar register.  There is no branch on the lane index
-// here: with `if (lane == 0) fetch` followed by a broadcast, the compiler may
-// merge that branch with a lane-0 branch at the end of the previous item and
-// run lane 0 and lanes 1..63 around separate loops, so that the broadcast runs
-// without lane 0 and lanes 1..63 never see the end of the work.  The scalar
-// result also lets the compiler treat everything derived from the item as
-// wave-uniform.
-__device__ __forceinline__ int next_item(int *counter, int lane)
+// Next work item of a wave.  The items of a launch (in the spatial order of
+// their sources) are split into kXcds contiguous chunks with one counter each;
+// the waves of work-group b start on chunk b % kXcds, which keeps the cells
+// that one die's L2 sees in a compact region of the grid, and move on to the
+// following chunks once theirs is used up.  Returns nitems when no chunk has
+// work left.
+//
+// Every lane takes part in each atomic (lane 0 adds 1, the others 0) and the
+// result is lane 0's, read into a scalar register.  There is no branch on the
+// lane index: with `if (lane == 0) fetch` followed by a broadcast, the compiler
+// may merge that branch with a lane-0 branch at the end of the previous item
+// and run lane 0 and lanes 1..63 around separate loops, so that the broadcast
+// runs without lane 0 and lanes 1..63 never see the end of the work.  The
+// scalar result also makes everything derived from the item wave-uniform.
+__device__ __forceinline__ int next_item(int *counters, int nitems, int home, int &chunk, int lane)
 {
-    const int got = atomicAdd(counter, lane == 0 ? 1 : 0);
-    return __builtin_amdgcn_readfirstlane(got);
+    for (;;) {
+        const int lo = (int)((long)nitems * chunk / kXcds);
+        const int hi = (int)((long)nitems * (chunk + 1) / kXcds);
+        const int got = atomicAdd(&counters[chunk], lane == 0 ? 1 : 0);
+        const int k = __builtin_amdgcn_readfirstlane(got);
+        if (lo + k < hi) return lo + k;
+        chunk = chunk + 1 == kXcds ? 0 : chunk + 1;
+        if (chunk == home) return nitems;
+    }
 }
 
 // Row table of shell q built by one wave: every lane owns up to kRowsPerLane

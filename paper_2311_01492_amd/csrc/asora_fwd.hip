@@ -28,7 +28,7 @@ struct FwdArgs {
     const double *Q;
     const float *R;         // may be NULL: every source has R = R_cap
     float R_cap;
-    const int *order;       // sources sorted by type and decreasing radius
+    const int *order;       // sources sorted by piece kind, then spatially (Morton blocks)
     const int *seg;         // seg[t] .. seg[t+1]: sources of type t in order[]
     int type, n_pieces;
     int *counter;
@@ -37,6 +37,9 @@ struct FwdArgs {
     int plain_src;          // >= 0: non-persistent launch for this source
     int region_bytes;       // per-wave LDS region (wave kernels)
     double coef_unit;       // sigma0 / (4 pi alpha^2)
+    const double *nHI_T;    // n_HI in the [k][i][j] layout (layer pieces with d = k)
+    double *gacc_T;         // Gamma accumulator in the [k][i][j] layout
+    int lay_S;              // row stride of the per-wave layer buffer (layer pieces)
 };
 
 struct Lds {
@@ -161,14 +164,14 @@ struct RateQueue {
 };
 
 __device__ __forceinline__ void rate_batch(const FwdArgs &A, const TabNode *T, const RateQueue &Qa,
-                                           int head, int lane, double coef)
+                                           int head, int lane, double coef, double *acc)
 {
     const int pos = (head + lane) & (kQueue - 1);
     const double ta = Qa.ta[pos];
     const float nd = neg_divdiff(T, A.tp, ta, (double)Qa.dt[pos]);
     if (nd > 0.f) {
         const double G = coef * (double)(nd * rcp_approx((float)Qa.r2[pos]));
-        unsafeAtomicAdd(&A.gacc[Qa.cp[pos]], G);
+        unsafeAtomicAdd(&acc[Qa.cp[pos]], G);
     }
 }
 
@@ -256,7 +259,7 @@ __device__ void sweep_piece_wave(const FwdArgs &A, const TabNode *T, double *rin
             tail += __popcll(mask);
             if (tail - head >= 64) {
                 wave_sync();
-                rate_batch(A, T, Qa, head, lane, X.coef);
+                rate_batch(A, T, Qa, head, lane, X.coef, A.gacc);
                 head += 64;
                 wave_sync();
             }
@@ -266,7 +269,7 @@ __device__ void sweep_piece_wave(const FwdArgs &A, const TabNode *T, double *rin
     // the rates still queued
     if (tail > head) {
         wave_sync();
-        if (lane < tail - head) rate_batch(A, T, Qa, head, lane, X.coef);
+        if (lane < tail - head) rate_batch(A, T, Qa, head, lane, X.coef, A.gacc);
         wave_sync();
     }
 }
@@ -306,13 +309,182 @@ __global__ __launch_bounds__(1024) void fwd_wave(FwdArgs A)
         return;
     }
     const int base = A.seg[TYPE];
-    const long nitems = (long)(A.seg[TYPE + 1] - base) * npieces;
+    const int nitems = (A.seg[TYPE + 1] - base) * npieces;
+    const int home = (int)(blockIdx.x % kXcds);
+    int chunk = home;
     for (;;) {
-        const int item = next_item(A.counter, lane);
+        const int item = next_item(A.counter, nitems, home, chunk, lane);
         if (item >= nitems) break;
         const int src = A.order[base + item / npieces];
         sweep_piece_wave<TYPE>(A, T, ring, rowbase, rowstart, Qa, src, item % npieces, lane);
     }
+}
+
+// ---- layer pieces --------------------------------------------------------
+// One wave sweeps one pyramid layer by layer (see LayerPiece).  The wave
+// covers a layer in tiles of (64 / TV) rows of u by TV consecutive v; the
+// previous layer lives in the wave's LDS buffer and is overwritten in place:
+// tiles go in decreasing u band, then decreasing v, so every slot a tile reads
+// (at or below its own u and v) still holds layer m - 1.  Rates go through the
+// same per-wave queue as the shell sweep.
+template <int TV>
+__device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *lay,
+                                  const RateQueue &Qa, int src, int p, int lane)
+{
+    constexpr int TU = 64 / TV;
+    const int N = A.N;
+    const int si = A.ijk[3 * src], sj = A.ijk[3 * src + 1], sk = A.ijk[3 * src + 2];
+    const float R = A.R ? A.R[src] : A.R_cap;
+    if (!(R >= 0.f && R <= A.R_cap) || si < 0 || si >= N || sj < 0 || sj >= N || sk < 0 ||
+        sk >= N) {
+        if (lane == 0) atomicOr(A.err, 1);
+        return;
+    }
+    const double Q = A.Q[src];
+    const int Rsq = (int)floor((double)R * (double)R);
+    const LayerPiece L = make_layer_piece(p, si, sj, sk, N, A.ex);
+    const uint32_t cs = ((uint32_t)si * (uint32_t)N + (uint32_t)sj) * (uint32_t)N + (uint32_t)sk;
+    const double n_s = A.nHI[cs];
+    LayerX X;
+    X.N = N;
+    X.reading = A.reading;
+    X.tau_w = A.tau_w;
+    X.sigma0 = A.sigma0;
+    X.alpha = A.alpha;
+    X.half_col = n_s * A.alpha * 0.5;
+    X.nHI = L.transposed ? A.nHI_T : A.nHI;
+    double *acc = L.transposed ? A.gacc_T : A.gacc;
+    const double coef = Q * A.coef_unit;
+    const int S = A.lay_S;
+
+    if (p == 3 * 0 + 2 && lane == 0) {   // the source cell, once per source
+        const double G = source_cell_rate(T, A.tp, A.sigma0, A.alpha, Q, n_s);
+        if (G != 0.0) unsafeAtomicAdd(&A.gacc[cs], G);
+        if (A.coldens) A.coldens[cs] = 0.0;
+    }
+    const int Mx = min(isqrt_floor(Rsq), L.ext_d);
+    for (int k = lane; k < (Mx + 1) * S; k += 64) lay[k] = 0.0;
+    wave_sync();
+    int head = 0, tail = 0;
+    for (int m = 1; m <= Mx; ++m) {
+        const int rem = Rsq - m * m;
+        const int umax = min(min(m, L.ext_u), isqrt_floor(rem));
+        const int vcap = min(m, L.ext_v);
+        for (int tu = umax / TU; tu >= 0; --tu) {
+            const int u0 = tu * TU;
+            const int vmax = min(vcap, isqrt_floor(rem - u0 * u0));
+            for (int tv = vmax / TV; tv >= 0; --tv) {
+                const int u = u0 + lane / TV, v = tv * TV + lane % TV;
+                const bool act = u <= umax && v <= vcap && u * u + v * v <= rem;
+                LayerCell lc;
+                lc.Nin = 0.0;
+                lc.owned = false;
+                if (act) layer_cell(L, X, m, u, v, lay, S, lc);
+                wave_sync();   // every read of layer m - 1 before the writes below
+                bool want = false;
+                if (act) {
+                    lay[u * S + v] = lc.Nout;
+                    if (lc.owned) {
+                        if (A.coldens) A.coldens[layer_std_index(L, N, m, u, v)] = lc.Nin;
+                        want = A.sigma0 * lc.Nin < A.tp.tau_hi;
+                    }
+                }
+                const uint64_t mask = __ballot(want);
+                if (want) {
+                    const int pos = (tail + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))) & (kQueue - 1);
+                    Qa.ta[pos] = A.sigma0 * lc.Nin;
+                    Qa.dt[pos] = A.sigma0 * lc.dN;
+                    Qa.cp[pos] = lc.cp;
+                    Qa.r2[pos] = lc.r2;
+                }
+                tail += __popcll(mask);
+                if (tail - head >= 64) {
+                    wave_sync();
+                    rate_batch(A, T, Qa, head, lane, coef, acc);
+                    head += 64;
+                }
+                wave_sync();
+            }
+        }
+    }
+    if (tail > head) {
+        wave_sync();
+        if (lane < tail - head) rate_batch(A, T, Qa, head, lane, coef, acc);
+        wave_sync();
+    }
+}
+
+template <int TV>
+__global__ __launch_bounds__(1024) void fwd_layer(FwdArgs A)
+{
+    extern __shared__ __align__(16) char smem[];
+    constexpr int TYPE = 3, npieces = 24;
+    if (A.plain_src < 0 && A.seg[TYPE + 1] == A.seg[TYPE]) return;   // no sources of this kind
+    TabNode *T = (TabNode *)smem;
+    {
+        const int4 *s = (const int4 *)A.tab;
+        int4 *d = (int4 *)smem;
+        for (int k = threadIdx.x; k < A.tp.n; k += blockDim.x) d[k] = s[k];
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int waves = blockDim.x >> 6;
+    char *region = smem + (size_t)A.tp.n * sizeof(TabNode) + (size_t)wave * A.region_bytes;
+    RateQueue Qa;
+    Qa.ta = (double *)region;
+    Qa.dt = (float *)(Qa.ta + kQueue);
+    Qa.cp = (uint32_t *)(Qa.dt + kQueue);
+    Qa.r2 = (int *)(Qa.cp + kQueue);
+    double *lay = (double *)(Qa.r2 + kQueue);
+    if (A.plain_src >= 0) {
+        const int item = blockIdx.x * waves + wave;
+        if (item < npieces) sweep_layer_piece<TV>(A, T, lay, Qa, A.plain_src, item, lane);
+        return;
+    }
+    const int base = A.seg[TYPE];
+    const int nitems = (A.seg[TYPE + 1] - base) * npieces;
+    const int home = (int)(blockIdx.x % kXcds);
+    int chunk = home;
+    for (;;) {
+        const int item = next_item(A.counter, nitems, home, chunk, lane);
+        if (item >= nitems) break;
+        const int src = A.order[base + item / npieces];
+        sweep_layer_piece<TV>(A, T, lay, Qa, src, item % npieces, lane);
+    }
+}
+
+// Per-wave LDS of the layer kernel: the rate queue, then (Mcap + 1) rows of S
+// doubles.
+size_t layer_region_bytes(int Mcap, int S)
+{
+    const size_t b = (size_t)kQueue * (sizeof(double) + sizeof(float) + sizeof(uint32_t) + sizeof(int)) +
+                     (size_t)(Mcap + 1) * S * sizeof(double);
+    return (b + 15) & ~(size_t)15;
+}
+
+static const void *layer_fn(int tv)
+{
+    return tv == 8 ? (const void *)fwd_layer<8> : (const void *)fwd_layer<16>;
+}
+
+hipError_t layer_occupancy(int tv, int waves, size_t lds, int *blocks_per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, layer_fn(tv), waves * 64, lds);
+}
+
+hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int tv, int Mcap, int waves, int grid,
+                            int plain_src)
+{
+    FwdArgs A = make_args(F);
+    A.plain_src = plain_src;
+    A.lay_S = Mcap + 1;
+    A.region_bytes = (int)layer_region_bytes(Mcap, A.lay_S);
+    const size_t lds = (size_t)F.tp.n * sizeof(TabNode) + (size_t)waves * A.region_bytes;
+    if (plain_src >= 0) grid = (24 + waves - 1) / waves;
+    if (tv == 8) hipLaunchKernelGGL(fwd_layer<8>, dim3(grid), dim3(64 * waves), lds, st, A);
+    else hipLaunchKernelGGL(fwd_layer<16>, dim3(grid), dim3(64 * waves), lds, st, A);
+    return hipGetLastError();
 }
 
 size_t wave_region_bytes(int ring_cap, int row_cap)
@@ -408,8 +580,23 @@ __global__ void prologue_kernel(const float *__restrict__ nH, const float *__res
         for (int k = threadIdx.x; k < nctl; k += blockDim.x) ctl[k] = 0;
 }
 
+// Morton index of the 16^3 block that holds cell (i, j, k).
+__device__ __forceinline__ int block_morton(int i, int j, int k, int N)
+{
+    const int bi = (int)((long)i * 16 / N), bj = (int)((long)j * 16 / N), bk = (int)((long)k * 16 / N);
+    int m = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        m |= (((bi >> b) & 1) << (3 * b + 2)) | (((bj >> b) & 1) << (3 * b + 1)) | (((bk >> b) & 1) << (3 * b));
+    return m;
+}
+
+// Source pre-pass: piece kind by radius, then the spatial block of the source
+// in Morton order, so that sources swept at the same time lie close together
+// and share cached field and accumulator lines.
 __global__ void classify_kernel(const float *R, const int32_t *ijk, long nsrc, int N, float R_max,
-                                float R_whole, float R_oct, int *keys, int *hist, int *err)
+                                float R_whole, float R_oct, int big_type, int *keys, int *hist,
+                                int *err)
 {
     const long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (s >= nsrc) return;
@@ -418,37 +605,54 @@ __global__ void classify_kernel(const float *R, const int32_t *ijk, long nsrc, i
     int key;
     if (!(r >= 0.f && r <= R_max) || i < 0 || i >= N || j < 0 || j >= N || k < 0 || k >= N) {
         atomicOr(err, 1);
-        key = 3 * kRBins;   // not scheduled
+        key = kTypes * kSBins;   // not scheduled
     } else {
-        const int type = r <= R_whole ? 0 : (r <= R_oct ? 1 : 2);
-        int bin = R_max > 0.f ? (int)(r / R_max * (float)(kRBins - 1)) : 0;
-        bin = bin < 0 ? 0 : (bin > kRBins - 1 ? kRBins - 1 : bin);
-        key = type * kRBins + (kRBins - 1 - bin);
+        const int type = r <= R_whole ? 0 : (r <= R_oct ? 1 : big_type);
+        key = type * kSBins + block_morton(i, j, k, N);
         atomicAdd(&hist[key], 1);
     }
     keys[s] = key;
 }
 
-// Exclusive scan of the 3*kRBins histogram (one work-group); offsets and
-// per-type segment starts.
-__global__ void scan_kernel(const int *hist, int *offs, int *seg)
+// Exclusive scan of the kTypes*kSBins histogram by one work-group of kScanThreads
+// threads (each owns a run of consecutive bins); offsets and per-kind segment
+// starts.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void scan_kernel(const int *hist, int *offs, int *seg)
 {
-    constexpr int n = 3 * kRBins;
-    __shared__ int buf[n];
-    for (int k = threadIdx.x; k < n; k += blockDim.x) buf[k] = hist[k];
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int run = 0;
-        for (int k = 0; k < n; ++k) {
-            const int v = buf[k];
-            buf[k] = run;
-            run += v;
-        }
-        for (int t = 0; t < 3; ++t) seg[t] = buf[t * kRBins];
-        seg[3] = run;
+    constexpr int n = kTypes * kSBins;
+    constexpr int per = (n + kScanThreads - 1) / kScanThreads;
+    __shared__ int wsum[kScanThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    int v[per];
+    int sum = 0;
+#pragma unroll
+    for (int u = 0; u < per; ++u) {
+        const int b = t * per + u;
+        v[u] = b < n ? hist[b] : 0;
+        sum += v[u];
     }
+    int incl = sum;   // inclusive scan over the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int x = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += x;
+    }
+    if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    for (int k = threadIdx.x; k < n; k += blockDim.x) offs[k] = buf[k];
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    int run = before + incl - sum;
+#pragma unroll
+    for (int u = 0; u < per; ++u) {
+        const int b = t * per + u;
+        if (b < n) {
+            offs[b] = run;
+            if (b % kSBins == 0) seg[b / kSBins] = run;
+        }
+        run += v[u];
+    }
+    if (t == kScanThreads - 1) seg[kTypes] = run;
 }
 
 __global__ void scatter_kernel(const int *keys, long nsrc, int *offs, int *order)
@@ -456,9 +660,64 @@ __global__ void scatter_kernel(const int *keys, long nsrc, int *offs, int *order
     const long s = blockIdx.x * (long)blockDim.x + threadIdx.x;
     if (s >= nsrc) return;
     const int key = keys[s];
-    if (key >= 3 * kRBins) return;
+    if (key >= kTypes * kSBins) return;
     const int pos = atomicAdd(&offs[key], 1);
     order[pos] = (int)s;
+}
+
+// n_HI and the zeroed accumulator in the [k][i][j] layout used by the layer
+// pieces whose dominant axis is k: one 32 x 32 (j, k) tile of one i plane
+// per work-group, staged through LDS so that both the reads (along k) and the
+// writes (along j) are contiguous.
+constexpr int kTile = 32;
+__global__ __launch_bounds__(256) void transpose_prologue_kernel(const float *__restrict__ nH,
+                                                                 const float *__restrict__ xHI,
+                                                                 double *__restrict__ nHI_T,
+                                                                 double *__restrict__ gacc_T, int N)
+{
+    __shared__ double tile[kTile][kTile + 1];
+    const int k0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile, i = blockIdx.z;
+    const int tx = threadIdx.x & (kTile - 1), ty = threadIdx.x / kTile;   // 32 x 8
+    for (int jj = ty; jj < kTile; jj += 8) {
+        const int j = j0 + jj, k = k0 + tx;
+        if (j < N && k < N) {
+            const size_t c = ((size_t)i * N + j) * N + k;
+            tile[jj][tx] = (double)nH[c] * (double)xHI[c];   // exact
+        }
+    }
+    __syncthreads();
+    for (int kk = ty; kk < kTile; kk += 8) {
+        const int k = k0 + kk, j = j0 + tx;
+        if (j < N && k < N) {
+            const size_t t = ((size_t)k * N + i) * N + j;
+            nHI_T[t] = tile[tx][kk];
+            gacc_T[t] = 0.0;
+        }
+    }
+}
+
+// Gamma = accumulator + transposed accumulator, in the standard layout.
+__global__ __launch_bounds__(256) void transpose_finalize_kernel(const double *__restrict__ gacc,
+                                                                 const double *__restrict__ gacc_T,
+                                                                 float *__restrict__ gamma, int N,
+                                                                 int accumulate)
+{
+    __shared__ double tile[kTile][kTile + 1];
+    const int k0 = blockIdx.x * kTile, j0 = blockIdx.y * kTile, i = blockIdx.z;
+    const int tx = threadIdx.x & (kTile - 1), ty = threadIdx.x / kTile;
+    for (int kk = ty; kk < kTile; kk += 8) {
+        const int k = k0 + kk, j = j0 + tx;
+        if (j < N && k < N) tile[kk][tx] = gacc_T[((size_t)k * N + i) * N + j];
+    }
+    __syncthreads();
+    for (int jj = ty; jj < kTile; jj += 8) {
+        const int j = j0 + jj, k = k0 + tx;
+        if (j < N && k < N) {
+            const size_t c = ((size_t)i * N + j) * N + k;
+            const float v = (float)(gacc[c] + tile[tx][jj]);
+            gamma[c] = accumulate ? gamma[c] + v : v;
+        }
+    }
 }
 
 __global__ void finalize_kernel(const double *__restrict__ gacc, float *__restrict__ gamma, long n3,
@@ -483,17 +742,34 @@ hipError_t launch_prologue(hipStream_t st, const float *nH, const float *xHI, do
     return hipGetLastError();
 }
 
+hipError_t launch_transpose_prologue(hipStream_t st, const float *nH, const float *xHI, double *nHI_T,
+                                     double *gacc_T, int N)
+{
+    const dim3 grid((N + kTile - 1) / kTile, (N + kTile - 1) / kTile, N);
+    hipLaunchKernelGGL(transpose_prologue_kernel, grid, dim3(256), 0, st, nH, xHI, nHI_T, gacc_T, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_finalize(hipStream_t st, const double *gacc, const double *gacc_T,
+                                     float *gamma, int N, int accumulate)
+{
+    const dim3 grid((N + kTile - 1) / kTile, (N + kTile - 1) / kTile, N);
+    hipLaunchKernelGGL(transpose_finalize_kernel, grid, dim3(256), 0, st, gacc, gacc_T, gamma, N,
+                       accumulate);
+    return hipGetLastError();
+}
+
 hipError_t launch_bucketing(hipStream_t st, const float *R, const int32_t *ijk, long nsrc, int N,
-                            float R_max, float R_whole, float R_oct, int *keys, int *ctl,
-                            int *order, int *err)
+                            float R_max, float R_whole, float R_oct, int big_type, int *keys,
+                            int *ctl, int *order, int *err)
 {
     int *hist = ctl + kCtlHist, *offs = ctl + kCtlOffs, *seg = ctl + kCtlSeg;
     const int b = (int)((nsrc + 255) / 256);
     if (nsrc > 0) {
         hipLaunchKernelGGL(classify_kernel, dim3(b), dim3(256), 0, st, R, ijk, nsrc, N, R_max,
-                           R_whole, R_oct, keys, hist, err);
+                           R_whole, R_oct, big_type, keys, hist, err);
     }
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(256), 0, st, hist, offs, seg);
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(kScanThreads), 0, st, hist, offs, seg);
     if (nsrc > 0)
         hipLaunchKernelGGL(scatter_kernel, dim3(b), dim3(256), 0, st, keys, nsrc, offs, order);
     return hipGetLastError();
@@ -513,6 +789,9 @@ static FwdArgs make_args(const FwdLaunch &F)
     A.nHI = F.nHI;
     A.gacc = F.gacc;
     A.coldens = F.coldens;
+    A.nHI_T = F.nHI_T;
+    A.gacc_T = F.gacc_T;
+    A.lay_S = 0;
     A.ijk = F.ijk;
     A.Q = F.Q;
     A.R = F.R;
@@ -521,7 +800,7 @@ static FwdArgs make_args(const FwdLaunch &F)
     A.seg = F.ctl + kCtlSeg;
     A.type = F.type;
     A.n_pieces = pieces_of_type(F.type);
-    A.counter = F.ctl + kCtlCounter + F.type;
+    A.counter = F.ctl + kCtlCounter + kXcds * F.type;
     A.err = F.err;
     A.ring_cap = F.ring_cap;
     A.row_cap = F.row_cap;
@@ -549,6 +828,8 @@ hipError_t fwd_configure(size_t max_lds)
     (void)hipFuncSetAttribute((const void *)fwd_wave<0>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipFuncSetAttribute((const void *)fwd_wave<1>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipFuncSetAttribute((const void *)fwd_wave<2>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)fwd_layer<8>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)fwd_layer<16>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipGetLastError();
     return hipSuccess;
 }

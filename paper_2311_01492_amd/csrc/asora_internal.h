@@ -9,12 +9,13 @@
 
 namespace asora {
 
-constexpr int kRBins = 256;                      // radius bins of the scheduling sort
-constexpr int kCtlCounter = 0;                   // 3 work counters (one per piece type)
-constexpr int kCtlSeg = 4;                       // 4 segment starts
-constexpr int kCtlHist = 16;                     // 3*kRBins histogram
-constexpr int kCtlOffs = kCtlHist + 3 * kRBins;  // 3*kRBins scatter offsets
-constexpr int kCtlSize = kCtlOffs + 3 * kRBins;
+constexpr int kTypes = 4;                        // piece kinds: whole, octants, shell pyramids, layer pyramids
+constexpr int kSBins = 4096;                     // spatial bins per piece kind (16^3 blocks, Morton order)
+constexpr int kCtlCounter = 0;                   // work counters: kXcds per piece kind
+constexpr int kCtlSeg = kTypes * kXcds;          // kTypes + 1 segment starts
+constexpr int kCtlHist = kCtlSeg + 8;            // kTypes*kSBins histogram
+constexpr int kCtlOffs = kCtlHist + kTypes * kSBins;  // kTypes*kSBins scatter offsets
+constexpr int kCtlSize = kCtlOffs + kTypes * kSBins;
 
 struct FwdLaunch {
     int N;
@@ -35,13 +36,23 @@ struct FwdLaunch {
     int *err;
     int type;
     int ring_cap, row_cap;
+    const double *nHI_T;    // [k][i][j] copies used by the layer pieces (may be NULL otherwise)
+    double *gacc_T;
 };
 
 hipError_t launch_prologue(hipStream_t st, const float *nH, const float *xHI, double *nHI,
                            double *gacc, double *coldens, long n3, int *ctl, int nctl, int n_cu);
 hipError_t launch_bucketing(hipStream_t st, const float *R, const int32_t *ijk, long nsrc, int N,
-                            float R_max, float R_whole, float R_oct, int *keys, int *ctl,
-                            int *order, int *err);
+                            float R_max, float R_whole, float R_oct, int big_type, int *keys,
+                            int *ctl, int *order, int *err);
+hipError_t launch_transpose_prologue(hipStream_t st, const float *nH, const float *xHI, double *nHI_T,
+                                     double *gacc_T, int N);
+hipError_t launch_transpose_finalize(hipStream_t st, const double *gacc, const double *gacc_T,
+                                     float *gamma, int N, int accumulate);
+size_t layer_region_bytes(int Mcap, int S);
+hipError_t layer_occupancy(int tv, int waves, size_t lds, int *blocks_per_cu);
+hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int tv, int Mcap, int waves, int grid,
+                            int plain_src);
 size_t fwd_lds_bytes(int n_tab, int ring_cap, int row_cap);
 hipError_t fwd_configure(size_t max_lds);
 hipError_t fwd_occupancy(size_t lds, int *blocks_per_cu);
@@ -77,6 +88,9 @@ struct AdjLaunch {
     int waves, grid;
     double *store;
     long store_stride;
+    const double *nHI_T;   // [k][i][j] copies for the layer pieces (may be NULL otherwise)
+    const double *gbar_T;
+    double *nbar_T;
 };
 
 size_t adj_region_bytes(int ring_cap, int row_cap, int shell_cap);
@@ -86,6 +100,15 @@ hipError_t launch_adj_prologue(hipStream_t st, const float *nH, const float *xHI
                                double *nbar, long n3, double *qbar, long nsrc, int zero_q, int *ctl,
                                int nctl, int n_cu);
 hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L);
+size_t adj_layer_region_bytes(int Mcap, int S);
+hipError_t adj_layer_occupancy(int tv, int waves, size_t lds, int *blocks_per_cu);
+hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int tv, int Mcap);
+hipError_t launch_adj_transpose_prologue(hipStream_t st, const float *nH, const float *xHI,
+                                         const double *gbar, double *nHI_T, double *gbar_T,
+                                         double *nbar_T, int N);
+hipError_t launch_adj_transpose_finalize(hipStream_t st, const double *nbar, const double *nbar_T,
+                                         const float *nH, const float *xHI, float *dnH, float *dxHI,
+                                         int N, int accumulate);
 hipError_t launch_adj_finalize(hipStream_t st, const double *nbar, const float *nH, const float *xHI,
                                float *dnH, float *dxHI, long n3, int accumulate, int n_cu);
 

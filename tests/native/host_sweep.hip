@@ -5,6 +5,7 @@
 // parts (wave scan, barriers, atomics) written as plain loops.
 #include <cmath>
 #include <cstdint>
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -131,6 +132,274 @@ extern "C" int hc_raytrace(int N, double alpha, double sigma0, int n, double lg_
     return 0;
 }
 
+// Forward on the CPU through the layer pieces (every source as 24 pyramids
+// swept layer by layer), in the kernel's tile order with its in-place layer
+// buffer: per tile all 64 lanes read before any writes.  Pyramids with
+// dominant axis k read n_HI from the [k][i][j] copy and accumulate into a
+// [k][i][j] accumulator, added at the end as on the GPU.  Every read of a
+// neighbour of non-zero weight is checked to hold layer m - 1 (returns -6
+// otherwise).  tv is the tile width along v (8 or 16).
+extern "C" int hc_raytrace_layer(int N, double alpha, double sigma0, int n, double lg_lo, double lg_hi,
+                                 const double *P, const double *dP, double tau_w, int reading,
+                                 const float *nH, const float *xHI, long nsrc, const int32_t *ijk,
+                                 const double *Q, const float *R, int tv, double *gacc, double *coldens)
+{
+    if (tv != 8 && tv != 16) return -1;
+    const int tu = 64 / tv;
+    TabParams tp;
+    std::vector<TabNode> T(n);
+    std::vector<double> m64(n);
+    prepare_table(n, lg_lo, lg_hi, P, dP, &tp, T.data(), m64.data());
+    const long n3 = (long)N * N * N;
+    std::vector<double> nhi(n3), nhiT(n3), gT(n3, 0.0);
+    for (long i = 0; i < N; ++i)
+        for (long j = 0; j < N; ++j)
+            for (long k = 0; k < N; ++k) {
+                const long c = (i * N + j) * N + k;
+                nhi[c] = (double)nH[c] * (double)xHI[c];
+                nhiT[(k * N + i) * N + j] = nhi[c];
+            }
+    const Extent ex = make_extent(N);
+    float R_cap = 0.f;
+    for (long s = 0; s < nsrc; ++s) R_cap = R[s] > R_cap ? R[s] : R_cap;
+    const int Rsq_cap = (int)std::floor((double)R_cap * (double)R_cap);
+    int Mcap = isqrt_floor(Rsq_cap);
+    Mcap = Mcap < ex.neg ? Mcap : ex.neg;
+    Mcap = Mcap < 1 ? 1 : Mcap;
+    const int S = Mcap + 1;
+    std::vector<double> lay((size_t)(Mcap + 1) * S);
+    std::vector<int> lay_id((size_t)(Mcap + 1) * S);
+    const double coef_unit = sigma0 / (4.0 * M_PI * alpha * alpha);
+    for (long s = 0; s < nsrc; ++s) {
+        const int si = ijk[3 * s], sj = ijk[3 * s + 1], sk = ijk[3 * s + 2];
+        const int Rsq = (int)std::floor((double)R[s] * (double)R[s]);
+        const long cs = ((long)si * N + sj) * N + sk;
+        const double coef = Q[s] * coef_unit;
+        gacc[cs] += source_cell_rate(T.data(), tp, sigma0, alpha, Q[s], nhi[cs]);
+        if (coldens) coldens[cs] = 0.0;
+        for (int p = 0; p < 24; ++p) {
+            const LayerPiece L = make_layer_piece(p, si, sj, sk, N, ex);
+            LayerX X;
+            X.N = N;
+            X.reading = reading;
+            X.tau_w = (float)(tau_w > 0 && std::isfinite(tau_w) ? tau_w : 0.0);
+            X.sigma0 = sigma0;
+            X.alpha = alpha;
+            X.half_col = nhi[cs] * alpha * 0.5;
+            X.nHI = L.transposed ? nhiT.data() : nhi.data();
+            double *acc = L.transposed ? gT.data() : gacc;
+            std::fill(lay.begin(), lay.end(), 0.0);
+            std::fill(lay_id.begin(), lay_id.end(), -1);
+            const int Mx = std::min(isqrt_floor(Rsq), L.ext_d);
+            for (int m = 1; m <= Mx; ++m) {
+                const int rem = Rsq - m * m;
+                const int umax = std::min(std::min(m, L.ext_u), isqrt_floor(rem));
+                const int vcap = std::min(m, L.ext_v);
+                for (int bu = umax / tu; bu >= 0; --bu) {
+                    const int u0 = bu * tu;
+                    const int vmax = std::min(vcap, isqrt_floor(rem - u0 * u0));
+                    for (int bv = vmax / tv; bv >= 0; --bv) {
+                        LayerCell lc[64];
+                        bool act[64];
+                        for (int lane = 0; lane < 64; ++lane) {
+                            const int u = u0 + lane / tv, v = bv * tv + lane % tv;
+                            act[lane] = u <= umax && v <= vcap && u * u + v * v <= rem;
+                            if (!act[lane]) continue;
+                            if (m > 1) {   // neighbours of non-zero weight must hold layer m - 1
+                                const bool a0 = u > 0, a1 = u < m, b0 = v > 0, b1 = v < m;
+                                const bool need[4] = {a1 && b1, a0 && b1, a1 && b0, a0 && b0};
+                                for (int k = 0; k < 4; ++k)
+                                    if (need[k] && lay_id[(size_t)(u - (k & 1)) * S + v - (k >> 1)] != m - 1)
+                                        return -6;
+                            }
+                            layer_cell(L, X, m, u, v, lay.data(), S, lc[lane]);
+                        }
+                        for (int lane = 0; lane < 64; ++lane) {
+                            if (!act[lane]) continue;
+                            const int u = u0 + lane / tv, v = bv * tv + lane % tv;
+                            lay[(size_t)u * S + v] = lc[lane].Nout;
+                            lay_id[(size_t)u * S + v] = m;
+                            if (!lc[lane].owned) continue;
+                            if (coldens) coldens[layer_std_index(L, N, m, u, v)] = lc[lane].Nin;
+                            const double ta = sigma0 * lc[lane].Nin;
+                            if (ta < tp.tau_hi) {
+                                const float nd = neg_divdiff(T.data(), tp, ta, (double)(float)(sigma0 * lc[lane].dN));
+                                if (nd > 0.f)
+                                    acc[lc[lane].cp] += coef * (double)(nd * rcp_approx((float)lc[lane].r2));
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    for (long i = 0; i < N; ++i)
+        for (long j = 0; j < N; ++j)
+            for (long k = 0; k < N; ++k) gacc[(i * N + j) * N + k] += gT[(k * N + i) * N + j];
+    return 0;
+}
+
+// Reverse mode on the CPU through the layer pieces, in the adjoint kernel's
+// order: forward columns layer by layer (stored per layer), then layers from
+// the outermost inward, layer m - 1 reloaded into the column buffer, tiles of
+// layer m in increasing u band and v, each tile reading its exit-column
+// adjoints, clearing them, then adding to its layer m - 1 neighbours.
+// dL/dn_HI of pyramids with dominant axis k goes through a [k][i][j] buffer
+// as on the GPU.  Returns -6 if a neighbour of non-zero weight is read from a
+// slot that does not hold layer m - 1.
+extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n, double lg_lo,
+                                      double lg_hi, const double *P, const double *dP, double tau_w,
+                                      int reading, const float *nH, const float *xHI, long nsrc,
+                                      const int32_t *ijk, const double *Q, const float *R, int tv,
+                                      const double *gbar, double *nbar, double *qbar)
+{
+    if (tv != 8 && tv != 16) return -1;
+    const int tu = 64 / tv;
+    TabParams tp;
+    std::vector<TabNode> T(n);
+    std::vector<double> m64(n);
+    prepare_table(n, lg_lo, lg_hi, P, dP, &tp, T.data(), m64.data());
+    const long n3 = (long)N * N * N;
+    std::vector<double> nhi(n3), nhiT(n3), gbT(n3), nbT(n3, 0.0);
+    for (long i = 0; i < N; ++i)
+        for (long j = 0; j < N; ++j)
+            for (long k = 0; k < N; ++k) {
+                const long c = (i * N + j) * N + k;
+                nhi[c] = (double)nH[c] * (double)xHI[c];
+                nhiT[(k * N + i) * N + j] = nhi[c];
+                gbT[(k * N + i) * N + j] = gbar[c];
+            }
+    const Extent ex = make_extent(N);
+    float R_cap = 0.f;
+    for (long s = 0; s < nsrc; ++s) R_cap = R[s] > R_cap ? R[s] : R_cap;
+    int Mcap = isqrt_floor((int)std::floor((double)R_cap * (double)R_cap));
+    Mcap = Mcap < ex.neg ? Mcap : ex.neg;
+    Mcap = Mcap < 1 ? 1 : Mcap;
+    const int S = Mcap + 1;
+    const size_t SS = (size_t)(Mcap + 1) * S;
+    std::vector<double> cols(SS), abar(SS), stN((Mcap + 1) * SS), stdN((Mcap + 1) * SS);
+    std::vector<int> cols_id(SS);
+    const double coef_unit = sigma0 / (4.0 * M_PI * alpha * alpha);
+    for (long s = 0; s < nsrc; ++s) {
+        qbar[s] = 0.0;
+        const int si = ijk[3 * s], sj = ijk[3 * s + 1], sk = ijk[3 * s + 2];
+        const int Rsq = (int)std::floor((double)R[s] * (double)R[s]);
+        const long cs = ((long)si * N + sj) * N + sk;
+        const double coef = Q[s] * coef_unit;
+        double nb_src = 0.0, qb = 0.0;
+        for (int p = 0; p < 24; ++p) {
+            const LayerPiece L = make_layer_piece(p, si, sj, sk, N, ex);
+            LayerX X;
+            X.N = N;
+            X.reading = reading;
+            X.tau_w = (float)(tau_w > 0 && std::isfinite(tau_w) ? tau_w : 0.0);
+            X.sigma0 = sigma0;
+            X.alpha = alpha;
+            X.half_col = nhi[cs] * alpha * 0.5;
+            X.nHI = L.transposed ? nhiT.data() : nhi.data();
+            const double *gb = L.transposed ? gbT.data() : gbar;
+            double *nb = L.transposed ? nbT.data() : nbar;
+            const int Mx = std::min(isqrt_floor(Rsq), L.ext_d);
+            std::fill(cols.begin(), cols.end(), 0.0);
+            std::fill(cols_id.begin(), cols_id.end(), -1);
+            auto in_layer = [&](int m, int u, int v) {
+                const int rem = Rsq - m * m;
+                if (rem < 0) return false;
+                const int umax = std::min(std::min(m, L.ext_u), isqrt_floor(rem));
+                const int vcap = std::min(m, L.ext_v);
+                return u <= umax && v <= vcap && u * u + v * v <= rem;
+            };
+            // forward (descending tiles, in place)
+            for (int m = 1; m <= Mx; ++m) {
+                const int rem = Rsq - m * m;
+                const int umax = std::min(std::min(m, L.ext_u), isqrt_floor(rem));
+                const int vcap = std::min(m, L.ext_v);
+                for (int bu = umax / tu; bu >= 0; --bu) {
+                    const int u0 = bu * tu;
+                    const int vmax = std::min(vcap, isqrt_floor(rem - u0 * u0));
+                    for (int bv = vmax / tv; bv >= 0; --bv) {
+                        LayerCell lc[64];
+                        bool act[64];
+                        for (int lane = 0; lane < 64; ++lane) {
+                            const int u = u0 + lane / tv, v = bv * tv + lane % tv;
+                            act[lane] = u <= umax && v <= vcap && u * u + v * v <= rem;
+                            if (act[lane]) layer_cell(L, X, m, u, v, cols.data(), S, lc[lane]);
+                        }
+                        for (int lane = 0; lane < 64; ++lane) {
+                            if (!act[lane]) continue;
+                            const int u = u0 + lane / tv, v = bv * tv + lane % tv;
+                            cols[(size_t)u * S + v] = lc[lane].Nout;
+                            stN[m * SS + (size_t)u * S + v] = lc[lane].Nout;
+                            stdN[m * SS + (size_t)u * S + v] = lc[lane].dN;
+                        }
+                    }
+                }
+            }
+            // reverse
+            std::fill(abar.begin(), abar.end(), 0.0);
+            for (int m = Mx; m >= 1; --m) {
+                if (m >= 2)
+                    for (int u = 0; u <= Mcap; ++u)
+                        for (int v = 0; v <= Mcap; ++v)
+                            if (in_layer(m - 1, u, v)) {
+                                cols[(size_t)u * S + v] = stN[(m - 1) * SS + (size_t)u * S + v];
+                                cols_id[(size_t)u * S + v] = m - 1;
+                            }
+                const int rem = Rsq - m * m;
+                const int umax = std::min(std::min(m, L.ext_u), isqrt_floor(rem));
+                const int vcap = std::min(m, L.ext_v);
+                for (int bu = 0; bu <= umax / tu; ++bu) {
+                    const int u0 = bu * tu;
+                    const int vmax = std::min(vcap, isqrt_floor(rem - u0 * u0));
+                    for (int bv = 0; bv <= vmax / tv; ++bv) {
+                        LayerAdj la[64];
+                        bool act[64];
+                        for (int lane = 0; lane < 64; ++lane) {
+                            const int u = u0 + lane / tv, v = bv * tv + lane % tv;
+                            act[lane] = u <= umax && v <= vcap && u * u + v * v <= rem;
+                            if (!act[lane]) continue;
+                            if (m > 1) {
+                                const bool a0 = u > 0, a1 = u < m, b0 = v > 0, b1 = v < m;
+                                const bool need[4] = {a1 && b1, a0 && b1, a1 && b0, a0 && b0};
+                                for (int k = 0; k < 4; ++k)
+                                    if (need[k] && cols_id[(size_t)(u - (k & 1)) * S + v - (k >> 1)] != m - 1)
+                                        return -6;
+                            }
+                            layer_cell_adjoint(L, X, T.data(), m64.data(), tp, coef, m, u, v, cols.data(), S,
+                                               abar[(size_t)u * S + v], stdN[m * SS + (size_t)u * S + v], gb,
+                                               la[lane]);
+                        }
+                        for (int lane = 0; lane < 64; ++lane) {
+                            if (!act[lane]) continue;
+                            const int u = u0 + lane / tv, v = bv * tv + lane % tv;
+                            abar[(size_t)u * S + v] = 0.0;
+                        }
+                        for (int lane = 0; lane < 64; ++lane) {
+                            if (!act[lane]) continue;
+                            const int u = u0 + lane / tv, v = bv * tv + lane % tv;
+                            if (m >= 2)
+                                for (int k = 0; k < 4; ++k)
+                                    if (la[lane].Mbar[k] != 0.0)
+                                        abar[(size_t)(u - (k & 1)) * S + (v - (k >> 1))] += la[lane].Mbar[k];
+                            nb[la[lane].cp] += la[lane].nbar;
+                            nb_src += la[lane].nbar_src;
+                            qb += la[lane].qbar;
+                        }
+                    }
+                }
+            }
+        }
+        double nb1, q1;
+        source_cell_adjoint(T.data(), m64.data(), tp, sigma0, alpha, Q[s], nhi[cs], gbar[cs], &nb1, &q1);
+        nbar[cs] += nb_src + nb1;
+        qbar[s] += (qb + q1) / Q[s];
+    }
+    for (long i = 0; i < N; ++i)
+        for (long j = 0; j < N; ++j)
+            for (long k = 0; k < N; ++k) nbar[(i * N + j) * N + k] += nbT[(k * N + i) * N + j];
+    return 0;
+}
+
 // Reverse mode on the CPU with the kernels' per-cell adjoint: forward column
 // pass per piece storing every shell, then shells outermost first.  Outputs
 // dL/dn_HI (FP64, accumulated) and dL/dQ.
@@ -160,7 +429,7 @@ extern "C" int hc_raytrace_grad(int N, double alpha, double sigma0, int n, doubl
             const Piece pc = make_piece(type, p);
             const int row_cap = pc.n_oct * (Qmax + 1);
             std::vector<std::vector<int>> rs_sh(Qmax + 1), rb_sh(Qmax + 1);
-            std::vector<std::vector<double>> nout_sh(Qmax + 1), nbar_sh(Qmax + 1);
+            std::vector<std::vector<double>> nout_sh(Qmax + 1), nbar_sh(Qmax + 1), dn_sh(Qmax + 1);
             int ring_cap = 1;
             for (int q = 1; q <= Qmax; ++q) {
                 rs_sh[q].resize(row_cap + 1);
@@ -168,6 +437,7 @@ extern "C" int hc_raytrace_grad(int N, double alpha, double sigma0, int n, doubl
                 const int t = build_rows(pc, ex, Rsq, q, rs_sh[q].data(), rb_sh[q].data());
                 nout_sh[q].assign(t, 0.0);
                 nbar_sh[q].assign(t, 0.0);
+                dn_sh[q].assign(t, 0.0);
                 ring_cap = t > ring_cap ? t : ring_cap;
             }
             std::vector<double> ring(4 * (size_t)ring_cap, NAN);
@@ -210,6 +480,7 @@ extern "C" int hc_raytrace_grad(int N, double alpha, double sigma0, int n, doubl
                     CellOut co;
                     cell_update<false>(X, q, (int)g, row, rb_sh[q][row], co);
                     nout_sh[q][g] = co.Nout;
+                    dn_sh[q][g] = co.dN;
                 }
             }
             // reverse
@@ -222,7 +493,7 @@ extern "C" int hc_raytrace_grad(int N, double alpha, double sigma0, int n, doubl
                 for (size_t g = 0; g < nout_sh[q].size(); ++g) {
                     const int row = find_row(rs_sh[q].data(), nrows, (int)g);
                     CellAdj ca;
-                    cell_adjoint(X, q, (int)g, row, rb_sh[q][row], nbar_sh[q][g], gbar, ca);
+                    cell_adjoint(X, q, (int)g, row, rb_sh[q][row], nbar_sh[q][g], dn_sh[q][g], gbar, ca);
                     nbar[ca.cp] += ca.nbar;
                     nbar[cs] += ca.nbar_src;
                     qbar[s] += ca.qbar / Q[s];

@@ -29,8 +29,10 @@ def _loss_grad(g, wt):
     return wt / ((g + 1e-20) * math.log(10))
 
 
-def _gpu_backward(asora, w, table, gbar, **kw):
+def _gpu_backward(asora, w, table, gbar, sweep=3, **kw):
+    """sweep: 3 = large sources as layer pyramids (the default), 2 = shell pyramids."""
     ctx = asora.Asora(w.N, w.cell_cm, table.P, table.dP, table.lg_lo, table.lg_hi, **kw)
+    ctx.set_tuning(pyramid_sweep=sweep)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     dn, dx, dq = ctx.backward(t(w.n_H), t(w.x_HI), t(w.src.ijk), t(w.src.Q), t(w.src.R), t(gbar))
     ctx.check()
@@ -46,28 +48,30 @@ def _case(name, **kw):
     return w, g, wt
 
 
-def test_c4_against_oracle_reverse(asora, bb):
-    print("case c4 adjoint vs oracle", flush=True)
+@pytest.mark.parametrize("sweep", [3, 2], ids=["layers", "shells"])
+def test_c4_against_oracle_reverse(asora, bb, sweep):
+    print("case c4 adjoint vs oracle sweep", sweep, flush=True)
     w, g, wt = _case("c4")
     gbar = _loss_grad(g, wt)
     on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
                                       w.src.R, gbar)
-    gn, gx, gq = _gpu_backward(asora, w, bb, gbar)
+    gn, gx, gq = _gpu_backward(asora, w, bb, gbar, sweep=sweep)
     assert_grad_parity(gn, on, 1e-5, what="dL/dn_H")
     assert_grad_parity(gx, ox, 1e-5, what="dL/dx_HI")
     np.testing.assert_allclose(gq, oq, rtol=1e-5)
 
 
+@pytest.mark.parametrize("sweep", [3, 2], ids=["layers", "shells"])
 @pytest.mark.parametrize("tau_w,scalar", [(math.inf, False), (0.6, True)])
-def test_uneven_radii_all_piece_kinds(asora, bb, tau_w, scalar):
-    print("case adjoint uneven", tau_w, scalar, flush=True)
+def test_uneven_radii_all_piece_kinds(asora, bb, tau_w, scalar, sweep):
+    print("case adjoint uneven", tau_w, scalar, "sweep", sweep, flush=True)
     w, g, wt = _case("c2", N=40, n_src=24, R=(2.0, 38.0))
     g = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R,
                         tau_w=tau_w, reading=1 if scalar else 0)
     gbar = _loss_grad(g, wt)
     on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
                                       w.src.R, gbar, tau_w=tau_w, reading=1 if scalar else 0)
-    gn, gx, gq = _gpu_backward(asora, w, bb, gbar, tau_w=tau_w, halfpath_scalar=scalar)
+    gn, gx, gq = _gpu_backward(asora, w, bb, gbar, sweep=sweep, tau_w=tau_w, halfpath_scalar=scalar)
     assert_grad_parity(gn, on, 1e-5, what="dL/dn_H")
     assert_grad_parity(gx, ox, 1e-5, what="dL/dx_HI")
     np.testing.assert_allclose(gq, oq, rtol=1e-5)

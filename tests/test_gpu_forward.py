@@ -27,8 +27,14 @@ def bb():
     return oracle.blackbody_table()
 
 
-def _ctx(asora, w, table, **kw):
-    return asora.Asora(w.N, w.cell_cm, table.P, table.dP, table.lg_lo, table.lg_hi, **kw)
+def _ctx(asora, w, table, sweep=3, **kw):
+    """sweep: 3 = large sources as layer pyramids (the default), 2 = shell pyramids."""
+    ctx = asora.Asora(w.N, w.cell_cm, table.P, table.dP, table.lg_lo, table.lg_hi, **kw)
+    ctx.set_tuning(pyramid_sweep=sweep)
+    return ctx
+
+
+SWEEPS = pytest.mark.parametrize("sweep", [3, 2], ids=["layers", "shells"])
 
 
 def _dev(w):
@@ -52,33 +58,38 @@ def _orc(w, table, src=None, **kw):
     return oracle.raytrace(w.N, w.cell_cm, table, w.n_H, w.x_HI, src.ijk, src.Q, src.R, **kw)
 
 
+@SWEEPS
 @pytest.mark.parametrize("plain", [False, True])
-def test_c1_gamma_and_column(asora, bb, plain):
+def test_c1_gamma_and_column(asora, bb, plain, sweep):
     w = make_workload("c1")
-    print("case c1 plain", plain, flush=True)
+    print("case c1 plain", plain, "sweep", sweep, flush=True)
     o, ocd = _orc(w, bb, coldens=True)
-    g, cd = _gpu(_ctx(asora, w, bb), w, coldens=True, plain=plain)
+    ctx = _ctx(asora, w, bb, sweep=sweep)
+    ctx.set_tuning(R_whole=6.0, R_oct=10.0)   # R = 15: a pyramid source
+    g, cd = _gpu(ctx, w, coldens=True, plain=plain)
     assert_parity(g, o, TOL)
     assert_parity(cd, ocd, TOL, what="coldens")
     assert np.count_nonzero(cd) == 14147 - 1
 
 
+@SWEEPS
 @pytest.mark.parametrize("plain", [False, True])
-def test_uneven_radii_all_piece_kinds(asora, bb, plain):
+def test_uneven_radii_all_piece_kinds(asora, bb, plain, sweep):
     """Radii 2..40 cover the whole-source, octant and pyramid pieces."""
     w = make_workload("c2", N=48, n_src=40, R=(2.0, 40.0))
-    print("case uneven N=48 n_src=40 plain", plain, flush=True)
+    print("case uneven N=48 n_src=40 plain", plain, "sweep", sweep, flush=True)
     o = _orc(w, bb)
-    g = _gpu(_ctx(asora, w, bb), w, plain=plain)
+    g = _gpu(_ctx(asora, w, bb, sweep=sweep), w, plain=plain)
     assert_parity(g, o, TOL)
 
 
-def test_c2_subset(asora, bb):
+@SWEEPS
+def test_c2_subset(asora, bb, sweep):
     w = make_workload("c2")
     sub = w.src.subset(np.arange(60))
-    print("case c2 subset 60", flush=True)
+    print("case c2 subset 60 sweep", sweep, flush=True)
     o = _orc(w, bb, src=sub)
-    g = _gpu(_ctx(asora, w, bb), w, src=sub)
+    g = _gpu(_ctx(asora, w, bb, sweep=sweep), w, src=sub)
     assert_parity(g, o, TOL)
 
 
@@ -127,18 +138,23 @@ def test_grey_table_and_zero_density(asora):
     assert_parity(_gpu(_ctx(asora, w, bb), w), _orc(w, bb), TOL)
 
 
-def test_edges_odd_grid_wrap_and_clip(asora, bb):
+@SWEEPS
+def test_edges_odd_grid_wrap_and_clip(asora, bb, sweep):
     """Odd N, sources on the faces and corners of the box (periodic wrap),
     radii beyond half the box (extent clip), a duplicate source, R = 0."""
     w = make_workload("c2", N=19, n_src=6, R=(3.0, 17.0))
     w.src.ijk[:] = [[0, 0, 0], [18, 18, 18], [0, 9, 18], [5, 5, 5], [5, 5, 5], [12, 0, 7]]
     w.src.R[:] = [17.0, 9.5, 12.0, 4.0, 4.0, 0.0]
-    print("case edges", flush=True)
-    assert_parity(_gpu(_ctx(asora, w, bb), w), _orc(w, bb), TOL)
+    print("case edges sweep", sweep, flush=True)
+    assert_parity(_gpu(_ctx(asora, w, bb, sweep=sweep), w), _orc(w, bb), TOL)
+    # even grid, radius beyond the box
+    w = make_workload("c2", N=20, n_src=3, R=(12.0, 30.0))
+    w.src.ijk[0] = [19, 0, 19]
+    assert_parity(_gpu(_ctx(asora, w, bb, sweep=sweep), w), _orc(w, bb), TOL)
 
 
 def test_empty_and_accumulate(asora, bb):
-    w = make_workload("c2", N=20, n_src=3, R=(4.0, 8.0))
+    w = make_workload("c2", N=24, n_src=3, R=(4.0, 18.0))
     ctx = _ctx(asora, w, bb)
     nH, xH = _dev(w)
     e = torch.empty(0, 3, dtype=torch.int32)

@@ -22,35 +22,63 @@ def bb():
     return oracle.blackbody_table()
 
 
-@pytest.mark.parametrize("type_force", [0, 1, 2])
-def test_c1_all_piece_kinds(bb, type_force):
+# shell piece kinds 0, 1, 2 and the layer pyramids with both tile widths
+KINDS = [dict(type_force=0), dict(type_force=1), dict(type_force=2), dict(layer_tv=8),
+         dict(layer_tv=16)]
+KIND_IDS = ["whole", "octants", "shell-pyramids", "layers-tv8", "layers-tv16"]
+
+
+@pytest.mark.parametrize("kind", KINDS, ids=KIND_IDS)
+def test_c1_all_piece_kinds(bb, kind):
     w = make_workload("c1")
     o, ocd = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R, coldens=True)
     g, cd = hostsweep.raytrace(w.N, w.cell_cm, oracle.SIGMA0, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
-                               w.src.R, type_force=type_force, coldens=True)
+                               w.src.R, coldens=True, **kind)
     assert_parity(g, o, TOL)
     assert_parity(cd, ocd, TOL, what="coldens")
     assert np.count_nonzero(cd) == 14147 - 1
 
 
-@pytest.mark.parametrize("type_force", [-1, 0, 1, 2])
+@pytest.mark.parametrize("kind", [dict(type_force=-1)] + KINDS, ids=["by-radius"] + KIND_IDS)
 @pytest.mark.parametrize("tau_w,reading", [(0.6, 0), (math.inf, 0), (0.6, 1)])
-def test_lognormal_sources(bb, type_force, tau_w, reading):
+def test_lognormal_sources(bb, kind, tau_w, reading):
     w = make_workload("c2", N=36, n_src=9, R=(3.0, 21.0))
     o = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R,
                         tau_w=tau_w, reading=reading)
     g = hostsweep.raytrace(w.N, w.cell_cm, oracle.SIGMA0, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
-                           w.src.R, tau_w=tau_w, reading=reading, type_force=type_force)
+                           w.src.R, tau_w=tau_w, reading=reading, **kind)
     assert_parity(g, o, TOL)
+
+
+@pytest.mark.parametrize("tv", [8, 16])
+def test_layers_ionized_medium_and_column(bb, tv):
+    """Mostly ionized medium (every cell carries a rate) and the column
+    density output of a single source through the layer pyramids, with a
+    source near the box corner so that offsets wrap."""
+    w = make_workload("c2", N=40, n_src=1, R=(19.0, 19.0))
+    xH = np.full_like(w.x_HI, 1e-3)
+    ijk = np.array([[1, 38, 39]], np.int32)
+    o, ocd = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, xH, ijk, w.src.Q, w.src.R, coldens=True)
+    g, cd = hostsweep.raytrace(w.N, w.cell_cm, oracle.SIGMA0, bb, w.n_H, xH, ijk, w.src.Q,
+                               w.src.R, coldens=True, layer_tv=tv)
+    assert_parity(g, o, TOL)
+    assert_parity(cd, ocd, TOL, what="coldens")
+    assert np.count_nonzero(g) > 0.9 * np.count_nonzero(o)
 
 
 def test_odd_grid_large_radius_extent_clip(bb):
     """R larger than the box: the periodic extent clips the ball (odd N)."""
     w = make_workload("c2", N=21, n_src=3, R=(14.0, 19.0))
     o = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
-    for tf in (0, 1, 2):
+    for kind in KINDS:
         g = hostsweep.raytrace(w.N, w.cell_cm, oracle.SIGMA0, bb, w.n_H, w.x_HI, w.src.ijk,
-                               w.src.Q, w.src.R, type_force=tf)
+                               w.src.Q, w.src.R, **kind)
+        assert_parity(g, o, TOL)
+    w = make_workload("c2", N=20, n_src=3, R=(12.0, 30.0))   # even grid, R beyond the box
+    o = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
+    for kind in KINDS[2:]:
+        g = hostsweep.raytrace(w.N, w.cell_cm, oracle.SIGMA0, bb, w.n_H, w.x_HI, w.src.ijk,
+                               w.src.Q, w.src.R, **kind)
         assert_parity(g, o, TOL)
 
 
@@ -64,6 +92,9 @@ def test_grey_and_thin(bb):
     thin = (w.n_H * 1e-9).astype(np.float32)        # tau per cell ~ 3e-6
     o = oracle.raytrace(w.N, w.cell_cm, bb, thin, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
     g = hostsweep.raytrace(w.N, w.cell_cm, oracle.SIGMA0, bb, thin, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
+    assert_parity(g, o, TOL)
+    g = hostsweep.raytrace(w.N, w.cell_cm, oracle.SIGMA0, bb, thin, w.x_HI, w.src.ijk, w.src.Q, w.src.R,
+                           layer_tv=16)
     assert_parity(g, o, TOL)
     zero = np.zeros_like(w.n_H)
     o = oracle.raytrace(w.N, w.cell_cm, bb, zero, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
@@ -126,9 +157,9 @@ def test_row_enumeration_matches_brute_force(N):
                 assert set(got) == want          # ghosts duplicate cells, nothing missing or extra
 
 
-@pytest.mark.parametrize("type_force", [-1, 0, 1, 2])
+@pytest.mark.parametrize("kind", [dict(type_force=-1)] + KINDS, ids=["by-radius"] + KIND_IDS)
 @pytest.mark.parametrize("tau_w,reading", [(0.6, 0), (math.inf, 0), (0.6, 1)])
-def test_adjoint_matches_oracle_reverse(bb, type_force, tau_w, reading):
+def test_adjoint_matches_oracle_reverse(bb, kind, tau_w, reading):
     """The library's per-cell adjoint, driven serially over the reversed
     shells, against the oracle's reverse mode for L = sum w log10(Gamma+1e-20)."""
     w = make_workload("c4", N=24, n_src=6, R=(3.0, 11.0))
@@ -140,8 +171,28 @@ def test_adjoint_matches_oracle_reverse(bb, type_force, tau_w, reading):
                                       w.src.R, gbar, tau_w=tau_w, reading=reading)
     hn, hx, hq = hostsweep.raytrace_grad(w.N, w.cell_cm, oracle.SIGMA0, bb, w.n_H, w.x_HI,
                                          w.src.ijk, w.src.Q, w.src.R, gbar, tau_w=tau_w,
-                                         reading=reading, type_force=type_force)
+                                         reading=reading, **kind)
     from tests.parity import assert_grad_parity
     assert_grad_parity(hn, on, 1e-5, what="dL/dn_H")
     assert_grad_parity(hx, ox, 1e-5, what="dL/dx_HI")
     np.testing.assert_allclose(hq, oq, rtol=1e-6)
+
+
+@pytest.mark.parametrize("tv", [8, 16])
+def test_layer_adjoint_extent_clip_and_wrap(bb, tv):
+    """Layer adjoint with radii beyond the box (extent clip, even and odd N)
+    and sources on the box faces, against the oracle's reverse mode."""
+    for N, ijk in ((15, [[0, 7, 14], [3, 3, 3]]), (16, [[15, 0, 15], [8, 8, 0]])):
+        w = make_workload("c4", N=N, n_src=2, R=(9.0, 13.0))
+        w.src.ijk[:] = ijk
+        g = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
+        wt = np.random.default_rng(2).standard_normal(g.shape)
+        gbar = wt / ((g + 1e-20) * math.log(10))
+        on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
+                                          w.src.R, gbar)
+        hn, hx, hq = hostsweep.raytrace_grad(w.N, w.cell_cm, oracle.SIGMA0, bb, w.n_H, w.x_HI,
+                                             w.src.ijk, w.src.Q, w.src.R, gbar, layer_tv=tv)
+        from tests.parity import assert_grad_parity
+        assert_grad_parity(hn, on, 1e-5, what="dL/dn_H")
+        assert_grad_parity(hx, ox, 1e-5, what="dL/dx_HI")
+        np.testing.assert_allclose(hq, oq, rtol=1e-6)
