@@ -40,7 +40,9 @@ FWD_BYTES_PER_SV = 16.0   # n_H + x_HI reads (2 x FP32), Gamma read-modify-write
 ADJ_BYTES_PER_SV = 32.0   # n_H + x_HI (2 x FP32), dL/dGamma (FP64), dL/dn_HI read-modify-write (2 x FP64)
 KERNEL_SOURCES = ["paper_2311_01492_amd/csrc/asora_dev.h", "paper_2311_01492_amd/csrc/asora_fwd.hip",
                   "paper_2311_01492_amd/csrc/asora_adj.hip"]
-KERNELS = {"fwd": "fwd_wave", "adj": "adj_wave"}
+# sweep kernels of each pass (one dispatch per piece kind up to the largest
+# radius; the kinds without sources return at once)
+KERNELS = {"fwd": ("fwd_wave", "fwd_layer"), "adj": ("adj_wave", "adj_layer")}
 
 WORKLOADS = {
     "c2": dict(name="c2", kw={}, plain_src=1000,
@@ -111,21 +113,23 @@ def reduce_pmc(directory: str, workload: str):
            "calibration": {"copy_bytes": copy_bytes, "fetch_kib": cf_kib, "write_kib": cw_kib,
                            "read_factor": f_read, "write_factor": f_write},
            "kernels": {}}
-    for key, sub in KERNELS.items():
-        if _per_dispatch(fetch, sub, "FETCH_SIZE") is None or _per_dispatch(write, sub, "WRITE_SIZE") is None:
+    for key, subs in KERNELS.items():
+        match = lambda name: any(sub + "<" in name for sub in subs)
+        if not any(match(n) for n in fetch) or not any(match(n) for n in write):
             continue
-        # one dispatch per piece kind up to the largest radius in each call (the
-        # kinds without sources return at once), so the per-call sum over the
-        # kinds is what one call moves; kind 0 is launched once per call
-        nf = sum(len(c.get("FETCH_SIZE", [])) for n, c in fetch.items() if sub in n)
-        calls = sum(len(c.get("FETCH_SIZE", [])) for n, c in fetch.items() if sub + "<0>" in n)
-        calls_w = sum(len(c.get("WRITE_SIZE", [])) for n, c in write.items() if sub + "<0>" in n)
+        # kind 0 (fwd_wave<0> / adj_wave<0>) is launched once per call, so its
+        # dispatch count is the number of calls; the per-call sum over the kinds
+        # is what one call moves
+        first = subs[0] + "<0>"
+        nf = sum(len(c.get("FETCH_SIZE", [])) for n, c in fetch.items() if match(n))
+        calls = sum(len(c.get("FETCH_SIZE", [])) for n, c in fetch.items() if first in n)
+        calls_w = sum(len(c.get("WRITE_SIZE", [])) for n, c in write.items() if first in n)
         if calls == 0 or calls != calls_w:
-            raise SystemExit(f"{sub}: {calls} / {calls_w} calls in the two counter runs")
-        fsum = sum(v for n, c in fetch.items() if sub in n for v in c.get("FETCH_SIZE", []))
-        wsum = sum(v for n, c in write.items() if sub in n for v in c.get("WRITE_SIZE", []))
+            raise SystemExit(f"{key}: {calls} / {calls_w} calls in the two counter runs")
+        fsum = sum(v for n, c in fetch.items() if match(n) for v in c.get("FETCH_SIZE", []))
+        wsum = sum(v for n, c in write.items() if match(n) for v in c.get("WRITE_SIZE", []))
         res["kernels"][key] = {
-            "kernel": sub,
+            "kernel": "+".join(subs),
             "fetch_bytes_per_call": fsum / calls * 1024.0 * f_read,
             "write_bytes_per_call": wsum / calls * 1024.0 * f_write,
             "hbm_bytes_per_call": (fsum * f_read + wsum * f_write) / calls * 1024.0,
@@ -270,6 +274,10 @@ def main():
         if pmc.get("kernel_sha") == kernel_sha() and pmc.get("workload") == args.workload:
             traffic = {k: v.get("hbm_bytes_per_call") for k, v in pmc.get("kernels", {}).items()}
 
+    # the dominant sweep kernel: layer pyramids (sweep 3) or shell pyramids
+    big = ctx.get_tuning()[3] == 3 and R_max > ctx.get_tuning()[1]
+    kname = {"fwd": "fwd_layer" if big else "fwd_wave", "adj": "adj_layer" if big else "adj_wave"}
+
     def roof(bytes_per_sv, sweep_ms, kernel, key):
         achieved = bytes_per_sv * work / (sweep_ms * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -285,9 +293,9 @@ def main():
                    "n_sources": len(w.src), "source_voxels": work, "seed": w.seed,
                    "step": "batched forward + adjoint (recompute)"},
         # the adjoint sweep dominates the step
-        "roofline": roof(ADJ_BYTES_PER_SV, adj_sweep_ms, "adj_wave", "adj"),
+        "roofline": roof(ADJ_BYTES_PER_SV, adj_sweep_ms, kname["adj"], "adj"),
         "fwd": {"ns_per_source_voxel": fwd_ms * 1e6 / work, "ms_per_call": fwd_ms,
-                "roofline": roof(FWD_BYTES_PER_SV, fwd_sweep_ms, "fwd_wave", "fwd")},
+                "roofline": roof(FWD_BYTES_PER_SV, fwd_sweep_ms, kname["fwd"], "fwd")},
         "adjoint": {"ns_per_source_voxel": (ms - fwd_ms) * 1e6 / work,
                     "sweep_ms": adj_sweep_ms, "call_ms": adj_call_ms},
         "fwd_call_ms_in_step": fwd_call_ms,
