@@ -60,6 +60,21 @@ typedef enum {
 #define ASORA_PROFILE    0x4u  /* record HIP events around the sweep kernels and the
                                   whole call on `stream`; read with asora_profile or
                                   asora_profile_read                                */
+#define ASORA_STORE      0x8u  /* forward: keep the column record of every pyramid
+                                  piece (sources above R_oct, swept in layers) in
+                                  library-owned device memory, if it fits the store
+                                  budget (asora_set_store_budget); otherwise nothing
+                                  is kept (asora_store_info tells which).  backward:
+                                  take the columns and the cells with a rate from
+                                  those records instead of re-sweeping the pyramids
+                                  forward, provided the most recent forward call with
+                                  ASORA_STORE kept them for the same n_H, x_HI,
+                                  src_ijk, src_Q, src_R pointers, n_src and R_max and
+                                  the tuning has not changed since; otherwise the
+                                  adjoint recomputes them.  The caller guarantees that
+                                  the contents of those buffers did not change in
+                                  between.  Whole-source and octant pieces are always
+                                  recomputed.  Results are the same either way.      */
 #define ASORA_PLAIN      0x2u  /* one kernel launch per source, in input order: the
                                   unbatched baseline form (Section 3.3, one block per
                                   source).  Default: all sources in one persistent
@@ -131,7 +146,7 @@ asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, double sigma
  *                ASORA_ACCUMULATE.  Summation runs in FP64 and is rounded once.
  *   coldens_in   device, N^3 doubles or NULL.  Only with n_src == 1: receives
  *                N_in (cm^-2) for every cell of the ball, 0 elsewhere.
- *   flags        ASORA_ACCUMULATE | ASORA_PLAIN.
+ *   flags        ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_PROFILE | ASORA_STORE.
  *   stream       hipStream_t.
  */
 asora_status asora_raytrace(asora_ctx *ctx, const float *n_H, const float *x_HI, int64_t n_src,
@@ -146,10 +161,10 @@ asora_status asora_raytrace(asora_ctx *ctx, const float *n_H, const float *x_HI,
  * with the same inputs (reverse mode through eq. sugg, the in-cell column
  * and the interpolation of eq. interp, with the optical-depth weights
  * differentiated as functions of the neighbour columns).  For every source
- * piece the exit columns are first recomputed shell by shell into scratch
- * memory, then the shells are swept from the outermost inward and every
- * cell pushes the adjoint of its entry column to its neighbours, so no
- * forward state is kept between the calls.
+ * piece the exit columns are first recomputed into scratch memory (or, with
+ * ASORA_STORE, taken from the records the forward kept), then the shells or
+ * layers are swept from the outermost inward and every cell pushes the
+ * adjoint of its entry column to its neighbours.
  *
  *   n_H, x_HI, n_src, src_ijk, src_Q, src_R, R_max: as for asora_raytrace.
  *   dL_dgamma    device, N^3 doubles (FP64: a cell's gradient can be a sum of
@@ -160,7 +175,8 @@ asora_status asora_raytrace(asora_ctx *ctx, const float *n_H, const float *x_HI,
  *   dL_dQ        device, n_src doubles, output (overwritten unless
  *                ASORA_ACCUMULATE).
  *   flags        ASORA_ACCUMULATE | ASORA_PROFILE (asora_profile then reports
- *                the reverse sweep as sweep_ms).
+ *                the reverse sweep as sweep_ms) | ASORA_STORE (use the column
+ *                records kept by the forward, see ASORA_STORE).
  * Scratch: about 16 N^3 bytes more than the forward, plus the stored columns
  * of the pieces in flight (allocated at the first call, grown on demand).
  * The derivative of the rate is taken on the interpolant as it is (a cubic
@@ -198,14 +214,33 @@ asora_status asora_table_grey(int32_t n, double lg_lo, double lg_hi, double *P, 
 asora_status asora_check(asora_ctx *ctx, void *stream);
 
 /*
+ * asora_store_info -- state of the kept column records: *valid = 1 if the
+ * most recent forward call with ASORA_STORE kept them; *bytes_needed = what
+ * that call needed (0 if it swept no pyramid pieces); *bytes_allocated = the
+ * device memory held for them.  Any pointer may be NULL.
+ */
+asora_status asora_store_info(const asora_ctx *ctx, int32_t *valid, uint64_t *bytes_needed,
+                              uint64_t *bytes_allocated);
+
+/*
+ * asora_set_store_budget -- largest number of bytes of device memory the kept
+ * column records may take (n_src x 24 x one pyramid's record, about 36 bytes
+ * per cell of the largest pyramid).  0 (the default) means half of the free
+ * device memory at the time of the forward call, plus what is already held.
+ * A forward call with ASORA_STORE that needs more keeps nothing.
+ */
+asora_status asora_set_store_budget(asora_ctx *ctx, uint64_t bytes);
+
+/*
  * asora_set_tuning -- scheduling parameters of the sweep (results do not
  * depend on them beyond the order of floating-point sums).  Sources with
  * R <= R_whole are swept whole by one wave; R_whole < R <= R_oct as eight
  * closed octants; larger R as 24 octant x dominant-axis pyramids (cells on
  * shared planes are computed by each piece and owned by one).  Those
  * pyramids are swept either shell by shell in L1 distance (pyramid_sweep 2)
- * or layer by layer along their dominant axis with memory-contiguous tiles
- * (pyramid_sweep 3, the default), in the forward and in the adjoint.
+ * or layer by layer along their dominant axis, each layer in chunks of 64
+ * memory-contiguous cells (pyramid_sweep 3, the default), in the forward and
+ * in the adjoint.
  * max_waves (1..16) caps the waves per work-group that share one LDS copy of
  * the table.  Values <= 0 keep the current setting.  ASORA_EINVAL if
  * R_oct < R_whole, max_waves > 16 or pyramid_sweep is not 0, 2 or 3.

@@ -21,10 +21,10 @@ import numpy as np
 import torch  # loads the HIP runtime that libasora.so binds to
 
 __all__ = ["Asora", "AsoraError", "raytrace", "table_blackbody", "table_grey", "lib_path",
-           "SIGMA0", "ACCUMULATE", "PLAIN", "HALFPATH_SCALAR"]
+           "SIGMA0", "ACCUMULATE", "PLAIN", "STORE", "HALFPATH_SCALAR"]
 
 SIGMA0 = 6.3e-18          # HI cross-section at 13.6 eV, cm^2
-ACCUMULATE, PLAIN, PROFILE = 0x1, 0x2, 0x4
+ACCUMULATE, PLAIN, PROFILE, STORE = 0x1, 0x2, 0x4, 0x8
 HALFPATH_SCALAR = 0x1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -61,6 +61,11 @@ _lib.asora_set_tuning.argtypes = [_p, _c_f, _c_f, _c_int, _c_int]
 _lib.asora_get_tuning.restype = _c_int
 _lib.asora_get_tuning.argtypes = [_p, ctypes.POINTER(_c_f), ctypes.POINTER(_c_f), ctypes.POINTER(_c_int),
                                   ctypes.POINTER(_c_int)]
+_lib.asora_store_info.restype = _c_int
+_lib.asora_store_info.argtypes = [_p, ctypes.POINTER(_c_int), ctypes.POINTER(ctypes.c_uint64),
+                                  ctypes.POINTER(ctypes.c_uint64)]
+_lib.asora_set_store_budget.restype = _c_int
+_lib.asora_set_store_budget.argtypes = [_p, ctypes.c_uint64]
 _lib.asora_last_error.restype = ctypes.c_char_p
 _lib.asora_last_error.argtypes = [_p]
 _lib.asora_free.restype = _c_int
@@ -164,14 +169,16 @@ class Asora:
         return ijk, Q, R, float(R_max), n
 
     def raytrace(self, n_H, x_HI, ijk, Q, R=None, R_max=None, plain=False, coldens=False,
-                 out=None, accumulate=False, profile=False, stream=None):
+                 out=None, accumulate=False, profile=False, store=False, stream=None):
         """Gamma (float32 cuda, N^3) for the sources; with coldens=True (one
-        source) also the entry column N_in (float64, N^3)."""
+        source) also the entry column N_in (float64, N^3).  store=True keeps the
+        pyramids' column records for a following backward(store=True)."""
         ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
         dev = n_H.device
         gamma = out if out is not None else torch.empty(self.N ** 3, dtype=torch.float32, device=dev)
         cd = torch.empty(self.N ** 3, dtype=torch.float64, device=dev) if coldens else None
         flags = (PLAIN if plain else 0) | (ACCUMULATE if accumulate else 0) | (PROFILE if profile else 0)
+        flags |= STORE if store else 0
         st = _lib.asora_raytrace(self._h, _dptr(n_H), _dptr(x_HI), n, _dptr(ijk), _dptr(Q),
                                  _dptr(R), R_max, _dptr(gamma), _dptr(cd), flags,
                                  _stream_ptr(stream))
@@ -180,9 +187,11 @@ class Asora:
         return (gamma.view(shape), cd.view(shape)) if coldens else gamma.view(shape)
 
     def backward(self, n_H, x_HI, ijk, Q, R, dL_dgamma, R_max=None, profile=False, stream=None,
-                 out=None):
+                 out=None, store=False):
         """(dL/dn_H, dL/dx_HI, dL/dQ) for the given dL/dgamma (converted to FP64).
-        out: optional (dn [N^3 float32], dx [N^3 float32], dq [n float64]) to fill."""
+        out: optional (dn [N^3 float32], dx [N^3 float32], dq [n float64]) to fill.
+        store=True: use the column records kept by raytrace(store=True) with the
+        same tensors (which must not have changed since), else recompute."""
         ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
         dev = n_H.device
         g = dL_dgamma.to(dev, torch.float64).contiguous()
@@ -198,7 +207,8 @@ class Asora:
             dq = torch.empty(n, dtype=torch.float64, device=dev)
         st = _lib.asora_raytrace_backward(self._h, _dptr(n_H), _dptr(x_HI), n, _dptr(ijk),
                                           _dptr(Q), _dptr(R), R_max, _dptr(g), _dptr(dn),
-                                          _dptr(dx), _dptr(dq), PROFILE if profile else 0,
+                                          _dptr(dx), _dptr(dq),
+                                          (PROFILE if profile else 0) | (STORE if store else 0),
                                           _stream_ptr(stream))
         _raise(st, self._h)
         shape = (self.N,) * 3
@@ -220,6 +230,17 @@ class Asora:
                                        _np_ptr(b)), self._h)
         return list(zip(a[:n.value].tolist(), b[:n.value].tolist()))
 
+    def store_info(self):
+        """(kept, bytes_needed, bytes_allocated) of the column records."""
+        v, need, alloc = _c_int(), ctypes.c_uint64(), ctypes.c_uint64()
+        _raise(_lib.asora_store_info(self._h, ctypes.byref(v), ctypes.byref(need), ctypes.byref(alloc)),
+               self._h)
+        return bool(v.value), need.value, alloc.value
+
+    def set_store_budget(self, nbytes: int):
+        """Largest device memory for kept column records (0: half the free memory)."""
+        _raise(_lib.asora_set_store_budget(self._h, int(nbytes)), self._h)
+
     def set_tuning(self, R_whole=0.0, R_oct=0.0, max_waves=0, pyramid_sweep=0):
         """Scheduling parameters; pyramid_sweep 2 = shells, 3 = layers (forward)."""
         _raise(_lib.asora_set_tuning(self._h, float(R_whole), float(R_oct), int(max_waves),
@@ -238,20 +259,33 @@ class Asora:
 
 class _RaytraceFn(torch.autograd.Function):
     @staticmethod
-    def forward(fctx, ctx: Asora, n_H, x_HI, ijk, Q, R, R_max):
-        fctx.save_for_backward(n_H, x_HI, ijk, Q, R if R is not None else torch.empty(0))
-        fctx.asora, fctx.R_max, fctx.has_R = ctx, R_max, R is not None
-        return ctx.raytrace(n_H.detach(), x_HI.detach(), ijk, Q.detach(), R, R_max=R_max)
+    def forward(fctx, ctx: Asora, n_H, x_HI, ijk, Q, R, R_max, store):
+        # the library reads the device buffers as given: pass the very tensors
+        # that backward will pass, so that kept column records match them
+        ijk, Qc, Rc, R_max, _ = ctx._prep(n_H, x_HI, ijk, Q.detach(), R, R_max)
+        fctx.save_for_backward(n_H, x_HI, ijk, Qc, Rc if Rc is not None else torch.empty(0))
+        fctx.asora, fctx.R_max, fctx.has_R = ctx, R_max, Rc is not None
+        fctx.q_dtype = Q.dtype
+        out = ctx.raytrace(n_H.detach(), x_HI.detach(), ijk, Qc, Rc, R_max=R_max, store=store)
+        # kept records belong to this call until another forward keeps its own
+        fctx.keep_gen = -1
+        if store:
+            ctx._keep_gen = getattr(ctx, "_keep_gen", 0) + 1
+            fctx.keep_gen = ctx._keep_gen
+        return out
 
     @staticmethod
     def backward(fctx, g):
         n_H, x_HI, ijk, Q, R = fctx.saved_tensors
         R = R if fctx.has_R else None
-        dn, dx, dq = fctx.asora.backward(n_H.detach(), x_HI.detach(), ijk, Q.detach(), R,
-                                         g.double().contiguous(), R_max=fctx.R_max)
-        return None, dn, dx, None, dq.to(Q.dtype), None, None
+        kept = fctx.keep_gen == getattr(fctx.asora, "_keep_gen", 0)
+        dn, dx, dq = fctx.asora.backward(n_H.detach(), x_HI.detach(), ijk, Q, R,
+                                         g.double().contiguous(), R_max=fctx.R_max, store=kept)
+        return None, dn, dx, None, dq.to(fctx.q_dtype), None, None, None
 
 
-def raytrace(ctx: Asora, n_H, x_HI, ijk, Q, R=None, R_max=None):
-    """Differentiable Gamma(n_H, x_HI, Q): backward runs the adjoint kernels."""
-    return _RaytraceFn.apply(ctx, n_H, x_HI, ijk, Q, R, R_max)
+def raytrace(ctx: Asora, n_H, x_HI, ijk, Q, R=None, R_max=None, store=True):
+    """Differentiable Gamma(n_H, x_HI, Q): backward runs the adjoint kernels.
+    store=True keeps the forward's column records for the backward when they
+    fit the store budget (otherwise the backward recomputes them)."""
+    return _RaytraceFn.apply(ctx, n_H, x_HI, ijk, Q, R, R_max, store)

@@ -48,6 +48,9 @@ struct AdjArgs {
     const double *gbar_T;
     double *nbar_T;
     int Mcap, lay_S;         // largest layer index, row stride of the layer buffers
+    const char *kept;        // column records kept by the forward (per source and pyramid), or NULL
+    size_t rec_piece_bytes;  // bytes of one pyramid's column record
+    long rec_cap;            // cells (and listed cells) per pyramid record
 };
 
 template <int TYPE>
@@ -208,20 +211,39 @@ __global__ __launch_bounds__(512) void adj_wave(AdjArgs A)
 }
 
 // ---- layer pieces --------------------------------------------------------
-// One wave per pyramid.  Forward pass: the columns layer by layer, in place in
-// the LDS buffer `cols` (as in the forward kernel), every layer's exit and
-// in-cell columns stored to the wave's scratch at [m][u][v].  Reverse pass,
-// from the outermost layer inward: layer m - 1's exit columns come back from
-// the scratch into `cols`; the cells of layer m, in increasing u band then
-// increasing v (so that every slot they push to belongs to an already
-// finished cell), take their exit-column adjoint from `abar`, clear it, and
-// add their entry-column adjoint to the slots of their layer m - 1 neighbours
-// with LDS atomics.
-template <int TV>
-__device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *cols, double *abar,
-                                    double *store, int src, int p, int lane)
+// One wave per pyramid, in three passes.
+//  (F) Unless the forward kept the pyramid's column record: the columns layer
+//      by layer, in place in the LDS buffer `cols` as in the forward kernel,
+//      every exit column written to the record in the wave's scratch, and the
+//      owned cells whose entry optical depth lies inside the table (the cells
+//      with a rate) listed with their optical depths.
+//  (G) The listed cells, 64 at a time with every lane busy: the rate's
+//      derivatives (FP64), its in-cell term of dL/dn_HI, its share of dL/dQ,
+//      and its entry-column term g_in, kept per listed cell.
+//  (R) Layers from the outermost inward: layer m - 1's exit columns come back
+//      from the record into `cols`; the g_in of layer m's listed cells are
+//      added to their adjoint slots in `abar`; then layer m's rectangle in
+//      chunks from the first to the last: every cell takes and clears its
+//      slot (the adjoint of its exit column, which flows into its entry
+//      column and its in-cell column alike), adds alpha ds times it to
+//      dL/dn_HI and pushes it through the interpolation weights to the slots
+//      of its layer m - 1 neighbours with LDS atomics.  A neighbour slot
+//      precedes the pushing cell in (u, v) order, so it was already taken in
+//      this layer.  Chunks whose slots are all zero (cells that no listed
+//      cell depends on) skip the arithmetic.
+__device__ __forceinline__ void wave_sync_global()
 {
-    constexpr int TU = 64 / TV;
+    // this wave's global stores complete before its later global loads by
+    // other lanes
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <bool KEPT>
+__device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *cols, double *abar,
+                                    int *litoff, char *scratch, int src, int p, int lane)
+{
     const int N = A.N;
     const int si = A.ijk[3 * src], sj = A.ijk[3 * src + 1], sk = A.ijk[3 * src + 2];
     const float R = A.R ? A.R[src] : A.R_cap;
@@ -247,81 +269,111 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
     double *nbar = L.transposed ? A.nbar_T : A.nbar;
     const double coef = Q * A.coef_unit;
     const int S = A.lay_S;
-    const size_t SS = (size_t)(A.Mcap + 1) * S;       // doubles per stored layer
-    double *st_N = store, *st_dN = store + (size_t)(A.Mcap + 1) * SS;
+    const LayerRecord rec = layer_record_at(
+        KEPT ? (char *)A.kept + ((size_t)src * 24 + p) * A.rec_piece_bytes : scratch, A.rec_cap);
+    double *gin = (double *)(scratch + A.rec_piece_bytes);   // g_in per listed cell
     const int Mx = min(isqrt_floor(Rsq), L.ext_d);
 
-    // ---- forward: columns of every layer, kept in place and stored
-    for (int k = lane; k < (Mx + 1) * S; k += 64) cols[k] = 0.0;
-    wave_sync();
-    for (int m = 1; m <= Mx; ++m) {
-        const int rem = Rsq - m * m;
-        const int umax = min(min(m, L.ext_u), isqrt_floor(rem));
-        const int vcap = min(m, L.ext_v);
-        for (int tu = umax / TU; tu >= 0; --tu) {
-            const int u0 = tu * TU;
-            const int vmax = min(vcap, isqrt_floor(rem - u0 * u0));
-            for (int tv = vmax / TV; tv >= 0; --tv) {
-                const int u = u0 + lane / TV, v = tv * TV + lane % TV;
-                const bool act = u <= umax && v <= vcap && u * u + v * v <= rem;
+    // ---- (F)
+    long off = 0;
+    if (!KEPT) {
+        int tail = 0;
+        for (int m = 1; m <= Mx; ++m) {
+            if (lane == 0) litoff[m] = tail;
+            const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
+            for (int c = (r.total + 63) / 64 - 1; c >= 0; --c) {
+                const int g = c * 64 + lane;
+                int u, v;
+                const bool act = rect_cell(r, g, u, v);
                 LayerCell lc;
+                lc.Nin = 0.0;
+                lc.owned = false;
                 if (act) layer_cell(L, X, m, u, v, cols, S, lc);
                 wave_sync();
+                bool lit = false;
                 if (act) {
                     cols[u * S + v] = lc.Nout;
-                    st_N[m * SS + u * S + v] = lc.Nout;
-                    st_dN[m * SS + u * S + v] = lc.dN;
+                    rec.N[off + g] = lc.Nout;
+                    lit = lc.owned && A.sigma0 * lc.Nin < A.tp.tau_hi;
                 }
+                const uint64_t mask = __ballot(lit);
+                if (lit) {
+                    const int k = tail + (int)__builtin_amdgcn_mbcnt_hi(
+                                             (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                    rec.ta[k] = A.sigma0 * lc.Nin;
+                    rec.dt[k] = A.sigma0 * lc.dN;
+                    rec.cp[k] = lc.cp;
+                    rec.pm[k] = (u * S + v) | (m << 16);
+                    rec.r2[k] = lc.r2;
+                }
+                tail += __popcll(mask);
                 wave_sync();
             }
+            off += r.total;
+        }
+        if (lane == 0) litoff[Mx + 1] = tail;
+    } else {
+        for (int k = 1 + lane; k <= Mx + 1; k += 64) litoff[k] = rec.litoff[k];
+        for (int m = 1; m <= Mx; ++m) off += layer_rect(L.ext_u, L.ext_v, Rsq, m).total;
+    }
+    wave_sync_global();
+    const int nrec = litoff[Mx + 1];
+
+    // ---- (G)
+    double nb_src = 0.0, qb = 0.0;
+    for (int k0 = 0; k0 < nrec; k0 += 64) {
+        const int k = k0 + lane;
+        if (k < nrec) {
+            const uint32_t cp = rec.cp[k];
+            const double gb = gbar[cp];
+            double gi = 0.0;
+            if (gb != 0.0) {
+                double ne, gG;
+                record_rate_adjoint(T, A.m64, A.tp, A.sigma0, A.alpha, coef, rec.ta[k], rec.dt[k], rec.r2[k],
+                                    rec.pm[k] >> 16, gb, &gi, &ne, &gG);
+                if (ne != 0.0) unsafeAtomicAdd(&nbar[cp], ne);
+                qb += gG;
+            }
+            gin[k] = gi;
         }
     }
-
-    // ---- reverse
     for (int k = lane; k < (Mx + 1) * S; k += 64) abar[k] = 0.0;
-    double nb_src = 0.0, qb = 0.0;
+    wave_sync_global();
+
+    // ---- (R)
     for (int m = Mx; m >= 1; --m) {
-        if (m >= 2) {   // exit columns of layer m - 1 back into cols
-            const int mp = m - 1, remp = Rsq - mp * mp;
-            const int umaxp = min(min(mp, L.ext_u), isqrt_floor(remp));
-            const int vcapp = min(mp, L.ext_v);
-            for (int tu = 0; tu <= umaxp / TU; ++tu) {
-                const int u0 = tu * TU;
-                const int vmax = min(vcapp, isqrt_floor(remp - u0 * u0));
-                for (int tv = 0; tv <= vmax / TV; ++tv) {
-                    const int u = u0 + lane / TV, v = tv * TV + lane % TV;
-                    if (u <= umaxp && v <= vcapp && u * u + v * v <= remp)
-                        cols[u * S + v] = st_N[mp * SS + u * S + v];
-                }
+        const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
+        off -= r.total;   // first cell of layer m in the record
+        if (m >= 2) {   // exit columns of layer m - 1 into cols
+            const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m - 1);
+            for (int g = lane; g < rp.total; g += 64) {
+                int u, v;
+                if (rect_cell(rp, g, u, v)) cols[u * S + v] = rec.N[off - rp.total + g];
             }
         }
+        for (int k = litoff[m] + lane; k < litoff[m + 1]; k += 64) abar[rec.pm[k] & 0xffff] += gin[k];
         wave_sync();
-        const int rem = Rsq - m * m;
-        const int umax = min(min(m, L.ext_u), isqrt_floor(rem));
-        const int vcap = min(m, L.ext_v);
-        for (int tu = 0; tu <= umax / TU; ++tu) {
-            const int u0 = tu * TU;
-            const int vmax = min(vcap, isqrt_floor(rem - u0 * u0));
-            for (int tv = 0; tv <= vmax / TV; ++tv) {
-                const int u = u0 + lane / TV, v = tv * TV + lane % TV;
-                const bool act = u <= umax && v <= vcap && u * u + v * v <= rem;
-                LayerAdj la;
-                if (act)
-                    layer_cell_adjoint(L, X, T, A.m64, A.tp, coef, m, u, v, cols, S, abar[u * S + v],
-                                       st_dN[m * SS + u * S + v], gbar, la);
-                wave_sync();
-                if (act) abar[u * S + v] = 0.0;
-                wave_sync();
-                if (act) {
+        for (int c = 0; c < (r.total + 63) / 64; ++c) {
+            const int g = c * 64 + lane;
+            int u, v;
+            const bool act = rect_cell(r, g, u, v);
+            double Tin = 0.0;
+            if (act) {
+                Tin = abar[u * S + v];
+                abar[u * S + v] = 0.0;
+            }
+            wave_sync();
+            if (__ballot(Tin != 0.0)) {
+                if (Tin != 0.0) {
+                    LayerRev lr;
+                    layer_cell_reverse(L, X, m, u, v, cols, S, Tin, lr);
                     if (m >= 2) {
 #pragma unroll
                         for (int n = 0; n < 4; ++n)
-                            if (la.Mbar[n] != 0.0)
-                                atomicAdd(&abar[(u - (n & 1)) * S + (v - (n >> 1))], la.Mbar[n]);
+                            if (lr.Mbar[n] != 0.0) atomicAdd(&abar[(u - (n & 1)) * S + (v - (n >> 1))], lr.Mbar[n]);
                     }
-                    if (la.nbar != 0.0) unsafeAtomicAdd(&nbar[la.cp], la.nbar);
-                    nb_src += la.nbar_src;
-                    qb += la.qbar;
+                    if (lr.nbar != 0.0) unsafeAtomicAdd(&nbar[lr.cp], lr.nbar);
+                    nb_src += lr.nbar_src;
                 }
                 wave_sync();
             }
@@ -334,9 +386,9 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
         qb += q1;
     }
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        nb_src += __shfl_xor(nb_src, off, 64);
-        qb += __shfl_xor(qb, off, 64);
+    for (int o = 32; o >= 1; o >>= 1) {
+        nb_src += __shfl_xor(nb_src, o, 64);
+        qb += __shfl_xor(qb, o, 64);
     }
     if (lane == 0) {
         if (nb_src != 0.0) unsafeAtomicAdd(&A.nbar[cs], nb_src);
@@ -344,7 +396,7 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
     }
 }
 
-template <int TV>
+template <bool KEPT>
 __global__ __launch_bounds__(512) void adj_layer(AdjArgs A)
 {
     extern __shared__ __align__(16) char smem[];
@@ -361,7 +413,8 @@ __global__ __launch_bounds__(512) void adj_layer(AdjArgs A)
     const int waves = blockDim.x >> 6;
     double *cols = (double *)(smem + (size_t)A.tp.n * sizeof(TabNode) + (size_t)wave * A.region_bytes);
     double *abar = cols + (size_t)(A.Mcap + 1) * A.lay_S;
-    double *store = A.store + (size_t)(blockIdx.x * waves + wave) * A.store_stride;
+    int *litoff = (int *)(abar + (size_t)(A.Mcap + 1) * A.lay_S);
+    char *scratch = (char *)(A.store + (size_t)(blockIdx.x * waves + wave) * A.store_stride);
     const int base = A.seg[TYPE];
     const int nitems = (A.seg[TYPE + 1] - base) * npieces;
     const int home = (int)(blockIdx.x % kXcds);
@@ -370,7 +423,7 @@ __global__ __launch_bounds__(512) void adj_layer(AdjArgs A)
         const int item = next_item(A.counter, nitems, home, chunk, lane);
         if (item >= nitems) break;
         const int src = A.order[base + item / npieces];
-        adjoint_layer_piece<TV>(A, T, cols, abar, store, src, item % npieces, lane);
+        adjoint_layer_piece<KEPT>(A, T, cols, abar, litoff, scratch, src, item % npieces, lane);
     }
 }
 
@@ -484,8 +537,8 @@ hipError_t adj_configure(size_t max_lds)
     const int dyn = (int)max_lds - 64;
     for (int t = 0; t < 3; ++t)
         (void)hipFuncSetAttribute(adj_fn(t), hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-    (void)hipFuncSetAttribute((const void *)adj_layer<8>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-    (void)hipFuncSetAttribute((const void *)adj_layer<16>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)adj_layer<false>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)adj_layer<true>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipGetLastError();
     return hipSuccess;
 }
@@ -540,6 +593,9 @@ static AdjArgs make_adj_args(const AdjLaunch &L)
     A.nbar_T = L.nbar_T;
     A.Mcap = 0;
     A.lay_S = 0;
+    A.kept = L.kept;
+    A.rec_piece_bytes = L.rec_piece_bytes;
+    A.rec_cap = L.rec_cap;
     return A;
 }
 
@@ -556,26 +612,29 @@ hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L)
     return hipGetLastError();
 }
 
+// Per-wave LDS of the layer adjoint: the column and adjoint buffers of
+// (Mcap + 1) rows of S doubles, then the per-layer offsets of the cell list.
 size_t adj_layer_region_bytes(int Mcap, int S)
 {
-    return ((size_t)2 * (Mcap + 1) * S * sizeof(double) + 15) & ~(size_t)15;
+    return ((size_t)2 * (Mcap + 1) * S * sizeof(double) + (size_t)(Mcap + 2) * sizeof(int) + 15) &
+           ~(size_t)15;
 }
 
-hipError_t adj_layer_occupancy(int tv, int waves, size_t lds, int *blocks_per_cu)
+hipError_t adj_layer_occupancy(int waves, size_t lds, int *blocks_per_cu)
 {
-    const void *f = tv == 8 ? (const void *)adj_layer<8> : (const void *)adj_layer<16>;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, waves * 64, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)adj_layer<false>,
+                                                        waves * 64, lds);
 }
 
-hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int tv, int Mcap)
+hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int Mcap)
 {
     AdjArgs A = make_adj_args(L);
     A.Mcap = Mcap;
     A.lay_S = Mcap + 1;
     A.region_bytes = (int)adj_layer_region_bytes(Mcap, A.lay_S);
     const size_t lds = (size_t)L.tp.n * sizeof(TabNode) + (size_t)L.waves * A.region_bytes;
-    if (tv == 8) hipLaunchKernelGGL(adj_layer<8>, dim3(L.grid), dim3(64 * L.waves), lds, st, A);
-    else hipLaunchKernelGGL(adj_layer<16>, dim3(L.grid), dim3(64 * L.waves), lds, st, A);
+    if (A.kept) hipLaunchKernelGGL(adj_layer<true>, dim3(L.grid), dim3(64 * L.waves), lds, st, A);
+    else hipLaunchKernelGGL(adj_layer<false>, dim3(L.grid), dim3(64 * L.waves), lds, st, A);
     return hipGetLastError();
 }
 

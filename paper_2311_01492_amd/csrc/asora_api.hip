@@ -24,7 +24,10 @@ struct PlanKey {
 struct Plan {
     int ring_cap, row_cap, Qmax;
     long piece_cells;   // largest number of cells of one piece (adjoint scratch)
-    int Mcap, tv;       // layer pieces: largest layer index, tile width along v
+    long scratch;       // adjoint: doubles of scratch per wave
+    int Mcap;           // layer pieces: largest layer index
+    long rec_cap;       // layer pieces: cells per pyramid record
+    size_t rec_bytes;   // layer pieces: bytes of one pyramid record
     int wave_mode;   // 1: one wave per piece (waves per work-group below); 0: one work-group per piece
     int waves;
     size_t lds;
@@ -63,6 +66,15 @@ struct asora_ctx {
     double *d_nbar;         // dL/dn_HI accumulator (allocated by the first backward call)
     double *d_store;        // stored exit columns of the adjoint pieces in flight
     size_t store_cap;       // doubles
+    // column records kept by a forward call made with ASORA_STORE (layer pieces)
+    char *d_keep;
+    size_t keep_alloc;      // bytes allocated
+    size_t keep_need;       // bytes the most recent ASORA_STORE forward needed
+    size_t keep_budget;     // 0: half the free device memory at the call
+    bool keep_valid;
+    const void *keep_sig[5];    // n_H, x_HI, src_ijk, src_Q, src_R of that call
+    int64_t keep_nsrc;
+    float keep_Rmax;
     std::map<PlanKey, Plan> adj_plans;
     // profiling: a ring of event quadruples (call start, sweep start, sweep
     // stop, call stop), one per call made with ASORA_PROFILE
@@ -232,6 +244,7 @@ extern "C" asora_status asora_free(asora_ctx *c)
     (void)hipFree(c->d_nbar_T);
     (void)hipFree(c->d_nbar);
     (void)hipFree(c->d_store);
+    (void)hipFree(c->d_keep);
     for (int sl = 0; sl < kProfSlots; ++sl)
         for (int k = 0; k < 4; ++k)
             if (c->pev[sl][k]) (void)hipEventDestroy(c->pev[sl][k]);
@@ -352,7 +365,9 @@ static asora_status get_layer_plan(asora_ctx *c, float R_cap, Plan *out)
     while ((long)(r + 1) * (r + 1) <= Rsq) ++r;
     P.Mcap = r < ex.neg ? r : ex.neg;
     if (P.Mcap < 1) P.Mcap = 1;
-    P.tv = P.Mcap + 1 > 8 ? 16 : 8;
+    P.rec_cap = layer_piece_capacity(Rsq, ex);
+    if (P.rec_cap < 1) P.rec_cap = 1;
+    P.rec_bytes = layer_record_bytes(P.rec_cap, P.Mcap);
     P.wave_mode = 1;
     const size_t tab = (size_t)c->tp.n * sizeof(TabNode);
     const size_t region = layer_region_bytes(P.Mcap, P.Mcap + 1);
@@ -364,7 +379,7 @@ static asora_status get_layer_plan(asora_ctx *c, float R_cap, Plan *out)
     P.waves = (int)(fit < c->max_waves ? fit : c->max_waves);
     P.lds = tab + (size_t)P.waves * region;
     int bpc = 0;
-    HIPCHK(c, layer_occupancy(P.tv, P.waves, P.lds, &bpc));
+    HIPCHK(c, layer_occupancy(P.waves, P.lds, &bpc));
     P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
     c->plans[key] = P;
     *out = P;
@@ -399,6 +414,52 @@ static asora_status ensure_src_cap(asora_ctx *c, long n)
     return ASORA_OK;
 }
 
+// Device memory for the kept column records: `need` bytes if they fit the
+// budget (the explicit one, else half of the free device memory plus what is
+// already allocated).  *ok = false leaves nothing kept.  Growing frees the old
+// allocation, which waits for the device.
+static asora_status reserve_keep(asora_ctx *c, size_t need, bool *ok)
+{
+    *ok = false;
+    if (need == 0) return ASORA_OK;
+    size_t budget = c->keep_budget;
+    if (budget == 0) {
+        size_t fr = 0, tot = 0;
+        HIPCHK(c, hipMemGetInfo(&fr, &tot));
+        budget = fr / 2 + c->keep_alloc;
+    }
+    if (need > budget) return ASORA_OK;
+    if (need > c->keep_alloc) {
+        (void)hipFree(c->d_keep);
+        c->d_keep = nullptr;
+        c->keep_alloc = 0;
+        if (hipMalloc(&c->d_keep, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return ASORA_OK;   // treated as not fitting
+        }
+        c->keep_alloc = need;
+    }
+    *ok = true;
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_store_info(const asora_ctx *c, int32_t *valid, uint64_t *bytes_needed,
+                                         uint64_t *bytes_allocated)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    if (valid) *valid = c->keep_valid ? 1 : 0;
+    if (bytes_needed) *bytes_needed = c->keep_need;
+    if (bytes_allocated) *bytes_allocated = c->keep_alloc;
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_set_store_budget(asora_ctx *c, uint64_t bytes)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    c->keep_budget = (size_t)bytes;
+    return ASORA_OK;
+}
+
 static asora_status check_common(asora_ctx *c, const float *n_H, const float *x_HI, int64_t n_src,
                                  const int32_t *ijk, const double *Q, float R_max)
 {
@@ -420,7 +481,7 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     if (st) return st;
     if (!gamma) return fail(c, ASORA_EINVAL, "gamma must not be NULL");
     if (coldens_in && n_src != 1) return fail(c, ASORA_EINVAL, "coldens_in requires n_src == 1");
-    if (flags & ~(ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_PROFILE))
+    if (flags & ~(ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_PROFILE | ASORA_STORE))
         return fail(c, ASORA_EINVAL, "unknown flags");
     const bool prof = (flags & ASORA_PROFILE) != 0;
     hipEvent_t *ev = c->pev[c->prof_count % kProfSlots];
@@ -439,6 +500,14 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     }
     if ((st = ensure_src_cap(c, n_src))) return st;
     if (layers && (st = ensure_layer_buffers(c))) return st;
+    // ASORA_STORE: keep the pyramids' column records for the adjoint when
+    // they fit the budget; any other forward with the flag replaces them
+    bool keep = false;
+    if (flags & ASORA_STORE) {
+        c->keep_valid = false;
+        c->keep_need = layers ? (size_t)n_src * 24 * plans[3].rec_bytes : 0;
+        if ((st = reserve_keep(c, c->keep_need, &keep))) return st;
+    }
 
     FwdLaunch F;
     F.N = c->N;
@@ -459,6 +528,9 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     F.err = c->d_err;
     F.nHI_T = c->d_nhi_T;
     F.gacc_T = c->d_gacc_T;
+    F.keep = keep ? c->d_keep : nullptr;
+    F.keep_piece_bytes = layers ? plans[3].rec_bytes : 0;
+    F.keep_cap = layers ? plans[3].rec_cap : 0;
 
     if (prof) HIPCHK(c, hipEventRecord(ev[0], s));
     HIPCHK(c, launch_prologue(s, n_H, x_HI, c->d_nhi, c->d_gacc, coldens_in, n3, c->d_ctl,
@@ -476,8 +548,7 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
             F.row_cap = plans[tmax].row_cap;
             for (long k = 0; k < n_src; ++k) {
                 if (tmax == 3)
-                    HIPCHK(c, launch_fwd_layer(s, F, plans[3].tv, plans[3].Mcap, plans[3].waves, 0,
-                                               (int)k));
+                    HIPCHK(c, launch_fwd_layer(s, F, plans[3].Mcap, plans[3].waves, 0, (int)k));
                 else if (plans[tmax].wave_mode)
                     HIPCHK(c, launch_fwd_wave(s, F, plans[tmax].waves, 0, (int)k));
                 else
@@ -491,8 +562,7 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
                 F.ring_cap = plans[t].ring_cap;
                 F.row_cap = plans[t].row_cap;
                 if (t == 3)
-                    HIPCHK(c, launch_fwd_layer(s, F, plans[3].tv, plans[3].Mcap, plans[3].waves,
-                                               plans[3].grid, -1));
+                    HIPCHK(c, launch_fwd_layer(s, F, plans[3].Mcap, plans[3].waves, plans[3].grid, -1));
                 else if (plans[t].wave_mode)
                     HIPCHK(c, launch_fwd_wave(s, F, plans[t].waves, plans[t].grid, -1));
                 else
@@ -511,6 +581,16 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
         HIPCHK(c, hipEventRecord(ev[3], s));
         c->prof_count++;
         if (c->prof_pending < kProfSlots) c->prof_pending++;
+    }
+    if (keep) {
+        c->keep_valid = true;
+        c->keep_sig[0] = n_H;
+        c->keep_sig[1] = x_HI;
+        c->keep_sig[2] = src_ijk;
+        c->keep_sig[3] = src_Q;
+        c->keep_sig[4] = src_R;
+        c->keep_nsrc = n_src;
+        c->keep_Rmax = R_max;
     }
     return ASORA_OK;
 }
@@ -532,6 +612,7 @@ extern "C" asora_status asora_set_tuning(asora_ctx *c, float R_whole, float R_oc
     if (pyramid_sweep) c->big_kind = pyramid_sweep;
     c->plans.clear();
     c->adj_plans.clear();
+    c->keep_valid = false;   // record layouts follow the plans
     return ASORA_OK;
 }
 
@@ -607,6 +688,7 @@ static asora_status get_adj_plan(asora_ctx *c, int type, float R_cap, Plan *out)
                     "asora_raytrace_backward: R_max=%.1f needs %zu bytes of LDS per wave (limit %zu)",
                     R_cap, region + tab, c->max_lds);
     P.wave_mode = 1;
+    P.scratch = 2 * P.piece_cells;   // exit and in-cell columns of a piece
     const int cap = c->max_waves < 8 ? c->max_waves : 8;   // adjoint work-groups: <= 512 threads
     P.waves = (int)(fit < cap ? fit : cap);
     P.lds = tab + (size_t)P.waves * region;
@@ -618,8 +700,8 @@ static asora_status get_adj_plan(asora_ctx *c, int type, float R_cap, Plan *out)
     return ASORA_OK;
 }
 
-// Adjoint layer pieces: two layer buffers per wave in LDS, every layer's
-// columns in the wave's scratch.
+// Adjoint layer pieces: two layer buffers per wave in LDS; a pyramid column
+// record and the rate's entry-column terms in the wave's scratch.
 static asora_status get_adj_layer_plan(asora_ctx *c, float R_cap, Plan *out)
 {
     const int Rsq = (int)std::floor((double)R_cap * (double)R_cap);
@@ -630,7 +712,7 @@ static asora_status get_adj_layer_plan(asora_ctx *c, float R_cap, Plan *out)
         return ASORA_OK;
     }
     Plan P;
-    asora_status st = get_layer_plan(c, R_cap, &P);   // Mcap, tile width
+    asora_status st = get_layer_plan(c, R_cap, &P);   // Mcap, record sizes
     if (st) return st;
     const size_t tab = (size_t)c->tp.n * sizeof(TabNode);
     const size_t region = adj_layer_region_bytes(P.Mcap, P.Mcap + 1);
@@ -643,10 +725,10 @@ static asora_status get_adj_layer_plan(asora_ctx *c, float R_cap, Plan *out)
     P.waves = (int)(fit < cap ? fit : cap);
     P.lds = tab + (size_t)P.waves * region;
     int bpc = 0;
-    HIPCHK(c, adj_layer_occupancy(P.tv, P.waves, P.lds, &bpc));
+    HIPCHK(c, adj_layer_occupancy(P.waves, P.lds, &bpc));
     P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
-    const long S = P.Mcap + 1;
-    P.piece_cells = (long)(P.Mcap + 1) * (P.Mcap + 1) * S;   // dense [m][u][v] per stored array
+    P.piece_cells = P.rec_cap;
+    P.scratch = (long)((P.rec_bytes + sizeof(double) * (size_t)P.rec_cap) / sizeof(double));
     c->adj_plans[key] = P;
     *out = P;
     return ASORA_OK;
@@ -679,7 +761,8 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
     if (st) return st;
     if (!dL_dgamma || !dL_dnH || !dL_dxHI || (n_src > 0 && !dL_dQ))
         return fail(c, ASORA_EINVAL, "gradient buffers must not be NULL");
-    if (flags & ~(ASORA_ACCUMULATE | ASORA_PROFILE)) return fail(c, ASORA_EINVAL, "unknown flags");
+    if (flags & ~(ASORA_ACCUMULATE | ASORA_PROFILE | ASORA_STORE))
+        return fail(c, ASORA_EINVAL, "unknown flags");
     const bool prof = (flags & ASORA_PROFILE) != 0;
     const bool acc = (flags & ASORA_ACCUMULATE) != 0;
     hipEvent_t *ev = c->pev[c->prof_count % kProfSlots];
@@ -696,7 +779,7 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
         const float cap = t == tmax ? R_max : (t == 0 ? c->R_whole : c->R_oct);
         if ((st = t == 3 ? get_adj_layer_plan(c, cap, &plans[t]) : get_adj_plan(c, t, cap, &plans[t])))
             return st;
-        const size_t need = (size_t)plans[t].grid * plans[t].waves * 2 * (size_t)plans[t].piece_cells;
+        const size_t need = (size_t)plans[t].grid * plans[t].waves * (size_t)plans[t].scratch;
         store_need = need > store_need ? need : store_need;
     }
     if ((st = ensure_src_cap(c, n_src))) return st;
@@ -744,6 +827,13 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
         L.nHI_T = c->d_nhi_T;
         L.gbar_T = c->d_gbar_T;
         L.nbar_T = c->d_nbar_T;
+        // ASORA_STORE: the records kept by the forward call with these inputs
+        const bool kept = (flags & ASORA_STORE) && layers && c->keep_valid && c->keep_nsrc == n_src &&
+                          c->keep_Rmax == R_max && c->keep_sig[0] == n_H && c->keep_sig[1] == x_HI &&
+                          c->keep_sig[2] == src_ijk && c->keep_sig[3] == src_Q && c->keep_sig[4] == src_R;
+        L.kept = kept ? c->d_keep : nullptr;
+        L.rec_piece_bytes = layers ? plans[3].rec_bytes : 0;
+        L.rec_cap = layers ? plans[3].rec_cap : 0;
         for (int t = tmax; t >= 0; --t) {
             if (t == 2 && layers) continue;
             L.type = t;
@@ -753,8 +843,8 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
             L.shell_cap = plans[t].Qmax;
             L.waves = plans[t].waves;
             L.grid = plans[t].grid;
-            L.store_stride = 2 * plans[t].piece_cells;
-            if (t == 3) HIPCHK(c, launch_adj_layer(s, L, plans[3].tv, plans[3].Mcap));
+            L.store_stride = plans[t].scratch;
+            if (t == 3) HIPCHK(c, launch_adj_layer(s, L, plans[3].Mcap));
             else HIPCHK(c, launch_adj_wave(s, L));
         }
     }

@@ -814,6 +814,88 @@ __host__ __device__ __forceinline__ int isqrt_floor(int x)
     return r;
 }
 
+// Layer m of a pyramid enumerated as a rectangle: rows u = 0..nu-1 of wv
+// cells v = 0..wv-1, cell g = u * wv + v (row-major, so increasing g is
+// increasing (u, v) in lexicographic order).  The rectangle is the bounding
+// box of the layer's cells inside the ball (u^2 + v^2 <= rem) and the
+// periodic extent; the cells outside the ball are inactive.
+struct LayerRect {
+    int rem;      // Rsq - m^2
+    int nu, wv;   // rows, row width
+    int total;    // nu * wv
+};
+
+__host__ __device__ __forceinline__ LayerRect layer_rect(int ext_u, int ext_v, int Rsq, int m)
+{
+    LayerRect r;
+    r.rem = Rsq - m * m;
+    const int s = isqrt_floor(r.rem);
+    const int cu = m < ext_u ? m : ext_u, cv = m < ext_v ? m : ext_v;
+    r.nu = (cu < s ? cu : s) + 1;
+    r.wv = (cv < s ? cv : s) + 1;
+    r.total = r.nu * r.wv;
+    return r;
+}
+
+// (u, v) of cell g of the rectangle; true if the cell is active.
+__host__ __device__ __forceinline__ bool rect_cell(const LayerRect &r, int g, int &u, int &v)
+{
+    int q = (int)((float)g * rcp_approx((float)r.wv));   // off by at most one (g < 2^24)
+    if (q * r.wv > g) --q;
+    else if ((q + 1) * r.wv <= g) ++q;
+    u = q;
+    v = g - q * r.wv;
+    return g < r.total && u * u + v * v <= r.rem;
+}
+
+// Cells of the largest pyramid of a source of squared radius Rsq, counted as
+// layer rectangles (an upper bound for every octant and axis: the negative
+// extent is the larger one).
+__host__ __device__ inline long layer_piece_capacity(int Rsq, const Extent &ex)
+{
+    const int r = isqrt_floor(Rsq);
+    const int Mx = r < ex.neg ? r : ex.neg;
+    long cap = 0;
+    for (int m = 1; m <= Mx; ++m) cap += layer_rect(ex.neg, ex.neg, Rsq, m).total;
+    return cap;
+}
+
+// Column record of one pyramid (a piece of layer kind) in global memory: the
+// exit column of every cell, layer by layer in rectangle order, and a list of
+// the owned cells whose entry optical depth lies inside the table (the cells
+// with a rate), in sweep order, with litoff[m] the first record of layer m.
+// `cap` bounds both the cells and the records of the pyramid.  Written by the
+// forward sweep when the columns are kept, or by the adjoint's own forward
+// pass; read by the adjoint's reverse pass.
+struct LayerRecord {
+    double *N;        // [cap] exit columns
+    double *ta;       // [cap] entry optical depth of each listed cell
+    double *dt;       // [cap] its in-cell optical depth (FP64)
+    uint32_t *cp;     // [cap] its cell index in the piece's field layout
+    int *pm;          // [cap] its buffer slot u * S + v (low 16 bits) and layer m (bits 16..)
+    int *r2;          // [cap] its squared distance from the source (cells)
+    int *litoff;      // [Mcap + 2] first record of each layer m; litoff[Mx + 1] = count
+};
+
+__host__ __device__ __forceinline__ size_t layer_record_bytes(long cap, int Mcap)
+{
+    const size_t b = (size_t)cap * (3 * sizeof(double) + 3 * sizeof(int)) + (size_t)(Mcap + 2) * sizeof(int);
+    return (b + 255) & ~(size_t)255;
+}
+
+__host__ __device__ __forceinline__ LayerRecord layer_record_at(char *base, long cap)
+{
+    LayerRecord s;
+    s.N = (double *)base;
+    s.ta = s.N + cap;
+    s.dt = s.ta + cap;
+    s.cp = (uint32_t *)(s.dt + cap);
+    s.pm = (int *)(s.cp + cap);
+    s.r2 = s.pm + cap;
+    s.litoff = s.r2 + cap;
+    return s;
+}
+
 // Everything one layer-cell update needs that is uniform over a piece.
 struct LayerX {
     int N;
@@ -991,6 +1073,99 @@ __host__ __device__ __forceinline__ void layer_cell_adjoint(const LayerPiece &L,
         out.Mbar[n] = m == 1 ? 0.0 : mb;
         if (m == 1) out.nbar_src += mb * (X.reading == 0 ? X.alpha * ds * 0.5 : X.alpha * 0.5);
     }
+}
+
+// Reverse-mode update of layer cell (u, v) of layer m through the
+// interpolation alone.  Tin is the total adjoint of the cell's entry column:
+// the adjoints its consumers pushed to its exit column plus the rate's own
+// entry-column term (the rate's in-cell term reaches dL/dn_HI separately, see
+// record_rate_adjoint).  Since N_out = N_in + dN, the exit-column adjoint
+// flows unchanged into both N_in and dN.  Returns the adjoints to push to
+// the four neighbours of layer m - 1 (Mbar[n] for neighbour
+// (u - (n & 1), v - (n >> 1)); zero where the weight is zero; for m = 1 the
+// source takes them through nbar_src) and dL/dn_HI of the cell.
+struct LayerRev {
+    uint32_t cp;
+    double Mbar[4];
+    double nbar_src;
+    double nbar;
+};
+
+__host__ __device__ __forceinline__ void layer_cell_reverse(const LayerPiece &L, const LayerX &X, int m,
+                                                            int u, int v, const double *cols, int S,
+                                                            double Tin, LayerRev &out)
+{
+    const int N = X.N;
+    out.cp = (uint32_t)wrap(L.c_d + L.sd * m, N) * L.st_d + (uint32_t)wrap(L.c_u + L.su * u, N) * L.st_u +
+             (uint32_t)wrap(L.c_v + L.sv * v, N);
+    const double inv_m = rcp_f64((double)m);
+    const double ds = sqrt_fast((double)(m * m + u * u + v * v)) * inv_m;
+    out.nbar = Tin * X.alpha * ds;                    // dN = n_HI alpha ds
+    out.nbar_src = 0.0;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) out.Mbar[n] = 0.0;
+    if (m == 1) {   // the only neighbour of non-zero weight is the source: N_in = its column
+        out.nbar_src = Tin * (X.reading == 0 ? X.alpha * ds * 0.5 : X.alpha * 0.5);
+        return;
+    }
+    const double a = u == m ? 1.0 : (double)u * inv_m;
+    const double b = v == m ? 1.0 : (double)v * inv_m;
+    const double sw[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
+    double Mv[4], wv[4], dw[4];
+    double num = 0.0, W = 0.0;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        Mv[n] = 0.0;
+        wv[n] = 0.0;
+        dw[n] = 0.0;
+        if (!(sw[n] > 0.0)) continue;
+        const double M = cols[(u - (n & 1)) * S + (v - (n >> 1))];
+        double wn = sw[n];
+        if (X.tau_w > 0.f) {
+            const double tau = X.sigma0 * M;
+            if (tau > (double)X.tau_w) {   // w = s / tau, dw/dM = -s sigma0 / tau^2
+                const double it = rcp_f64(tau);
+                wn *= it;
+                dw[n] = -sw[n] * X.sigma0 * it * it;
+            } else {
+                wn *= rcp_f64((double)X.tau_w);
+            }
+        }
+        Mv[n] = M;
+        wv[n] = wn;
+        num += wn * M;
+        W += wn;
+    }
+    const double iW = rcp_f64(W);
+    const double Nin = num * iW;
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+        out.Mbar[n] = sw[n] > 0.0 ? Tin * (wv[n] + (Mv[n] - Nin) * dw[n]) * iW : 0.0;
+}
+
+// The rate's part of the adjoint for one listed cell (entry optical depth
+// ta, in-cell optical depth dt, squared distance r2, layer m, dL/dGamma
+// gbar): Gamma = k D(ta, dt) with k = -coef / r2.  Returns the rate's
+// entry-column term g_in = gbar dGamma/dN_in (added to the cell's exit-column
+// adjoint before the interpolation is reversed), the part of dL/dn_HI of the
+// cell that the interpolation reverse does not produce,
+// (g_dN - g_in) alpha ds with g_dN = gbar dGamma/d(dN), and gbar Gamma.
+__host__ __device__ __forceinline__ void record_rate_adjoint(const TabNode *T, const double *m64,
+                                                             const TabParams &tp, double sigma0,
+                                                             double alpha, double coef, double ta,
+                                                             double dt, int r2, int m, double gbar,
+                                                             double *g_in, double *nbar_extra,
+                                                             double *gG)
+{
+    double D, Da, Ddt;
+    rate_derivs64(T, m64, tp, ta, dt, &D, &Da, &Ddt);
+    const double k = -coef / (double)r2;
+    const double gi = gbar * k * Da * sigma0;
+    const double gd = gbar * k * Ddt * sigma0;
+    const double ds = sqrt_fast((double)r2) * rcp_f64((double)m);
+    *g_in = gi;
+    *nbar_extra = (gd - gi) * alpha * ds;
+    *gG = gbar * k * D;
 }
 
 // Build the row table of shell q of a piece (serial form; the kernel runs

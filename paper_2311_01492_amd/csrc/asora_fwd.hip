@@ -40,6 +40,9 @@ struct FwdArgs {
     const double *nHI_T;    // n_HI in the [k][i][j] layout (layer pieces with d = k)
     double *gacc_T;         // Gamma accumulator in the [k][i][j] layout
     int lay_S;              // row stride of the per-wave layer buffer (layer pieces)
+    char *keep;             // layer pieces: column records, per (source, pyramid); NULL = none
+    size_t keep_piece_bytes;
+    long keep_cap;          // cells (and listed cells) per pyramid record
 };
 
 struct Lds {
@@ -321,17 +324,19 @@ __global__ __launch_bounds__(1024) void fwd_wave(FwdArgs A)
 }
 
 // ---- layer pieces --------------------------------------------------------
-// One wave sweeps one pyramid layer by layer (see LayerPiece).  The wave
-// covers a layer in tiles of (64 / TV) rows of u by TV consecutive v; the
+// One wave sweeps one pyramid layer by layer (see LayerPiece).  Layer m is
+// the rectangle of LayerRect, covered in chunks of 64 consecutive cells; the
 // previous layer lives in the wave's LDS buffer and is overwritten in place:
-// tiles go in decreasing u band, then decreasing v, so every slot a tile reads
-// (at or below its own u and v) still holds layer m - 1.  Rates go through the
-// same per-wave queue as the shell sweep.
-template <int TV>
+// chunks go from the last to the first, and a cell reads only slots at or
+// before its own (u, v) in lexicographic order, so every slot a chunk reads
+// still holds layer m - 1 (the chunk's own writes follow its reads).  Rates go
+// through the same per-wave queue as the shell sweep.  With KEEP the sweep
+// also writes the pyramid's column record (exit columns and the cells with a
+// rate) for a later adjoint.
+template <bool KEEP>
 __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *lay,
                                   const RateQueue &Qa, int src, int p, int lane)
 {
-    constexpr int TU = 64 / TV;
     const int N = A.N;
     const int si = A.ijk[3 * src], sj = A.ijk[3 * src + 1], sk = A.ijk[3 * src + 2];
     const float R = A.R ? A.R[src] : A.R_cap;
@@ -356,6 +361,8 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
     double *acc = L.transposed ? A.gacc_T : A.gacc;
     const double coef = Q * A.coef_unit;
     const int S = A.lay_S;
+    LayerRecord rec;
+    if (KEEP) rec = layer_record_at(A.keep + ((size_t)src * 24 + p) * A.keep_piece_bytes, A.keep_cap);
 
     if (p == 3 * 0 + 2 && lane == 0) {   // the source cell, once per source
         const double G = source_cell_rate(T, A.tp, A.sigma0, A.alpha, Q, n_s);
@@ -363,51 +370,58 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
         if (A.coldens) A.coldens[cs] = 0.0;
     }
     const int Mx = min(isqrt_floor(Rsq), L.ext_d);
-    for (int k = lane; k < (Mx + 1) * S; k += 64) lay[k] = 0.0;
-    wave_sync();
     int head = 0, tail = 0;
+    long off = 0;   // first cell of layer m in the record
     for (int m = 1; m <= Mx; ++m) {
-        const int rem = Rsq - m * m;
-        const int umax = min(min(m, L.ext_u), isqrt_floor(rem));
-        const int vcap = min(m, L.ext_v);
-        for (int tu = umax / TU; tu >= 0; --tu) {
-            const int u0 = tu * TU;
-            const int vmax = min(vcap, isqrt_floor(rem - u0 * u0));
-            for (int tv = vmax / TV; tv >= 0; --tv) {
-                const int u = u0 + lane / TV, v = tv * TV + lane % TV;
-                const bool act = u <= umax && v <= vcap && u * u + v * v <= rem;
-                LayerCell lc;
-                lc.Nin = 0.0;
-                lc.owned = false;
-                if (act) layer_cell(L, X, m, u, v, lay, S, lc);
-                wave_sync();   // every read of layer m - 1 before the writes below
-                bool want = false;
-                if (act) {
-                    lay[u * S + v] = lc.Nout;
-                    if (lc.owned) {
-                        if (A.coldens) A.coldens[layer_std_index(L, N, m, u, v)] = lc.Nin;
-                        want = A.sigma0 * lc.Nin < A.tp.tau_hi;
-                    }
+        if (KEEP && lane == 0) rec.litoff[m] = tail;
+        const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
+        for (int c = (r.total + 63) / 64 - 1; c >= 0; --c) {
+            const int g = c * 64 + lane;
+            int u, v;
+            const bool act = rect_cell(r, g, u, v);
+            LayerCell lc;
+            lc.Nin = 0.0;
+            lc.owned = false;
+            if (act) layer_cell(L, X, m, u, v, lay, S, lc);
+            wave_sync();   // every read of layer m - 1 before the writes below
+            bool want = false;
+            if (act) {
+                lay[u * S + v] = lc.Nout;
+                if (KEEP) rec.N[off + g] = lc.Nout;
+                if (lc.owned) {
+                    if (A.coldens) A.coldens[layer_std_index(L, N, m, u, v)] = lc.Nin;
+                    want = A.sigma0 * lc.Nin < A.tp.tau_hi;
                 }
-                const uint64_t mask = __ballot(want);
-                if (want) {
-                    const int pos = (tail + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
-                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))) & (kQueue - 1);
-                    Qa.ta[pos] = A.sigma0 * lc.Nin;
-                    Qa.dt[pos] = A.sigma0 * lc.dN;
-                    Qa.cp[pos] = lc.cp;
-                    Qa.r2[pos] = lc.r2;
-                }
-                tail += __popcll(mask);
-                if (tail - head >= 64) {
-                    wave_sync();
-                    rate_batch(A, T, Qa, head, lane, coef, acc);
-                    head += 64;
-                }
-                wave_sync();
             }
+            const uint64_t mask = __ballot(want);
+            if (want) {
+                const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+                const int pos = (tail + rank) & (kQueue - 1);
+                Qa.ta[pos] = A.sigma0 * lc.Nin;
+                Qa.dt[pos] = A.sigma0 * lc.dN;
+                Qa.cp[pos] = lc.cp;
+                Qa.r2[pos] = lc.r2;
+                if (KEEP) {
+                    const int k = tail + rank;
+                    rec.ta[k] = A.sigma0 * lc.Nin;
+                    rec.dt[k] = A.sigma0 * lc.dN;
+                    rec.cp[k] = lc.cp;
+                    rec.pm[k] = (u * S + v) | (m << 16);
+                    rec.r2[k] = lc.r2;
+                }
+            }
+            tail += __popcll(mask);
+            if (tail - head >= 64) {
+                wave_sync();
+                rate_batch(A, T, Qa, head, lane, coef, acc);
+                head += 64;
+            }
+            wave_sync();
         }
+        off += r.total;
     }
+    if (KEEP && lane == 0) rec.litoff[Mx + 1] = tail;
     if (tail > head) {
         wave_sync();
         if (lane < tail - head) rate_batch(A, T, Qa, head, lane, coef, acc);
@@ -415,7 +429,7 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
     }
 }
 
-template <int TV>
+template <bool KEEP>
 __global__ __launch_bounds__(1024) void fwd_layer(FwdArgs A)
 {
     extern __shared__ __align__(16) char smem[];
@@ -439,7 +453,7 @@ __global__ __launch_bounds__(1024) void fwd_layer(FwdArgs A)
     double *lay = (double *)(Qa.r2 + kQueue);
     if (A.plain_src >= 0) {
         const int item = blockIdx.x * waves + wave;
-        if (item < npieces) sweep_layer_piece<TV>(A, T, lay, Qa, A.plain_src, item, lane);
+        if (item < npieces) sweep_layer_piece<KEEP>(A, T, lay, Qa, A.plain_src, item, lane);
         return;
     }
     const int base = A.seg[TYPE];
@@ -450,7 +464,7 @@ __global__ __launch_bounds__(1024) void fwd_layer(FwdArgs A)
         const int item = next_item(A.counter, nitems, home, chunk, lane);
         if (item >= nitems) break;
         const int src = A.order[base + item / npieces];
-        sweep_layer_piece<TV>(A, T, lay, Qa, src, item % npieces, lane);
+        sweep_layer_piece<KEEP>(A, T, lay, Qa, src, item % npieces, lane);
     }
 }
 
@@ -463,17 +477,13 @@ size_t layer_region_bytes(int Mcap, int S)
     return (b + 15) & ~(size_t)15;
 }
 
-static const void *layer_fn(int tv)
+hipError_t layer_occupancy(int waves, size_t lds, int *blocks_per_cu)
 {
-    return tv == 8 ? (const void *)fwd_layer<8> : (const void *)fwd_layer<16>;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)fwd_layer<false>,
+                                                        waves * 64, lds);
 }
 
-hipError_t layer_occupancy(int tv, int waves, size_t lds, int *blocks_per_cu)
-{
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, layer_fn(tv), waves * 64, lds);
-}
-
-hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int tv, int Mcap, int waves, int grid,
+hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int Mcap, int waves, int grid,
                             int plain_src)
 {
     FwdArgs A = make_args(F);
@@ -482,8 +492,8 @@ hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int tv, int Mcap
     A.region_bytes = (int)layer_region_bytes(Mcap, A.lay_S);
     const size_t lds = (size_t)F.tp.n * sizeof(TabNode) + (size_t)waves * A.region_bytes;
     if (plain_src >= 0) grid = (24 + waves - 1) / waves;
-    if (tv == 8) hipLaunchKernelGGL(fwd_layer<8>, dim3(grid), dim3(64 * waves), lds, st, A);
-    else hipLaunchKernelGGL(fwd_layer<16>, dim3(grid), dim3(64 * waves), lds, st, A);
+    if (A.keep) hipLaunchKernelGGL(fwd_layer<true>, dim3(grid), dim3(64 * waves), lds, st, A);
+    else hipLaunchKernelGGL(fwd_layer<false>, dim3(grid), dim3(64 * waves), lds, st, A);
     return hipGetLastError();
 }
 
@@ -792,6 +802,9 @@ static FwdArgs make_args(const FwdLaunch &F)
     A.nHI_T = F.nHI_T;
     A.gacc_T = F.gacc_T;
     A.lay_S = 0;
+    A.keep = F.keep;
+    A.keep_piece_bytes = F.keep_piece_bytes;
+    A.keep_cap = F.keep_cap;
     A.ijk = F.ijk;
     A.Q = F.Q;
     A.R = F.R;
@@ -828,8 +841,8 @@ hipError_t fwd_configure(size_t max_lds)
     (void)hipFuncSetAttribute((const void *)fwd_wave<0>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipFuncSetAttribute((const void *)fwd_wave<1>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipFuncSetAttribute((const void *)fwd_wave<2>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-    (void)hipFuncSetAttribute((const void *)fwd_layer<8>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-    (void)hipFuncSetAttribute((const void *)fwd_layer<16>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)fwd_layer<false>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)fwd_layer<true>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipGetLastError();
     return hipSuccess;
 }

@@ -38,6 +38,9 @@ struct FwdLaunch {
     int ring_cap, row_cap;
     const double *nHI_T;    // [k][i][j] copies used by the layer pieces (may be NULL otherwise)
     double *gacc_T;
+    char *keep;             // layer pieces: column records per (source, pyramid), or NULL
+    size_t keep_piece_bytes;
+    long keep_cap;
 };
 
 hipError_t launch_prologue(hipStream_t st, const float *nH, const float *xHI, double *nHI,
@@ -50,8 +53,8 @@ hipError_t launch_transpose_prologue(hipStream_t st, const float *nH, const floa
 hipError_t launch_transpose_finalize(hipStream_t st, const double *gacc, const double *gacc_T,
                                      float *gamma, int N, int accumulate);
 size_t layer_region_bytes(int Mcap, int S);
-hipError_t layer_occupancy(int tv, int waves, size_t lds, int *blocks_per_cu);
-hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int tv, int Mcap, int waves, int grid,
+hipError_t layer_occupancy(int waves, size_t lds, int *blocks_per_cu);
+hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int Mcap, int waves, int grid,
                             int plain_src);
 size_t fwd_lds_bytes(int n_tab, int ring_cap, int row_cap);
 hipError_t fwd_configure(size_t max_lds);
@@ -91,6 +94,9 @@ struct AdjLaunch {
     const double *nHI_T;   // [k][i][j] copies for the layer pieces (may be NULL otherwise)
     const double *gbar_T;
     double *nbar_T;
+    const char *kept;      // layer pieces: column records kept by the forward, or NULL
+    size_t rec_piece_bytes;   // bytes of one pyramid's column record
+    long rec_cap;             // cells (and listed cells) per pyramid record
 };
 
 size_t adj_region_bytes(int ring_cap, int row_cap, int shell_cap);
@@ -101,8 +107,8 @@ hipError_t launch_adj_prologue(hipStream_t st, const float *nH, const float *xHI
                                int nctl, int n_cu);
 hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L);
 size_t adj_layer_region_bytes(int Mcap, int S);
-hipError_t adj_layer_occupancy(int tv, int waves, size_t lds, int *blocks_per_cu);
-hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int tv, int Mcap);
+hipError_t adj_layer_occupancy(int waves, size_t lds, int *blocks_per_cu);
+hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int Mcap);
 hipError_t launch_adj_transpose_prologue(hipStream_t st, const float *nH, const float *xHI,
                                          const double *gbar, double *nHI_T, double *gbar_T,
                                          double *nbar_T, int N);

@@ -139,98 +139,144 @@ extern "C" int hc_raytrace(int N, double alpha, double sigma0, int n, double lg_
 // [k][i][j] accumulator, added at the end as on the GPU.  Every read of a
 // neighbour of non-zero weight is checked to hold layer m - 1 (returns -6
 // otherwise).  tv is the tile width along v (8 or 16).
-extern "C" int hc_raytrace_layer(int N, double alpha, double sigma0, int n, double lg_lo, double lg_hi,
-                                 const double *P, const double *dP, double tau_w, int reading,
-                                 const float *nH, const float *xHI, long nsrc, const int32_t *ijk,
-                                 const double *Q, const float *R, int tv, double *gacc, double *coldens)
+// One pyramid swept forward in the layer kernels' order: layers m = 1..Mx,
+// each layer's rectangle in chunks of 64 cells from the last chunk to the
+// first, every chunk reading layer m - 1 from the in-place buffer before it
+// writes layer m.  Adds the rates to acc (when acc != NULL) and, when rec is
+// given, fills the column record as the kernels do (exit columns in rectangle
+// order, listed cells in chunk and lane order).  Returns -6 if a neighbour of
+// non-zero weight is read from a slot that does not hold layer m - 1.
+static int layer_forward_piece(const LayerPiece &L, const LayerX &X, int Rsq, const TabNode *T,
+                               const TabParams &tp, double coef, int S, double *lay, int *lay_id,
+                               double *acc, double *coldens, int N, LayerRecord *rec)
 {
-    if (tv != 8 && tv != 16) return -1;
-    const int tu = 64 / tv;
+    const int Mx = std::min(isqrt_floor(Rsq), L.ext_d);
+    long off = 0;
+    int nrec = 0;
+    for (int m = 1; m <= Mx; ++m) {
+        if (rec) rec->litoff[m] = nrec;
+        const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
+        for (int c = (r.total + 63) / 64 - 1; c >= 0; --c) {
+            LayerCell lc[64];
+            bool act[64];
+            int uu[64], vv[64];
+            for (int lane = 0; lane < 64; ++lane) {
+                act[lane] = rect_cell(r, c * 64 + lane, uu[lane], vv[lane]);
+                if (!act[lane]) continue;
+                const int u = uu[lane], v = vv[lane];
+                if (m > 1) {   // neighbours of non-zero weight must hold layer m - 1
+                    const bool a0 = u > 0, a1 = u < m, b0 = v > 0, b1 = v < m;
+                    const bool need[4] = {a1 && b1, a0 && b1, a1 && b0, a0 && b0};
+                    for (int k = 0; k < 4; ++k)
+                        if (need[k] && lay_id[(size_t)(u - (k & 1)) * S + v - (k >> 1)] != m - 1) return -6;
+                }
+                layer_cell(L, X, m, u, v, lay, S, lc[lane]);
+            }
+            for (int lane = 0; lane < 64; ++lane) {
+                if (!act[lane]) continue;
+                const int u = uu[lane], v = vv[lane];
+                lay[(size_t)u * S + v] = lc[lane].Nout;
+                lay_id[(size_t)u * S + v] = m;
+                if (rec) rec->N[off + c * 64 + lane] = lc[lane].Nout;
+                if (!lc[lane].owned) continue;
+                if (coldens) coldens[layer_std_index(L, N, m, u, v)] = lc[lane].Nin;
+                const double ta = X.sigma0 * lc[lane].Nin;
+                if (ta >= tp.tau_hi) continue;
+                if (rec) {
+                    rec->ta[nrec] = ta;
+                    rec->dt[nrec] = X.sigma0 * lc[lane].dN;
+                    rec->cp[nrec] = lc[lane].cp;
+                    rec->pm[nrec] = (u * S + v) | (m << 16);
+                    rec->r2[nrec] = lc[lane].r2;
+                    ++nrec;
+                }
+                if (acc) {
+                    const float nd = neg_divdiff(T, tp, ta, (double)(float)(X.sigma0 * lc[lane].dN));
+                    if (nd > 0.f) acc[lc[lane].cp] += coef * (double)(nd * rcp_approx((float)lc[lane].r2));
+                }
+            }
+        }
+        off += r.total;
+    }
+    if (rec) rec->litoff[Mx + 1] = nrec;
+    return 0;
+}
+
+struct HostLayerSetup {
     TabParams tp;
-    std::vector<TabNode> T(n);
-    std::vector<double> m64(n);
-    prepare_table(n, lg_lo, lg_hi, P, dP, &tp, T.data(), m64.data());
+    std::vector<TabNode> T;
+    std::vector<double> m64, nhi, nhiT;
+    Extent ex;
+    int Mcap, S;
+    long cap;
+};
+
+static void host_layer_setup(HostLayerSetup &H, int N, int n, double lg_lo, double lg_hi, const double *P,
+                             const double *dP, const float *nH, const float *xHI, long nsrc, const float *R)
+{
+    H.T.resize(n);
+    H.m64.resize(n);
+    prepare_table(n, lg_lo, lg_hi, P, dP, &H.tp, H.T.data(), H.m64.data());
     const long n3 = (long)N * N * N;
-    std::vector<double> nhi(n3), nhiT(n3), gT(n3, 0.0);
+    H.nhi.resize(n3);
+    H.nhiT.resize(n3);
     for (long i = 0; i < N; ++i)
         for (long j = 0; j < N; ++j)
             for (long k = 0; k < N; ++k) {
                 const long c = (i * N + j) * N + k;
-                nhi[c] = (double)nH[c] * (double)xHI[c];
-                nhiT[(k * N + i) * N + j] = nhi[c];
+                H.nhi[c] = (double)nH[c] * (double)xHI[c];
+                H.nhiT[(k * N + i) * N + j] = H.nhi[c];
             }
-    const Extent ex = make_extent(N);
+    H.ex = make_extent(N);
     float R_cap = 0.f;
     for (long s = 0; s < nsrc; ++s) R_cap = R[s] > R_cap ? R[s] : R_cap;
     const int Rsq_cap = (int)std::floor((double)R_cap * (double)R_cap);
-    int Mcap = isqrt_floor(Rsq_cap);
-    Mcap = Mcap < ex.neg ? Mcap : ex.neg;
-    Mcap = Mcap < 1 ? 1 : Mcap;
-    const int S = Mcap + 1;
-    std::vector<double> lay((size_t)(Mcap + 1) * S);
-    std::vector<int> lay_id((size_t)(Mcap + 1) * S);
+    H.Mcap = std::max(1, std::min(isqrt_floor(Rsq_cap), H.ex.neg));
+    H.S = H.Mcap + 1;
+    H.cap = std::max(1L, layer_piece_capacity(Rsq_cap, H.ex));
+}
+
+static LayerX host_layer_x(const HostLayerSetup &H, const LayerPiece &L, int N, double alpha, double sigma0,
+                           double tau_w, int reading, long cs)
+{
+    LayerX X;
+    X.N = N;
+    X.reading = reading;
+    X.tau_w = (float)(tau_w > 0 && std::isfinite(tau_w) ? tau_w : 0.0);
+    X.sigma0 = sigma0;
+    X.alpha = alpha;
+    X.half_col = H.nhi[cs] * alpha * 0.5;
+    X.nHI = L.transposed ? H.nhiT.data() : H.nhi.data();
+    return X;
+}
+
+extern "C" int hc_raytrace_layer(int N, double alpha, double sigma0, int n, double lg_lo, double lg_hi,
+                                 const double *P, const double *dP, double tau_w, int reading,
+                                 const float *nH, const float *xHI, long nsrc, const int32_t *ijk,
+                                 const double *Q, const float *R, double *gacc, double *coldens)
+{
+    HostLayerSetup H;
+    host_layer_setup(H, N, n, lg_lo, lg_hi, P, dP, nH, xHI, nsrc, R);
+    const long n3 = (long)N * N * N;
+    std::vector<double> gT(n3, 0.0);
+    std::vector<double> lay((size_t)(H.Mcap + 1) * H.S);
+    std::vector<int> lay_id((size_t)(H.Mcap + 1) * H.S);
     const double coef_unit = sigma0 / (4.0 * M_PI * alpha * alpha);
     for (long s = 0; s < nsrc; ++s) {
         const int si = ijk[3 * s], sj = ijk[3 * s + 1], sk = ijk[3 * s + 2];
         const int Rsq = (int)std::floor((double)R[s] * (double)R[s]);
         const long cs = ((long)si * N + sj) * N + sk;
-        const double coef = Q[s] * coef_unit;
-        gacc[cs] += source_cell_rate(T.data(), tp, sigma0, alpha, Q[s], nhi[cs]);
+        gacc[cs] += source_cell_rate(H.T.data(), H.tp, sigma0, alpha, Q[s], H.nhi[cs]);
         if (coldens) coldens[cs] = 0.0;
         for (int p = 0; p < 24; ++p) {
-            const LayerPiece L = make_layer_piece(p, si, sj, sk, N, ex);
-            LayerX X;
-            X.N = N;
-            X.reading = reading;
-            X.tau_w = (float)(tau_w > 0 && std::isfinite(tau_w) ? tau_w : 0.0);
-            X.sigma0 = sigma0;
-            X.alpha = alpha;
-            X.half_col = nhi[cs] * alpha * 0.5;
-            X.nHI = L.transposed ? nhiT.data() : nhi.data();
-            double *acc = L.transposed ? gT.data() : gacc;
+            const LayerPiece L = make_layer_piece(p, si, sj, sk, N, H.ex);
+            const LayerX X = host_layer_x(H, L, N, alpha, sigma0, tau_w, reading, cs);
             std::fill(lay.begin(), lay.end(), 0.0);
             std::fill(lay_id.begin(), lay_id.end(), -1);
-            const int Mx = std::min(isqrt_floor(Rsq), L.ext_d);
-            for (int m = 1; m <= Mx; ++m) {
-                const int rem = Rsq - m * m;
-                const int umax = std::min(std::min(m, L.ext_u), isqrt_floor(rem));
-                const int vcap = std::min(m, L.ext_v);
-                for (int bu = umax / tu; bu >= 0; --bu) {
-                    const int u0 = bu * tu;
-                    const int vmax = std::min(vcap, isqrt_floor(rem - u0 * u0));
-                    for (int bv = vmax / tv; bv >= 0; --bv) {
-                        LayerCell lc[64];
-                        bool act[64];
-                        for (int lane = 0; lane < 64; ++lane) {
-                            const int u = u0 + lane / tv, v = bv * tv + lane % tv;
-                            act[lane] = u <= umax && v <= vcap && u * u + v * v <= rem;
-                            if (!act[lane]) continue;
-                            if (m > 1) {   // neighbours of non-zero weight must hold layer m - 1
-                                const bool a0 = u > 0, a1 = u < m, b0 = v > 0, b1 = v < m;
-                                const bool need[4] = {a1 && b1, a0 && b1, a1 && b0, a0 && b0};
-                                for (int k = 0; k < 4; ++k)
-                                    if (need[k] && lay_id[(size_t)(u - (k & 1)) * S + v - (k >> 1)] != m - 1)
-                                        return -6;
-                            }
-                            layer_cell(L, X, m, u, v, lay.data(), S, lc[lane]);
-                        }
-                        for (int lane = 0; lane < 64; ++lane) {
-                            if (!act[lane]) continue;
-                            const int u = u0 + lane / tv, v = bv * tv + lane % tv;
-                            lay[(size_t)u * S + v] = lc[lane].Nout;
-                            lay_id[(size_t)u * S + v] = m;
-                            if (!lc[lane].owned) continue;
-                            if (coldens) coldens[layer_std_index(L, N, m, u, v)] = lc[lane].Nin;
-                            const double ta = sigma0 * lc[lane].Nin;
-                            if (ta < tp.tau_hi) {
-                                const float nd = neg_divdiff(T.data(), tp, ta, (double)(float)(sigma0 * lc[lane].dN));
-                                if (nd > 0.f)
-                                    acc[lc[lane].cp] += coef * (double)(nd * rcp_approx((float)lc[lane].r2));
-                            }
-                        }
-                    }
-                }
-            }
+            const int st = layer_forward_piece(L, X, Rsq, H.T.data(), H.tp, Q[s] * coef_unit, H.S, lay.data(),
+                                               lay_id.data(), L.transposed ? gT.data() : gacc, coldens, N,
+                                               nullptr);
+            if (st) return st;
         }
     }
     for (long i = 0; i < N; ++i)
@@ -240,45 +286,35 @@ extern "C" int hc_raytrace_layer(int N, double alpha, double sigma0, int n, doub
 }
 
 // Reverse mode on the CPU through the layer pieces, in the adjoint kernel's
-// order: forward columns layer by layer (stored per layer), then layers from
-// the outermost inward, layer m - 1 reloaded into the column buffer, tiles of
-// layer m in increasing u band and v, each tile reading its exit-column
-// adjoints, clearing them, then adding to its layer m - 1 neighbours.
-// dL/dn_HI of pyramids with dominant axis k goes through a [k][i][j] buffer
-// as on the GPU.  Returns -6 if a neighbour of non-zero weight is read from a
-// slot that does not hold layer m - 1.
+// order, per pyramid: (F) the forward pass fills the column record (exit
+// columns, listed cells); (G) the listed cells' rate terms in record order;
+// (R) layers from the outermost inward: layer m - 1's exit columns reloaded
+// into the column buffer, the rate's entry-column terms of layer m added to
+// its adjoint slots, then layer m's rectangle in chunks from the first to the
+// last, each chunk reading its slots, clearing them and adding to its layer
+// m - 1 neighbours.  dL/dn_HI of pyramids with dominant axis k goes through a
+// [k][i][j] buffer as on the GPU.  Returns -6 if a neighbour of non-zero
+// weight is read from a slot that does not hold layer m - 1, -7 if a record
+// slot is not a cell of its layer.
 extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n, double lg_lo,
                                       double lg_hi, const double *P, const double *dP, double tau_w,
                                       int reading, const float *nH, const float *xHI, long nsrc,
-                                      const int32_t *ijk, const double *Q, const float *R, int tv,
+                                      const int32_t *ijk, const double *Q, const float *R,
                                       const double *gbar, double *nbar, double *qbar)
 {
-    if (tv != 8 && tv != 16) return -1;
-    const int tu = 64 / tv;
-    TabParams tp;
-    std::vector<TabNode> T(n);
-    std::vector<double> m64(n);
-    prepare_table(n, lg_lo, lg_hi, P, dP, &tp, T.data(), m64.data());
+    HostLayerSetup H;
+    host_layer_setup(H, N, n, lg_lo, lg_hi, P, dP, nH, xHI, nsrc, R);
     const long n3 = (long)N * N * N;
-    std::vector<double> nhi(n3), nhiT(n3), gbT(n3), nbT(n3, 0.0);
+    std::vector<double> gbT(n3), nbT(n3, 0.0);
     for (long i = 0; i < N; ++i)
         for (long j = 0; j < N; ++j)
-            for (long k = 0; k < N; ++k) {
-                const long c = (i * N + j) * N + k;
-                nhi[c] = (double)nH[c] * (double)xHI[c];
-                nhiT[(k * N + i) * N + j] = nhi[c];
-                gbT[(k * N + i) * N + j] = gbar[c];
-            }
-    const Extent ex = make_extent(N);
-    float R_cap = 0.f;
-    for (long s = 0; s < nsrc; ++s) R_cap = R[s] > R_cap ? R[s] : R_cap;
-    int Mcap = isqrt_floor((int)std::floor((double)R_cap * (double)R_cap));
-    Mcap = Mcap < ex.neg ? Mcap : ex.neg;
-    Mcap = Mcap < 1 ? 1 : Mcap;
-    const int S = Mcap + 1;
-    const size_t SS = (size_t)(Mcap + 1) * S;
-    std::vector<double> cols(SS), abar(SS), stN((Mcap + 1) * SS), stdN((Mcap + 1) * SS);
+            for (long k = 0; k < N; ++k) gbT[(k * N + i) * N + j] = gbar[(i * N + j) * N + k];
+    const int S = H.S;
+    const size_t SS = (size_t)(H.Mcap + 1) * S;
+    std::vector<double> cols(SS), abar(SS), G(H.cap);
     std::vector<int> cols_id(SS);
+    std::vector<char> recmem(layer_record_bytes(H.cap, H.Mcap));
+    LayerRecord rec = layer_record_at(recmem.data(), H.cap);
     const double coef_unit = sigma0 / (4.0 * M_PI * alpha * alpha);
     for (long s = 0; s < nsrc; ++s) {
         qbar[s] = 0.0;
@@ -288,109 +324,83 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
         const double coef = Q[s] * coef_unit;
         double nb_src = 0.0, qb = 0.0;
         for (int p = 0; p < 24; ++p) {
-            const LayerPiece L = make_layer_piece(p, si, sj, sk, N, ex);
-            LayerX X;
-            X.N = N;
-            X.reading = reading;
-            X.tau_w = (float)(tau_w > 0 && std::isfinite(tau_w) ? tau_w : 0.0);
-            X.sigma0 = sigma0;
-            X.alpha = alpha;
-            X.half_col = nhi[cs] * alpha * 0.5;
-            X.nHI = L.transposed ? nhiT.data() : nhi.data();
+            const LayerPiece L = make_layer_piece(p, si, sj, sk, N, H.ex);
+            const LayerX X = host_layer_x(H, L, N, alpha, sigma0, tau_w, reading, cs);
             const double *gb = L.transposed ? gbT.data() : gbar;
             double *nb = L.transposed ? nbT.data() : nbar;
             const int Mx = std::min(isqrt_floor(Rsq), L.ext_d);
+            // (F)
             std::fill(cols.begin(), cols.end(), 0.0);
             std::fill(cols_id.begin(), cols_id.end(), -1);
-            auto in_layer = [&](int m, int u, int v) {
-                const int rem = Rsq - m * m;
-                if (rem < 0) return false;
-                const int umax = std::min(std::min(m, L.ext_u), isqrt_floor(rem));
-                const int vcap = std::min(m, L.ext_v);
-                return u <= umax && v <= vcap && u * u + v * v <= rem;
-            };
-            // forward (descending tiles, in place)
-            for (int m = 1; m <= Mx; ++m) {
-                const int rem = Rsq - m * m;
-                const int umax = std::min(std::min(m, L.ext_u), isqrt_floor(rem));
-                const int vcap = std::min(m, L.ext_v);
-                for (int bu = umax / tu; bu >= 0; --bu) {
-                    const int u0 = bu * tu;
-                    const int vmax = std::min(vcap, isqrt_floor(rem - u0 * u0));
-                    for (int bv = vmax / tv; bv >= 0; --bv) {
-                        LayerCell lc[64];
-                        bool act[64];
-                        for (int lane = 0; lane < 64; ++lane) {
-                            const int u = u0 + lane / tv, v = bv * tv + lane % tv;
-                            act[lane] = u <= umax && v <= vcap && u * u + v * v <= rem;
-                            if (act[lane]) layer_cell(L, X, m, u, v, cols.data(), S, lc[lane]);
-                        }
-                        for (int lane = 0; lane < 64; ++lane) {
-                            if (!act[lane]) continue;
-                            const int u = u0 + lane / tv, v = bv * tv + lane % tv;
-                            cols[(size_t)u * S + v] = lc[lane].Nout;
-                            stN[m * SS + (size_t)u * S + v] = lc[lane].Nout;
-                            stdN[m * SS + (size_t)u * S + v] = lc[lane].dN;
-                        }
+            int st = layer_forward_piece(L, X, Rsq, H.T.data(), H.tp, coef, S, cols.data(), cols_id.data(),
+                                         nullptr, nullptr, N, &rec);
+            if (st) return st;
+            // (G)
+            const int nrec = rec.litoff[Mx + 1];
+            for (int k = 0; k < nrec; ++k) {
+                G[k] = 0.0;
+                const double g = gb[rec.cp[k]];
+                if (g == 0.0) continue;
+                double ne, gG;
+                record_rate_adjoint(H.T.data(), H.m64.data(), H.tp, sigma0, alpha, coef, rec.ta[k], rec.dt[k],
+                                    rec.r2[k], rec.pm[k] >> 16, g, &G[k], &ne, &gG);
+                nb[rec.cp[k]] += ne;
+                qb += gG;
+            }
+            // (R)
+            std::fill(abar.begin(), abar.end(), 0.0);
+            long off = 0;
+            for (int m = 1; m <= Mx; ++m) off += layer_rect(L.ext_u, L.ext_v, Rsq, m).total;
+            for (int m = Mx; m >= 1; --m) {
+                const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
+                off -= r.total;   // first cell of layer m
+                if (m >= 2) {
+                    const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m - 1);
+                    for (int g = 0; g < rp.total; ++g) {
+                        int u, v;
+                        if (!rect_cell(rp, g, u, v)) continue;
+                        cols[(size_t)u * S + v] = rec.N[off - rp.total + g];
+                        cols_id[(size_t)u * S + v] = m - 1;
                     }
                 }
-            }
-            // reverse
-            std::fill(abar.begin(), abar.end(), 0.0);
-            for (int m = Mx; m >= 1; --m) {
-                if (m >= 2)
-                    for (int u = 0; u <= Mcap; ++u)
-                        for (int v = 0; v <= Mcap; ++v)
-                            if (in_layer(m - 1, u, v)) {
-                                cols[(size_t)u * S + v] = stN[(m - 1) * SS + (size_t)u * S + v];
-                                cols_id[(size_t)u * S + v] = m - 1;
-                            }
-                const int rem = Rsq - m * m;
-                const int umax = std::min(std::min(m, L.ext_u), isqrt_floor(rem));
-                const int vcap = std::min(m, L.ext_v);
-                for (int bu = 0; bu <= umax / tu; ++bu) {
-                    const int u0 = bu * tu;
-                    const int vmax = std::min(vcap, isqrt_floor(rem - u0 * u0));
-                    for (int bv = 0; bv <= vmax / tv; ++bv) {
-                        LayerAdj la[64];
-                        bool act[64];
-                        for (int lane = 0; lane < 64; ++lane) {
-                            const int u = u0 + lane / tv, v = bv * tv + lane % tv;
-                            act[lane] = u <= umax && v <= vcap && u * u + v * v <= rem;
-                            if (!act[lane]) continue;
-                            if (m > 1) {
-                                const bool a0 = u > 0, a1 = u < m, b0 = v > 0, b1 = v < m;
-                                const bool need[4] = {a1 && b1, a0 && b1, a1 && b0, a0 && b0};
-                                for (int k = 0; k < 4; ++k)
-                                    if (need[k] && cols_id[(size_t)(u - (k & 1)) * S + v - (k >> 1)] != m - 1)
-                                        return -6;
-                            }
-                            layer_cell_adjoint(L, X, T.data(), m64.data(), tp, coef, m, u, v, cols.data(), S,
-                                               abar[(size_t)u * S + v], stdN[m * SS + (size_t)u * S + v], gb,
-                                               la[lane]);
+                for (int k = rec.litoff[m]; k < rec.litoff[m + 1]; ++k) {
+                    const int pos = rec.pm[k] & 0xffff;
+                    if ((rec.pm[k] >> 16) != m) return -7;
+                    abar[pos] += G[k];
+                }
+                for (int c = 0; c < (r.total + 63) / 64; ++c) {
+                    LayerRev lr[64];
+                    bool act[64];
+                    int uu[64], vv[64];
+                    double Tin[64];
+                    for (int lane = 0; lane < 64; ++lane) {
+                        act[lane] = rect_cell(r, c * 64 + lane, uu[lane], vv[lane]);
+                        Tin[lane] = act[lane] ? abar[(size_t)uu[lane] * S + vv[lane]] : 0.0;
+                    }
+                    for (int lane = 0; lane < 64; ++lane)
+                        if (act[lane]) abar[(size_t)uu[lane] * S + vv[lane]] = 0.0;
+                    for (int lane = 0; lane < 64; ++lane) {
+                        if (!act[lane] || Tin[lane] == 0.0) continue;
+                        const int u = uu[lane], v = vv[lane];
+                        if (m > 1) {
+                            const bool a0 = u > 0, a1 = u < m, b0 = v > 0, b1 = v < m;
+                            const bool need[4] = {a1 && b1, a0 && b1, a1 && b0, a0 && b0};
+                            for (int k = 0; k < 4; ++k)
+                                if (need[k] && cols_id[(size_t)(u - (k & 1)) * S + v - (k >> 1)] != m - 1)
+                                    return -6;
                         }
-                        for (int lane = 0; lane < 64; ++lane) {
-                            if (!act[lane]) continue;
-                            const int u = u0 + lane / tv, v = bv * tv + lane % tv;
-                            abar[(size_t)u * S + v] = 0.0;
-                        }
-                        for (int lane = 0; lane < 64; ++lane) {
-                            if (!act[lane]) continue;
-                            const int u = u0 + lane / tv, v = bv * tv + lane % tv;
-                            if (m >= 2)
-                                for (int k = 0; k < 4; ++k)
-                                    if (la[lane].Mbar[k] != 0.0)
-                                        abar[(size_t)(u - (k & 1)) * S + (v - (k >> 1))] += la[lane].Mbar[k];
-                            nb[la[lane].cp] += la[lane].nbar;
-                            nb_src += la[lane].nbar_src;
-                            qb += la[lane].qbar;
-                        }
+                        layer_cell_reverse(L, X, m, u, v, cols.data(), S, Tin[lane], lr[lane]);
+                        for (int k = 0; k < 4; ++k)
+                            if (lr[lane].Mbar[k] != 0.0)
+                                abar[(size_t)(u - (k & 1)) * S + (v - (k >> 1))] += lr[lane].Mbar[k];
+                        nb[lr[lane].cp] += lr[lane].nbar;
+                        nb_src += lr[lane].nbar_src;
                     }
                 }
             }
         }
         double nb1, q1;
-        source_cell_adjoint(T.data(), m64.data(), tp, sigma0, alpha, Q[s], nhi[cs], gbar[cs], &nb1, &q1);
+        source_cell_adjoint(H.T.data(), H.m64.data(), H.tp, sigma0, alpha, Q[s], H.nhi[cs], gbar[cs], &nb1, &q1);
         nbar[cs] += nb_src + nb1;
         qbar[s] += (qb + q1) / Q[s];
     }

@@ -40,9 +40,9 @@ def load():
         lib.hc_raytrace_grad.restype = i
         lib.hc_raytrace_grad.argtypes = [i, d, d, i, d, d, p, p, d, i, p, p, l, p, p, p, f, f, i, p, p, p]
         lib.hc_raytrace_layer.restype = i
-        lib.hc_raytrace_layer.argtypes = [i, d, d, i, d, d, p, p, d, i, p, p, l, p, p, p, i, p, p]
+        lib.hc_raytrace_layer.argtypes = [i, d, d, i, d, d, p, p, d, i, p, p, l, p, p, p, p, p]
         lib.hc_raytrace_layer_grad.restype = i
-        lib.hc_raytrace_layer_grad.argtypes = [i, d, d, i, d, d, p, p, d, i, p, p, l, p, p, p, i, p, p, p]
+        lib.hc_raytrace_layer_grad.argtypes = [i, d, d, i, d, d, p, p, d, i, p, p, l, p, p, p, p, p, p]
         lib.hc_rows.restype = i
         lib.hc_rows.argtypes = [i, i, i, i, i, p, p]
         _lib = lib
@@ -54,9 +54,9 @@ def _p(a):
 
 
 def raytrace(N, cell_cm, sigma0, table, n_H, x_HI, ijk, Q, R, tau_w=0.6, reading=0, type_force=-1,
-             R_whole=10.0, R_oct=30.0, coldens=False, layer_tv=None):
+             R_whole=10.0, R_oct=30.0, coldens=False, layers=False):
     """type_force: shell piece kind for every source (0, 1, 2), or -1 by radius;
-    layer_tv (8 or 16): every source as layer pyramids with that tile width."""
+    layers: every source as layer pyramids."""
     lib = load()
     g = np.zeros(N ** 3)
     cd = np.zeros(N ** 3) if coldens else None
@@ -66,10 +66,10 @@ def raytrace(N, cell_cm, sigma0, table, n_H, x_HI, ijk, Q, R, tau_w=0.6, reading
     ijk = np.ascontiguousarray(ijk, np.int32)
     Q = np.ascontiguousarray(Q, np.float64)
     R = np.ascontiguousarray(R, np.float32)
-    if layer_tv is not None:
+    if layers:
         st = lib.hc_raytrace_layer(N, cell_cm, sigma0, len(P), table.lg_lo, table.lg_hi, _p(P), _p(dP),
                                    float(tau_w), reading, _p(nH), _p(xH), len(Q), _p(ijk), _p(Q),
-                                   _p(R), int(layer_tv), _p(g), _p(cd))
+                                   _p(R), _p(g), _p(cd))
     else:
         st = lib.hc_raytrace(N, cell_cm, sigma0, len(P), table.lg_lo, table.lg_hi, _p(P), _p(dP),
                              float(tau_w), reading, _p(nH), _p(xH), len(Q), _p(ijk), _p(Q), _p(R),
@@ -100,9 +100,9 @@ def rows(N, type_, piece, Rsq, q):
 
 
 def raytrace_grad(N, cell_cm, sigma0, table, n_H, x_HI, ijk, Q, R, gbar, tau_w=0.6, reading=0,
-                  type_force=-1, R_whole=10.0, R_oct=30.0, layer_tv=None):
-    """(dL/dn_H, dL/dx_HI, dL/dQ) for dL/dGamma = gbar (FP64); layer_tv (8 or
-    16): every source as layer pyramids."""
+                  type_force=-1, R_whole=10.0, R_oct=30.0, layers=False):
+    """(dL/dn_H, dL/dx_HI, dL/dQ) for dL/dGamma = gbar (FP64); layers: every
+    source as layer pyramids."""
     lib = load()
     P, dP = np.ascontiguousarray(table.P, np.float64), np.ascontiguousarray(table.dP, np.float64)
     nH = np.ascontiguousarray(n_H, np.float32)
@@ -113,10 +113,10 @@ def raytrace_grad(N, cell_cm, sigma0, table, n_H, x_HI, ijk, Q, R, gbar, tau_w=0
     gb = np.ascontiguousarray(gbar, np.float64)
     nbar = np.zeros(N ** 3)
     qbar = np.zeros(len(Q))
-    if layer_tv is not None:
+    if layers:
         st = lib.hc_raytrace_layer_grad(N, cell_cm, sigma0, len(P), table.lg_lo, table.lg_hi, _p(P),
                                         _p(dP), float(tau_w), reading, _p(nH), _p(xH), len(Q), _p(ijk),
-                                        _p(Q), _p(R), int(layer_tv), _p(gb), _p(nbar), _p(qbar))
+                                        _p(Q), _p(R), _p(gb), _p(nbar), _p(qbar))
     else:
         st = lib.hc_raytrace_grad(N, cell_cm, sigma0, len(P), table.lg_lo, table.lg_hi, _p(P), _p(dP),
                                   float(tau_w), reading, _p(nH), _p(xH), len(Q), _p(ijk), _p(Q), _p(R),

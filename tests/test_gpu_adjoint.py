@@ -143,3 +143,83 @@ def test_autograd_function(asora, bb):
     torch.testing.assert_close(nH.grad, dn, rtol=1e-5, atol=1e-6 * float(dn.abs().max()))
     torch.testing.assert_close(xH.grad, dx, rtol=1e-5, atol=1e-6 * float(dx.abs().max()))
     torch.testing.assert_close(Q.grad, dq, rtol=1e-6, atol=0)
+    # the same through the recomputing backward
+    for t_ in (nH, xH, Q):
+        t_.grad = None
+    gam = asora.raytrace(ctx, nH, xH, ijk, Q, R, store=False)
+    (wt * torch.log10(gam.double() + 1e-20)).sum().backward()
+    torch.testing.assert_close(nH.grad, dn, rtol=1e-5, atol=1e-6 * float(dn.abs().max()))
+    torch.testing.assert_close(Q.grad, dq, rtol=1e-6, atol=0)
+
+
+def test_kept_records_match_recompute_and_oracle(asora, bb):
+    """Forward with ASORA_STORE keeps the pyramids' column records; the
+    backward that reads them gives the recomputing backward's gradients and
+    the oracle's.  Uneven radii cover whole-source and octant pieces (always
+    recomputed) next to the pyramids."""
+    print("case kept records c4", flush=True)
+    w, g, wt = _case("c4")
+    gbar = _loss_grad(g, wt)
+    on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
+                                      w.src.R, gbar)
+    ctx = asora.Asora(w.N, w.cell_cm, bb.P, bb.dP, bb.lg_lo, bb.lg_hi)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    nH, xH, ijk, Q, R, gb = t(w.n_H), t(w.x_HI), t(w.src.ijk), t(w.src.Q), t(w.src.R), t(gbar)
+    ctx.raytrace(nH, xH, ijk, Q, R, store=True)
+    kept, need, alloc = ctx.store_info()
+    assert kept and 0 < need <= alloc
+    ks = ctx.backward(nH, xH, ijk, Q, R, gb, store=True)
+    rc = ctx.backward(nH, xH, ijk, Q, R, gb)
+    ctx.check()
+    for a, b, o, name in zip(ks, rc, (on, ox, oq), ("dL/dn_H", "dL/dx_HI", "dL/dQ")):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-12 * np.abs(b).max(), err_msg=name)
+        if name == "dL/dQ":
+            np.testing.assert_allclose(a, o, rtol=1e-5)
+        else:
+            assert_grad_parity(a, o, 1e-5, what=name)
+    # uneven radii: whole-source, octant and pyramid pieces in one call
+    print("case kept records uneven", flush=True)
+    w, g, wt = _case("c2", N=40, n_src=24, R=(2.0, 38.0))
+    gbar = _loss_grad(g, wt)
+    on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
+                                      w.src.R, gbar)
+    ctx = asora.Asora(w.N, w.cell_cm, bb.P, bb.dP, bb.lg_lo, bb.lg_hi)
+    nH, xH, ijk, Q, R, gb = t(w.n_H), t(w.x_HI), t(w.src.ijk), t(w.src.Q), t(w.src.R), t(gbar)
+    ctx.raytrace(nH, xH, ijk, Q, R, store=True)
+    assert ctx.store_info()[0]
+    gn, gx, gq = (a.cpu().numpy() for a in ctx.backward(nH, xH, ijk, Q, R, gb, store=True))
+    ctx.check()
+    assert_grad_parity(gn, on, 1e-5, what="dL/dn_H")
+    assert_grad_parity(gx, ox, 1e-5, what="dL/dx_HI")
+    np.testing.assert_allclose(gq, oq, rtol=1e-5)
+
+
+def test_kept_records_fall_back_to_recompute(asora, bb):
+    """Records that do not fit the budget are not kept; records kept for other
+    input buffers are not used: both backwards recompute."""
+    print("case kept records fallback", flush=True)
+    w, g, wt = _case("c2", N=32, n_src=6, R=(16.0, 20.0))
+    gbar = _loss_grad(g, wt)
+    ctx = asora.Asora(w.N, w.cell_cm, bb.P, bb.dP, bb.lg_lo, bb.lg_hi)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    nH, xH, ijk, Q, R, gb = t(w.n_H), t(w.x_HI), t(w.src.ijk), t(w.src.Q), t(w.src.R), t(gbar)
+    on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
+                                      w.src.R, gbar)
+    ctx.set_store_budget(1024)
+    ctx.raytrace(nH, xH, ijk, Q, R, store=True)
+    kept, need, _ = ctx.store_info()
+    assert not kept and need > 1024
+    gn, gx, gq = (a.cpu().numpy() for a in ctx.backward(nH, xH, ijk, Q, R, gb, store=True))
+    assert_grad_parity(gn, on, 1e-5, what="dL/dn_H")
+    np.testing.assert_allclose(gq, oq, rtol=1e-5)
+    # records kept for a fully neutral x_HI; the backward is asked about the real one
+    ctx.set_store_budget(0)
+    x_other = torch.ones_like(xH)
+    ctx.raytrace(nH, x_other, ijk, Q, R, store=True)
+    assert ctx.store_info()[0]
+    gn, gx, gq = (a.cpu().numpy() for a in ctx.backward(nH, xH, ijk, Q, R, gb, store=True))
+    ctx.check()
+    assert_grad_parity(gn, on, 1e-5, what="dL/dn_H")
+    assert_grad_parity(gx, ox, 1e-5, what="dL/dx_HI")
+    np.testing.assert_allclose(gq, oq, rtol=1e-5)

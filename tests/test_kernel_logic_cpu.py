@@ -23,9 +23,8 @@ def bb():
 
 
 # shell piece kinds 0, 1, 2 and the layer pyramids with both tile widths
-KINDS = [dict(type_force=0), dict(type_force=1), dict(type_force=2), dict(layer_tv=8),
-         dict(layer_tv=16)]
-KIND_IDS = ["whole", "octants", "shell-pyramids", "layers-tv8", "layers-tv16"]
+KINDS = [dict(type_force=0), dict(type_force=1), dict(type_force=2), dict(layers=True)]
+KIND_IDS = ["whole", "octants", "shell-pyramids", "layers"]
 
 
 @pytest.mark.parametrize("kind", KINDS, ids=KIND_IDS)
@@ -50,8 +49,7 @@ def test_lognormal_sources(bb, kind, tau_w, reading):
     assert_parity(g, o, TOL)
 
 
-@pytest.mark.parametrize("tv", [8, 16])
-def test_layers_ionized_medium_and_column(bb, tv):
+def test_layers_ionized_medium_and_column(bb):
     """Mostly ionized medium (every cell carries a rate) and the column
     density output of a single source through the layer pyramids, with a
     source near the box corner so that offsets wrap."""
@@ -60,7 +58,7 @@ def test_layers_ionized_medium_and_column(bb, tv):
     ijk = np.array([[1, 38, 39]], np.int32)
     o, ocd = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, xH, ijk, w.src.Q, w.src.R, coldens=True)
     g, cd = hostsweep.raytrace(w.N, w.cell_cm, oracle.SIGMA0, bb, w.n_H, xH, ijk, w.src.Q,
-                               w.src.R, coldens=True, layer_tv=tv)
+                               w.src.R, coldens=True, layers=True)
     assert_parity(g, o, TOL)
     assert_parity(cd, ocd, TOL, what="coldens")
     assert np.count_nonzero(g) > 0.9 * np.count_nonzero(o)
@@ -94,7 +92,7 @@ def test_grey_and_thin(bb):
     g = hostsweep.raytrace(w.N, w.cell_cm, oracle.SIGMA0, bb, thin, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
     assert_parity(g, o, TOL)
     g = hostsweep.raytrace(w.N, w.cell_cm, oracle.SIGMA0, bb, thin, w.x_HI, w.src.ijk, w.src.Q, w.src.R,
-                           layer_tv=16)
+                           layers=True)
     assert_parity(g, o, TOL)
     zero = np.zeros_like(w.n_H)
     o = oracle.raytrace(w.N, w.cell_cm, bb, zero, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
@@ -178,8 +176,7 @@ def test_adjoint_matches_oracle_reverse(bb, kind, tau_w, reading):
     np.testing.assert_allclose(hq, oq, rtol=1e-6)
 
 
-@pytest.mark.parametrize("tv", [8, 16])
-def test_layer_adjoint_extent_clip_and_wrap(bb, tv):
+def test_layer_adjoint_extent_clip_and_wrap(bb):
     """Layer adjoint with radii beyond the box (extent clip, even and odd N)
     and sources on the box faces, against the oracle's reverse mode."""
     for N, ijk in ((15, [[0, 7, 14], [3, 3, 3]]), (16, [[15, 0, 15], [8, 8, 0]])):
@@ -191,7 +188,7 @@ def test_layer_adjoint_extent_clip_and_wrap(bb, tv):
         on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
                                           w.src.R, gbar)
         hn, hx, hq = hostsweep.raytrace_grad(w.N, w.cell_cm, oracle.SIGMA0, bb, w.n_H, w.x_HI,
-                                             w.src.ijk, w.src.Q, w.src.R, gbar, layer_tv=tv)
+                                             w.src.ijk, w.src.Q, w.src.R, gbar, layers=True)
         from tests.parity import assert_grad_parity
         assert_grad_parity(hn, on, 1e-5, what="dL/dn_H")
         assert_grad_parity(hx, ox, 1e-5, what="dL/dx_HI")
