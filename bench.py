@@ -91,7 +91,8 @@ def reduce_pmc(directory: str, workload: str):
     fetch/ and write/ (FETCH_SIZE, WRITE_SIZE of this benchmark), and
     copy_fetch/ and copy_write/ (the same counters for `--copy-calibration`,
     a 1 GiB device copy).  Each counter is scaled by known bytes / counted
-    bytes of the copy, per launch of each sweep kernel."""
+    bytes of the copy; the result is the mean per dispatch of every sweep
+    kernel (each is launched once per call)."""
     def load(sub):
         files = glob.glob(os.path.join(directory, sub, "**", "*counter_collection.csv"), recursive=True)
         if not files:
@@ -113,28 +114,25 @@ def reduce_pmc(directory: str, workload: str):
            "calibration": {"copy_bytes": copy_bytes, "fetch_kib": cf_kib, "write_kib": cw_kib,
                            "read_factor": f_read, "write_factor": f_write},
            "kernels": {}}
-    for key, subs in KERNELS.items():
-        match = lambda name: any(sub + "<" in name for sub in subs)
-        if not any(match(n) for n in fetch) or not any(match(n) for n in write):
+
+    def short(name):
+        n = name.split("(")[0].replace("void ", "").replace("asora::", "")
+        return n
+
+    for name, c in fetch.items():
+        k = short(name)
+        if not any(k.startswith(sub) for subs in KERNELS.values() for sub in subs):
             continue
-        # kind 0 (fwd_wave<0> / adj_wave<0>) is launched once per call, so its
-        # dispatch count is the number of calls; the per-call sum over the kinds
-        # is what one call moves
-        first = subs[0] + "<0>"
-        nf = sum(len(c.get("FETCH_SIZE", [])) for n, c in fetch.items() if match(n))
-        calls = sum(len(c.get("FETCH_SIZE", [])) for n, c in fetch.items() if first in n)
-        calls_w = sum(len(c.get("WRITE_SIZE", [])) for n, c in write.items() if first in n)
-        if calls == 0 or calls != calls_w:
-            raise SystemExit(f"{key}: {calls} / {calls_w} calls in the two counter runs")
-        fsum = sum(v for n, c in fetch.items() if match(n) for v in c.get("FETCH_SIZE", []))
-        wsum = sum(v for n, c in write.items() if match(n) for v in c.get("WRITE_SIZE", []))
-        res["kernels"][key] = {
-            "kernel": "+".join(subs),
-            "fetch_bytes_per_call": fsum / calls * 1024.0 * f_read,
-            "write_bytes_per_call": wsum / calls * 1024.0 * f_write,
-            "hbm_bytes_per_call": (fsum * f_read + wsum * f_write) / calls * 1024.0,
-            "dispatches": nf, "calls": calls,
-        }
+        wname = [n for n in write if short(n) == k]
+        if not wname:
+            continue
+        fv, wv = c.get("FETCH_SIZE", []), write[wname[0]].get("WRITE_SIZE", [])
+        if not fv or not wv:
+            continue
+        fb = sum(fv) / len(fv) * 1024.0 * f_read
+        wb = sum(wv) / len(wv) * 1024.0 * f_write
+        res["kernels"][k] = {"fetch_bytes_per_dispatch": fb, "write_bytes_per_dispatch": wb,
+                             "hbm_bytes_per_dispatch": fb + wb, "dispatches": len(fv)}
     os.makedirs(os.path.dirname(pmc_file(workload)), exist_ok=True)
     with open(pmc_file(workload), "w") as f:
         json.dump(res, f, indent=1)
@@ -179,6 +177,7 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-source form")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default scheduling parameters")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--reduce-pmc", metavar="DIR", help="reduce rocprofv3 counter CSVs and exit")
@@ -232,33 +231,74 @@ def main():
     wt = torch.from_numpy(np.random.default_rng(w.seed + 1).standard_normal(n3)).to(dev)
     gbar = (wt / ((gamma.double() + 1e-20) * math.log(10))).contiguous()
 
-    def fwd(profile=False, plain=False, n=None):
+    def fwd(profile=False, plain=False, n=None, store=False):
         s = slice(0, n)
-        ctx.raytrace(nH, xH, ijk[s], Q[s], R[s], R_max=R_max, out=gamma, plain=plain, profile=profile)
+        ctx.raytrace(nH, xH, ijk[s], Q[s], R[s], R_max=R_max, out=gamma, plain=plain, profile=profile,
+                     store=store)
 
-    def adj(profile=False):
-        ctx.backward(nH, xH, ijk, Q, R, gbar, R_max=R_max, profile=profile, out=(dn, dx, dq))
+    def adj(profile=False, store=False):
+        ctx.backward(nH, xH, ijk, Q, R, gbar, R_max=R_max, profile=profile, out=(dn, dx, dq), store=store)
 
-    # ---- the step: forward + adjoint, sweep kernels timed with HIP events
+    # ---- scheduling parameters: the library's autotuner on this workload
+    # (forward with kept records + adjoint), before anything is timed
+    tuning = {"autotuned": False}
+    if not args.no_tune:
+        print("[bench] autotune", file=sys.stderr, flush=True)
+        best, rep = ctx.autotune(nH, xH, ijk, Q, R, R_max=R_max, passes=2)
+        tuning = {"autotuned": True, "candidates": len(rep), "best_ms": best}
+    tw, to, twv, tsw = ctx.get_tuning()
+    tuning.update({"R_whole": tw, "R_oct": to, "max_waves": twv, "pyramid_sweep": tsw})
+
+    def timed_step(store):
+        """Mean wall ms per step over args.steps steps (warm-up first), and the
+        HIP-event durations of the sweep kernels and of the whole calls."""
+        for _ in range(args.warmup):
+            fwd(store=store)
+            adj(store=store)
+        torch.cuda.synchronize()
+        ctx.profile_read()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fwd(profile=True, store=store)
+            adj(profile=True, store=store)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        ctx.check()
+        prof = ctx.profile_read()
+        assert len(prof) == 2 * args.steps, len(prof)
+        return {"ms": ms, "fwd_sweep_ms": float(np.mean([p[0] for p in prof[0::2]])),
+                "adj_sweep_ms": float(np.mean([p[0] for p in prof[1::2]])),
+                "fwd_call_ms": float(np.mean([p[1] for p in prof[0::2]])),
+                "adj_call_ms": float(np.mean([p[1] for p in prof[1::2]]))}
+
+    # ---- the step: forward + adjoint, sweep kernels timed with HIP events.
+    # With the column records kept by the forward when they fit in memory
+    # (what the differentiable path does), else recomputed by the adjoint.
+    print(f"[bench] timing {args.steps} steps (kept column records)", file=sys.stderr, flush=True)
+    step_kept = timed_step(True)
+    kept, keep_bytes, _ = ctx.store_info()
+    print(f"[bench] timing {args.steps} steps (recompute)", file=sys.stderr, flush=True)
+    step_rc = timed_step(False)
+    step = step_kept if kept else step_rc
+    ms = step["ms"]
+    fwd_sweep_ms, adj_sweep_ms = step["fwd_sweep_ms"], step["adj_sweep_ms"]
+    fwd_call_ms, adj_call_ms = step["fwd_call_ms"], step["adj_call_ms"]
+
+    # ---- the same step recorded once as a HIP graph and replayed
+    print("[bench] recorded step", file=sys.stderr, flush=True)
+    graph = ctx.record_step(nH, xH, ijk, Q, R, gamma, dL_dgamma=gbar, grads=(dn, dx, dq), R_max=R_max,
+                            store=kept)
     for _ in range(args.warmup):
-        fwd()
-        adj()
+        graph.launch()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     torch.cuda.synchronize()
-    ctx.profile_read()
-    print(f"[bench] warmup done, timing {args.steps} steps", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
+    ev[0].record()
     for _ in range(args.steps):
-        fwd(profile=True)
-        adj(profile=True)
+        graph.launch()
+    ev[1].record()
     torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) / args.steps * 1e3
-    ctx.check()
-    prof = ctx.profile_read()
-    assert len(prof) == 2 * args.steps, len(prof)
-    fwd_sweep_ms = float(np.mean([p[0] for p in prof[0::2]]))
-    adj_sweep_ms = float(np.mean([p[0] for p in prof[1::2]]))
-    fwd_call_ms = float(np.mean([p[1] for p in prof[0::2]]))
-    adj_call_ms = float(np.mean([p[1] for p in prof[1::2]]))
+    graph_ms = ev[0].elapsed_time(ev[1]) / args.steps
+    graph.close()
 
     # ---- batched forward alone
     print("[bench] batched forward", file=sys.stderr, flush=True)
@@ -272,16 +312,23 @@ def main():
     if os.path.exists(pmc_file(args.workload)):
         pmc = json.load(open(pmc_file(args.workload)))
         if pmc.get("kernel_sha") == kernel_sha() and pmc.get("workload") == args.workload:
-            traffic = {k: v.get("hbm_bytes_per_call") for k, v in pmc.get("kernels", {}).items()}
+            traffic = {k: v.get("hbm_bytes_per_dispatch") for k, v in pmc.get("kernels", {}).items()}
 
-    # the dominant sweep kernel: layer pyramids (sweep 3) or shell pyramids
-    big = ctx.get_tuning()[3] == 3 and R_max > ctx.get_tuning()[1]
-    kname = {"fwd": "fwd_layer" if big else "fwd_wave", "adj": "adj_layer" if big else "adj_wave"}
+    # the dominant sweep kernels: layer pyramids (sweep 3) or shell pyramids;
+    # the step's adjoint reads kept records or recomputes; the forward alone
+    # keeps nothing
+    tun = ctx.get_tuning()
+    big = R_max > tun[1]
+    layer = big and tun[3] == 3
+    kname = {"fwd": "fwd_layer<false>" if layer else "fwd_wave<2>",
+             "adj": ("adj_layer<true>" if kept else "adj_layer<false>") if layer else "adj_wave<2>"}
+    if not big:
+        kname = {"fwd": "fwd_wave<1>", "adj": "adj_wave<1>"}
 
     def roof(bytes_per_sv, sweep_ms, kernel, key):
         achieved = bytes_per_sv * work / (sweep_ms * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic.get(key),
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic.get(kernel),
                 "kernel": kernel, "launch_ms": sweep_ms,
                 "alg_bytes_per_source_voxel": bytes_per_sv, "source_voxels_per_launch": work}
 
@@ -291,14 +338,23 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64/f32", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {spec['desc']}", "grid": w.N,
                    "n_sources": len(w.src), "source_voxels": work, "seed": w.seed,
-                   "step": "batched forward + adjoint (recompute)"},
+                   "step": "batched forward + adjoint" + (" (columns kept by the forward)" if kept
+                                                          else " (columns recomputed by the adjoint)")},
         # the adjoint sweep dominates the step
         "roofline": roof(ADJ_BYTES_PER_SV, adj_sweep_ms, kname["adj"], "adj"),
         "fwd": {"ns_per_source_voxel": fwd_ms * 1e6 / work, "ms_per_call": fwd_ms,
-                "roofline": roof(FWD_BYTES_PER_SV, fwd_sweep_ms, kname["fwd"], "fwd")},
+                "roofline": roof(FWD_BYTES_PER_SV, step_rc["fwd_sweep_ms"], kname["fwd"], "fwd")},
         "adjoint": {"ns_per_source_voxel": (ms - fwd_ms) * 1e6 / work,
                     "sweep_ms": adj_sweep_ms, "call_ms": adj_call_ms},
         "fwd_call_ms_in_step": fwd_call_ms,
+        "tuning": tuning,
+        "graph_step": {"ms_per_step": graph_ms, "ns_per_source_voxel": graph_ms * 1e6 / work},
+        "steps_by_mode": {
+            "kept": {"ns_per_source_voxel": step_kept["ms"] * 1e6 / work, "ms_per_step": step_kept["ms"],
+                     "adj_sweep_ms": step_kept["adj_sweep_ms"], "fwd_sweep_ms": step_kept["fwd_sweep_ms"],
+                     "records_kept": kept, "record_bytes": keep_bytes},
+            "recompute": {"ns_per_source_voxel": step_rc["ms"] * 1e6 / work, "ms_per_step": step_rc["ms"],
+                          "adj_sweep_ms": step_rc["adj_sweep_ms"], "fwd_sweep_ms": step_rc["fwd_sweep_ms"]}},
     }
 
     if not args.no_plain:

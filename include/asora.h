@@ -248,6 +248,69 @@ asora_status asora_set_store_budget(asora_ctx *ctx, uint64_t bytes);
 asora_status asora_set_tuning(asora_ctx *ctx, float R_whole, float R_oct, int32_t max_waves,
                               int32_t pyramid_sweep);
 
+/* asora_autotune flags */
+#define ASORA_TUNE_RETUNE 0x1u  /* time again even if this workload was tuned before */
+
+/*
+ * asora_autotune -- pick the scheduling parameters of asora_set_tuning by
+ * timing candidates on the given inputs (the sources' independence, Section
+ * 2.2, leaves the order and grouping of the work free; this chooses it by
+ * measurement, not by rule).  Coordinate descent over: the sweep of pyramid
+ * pieces (layers, shells), the waves per work-group (4, 8, 12, 16), R_oct
+ * (8, 10, 12, 15, 20) and R_whole (3, 4, 6, 8); every candidate is one
+ * warm-up call and the median of three calls timed with HIP events on
+ * `stream`.  passes = 1 times the forward; passes = 2 the forward with
+ * ASORA_STORE followed by the adjoint (with dL/dgamma = 1).  The best
+ * candidate is kept in the context (asora_get_tuning reads it) and cached
+ * per (n_src, R_max, passes): a later call for the same key sets the cached
+ * parameters without timing, unless flags has ASORA_TUNE_RETUNE.
+ *
+ *   n_H .. R_max  as for asora_raytrace (device buffers; only read).
+ *   passes        1 or 2.
+ *   best_ms       host, may be NULL: time of the best candidate (ms).
+ *   report        host array of max_report x 5 floats (may be NULL when
+ *                 max_report = 0): per timed candidate R_whole, R_oct,
+ *                 max_waves, pyramid_sweep, ms; *n_report (may be NULL)
+ *                 receives the number of rows written.
+ * Allocates scratch outputs of the size of the grid for its duration and
+ * waits for `stream`.  ASORA_ESTATE while a recorded graph of the context
+ * exists.
+ */
+asora_status asora_autotune(asora_ctx *ctx, const float *n_H, const float *x_HI, int64_t n_src,
+                            const int32_t *src_ijk, const double *src_Q, const float *src_R,
+                            float R_max, int32_t passes, uint32_t flags, void *stream,
+                            float *best_ms, int32_t max_report, int32_t *n_report, float *report);
+
+/*
+ * asora_graph_create -- record one ray-tracing step into a HIP graph owned
+ * by the library, to be replayed with asora_graph_launch: asora_raytrace with
+ * the given arguments (no column output) and, if dL_dgamma is not NULL,
+ * asora_raytrace_backward right after it (flags ASORA_ACCUMULATE and
+ * ASORA_STORE carried over).  The step is first run once eagerly on a
+ * private stream (this sizes every library buffer, so that recording
+ * allocates nothing; it writes the outputs), then recorded.  A replay reads
+ * the inputs' current contents and writes the same outputs; every buffer
+ * given here must stay allocated while the graph exists.  While a graph of a
+ * context exists, a call that would have to grow one of the context's
+ * buffers (more sources, a larger R_max, kept records of another size, a
+ * retuning) fails with ASORA_ESTATE instead.
+ *
+ *   flags   ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_STORE (not ASORA_PROFILE).
+ *   out     host, receives the graph.
+ */
+typedef struct asora_graph asora_graph;
+asora_status asora_graph_create(asora_ctx *ctx, const float *n_H, const float *x_HI, int64_t n_src,
+                                const int32_t *src_ijk, const double *src_Q, const float *src_R,
+                                float R_max, float *gamma, const double *dL_dgamma, float *dL_dnH,
+                                float *dL_dxHI, double *dL_dQ, uint32_t flags, asora_graph **out);
+
+/* asora_graph_launch -- replay the recorded step on `stream` (asynchronous). */
+asora_status asora_graph_launch(asora_graph *graph, void *stream);
+
+/* asora_graph_free -- wait for the device and release the graph.  NULL is
+ * accepted.  Free every graph of a context before the context. */
+asora_status asora_graph_free(asora_graph *graph);
+
 /*
  * asora_get_tuning -- the current scheduling parameters (any pointer may be
  * NULL).
@@ -284,7 +347,8 @@ asora_status asora_profile_read(asora_ctx *ctx, int32_t max_calls, int32_t *n_ca
 const char *asora_last_error(const asora_ctx *ctx);
 
 /* asora_free -- release the context and its device memory (waits for the
- * device).  NULL is accepted. */
+ * device).  NULL is accepted.  ASORA_ESTATE (nothing freed) while a recorded
+ * graph of the context exists. */
 asora_status asora_free(asora_ctx *ctx);
 
 #ifdef __cplusplus

@@ -66,6 +66,16 @@ _lib.asora_store_info.argtypes = [_p, ctypes.POINTER(_c_int), ctypes.POINTER(cty
                                   ctypes.POINTER(ctypes.c_uint64)]
 _lib.asora_set_store_budget.restype = _c_int
 _lib.asora_set_store_budget.argtypes = [_p, ctypes.c_uint64]
+_lib.asora_autotune.restype = _c_int
+_lib.asora_autotune.argtypes = [_p, _p, _p, _c_i64, _p, _p, _p, _c_f, _c_int, _c_u32, _p,
+                                ctypes.POINTER(_c_f), _c_int, ctypes.POINTER(_c_int), _p]
+_lib.asora_graph_create.restype = _c_int
+_lib.asora_graph_create.argtypes = [_p, _p, _p, _c_i64, _p, _p, _p, _c_f, _p, _p, _p, _p, _p, _c_u32,
+                                    ctypes.POINTER(_p)]
+_lib.asora_graph_launch.restype = _c_int
+_lib.asora_graph_launch.argtypes = [_p, _p]
+_lib.asora_graph_free.restype = _c_int
+_lib.asora_graph_free.argtypes = [_p]
 _lib.asora_last_error.restype = ctypes.c_char_p
 _lib.asora_last_error.argtypes = [_p]
 _lib.asora_free.restype = _c_int
@@ -139,8 +149,9 @@ class Asora:
         self._h = h
 
     def close(self):
+        """Release the context (not while a StepGraph of it is open)."""
         if getattr(self, "_h", None):
-            _lib.asora_free(self._h)
+            _raise(_lib.asora_free(self._h), self._h)
             self._h = None
 
     def __del__(self):
@@ -230,6 +241,41 @@ class Asora:
                                        _np_ptr(b)), self._h)
         return list(zip(a[:n.value].tolist(), b[:n.value].tolist()))
 
+    def autotune(self, n_H, x_HI, ijk, Q, R=None, R_max=None, passes=1, retune=False, stream=None):
+        """Time candidate scheduling parameters on these inputs (library's
+        asora_autotune) and keep the fastest.  Returns (best_ms, report) with one
+        dict per timed candidate."""
+        ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
+        rep = np.zeros((64, 5), np.float32)
+        best, nrep = _c_f(), _c_int()
+        _raise(_lib.asora_autotune(self._h, _dptr(n_H), _dptr(x_HI), n, _dptr(ijk), _dptr(Q), _dptr(R),
+                                   R_max, int(passes), 1 if retune else 0, _stream_ptr(stream),
+                                   ctypes.byref(best), 64, ctypes.byref(nrep),
+                                   rep.ctypes.data_as(_p)), self._h)
+        keys = ("R_whole", "R_oct", "max_waves", "pyramid_sweep", "ms")
+        return best.value, [dict(zip(keys, map(float, r))) for r in rep[:nrep.value]]
+
+    def record_step(self, n_H, x_HI, ijk, Q, R, gamma, dL_dgamma=None, grads=None, R_max=None,
+                    store=False, accumulate=False, plain=False):
+        """Record the step (forward into gamma; with dL_dgamma also the adjoint
+        into grads = (dn, dx, dq)) as a HIP graph: StepGraph.launch() replays it
+        on the tensors' current contents.  Runs the step once while recording."""
+        ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
+        if gamma.dtype != torch.float32 or not gamma.is_contiguous() or gamma.numel() != self.N ** 3:
+            raise AsoraError(-1, "gamma must be a contiguous float32 tensor of N^3 cells")
+        dn = dx = dq = g = None
+        if dL_dgamma is not None:
+            g = dL_dgamma
+            if g.dtype != torch.float64 or not g.is_contiguous() or g.numel() != self.N ** 3:
+                raise AsoraError(-1, "dL_dgamma must be a contiguous float64 tensor of N^3 cells")
+            dn, dx, dq = grads
+        flags = (STORE if store else 0) | (ACCUMULATE if accumulate else 0) | (PLAIN if plain else 0)
+        h = _p()
+        _raise(_lib.asora_graph_create(self._h, _dptr(n_H), _dptr(x_HI), n, _dptr(ijk), _dptr(Q),
+                                       _dptr(R), R_max, _dptr(gamma), _dptr(g), _dptr(dn), _dptr(dx),
+                                       _dptr(dq), flags, ctypes.byref(h)), self._h)
+        return StepGraph(self, h, (n_H, x_HI, ijk, Q, R, gamma, g, dn, dx, dq))
+
     def store_info(self):
         """(kept, bytes_needed, bytes_allocated) of the column records."""
         v, need, alloc = _c_int(), ctypes.c_uint64(), ctypes.c_uint64()
@@ -255,6 +301,27 @@ class Asora:
     def check(self, stream=None):
         """Wait for the stream; raise if a kernel flagged a source."""
         _raise(_lib.asora_check(self._h, _stream_ptr(stream)), self._h)
+
+
+class StepGraph:
+    """A recorded step (asora_graph_create); holds the tensors it uses."""
+
+    def __init__(self, ctx: Asora, handle, tensors):
+        self._ctx, self._h, self._tensors = ctx, handle, tensors
+
+    def launch(self, stream=None):
+        _raise(_lib.asora_graph_launch(self._h, _stream_ptr(stream)), self._ctx._h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.asora_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class _RaytraceFn(torch.autograd.Function):

@@ -2,6 +2,7 @@
 // context and scratch memory, table preparation, launch planning.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -81,6 +82,9 @@ struct asora_ctx {
     hipEvent_t pev[kProfSlots][4];
     long prof_count;        // profiled calls so far
     int prof_pending;       // profiled calls since the last summary reset (<= kProfSlots)
+    int live_graphs;        // graphs recorded from this context and not yet freed: they
+                            // hold its buffers' addresses, so no buffer may move
+    std::map<std::string, std::vector<float>> tuned;   // autotune results by workload key
     std::string err;
 };
 
@@ -228,6 +232,9 @@ extern "C" asora_status asora_free(asora_ctx *c)
 {
     if (!c) return ASORA_OK;
     if (c->magic != kMagic) return ASORA_ESTATE;
+    if (c->live_graphs)
+        return fail(c, ASORA_ESTATE, "asora_free: %d recorded graph(s) still use this context",
+                    c->live_graphs);
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(c->d_tab);
@@ -399,9 +406,17 @@ static asora_status ensure_layer_buffers(asora_ctx *c)
     return ASORA_OK;
 }
 
+static asora_status pinned(asora_ctx *c, const char *what)
+{
+    return fail(c, ASORA_ESTATE,
+                "%s would have to grow while a recorded graph holds the current buffers; free the "
+                "graphs (asora_graph_free) first", what);
+}
+
 static asora_status ensure_src_cap(asora_ctx *c, long n)
 {
     if (n <= c->src_cap) return ASORA_OK;
+    if (c->live_graphs) return pinned(c, "the source order buffer");
     long cap = c->src_cap ? c->src_cap : 1024;
     while (cap < n) cap *= 2;
     (void)hipFree(c->d_keys);
@@ -422,6 +437,10 @@ static asora_status reserve_keep(asora_ctx *c, size_t need, bool *ok)
 {
     *ok = false;
     if (need == 0) return ASORA_OK;
+    if (need <= c->keep_alloc && (c->keep_budget == 0 || need <= c->keep_budget)) {
+        *ok = true;   // fits what is held (no device query: this may run while a graph records)
+        return ASORA_OK;
+    }
     size_t budget = c->keep_budget;
     if (budget == 0) {
         size_t fr = 0, tot = 0;
@@ -430,6 +449,7 @@ static asora_status reserve_keep(asora_ctx *c, size_t need, bool *ok)
     }
     if (need > budget) return ASORA_OK;
     if (need > c->keep_alloc) {
+        if (c->live_graphs) return pinned(c, "the kept column records");
         (void)hipFree(c->d_keep);
         c->d_keep = nullptr;
         c->keep_alloc = 0;
@@ -786,6 +806,7 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
     if (layers && (st = ensure_adj_layer_buffers(c))) return st;
     if (!c->d_nbar) HIPCHK(c, hipMalloc(&c->d_nbar, sizeof(double) * n3));
     if (store_need > c->store_cap) {
+        if (c->live_graphs) return pinned(c, "the adjoint scratch");
         (void)hipFree(c->d_store);
         c->d_store = nullptr;
         c->store_cap = 0;
@@ -860,5 +881,233 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
         c->prof_count++;
         if (c->prof_pending < kProfSlots) c->prof_pending++;
     }
+    return ASORA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Graphs: one step recorded once and replayed.
+struct asora_graph {
+    int magic;
+    asora_ctx *ctx;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+static const int kGraphMagic = 0x41475248;
+
+extern "C" asora_status asora_graph_create(asora_ctx *c, const float *n_H, const float *x_HI,
+                                           int64_t n_src, const int32_t *src_ijk, const double *src_Q,
+                                           const float *src_R, float R_max, float *gamma,
+                                           const double *dL_dgamma, float *dL_dnH, float *dL_dxHI,
+                                           double *dL_dQ, uint32_t flags, asora_graph **out)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    if (!out) return fail(c, ASORA_EINVAL, "asora_graph_create: out is NULL");
+    *out = nullptr;
+    if (flags & ~(ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_STORE))
+        return fail(c, ASORA_EINVAL, "asora_graph_create: flags may be ACCUMULATE, PLAIN, STORE");
+    const bool adj = dL_dgamma != nullptr;
+    const uint32_t ff = flags, bf = flags & (ASORA_ACCUMULATE | ASORA_STORE);
+    HIPCHK(c, hipSetDevice(c->device));
+    // the inputs may still be in production on other streams
+    HIPCHK(c, hipDeviceSynchronize());
+    hipStream_t s = nullptr;
+    HIPCHK(c, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    auto step = [&]() -> asora_status {
+        asora_status st = asora_raytrace(c, n_H, x_HI, n_src, src_ijk, src_Q, src_R, R_max, gamma,
+                                         nullptr, ff, s);
+        if (st || !adj) return st;
+        return asora_raytrace_backward(c, n_H, x_HI, n_src, src_ijk, src_Q, src_R, R_max, dL_dgamma,
+                                       dL_dnH, dL_dxHI, dL_dQ, bf, s);
+    };
+    // one eager step sizes every buffer, so that recording allocates nothing
+    asora_status st = step();
+    if (!st && hipStreamSynchronize(s) != hipSuccess) st = fail(c, ASORA_EHIP, "warm-up step failed");
+    asora_graph *g = nullptr;
+    if (!st) {
+        g = new asora_graph();
+        g->magic = kGraphMagic;
+        g->ctx = c;
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed) != hipSuccess) {
+            st = fail(c, ASORA_EHIP, "hipStreamBeginCapture failed");
+        } else {
+            st = step();
+            hipGraph_t gr = nullptr;
+            const hipError_t e = hipStreamEndCapture(s, &gr);
+            g->graph = gr;
+            if (!st && (e != hipSuccess || !gr)) st = fail(c, ASORA_EHIP, "hipStreamEndCapture failed");
+            if (!st && hipGraphInstantiate(&g->exec, gr, nullptr, nullptr, 0) != hipSuccess)
+                st = fail(c, ASORA_EHIP, "hipGraphInstantiate failed");
+        }
+    }
+    (void)hipStreamDestroy(s);
+    if (st) {
+        if (g) {
+            if (g->exec) (void)hipGraphExecDestroy(g->exec);
+            if (g->graph) (void)hipGraphDestroy(g->graph);
+            delete g;
+        }
+        (void)hipGetLastError();
+        return st;
+    }
+    c->live_graphs++;
+    *out = g;
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_graph_launch(asora_graph *g, void *stream)
+{
+    if (!g || g->magic != kGraphMagic || !ctx_ok(g->ctx)) return ASORA_ESTATE;
+    asora_ctx *c = g->ctx;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_graph_free(asora_graph *g)
+{
+    if (!g) return ASORA_OK;
+    if (g->magic != kGraphMagic) return ASORA_ESTATE;
+    asora_ctx *c = g->ctx;
+    if (ctx_ok(c)) {
+        (void)hipSetDevice(c->device);
+        (void)hipDeviceSynchronize();
+        c->live_graphs--;
+    }
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
+    g->magic = 0;
+    delete g;
+    return ASORA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: times candidate scheduling parameters on the caller's inputs and
+// keeps the fastest.  Coordinate descent over the large-source sweep (layers,
+// shells), the waves per work-group and the whole / octant radius thresholds;
+// each candidate is one warm-up call and the median of three timed calls.
+extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const float *x_HI,
+                                       int64_t n_src, const int32_t *src_ijk, const double *src_Q,
+                                       const float *src_R, float R_max, int32_t passes,
+                                       uint32_t flags, void *stream, float *best_ms,
+                                       int32_t max_report, int32_t *n_report, float *report)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    asora_status st = check_common(c, n_H, x_HI, n_src, src_ijk, src_Q, R_max);
+    if (st) return st;
+    if (passes != 1 && passes != 2) return fail(c, ASORA_EINVAL, "asora_autotune: passes must be 1 or 2");
+    if (flags & ~ASORA_TUNE_RETUNE) return fail(c, ASORA_EINVAL, "asora_autotune: unknown flags");
+    if (max_report < 0 || (max_report > 0 && !report))
+        return fail(c, ASORA_EINVAL, "asora_autotune: need max_report >= 0 and a report array");
+    if (c->live_graphs) return pinned(c, "the tuning");
+    if (n_report) *n_report = 0;
+    char keybuf[96];
+    snprintf(keybuf, sizeof keybuf, "%lld/%.4f/%d", (long long)n_src, (double)R_max, passes);
+    const std::string key(keybuf);
+    auto hit = c->tuned.find(key);
+    if (hit != c->tuned.end() && !(flags & ASORA_TUNE_RETUNE)) {
+        const std::vector<float> &v = hit->second;
+        st = asora_set_tuning(c, v[0], v[1], (int)v[2], (int)v[3]);
+        if (!st && best_ms) *best_ms = v[4];
+        return st;
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const size_t n3 = (size_t)c->N * c->N * c->N;
+    float *gamma = nullptr, *dn = nullptr, *dx = nullptr;
+    double *gb = nullptr, *dq = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(gamma);
+        (void)hipFree(dn);
+        (void)hipFree(dx);
+        (void)hipFree(gb);
+        (void)hipFree(dq);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    };
+    bool ok = hipMalloc(&gamma, sizeof(float) * n3) == hipSuccess && hipEventCreate(&e0) == hipSuccess &&
+              hipEventCreate(&e1) == hipSuccess;
+    if (ok && passes == 2) {
+        ok = hipMalloc(&dn, sizeof(float) * n3) == hipSuccess && hipMalloc(&dx, sizeof(float) * n3) == hipSuccess &&
+             hipMalloc(&gb, sizeof(double) * n3) == hipSuccess &&
+             hipMalloc(&dq, sizeof(double) * (n_src > 0 ? n_src : 1)) == hipSuccess;
+        if (ok) {   // dL/dGamma = 1 everywhere
+            std::vector<double> ones(n3, 1.0);
+            ok = hipMemcpy(gb, ones.data(), sizeof(double) * n3, hipMemcpyHostToDevice) == hipSuccess;
+        }
+    }
+    if (!ok) {
+        cleanup();
+        return fail(c, ASORA_ENOMEM, "asora_autotune: scratch allocation failed");
+    }
+    const uint32_t sf = passes == 2 ? ASORA_STORE : 0;
+    auto one = [&]() -> asora_status {
+        asora_status r = asora_raytrace(c, n_H, x_HI, n_src, src_ijk, src_Q, src_R, R_max, gamma, nullptr,
+                                        sf, s);
+        if (r || passes == 1) return r;
+        return asora_raytrace_backward(c, n_H, x_HI, n_src, src_ijk, src_Q, src_R, R_max, gb, dn, dx, dq,
+                                       sf, s);
+    };
+    int nrep = 0;
+    auto trial = [&](float w, float o, int waves, int sweep, float *ms) -> asora_status {
+        asora_status r = asora_set_tuning(c, w, o, waves, sweep);
+        if (r) return r;
+        if ((r = one())) return r;   // plans, buffers, warm caches
+        float t[3];
+        for (int k = 0; k < 3; ++k) {
+            HIPCHK(c, hipEventRecord(e0, s));
+            if ((r = one())) return r;
+            HIPCHK(c, hipEventRecord(e1, s));
+            HIPCHK(c, hipEventSynchronize(e1));
+            HIPCHK(c, hipEventElapsedTime(&t[k], e0, e1));
+        }
+        std::sort(t, t + 3);
+        *ms = t[1];
+        if (nrep < max_report) {
+            float *row = report + 5 * nrep;
+            row[0] = w;
+            row[1] = o;
+            row[2] = (float)waves;
+            row[3] = (float)sweep;
+            row[4] = *ms;
+        }
+        ++nrep;
+        return ASORA_OK;
+    };
+    float bw = c->R_whole, bo = c->R_oct, best = 0.f;
+    int bwv = c->max_waves, bsw = c->big_kind;
+    st = trial(bw, bo, bwv, bsw, &best);
+    auto consider = [&](float w, float o, int waves, int sweep) -> asora_status {
+        if (!(o >= w)) return ASORA_OK;
+        if (w == bw && o == bo && waves == bwv && sweep == bsw) return ASORA_OK;
+        float ms = 0.f;
+        asora_status r = trial(w, o, waves, sweep, &ms);
+        if (r) return r;
+        if (ms < best) {
+            best = ms;
+            bw = w;
+            bo = o;
+            bwv = waves;
+            bsw = sweep;
+        }
+        return ASORA_OK;
+    };
+    if (!st && R_max > bo)
+        for (int sw : {3, 2})
+            if (!st) st = consider(bw, bo, bwv, sw);
+    for (int wv : {4, 8, 12, 16})
+        if (!st) st = consider(bw, bo, wv, bsw);
+    if (R_max > 8.f)
+        for (float o : {8.f, 10.f, 12.f, 15.f, 20.f})
+            if (!st) st = consider(bw, o, bwv, bsw);
+    for (float w : {3.f, 4.f, 6.f, 8.f})
+        if (!st) st = consider(w, bo, bwv, bsw);
+    cleanup();
+    if (st) return st;
+    if ((st = asora_set_tuning(c, bw, bo, bwv, bsw))) return st;
+    c->tuned[key] = {bw, bo, (float)bwv, (float)bsw, best};
+    if (best_ms) *best_ms = best;
+    if (n_report) *n_report = nrep < max_report ? nrep : max_report;
     return ASORA_OK;
 }

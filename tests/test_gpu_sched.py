@@ -1,0 +1,121 @@
+"""GPU tests of the scheduling layer: the recorded step (HIP graph) and the
+autotuner, both through the C ABI.  Results are checked against the eager
+calls and the FP64 oracle."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.parity import assert_grad_parity, assert_parity
+from workloads import make_workload
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def asora():
+    import paper_2311_01492_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def bb():
+    return oracle.blackbody_table()
+
+
+def _tensors(w, gbar=None):
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    out = [t(w.n_H), t(w.x_HI), t(w.src.ijk), t(w.src.Q), t(w.src.R)]
+    return out + ([t(gbar)] if gbar is not None else [])
+
+
+@pytest.mark.parametrize("store", [True, False], ids=["kept", "recompute"])
+def test_recorded_step_replays_match_eager(asora, bb, store):
+    """Replays of the recorded forward + adjoint equal the eager calls on the
+    inputs' current contents, with eager work and synchronisation between the
+    replays; every piece kind is in use (radii 2..30)."""
+    print("case graph store", store, flush=True)
+    w = make_workload("c2", N=40, n_src=20, R=(2.0, 30.0))
+    g0 = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
+    wt = np.random.default_rng(5).standard_normal(g0.shape)
+    gbar = wt / ((g0 + 1e-20) * math.log(10))
+    ctx = asora.Asora(w.N, w.cell_cm, bb.P, bb.dP, bb.lg_lo, bb.lg_hi)
+    nH, xH, ijk, Q, R, gb = _tensors(w, gbar)
+    n3 = w.N ** 3
+    gamma = torch.zeros(n3, dtype=torch.float32, device="cuda")
+    dn, dx = torch.zeros_like(gamma), torch.zeros_like(gamma)
+    dq = torch.zeros(len(w.src), dtype=torch.float64, device="cuda")
+    graph = ctx.record_step(nH, xH, ijk, Q, R, gamma, dL_dgamma=gb, grads=(dn, dx, dq), store=store)
+    on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R,
+                                      gbar)
+    for rep in range(3):
+        for t_ in (gamma, dn, dx, dq):
+            t_.fill_(-1.0)
+        scale = 2.0 ** rep            # Gamma and dL/dn are linear in Q; dL/dQ does not change
+        Q.copy_(torch.from_numpy(w.src.Q * scale))
+        graph.launch()
+        torch.cuda.synchronize()
+        # eager calls on the same inputs between replays
+        ge = ctx.raytrace(nH, xH, ijk, Q, R)
+        en, ex, eq = ctx.backward(nH, xH, ijk, Q, R, gb)
+        ctx.check()
+        torch.testing.assert_close(gamma.view_as(ge), ge, rtol=1e-6, atol=0)
+        torch.testing.assert_close(dn.view_as(en), en, rtol=1e-6, atol=1e-9 * float(en.abs().max()))
+        torch.testing.assert_close(dx.view_as(ex), ex, rtol=1e-6, atol=1e-9 * float(ex.abs().max()))
+        torch.testing.assert_close(dq, eq, rtol=1e-9, atol=0)
+        assert_parity(gamma.cpu().numpy() / scale, g0.ravel(), TOL)
+        assert_grad_parity(dn.cpu().numpy() / scale, on.ravel(), TOL, what="dL/dn_H")
+        np.testing.assert_allclose(dq.cpu().numpy(), oq, rtol=1e-5)
+    graph.close()
+
+
+def test_recorded_step_pins_buffers(asora, bb):
+    """While a recorded graph exists, calls that would move the context's
+    buffers and freeing the context are refused; afterwards they work."""
+    w = make_workload("c2", N=24, n_src=4, R=(8.0, 18.0))
+    ctx = asora.Asora(w.N, w.cell_cm, bb.P, bb.dP, bb.lg_lo, bb.lg_hi)
+    nH, xH, ijk, Q, R = _tensors(w)
+    gamma = torch.empty(w.N ** 3, dtype=torch.float32, device="cuda")
+    graph = ctx.record_step(nH, xH, ijk, Q, R, gamma)
+    big = make_workload("c2", N=24, n_src=3000, R=(8.0, 18.0))
+    _, _, ijk2, Q2, R2 = _tensors(big)
+    with pytest.raises(asora.AsoraError):
+        ctx.raytrace(nH, xH, ijk2, Q2, R2)       # the source buffers would grow
+    with pytest.raises(asora.AsoraError):
+        ctx.close()
+    graph.launch()
+    torch.cuda.synchronize()
+    assert_parity(gamma.cpu().numpy(), oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk,
+                                                       w.src.Q, w.src.R).ravel(), TOL)
+    graph.close()
+    g2 = ctx.raytrace(nH, xH, ijk2, Q2, R2)
+    ctx.check()
+    assert torch.isfinite(g2).all()
+    ctx.close()
+
+
+@pytest.mark.parametrize("passes", [1, 2])
+def test_autotune_keeps_results(asora, bb, passes):
+    """The autotuner times candidates, keeps the fastest, caches it per
+    workload, and the tuned context still matches the oracle."""
+    print("case autotune passes", passes, flush=True)
+    w = make_workload("c2", N=40, n_src=16, R=(3.0, 24.0))
+    ctx = asora.Asora(w.N, w.cell_cm, bb.P, bb.dP, bb.lg_lo, bb.lg_hi)
+    nH, xH, ijk, Q, R = _tensors(w)
+    best, rep = ctx.autotune(nH, xH, ijk, Q, R, passes=passes)
+    assert len(rep) >= 8 and best > 0
+    assert best == pytest.approx(min(r["ms"] for r in rep))
+    chosen = [r for r in rep if r["ms"] == best][0]
+    tun = ctx.get_tuning()
+    assert (tun[0], tun[1], tun[2], tun[3]) == (chosen["R_whole"], chosen["R_oct"],
+                                                chosen["max_waves"], chosen["pyramid_sweep"])
+    ctx.set_tuning(R_whole=5.0, R_oct=9.0, max_waves=4, pyramid_sweep=2)
+    best2, rep2 = ctx.autotune(nH, xH, ijk, Q, R, passes=passes)   # cached: no timing
+    assert rep2 == [] and best2 == best and ctx.get_tuning() == tun
+    o = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
+    g = ctx.raytrace(nH, xH, ijk, Q, R)
+    ctx.check()
+    assert_parity(g.cpu().numpy().astype(np.float64), o, TOL)
