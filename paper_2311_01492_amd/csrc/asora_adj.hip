@@ -18,6 +18,8 @@
 
 namespace asora {
 
+constexpr int kAdjLayerThreads = 64 * kAdjLayerWaves;   // layer adjoint work-groups
+
 struct AdjArgs {
     int N;
     Extent ex;
@@ -220,17 +222,19 @@ __global__ __launch_bounds__(512) void adj_wave(AdjArgs A)
 //  (G) The listed cells, 64 at a time with every lane busy: the rate's
 //      derivatives (FP64), its in-cell term of dL/dn_HI, its share of dL/dQ,
 //      and its entry-column term g_in, kept per listed cell.
-//  (R) Layers from the outermost inward: layer m - 1's exit columns come back
-//      from the record into `cols`; the g_in of layer m's listed cells are
-//      added to their adjoint slots in `abar`; then layer m's rectangle in
-//      chunks from the first to the last: every cell takes and clears its
+//  (R) Layers from the outermost inward: the g_in of layer m's listed cells
+//      are added to their adjoint slots in `abar`; then layer m's rectangle
+//      in chunks from the first to the last: every cell takes and clears its
 //      slot (the adjoint of its exit column, which flows into its entry
 //      column and its in-cell column alike), adds alpha ds times it to
-//      dL/dn_HI and pushes it through the interpolation weights to the slots
-//      of its layer m - 1 neighbours with LDS atomics.  A neighbour slot
-//      precedes the pushing cell in (u, v) order, so it was already taken in
-//      this layer.  Chunks whose slots are all zero (cells that no listed
-//      cell depends on) skip the arithmetic.
+//      dL/dn_HI and pushes it through the interpolation weights, with its
+//      neighbours' exit columns read from the record, to the slots of its
+//      layer m - 1 neighbours with LDS atomics.  A neighbour slot precedes the
+//      pushing cell in (u, v) order, so it was already taken in this layer.
+//      Chunks whose slots are all zero (cells that no listed cell depends on)
+//      skip the arithmetic and the record.
+// The table is read from global memory (only the listed cells use it), which
+// leaves the LDS to the per-wave buffers.
 __device__ __forceinline__ void wave_sync_global()
 {
     // this wave's global stores complete before its later global loads by
@@ -344,13 +348,9 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
     for (int m = Mx; m >= 1; --m) {
         const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
         off -= r.total;   // first cell of layer m in the record
-        if (m >= 2) {   // exit columns of layer m - 1 into cols
-            const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m - 1);
-            for (int g = lane; g < rp.total; g += 64) {
-                int u, v;
-                if (rect_cell(rp, g, u, v)) cols[u * S + v] = rec.N[off - rp.total + g];
-            }
-        }
+        // exit columns of layer m - 1 (its rectangle precedes layer m's)
+        const int wvp = m >= 2 ? layer_rect(L.ext_u, L.ext_v, Rsq, m - 1).wv : 1;
+        const double *Nprev = rec.N + (m >= 2 ? off - layer_rect(L.ext_u, L.ext_v, Rsq, m - 1).total : 0);
         for (int k = litoff[m] + lane; k < litoff[m + 1]; k += 64) abar[rec.pm[k] & 0xffff] += gin[k];
         wave_sync();
         for (int c = 0; c < (r.total + 63) / 64; ++c) {
@@ -366,7 +366,7 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
             if (__ballot(Tin != 0.0)) {
                 if (Tin != 0.0) {
                     LayerRev lr;
-                    layer_cell_reverse(L, X, m, u, v, cols, S, Tin, lr);
+                    layer_cell_reverse(L, X, m, u, v, Nprev, wvp, Tin, lr);
                     if (m >= 2) {
 #pragma unroll
                         for (int n = 0; n < 4; ++n)
@@ -397,23 +397,19 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
 }
 
 template <bool KEPT>
-__global__ __launch_bounds__(512) void adj_layer(AdjArgs A)
+__global__ __launch_bounds__(kAdjLayerThreads) void adj_layer(AdjArgs A)
 {
     extern __shared__ __align__(16) char smem[];
     constexpr int TYPE = 3, npieces = 24;
     if (A.seg[TYPE + 1] == A.seg[TYPE]) return;   // no sources of this kind
-    TabNode *T = (TabNode *)smem;
-    {
-        const int4 *s = (const int4 *)A.tab;
-        int4 *d = (int4 *)smem;
-        for (int k = threadIdx.x; k < A.tp.n; k += blockDim.x) d[k] = s[k];
-    }
-    __syncthreads();
+    const TabNode *T = A.tab;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
-    double *cols = (double *)(smem + (size_t)A.tp.n * sizeof(TabNode) + (size_t)wave * A.region_bytes);
-    double *abar = cols + (size_t)(A.Mcap + 1) * A.lay_S;
-    int *litoff = (int *)(abar + (size_t)(A.Mcap + 1) * A.lay_S);
+    // per wave: [column buffer (recompute only)] adjoint buffer, layer offsets
+    const size_t buf = (size_t)(A.Mcap + 1) * A.lay_S;
+    double *cols = (double *)(smem + (size_t)wave * A.region_bytes);
+    double *abar = KEPT ? cols : cols + buf;
+    int *litoff = (int *)(abar + buf);
     char *scratch = (char *)(A.store + (size_t)(blockIdx.x * waves + wave) * A.store_stride);
     const int base = A.seg[TYPE];
     const int nitems = (A.seg[TYPE + 1] - base) * npieces;
@@ -612,18 +608,19 @@ hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L)
     return hipGetLastError();
 }
 
-// Per-wave LDS of the layer adjoint: the column and adjoint buffers of
-// (Mcap + 1) rows of S doubles, then the per-layer offsets of the cell list.
-size_t adj_layer_region_bytes(int Mcap, int S)
+// Per-wave LDS of the layer adjoint: the column buffer (recompute only) and
+// the adjoint buffer, (Mcap + 1) rows of S doubles each, then the per-layer
+// offsets of the cell list.
+size_t adj_layer_region_bytes(int Mcap, int S, bool kept)
 {
-    return ((size_t)2 * (Mcap + 1) * S * sizeof(double) + (size_t)(Mcap + 2) * sizeof(int) + 15) &
-           ~(size_t)15;
+    return ((size_t)(kept ? 1 : 2) * (Mcap + 1) * S * sizeof(double) + (size_t)(Mcap + 2) * sizeof(int) +
+            15) & ~(size_t)15;
 }
 
-hipError_t adj_layer_occupancy(int waves, size_t lds, int *blocks_per_cu)
+hipError_t adj_layer_occupancy(bool kept, int waves, size_t lds, int *blocks_per_cu)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)adj_layer<false>,
-                                                        waves * 64, lds);
+    const void *f = kept ? (const void *)adj_layer<true> : (const void *)adj_layer<false>;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, waves * 64, lds);
 }
 
 hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int Mcap)
@@ -631,8 +628,8 @@ hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int Mcap)
     AdjArgs A = make_adj_args(L);
     A.Mcap = Mcap;
     A.lay_S = Mcap + 1;
-    A.region_bytes = (int)adj_layer_region_bytes(Mcap, A.lay_S);
-    const size_t lds = (size_t)L.tp.n * sizeof(TabNode) + (size_t)L.waves * A.region_bytes;
+    A.region_bytes = (int)adj_layer_region_bytes(Mcap, A.lay_S, A.kept != nullptr);
+    const size_t lds = (size_t)L.waves * A.region_bytes;
     if (A.kept) hipLaunchKernelGGL(adj_layer<true>, dim3(L.grid), dim3(64 * L.waves), lds, st, A);
     else hipLaunchKernelGGL(adj_layer<false>, dim3(L.grid), dim3(64 * L.waves), lds, st, A);
     return hipGetLastError();

@@ -720,12 +720,13 @@ static asora_status get_adj_plan(asora_ctx *c, int type, float R_cap, Plan *out)
     return ASORA_OK;
 }
 
-// Adjoint layer pieces: two layer buffers per wave in LDS; a pyramid column
-// record and the rate's entry-column terms in the wave's scratch.
-static asora_status get_adj_layer_plan(asora_ctx *c, float R_cap, Plan *out)
+// Adjoint layer pieces: the adjoint buffer (and, when the columns are
+// recomputed, the column buffer) per wave in LDS; a pyramid column record and
+// the rate's entry-column terms in the wave's scratch.
+static asora_status get_adj_layer_plan(asora_ctx *c, float R_cap, bool kept, Plan *out)
 {
     const int Rsq = (int)std::floor((double)R_cap * (double)R_cap);
-    const PlanKey key{3, Rsq};
+    const PlanKey key{kept ? 4 : 3, Rsq};
     auto it = c->adj_plans.find(key);
     if (it != c->adj_plans.end()) {
         *out = it->second;
@@ -734,18 +735,17 @@ static asora_status get_adj_layer_plan(asora_ctx *c, float R_cap, Plan *out)
     Plan P;
     asora_status st = get_layer_plan(c, R_cap, &P);   // Mcap, record sizes
     if (st) return st;
-    const size_t tab = (size_t)c->tp.n * sizeof(TabNode);
-    const size_t region = adj_layer_region_bytes(P.Mcap, P.Mcap + 1);
-    const long fit = c->max_lds > tab + 64 ? (long)((c->max_lds - tab - 64) / region) : 0;
+    const size_t region = adj_layer_region_bytes(P.Mcap, P.Mcap + 1, kept);
+    const long fit = c->max_lds > 64 ? (long)((c->max_lds - 64) / region) : 0;
     if (fit < 1)
         return fail(c, ASORA_ENOSYS,
                     "asora_raytrace_backward: R_max=%.1f needs %zu bytes of LDS per wave (limit %zu)",
-                    R_cap, region + tab, c->max_lds);
-    const int cap = c->max_waves < 8 ? c->max_waves : 8;   // adjoint work-groups: <= 512 threads
+                    R_cap, region, c->max_lds);
+    const int cap = c->max_waves < kAdjLayerWaves ? c->max_waves : kAdjLayerWaves;
     P.waves = (int)(fit < cap ? fit : cap);
-    P.lds = tab + (size_t)P.waves * region;
+    P.lds = (size_t)P.waves * region;
     int bpc = 0;
-    HIPCHK(c, adj_layer_occupancy(P.waves, P.lds, &bpc));
+    HIPCHK(c, adj_layer_occupancy(kept, P.waves, P.lds, &bpc));
     P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
     P.piece_cells = P.rec_cap;
     P.scratch = (long)((P.rec_bytes + sizeof(double) * (size_t)P.rec_cap) / sizeof(double));
@@ -792,12 +792,16 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
     const int tbig = type_of(c, R_max);
     const int tmax = tbig == 2 ? c->big_kind : tbig;
     const bool layers = tmax == 3;
+    // ASORA_STORE: the records kept by the forward call with these inputs
+    const bool kept = (flags & ASORA_STORE) && layers && c->keep_valid && c->keep_nsrc == n_src &&
+                      c->keep_Rmax == R_max && c->keep_sig[0] == n_H && c->keep_sig[1] == x_HI &&
+                      c->keep_sig[2] == src_ijk && c->keep_sig[3] == src_Q && c->keep_sig[4] == src_R;
     Plan plans[4];
     size_t store_need = 0;
     for (int t = 0; t <= tmax; ++t) {
         if (t == 2 && layers) continue;
         const float cap = t == tmax ? R_max : (t == 0 ? c->R_whole : c->R_oct);
-        if ((st = t == 3 ? get_adj_layer_plan(c, cap, &plans[t]) : get_adj_plan(c, t, cap, &plans[t])))
+        if ((st = t == 3 ? get_adj_layer_plan(c, cap, kept, &plans[t]) : get_adj_plan(c, t, cap, &plans[t])))
             return st;
         const size_t need = (size_t)plans[t].grid * plans[t].waves * (size_t)plans[t].scratch;
         store_need = need > store_need ? need : store_need;
@@ -848,10 +852,6 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
         L.nHI_T = c->d_nhi_T;
         L.gbar_T = c->d_gbar_T;
         L.nbar_T = c->d_nbar_T;
-        // ASORA_STORE: the records kept by the forward call with these inputs
-        const bool kept = (flags & ASORA_STORE) && layers && c->keep_valid && c->keep_nsrc == n_src &&
-                          c->keep_Rmax == R_max && c->keep_sig[0] == n_H && c->keep_sig[1] == x_HI &&
-                          c->keep_sig[2] == src_ijk && c->keep_sig[3] == src_Q && c->keep_sig[4] == src_R;
         L.kept = kept ? c->d_keep : nullptr;
         L.rec_piece_bytes = layers ? plans[3].rec_bytes : 0;
         L.rec_cap = layers ? plans[3].rec_cap : 0;

@@ -918,15 +918,30 @@ struct LayerCell {
 // 11-12; for m = 1 the only neighbour of non-zero weight is the source),
 // in-cell column (eqs. 9-10), ownership.  lay holds layer m - 1 as
 // lay[u * S + v].  The arithmetic is the same as cell_update's.
+// Index of layer cell (u, v) of layer m in the piece's field layout.
+__host__ __device__ __forceinline__ uint32_t layer_cp(const LayerPiece &L, int N, int m, int u, int v)
+{
+    return (uint32_t)wrap(L.c_d + L.sd * m, N) * L.st_d + (uint32_t)wrap(L.c_u + L.su * u, N) * L.st_u +
+           (uint32_t)wrap(L.c_v + L.sv * v, N);
+}
+
+// layer_cell with the cell's index cp and n_HI already at hand.
+__host__ __device__ __forceinline__ void layer_cell_at(const LayerPiece &L, const LayerX &X, int m, int u,
+                                                       int v, uint32_t cp, double nhi, const double *lay,
+                                                       int S, LayerCell &out);
+
 __host__ __device__ __forceinline__ void layer_cell(const LayerPiece &L, const LayerX &X, int m,
                                                     int u, int v, const double *lay, int S,
                                                     LayerCell &out)
 {
-    const int N = X.N;
-    const uint32_t cp = (uint32_t)wrap(L.c_d + L.sd * m, N) * L.st_d +
-                        (uint32_t)wrap(L.c_u + L.su * u, N) * L.st_u +
-                        (uint32_t)wrap(L.c_v + L.sv * v, N);
-    const double nhi = X.nHI[cp];
+    const uint32_t cp = layer_cp(L, X.N, m, u, v);
+    layer_cell_at(L, X, m, u, v, cp, X.nHI[cp], lay, S, out);
+}
+
+__host__ __device__ __forceinline__ void layer_cell_at(const LayerPiece &L, const LayerX &X, int m, int u,
+                                                       int v, uint32_t cp, double nhi, const double *lay,
+                                                       int S, LayerCell &out)
+{
     const double inv_m = rcp_f64((double)m);
     // a = 1 (b = 1) must be exact: the weights of neighbours that leave the
     // pyramid then vanish exactly
@@ -1080,10 +1095,12 @@ __host__ __device__ __forceinline__ void layer_cell_adjoint(const LayerPiece &L,
 // the adjoints its consumers pushed to its exit column plus the rate's own
 // entry-column term (the rate's in-cell term reaches dL/dn_HI separately, see
 // record_rate_adjoint).  Since N_out = N_in + dN, the exit-column adjoint
-// flows unchanged into both N_in and dN.  Returns the adjoints to push to
-// the four neighbours of layer m - 1 (Mbar[n] for neighbour
-// (u - (n & 1), v - (n >> 1)); zero where the weight is zero; for m = 1 the
-// source takes them through nbar_src) and dL/dn_HI of the cell.
+// flows unchanged into both N_in and dN.  Nprev holds the exit columns of
+// layer m - 1 as its rectangle (row width wvp): neighbour (u', v') is
+// Nprev[u' * wvp + v'].  Returns the adjoints to push to the four neighbours
+// of layer m - 1 (Mbar[n] for neighbour (u - (n & 1), v - (n >> 1)); zero
+// where the weight is zero; for m = 1 the source takes them through
+// nbar_src) and dL/dn_HI of the cell.
 struct LayerRev {
     uint32_t cp;
     double Mbar[4];
@@ -1092,7 +1109,7 @@ struct LayerRev {
 };
 
 __host__ __device__ __forceinline__ void layer_cell_reverse(const LayerPiece &L, const LayerX &X, int m,
-                                                            int u, int v, const double *cols, int S,
+                                                            int u, int v, const double *Nprev, int wvp,
                                                             double Tin, LayerRev &out)
 {
     const int N = X.N;
@@ -1112,14 +1129,16 @@ __host__ __device__ __forceinline__ void layer_cell_reverse(const LayerPiece &L,
     const double b = v == m ? 1.0 : (double)v * inv_m;
     const double sw[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
     double Mv[4], wv[4], dw[4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n)   // the neighbour columns first: independent loads
+        Mv[n] = sw[n] > 0.0 ? Nprev[(u - (n & 1)) * wvp + (v - (n >> 1))] : 0.0;
     double num = 0.0, W = 0.0;
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
-        Mv[n] = 0.0;
         wv[n] = 0.0;
         dw[n] = 0.0;
         if (!(sw[n] > 0.0)) continue;
-        const double M = cols[(u - (n & 1)) * S + (v - (n >> 1))];
+        const double M = Mv[n];
         double wn = sw[n];
         if (X.tau_w > 0.f) {
             const double tau = X.sigma0 * M;
@@ -1131,7 +1150,6 @@ __host__ __device__ __forceinline__ void layer_cell_reverse(const LayerPiece &L,
                 wn *= rcp_f64((double)X.tau_w);
             }
         }
-        Mv[n] = M;
         wv[n] = wn;
         num += wn * M;
         W += wn;

@@ -106,8 +106,9 @@ hipError_t launch_adj_prologue(hipStream_t st, const float *nH, const float *xHI
                                double *nbar, long n3, double *qbar, long nsrc, int zero_q, int *ctl,
                                int nctl, int n_cu);
 hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L);
-size_t adj_layer_region_bytes(int Mcap, int S);
-hipError_t adj_layer_occupancy(int waves, size_t lds, int *blocks_per_cu);
+constexpr int kAdjLayerWaves = 12;   // largest work-group of the layer adjoint (waves)
+size_t adj_layer_region_bytes(int Mcap, int S, bool kept);
+hipError_t adj_layer_occupancy(bool kept, int waves, size_t lds, int *blocks_per_cu);
 hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int Mcap);
 hipError_t launch_adj_transpose_prologue(hipStream_t st, const float *nH, const float *xHI,
                                          const double *gbar, double *nHI_T, double *gbar_T,

@@ -288,14 +288,14 @@ extern "C" int hc_raytrace_layer(int N, double alpha, double sigma0, int n, doub
 // Reverse mode on the CPU through the layer pieces, in the adjoint kernel's
 // order, per pyramid: (F) the forward pass fills the column record (exit
 // columns, listed cells); (G) the listed cells' rate terms in record order;
-// (R) layers from the outermost inward: layer m - 1's exit columns reloaded
-// into the column buffer, the rate's entry-column terms of layer m added to
-// its adjoint slots, then layer m's rectangle in chunks from the first to the
-// last, each chunk reading its slots, clearing them and adding to its layer
-// m - 1 neighbours.  dL/dn_HI of pyramids with dominant axis k goes through a
+// (R) layers from the outermost inward: the rate's entry-column terms of
+// layer m added to its adjoint slots, then layer m's rectangle in chunks from
+// the first to the last, each chunk reading its slots, clearing them and
+// adding to its layer m - 1 neighbours, whose exit columns it reads from the
+// record.  dL/dn_HI of pyramids with dominant axis k goes through a
 // [k][i][j] buffer as on the GPU.  Returns -6 if a neighbour of non-zero
-// weight is read from a slot that does not hold layer m - 1, -7 if a record
-// slot is not a cell of its layer.
+// weight is not an active cell of layer m - 1, -7 if a record slot is not a
+// cell of its layer.
 extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n, double lg_lo,
                                       double lg_hi, const double *P, const double *dP, double tau_w,
                                       int reading, const float *nH, const float *xHI, long nsrc,
@@ -354,14 +354,11 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
             for (int m = Mx; m >= 1; --m) {
                 const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
                 off -= r.total;   // first cell of layer m
+                LayerRect rp = r;
+                const double *Nprev = nullptr;
                 if (m >= 2) {
-                    const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m - 1);
-                    for (int g = 0; g < rp.total; ++g) {
-                        int u, v;
-                        if (!rect_cell(rp, g, u, v)) continue;
-                        cols[(size_t)u * S + v] = rec.N[off - rp.total + g];
-                        cols_id[(size_t)u * S + v] = m - 1;
-                    }
+                    rp = layer_rect(L.ext_u, L.ext_v, Rsq, m - 1);
+                    Nprev = rec.N + off - rp.total;
                 }
                 for (int k = rec.litoff[m]; k < rec.litoff[m + 1]; ++k) {
                     const int pos = rec.pm[k] & 0xffff;
@@ -382,14 +379,18 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
                     for (int lane = 0; lane < 64; ++lane) {
                         if (!act[lane] || Tin[lane] == 0.0) continue;
                         const int u = uu[lane], v = vv[lane];
-                        if (m > 1) {
+                        if (m > 1) {   // neighbours of non-zero weight: active cells of layer m - 1
                             const bool a0 = u > 0, a1 = u < m, b0 = v > 0, b1 = v < m;
                             const bool need[4] = {a1 && b1, a0 && b1, a1 && b0, a0 && b0};
-                            for (int k = 0; k < 4; ++k)
-                                if (need[k] && cols_id[(size_t)(u - (k & 1)) * S + v - (k >> 1)] != m - 1)
+                            for (int k = 0; k < 4; ++k) {
+                                if (!need[k]) continue;
+                                const int un = u - (k & 1), vn = v - (k >> 1);
+                                int u2, v2;
+                                if (un >= rp.nu || vn >= rp.wv || !rect_cell(rp, un * rp.wv + vn, u2, v2))
                                     return -6;
+                            }
                         }
-                        layer_cell_reverse(L, X, m, u, v, cols.data(), S, Tin[lane], lr[lane]);
+                        layer_cell_reverse(L, X, m, u, v, Nprev, rp.wv, Tin[lane], lr[lane]);
                         for (int k = 0; k < 4; ++k)
                             if (lr[lane].Mbar[k] != 0.0)
                                 abar[(size_t)(u - (k & 1)) * S + (v - (k >> 1))] += lr[lane].Mbar[k];
