@@ -246,8 +246,9 @@ def main():
         print("[bench] autotune", file=sys.stderr, flush=True)
         best, rep = ctx.autotune(nH, xH, ijk, Q, R, R_max=R_max, passes=2)
         tuning = {"autotuned": True, "candidates": len(rep), "best_ms": best}
-    tw, to, twv, tsw = ctx.get_tuning()
-    tuning.update({"R_whole": tw, "R_oct": to, "max_waves": twv, "pyramid_sweep": tsw})
+    tw, to, twv, tsw, tpl = ctx.get_tuning()
+    tuning.update({"R_whole": tw, "R_oct": to, "max_waves": twv, "pyramid_sweep": tsw,
+                   "table_place": "lds" if tpl == 1 else "caches"})
 
     def timed_step(store):
         """Mean wall ms per step over args.steps steps (warm-up first), and the
@@ -320,7 +321,8 @@ def main():
     tun = ctx.get_tuning()
     big = R_max > tun[1]
     layer = big and tun[3] == 3
-    kname = {"fwd": "fwd_layer<false>" if layer else "fwd_wave<2>",
+    tl = "true" if tun[4] == 1 else "false"
+    kname = {"fwd": f"fwd_layer<false, {tl}>" if layer else "fwd_wave<2>",
              "adj": ("adj_layer<true>" if kept else "adj_layer<false>") if layer else "adj_wave<2>"}
     if not big:
         kname = {"fwd": "fwd_wave<1>", "adj": "adj_wave<1>"}

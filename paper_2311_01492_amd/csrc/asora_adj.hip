@@ -269,6 +269,7 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
     X.alpha = A.alpha;
     X.half_col = n_s * A.alpha * 0.5;
     X.nHI = L.transposed ? A.nHI_T : A.nHI;
+    layer_x_weights(X);
     const double *gbar = L.transposed ? A.gbar_T : A.gbar;
     double *nbar = L.transposed ? A.nbar_T : A.nbar;
     const double coef = Q * A.coef_unit;
@@ -281,22 +282,32 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
     // ---- (F)
     long off = 0;
     if (!KEPT) {
+        for (int k = lane; k < (Mx + 1) * S; k += 64) cols[k] = 0.0;   // finite everywhere it is read
+        wave_sync();
         int tail = 0;
         for (int m = 1; m <= Mx; ++m) {
             if (lane == 0) litoff[m] = tail;
             const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
-            for (int c = (r.total + 63) / 64 - 1; c >= 0; --c) {
+            const double inv_m = rcp_f64((double)m);
+            const int nch = (r.total + 63) / 64;
+            RectWalk w;
+            w.init(r, (nch - 1) * 64 + lane);
+            for (int c = nch - 1; c >= 0; --c, w.down()) {
                 const int g = c * 64 + lane;
-                int u, v;
-                const bool act = rect_cell(r, g, u, v);
+                const int u = w.u, v = w.v;
+                const bool act = g < r.total && mul24(u, u) + mul24(v, v) <= r.rem;
+                const int pos = mul24(u, S) + v;
                 LayerCell lc;
                 lc.Nin = 0.0;
                 lc.owned = false;
-                if (act) layer_cell(L, X, m, u, v, cols, S, lc);
+                if (act) {
+                    const uint32_t cp = layer_cp(L, N, m, u, v);
+                    layer_cell_at(L, X, m, inv_m, u, v, cp, X.nHI[cp], cols, pos, S, lc);
+                }
                 wave_sync();
                 bool lit = false;
                 if (act) {
-                    cols[u * S + v] = lc.Nout;
+                    cols[pos] = lc.h;
                     rec.N[off + g] = lc.Nout;
                     lit = lc.owned && A.sigma0 * lc.Nin < A.tp.tau_hi;
                 }
@@ -307,7 +318,7 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
                     rec.ta[k] = A.sigma0 * lc.Nin;
                     rec.dt[k] = A.sigma0 * lc.dN;
                     rec.cp[k] = lc.cp;
-                    rec.pm[k] = (u * S + v) | (m << 16);
+                    rec.pm[k] = pos | (m << 16);
                     rec.r2[k] = lc.r2;
                 }
                 tail += __popcll(mask);
@@ -353,14 +364,16 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
         const double *Nprev = rec.N + (m >= 2 ? off - layer_rect(L.ext_u, L.ext_v, Rsq, m - 1).total : 0);
         for (int k = litoff[m] + lane; k < litoff[m + 1]; k += 64) abar[rec.pm[k] & 0xffff] += gin[k];
         wave_sync();
-        for (int c = 0; c < (r.total + 63) / 64; ++c) {
+        RectWalk w;
+        w.init(r, lane);
+        for (int c = 0; c < (r.total + 63) / 64; ++c, w.up()) {
             const int g = c * 64 + lane;
-            int u, v;
-            const bool act = rect_cell(r, g, u, v);
+            const int u = w.u, v = w.v;
+            const bool act = g < r.total && mul24(u, u) + mul24(v, v) <= r.rem;
             double Tin = 0.0;
             if (act) {
-                Tin = abar[u * S + v];
-                abar[u * S + v] = 0.0;
+                Tin = abar[mul24(u, S) + v];
+                abar[mul24(u, S) + v] = 0.0;
             }
             wave_sync();
             if (__ballot(Tin != 0.0)) {

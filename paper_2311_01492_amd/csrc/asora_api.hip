@@ -60,6 +60,7 @@ struct asora_ctx {
     int min_waves, max_waves;   // wave-per-piece mode bounds
     std::map<PlanKey, Plan> plans;
     int big_kind;           // piece kind of the forward above R_oct: 2 shell pyramids, 3 layer pyramids
+    int tab_lds;            // layer forward: table in LDS (1) or through the caches (0)
     double *d_nhi_T;        // [k][i][j] copies for the layer pieces (allocated on first use)
     double *d_gacc_T;
     double *d_gbar_T;       // adjoint: dL/dGamma and dL/dn_HI in the [k][i][j] layout
@@ -186,6 +187,7 @@ extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, d
     c->min_waves = 4;
     c->max_waves = 16;
     c->big_kind = 3;
+    c->tab_lds = 1;
 
     // table in the kernels' form
     std::vector<TabNode> nodes(n_tab);
@@ -359,7 +361,7 @@ static asora_status get_plan(asora_ctx *c, int type, float R_cap, Plan *out)
 static asora_status get_layer_plan(asora_ctx *c, float R_cap, Plan *out)
 {
     const int Rsq = (int)std::floor((double)R_cap * (double)R_cap);
-    const PlanKey key{3, Rsq};
+    const PlanKey key{c->tab_lds ? 3 : 5, Rsq};
     auto it = c->plans.find(key);
     if (it != c->plans.end()) {
         *out = it->second;
@@ -376,7 +378,7 @@ static asora_status get_layer_plan(asora_ctx *c, float R_cap, Plan *out)
     if (P.rec_cap < 1) P.rec_cap = 1;
     P.rec_bytes = layer_record_bytes(P.rec_cap, P.Mcap);
     P.wave_mode = 1;
-    const size_t tab = (size_t)c->tp.n * sizeof(TabNode);
+    const size_t tab = c->tab_lds ? (size_t)c->tp.n * sizeof(TabNode) : 0;
     const size_t region = layer_region_bytes(P.Mcap, P.Mcap + 1);
     const long fit = c->max_lds > tab + 64 ? (long)((c->max_lds - tab - 64) / region) : 0;
     if (fit < 1)
@@ -386,7 +388,7 @@ static asora_status get_layer_plan(asora_ctx *c, float R_cap, Plan *out)
     P.waves = (int)(fit < c->max_waves ? fit : c->max_waves);
     P.lds = tab + (size_t)P.waves * region;
     int bpc = 0;
-    HIPCHK(c, layer_occupancy(P.waves, P.lds, &bpc));
+    HIPCHK(c, layer_occupancy(c->tab_lds != 0, P.waves, P.lds, &bpc));
     P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
     c->plans[key] = P;
     *out = P;
@@ -551,6 +553,7 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     F.keep = keep ? c->d_keep : nullptr;
     F.keep_piece_bytes = layers ? plans[3].rec_bytes : 0;
     F.keep_cap = layers ? plans[3].rec_cap : 0;
+    F.tab_lds = c->tab_lds;
 
     if (prof) HIPCHK(c, hipEventRecord(ev[0], s));
     HIPCHK(c, launch_prologue(s, n_H, x_HI, c->d_nhi, c->d_gacc, coldens_in, n3, c->d_ctl,
@@ -616,20 +619,24 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
 }
 
 extern "C" asora_status asora_set_tuning(asora_ctx *c, float R_whole, float R_oct, int32_t max_waves,
-                                         int32_t pyramid_sweep)
+                                         int32_t pyramid_sweep, int32_t table_place)
 {
     if (!ctx_ok(c)) return ASORA_ESTATE;
     const float w = R_whole > 0 ? R_whole : c->R_whole;
     const float o = R_oct > 0 ? R_oct : c->R_oct;
     if (!(o >= w) || !std::isfinite(w) || !std::isfinite(o) || max_waves > 16 ||
-        !(pyramid_sweep == 0 || pyramid_sweep == 2 || pyramid_sweep == 3))
+        !(pyramid_sweep == 0 || pyramid_sweep == 2 || pyramid_sweep == 3) || table_place < 0 ||
+        table_place > 2)
         return fail(c, ASORA_EINVAL,
-                    "asora_set_tuning: need 0 < R_whole <= R_oct, max_waves <= 16, pyramid_sweep 0/2/3");
+                    "asora_set_tuning: need 0 < R_whole <= R_oct, max_waves <= 16, pyramid_sweep 0/2/3, "
+                    "table_place 0/1/2");
+    if (c->live_graphs) return pinned(c, "the tuning");
     c->R_whole = w;
     c->R_oct = o;
     if (max_waves > 0) c->max_waves = max_waves;
     if (c->min_waves > c->max_waves) c->min_waves = c->max_waves;
     if (pyramid_sweep) c->big_kind = pyramid_sweep;
+    if (table_place) c->tab_lds = table_place == 1 ? 1 : 0;
     c->plans.clear();
     c->adj_plans.clear();
     c->keep_valid = false;   // record layouts follow the plans
@@ -637,13 +644,15 @@ extern "C" asora_status asora_set_tuning(asora_ctx *c, float R_whole, float R_oc
 }
 
 extern "C" asora_status asora_get_tuning(const asora_ctx *c, float *R_whole, float *R_oct,
-                                         int32_t *max_waves, int32_t *pyramid_sweep)
+                                         int32_t *max_waves, int32_t *pyramid_sweep,
+                                         int32_t *table_place)
 {
     if (!ctx_ok(c)) return ASORA_ESTATE;
     if (R_whole) *R_whole = c->R_whole;
     if (R_oct) *R_oct = c->R_oct;
     if (max_waves) *max_waves = c->max_waves;
     if (pyramid_sweep) *pyramid_sweep = c->big_kind;
+    if (table_place) *table_place = c->tab_lds ? 1 : 2;
     return ASORA_OK;
 }
 
@@ -1006,8 +1015,8 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
     auto hit = c->tuned.find(key);
     if (hit != c->tuned.end() && !(flags & ASORA_TUNE_RETUNE)) {
         const std::vector<float> &v = hit->second;
-        st = asora_set_tuning(c, v[0], v[1], (int)v[2], (int)v[3]);
-        if (!st && best_ms) *best_ms = v[4];
+        st = asora_set_tuning(c, v[0], v[1], (int)v[2], (int)v[3], (int)v[4]);
+        if (!st && best_ms) *best_ms = v[5];
         return st;
     }
     HIPCHK(c, hipSetDevice(c->device));
@@ -1050,8 +1059,8 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
                                        sf, s);
     };
     int nrep = 0;
-    auto trial = [&](float w, float o, int waves, int sweep, float *ms) -> asora_status {
-        asora_status r = asora_set_tuning(c, w, o, waves, sweep);
+    auto trial = [&](float w, float o, int waves, int sweep, int place, float *ms) -> asora_status {
+        asora_status r = asora_set_tuning(c, w, o, waves, sweep, place);
         if (r) return r;
         if ((r = one())) return r;   // plans, buffers, warm caches
         float t[3];
@@ -1065,24 +1074,25 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
         std::sort(t, t + 3);
         *ms = t[1];
         if (nrep < max_report) {
-            float *row = report + 5 * nrep;
+            float *row = report + 6 * nrep;
             row[0] = w;
             row[1] = o;
             row[2] = (float)waves;
             row[3] = (float)sweep;
-            row[4] = *ms;
+            row[4] = (float)place;
+            row[5] = *ms;
         }
         ++nrep;
         return ASORA_OK;
     };
     float bw = c->R_whole, bo = c->R_oct, best = 0.f;
-    int bwv = c->max_waves, bsw = c->big_kind;
-    st = trial(bw, bo, bwv, bsw, &best);
-    auto consider = [&](float w, float o, int waves, int sweep) -> asora_status {
+    int bwv = c->max_waves, bsw = c->big_kind, bpl = c->tab_lds ? 1 : 2;
+    st = trial(bw, bo, bwv, bsw, bpl, &best);
+    auto consider = [&](float w, float o, int waves, int sweep, int place) -> asora_status {
         if (!(o >= w)) return ASORA_OK;
-        if (w == bw && o == bo && waves == bwv && sweep == bsw) return ASORA_OK;
+        if (w == bw && o == bo && waves == bwv && sweep == bsw && place == bpl) return ASORA_OK;
         float ms = 0.f;
-        asora_status r = trial(w, o, waves, sweep, &ms);
+        asora_status r = trial(w, o, waves, sweep, place, &ms);
         if (r) return r;
         if (ms < best) {
             best = ms;
@@ -1090,23 +1100,27 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
             bo = o;
             bwv = waves;
             bsw = sweep;
+            bpl = place;
         }
         return ASORA_OK;
     };
     if (!st && R_max > bo)
         for (int sw : {3, 2})
-            if (!st) st = consider(bw, bo, bwv, sw);
+            if (!st) st = consider(bw, bo, bwv, sw, bpl);
+    if (R_max > bo && bsw == 3)
+        for (int pl : {1, 2})
+            if (!st) st = consider(bw, bo, bwv, bsw, pl);
     for (int wv : {4, 8, 12, 16})
-        if (!st) st = consider(bw, bo, wv, bsw);
+        if (!st) st = consider(bw, bo, wv, bsw, bpl);
     if (R_max > 8.f)
         for (float o : {8.f, 10.f, 12.f, 15.f, 20.f})
-            if (!st) st = consider(bw, o, bwv, bsw);
+            if (!st) st = consider(bw, o, bwv, bsw, bpl);
     for (float w : {3.f, 4.f, 6.f, 8.f})
-        if (!st) st = consider(w, bo, bwv, bsw);
+        if (!st) st = consider(w, bo, bwv, bsw, bpl);
     cleanup();
     if (st) return st;
-    if ((st = asora_set_tuning(c, bw, bo, bwv, bsw))) return st;
-    c->tuned[key] = {bw, bo, (float)bwv, (float)bsw, best};
+    if ((st = asora_set_tuning(c, bw, bo, bwv, bsw, bpl))) return st;
+    c->tuned[key] = {bw, bo, (float)bwv, (float)bsw, (float)bpl, best};
     if (best_ms) *best_ms = best;
     if (n_report) *n_report = nrep < max_report ? nrep : max_report;
     return ASORA_OK;

@@ -762,6 +762,11 @@ __host__ __device__ __forceinline__ double source_cell_rate(const TabNode *T, co
 struct LayerPiece {
     int d, au, av;             // dominant axis and the (u, v) axes (0 = i, 1 = j, 2 = k)
     int oct;                   // octant bits: 1 = i negative, 2 = j negative, 4 = k negative
+    // ownership: a cell with u = 0 (v = 0) on a negative axis belongs to the
+    // neighbouring octant (neg_u, neg_v); a cell tied with u (v) for the
+    // largest offset belongs to the pyramid of the first tied axis in the
+    // order k, j, i (tie_u, tie_v: that is not this pyramid)
+    bool neg_u, neg_v, tie_u, tie_v;
     int sd, su, sv;            // +1 / -1: direction of the offsets along d, u, v
     int ext_d, ext_u, ext_v;   // periodic extents in those directions
     int c_d, c_u, c_v;         // source coordinates along d, u, v
@@ -783,6 +788,10 @@ __host__ __device__ inline LayerPiece make_layer_piece(int p, int si, int sj, in
     L.sd = axis_sign(L.oct, L.d);
     L.su = axis_sign(L.oct, L.au);
     L.sv = axis_sign(L.oct, L.av);
+    L.neg_u = L.su < 0;
+    L.neg_v = L.sv < 0;
+    L.tie_u = L.d == 0;   // u is j: j comes before i
+    L.tie_v = L.d != 2;   // v is k (d = i, j): k comes first
     L.ext_d = L.sd < 0 ? ex.neg : ex.pos;
     L.ext_u = L.su < 0 ? ex.neg : ex.pos;
     L.ext_v = L.sv < 0 ? ex.neg : ex.pos;
@@ -904,13 +913,77 @@ struct LayerX {
     double sigma0, alpha;
     double half_col;       // n_HI(s) alpha / 2
     const double *nHI;     // n_HI in the piece's layout
+    double inv_s0;         // 1 / sigma0
+    double inv_tw;         // 1 / tau_w, or 1 with geometric weights
 };
+
+__host__ __device__ __forceinline__ void layer_x_weights(LayerX &X)
+{
+    X.inv_s0 = 1.0 / X.sigma0;
+    X.inv_tw = X.tau_w > 0.f ? 1.0 / (double)X.tau_w : 1.0;
+}
+
+// 24-bit unsigned product (operands below 2^24): a full-rate instruction on
+// the GPU, where a 32-bit integer product is a quarter-rate one.
+__host__ __device__ __forceinline__ int mul24(int a, int b)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return (int)__umul24((unsigned)a, (unsigned)b);
+#else
+    return a * b;
+#endif
+}
+
+// The layer buffer holds, for every cell of the previous layer, what its
+// consumers need of its exit column M for the optical-depth weights
+// w = s / max(sigma0 M, tau_w): the factor f = 1 / max(sigma0 M, tau_w) and the
+// product g = f M.  A cell with sigma0 M > tau_w stores h = 1 / (sigma0 M) > 0
+// (then f = h, g = 1 / sigma0); any other cell stores h = -M (then
+// f = 1 / tau_w, g = M / tau_w).  With geometric weights every cell stores -M
+// (f = 1, g = M).  One reciprocal per cell instead of one per neighbour.
+__host__ __device__ __forceinline__ double layer_entry(const LayerX &X, double M)
+{
+    const double t = X.sigma0 * M;
+    return (X.tau_w > 0.f && t > (double)X.tau_w) ? rcp_f64(t) : -M;
+}
 
 struct LayerCell {
     uint32_t cp;    // cell index in the piece's layout
     double Nin, Nout, dN;
+    double h;       // layer-buffer entry of the cell (layer_entry of Nout)
     int r2;
     bool owned;
+};
+
+// Walks the cells of a layer rectangle 64 at a time: every lane holds cell
+// g = c * 64 + lane of chunk c, and down() / up() move all lanes to chunk
+// c - 1 / c + 1 without a division (64 = q64 * wv + r64).
+struct RectWalk {
+    int u, v, wv, q64, r64;
+    __host__ __device__ __forceinline__ void init(const LayerRect &r, int g)
+    {
+        wv = r.wv;
+        q64 = 64 / wv;
+        r64 = 64 - q64 * wv;
+        int q = (int)((float)g * rcp_approx((float)wv));   // off by at most one (g < 2^24)
+        if (mul24(q, wv) > g) --q;
+        else if (mul24(q + 1, wv) <= g) ++q;
+        u = q;
+        v = g - mul24(q, wv);
+    }
+    __host__ __device__ __forceinline__ void down()
+    {
+        const bool b = v < r64;
+        u -= q64 + (b ? 1 : 0);
+        v += b ? wv - r64 : -r64;
+    }
+    __host__ __device__ __forceinline__ void up()
+    {
+        v += r64;
+        const bool c = v >= wv;
+        u += q64 + (c ? 1 : 0);
+        v -= c ? wv : 0;
+    }
 };
 
 // The short-characteristics update of cell (u, v) of layer m of a pyramid:
@@ -921,68 +994,63 @@ struct LayerCell {
 // Index of layer cell (u, v) of layer m in the piece's field layout.
 __host__ __device__ __forceinline__ uint32_t layer_cp(const LayerPiece &L, int N, int m, int u, int v)
 {
-    return (uint32_t)wrap(L.c_d + L.sd * m, N) * L.st_d + (uint32_t)wrap(L.c_u + L.su * u, N) * L.st_u +
-           (uint32_t)wrap(L.c_v + L.sv * v, N);
+    // strides are N or N^2 (< 2^22); the N^2 stride is applied with a full product
+    const uint32_t cd = (uint32_t)wrap(L.c_d + L.sd * m, N), cu = (uint32_t)wrap(L.c_u + L.su * u, N);
+    return cd * L.st_d + cu * L.st_u + (uint32_t)wrap(L.c_v + L.sv * v, N);
 }
 
-// layer_cell with the cell's index cp and n_HI already at hand.
-__host__ __device__ __forceinline__ void layer_cell_at(const LayerPiece &L, const LayerX &X, int m, int u,
-                                                       int v, uint32_t cp, double nhi, const double *lay,
-                                                       int S, LayerCell &out);
+// The short-characteristics update of cell (u, v) of layer m (inv_m = 1/m)
+// with its index cp, its n_HI and its buffer slot pos = u * S + v at hand:
+// entry column interpolated from the four neighbours in layer m - 1 (eqs.
+// 11-12; for m = 1 the only neighbour of non-zero weight is the source),
+// in-cell column (eqs. 9-10), ownership.  lay holds layer m - 1's entries
+// (layer_entry) at u * S + v.  Neighbours of zero weight are read from a
+// clamped slot and contribute exactly zero, so the lanes do not branch; the
+// buffer must hold finite values wherever it is read.
+__host__ __device__ __forceinline__ void layer_cell_at(const LayerPiece &L, const LayerX &X, int m,
+                                                       double inv_m, int u, int v, uint32_t cp, double nhi,
+                                                       const double *lay, int pos, int S, LayerCell &out)
+{
+    // a = 1 (b = 1) must be exact: the weights of neighbours that leave the
+    // pyramid then vanish exactly
+    const double a = u == m ? 1.0 : (double)u * inv_m;
+    const double b = v == m ? 1.0 : (double)v * inv_m;
+    const int r2 = mul24(m, m) + mul24(u, u) + mul24(v, v);
+    const double ds = sqrt_fast((double)r2) * inv_m;
+    double Nin;
+    if (m == 1) {
+        Nin = X.reading == 0 ? X.half_col * ds : X.half_col;
+    } else {
+        const int du = u > 0 ? S : 0, dv = v > 0 ? 1 : 0;
+        const double h[4] = {lay[pos], lay[pos - du], lay[pos - dv], lay[pos - du - dv]};
+        const double sw[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
+        double num = 0.0, W = 0.0;
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const bool thick = h[n] > 0.0;
+            const double f = thick ? h[n] : X.inv_tw;
+            const double g = thick ? X.inv_s0 : -h[n] * X.inv_tw;
+            num += sw[n] * g;
+            W += sw[n] * f;
+        }
+        Nin = num * rcp_f64(W);
+    }
+    const double dN = nhi * X.alpha * ds;
+    out.cp = cp;
+    out.Nin = Nin;
+    out.Nout = Nin + dN;
+    out.h = layer_entry(X, out.Nout);
+    out.dN = dN;
+    out.r2 = r2;
+    out.owned = !(L.neg_u && u == 0) && !(L.neg_v && v == 0) && !(L.tie_u && u == m) && !(L.tie_v && v == m);
+}
 
 __host__ __device__ __forceinline__ void layer_cell(const LayerPiece &L, const LayerX &X, int m,
                                                     int u, int v, const double *lay, int S,
                                                     LayerCell &out)
 {
     const uint32_t cp = layer_cp(L, X.N, m, u, v);
-    layer_cell_at(L, X, m, u, v, cp, X.nHI[cp], lay, S, out);
-}
-
-__host__ __device__ __forceinline__ void layer_cell_at(const LayerPiece &L, const LayerX &X, int m, int u,
-                                                       int v, uint32_t cp, double nhi, const double *lay,
-                                                       int S, LayerCell &out)
-{
-    const double inv_m = rcp_f64((double)m);
-    // a = 1 (b = 1) must be exact: the weights of neighbours that leave the
-    // pyramid then vanish exactly
-    const double a = u == m ? 1.0 : (double)u * inv_m;
-    const double b = v == m ? 1.0 : (double)v * inv_m;
-    const int r2 = m * m + u * u + v * v;
-    const double ds = sqrt_fast((double)r2) * inv_m;
-    double Nin;
-    if (m == 1) {
-        Nin = X.reading == 0 ? X.half_col * ds : X.half_col;
-    } else {
-        const double sw[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
-        double num = 0.0, W = 0.0;
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            if (!(sw[n] > 0.0)) continue;
-            const double M = lay[(u - (n & 1)) * S + (v - (n >> 1))];
-            double wn = sw[n];
-            if (X.tau_w > 0.f) wn *= rcp_f64(fmax(X.sigma0 * M, (double)X.tau_w));
-            num += wn * M;
-            W += wn;
-        }
-        Nin = num * rcp_f64(W);
-    }
-    const double dN = nhi * X.alpha * ds;
-    // ownership: zero planes of negative axes belong to the neighbouring
-    // octant; a tied cell to the first dominant axis in the order k, j, i
-    bool owned = !((((L.oct >> L.au) & 1) && u == 0) || (((L.oct >> L.av) & 1) && v == 0));
-    int canon = 0;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        const int t = ax == L.d ? m : (ax == L.au ? u : v);
-        if (t == m) canon = ax;   // the last tied axis in i, j, k order = the first in k, j, i
-    }
-    owned = owned && canon == L.d;
-    out.cp = cp;
-    out.Nin = Nin;
-    out.Nout = Nin + dN;
-    out.dN = dN;
-    out.r2 = r2;
-    out.owned = owned;
+    layer_cell_at(L, X, m, rcp_f64((double)m), u, v, cp, X.nHI[cp], lay, u * S + v, S, out);
 }
 
 // Cell (i, j, k) of layer cell (m, u, v), in the standard layout.

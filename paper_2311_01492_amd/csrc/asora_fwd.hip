@@ -358,6 +358,7 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
     X.alpha = A.alpha;
     X.half_col = n_s * A.alpha * 0.5;
     X.nHI = L.transposed ? A.nHI_T : A.nHI;
+    layer_x_weights(X);
     double *acc = L.transposed ? A.gacc_T : A.gacc;
     const double coef = Q * A.coef_unit;
     const int S = A.lay_S;
@@ -370,23 +371,33 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
         if (A.coldens) A.coldens[cs] = 0.0;
     }
     const int Mx = min(isqrt_floor(Rsq), L.ext_d);
+    for (int k = lane; k < (Mx + 1) * S; k += 64) lay[k] = 0.0;   // finite everywhere it is read
+    wave_sync();
     int head = 0, tail = 0;
     long off = 0;   // first cell of layer m in the record
     for (int m = 1; m <= Mx; ++m) {
         if (KEEP && lane == 0) rec.litoff[m] = tail;
         const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
-        for (int c = (r.total + 63) / 64 - 1; c >= 0; --c) {
+        const double inv_m = rcp_f64((double)m);
+        const int nch = (r.total + 63) / 64;
+        RectWalk w;
+        w.init(r, (nch - 1) * 64 + lane);
+        for (int c = nch - 1; c >= 0; --c, w.down()) {
             const int g = c * 64 + lane;
-            int u, v;
-            const bool act = rect_cell(r, g, u, v);
+            const int u = w.u, v = w.v;
+            const bool act = g < r.total && mul24(u, u) + mul24(v, v) <= r.rem;
+            const int pos = mul24(u, S) + v;
             LayerCell lc;
             lc.Nin = 0.0;
             lc.owned = false;
-            if (act) layer_cell(L, X, m, u, v, lay, S, lc);
+            if (act) {
+                const uint32_t cp = layer_cp(L, N, m, u, v);
+                layer_cell_at(L, X, m, inv_m, u, v, cp, X.nHI[cp], lay, pos, S, lc);
+            }
             wave_sync();   // every read of layer m - 1 before the writes below
             bool want = false;
             if (act) {
-                lay[u * S + v] = lc.Nout;
+                lay[pos] = lc.h;
                 if (KEEP) rec.N[off + g] = lc.Nout;
                 if (lc.owned) {
                     if (A.coldens) A.coldens[layer_std_index(L, N, m, u, v)] = lc.Nin;
@@ -397,17 +408,17 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
             if (want) {
                 const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                const int pos = (tail + rank) & (kQueue - 1);
-                Qa.ta[pos] = A.sigma0 * lc.Nin;
-                Qa.dt[pos] = A.sigma0 * lc.dN;
-                Qa.cp[pos] = lc.cp;
-                Qa.r2[pos] = lc.r2;
+                const int qpos = (tail + rank) & (kQueue - 1);
+                Qa.ta[qpos] = A.sigma0 * lc.Nin;
+                Qa.dt[qpos] = A.sigma0 * lc.dN;
+                Qa.cp[qpos] = lc.cp;
+                Qa.r2[qpos] = lc.r2;
                 if (KEEP) {
                     const int k = tail + rank;
                     rec.ta[k] = A.sigma0 * lc.Nin;
                     rec.dt[k] = A.sigma0 * lc.dN;
                     rec.cp[k] = lc.cp;
-                    rec.pm[k] = (u * S + v) | (m << 16);
+                    rec.pm[k] = pos | (m << 16);
                     rec.r2[k] = lc.r2;
                 }
             }
@@ -429,22 +440,24 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
     }
 }
 
-template <bool KEEP>
+// TLDS: the table is copied to LDS once per work-group; otherwise the rate
+// batches read it through the caches, which leaves the LDS to more waves.
+template <bool KEEP, bool TLDS>
 __global__ __launch_bounds__(1024) void fwd_layer(FwdArgs A)
 {
     extern __shared__ __align__(16) char smem[];
     constexpr int TYPE = 3, npieces = 24;
     if (A.plain_src < 0 && A.seg[TYPE + 1] == A.seg[TYPE]) return;   // no sources of this kind
-    TabNode *T = (TabNode *)smem;
-    {
+    const TabNode *T = TLDS ? (const TabNode *)smem : A.tab;
+    if (TLDS) {
         const int4 *s = (const int4 *)A.tab;
         int4 *d = (int4 *)smem;
         for (int k = threadIdx.x; k < A.tp.n; k += blockDim.x) d[k] = s[k];
+        __syncthreads();
     }
-    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
-    char *region = smem + (size_t)A.tp.n * sizeof(TabNode) + (size_t)wave * A.region_bytes;
+    char *region = smem + (TLDS ? (size_t)A.tp.n * sizeof(TabNode) : 0) + (size_t)wave * A.region_bytes;
     RateQueue Qa;
     Qa.ta = (double *)region;
     Qa.dt = (float *)(Qa.ta + kQueue);
@@ -477,10 +490,10 @@ size_t layer_region_bytes(int Mcap, int S)
     return (b + 15) & ~(size_t)15;
 }
 
-hipError_t layer_occupancy(int waves, size_t lds, int *blocks_per_cu)
+hipError_t layer_occupancy(bool tab_lds, int waves, size_t lds, int *blocks_per_cu)
 {
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, (const void *)fwd_layer<false>,
-                                                        waves * 64, lds);
+    const void *f = tab_lds ? (const void *)fwd_layer<false, true> : (const void *)fwd_layer<false, false>;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, waves * 64, lds);
 }
 
 hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int Mcap, int waves, int grid,
@@ -490,10 +503,13 @@ hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int Mcap, int wa
     A.plain_src = plain_src;
     A.lay_S = Mcap + 1;
     A.region_bytes = (int)layer_region_bytes(Mcap, A.lay_S);
-    const size_t lds = (size_t)F.tp.n * sizeof(TabNode) + (size_t)waves * A.region_bytes;
+    const size_t lds = (F.tab_lds ? (size_t)F.tp.n * sizeof(TabNode) : 0) + (size_t)waves * A.region_bytes;
     if (plain_src >= 0) grid = (24 + waves - 1) / waves;
-    if (A.keep) hipLaunchKernelGGL(fwd_layer<true>, dim3(grid), dim3(64 * waves), lds, st, A);
-    else hipLaunchKernelGGL(fwd_layer<false>, dim3(grid), dim3(64 * waves), lds, st, A);
+    const dim3 g(grid), b(64 * waves);
+    if (A.keep && F.tab_lds) hipLaunchKernelGGL((fwd_layer<true, true>), g, b, lds, st, A);
+    else if (A.keep) hipLaunchKernelGGL((fwd_layer<true, false>), g, b, lds, st, A);
+    else if (F.tab_lds) hipLaunchKernelGGL((fwd_layer<false, true>), g, b, lds, st, A);
+    else hipLaunchKernelGGL((fwd_layer<false, false>), g, b, lds, st, A);
     return hipGetLastError();
 }
 
@@ -841,8 +857,10 @@ hipError_t fwd_configure(size_t max_lds)
     (void)hipFuncSetAttribute((const void *)fwd_wave<0>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipFuncSetAttribute((const void *)fwd_wave<1>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipFuncSetAttribute((const void *)fwd_wave<2>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-    (void)hipFuncSetAttribute((const void *)fwd_layer<false>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-    (void)hipFuncSetAttribute((const void *)fwd_layer<true>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)fwd_layer<false, true>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)fwd_layer<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)fwd_layer<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)fwd_layer<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipGetLastError();
     return hipSuccess;
 }

@@ -41,6 +41,7 @@ struct FwdLaunch {
     char *keep;             // layer pieces: column records per (source, pyramid), or NULL
     size_t keep_piece_bytes;
     long keep_cap;
+    int tab_lds;            // layer pieces: table in LDS (1) or read through the caches (0)
 };
 
 hipError_t launch_prologue(hipStream_t st, const float *nH, const float *xHI, double *nHI,
@@ -53,7 +54,7 @@ hipError_t launch_transpose_prologue(hipStream_t st, const float *nH, const floa
 hipError_t launch_transpose_finalize(hipStream_t st, const double *gacc, const double *gacc_T,
                                      float *gamma, int N, int accumulate);
 size_t layer_region_bytes(int Mcap, int S);
-hipError_t layer_occupancy(int waves, size_t lds, int *blocks_per_cu);
+hipError_t layer_occupancy(bool tab_lds, int waves, size_t lds, int *blocks_per_cu);
 hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int Mcap, int waves, int grid,
                             int plain_src);
 size_t fwd_lds_bytes(int n_tab, int ring_cap, int row_cap);

@@ -35,6 +35,34 @@ extern "C" void hc_neg_divdiff_batch(int n, double lg_lo, double lg_hi, const do
     for (long i = 0; i < m; ++i) out[i] = neg_divdiff(T.data(), tp, a[i], dt[i]);
 }
 
+// The chunk walk of the layer kernels against plain division: for every row
+// width wv in [1, wv_max] and every cell g of rectangles up to 40 rows, the
+// lanes' (u, v) after init, down() and up() equal (g / wv, g % wv).  Returns 0
+// or the first failing wv.
+extern "C" int hc_rectwalk_check(int wv_max)
+{
+    for (int wv = 1; wv <= wv_max; ++wv) {
+        LayerRect r;
+        r.rem = 1 << 30;
+        r.nu = 40;
+        r.wv = wv;
+        r.total = r.nu * wv;
+        const int nch = (r.total + 63) / 64;
+        for (int lane = 0; lane < 64; ++lane) {
+            RectWalk d, u;
+            d.init(r, (nch - 1) * 64 + lane);
+            u.init(r, lane);
+            for (int c = 0; c < nch; ++c) {
+                const int gd = (nch - 1 - c) * 64 + lane, gu = c * 64 + lane;
+                if (d.u != gd / wv || d.v != gd % wv || u.u != gu / wv || u.v != gu % wv) return wv;
+                d.down();
+                u.up();
+            }
+        }
+    }
+    return 0;
+}
+
 // Rows of shell q of piece (type, p): writes Blo and counts of nrows rows.
 extern "C" int hc_rows(int N, int type, int p, int Rsq, int q, int *blo, int *cnt)
 {
@@ -156,12 +184,18 @@ static int layer_forward_piece(const LayerPiece &L, const LayerX &X, int Rsq, co
     for (int m = 1; m <= Mx; ++m) {
         if (rec) rec->litoff[m] = nrec;
         const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
-        for (int c = (r.total + 63) / 64 - 1; c >= 0; --c) {
+        const int nch = (r.total + 63) / 64;
+        RectWalk wk[64];
+        for (int lane = 0; lane < 64; ++lane) wk[lane].init(r, (nch - 1) * 64 + lane);
+        for (int c = nch - 1; c >= 0; --c) {
             LayerCell lc[64];
             bool act[64];
             int uu[64], vv[64];
             for (int lane = 0; lane < 64; ++lane) {
-                act[lane] = rect_cell(r, c * 64 + lane, uu[lane], vv[lane]);
+                uu[lane] = wk[lane].u;
+                vv[lane] = wk[lane].v;
+                wk[lane].down();
+                act[lane] = c * 64 + lane < r.total && uu[lane] * uu[lane] + vv[lane] * vv[lane] <= r.rem;
                 if (!act[lane]) continue;
                 const int u = uu[lane], v = vv[lane];
                 if (m > 1) {   // neighbours of non-zero weight must hold layer m - 1
@@ -175,7 +209,7 @@ static int layer_forward_piece(const LayerPiece &L, const LayerX &X, int Rsq, co
             for (int lane = 0; lane < 64; ++lane) {
                 if (!act[lane]) continue;
                 const int u = uu[lane], v = vv[lane];
-                lay[(size_t)u * S + v] = lc[lane].Nout;
+                lay[(size_t)u * S + v] = lc[lane].h;
                 lay_id[(size_t)u * S + v] = m;
                 if (rec) rec->N[off + c * 64 + lane] = lc[lane].Nout;
                 if (!lc[lane].owned) continue;
@@ -247,6 +281,7 @@ static LayerX host_layer_x(const HostLayerSetup &H, const LayerPiece &L, int N, 
     X.alpha = alpha;
     X.half_col = H.nhi[cs] * alpha * 0.5;
     X.nHI = L.transposed ? H.nhiT.data() : H.nhi.data();
+    layer_x_weights(X);
     return X;
 }
 
@@ -365,13 +400,18 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
                     if ((rec.pm[k] >> 16) != m) return -7;
                     abar[pos] += G[k];
                 }
+                RectWalk wk[64];
+                for (int lane = 0; lane < 64; ++lane) wk[lane].init(r, lane);
                 for (int c = 0; c < (r.total + 63) / 64; ++c) {
                     LayerRev lr[64];
                     bool act[64];
                     int uu[64], vv[64];
                     double Tin[64];
                     for (int lane = 0; lane < 64; ++lane) {
-                        act[lane] = rect_cell(r, c * 64 + lane, uu[lane], vv[lane]);
+                        uu[lane] = wk[lane].u;
+                        vv[lane] = wk[lane].v;
+                        wk[lane].up();
+                        act[lane] = c * 64 + lane < r.total && uu[lane] * uu[lane] + vv[lane] * vv[lane] <= r.rem;
                         Tin[lane] = act[lane] ? abar[(size_t)uu[lane] * S + vv[lane]] : 0.0;
                     }
                     for (int lane = 0; lane < 64; ++lane)

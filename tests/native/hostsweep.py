@@ -33,6 +33,8 @@ def load():
         build()
         lib = ctypes.CDLL(LIB)
         p, i, d, f, l = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_float, ctypes.c_long
+        lib.hc_rectwalk_check.restype = i
+        lib.hc_rectwalk_check.argtypes = [i]
         lib.hc_raytrace.restype = i
         lib.hc_raytrace.argtypes = [i, d, d, i, d, d, p, p, d, i, p, p, l, p, p, p, f, f, i, p, p]
         lib.hc_neg_divdiff_batch.restype = None
@@ -78,6 +80,10 @@ def raytrace(N, cell_cm, sigma0, table, n_H, x_HI, ijk, Q, R, tau_w=0.6, reading
         raise RuntimeError(f"host sweep failed: {st}")
     g = g.reshape((N,) * 3)
     return (g, cd.reshape((N,) * 3)) if coldens else g
+
+
+def rectwalk_check(wv_max):
+    return load().hc_rectwalk_check(int(wv_max))
 
 
 def neg_divdiff(table, a, dt):

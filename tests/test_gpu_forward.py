@@ -28,13 +28,14 @@ def bb():
 
 
 def _ctx(asora, w, table, sweep=3, **kw):
-    """sweep: 3 = large sources as layer pyramids (the default), 2 = shell pyramids."""
+    """sweep: 3 = large sources as layer pyramids (the default), 2 = shell
+    pyramids, -3 = layer pyramids with the table read through the caches."""
     ctx = asora.Asora(w.N, w.cell_cm, table.P, table.dP, table.lg_lo, table.lg_hi, **kw)
-    ctx.set_tuning(pyramid_sweep=sweep)
+    ctx.set_tuning(pyramid_sweep=abs(sweep), table_place=2 if sweep < 0 else 1)
     return ctx
 
 
-SWEEPS = pytest.mark.parametrize("sweep", [3, 2], ids=["layers", "shells"])
+SWEEPS = pytest.mark.parametrize("sweep", [3, -3, 2], ids=["layers", "layers-cached-table", "shells"])
 
 
 def _dev(w):

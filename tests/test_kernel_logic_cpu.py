@@ -128,6 +128,13 @@ def test_divided_difference_regimes(bb):
     assert np.all(got[~ok] == 0)
 
 
+def test_layer_chunk_walk_matches_division():
+    """The division-free stepping of the layer kernels' chunk walk (64 cells
+    forward and backward through a layer rectangle) decodes the same (u, v)
+    as g / wv, g % wv for every row width up to 130."""
+    assert hostsweep.rectwalk_check(130) == 0
+
+
 @pytest.mark.parametrize("N", [16, 17])
 def test_row_enumeration_matches_brute_force(N):
     """Union of the rows of all pieces of a type = the shell's cells in the
