@@ -282,7 +282,7 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
     // ---- (F)
     long off = 0;
     if (!KEPT) {
-        for (int k = lane; k < (Mx + 1) * S; k += 64) cols[k] = 0.0;   // finite everywhere it is read
+        for (int k = lane; k < S * S; k += 64) cols[k] = 0.0;   // finite everywhere it is read
         wave_sync();
         int tail = 0;
         for (int m = 1; m <= Mx; ++m) {
@@ -352,7 +352,7 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
             gin[k] = gi;
         }
     }
-    for (int k = lane; k < (Mx + 1) * S; k += 64) abar[k] = 0.0;
+    for (int k = lane; k < S * S; k += 64) abar[k] = 0.0;   // the column buffer of (F), reused
     wave_sync_global();
 
     // ---- (R)
@@ -418,11 +418,12 @@ __global__ __launch_bounds__(kAdjLayerThreads) void adj_layer(AdjArgs A)
     const TabNode *T = A.tab;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
-    // per wave: [column buffer (recompute only)] adjoint buffer, layer offsets
-    const size_t buf = (size_t)(A.Mcap + 1) * A.lay_S;
+    // per wave: one S x S buffer, the columns in (F) and the adjoints in (R),
+    // then the layer offsets of the cell list
+    const size_t buf = (size_t)A.lay_S * A.lay_S;
     double *cols = (double *)(smem + (size_t)wave * A.region_bytes);
-    double *abar = KEPT ? cols : cols + buf;
-    int *litoff = (int *)(abar + buf);
+    double *abar = cols;
+    int *litoff = (int *)(cols + buf);
     char *scratch = (char *)(A.store + (size_t)(blockIdx.x * waves + wave) * A.store_stride);
     const int base = A.seg[TYPE];
     const int nitems = (A.seg[TYPE + 1] - base) * npieces;
@@ -621,13 +622,11 @@ hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L)
     return hipGetLastError();
 }
 
-// Per-wave LDS of the layer adjoint: the column buffer (recompute only) and
-// the adjoint buffer, (Mcap + 1) rows of S doubles each, then the per-layer
-// offsets of the cell list.
-size_t adj_layer_region_bytes(int Mcap, int S, bool kept)
+// Per-wave LDS of the layer adjoint: the S x S buffer (columns, then
+// adjoints), then the per-layer offsets of the cell list.
+size_t adj_layer_region_bytes(int Mcap, int S)
 {
-    return ((size_t)(kept ? 1 : 2) * (Mcap + 1) * S * sizeof(double) + (size_t)(Mcap + 2) * sizeof(int) +
-            15) & ~(size_t)15;
+    return ((size_t)S * S * sizeof(double) + (size_t)(Mcap + 2) * sizeof(int) + 15) & ~(size_t)15;
 }
 
 hipError_t adj_layer_occupancy(bool kept, int waves, size_t lds, int *blocks_per_cu)
@@ -636,12 +635,12 @@ hipError_t adj_layer_occupancy(bool kept, int waves, size_t lds, int *blocks_per
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, waves * 64, lds);
 }
 
-hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int Mcap)
+hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int Mcap, int S)
 {
     AdjArgs A = make_adj_args(L);
     A.Mcap = Mcap;
-    A.lay_S = Mcap + 1;
-    A.region_bytes = (int)adj_layer_region_bytes(Mcap, A.lay_S, A.kept != nullptr);
+    A.lay_S = S;
+    A.region_bytes = (int)adj_layer_region_bytes(Mcap, S);
     const size_t lds = (size_t)L.waves * A.region_bytes;
     if (A.kept) hipLaunchKernelGGL(adj_layer<true>, dim3(L.grid), dim3(64 * L.waves), lds, st, A);
     else hipLaunchKernelGGL(adj_layer<false>, dim3(L.grid), dim3(64 * L.waves), lds, st, A);

@@ -24,6 +24,7 @@ struct PlanKey {
 
 struct Plan {
     int ring_cap, row_cap, Qmax;
+    int S;              // layer pieces: side of the per-wave layer buffer
     long piece_cells;   // largest number of cells of one piece (adjoint scratch)
     long scratch;       // adjoint: doubles of scratch per wave
     int Mcap;           // layer pieces: largest layer index
@@ -374,12 +375,13 @@ static asora_status get_layer_plan(asora_ctx *c, float R_cap, Plan *out)
     while ((long)(r + 1) * (r + 1) <= Rsq) ++r;
     P.Mcap = r < ex.neg ? r : ex.neg;
     if (P.Mcap < 1) P.Mcap = 1;
+    P.S = layer_buffer_side(Rsq, ex);
     P.rec_cap = layer_piece_capacity(Rsq, ex);
     if (P.rec_cap < 1) P.rec_cap = 1;
     P.rec_bytes = layer_record_bytes(P.rec_cap, P.Mcap);
     P.wave_mode = 1;
     const size_t tab = c->tab_lds ? (size_t)c->tp.n * sizeof(TabNode) : 0;
-    const size_t region = layer_region_bytes(P.Mcap, P.Mcap + 1);
+    const size_t region = layer_region_bytes(P.S);
     const long fit = c->max_lds > tab + 64 ? (long)((c->max_lds - tab - 64) / region) : 0;
     if (fit < 1)
         return fail(c, ASORA_ENOSYS,
@@ -571,7 +573,7 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
             F.row_cap = plans[tmax].row_cap;
             for (long k = 0; k < n_src; ++k) {
                 if (tmax == 3)
-                    HIPCHK(c, launch_fwd_layer(s, F, plans[3].Mcap, plans[3].waves, 0, (int)k));
+                    HIPCHK(c, launch_fwd_layer(s, F, plans[3].S, plans[3].waves, 0, (int)k));
                 else if (plans[tmax].wave_mode)
                     HIPCHK(c, launch_fwd_wave(s, F, plans[tmax].waves, 0, (int)k));
                 else
@@ -585,7 +587,7 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
                 F.ring_cap = plans[t].ring_cap;
                 F.row_cap = plans[t].row_cap;
                 if (t == 3)
-                    HIPCHK(c, launch_fwd_layer(s, F, plans[3].Mcap, plans[3].waves, plans[3].grid, -1));
+                    HIPCHK(c, launch_fwd_layer(s, F, plans[3].S, plans[3].waves, plans[3].grid, -1));
                 else if (plans[t].wave_mode)
                     HIPCHK(c, launch_fwd_wave(s, F, plans[t].waves, plans[t].grid, -1));
                 else
@@ -744,7 +746,7 @@ static asora_status get_adj_layer_plan(asora_ctx *c, float R_cap, bool kept, Pla
     Plan P;
     asora_status st = get_layer_plan(c, R_cap, &P);   // Mcap, record sizes
     if (st) return st;
-    const size_t region = adj_layer_region_bytes(P.Mcap, P.Mcap + 1, kept);
+    const size_t region = adj_layer_region_bytes(P.Mcap, P.S);
     const long fit = c->max_lds > 64 ? (long)((c->max_lds - 64) / region) : 0;
     if (fit < 1)
         return fail(c, ASORA_ENOSYS,
@@ -874,7 +876,7 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
             L.waves = plans[t].waves;
             L.grid = plans[t].grid;
             L.store_stride = plans[t].scratch;
-            if (t == 3) HIPCHK(c, launch_adj_layer(s, L, plans[3].Mcap));
+            if (t == 3) HIPCHK(c, launch_adj_layer(s, L, plans[3].Mcap, plans[3].S));
             else HIPCHK(c, launch_adj_wave(s, L));
         }
     }

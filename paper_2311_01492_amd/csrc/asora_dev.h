@@ -857,6 +857,16 @@ __host__ __device__ __forceinline__ bool rect_cell(const LayerRect &r, int g, in
     return g < r.total && u * u + v * v <= r.rem;
 }
 
+// Side of the layer buffer of pyramids of squared radius up to Rsq: a cell
+// (u, v) of layer m has u, v <= m and u^2 + v^2 + m^2 <= Rsq, hence
+// u^2, v^2 <= Rsq / 2 (and u, v within the extent), so an S x S buffer with
+// S = floor(sqrt(Rsq / 2)) + 1 holds every layer.
+__host__ __device__ inline int layer_buffer_side(int Rsq, const Extent &ex)
+{
+    const int s = isqrt_floor(Rsq / 2);
+    return (s < ex.neg ? s : ex.neg) + 1;
+}
+
 // Cells of the largest pyramid of a source of squared radius Rsq, counted as
 // layer rectangles (an upper bound for every octant and axis: the negative
 // extent is the larger one).

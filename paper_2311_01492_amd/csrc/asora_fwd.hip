@@ -371,7 +371,7 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
         if (A.coldens) A.coldens[cs] = 0.0;
     }
     const int Mx = min(isqrt_floor(Rsq), L.ext_d);
-    for (int k = lane; k < (Mx + 1) * S; k += 64) lay[k] = 0.0;   // finite everywhere it is read
+    for (int k = lane; k < S * S; k += 64) lay[k] = 0.0;   // finite everywhere it is read
     wave_sync();
     int head = 0, tail = 0;
     long off = 0;   // first cell of layer m in the record
@@ -481,12 +481,12 @@ __global__ __launch_bounds__(1024) void fwd_layer(FwdArgs A)
     }
 }
 
-// Per-wave LDS of the layer kernel: the rate queue, then (Mcap + 1) rows of S
-// doubles.
-size_t layer_region_bytes(int Mcap, int S)
+// Per-wave LDS of the layer kernel: the rate queue, then the S x S layer
+// buffer.
+size_t layer_region_bytes(int S)
 {
     const size_t b = (size_t)kQueue * (sizeof(double) + sizeof(float) + sizeof(uint32_t) + sizeof(int)) +
-                     (size_t)(Mcap + 1) * S * sizeof(double);
+                     (size_t)S * S * sizeof(double);
     return (b + 15) & ~(size_t)15;
 }
 
@@ -496,13 +496,13 @@ hipError_t layer_occupancy(bool tab_lds, int waves, size_t lds, int *blocks_per_
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, waves * 64, lds);
 }
 
-hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int Mcap, int waves, int grid,
+hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int S, int waves, int grid,
                             int plain_src)
 {
     FwdArgs A = make_args(F);
     A.plain_src = plain_src;
-    A.lay_S = Mcap + 1;
-    A.region_bytes = (int)layer_region_bytes(Mcap, A.lay_S);
+    A.lay_S = S;
+    A.region_bytes = (int)layer_region_bytes(S);
     const size_t lds = (F.tab_lds ? (size_t)F.tp.n * sizeof(TabNode) : 0) + (size_t)waves * A.region_bytes;
     if (plain_src >= 0) grid = (24 + waves - 1) / waves;
     const dim3 g(grid), b(64 * waves);

@@ -53,9 +53,9 @@ hipError_t launch_transpose_prologue(hipStream_t st, const float *nH, const floa
                                      double *gacc_T, int N);
 hipError_t launch_transpose_finalize(hipStream_t st, const double *gacc, const double *gacc_T,
                                      float *gamma, int N, int accumulate);
-size_t layer_region_bytes(int Mcap, int S);
+size_t layer_region_bytes(int S);
 hipError_t layer_occupancy(bool tab_lds, int waves, size_t lds, int *blocks_per_cu);
-hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int Mcap, int waves, int grid,
+hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int S, int waves, int grid,
                             int plain_src);
 size_t fwd_lds_bytes(int n_tab, int ring_cap, int row_cap);
 hipError_t fwd_configure(size_t max_lds);
@@ -108,9 +108,9 @@ hipError_t launch_adj_prologue(hipStream_t st, const float *nH, const float *xHI
                                int nctl, int n_cu);
 hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L);
 constexpr int kAdjLayerWaves = 12;   // largest work-group of the layer adjoint (waves)
-size_t adj_layer_region_bytes(int Mcap, int S, bool kept);
+size_t adj_layer_region_bytes(int Mcap, int S);
 hipError_t adj_layer_occupancy(bool kept, int waves, size_t lds, int *blocks_per_cu);
-hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int Mcap);
+hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int Mcap, int S);
 hipError_t launch_adj_transpose_prologue(hipStream_t st, const float *nH, const float *xHI,
                                          const double *gbar, double *nHI_T, double *gbar_T,
                                          double *nbar_T, int N);

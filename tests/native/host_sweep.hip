@@ -173,7 +173,8 @@ extern "C" int hc_raytrace(int N, double alpha, double sigma0, int n, double lg_
 // writes layer m.  Adds the rates to acc (when acc != NULL) and, when rec is
 // given, fills the column record as the kernels do (exit columns in rectangle
 // order, listed cells in chunk and lane order).  Returns -6 if a neighbour of
-// non-zero weight is read from a slot that does not hold layer m - 1.
+// non-zero weight is read from a slot that does not hold layer m - 1, -8 if a
+// cell falls outside the S x S layer buffer.
 static int layer_forward_piece(const LayerPiece &L, const LayerX &X, int Rsq, const TabNode *T,
                                const TabParams &tp, double coef, int S, double *lay, int *lay_id,
                                double *acc, double *coldens, int N, LayerRecord *rec)
@@ -198,6 +199,7 @@ static int layer_forward_piece(const LayerPiece &L, const LayerX &X, int Rsq, co
                 act[lane] = c * 64 + lane < r.total && uu[lane] * uu[lane] + vv[lane] * vv[lane] <= r.rem;
                 if (!act[lane]) continue;
                 const int u = uu[lane], v = vv[lane];
+                if (u >= S || v >= S) return -8;   // outside the S x S layer buffer
                 if (m > 1) {   // neighbours of non-zero weight must hold layer m - 1
                     const bool a0 = u > 0, a1 = u < m, b0 = v > 0, b1 = v < m;
                     const bool need[4] = {a1 && b1, a0 && b1, a1 && b0, a0 && b0};
@@ -266,7 +268,7 @@ static void host_layer_setup(HostLayerSetup &H, int N, int n, double lg_lo, doub
     for (long s = 0; s < nsrc; ++s) R_cap = R[s] > R_cap ? R[s] : R_cap;
     const int Rsq_cap = (int)std::floor((double)R_cap * (double)R_cap);
     H.Mcap = std::max(1, std::min(isqrt_floor(Rsq_cap), H.ex.neg));
-    H.S = H.Mcap + 1;
+    H.S = layer_buffer_side(Rsq_cap, H.ex);
     H.cap = std::max(1L, layer_piece_capacity(Rsq_cap, H.ex));
 }
 
@@ -294,8 +296,8 @@ extern "C" int hc_raytrace_layer(int N, double alpha, double sigma0, int n, doub
     host_layer_setup(H, N, n, lg_lo, lg_hi, P, dP, nH, xHI, nsrc, R);
     const long n3 = (long)N * N * N;
     std::vector<double> gT(n3, 0.0);
-    std::vector<double> lay((size_t)(H.Mcap + 1) * H.S);
-    std::vector<int> lay_id((size_t)(H.Mcap + 1) * H.S);
+    std::vector<double> lay((size_t)H.S * H.S);
+    std::vector<int> lay_id((size_t)H.S * H.S);
     const double coef_unit = sigma0 / (4.0 * M_PI * alpha * alpha);
     for (long s = 0; s < nsrc; ++s) {
         const int si = ijk[3 * s], sj = ijk[3 * s + 1], sk = ijk[3 * s + 2];
@@ -345,7 +347,7 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
         for (long j = 0; j < N; ++j)
             for (long k = 0; k < N; ++k) gbT[(k * N + i) * N + j] = gbar[(i * N + j) * N + k];
     const int S = H.S;
-    const size_t SS = (size_t)(H.Mcap + 1) * S;
+    const size_t SS = (size_t)S * S;
     std::vector<double> cols(SS), abar(SS), G(H.cap);
     std::vector<int> cols_id(SS);
     std::vector<char> recmem(layer_record_bytes(H.cap, H.Mcap));
