@@ -224,7 +224,7 @@ asora_status asora_store_info(const asora_ctx *ctx, int32_t *valid, uint64_t *by
 
 /*
  * asora_set_store_budget -- largest number of bytes of device memory the kept
- * column records may take (n_src x 24 x one pyramid's record, about 36 bytes
+ * column records may take (n_src x 24 x one pyramid's record, about 8 bytes
  * per cell of the largest pyramid).  0 (the default) means half of the free
  * device memory at the time of the forward call, plus what is already held.
  * A forward call with ASORA_STORE that needs more keeps nothing.

@@ -213,28 +213,23 @@ __global__ __launch_bounds__(512) void adj_wave(AdjArgs A)
 }
 
 // ---- layer pieces --------------------------------------------------------
-// One wave per pyramid, in three passes.
+// One wave per pyramid, in two passes.
 //  (F) Unless the forward kept the pyramid's column record: the columns layer
-//      by layer, in place in the LDS buffer `cols` as in the forward kernel,
-//      every exit column written to the record in the wave's scratch, and the
-//      owned cells whose entry optical depth lies inside the table (the cells
-//      with a rate) listed with their optical depths.
-//  (G) The listed cells, 64 at a time with every lane busy: the rate's
-//      derivatives (FP64), its in-cell term of dL/dn_HI, its share of dL/dQ,
-//      and its entry-column term g_in, kept per listed cell.
-//  (R) Layers from the outermost inward: the g_in of layer m's listed cells
-//      are added to their adjoint slots in `abar`; then layer m's rectangle
-//      in chunks from the first to the last: every cell takes and clears its
-//      slot (the adjoint of its exit column, which flows into its entry
-//      column and its in-cell column alike), adds alpha ds times it to
-//      dL/dn_HI and pushes it through the interpolation weights, with its
-//      neighbours' exit columns read from the record, to the slots of its
-//      layer m - 1 neighbours with LDS atomics.  A neighbour slot precedes the
-//      pushing cell in (u, v) order, so it was already taken in this layer.
-//      Chunks whose slots are all zero (cells that no listed cell depends on)
-//      skip the arithmetic and the record.
-// The table is read from global memory (only the listed cells use it), which
-// leaves the LDS to the per-wave buffers.
+//      by layer, in place in the LDS buffer as in the forward kernel, every
+//      cell's layer-buffer entry written to the record in the wave's scratch
+//      together with each chunk's mask of cells with a rate.
+//  (R) Layers from the outermost inward, each layer's rectangle in chunks
+//      from the first to the last: every cell takes and clears its slot in
+//      the LDS adjoint buffer (the adjoint of its exit column, pushed by its
+//      consumers), adds its rate's terms if it has one (FP64 derivatives),
+//      adds its dL/dn_HI with one atomic and pushes the adjoint of its entry
+//      column through the interpolation weights, read from the record's
+//      entries of layer m - 1, to its neighbours' slots with LDS atomics.  A
+//      neighbour slot precedes the pushing cell in (u, v) order, so it was
+//      already taken in this layer.  Chunks with no rate and all slots zero
+//      (cells no rate depends on) skip the arithmetic and the record.
+// The table is read from global memory (only cells with a rate use it),
+// which leaves the LDS to the per-wave buffers.
 __device__ __forceinline__ void wave_sync_global()
 {
     // this wave's global stores complete before its later global loads by
@@ -245,8 +240,8 @@ __device__ __forceinline__ void wave_sync_global()
 }
 
 template <bool KEPT>
-__device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *cols, double *abar,
-                                    int *litoff, char *scratch, int src, int p, int lane)
+__device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *buf, char *scratch, int src,
+                                    int p, int lane)
 {
     const int N = A.N;
     const int si = A.ijk[3 * src], sj = A.ijk[3 * src + 1], sk = A.ijk[3 * src + 2];
@@ -276,17 +271,14 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
     const int S = A.lay_S;
     const LayerRecord rec = layer_record_at(
         KEPT ? (char *)A.kept + ((size_t)src * 24 + p) * A.rec_piece_bytes : scratch, A.rec_cap);
-    double *gin = (double *)(scratch + A.rec_piece_bytes);   // g_in per listed cell
     const int Mx = min(isqrt_floor(Rsq), L.ext_d);
 
     // ---- (F)
-    long off = 0;
+    long off = 0, choff = 0;   // ends: cells and chunks of the record
     if (!KEPT) {
-        for (int k = lane; k < S * S; k += 64) cols[k] = 0.0;   // finite everywhere it is read
+        for (int k = lane; k < S * S; k += 64) buf[k] = 0.0;   // finite everywhere it is read
         wave_sync();
-        int tail = 0;
         for (int m = 1; m <= Mx; ++m) {
-            if (lane == 0) litoff[m] = tail;
             const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
             const double inv_m = rcp_f64((double)m);
             const int nch = (r.total + 63) / 64;
@@ -302,91 +294,74 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
                 lc.owned = false;
                 if (act) {
                     const uint32_t cp = layer_cp(L, N, m, u, v);
-                    layer_cell_at(L, X, m, inv_m, u, v, cp, X.nHI[cp], cols, pos, S, lc);
+                    layer_cell_at(L, X, m, inv_m, u, v, cp, X.nHI[cp], buf, pos, S, lc);
                 }
                 wave_sync();
                 bool lit = false;
                 if (act) {
-                    cols[pos] = lc.h;
-                    rec.N[off + g] = lc.Nout;
+                    buf[pos] = lc.h;
+                    rec.h[off + g] = lc.h;
                     lit = lc.owned && A.sigma0 * lc.Nin < A.tp.tau_hi;
                 }
                 const uint64_t mask = __ballot(lit);
-                if (lit) {
-                    const int k = tail + (int)__builtin_amdgcn_mbcnt_hi(
-                                             (uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
-                    rec.ta[k] = A.sigma0 * lc.Nin;
-                    rec.dt[k] = A.sigma0 * lc.dN;
-                    rec.cp[k] = lc.cp;
-                    rec.pm[k] = pos | (m << 16);
-                    rec.r2[k] = lc.r2;
-                }
-                tail += __popcll(mask);
+                if (lane == 0) rec.lit[choff + c] = mask;
                 wave_sync();
             }
             off += r.total;
+            choff += nch;
         }
-        if (lane == 0) litoff[Mx + 1] = tail;
     } else {
-        for (int k = 1 + lane; k <= Mx + 1; k += 64) litoff[k] = rec.litoff[k];
-        for (int m = 1; m <= Mx; ++m) off += layer_rect(L.ext_u, L.ext_v, Rsq, m).total;
-    }
-    wave_sync_global();
-    const int nrec = litoff[Mx + 1];
-
-    // ---- (G)
-    double nb_src = 0.0, qb = 0.0;
-    for (int k0 = 0; k0 < nrec; k0 += 64) {
-        const int k = k0 + lane;
-        if (k < nrec) {
-            const uint32_t cp = rec.cp[k];
-            const double gb = gbar[cp];
-            double gi = 0.0;
-            if (gb != 0.0) {
-                double ne, gG;
-                record_rate_adjoint(T, A.m64, A.tp, A.sigma0, A.alpha, coef, rec.ta[k], rec.dt[k], rec.r2[k],
-                                    rec.pm[k] >> 16, gb, &gi, &ne, &gG);
-                if (ne != 0.0) unsafeAtomicAdd(&nbar[cp], ne);
-                qb += gG;
-            }
-            gin[k] = gi;
+        for (int m = 1; m <= Mx; ++m) {
+            const int t = layer_rect(L.ext_u, L.ext_v, Rsq, m).total;
+            off += t;
+            choff += (t + 63) / 64;
         }
     }
-    for (int k = lane; k < S * S; k += 64) abar[k] = 0.0;   // the column buffer of (F), reused
+    for (int k = lane; k < S * S; k += 64) buf[k] = 0.0;   // the adjoint slots
     wave_sync_global();
 
     // ---- (R)
+    double nb_src = 0.0, qb = 0.0;
     for (int m = Mx; m >= 1; --m) {
         const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
-        off -= r.total;   // first cell of layer m in the record
-        // exit columns of layer m - 1 (its rectangle precedes layer m's)
-        const int wvp = m >= 2 ? layer_rect(L.ext_u, L.ext_v, Rsq, m - 1).wv : 1;
-        const double *Nprev = rec.N + (m >= 2 ? off - layer_rect(L.ext_u, L.ext_v, Rsq, m - 1).total : 0);
-        for (int k = litoff[m] + lane; k < litoff[m + 1]; k += 64) abar[rec.pm[k] & 0xffff] += gin[k];
-        wave_sync();
+        const int nch = (r.total + 63) / 64;
+        off -= r.total;    // first cell of layer m in the record
+        choff -= nch;      // its first chunk
+        // entries of layer m - 1 (its rectangle precedes layer m's)
+        const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m >= 2 ? m - 1 : 1);
+        const int wvp = rp.wv;
+        const double *Hprev = rec.h + (m >= 2 ? off - rp.total : 0);
         RectWalk w;
         w.init(r, lane);
-        for (int c = 0; c < (r.total + 63) / 64; ++c, w.up()) {
+        uint64_t masks = 0;   // the rate masks of chunks c0 .. c0 + 63, one per lane
+        for (int c = 0; c < nch; ++c, w.up()) {
+            if ((c & 63) == 0) masks = c + lane < nch ? rec.lit[choff + c + lane] : 0;
             const int g = c * 64 + lane;
             const int u = w.u, v = w.v;
             const bool act = g < r.total && mul24(u, u) + mul24(v, v) <= r.rem;
-            double Tin = 0.0;
+            const uint64_t litmask =
+                ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(masks >> 32), c & 63) << 32) |
+                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)masks, c & 63);
+            const bool lit = (litmask >> lane) & 1;
+            double Tout = 0.0;
             if (act) {
-                Tin = abar[mul24(u, S) + v];
-                abar[mul24(u, S) + v] = 0.0;
+                Tout = buf[mul24(u, S) + v];
+                buf[mul24(u, S) + v] = 0.0;
             }
             wave_sync();
-            if (__ballot(Tin != 0.0)) {
-                if (Tin != 0.0) {
+            if (__ballot(Tout != 0.0) | litmask) {
+                if (Tout != 0.0 || lit) {
                     LayerRev lr;
-                    layer_cell_reverse(L, X, m, u, v, Nprev, wvp, Tin, lr);
+                    layer_cell_reverse(L, X, T, A.m64, A.tp, coef, m, u, v, Hprev, wvp, lit, gbar, Tout, lr);
                     if (m >= 2) {
 #pragma unroll
                         for (int n = 0; n < 4; ++n)
-                            if (lr.Mbar[n] != 0.0) atomicAdd(&abar[(u - (n & 1)) * S + (v - (n >> 1))], lr.Mbar[n]);
+                            if (lr.Mbar[n] != 0.0)
+                                atomicAdd(&buf[mul24(u - (n & 1), S) + (v - (n >> 1))], lr.Mbar[n]);
                     }
                     if (lr.nbar != 0.0) unsafeAtomicAdd(&nbar[lr.cp], lr.nbar);
                     nb_src += lr.nbar_src;
+                    qb += lr.qb;
                 }
                 wave_sync();
             }
@@ -418,12 +393,8 @@ __global__ __launch_bounds__(kAdjLayerThreads) void adj_layer(AdjArgs A)
     const TabNode *T = A.tab;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
-    // per wave: one S x S buffer, the columns in (F) and the adjoints in (R),
-    // then the layer offsets of the cell list
-    const size_t buf = (size_t)A.lay_S * A.lay_S;
-    double *cols = (double *)(smem + (size_t)wave * A.region_bytes);
-    double *abar = cols;
-    int *litoff = (int *)(cols + buf);
+    // per wave: one S x S buffer, the columns in (F) and the adjoints in (R)
+    double *buf = (double *)(smem + (size_t)wave * A.region_bytes);
     char *scratch = (char *)(A.store + (size_t)(blockIdx.x * waves + wave) * A.store_stride);
     const int base = A.seg[TYPE];
     const int nitems = (A.seg[TYPE + 1] - base) * npieces;
@@ -433,7 +404,7 @@ __global__ __launch_bounds__(kAdjLayerThreads) void adj_layer(AdjArgs A)
         const int item = next_item(A.counter, nitems, home, chunk, lane);
         if (item >= nitems) break;
         const int src = A.order[base + item / npieces];
-        adjoint_layer_piece<KEPT>(A, T, cols, abar, litoff, scratch, src, item % npieces, lane);
+        adjoint_layer_piece<KEPT>(A, T, buf, scratch, src, item % npieces, lane);
     }
 }
 
@@ -623,10 +594,10 @@ hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L)
 }
 
 // Per-wave LDS of the layer adjoint: the S x S buffer (columns, then
-// adjoints), then the per-layer offsets of the cell list.
-size_t adj_layer_region_bytes(int Mcap, int S)
+// adjoints).
+size_t adj_layer_region_bytes(int S)
 {
-    return ((size_t)S * S * sizeof(double) + (size_t)(Mcap + 2) * sizeof(int) + 15) & ~(size_t)15;
+    return ((size_t)S * S * sizeof(double) + 15) & ~(size_t)15;
 }
 
 hipError_t adj_layer_occupancy(bool kept, int waves, size_t lds, int *blocks_per_cu)
@@ -640,7 +611,7 @@ hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int Mcap, int S)
     AdjArgs A = make_adj_args(L);
     A.Mcap = Mcap;
     A.lay_S = S;
-    A.region_bytes = (int)adj_layer_region_bytes(Mcap, S);
+    A.region_bytes = (int)adj_layer_region_bytes(S);
     const size_t lds = (size_t)L.waves * A.region_bytes;
     if (A.kept) hipLaunchKernelGGL(adj_layer<true>, dim3(L.grid), dim3(64 * L.waves), lds, st, A);
     else hipLaunchKernelGGL(adj_layer<false>, dim3(L.grid), dim3(64 * L.waves), lds, st, A);

@@ -731,9 +731,8 @@ static asora_status get_adj_plan(asora_ctx *c, int type, float R_cap, Plan *out)
     return ASORA_OK;
 }
 
-// Adjoint layer pieces: the adjoint buffer (and, when the columns are
-// recomputed, the column buffer) per wave in LDS; a pyramid column record and
-// the rate's entry-column terms in the wave's scratch.
+// Adjoint layer pieces: one layer buffer per wave in LDS (columns, then
+// adjoints); a pyramid column record in the wave's scratch.
 static asora_status get_adj_layer_plan(asora_ctx *c, float R_cap, bool kept, Plan *out)
 {
     const int Rsq = (int)std::floor((double)R_cap * (double)R_cap);
@@ -746,7 +745,7 @@ static asora_status get_adj_layer_plan(asora_ctx *c, float R_cap, bool kept, Pla
     Plan P;
     asora_status st = get_layer_plan(c, R_cap, &P);   // Mcap, record sizes
     if (st) return st;
-    const size_t region = adj_layer_region_bytes(P.Mcap, P.S);
+    const size_t region = adj_layer_region_bytes(P.S);
     const long fit = c->max_lds > 64 ? (long)((c->max_lds - 64) / region) : 0;
     if (fit < 1)
         return fail(c, ASORA_ENOSYS,
@@ -759,7 +758,7 @@ static asora_status get_adj_layer_plan(asora_ctx *c, float R_cap, bool kept, Pla
     HIPCHK(c, adj_layer_occupancy(kept, P.waves, P.lds, &bpc));
     P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
     P.piece_cells = P.rec_cap;
-    P.scratch = (long)((P.rec_bytes + sizeof(double) * (size_t)P.rec_cap) / sizeof(double));
+    P.scratch = (long)(P.rec_bytes / sizeof(double));
     c->adj_plans[key] = P;
     *out = P;
     return ASORA_OK;

@@ -127,6 +127,7 @@ struct TabParams {
     int n;          // number of nodes
     double x_lo;    // ln tau_0
     double inv_h;   // 1 / h, h = node spacing in ln tau
+    double h64;     // h
     float h, inv_hf;
     double tau_lo;  // tau_0
     double tau_hi;  // tau_{n-1}
@@ -540,7 +541,7 @@ __host__ __device__ __forceinline__ void tab_eval64(const TabNode *T, const doub
     int j = (int)floor(t);
     j = j < 0 ? 0 : (j > tp.n - 2 ? tp.n - 2 : j);
     const double f = t - (double)j;
-    const double h = 1.0 / tp.inv_h;
+    const double h = tp.h64;
     const double d = T[j + 1].y - T[j].y;
     const double hm0 = h * m64[j], hm1 = h * m64[j + 1];
     const double c1 = hm0, c2 = 3.0 * d - 2.0 * hm0 - hm1, c3 = -2.0 * d + hm0 + hm1;
@@ -548,7 +549,7 @@ __host__ __device__ __forceinline__ void tab_eval64(const TabNode *T, const doub
     const double yx = (c1 + f * (2.0 * c2 + 3.0 * f * c3)) * tp.inv_h;
     const double yxx = (2.0 * c2 + 6.0 * f * c3) * tp.inv_h * tp.inv_h;
     const double p = exp_f64(y);
-    const double it = 1.0 / tau;
+    const double it = rcp_f64(tau);   // tau in [tau_lo, tau_hi): FP32 normal range
     *P = p;
     *d1 = p * yx * it;
     *d2 = p * (yx * yx + yxx - yx) * it * it;
@@ -569,7 +570,7 @@ __host__ __device__ __forceinline__ void rate_derivs64(const TabNode *T, const d
     if (dt > 1e-4 * a && dt > 0.0) {
         double Pb, Pb1, Pb2;
         tab_eval64(T, m64, tp, a + dt, &Pb, &Pb1, &Pb2);
-        const double idt = 1.0 / dt;
+        const double idt = dt > 1e-30 ? rcp_f64(dt) : 1.0 / dt;
         const double d = (Pb - Pa) * idt;
         *D = d;
         *dDda = (Pb1 - Pa1) * idt;
@@ -880,38 +881,28 @@ __host__ __device__ inline long layer_piece_capacity(int Rsq, const Extent &ex)
 }
 
 // Column record of one pyramid (a piece of layer kind) in global memory: the
-// exit column of every cell, layer by layer in rectangle order, and a list of
-// the owned cells whose entry optical depth lies inside the table (the cells
-// with a rate), in sweep order, with litoff[m] the first record of layer m.
-// `cap` bounds both the cells and the records of the pyramid.  Written by the
-// forward sweep when the columns are kept, or by the adjoint's own forward
-// pass; read by the adjoint's reverse pass.
+// exit column of every cell as its layer-buffer entry (layer_entry), layer by
+// layer in rectangle order, and for every chunk of 64 cells (layers in
+// order, chunks of a layer in order) the mask of its cells that carry a rate
+// (owned, entry optical depth inside the table).  Written by the forward
+// sweep when the columns are kept, or by the adjoint's own forward pass; read
+// by the adjoint's reverse pass.  `cap` bounds the cells of one pyramid.
 struct LayerRecord {
-    double *N;        // [cap] exit columns
-    double *ta;       // [cap] entry optical depth of each listed cell
-    double *dt;       // [cap] its in-cell optical depth (FP64)
-    uint32_t *cp;     // [cap] its cell index in the piece's field layout
-    int *pm;          // [cap] its buffer slot u * S + v (low 16 bits) and layer m (bits 16..)
-    int *r2;          // [cap] its squared distance from the source (cells)
-    int *litoff;      // [Mcap + 2] first record of each layer m; litoff[Mx + 1] = count
+    double *h;        // [cap] layer-buffer entries of the cells
+    uint64_t *lit;    // [cap / 64 + Mcap + 1] rate masks, one per chunk
 };
 
 __host__ __device__ __forceinline__ size_t layer_record_bytes(long cap, int Mcap)
 {
-    const size_t b = (size_t)cap * (3 * sizeof(double) + 3 * sizeof(int)) + (size_t)(Mcap + 2) * sizeof(int);
+    const size_t b = (size_t)cap * sizeof(double) + ((size_t)cap / 64 + Mcap + 1) * sizeof(uint64_t);
     return (b + 255) & ~(size_t)255;
 }
 
 __host__ __device__ __forceinline__ LayerRecord layer_record_at(char *base, long cap)
 {
     LayerRecord s;
-    s.N = (double *)base;
-    s.ta = s.N + cap;
-    s.dt = s.ta + cap;
-    s.cp = (uint32_t *)(s.dt + cap);
-    s.pm = (int *)(s.cp + cap);
-    s.r2 = s.pm + cap;
-    s.litoff = s.r2 + cap;
+    s.h = (double *)base;
+    s.lit = (uint64_t *)(s.h + cap);
     return s;
 }
 
@@ -1168,100 +1159,87 @@ __host__ __device__ __forceinline__ void layer_cell_adjoint(const LayerPiece &L,
     }
 }
 
-// Reverse-mode update of layer cell (u, v) of layer m through the
-// interpolation alone.  Tin is the total adjoint of the cell's entry column:
-// the adjoints its consumers pushed to its exit column plus the rate's own
-// entry-column term (the rate's in-cell term reaches dL/dn_HI separately, see
-// record_rate_adjoint).  Since N_out = N_in + dN, the exit-column adjoint
-// flows unchanged into both N_in and dN.  Nprev holds the exit columns of
-// layer m - 1 as its rectangle (row width wvp): neighbour (u', v') is
-// Nprev[u' * wvp + v'].  Returns the adjoints to push to the four neighbours
-// of layer m - 1 (Mbar[n] for neighbour (u - (n & 1), v - (n >> 1)); zero
-// where the weight is zero; for m = 1 the source takes them through
-// nbar_src) and dL/dn_HI of the cell.
+// Reverse-mode update of layer cell (u, v) of layer m.  T is the adjoint of
+// the cell's exit column (what its consumers pushed); lit says that the cell
+// carries a rate (owned, entry optical depth inside the table, as the forward
+// found).  Since N_out = N_in + dN, T flows into both N_in and dN; a lit cell
+// adds its rate's terms: with Gamma = k D(tau_in, dtau), k = -coef / r2,
+// g_in = gbar dGamma/dN_in and g_dN = gbar dGamma/d(dN) from the FP64 rate
+// derivatives (dL/dGamma gbar read only for lit cells).  Hprev holds the
+// layer-buffer entries (layer_entry) of layer m - 1 as its rectangle (row
+// width wvp): neighbour (u', v') is Hprev[u' * wvp + v'].  With
+// N_in = sum s g / sum s f (f, g as in layer_entry),
+// dN_in/dM_n = s_n sigma0 N_in f_n^2 / W for a neighbour with
+// sigma0 M_n > tau_w (f_n = 1/(sigma0 M_n)) and s_n f_n / W for any other
+// (f_n constant), W = sum s f: the entries alone suffice.  Returns the
+// adjoints to push to the four neighbours of layer m - 1 (Mbar[n] for
+// neighbour (u - (n & 1), v - (n >> 1)); zero where the weight is zero; for
+// m = 1 the source takes them through nbar_src), dL/dn_HI of the cell
+// ((T + g_dN) alpha ds) and gbar Gamma (for dL/dQ).
 struct LayerRev {
     uint32_t cp;
     double Mbar[4];
     double nbar_src;
     double nbar;
+    double qb;
 };
 
-__host__ __device__ __forceinline__ void layer_cell_reverse(const LayerPiece &L, const LayerX &X, int m,
-                                                            int u, int v, const double *Nprev, int wvp,
-                                                            double Tin, LayerRev &out)
+__host__ __device__ __forceinline__ void layer_cell_reverse(const LayerPiece &L, const LayerX &X,
+                                                            const TabNode *T, const double *m64,
+                                                            const TabParams &tp, double coef, int m,
+                                                            int u, int v, const double *Hprev, int wvp,
+                                                            bool lit, const double *gbar_grid, double Tout,
+                                                            LayerRev &out)
 {
-    const int N = X.N;
-    out.cp = (uint32_t)wrap(L.c_d + L.sd * m, N) * L.st_d + (uint32_t)wrap(L.c_u + L.su * u, N) * L.st_u +
-             (uint32_t)wrap(L.c_v + L.sv * v, N);
+    out.cp = layer_cp(L, X.N, m, u, v);
     const double inv_m = rcp_f64((double)m);
-    const double ds = sqrt_fast((double)(m * m + u * u + v * v)) * inv_m;
-    out.nbar = Tin * X.alpha * ds;                    // dN = n_HI alpha ds
-    out.nbar_src = 0.0;
-#pragma unroll
-    for (int n = 0; n < 4; ++n) out.Mbar[n] = 0.0;
-    if (m == 1) {   // the only neighbour of non-zero weight is the source: N_in = its column
-        out.nbar_src = Tin * (X.reading == 0 ? X.alpha * ds * 0.5 : X.alpha * 0.5);
-        return;
-    }
+    const int r2 = mul24(m, m) + mul24(u, u) + mul24(v, v);
+    const double ds = sqrt_fast((double)r2) * inv_m;
     const double a = u == m ? 1.0 : (double)u * inv_m;
     const double b = v == m ? 1.0 : (double)v * inv_m;
     const double sw[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
-    double Mv[4], wv[4], dw[4];
+    double f[4];
+    bool thick[4];
+    double Nin, iW = 1.0;
+    if (m == 1) {   // the only neighbour of non-zero weight is the source: N_in = its column
+        Nin = X.reading == 0 ? X.half_col * ds : X.half_col;
+    } else {
+        double num = 0.0, W = 0.0;
 #pragma unroll
-    for (int n = 0; n < 4; ++n)   // the neighbour columns first: independent loads
-        Mv[n] = sw[n] > 0.0 ? Nprev[(u - (n & 1)) * wvp + (v - (n >> 1))] : 0.0;
-    double num = 0.0, W = 0.0;
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-        wv[n] = 0.0;
-        dw[n] = 0.0;
-        if (!(sw[n] > 0.0)) continue;
-        const double M = Mv[n];
-        double wn = sw[n];
-        if (X.tau_w > 0.f) {
-            const double tau = X.sigma0 * M;
-            if (tau > (double)X.tau_w) {   // w = s / tau, dw/dM = -s sigma0 / tau^2
-                const double it = rcp_f64(tau);
-                wn *= it;
-                dw[n] = -sw[n] * X.sigma0 * it * it;
-            } else {
-                wn *= rcp_f64((double)X.tau_w);
-            }
+        for (int n = 0; n < 4; ++n) {   // zero-weight neighbours may lie outside layer m - 1: not read
+            const double h = sw[n] > 0.0 ? Hprev[(u - (n & 1)) * wvp + (v - (n >> 1))] : 0.0;
+            thick[n] = h > 0.0;
+            f[n] = thick[n] ? h : X.inv_tw;
+            const double g = thick[n] ? X.inv_s0 : -h * X.inv_tw;
+            num += sw[n] * g;
+            W += sw[n] * f[n];
         }
-        wv[n] = wn;
-        num += wn * M;
-        W += wn;
+        iW = rcp_f64(W);
+        Nin = num * iW;
     }
-    const double iW = rcp_f64(W);
-    const double Nin = num * iW;
+    double Tin = Tout, Tdn = Tout;
+    out.qb = 0.0;
+    const double gb = lit ? gbar_grid[out.cp] : 0.0;
+    if (gb != 0.0) {
+        const double dN = X.nHI[out.cp] * X.alpha * ds;
+        double D, Da, Ddt;
+        rate_derivs64(T, m64, tp, X.sigma0 * Nin, X.sigma0 * dN, &D, &Da, &Ddt);
+        const double k = -coef * rcp_f64((double)r2);
+        Tin += gb * k * Da * X.sigma0;
+        Tdn += gb * k * Ddt * X.sigma0;
+        out.qb = gb * k * D;
+    }
+    out.nbar = Tdn * X.alpha * ds;                    // dN = n_HI alpha ds
+    out.nbar_src = 0.0;
 #pragma unroll
-    for (int n = 0; n < 4; ++n)
-        out.Mbar[n] = sw[n] > 0.0 ? Tin * (wv[n] + (Mv[n] - Nin) * dw[n]) * iW : 0.0;
-}
-
-// The rate's part of the adjoint for one listed cell (entry optical depth
-// ta, in-cell optical depth dt, squared distance r2, layer m, dL/dGamma
-// gbar): Gamma = k D(ta, dt) with k = -coef / r2.  Returns the rate's
-// entry-column term g_in = gbar dGamma/dN_in (added to the cell's exit-column
-// adjoint before the interpolation is reversed), the part of dL/dn_HI of the
-// cell that the interpolation reverse does not produce,
-// (g_dN - g_in) alpha ds with g_dN = gbar dGamma/d(dN), and gbar Gamma.
-__host__ __device__ __forceinline__ void record_rate_adjoint(const TabNode *T, const double *m64,
-                                                             const TabParams &tp, double sigma0,
-                                                             double alpha, double coef, double ta,
-                                                             double dt, int r2, int m, double gbar,
-                                                             double *g_in, double *nbar_extra,
-                                                             double *gG)
-{
-    double D, Da, Ddt;
-    rate_derivs64(T, m64, tp, ta, dt, &D, &Da, &Ddt);
-    const double k = -coef / (double)r2;
-    const double gi = gbar * k * Da * sigma0;
-    const double gd = gbar * k * Ddt * sigma0;
-    const double ds = sqrt_fast((double)r2) * rcp_f64((double)m);
-    *g_in = gi;
-    *nbar_extra = (gd - gi) * alpha * ds;
-    *gG = gbar * k * D;
+    for (int n = 0; n < 4; ++n) out.Mbar[n] = 0.0;
+    if (m == 1) {
+        out.nbar_src = Tin * (X.reading == 0 ? X.alpha * ds * 0.5 : X.alpha * 0.5);
+        return;
+    }
+    const double tk = Tin * iW, tt = tk * X.sigma0 * Nin;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) out.Mbar[n] = sw[n] * f[n] * (thick[n] ? tt * f[n] : tk);
 }
 
 // Build the row table of shell q of a piece (serial form; the kernel runs

@@ -331,8 +331,8 @@ __global__ __launch_bounds__(1024) void fwd_wave(FwdArgs A)
 // before its own (u, v) in lexicographic order, so every slot a chunk reads
 // still holds layer m - 1 (the chunk's own writes follow its reads).  Rates go
 // through the same per-wave queue as the shell sweep.  With KEEP the sweep
-// also writes the pyramid's column record (exit columns and the cells with a
-// rate) for a later adjoint.
+// also writes the pyramid's column record (the cells' layer-buffer entries and
+// the chunks' masks of cells with a rate) for a later adjoint.
 template <bool KEEP>
 __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *lay,
                                   const RateQueue &Qa, int src, int p, int lane)
@@ -374,9 +374,9 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
     for (int k = lane; k < S * S; k += 64) lay[k] = 0.0;   // finite everywhere it is read
     wave_sync();
     int head = 0, tail = 0;
-    long off = 0;   // first cell of layer m in the record
+    long off = 0;     // first cell of layer m in the record
+    long choff = 0;   // first chunk of layer m in the record
     for (int m = 1; m <= Mx; ++m) {
-        if (KEEP && lane == 0) rec.litoff[m] = tail;
         const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
         const double inv_m = rcp_f64((double)m);
         const int nch = (r.total + 63) / 64;
@@ -398,13 +398,14 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
             bool want = false;
             if (act) {
                 lay[pos] = lc.h;
-                if (KEEP) rec.N[off + g] = lc.Nout;
+                if (KEEP) rec.h[off + g] = lc.h;
                 if (lc.owned) {
                     if (A.coldens) A.coldens[layer_std_index(L, N, m, u, v)] = lc.Nin;
                     want = A.sigma0 * lc.Nin < A.tp.tau_hi;
                 }
             }
             const uint64_t mask = __ballot(want);
+            if (KEEP && lane == 0) rec.lit[choff + c] = mask;
             if (want) {
                 const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -413,14 +414,6 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
                 Qa.dt[qpos] = A.sigma0 * lc.dN;
                 Qa.cp[qpos] = lc.cp;
                 Qa.r2[qpos] = lc.r2;
-                if (KEEP) {
-                    const int k = tail + rank;
-                    rec.ta[k] = A.sigma0 * lc.Nin;
-                    rec.dt[k] = A.sigma0 * lc.dN;
-                    rec.cp[k] = lc.cp;
-                    rec.pm[k] = pos | (m << 16);
-                    rec.r2[k] = lc.r2;
-                }
             }
             tail += __popcll(mask);
             if (tail - head >= 64) {
@@ -431,8 +424,8 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
             wave_sync();
         }
         off += r.total;
+        choff += nch;
     }
-    if (KEEP && lane == 0) rec.litoff[Mx + 1] = tail;
     if (tail > head) {
         wave_sync();
         if (lane < tail - head) rate_batch(A, T, Qa, head, lane, coef, acc);

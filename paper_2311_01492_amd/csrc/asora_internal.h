@@ -108,7 +108,7 @@ hipError_t launch_adj_prologue(hipStream_t st, const float *nH, const float *xHI
                                int nctl, int n_cu);
 hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L);
 constexpr int kAdjLayerWaves = 12;   // largest work-group of the layer adjoint (waves)
-size_t adj_layer_region_bytes(int Mcap, int S);
+size_t adj_layer_region_bytes(int S);
 hipError_t adj_layer_occupancy(bool kept, int waves, size_t lds, int *blocks_per_cu);
 hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int Mcap, int S);
 hipError_t launch_adj_transpose_prologue(hipStream_t st, const float *nH, const float *xHI,

@@ -102,6 +102,7 @@ void prepare_table(int n, double lg_lo, double lg_hi, const double *P, const dou
     tp->inv_h = 1.0 / h;
     tp->h = (float)h;
     tp->inv_hf = (float)(1.0 / h);
+    tp->h64 = h;
     tp->tau_lo = std::exp(tp->x_lo);
     tp->tau_hi = std::exp(tp->x_lo + h * (n - 1));
     tp->dP0 = (float)dP[0];

@@ -180,10 +180,8 @@ static int layer_forward_piece(const LayerPiece &L, const LayerX &X, int Rsq, co
                                double *acc, double *coldens, int N, LayerRecord *rec)
 {
     const int Mx = std::min(isqrt_floor(Rsq), L.ext_d);
-    long off = 0;
-    int nrec = 0;
+    long off = 0, choff = 0;
     for (int m = 1; m <= Mx; ++m) {
-        if (rec) rec->litoff[m] = nrec;
         const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
         const int nch = (r.total + 63) / 64;
         RectWalk wk[64];
@@ -208,33 +206,28 @@ static int layer_forward_piece(const LayerPiece &L, const LayerX &X, int Rsq, co
                 }
                 layer_cell(L, X, m, u, v, lay, S, lc[lane]);
             }
+            uint64_t mask = 0;
             for (int lane = 0; lane < 64; ++lane) {
                 if (!act[lane]) continue;
                 const int u = uu[lane], v = vv[lane];
                 lay[(size_t)u * S + v] = lc[lane].h;
                 lay_id[(size_t)u * S + v] = m;
-                if (rec) rec->N[off + c * 64 + lane] = lc[lane].Nout;
+                if (rec) rec->h[off + c * 64 + lane] = lc[lane].h;
                 if (!lc[lane].owned) continue;
                 if (coldens) coldens[layer_std_index(L, N, m, u, v)] = lc[lane].Nin;
                 const double ta = X.sigma0 * lc[lane].Nin;
                 if (ta >= tp.tau_hi) continue;
-                if (rec) {
-                    rec->ta[nrec] = ta;
-                    rec->dt[nrec] = X.sigma0 * lc[lane].dN;
-                    rec->cp[nrec] = lc[lane].cp;
-                    rec->pm[nrec] = (u * S + v) | (m << 16);
-                    rec->r2[nrec] = lc[lane].r2;
-                    ++nrec;
-                }
+                mask |= 1ull << lane;
                 if (acc) {
                     const float nd = neg_divdiff(T, tp, ta, (double)(float)(X.sigma0 * lc[lane].dN));
                     if (nd > 0.f) acc[lc[lane].cp] += coef * (double)(nd * rcp_approx((float)lc[lane].r2));
                 }
             }
+            if (rec) rec->lit[choff + c] = mask;
         }
         off += r.total;
+        choff += nch;
     }
-    if (rec) rec->litoff[Mx + 1] = nrec;
     return 0;
 }
 
@@ -323,16 +316,15 @@ extern "C" int hc_raytrace_layer(int N, double alpha, double sigma0, int n, doub
 }
 
 // Reverse mode on the CPU through the layer pieces, in the adjoint kernel's
-// order, per pyramid: (F) the forward pass fills the column record (exit
-// columns, listed cells); (G) the listed cells' rate terms in record order;
-// (R) layers from the outermost inward: the rate's entry-column terms of
-// layer m added to its adjoint slots, then layer m's rectangle in chunks from
-// the first to the last, each chunk reading its slots, clearing them and
-// adding to its layer m - 1 neighbours, whose exit columns it reads from the
-// record.  dL/dn_HI of pyramids with dominant axis k goes through a
-// [k][i][j] buffer as on the GPU.  Returns -6 if a neighbour of non-zero
-// weight is not an active cell of layer m - 1, -7 if a record slot is not a
-// cell of its layer.
+// order, per pyramid: (F) the forward pass fills the column record (the
+// cells' layer-buffer entries, each chunk's mask of cells with a rate); (R)
+// layers from the outermost inward, each layer's rectangle in chunks from the
+// first to the last, each chunk reading its slots and clearing them, adding
+// the rate terms of its cells with a rate, and pushing to its layer m - 1
+// neighbours, whose entries it reads from the record.  dL/dn_HI of pyramids
+// with dominant axis k goes through a [k][i][j] buffer as on the GPU.
+// Returns -6 if a neighbour of non-zero weight is not an active cell of layer
+// m - 1, -7 if a chunk mask marks an inactive lane.
 extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n, double lg_lo,
                                       double lg_hi, const double *P, const double *dP, double tau_w,
                                       int reading, const float *nH, const float *xHI, long nsrc,
@@ -348,7 +340,7 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
             for (long k = 0; k < N; ++k) gbT[(k * N + i) * N + j] = gbar[(i * N + j) * N + k];
     const int S = H.S;
     const size_t SS = (size_t)S * S;
-    std::vector<double> cols(SS), abar(SS), G(H.cap);
+    std::vector<double> cols(SS), abar(SS);
     std::vector<int> cols_id(SS);
     std::vector<char> recmem(layer_record_bytes(H.cap, H.Mcap));
     LayerRecord rec = layer_record_at(recmem.data(), H.cap);
@@ -372,54 +364,42 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
             int st = layer_forward_piece(L, X, Rsq, H.T.data(), H.tp, coef, S, cols.data(), cols_id.data(),
                                          nullptr, nullptr, N, &rec);
             if (st) return st;
-            // (G)
-            const int nrec = rec.litoff[Mx + 1];
-            for (int k = 0; k < nrec; ++k) {
-                G[k] = 0.0;
-                const double g = gb[rec.cp[k]];
-                if (g == 0.0) continue;
-                double ne, gG;
-                record_rate_adjoint(H.T.data(), H.m64.data(), H.tp, sigma0, alpha, coef, rec.ta[k], rec.dt[k],
-                                    rec.r2[k], rec.pm[k] >> 16, g, &G[k], &ne, &gG);
-                nb[rec.cp[k]] += ne;
-                qb += gG;
-            }
             // (R)
             std::fill(abar.begin(), abar.end(), 0.0);
-            long off = 0;
-            for (int m = 1; m <= Mx; ++m) off += layer_rect(L.ext_u, L.ext_v, Rsq, m).total;
+            long off = 0, choff = 0;
+            for (int m = 1; m <= Mx; ++m) {
+                const int t = layer_rect(L.ext_u, L.ext_v, Rsq, m).total;
+                off += t;
+                choff += (t + 63) / 64;
+            }
             for (int m = Mx; m >= 1; --m) {
                 const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
+                const int nch = (r.total + 63) / 64;
                 off -= r.total;   // first cell of layer m
-                LayerRect rp = r;
-                const double *Nprev = nullptr;
-                if (m >= 2) {
-                    rp = layer_rect(L.ext_u, L.ext_v, Rsq, m - 1);
-                    Nprev = rec.N + off - rp.total;
-                }
-                for (int k = rec.litoff[m]; k < rec.litoff[m + 1]; ++k) {
-                    const int pos = rec.pm[k] & 0xffff;
-                    if ((rec.pm[k] >> 16) != m) return -7;
-                    abar[pos] += G[k];
-                }
+                choff -= nch;
+                const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m >= 2 ? m - 1 : 1);
+                const double *Hprev = rec.h + (m >= 2 ? off - rp.total : 0);
                 RectWalk wk[64];
                 for (int lane = 0; lane < 64; ++lane) wk[lane].init(r, lane);
-                for (int c = 0; c < (r.total + 63) / 64; ++c) {
+                for (int c = 0; c < nch; ++c) {
                     LayerRev lr[64];
                     bool act[64];
                     int uu[64], vv[64];
-                    double Tin[64];
+                    double Tout[64];
+                    const uint64_t litmask = rec.lit[choff + c];
                     for (int lane = 0; lane < 64; ++lane) {
                         uu[lane] = wk[lane].u;
                         vv[lane] = wk[lane].v;
                         wk[lane].up();
                         act[lane] = c * 64 + lane < r.total && uu[lane] * uu[lane] + vv[lane] * vv[lane] <= r.rem;
-                        Tin[lane] = act[lane] ? abar[(size_t)uu[lane] * S + vv[lane]] : 0.0;
+                        if (((litmask >> lane) & 1) && !act[lane]) return -7;
+                        Tout[lane] = act[lane] ? abar[(size_t)uu[lane] * S + vv[lane]] : 0.0;
                     }
                     for (int lane = 0; lane < 64; ++lane)
                         if (act[lane]) abar[(size_t)uu[lane] * S + vv[lane]] = 0.0;
                     for (int lane = 0; lane < 64; ++lane) {
-                        if (!act[lane] || Tin[lane] == 0.0) continue;
+                        const bool lit = (litmask >> lane) & 1;
+                        if (!act[lane] || (Tout[lane] == 0.0 && !lit)) continue;
                         const int u = uu[lane], v = vv[lane];
                         if (m > 1) {   // neighbours of non-zero weight: active cells of layer m - 1
                             const bool a0 = u > 0, a1 = u < m, b0 = v > 0, b1 = v < m;
@@ -427,17 +407,17 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
                             for (int k = 0; k < 4; ++k) {
                                 if (!need[k]) continue;
                                 const int un = u - (k & 1), vn = v - (k >> 1);
-                                int u2, v2;
-                                if (un >= rp.nu || vn >= rp.wv || !rect_cell(rp, un * rp.wv + vn, u2, v2))
-                                    return -6;
+                                if (un >= rp.nu || vn >= rp.wv || un * un + vn * vn > rp.rem) return -6;
                             }
                         }
-                        layer_cell_reverse(L, X, m, u, v, Nprev, rp.wv, Tin[lane], lr[lane]);
+                        layer_cell_reverse(L, X, H.T.data(), H.m64.data(), H.tp, coef, m, u, v, Hprev, rp.wv,
+                                           lit, gb, Tout[lane], lr[lane]);
                         for (int k = 0; k < 4; ++k)
                             if (lr[lane].Mbar[k] != 0.0)
                                 abar[(size_t)(u - (k & 1)) * S + (v - (k >> 1))] += lr[lane].Mbar[k];
                         nb[lr[lane].cp] += lr[lane].nbar;
                         nb_src += lr[lane].nbar_src;
+                        qb += lr[lane].qb;
                     }
                 }
             }
