@@ -335,7 +335,18 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
         w.init(r, lane);
         uint64_t masks = 0;   // the rate masks of chunks c0 .. c0 + 63, one per lane
         for (int c = 0; c < nch; ++c, w.up()) {
-            if ((c & 63) == 0) masks = c + lane < nch ? rec.lit[choff + c + lane] : 0;
+            if ((c & 63) == 0) {
+                uint32_t lo = 0, hi = 0;
+                if (c + lane < nch) {
+                    const uint64_t mk = rec.lit[choff + c + lane];
+                    lo = (uint32_t)mk;
+                    hi = (uint32_t)(mk >> 32);
+                }
+                // keep the 64 masks in registers: without this the compiler
+                // turns every readlane below back into a global load per chunk
+                asm volatile("" : "+v"(lo), "+v"(hi));
+                masks = ((uint64_t)hi << 32) | lo;
+            }
             const int g = c * 64 + lane;
             const int u = w.u, v = w.v;
             const bool act = g < r.total && mul24(u, u) + mul24(v, v) <= r.rem;
@@ -561,7 +572,7 @@ static AdjArgs make_adj_args(const AdjLaunch &L)
     A.R_cap = L.R_cap;
     A.order = L.order;
     A.seg = L.ctl + kCtlSeg;
-    A.counter = L.ctl + kCtlCounter + kXcds * L.type;
+    A.counter = L.ctl + kCtlCounter + kXcds * kCounterPad * L.type;
     A.err = L.err;
     A.ring_cap = L.ring_cap;
     A.row_cap = L.row_cap;

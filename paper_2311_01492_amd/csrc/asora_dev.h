@@ -8,6 +8,9 @@
 namespace asora {
 
 constexpr int kXcds = 8;   // accelerator dies (XCDs) of the MI355X, each with its own L2
+// Ints between two work counters: every counter has a 128-byte line of its
+// own, so that the atomics of different dies do not serialise on one line.
+constexpr int kCounterPad = 32;
 
 // Approximate reciprocal (about 1 ulp): the hardware instruction on the GPU.
 __host__ __device__ __forceinline__ float rcp_approx(float x)
@@ -1290,7 +1293,7 @@ __device__ __forceinline__ int next_item(int *counters, int nitems, int home, in
     for (;;) {
         const int lo = (int)((long)nitems * chunk / kXcds);
         const int hi = (int)((long)nitems * (chunk + 1) / kXcds);
-        const int got = atomicAdd(&counters[chunk], lane == 0 ? 1 : 0);
+        const int got = atomicAdd(&counters[chunk * kCounterPad], lane == 0 ? 1 : 0);
         const int k = __builtin_amdgcn_readfirstlane(got);
         if (lo + k < hi) return lo + k;
         chunk = chunk + 1 == kXcds ? 0 : chunk + 1;

@@ -822,7 +822,7 @@ static FwdArgs make_args(const FwdLaunch &F)
     A.seg = F.ctl + kCtlSeg;
     A.type = F.type;
     A.n_pieces = pieces_of_type(F.type);
-    A.counter = F.ctl + kCtlCounter + kXcds * F.type;
+    A.counter = F.ctl + kCtlCounter + kXcds * kCounterPad * F.type;
     A.err = F.err;
     A.ring_cap = F.ring_cap;
     A.row_cap = F.row_cap;

@@ -11,9 +11,10 @@ namespace asora {
 
 constexpr int kTypes = 4;                        // piece kinds: whole, octants, shell pyramids, layer pyramids
 constexpr int kSBins = 4096;                     // spatial bins per piece kind (16^3 blocks, Morton order)
-constexpr int kCtlCounter = 0;                   // work counters: kXcds per piece kind
-constexpr int kCtlSeg = kTypes * kXcds;          // kTypes + 1 segment starts
-constexpr int kCtlHist = kCtlSeg + 8;            // kTypes*kSBins histogram
+constexpr int kCtlCounter = 0;                   // work counters: kXcds per piece kind, one per
+                                                 // 128-byte line (kCounterPad ints apart)
+constexpr int kCtlSeg = kTypes * kXcds * kCounterPad;   // kTypes + 1 segment starts
+constexpr int kCtlHist = kCtlSeg + kCounterPad;  // kTypes*kSBins histogram
 constexpr int kCtlOffs = kCtlHist + kTypes * kSBins;  // kTypes*kSBins scatter offsets
 constexpr int kCtlSize = kCtlOffs + kTypes * kSBins;
 
