@@ -246,9 +246,10 @@ def main():
         print("[bench] autotune", file=sys.stderr, flush=True)
         best, rep = ctx.autotune(nH, xH, ijk, Q, R, R_max=R_max, passes=2)
         tuning = {"autotuned": True, "candidates": len(rep), "best_ms": best}
-    tw, to, twv, tsw, tpl = ctx.get_tuning()
-    tuning.update({"R_whole": tw, "R_oct": to, "max_waves": twv, "pyramid_sweep": tsw,
-                   "table_place": "lds" if tpl == 1 else "caches"})
+    tun = dict(zip(asora.TUNING_KEYS, ctx.get_tuning()))
+    tun["table_place"] = "lds" if tun["table_place"] == 1 else "caches"
+    tun["adj_rate"] = "split" if tun["adj_rate"] == 2 else "gathered"
+    tuning.update(tun)
 
     def timed_step(store):
         """Mean wall ms per step over args.steps steps (warm-up first), and the
@@ -318,12 +319,14 @@ def main():
     # the dominant sweep kernels: layer pyramids (sweep 3) or shell pyramids;
     # the step's adjoint reads kept records or recomputes; the forward alone
     # keeps nothing
-    tun = ctx.get_tuning()
-    big = R_max > tun[1]
-    layer = big and tun[3] == 3
-    tl = "true" if tun[4] == 1 else "false"
+    tun = dict(zip(asora.TUNING_KEYS, ctx.get_tuning()))
+    big = R_max > tun["R_oct"]
+    layer = big and tun["pyramid_sweep"] == 3
+    tl = "true" if tun["table_place"] == 1 else "false"
+    kp = "true" if kept else "false"
+    sp = "true" if tun["adj_rate"] == 2 else "false"
     kname = {"fwd": f"fwd_layer<false, {tl}>" if layer else "fwd_wave<2>",
-             "adj": ("adj_layer<true>" if kept else "adj_layer<false>") if layer else "adj_wave<2>"}
+             "adj": f"adj_layer<{kp}, {sp}>" if layer else "adj_wave<2>"}
     if not big:
         kname = {"fwd": "fwd_wave<1>", "adj": "adj_wave<1>"}
 

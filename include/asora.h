@@ -243,13 +243,20 @@ asora_status asora_set_store_budget(asora_ctx *ctx, uint64_t bytes);
  * in the adjoint.  table_place: where the layer forward reads the table, 1 =
  * a copy in LDS per work-group (the default), 2 = through the caches (which
  * leaves the LDS to more waves).  max_waves (1..16) caps the waves per
- * work-group.  Values <= 0 keep the current setting.  ASORA_EINVAL if
- * R_oct < R_whole, max_waves > 16, pyramid_sweep is not 0, 2 or 3 or
- * table_place not 0, 1 or 2; ASORA_ESTATE while a recorded graph of the
+ * work-group.  The adjoint of layer pyramids: adj_waves (1..12, default 4)
+ * waves per work-group; adj_rate 1 = the rate terms of every cell with a rate
+ * gathered into full waves before the reverse pass (fewer registers: suits
+ * sources whose rate reaches few cells), 2 = those of chunks where at least
+ * half the cells have a rate evaluated in the reverse pass itself (the
+ * default: suits sources that ionise most of their sphere).  Values <= 0
+ * keep the current setting.  ASORA_EINVAL if R_oct < R_whole, max_waves > 16,
+ * pyramid_sweep is not 0, 2 or 3, table_place not 0, 1 or 2, adj_waves > 12
+ * or adj_rate not 0, 1 or 2; ASORA_ESTATE while a recorded graph of the
  * context exists.
  */
 asora_status asora_set_tuning(asora_ctx *ctx, float R_whole, float R_oct, int32_t max_waves,
-                              int32_t pyramid_sweep, int32_t table_place);
+                              int32_t pyramid_sweep, int32_t table_place, int32_t adj_waves,
+                              int32_t adj_rate);
 
 /* asora_autotune flags */
 #define ASORA_TUNE_RETUNE 0x1u  /* time again even if this workload was tuned before */
@@ -260,8 +267,9 @@ asora_status asora_set_tuning(asora_ctx *ctx, float R_whole, float R_oct, int32_
  * 2.2, leaves the order and grouping of the work free; this chooses it by
  * measurement, not by rule).  Coordinate descent over: the sweep of pyramid
  * pieces (layers, shells), the place of the table (LDS, caches), the waves
- * per work-group (4, 8, 12, 16), R_oct (8, 10, 12, 15, 20) and R_whole (3, 4,
- * 6, 8); every candidate is one
+ * per work-group (4, 8, 12, 16), for passes = 2 with layer pyramids the
+ * layer adjoint's adj_rate (1, 2) and adj_waves (2, 4, 8, 12), R_oct (8, 10,
+ * 12, 15, 20) and R_whole (3, 4, 6, 8); every candidate is one
  * warm-up call and the median of three calls timed with HIP events on
  * `stream`.  passes = 1 times the forward; passes = 2 the forward with
  * ASORA_STORE followed by the adjoint (with dL/dgamma = 1).  The best
@@ -272,10 +280,11 @@ asora_status asora_set_tuning(asora_ctx *ctx, float R_whole, float R_oct, int32_
  *   n_H .. R_max  as for asora_raytrace (device buffers; only read).
  *   passes        1 or 2.
  *   best_ms       host, may be NULL: time of the best candidate (ms).
- *   report        host array of max_report x 6 floats (may be NULL when
+ *   report        host array of max_report x 8 floats (may be NULL when
  *                 max_report = 0): per timed candidate R_whole, R_oct,
- *                 max_waves, pyramid_sweep, table_place, ms; *n_report (may be NULL)
- *                 receives the number of rows written.
+ *                 max_waves, pyramid_sweep, table_place, adj_waves, adj_rate,
+ *                 ms; *n_report (may be NULL) receives the number of rows
+ *                 written.
  * Allocates scratch outputs of the size of the grid for its duration and
  * waits for `stream`.  ASORA_ESTATE while a recorded graph of the context
  * exists.
@@ -320,7 +329,8 @@ asora_status asora_graph_free(asora_graph *graph);
  * NULL).
  */
 asora_status asora_get_tuning(const asora_ctx *ctx, float *R_whole, float *R_oct,
-                              int32_t *max_waves, int32_t *pyramid_sweep, int32_t *table_place);
+                              int32_t *max_waves, int32_t *pyramid_sweep, int32_t *table_place,
+                              int32_t *adj_waves, int32_t *adj_rate);
 
 /*
  * asora_profile -- durations (ms) of the most recent call made with

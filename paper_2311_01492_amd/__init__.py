@@ -26,6 +26,8 @@ __all__ = ["Asora", "AsoraError", "raytrace", "table_blackbody", "table_grey", "
 SIGMA0 = 6.3e-18          # HI cross-section at 13.6 eV, cm^2
 ACCUMULATE, PLAIN, PROFILE, STORE = 0x1, 0x2, 0x4, 0x8
 HALFPATH_SCALAR = 0x1
+# scheduling parameters, in the order asora_get_tuning returns them
+TUNING_KEYS = ("R_whole", "R_oct", "max_waves", "pyramid_sweep", "table_place", "adj_waves", "adj_rate")
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libasora.so")
@@ -57,10 +59,10 @@ _lib.asora_profile.argtypes = [_p, ctypes.POINTER(_c_d), ctypes.POINTER(_c_d)]
 _lib.asora_profile_read.restype = _c_int
 _lib.asora_profile_read.argtypes = [_p, _c_int, ctypes.POINTER(_c_int), _p, _p]
 _lib.asora_set_tuning.restype = _c_int
-_lib.asora_set_tuning.argtypes = [_p, _c_f, _c_f, _c_int, _c_int, _c_int]
+_lib.asora_set_tuning.argtypes = [_p, _c_f, _c_f, _c_int, _c_int, _c_int, _c_int, _c_int]
 _lib.asora_get_tuning.restype = _c_int
-_lib.asora_get_tuning.argtypes = [_p, ctypes.POINTER(_c_f), ctypes.POINTER(_c_f), ctypes.POINTER(_c_int),
-                                  ctypes.POINTER(_c_int), ctypes.POINTER(_c_int)]
+_lib.asora_get_tuning.argtypes = [_p, ctypes.POINTER(_c_f), ctypes.POINTER(_c_f)] + \
+    [ctypes.POINTER(_c_int)] * 5
 _lib.asora_store_info.restype = _c_int
 _lib.asora_store_info.argtypes = [_p, ctypes.POINTER(_c_int), ctypes.POINTER(ctypes.c_uint64),
                                   ctypes.POINTER(ctypes.c_uint64)]
@@ -246,13 +248,13 @@ class Asora:
         asora_autotune) and keep the fastest.  Returns (best_ms, report) with one
         dict per timed candidate."""
         ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
-        rep = np.zeros((64, 6), np.float32)
+        rep = np.zeros((64, 8), np.float32)
         best, nrep = _c_f(), _c_int()
         _raise(_lib.asora_autotune(self._h, _dptr(n_H), _dptr(x_HI), n, _dptr(ijk), _dptr(Q), _dptr(R),
                                    R_max, int(passes), 1 if retune else 0, _stream_ptr(stream),
                                    ctypes.byref(best), 64, ctypes.byref(nrep),
                                    rep.ctypes.data_as(_p)), self._h)
-        keys = ("R_whole", "R_oct", "max_waves", "pyramid_sweep", "table_place", "ms")
+        keys = TUNING_KEYS + ("ms",)
         return best.value, [dict(zip(keys, map(float, r))) for r in rep[:nrep.value]]
 
     def record_step(self, n_H, x_HI, ijk, Q, R, gamma, dL_dgamma=None, grads=None, R_max=None,
@@ -287,18 +289,23 @@ class Asora:
         """Largest device memory for kept column records (0: half the free memory)."""
         _raise(_lib.asora_set_store_budget(self._h, int(nbytes)), self._h)
 
-    def set_tuning(self, R_whole=0.0, R_oct=0.0, max_waves=0, pyramid_sweep=0, table_place=0):
+    def set_tuning(self, R_whole=0.0, R_oct=0.0, max_waves=0, pyramid_sweep=0, table_place=0,
+                   adj_waves=0, adj_rate=0):
         """Scheduling parameters (0 keeps a value): pyramid_sweep 2 = shells,
-        3 = layers; table_place 1 = LDS, 2 = through the caches."""
+        3 = layers; table_place 1 = LDS, 2 = through the caches; adj_waves
+        waves per work-group of the layer adjoint; adj_rate 1 = its rate terms
+        all gathered into full waves, 2 = dense chunks' in the reverse pass."""
         _raise(_lib.asora_set_tuning(self._h, float(R_whole), float(R_oct), int(max_waves),
-                                     int(pyramid_sweep), int(table_place)), self._h)
+                                     int(pyramid_sweep), int(table_place), int(adj_waves),
+                                     int(adj_rate)), self._h)
 
     def get_tuning(self):
-        """(R_whole, R_oct, max_waves, pyramid_sweep, table_place)."""
-        a, b, w, k, t = _c_f(), _c_f(), _c_int(), _c_int(), _c_int()
-        _raise(_lib.asora_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(w),
-                                     ctypes.byref(k), ctypes.byref(t)), self._h)
-        return a.value, b.value, w.value, k.value, t.value
+        """The scheduling parameters, in the order of TUNING_KEYS."""
+        a, b = _c_f(), _c_f()
+        ints = [_c_int() for _ in range(5)]
+        _raise(_lib.asora_get_tuning(self._h, ctypes.byref(a), ctypes.byref(b),
+                                     *[ctypes.byref(x) for x in ints]), self._h)
+        return (a.value, b.value) + tuple(x.value for x in ints)
 
     def check(self, stream=None):
         """Wait for the stream; raise if a kernel flagged a source."""

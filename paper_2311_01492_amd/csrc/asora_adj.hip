@@ -213,21 +213,30 @@ __global__ __launch_bounds__(512) void adj_wave(AdjArgs A)
 }
 
 // ---- layer pieces --------------------------------------------------------
-// One wave per pyramid, in two passes.
+// One wave per pyramid, in three passes.
 //  (F) Unless the forward kept the pyramid's column record: the columns layer
 //      by layer, in place in the LDS buffer as in the forward kernel, every
 //      cell's layer-buffer entry written to the record in the wave's scratch
 //      together with each chunk's mask of cells with a rate.
+//  (G) The cells with a rate (SPLIT: only those in sparse chunks, fewer than
+//      kDenseChunk of them), found from the chunk masks and compacted into an
+//      LDS queue, 64 at a time with every lane busy: their entry columns from the record,
+//      the FP64 rate derivatives, the rate's in-cell term of dL/dn_HI, its
+//      share of dL/dQ, and its entry-column term g_in, kept per cell in the
+//      wave's scratch.  With SPLIT, dense chunks leave theirs to (R), which
+//      has the interpolation at hand; without, the kernel holds fewer
+//      registers (more waves per SIMD), which pays when few cells have a rate.
 //  (R) Layers from the outermost inward, each layer's rectangle in chunks
 //      from the first to the last: every cell takes and clears its slot in
 //      the LDS adjoint buffer (the adjoint of its exit column, pushed by its
-//      consumers), adds its rate's terms if it has one (FP64 derivatives),
-//      adds its dL/dn_HI with one atomic and pushes the adjoint of its entry
-//      column through the interpolation weights, read from the record's
-//      entries of layer m - 1, to its neighbours' slots with LDS atomics.  A
-//      neighbour slot precedes the pushing cell in (u, v) order, so it was
-//      already taken in this layer.  Chunks with no rate and all slots zero
-//      (cells no rate depends on) skip the arithmetic and the record.
+//      consumers), adds its g_in if it has a rate (from (G), or evaluated
+//      here in a dense chunk), adds alpha ds times the sum (and, in a dense
+//      chunk, the rate's in-cell term) to dL/dn_HI with one atomic and pushes
+//      it through the interpolation weights, read
+//      from the record's entries of layer m - 1, to its neighbours' slots
+//      with LDS atomics.  A neighbour slot precedes the pushing cell in (u, v)
+//      order, so it was already taken in this layer.  Chunks with no rate and
+//      all slots zero (cells no rate depends on) skip the arithmetic.
 // The table is read from global memory (only cells with a rate use it),
 // which leaves the LDS to the per-wave buffers.
 __device__ __forceinline__ void wave_sync_global()
@@ -239,9 +248,33 @@ __device__ __forceinline__ void wave_sync_global()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-template <bool KEPT>
-__device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *buf, char *scratch, int src,
-                                    int p, int lane)
+constexpr int kAdjQueue = 128;   // (G) queue entries per wave
+
+// The rate masks of chunks c0 .. c0 + 63 of a layer (first chunk at choff),
+// one per lane, held in registers.
+__device__ __forceinline__ uint64_t load_masks(const LayerRecord &rec, long choff, int c0, int nch, int lane)
+{
+    uint32_t lo = 0, hi = 0;
+    if (c0 + lane < nch) {
+        const uint64_t mk = rec.lit[choff + c0 + lane];
+        lo = (uint32_t)mk;
+        hi = (uint32_t)(mk >> 32);
+    }
+    // without this the compiler turns every readlane of the masks back into
+    // a global load per chunk
+    asm volatile("" : "+v"(lo), "+v"(hi));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t mask_of_chunk(uint64_t masks, int c)
+{
+    return ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(masks >> 32), c & 63) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)masks, c & 63);
+}
+
+template <bool KEPT, bool SPLIT>
+__device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *buf, int *qk, int *qm,
+                                    char *scratch, int src, int p, int lane)
 {
     const int N = A.N;
     const int si = A.ijk[3 * src], sj = A.ijk[3 * src + 1], sk = A.ijk[3 * src + 2];
@@ -271,13 +304,15 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
     const int S = A.lay_S;
     const LayerRecord rec = layer_record_at(
         KEPT ? (char *)A.kept + ((size_t)src * 24 + p) * A.rec_piece_bytes : scratch, A.rec_cap);
+    double *gin = (double *)(scratch + A.rec_piece_bytes);   // g_in by record cell
     const int Mx = min(isqrt_floor(Rsq), L.ext_d);
+    constexpr int dense_at = SPLIT ? kDenseChunk : 65;   // popcount of a dense chunk
 
     // ---- (F)
-    long off = 0, choff = 0;   // ends: cells and chunks of the record
     if (!KEPT) {
         for (int k = lane; k < S * S; k += 64) buf[k] = 0.0;   // finite everywhere it is read
         wave_sync();
+        long off = 0, choff = 0;
         for (int m = 1; m <= Mx; ++m) {
             const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
             const double inv_m = rcp_f64((double)m);
@@ -310,71 +345,130 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
             off += r.total;
             choff += nch;
         }
-    } else {
-        for (int m = 1; m <= Mx; ++m) {
-            const int t = layer_rect(L.ext_u, L.ext_v, Rsq, m).total;
-            off += t;
-            choff += (t + 63) / 64;
-        }
+        wave_sync_global();
     }
-    for (int k = lane; k < S * S; k += 64) buf[k] = 0.0;   // the adjoint slots
-    wave_sync_global();
 
-    // ---- (R)
+    // ---- (G)
     double nb_src = 0.0, qb = 0.0;
-    for (int m = Mx; m >= 1; --m) {
-        const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
-        const int nch = (r.total + 63) / 64;
-        off -= r.total;    // first cell of layer m in the record
-        choff -= nch;      // its first chunk
-        // entries of layer m - 1 (its rectangle precedes layer m's)
-        const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m >= 2 ? m - 1 : 1);
-        const int wvp = rp.wv;
-        const double *Hprev = rec.h + (m >= 2 ? off - rp.total : 0);
-        RectWalk w;
-        w.init(r, lane);
-        uint64_t masks = 0;   // the rate masks of chunks c0 .. c0 + 63, one per lane
-        for (int c = 0; c < nch; ++c, w.up()) {
-            if ((c & 63) == 0) {
-                uint32_t lo = 0, hi = 0;
-                if (c + lane < nch) {
-                    const uint64_t mk = rec.lit[choff + c + lane];
-                    lo = (uint32_t)mk;
-                    hi = (uint32_t)(mk >> 32);
+    {
+        int head = 0, tail = 0;
+        auto batch = [&](int count) {
+            if (lane < count) {
+                const int q = (head + lane) & (kAdjQueue - 1);
+                const int k = qk[q], mg = qm[q];
+                const int m = mg >> 16, g = mg & 0xffff;
+                const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
+                RectWalk w;
+                w.init(r, g);
+                const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m >= 2 ? m - 1 : 1);
+                const double *Hprev = rec.h + (m >= 2 ? k - g - rp.total : 0);
+                LayerInterp I;
+                layer_interp(L, X, m, w.u, w.v, Hprev, rp.wv, I);
+                const double gb = gbar[I.cp];
+                double gi = 0.0;
+                if (gb != 0.0) {
+                    double ne, gG;
+                    layer_rate_adjoint(T, A.m64, A.tp, X, coef, I, X.nHI[I.cp], gb, &gi, &ne, &gG);
+                    if (ne != 0.0) unsafeAtomicAdd(&nbar[I.cp], ne);
+                    qb += gG;
                 }
-                // keep the 64 masks in registers: without this the compiler
-                // turns every readlane below back into a global load per chunk
-                asm volatile("" : "+v"(lo), "+v"(hi));
-                masks = ((uint64_t)hi << 32) | lo;
+                gin[k] = gi;
             }
-            const int g = c * 64 + lane;
-            const int u = w.u, v = w.v;
-            const bool act = g < r.total && mul24(u, u) + mul24(v, v) <= r.rem;
-            const uint64_t litmask =
-                ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(masks >> 32), c & 63) << 32) |
-                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)masks, c & 63);
-            const bool lit = (litmask >> lane) & 1;
-            double Tout = 0.0;
-            if (act) {
-                Tout = buf[mul24(u, S) + v];
-                buf[mul24(u, S) + v] = 0.0;
-            }
-            wave_sync();
-            if (__ballot(Tout != 0.0) | litmask) {
-                if (Tout != 0.0 || lit) {
-                    LayerRev lr;
-                    layer_cell_reverse(L, X, T, A.m64, A.tp, coef, m, u, v, Hprev, wvp, lit, gbar, Tout, lr);
-                    if (m >= 2) {
-#pragma unroll
-                        for (int n = 0; n < 4; ++n)
-                            if (lr.Mbar[n] != 0.0)
-                                atomicAdd(&buf[mul24(u - (n & 1), S) + (v - (n >> 1))], lr.Mbar[n]);
+        };
+        long off = 0, choff = 0;
+        for (int m = 1; m <= Mx; ++m) {
+            const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
+            const int nch = (r.total + 63) / 64;
+            uint64_t masks = 0;
+            for (int c = 0; c < nch; ++c) {
+                if ((c & 63) == 0) masks = load_masks(rec, choff, c, nch, lane);
+                const uint64_t litmask = mask_of_chunk(masks, c);
+                if (litmask && __popcll(litmask) < dense_at) {
+                    if ((litmask >> lane) & 1) {
+                        const int q = (tail + (int)__builtin_amdgcn_mbcnt_hi(
+                                                  (uint32_t)(litmask >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)litmask, 0u))) &
+                                      (kAdjQueue - 1);
+                        qk[q] = (int)(off + c * 64 + lane);
+                        qm[q] = (m << 16) | (c * 64 + lane);
                     }
-                    if (lr.nbar != 0.0) unsafeAtomicAdd(&nbar[lr.cp], lr.nbar);
-                    nb_src += lr.nbar_src;
-                    qb += lr.qb;
+                    tail += __popcll(litmask);
+                    if (tail - head >= 64) {
+                        wave_sync();
+                        batch(64);
+                        head += 64;
+                        wave_sync();
+                    }
+                }
+            }
+            off += r.total;
+            choff += nch;
+        }
+        if (tail > head) {
+            wave_sync();
+            batch(tail - head);
+            wave_sync();
+        }
+        for (int k = lane; k < S * S; k += 64) buf[k] = 0.0;   // the adjoint slots
+        wave_sync_global();
+
+        // ---- (R)
+        for (int m = Mx; m >= 1; --m) {
+            const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
+            const int nch = (r.total + 63) / 64;
+            off -= r.total;    // first cell of layer m in the record
+            choff -= nch;      // its first chunk
+            // entries of layer m - 1 (its rectangle precedes layer m's)
+            const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m >= 2 ? m - 1 : 1);
+            const int wvp = rp.wv;
+            const double *Hprev = rec.h + (m >= 2 ? off - rp.total : 0);
+            RectWalk w;
+            w.init(r, lane);
+            uint64_t masks = 0;
+            for (int c = 0; c < nch; ++c, w.up()) {
+                if ((c & 63) == 0) masks = load_masks(rec, choff, c, nch, lane);
+                const int g = c * 64 + lane;
+                const int u = w.u, v = w.v;
+                const bool act = g < r.total && mul24(u, u) + mul24(v, v) <= r.rem;
+                const uint64_t litmask = mask_of_chunk(masks, c);
+                const bool lit = (litmask >> lane) & 1;
+                double Tin = 0.0;
+                if (act) {
+                    Tin = buf[mul24(u, S) + v];
+                    buf[mul24(u, S) + v] = 0.0;
                 }
                 wave_sync();
+                if (__ballot(Tin != 0.0) | litmask) {
+                    const bool dense = __popcll(litmask) >= dense_at;
+                    if (lit && !dense) Tin += gin[off + g];
+                    if (Tin != 0.0 || (lit && dense)) {
+                        LayerInterp I;
+                        layer_interp(L, X, m, u, v, Hprev, wvp, I);
+                        double extra = 0.0;
+                        if (lit && dense) {
+                            const double gb = gbar[I.cp];
+                            if (gb != 0.0) {
+                                double gi, gG;
+                                layer_rate_adjoint(T, A.m64, A.tp, X, coef, I, X.nHI[I.cp], gb, &gi, &extra,
+                                                   &gG);
+                                Tin += gi;
+                                qb += gG;
+                            }
+                        }
+                        LayerRev lr;
+                        layer_cell_reverse(X, m, I, Tin, lr);
+                        if (m >= 2) {
+#pragma unroll
+                            for (int n = 0; n < 4; ++n)
+                                if (lr.Mbar[n] != 0.0)
+                                    atomicAdd(&buf[mul24(u - (n & 1), S) + (v - (n >> 1))], lr.Mbar[n]);
+                        }
+                        const double nb = lr.nbar + extra;
+                        if (nb != 0.0) unsafeAtomicAdd(&nbar[lr.cp], nb);
+                        nb_src += lr.nbar_src;
+                    }
+                    wave_sync();
+                }
             }
         }
     }
@@ -395,7 +489,7 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
     }
 }
 
-template <bool KEPT>
+template <bool KEPT, bool SPLIT>
 __global__ __launch_bounds__(kAdjLayerThreads) void adj_layer(AdjArgs A)
 {
     extern __shared__ __align__(16) char smem[];
@@ -404,8 +498,11 @@ __global__ __launch_bounds__(kAdjLayerThreads) void adj_layer(AdjArgs A)
     const TabNode *T = A.tab;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
-    // per wave: one S x S buffer, the columns in (F) and the adjoints in (R)
+    // per wave: one S x S buffer, the columns in (F) and the adjoints in (R),
+    // then the (G) queue
     double *buf = (double *)(smem + (size_t)wave * A.region_bytes);
+    int *qk = (int *)(buf + (size_t)A.lay_S * A.lay_S);
+    int *qm = qk + kAdjQueue;
     char *scratch = (char *)(A.store + (size_t)(blockIdx.x * waves + wave) * A.store_stride);
     const int base = A.seg[TYPE];
     const int nitems = (A.seg[TYPE + 1] - base) * npieces;
@@ -415,7 +512,7 @@ __global__ __launch_bounds__(kAdjLayerThreads) void adj_layer(AdjArgs A)
         const int item = next_item(A.counter, nitems, home, chunk, lane);
         if (item >= nitems) break;
         const int src = A.order[base + item / npieces];
-        adjoint_layer_piece<KEPT>(A, T, buf, scratch, src, item % npieces, lane);
+        adjoint_layer_piece<KEPT, SPLIT>(A, T, buf, qk, qm, scratch, src, item % npieces, lane);
     }
 }
 
@@ -529,8 +626,9 @@ hipError_t adj_configure(size_t max_lds)
     const int dyn = (int)max_lds - 64;
     for (int t = 0; t < 3; ++t)
         (void)hipFuncSetAttribute(adj_fn(t), hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-    (void)hipFuncSetAttribute((const void *)adj_layer<false>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-    (void)hipFuncSetAttribute((const void *)adj_layer<true>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    for (const void *f : {(const void *)adj_layer<false, false>, (const void *)adj_layer<false, true>,
+                          (const void *)adj_layer<true, false>, (const void *)adj_layer<true, true>})
+        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipGetLastError();
     return hipSuccess;
 }
@@ -605,15 +703,16 @@ hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L)
 }
 
 // Per-wave LDS of the layer adjoint: the S x S buffer (columns, then
-// adjoints).
+// adjoints) and the queue of cells with a rate.
 size_t adj_layer_region_bytes(int S)
 {
-    return ((size_t)S * S * sizeof(double) + 15) & ~(size_t)15;
+    return ((size_t)S * S * sizeof(double) + 2 * kAdjQueue * sizeof(int) + 15) & ~(size_t)15;
 }
 
-hipError_t adj_layer_occupancy(bool kept, int waves, size_t lds, int *blocks_per_cu)
+hipError_t adj_layer_occupancy(bool kept, bool split, int waves, size_t lds, int *blocks_per_cu)
 {
-    const void *f = kept ? (const void *)adj_layer<true> : (const void *)adj_layer<false>;
+    const void *f = kept ? (split ? (const void *)adj_layer<true, true> : (const void *)adj_layer<true, false>)
+                         : (split ? (const void *)adj_layer<false, true> : (const void *)adj_layer<false, false>);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, waves * 64, lds);
 }
 
@@ -624,8 +723,11 @@ hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int Mcap, int S)
     A.lay_S = S;
     A.region_bytes = (int)adj_layer_region_bytes(S);
     const size_t lds = (size_t)L.waves * A.region_bytes;
-    if (A.kept) hipLaunchKernelGGL(adj_layer<true>, dim3(L.grid), dim3(64 * L.waves), lds, st, A);
-    else hipLaunchKernelGGL(adj_layer<false>, dim3(L.grid), dim3(64 * L.waves), lds, st, A);
+    const dim3 grid(L.grid), block(64 * L.waves);
+    if (A.kept && L.split) hipLaunchKernelGGL((adj_layer<true, true>), grid, block, lds, st, A);
+    else if (A.kept) hipLaunchKernelGGL((adj_layer<true, false>), grid, block, lds, st, A);
+    else if (L.split) hipLaunchKernelGGL((adj_layer<false, true>), grid, block, lds, st, A);
+    else hipLaunchKernelGGL((adj_layer<false, false>), grid, block, lds, st, A);
     return hipGetLastError();
 }
 

@@ -62,6 +62,8 @@ struct asora_ctx {
     std::map<PlanKey, Plan> plans;
     int big_kind;           // piece kind of the forward above R_oct: 2 shell pyramids, 3 layer pyramids
     int tab_lds;            // layer forward: table in LDS (1) or through the caches (0)
+    int adj_waves;          // layer adjoint: waves per work-group
+    int adj_split;          // layer adjoint: rate terms of dense chunks in the reverse pass (1) or all gathered (0)
     double *d_nhi_T;        // [k][i][j] copies for the layer pieces (allocated on first use)
     double *d_gacc_T;
     double *d_gbar_T;       // adjoint: dL/dGamma and dL/dn_HI in the [k][i][j] layout
@@ -189,6 +191,8 @@ extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, d
     c->max_waves = 16;
     c->big_kind = 3;
     c->tab_lds = 1;
+    c->adj_waves = 4;
+    c->adj_split = 1;
 
     // table in the kernels' form
     std::vector<TabNode> nodes(n_tab);
@@ -621,17 +625,18 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
 }
 
 extern "C" asora_status asora_set_tuning(asora_ctx *c, float R_whole, float R_oct, int32_t max_waves,
-                                         int32_t pyramid_sweep, int32_t table_place)
+                                         int32_t pyramid_sweep, int32_t table_place, int32_t adj_waves,
+                                         int32_t adj_rate)
 {
     if (!ctx_ok(c)) return ASORA_ESTATE;
     const float w = R_whole > 0 ? R_whole : c->R_whole;
     const float o = R_oct > 0 ? R_oct : c->R_oct;
     if (!(o >= w) || !std::isfinite(w) || !std::isfinite(o) || max_waves > 16 ||
         !(pyramid_sweep == 0 || pyramid_sweep == 2 || pyramid_sweep == 3) || table_place < 0 ||
-        table_place > 2)
+        table_place > 2 || adj_waves > kAdjLayerWaves || adj_rate < 0 || adj_rate > 2)
         return fail(c, ASORA_EINVAL,
                     "asora_set_tuning: need 0 < R_whole <= R_oct, max_waves <= 16, pyramid_sweep 0/2/3, "
-                    "table_place 0/1/2");
+                    "table_place 0/1/2, adj_waves <= %d, adj_rate 0/1/2", kAdjLayerWaves);
     if (c->live_graphs) return pinned(c, "the tuning");
     c->R_whole = w;
     c->R_oct = o;
@@ -639,6 +644,8 @@ extern "C" asora_status asora_set_tuning(asora_ctx *c, float R_whole, float R_oc
     if (c->min_waves > c->max_waves) c->min_waves = c->max_waves;
     if (pyramid_sweep) c->big_kind = pyramid_sweep;
     if (table_place) c->tab_lds = table_place == 1 ? 1 : 0;
+    if (adj_waves > 0) c->adj_waves = adj_waves;
+    if (adj_rate) c->adj_split = adj_rate == 2 ? 1 : 0;
     c->plans.clear();
     c->adj_plans.clear();
     c->keep_valid = false;   // record layouts follow the plans
@@ -647,7 +654,7 @@ extern "C" asora_status asora_set_tuning(asora_ctx *c, float R_whole, float R_oc
 
 extern "C" asora_status asora_get_tuning(const asora_ctx *c, float *R_whole, float *R_oct,
                                          int32_t *max_waves, int32_t *pyramid_sweep,
-                                         int32_t *table_place)
+                                         int32_t *table_place, int32_t *adj_waves, int32_t *adj_rate)
 {
     if (!ctx_ok(c)) return ASORA_ESTATE;
     if (R_whole) *R_whole = c->R_whole;
@@ -655,6 +662,8 @@ extern "C" asora_status asora_get_tuning(const asora_ctx *c, float *R_whole, flo
     if (max_waves) *max_waves = c->max_waves;
     if (pyramid_sweep) *pyramid_sweep = c->big_kind;
     if (table_place) *table_place = c->tab_lds ? 1 : 2;
+    if (adj_waves) *adj_waves = c->adj_waves;
+    if (adj_rate) *adj_rate = c->adj_split ? 2 : 1;
     return ASORA_OK;
 }
 
@@ -731,8 +740,9 @@ static asora_status get_adj_plan(asora_ctx *c, int type, float R_cap, Plan *out)
     return ASORA_OK;
 }
 
-// Adjoint layer pieces: one layer buffer per wave in LDS (columns, then
-// adjoints); a pyramid column record in the wave's scratch.
+// Adjoint layer pieces: one layer buffer and a small queue per wave in LDS; a
+// pyramid column record and the rate's entry-column terms in the wave's
+// scratch.
 static asora_status get_adj_layer_plan(asora_ctx *c, float R_cap, bool kept, Plan *out)
 {
     const int Rsq = (int)std::floor((double)R_cap * (double)R_cap);
@@ -751,14 +761,13 @@ static asora_status get_adj_layer_plan(asora_ctx *c, float R_cap, bool kept, Pla
         return fail(c, ASORA_ENOSYS,
                     "asora_raytrace_backward: R_max=%.1f needs %zu bytes of LDS per wave (limit %zu)",
                     R_cap, region, c->max_lds);
-    const int cap = c->max_waves < kAdjLayerWaves ? c->max_waves : kAdjLayerWaves;
-    P.waves = (int)(fit < cap ? fit : cap);
+    P.waves = (int)(fit < c->adj_waves ? fit : c->adj_waves);
     P.lds = (size_t)P.waves * region;
     int bpc = 0;
-    HIPCHK(c, adj_layer_occupancy(kept, P.waves, P.lds, &bpc));
+    HIPCHK(c, adj_layer_occupancy(kept, c->adj_split != 0, P.waves, P.lds, &bpc));
     P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
     P.piece_cells = P.rec_cap;
-    P.scratch = (long)(P.rec_bytes / sizeof(double));
+    P.scratch = (long)(P.rec_bytes / sizeof(double)) + P.rec_cap;   // record, then g_in per cell
     c->adj_plans[key] = P;
     *out = P;
     return ASORA_OK;
@@ -865,6 +874,7 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
         L.kept = kept ? c->d_keep : nullptr;
         L.rec_piece_bytes = layers ? plans[3].rec_bytes : 0;
         L.rec_cap = layers ? plans[3].rec_cap : 0;
+        L.split = c->adj_split != 0;
         for (int t = tmax; t >= 0; --t) {
             if (t == 2 && layers) continue;
             L.type = t;
@@ -993,8 +1003,10 @@ extern "C" asora_status asora_graph_free(asora_graph *g)
 // ---------------------------------------------------------------------------
 // Autotuner: times candidate scheduling parameters on the caller's inputs and
 // keeps the fastest.  Coordinate descent over the large-source sweep (layers,
-// shells), the waves per work-group and the whole / octant radius thresholds;
+// shells), the table's place, the waves per work-group, the layer adjoint's
+// rate split and work-group size, and the whole / octant radius thresholds;
 // each candidate is one warm-up call and the median of three timed calls.
+constexpr int kTuneRow = 8;   // floats per report row
 extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const float *x_HI,
                                        int64_t n_src, const int32_t *src_ijk, const double *src_Q,
                                        const float *src_R, float R_max, int32_t passes,
@@ -1016,8 +1028,8 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
     auto hit = c->tuned.find(key);
     if (hit != c->tuned.end() && !(flags & ASORA_TUNE_RETUNE)) {
         const std::vector<float> &v = hit->second;
-        st = asora_set_tuning(c, v[0], v[1], (int)v[2], (int)v[3], (int)v[4]);
-        if (!st && best_ms) *best_ms = v[5];
+        st = asora_set_tuning(c, v[0], v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5], (int)v[6]);
+        if (!st && best_ms) *best_ms = v[7];
         return st;
     }
     HIPCHK(c, hipSetDevice(c->device));
@@ -1060,68 +1072,80 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
                                        sf, s);
     };
     int nrep = 0;
-    auto trial = [&](float w, float o, int waves, int sweep, int place, float *ms) -> asora_status {
-        asora_status r = asora_set_tuning(c, w, o, waves, sweep, place);
+    struct Cand {
+        float w, o;
+        int waves, sweep, place, aw, ar;
+        bool operator==(const Cand &x) const
+        {
+            return w == x.w && o == x.o && waves == x.waves && sweep == x.sweep && place == x.place &&
+                   aw == x.aw && ar == x.ar;
+        }
+    };
+    auto apply = [&](const Cand &k) {
+        return asora_set_tuning(c, k.w, k.o, k.waves, k.sweep, k.place, k.aw, k.ar);
+    };
+    auto trial = [&](const Cand &k, float *ms) -> asora_status {
+        asora_status r = apply(k);
         if (r) return r;
         if ((r = one())) return r;   // plans, buffers, warm caches
         float t[3];
-        for (int k = 0; k < 3; ++k) {
+        for (int i = 0; i < 3; ++i) {
             HIPCHK(c, hipEventRecord(e0, s));
             if ((r = one())) return r;
             HIPCHK(c, hipEventRecord(e1, s));
             HIPCHK(c, hipEventSynchronize(e1));
-            HIPCHK(c, hipEventElapsedTime(&t[k], e0, e1));
+            HIPCHK(c, hipEventElapsedTime(&t[i], e0, e1));
         }
         std::sort(t, t + 3);
         *ms = t[1];
         if (nrep < max_report) {
-            float *row = report + 6 * nrep;
-            row[0] = w;
-            row[1] = o;
-            row[2] = (float)waves;
-            row[3] = (float)sweep;
-            row[4] = (float)place;
-            row[5] = *ms;
+            float *row = report + kTuneRow * nrep;
+            const float v[kTuneRow] = {k.w, k.o, (float)k.waves, (float)k.sweep, (float)k.place,
+                                       (float)k.aw, (float)k.ar, *ms};
+            std::copy(v, v + kTuneRow, row);
         }
         ++nrep;
         return ASORA_OK;
     };
-    float bw = c->R_whole, bo = c->R_oct, best = 0.f;
-    int bwv = c->max_waves, bsw = c->big_kind, bpl = c->tab_lds ? 1 : 2;
-    st = trial(bw, bo, bwv, bsw, bpl, &best);
-    auto consider = [&](float w, float o, int waves, int sweep, int place) -> asora_status {
-        if (!(o >= w)) return ASORA_OK;
-        if (w == bw && o == bo && waves == bwv && sweep == bsw && place == bpl) return ASORA_OK;
+    Cand b{c->R_whole, c->R_oct, c->max_waves, c->big_kind, c->tab_lds ? 1 : 2, c->adj_waves,
+           c->adj_split ? 2 : 1};
+    float best = 0.f;
+    st = trial(b, &best);
+    auto consider = [&](Cand k) -> asora_status {
+        if (!(k.o >= k.w) || k == b) return ASORA_OK;
         float ms = 0.f;
-        asora_status r = trial(w, o, waves, sweep, place, &ms);
+        asora_status r = trial(k, &ms);
         if (r) return r;
         if (ms < best) {
             best = ms;
-            bw = w;
-            bo = o;
-            bwv = waves;
-            bsw = sweep;
-            bpl = place;
+            b = k;
         }
         return ASORA_OK;
     };
-    if (!st && R_max > bo)
+    Cand k;
+    if (!st && R_max > b.o)
         for (int sw : {3, 2})
-            if (!st) st = consider(bw, bo, bwv, sw, bpl);
-    if (R_max > bo && bsw == 3)
+            if (!st) (k = b).sweep = sw, st = consider(k);
+    if (R_max > b.o && b.sweep == 3)
         for (int pl : {1, 2})
-            if (!st) st = consider(bw, bo, bwv, bsw, pl);
+            if (!st) (k = b).place = pl, st = consider(k);
     for (int wv : {4, 8, 12, 16})
-        if (!st) st = consider(bw, bo, wv, bsw, bpl);
+        if (!st) (k = b).waves = wv, st = consider(k);
+    if (passes == 2 && R_max > b.o && b.sweep == 3) {   // the layer adjoint
+        for (int ar : {1, 2})
+            if (!st) (k = b).ar = ar, st = consider(k);
+        for (int aw : {2, 4, 8, 12})
+            if (!st) (k = b).aw = aw, st = consider(k);
+    }
     if (R_max > 8.f)
         for (float o : {8.f, 10.f, 12.f, 15.f, 20.f})
-            if (!st) st = consider(bw, o, bwv, bsw, bpl);
+            if (!st) (k = b).o = o, st = consider(k);
     for (float w : {3.f, 4.f, 6.f, 8.f})
-        if (!st) st = consider(w, bo, bwv, bsw, bpl);
+        if (!st) (k = b).w = w, st = consider(k);
     cleanup();
     if (st) return st;
-    if ((st = asora_set_tuning(c, bw, bo, bwv, bsw, bpl))) return st;
-    c->tuned[key] = {bw, bo, (float)bwv, (float)bsw, (float)bpl, best};
+    if ((st = apply(b))) return st;
+    c->tuned[key] = {b.w, b.o, (float)b.waves, (float)b.sweep, (float)b.place, (float)b.aw, (float)b.ar, best};
     if (best_ms) *best_ms = best;
     if (n_report) *n_report = nrep < max_report ? nrep : max_report;
     return ASORA_OK;

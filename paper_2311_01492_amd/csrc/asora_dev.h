@@ -1162,87 +1162,122 @@ __host__ __device__ __forceinline__ void layer_cell_adjoint(const LayerPiece &L,
     }
 }
 
-// Reverse-mode update of layer cell (u, v) of layer m.  T is the adjoint of
-// the cell's exit column (what its consumers pushed); lit says that the cell
-// carries a rate (owned, entry optical depth inside the table, as the forward
-// found).  Since N_out = N_in + dN, T flows into both N_in and dN; a lit cell
-// adds its rate's terms: with Gamma = k D(tau_in, dtau), k = -coef / r2,
-// g_in = gbar dGamma/dN_in and g_dN = gbar dGamma/d(dN) from the FP64 rate
-// derivatives (dL/dGamma gbar read only for lit cells).  Hprev holds the
-// layer-buffer entries (layer_entry) of layer m - 1 as its rectangle (row
-// width wvp): neighbour (u', v') is Hprev[u' * wvp + v'].  With
-// N_in = sum s g / sum s f (f, g as in layer_entry),
+// The entry column of layer cell (u, v) of layer m recomputed from the
+// layer-buffer entries (layer_entry) of layer m - 1, kept as Hprev[u' * wvp +
+// v'] (its rectangle), with what the adjoint needs: the geometric weights s,
+// the weight factors f, which neighbours are optically thick, W = sum s f
+// (as 1/W) and N_in = sum s g / W.  For m = 1 the entry column is the
+// source's.
+// A chunk of 64 layer cells with at least this many cells with a rate has
+// their rate terms evaluated in the reverse pass itself (the lanes are mostly
+// busy anyway); sparser chunks have them evaluated beforehand in batches of
+// 64 gathered from many chunks.
+constexpr int kDenseChunk = 32;
+
+struct LayerInterp {
+    uint32_t cp;
+    int r2;
+    double ds, Nin, iW;
+    double sw[4], f[4];
+    bool thick[4];
+};
+
+__host__ __device__ __forceinline__ void layer_interp(const LayerPiece &L, const LayerX &X, int m, int u,
+                                                      int v, const double *Hprev, int wvp, LayerInterp &I)
+{
+    I.cp = layer_cp(L, X.N, m, u, v);
+    const double inv_m = rcp_f64((double)m);
+    I.r2 = mul24(m, m) + mul24(u, u) + mul24(v, v);
+    I.ds = sqrt_fast((double)I.r2) * inv_m;
+    const double a = u == m ? 1.0 : (double)u * inv_m;
+    const double b = v == m ? 1.0 : (double)v * inv_m;
+    I.sw[0] = (1.0 - a) * (1.0 - b);
+    I.sw[1] = a * (1.0 - b);
+    I.sw[2] = (1.0 - a) * b;
+    I.sw[3] = a * b;
+    I.iW = 1.0;
+    if (m == 1) {   // the only neighbour of non-zero weight is the source: N_in = its column
+        I.Nin = X.reading == 0 ? X.half_col * I.ds : X.half_col;
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            I.f[n] = 0.0;
+            I.thick[n] = false;
+        }
+        return;
+    }
+    double num = 0.0, W = 0.0;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {   // zero-weight neighbours may lie outside layer m - 1: not read
+        const double h = I.sw[n] > 0.0 ? Hprev[(u - (n & 1)) * wvp + (v - (n >> 1))] : 0.0;
+        I.thick[n] = h > 0.0;
+        I.f[n] = I.thick[n] ? h : X.inv_tw;
+        const double g = I.thick[n] ? X.inv_s0 : -h * X.inv_tw;
+        num += I.sw[n] * g;
+        W += I.sw[n] * I.f[n];
+    }
+    I.iW = rcp_f64(W);
+    I.Nin = num * I.iW;
+}
+
+// The rate's share of the adjoint of a cell with a rate (owned, entry optical
+// depth inside the table): with Gamma = k D(tau_in, dtau), k = -coef / r2,
+// g_in = gbar dGamma/dN_in and g_dN = gbar dGamma/d(dN) from the FP64
+// derivatives of the divided difference.  Returns g_in (added to the cell's
+// exit-column adjoint before the interpolation is reversed), the part of
+// dL/dn_HI of the cell that the reverse does not produce,
+// (g_dN - g_in) alpha ds, and gbar Gamma.
+__host__ __device__ __forceinline__ void layer_rate_adjoint(const TabNode *T, const double *m64,
+                                                            const TabParams &tp, const LayerX &X,
+                                                            double coef, const LayerInterp &I, double nhi,
+                                                            double gbar, double *g_in, double *nbar_extra,
+                                                            double *gG)
+{
+    double D, Da, Ddt;
+    rate_derivs64(T, m64, tp, X.sigma0 * I.Nin, X.sigma0 * nhi * X.alpha * I.ds, &D, &Da, &Ddt);
+    const double k = -coef * rcp_f64((double)I.r2);
+    const double gi = gbar * k * Da * X.sigma0;
+    const double gd = gbar * k * Ddt * X.sigma0;
+    *g_in = gi;
+    *nbar_extra = (gd - gi) * X.alpha * I.ds;
+    *gG = gbar * k * D;
+}
+
+// Reverse-mode update of layer cell (u, v) of layer m through the
+// interpolation.  Tin is the total adjoint of the cell's entry column: what
+// its consumers pushed to its exit column plus, for a cell with a rate, the
+// rate's entry-column term g_in.  Since N_out = N_in + dN, the exit-column
+// adjoint flows unchanged into N_in and dN, so the cell's dL/dn_HI is
+// Tin alpha ds here (the rate's remaining part comes from layer_rate_adjoint).
+// With N_in = sum s g / sum s f (f, g as in layer_entry),
 // dN_in/dM_n = s_n sigma0 N_in f_n^2 / W for a neighbour with
 // sigma0 M_n > tau_w (f_n = 1/(sigma0 M_n)) and s_n f_n / W for any other
 // (f_n constant), W = sum s f: the entries alone suffice.  Returns the
 // adjoints to push to the four neighbours of layer m - 1 (Mbar[n] for
 // neighbour (u - (n & 1), v - (n >> 1)); zero where the weight is zero; for
-// m = 1 the source takes them through nbar_src), dL/dn_HI of the cell
-// ((T + g_dN) alpha ds) and gbar Gamma (for dL/dQ).
+// m = 1 the source takes them through nbar_src) and dL/dn_HI of the cell.
+// I is the cell's layer_interp.
 struct LayerRev {
     uint32_t cp;
     double Mbar[4];
     double nbar_src;
     double nbar;
-    double qb;
 };
 
-__host__ __device__ __forceinline__ void layer_cell_reverse(const LayerPiece &L, const LayerX &X,
-                                                            const TabNode *T, const double *m64,
-                                                            const TabParams &tp, double coef, int m,
-                                                            int u, int v, const double *Hprev, int wvp,
-                                                            bool lit, const double *gbar_grid, double Tout,
-                                                            LayerRev &out)
+__host__ __device__ __forceinline__ void layer_cell_reverse(const LayerX &X, int m, const LayerInterp &I,
+                                                            double Tin, LayerRev &out)
 {
-    out.cp = layer_cp(L, X.N, m, u, v);
-    const double inv_m = rcp_f64((double)m);
-    const int r2 = mul24(m, m) + mul24(u, u) + mul24(v, v);
-    const double ds = sqrt_fast((double)r2) * inv_m;
-    const double a = u == m ? 1.0 : (double)u * inv_m;
-    const double b = v == m ? 1.0 : (double)v * inv_m;
-    const double sw[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
-    double f[4];
-    bool thick[4];
-    double Nin, iW = 1.0;
-    if (m == 1) {   // the only neighbour of non-zero weight is the source: N_in = its column
-        Nin = X.reading == 0 ? X.half_col * ds : X.half_col;
-    } else {
-        double num = 0.0, W = 0.0;
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {   // zero-weight neighbours may lie outside layer m - 1: not read
-            const double h = sw[n] > 0.0 ? Hprev[(u - (n & 1)) * wvp + (v - (n >> 1))] : 0.0;
-            thick[n] = h > 0.0;
-            f[n] = thick[n] ? h : X.inv_tw;
-            const double g = thick[n] ? X.inv_s0 : -h * X.inv_tw;
-            num += sw[n] * g;
-            W += sw[n] * f[n];
-        }
-        iW = rcp_f64(W);
-        Nin = num * iW;
-    }
-    double Tin = Tout, Tdn = Tout;
-    out.qb = 0.0;
-    const double gb = lit ? gbar_grid[out.cp] : 0.0;
-    if (gb != 0.0) {
-        const double dN = X.nHI[out.cp] * X.alpha * ds;
-        double D, Da, Ddt;
-        rate_derivs64(T, m64, tp, X.sigma0 * Nin, X.sigma0 * dN, &D, &Da, &Ddt);
-        const double k = -coef * rcp_f64((double)r2);
-        Tin += gb * k * Da * X.sigma0;
-        Tdn += gb * k * Ddt * X.sigma0;
-        out.qb = gb * k * D;
-    }
-    out.nbar = Tdn * X.alpha * ds;                    // dN = n_HI alpha ds
+    out.cp = I.cp;
+    out.nbar = Tin * X.alpha * I.ds;                  // dN = n_HI alpha ds
     out.nbar_src = 0.0;
 #pragma unroll
     for (int n = 0; n < 4; ++n) out.Mbar[n] = 0.0;
     if (m == 1) {
-        out.nbar_src = Tin * (X.reading == 0 ? X.alpha * ds * 0.5 : X.alpha * 0.5);
+        out.nbar_src = Tin * (X.reading == 0 ? X.alpha * I.ds * 0.5 : X.alpha * 0.5);
         return;
     }
-    const double tk = Tin * iW, tt = tk * X.sigma0 * Nin;
+    const double tk = Tin * I.iW, tt = tk * X.sigma0 * I.Nin;
 #pragma unroll
-    for (int n = 0; n < 4; ++n) out.Mbar[n] = sw[n] * f[n] * (thick[n] ? tt * f[n] : tk);
+    for (int n = 0; n < 4; ++n) out.Mbar[n] = I.sw[n] * I.f[n] * (I.thick[n] ? tt * I.f[n] : tk);
 }
 
 // Build the row table of shell q of a piece (serial form; the kernel runs

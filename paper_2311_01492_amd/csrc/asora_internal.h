@@ -99,6 +99,7 @@ struct AdjLaunch {
     const char *kept;      // layer pieces: column records kept by the forward, or NULL
     size_t rec_piece_bytes;   // bytes of one pyramid's column record
     long rec_cap;             // cells (and listed cells) per pyramid record
+    bool split;               // layer pieces: rate terms of dense chunks in the reverse pass
 };
 
 size_t adj_region_bytes(int ring_cap, int row_cap, int shell_cap);
@@ -110,7 +111,7 @@ hipError_t launch_adj_prologue(hipStream_t st, const float *nH, const float *xHI
 hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L);
 constexpr int kAdjLayerWaves = 12;   // largest work-group of the layer adjoint (waves)
 size_t adj_layer_region_bytes(int S);
-hipError_t adj_layer_occupancy(bool kept, int waves, size_t lds, int *blocks_per_cu);
+hipError_t adj_layer_occupancy(bool kept, bool split, int waves, size_t lds, int *blocks_per_cu);
 hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int Mcap, int S);
 hipError_t launch_adj_transpose_prologue(hipStream_t st, const float *nH, const float *xHI,
                                          const double *gbar, double *nHI_T, double *gbar_T,

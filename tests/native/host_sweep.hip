@@ -317,20 +317,24 @@ extern "C" int hc_raytrace_layer(int N, double alpha, double sigma0, int n, doub
 
 // Reverse mode on the CPU through the layer pieces, in the adjoint kernel's
 // order, per pyramid: (F) the forward pass fills the column record (the
-// cells' layer-buffer entries, each chunk's mask of cells with a rate); (R)
-// layers from the outermost inward, each layer's rectangle in chunks from the
-// first to the last, each chunk reading its slots and clearing them, adding
-// the rate terms of its cells with a rate, and pushing to its layer m - 1
-// neighbours, whose entries it reads from the record.  dL/dn_HI of pyramids
+// cells' layer-buffer entries, each chunk's mask of cells with a rate); (G)
+// the rate terms of the cells with a rate; (R) layers from the outermost
+// inward, each layer's rectangle in chunks from the first to the last, each
+// chunk reading its slots and clearing them, adding the rate's entry-column
+// terms of its cells with a rate, and pushing to its layer m - 1 neighbours,
+// whose entries it reads from the record.  dL/dn_HI of pyramids
 // with dominant axis k goes through a [k][i][j] buffer as on the GPU.
+// split != 0: chunks with at least kDenseChunk cells with a rate evaluate
+// them in (R), as the kernel's split form; else all are gathered in (G).
 // Returns -6 if a neighbour of non-zero weight is not an active cell of layer
 // m - 1, -7 if a chunk mask marks an inactive lane.
 extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n, double lg_lo,
                                       double lg_hi, const double *P, const double *dP, double tau_w,
                                       int reading, const float *nH, const float *xHI, long nsrc,
                                       const int32_t *ijk, const double *Q, const float *R,
-                                      const double *gbar, double *nbar, double *qbar)
+                                      const double *gbar, double *nbar, double *qbar, int split)
 {
+    const int dense_at = split ? kDenseChunk : 65;
     HostLayerSetup H;
     host_layer_setup(H, N, n, lg_lo, lg_hi, P, dP, nH, xHI, nsrc, R);
     const long n3 = (long)N * N * N;
@@ -340,7 +344,7 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
             for (long k = 0; k < N; ++k) gbT[(k * N + i) * N + j] = gbar[(i * N + j) * N + k];
     const int S = H.S;
     const size_t SS = (size_t)S * S;
-    std::vector<double> cols(SS), abar(SS);
+    std::vector<double> cols(SS), abar(SS), gin(H.cap);
     std::vector<int> cols_id(SS);
     std::vector<char> recmem(layer_record_bytes(H.cap, H.Mcap));
     LayerRecord rec = layer_record_at(recmem.data(), H.cap);
@@ -364,14 +368,41 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
             int st = layer_forward_piece(L, X, Rsq, H.T.data(), H.tp, coef, S, cols.data(), cols_id.data(),
                                          nullptr, nullptr, N, &rec);
             if (st) return st;
-            // (R)
-            std::fill(abar.begin(), abar.end(), 0.0);
+            // (G)
             long off = 0, choff = 0;
             for (int m = 1; m <= Mx; ++m) {
-                const int t = layer_rect(L.ext_u, L.ext_v, Rsq, m).total;
-                off += t;
-                choff += (t + 63) / 64;
+                const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
+                const int nch = (r.total + 63) / 64;
+                const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m >= 2 ? m - 1 : 1);
+                for (int c = 0; c < nch; ++c) {
+                    const uint64_t litmask = rec.lit[choff + c];
+                    if (__builtin_popcountll(litmask) >= dense_at) continue;   // left to (R)
+                    for (int lane = 0; lane < 64; ++lane) {
+                        if (!((litmask >> lane) & 1)) continue;
+                        const int g = c * 64 + lane;
+                        RectWalk w;
+                        w.init(r, g);
+                        if (g >= r.total || w.u * w.u + w.v * w.v > r.rem) return -7;
+                        const double *Hprev = rec.h + (m >= 2 ? off - rp.total : 0);
+                        LayerInterp I;
+                        layer_interp(L, X, m, w.u, w.v, Hprev, rp.wv, I);
+                        double gi = 0.0;
+                        const double g_ = gb[I.cp];
+                        if (g_ != 0.0) {
+                            double ne, gG;
+                            layer_rate_adjoint(H.T.data(), H.m64.data(), H.tp, X, coef, I, X.nHI[I.cp], g_, &gi,
+                                               &ne, &gG);
+                            nb[I.cp] += ne;
+                            qb += gG;
+                        }
+                        gin[off + g] = gi;
+                    }
+                }
+                off += r.total;
+                choff += nch;
             }
+            // (R)
+            std::fill(abar.begin(), abar.end(), 0.0);
             for (int m = Mx; m >= 1; --m) {
                 const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
                 const int nch = (r.total + 63) / 64;
@@ -385,21 +416,22 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
                     LayerRev lr[64];
                     bool act[64];
                     int uu[64], vv[64];
-                    double Tout[64];
+                    double Tin[64];
                     const uint64_t litmask = rec.lit[choff + c];
                     for (int lane = 0; lane < 64; ++lane) {
                         uu[lane] = wk[lane].u;
                         vv[lane] = wk[lane].v;
                         wk[lane].up();
                         act[lane] = c * 64 + lane < r.total && uu[lane] * uu[lane] + vv[lane] * vv[lane] <= r.rem;
-                        if (((litmask >> lane) & 1) && !act[lane]) return -7;
-                        Tout[lane] = act[lane] ? abar[(size_t)uu[lane] * S + vv[lane]] : 0.0;
+                        Tin[lane] = act[lane] ? abar[(size_t)uu[lane] * S + vv[lane]] : 0.0;
                     }
                     for (int lane = 0; lane < 64; ++lane)
                         if (act[lane]) abar[(size_t)uu[lane] * S + vv[lane]] = 0.0;
+                    const bool dense = __builtin_popcountll(litmask) >= dense_at;
                     for (int lane = 0; lane < 64; ++lane) {
                         const bool lit = (litmask >> lane) & 1;
-                        if (!act[lane] || (Tout[lane] == 0.0 && !lit)) continue;
+                        if (lit && !dense) Tin[lane] += gin[off + c * 64 + lane];
+                        if (!act[lane] || (Tin[lane] == 0.0 && !(lit && dense))) continue;
                         const int u = uu[lane], v = vv[lane];
                         if (m > 1) {   // neighbours of non-zero weight: active cells of layer m - 1
                             const bool a0 = u > 0, a1 = u < m, b0 = v > 0, b1 = v < m;
@@ -410,14 +442,22 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
                                 if (un >= rp.nu || vn >= rp.wv || un * un + vn * vn > rp.rem) return -6;
                             }
                         }
-                        layer_cell_reverse(L, X, H.T.data(), H.m64.data(), H.tp, coef, m, u, v, Hprev, rp.wv,
-                                           lit, gb, Tout[lane], lr[lane]);
+                        LayerInterp I;
+                        layer_interp(L, X, m, u, v, Hprev, rp.wv, I);
+                        double extra = 0.0;
+                        if (lit && dense && gb[I.cp] != 0.0) {
+                            double gi, gG;
+                            layer_rate_adjoint(H.T.data(), H.m64.data(), H.tp, X, coef, I, X.nHI[I.cp], gb[I.cp],
+                                               &gi, &extra, &gG);
+                            Tin[lane] += gi;
+                            qb += gG;
+                        }
+                        layer_cell_reverse(X, m, I, Tin[lane], lr[lane]);
                         for (int k = 0; k < 4; ++k)
                             if (lr[lane].Mbar[k] != 0.0)
                                 abar[(size_t)(u - (k & 1)) * S + (v - (k >> 1))] += lr[lane].Mbar[k];
-                        nb[lr[lane].cp] += lr[lane].nbar;
+                        nb[lr[lane].cp] += lr[lane].nbar + extra;
                         nb_src += lr[lane].nbar_src;
-                        qb += lr[lane].qb;
                     }
                 }
             }

@@ -44,7 +44,7 @@ def load():
         lib.hc_raytrace_layer.restype = i
         lib.hc_raytrace_layer.argtypes = [i, d, d, i, d, d, p, p, d, i, p, p, l, p, p, p, p, p]
         lib.hc_raytrace_layer_grad.restype = i
-        lib.hc_raytrace_layer_grad.argtypes = [i, d, d, i, d, d, p, p, d, i, p, p, l, p, p, p, p, p, p]
+        lib.hc_raytrace_layer_grad.argtypes = [i, d, d, i, d, d, p, p, d, i, p, p, l, p, p, p, p, p, p, i]
         lib.hc_rows.restype = i
         lib.hc_rows.argtypes = [i, i, i, i, i, p, p]
         _lib = lib
@@ -106,9 +106,10 @@ def rows(N, type_, piece, Rsq, q):
 
 
 def raytrace_grad(N, cell_cm, sigma0, table, n_H, x_HI, ijk, Q, R, gbar, tau_w=0.6, reading=0,
-                  type_force=-1, R_whole=10.0, R_oct=30.0, layers=False):
+                  type_force=-1, R_whole=10.0, R_oct=30.0, layers=False, split=True):
     """(dL/dn_H, dL/dx_HI, dL/dQ) for dL/dGamma = gbar (FP64); layers: every
-    source as layer pyramids."""
+    source as layer pyramids, the rate terms of dense chunks in the reverse
+    pass (split) or all gathered first."""
     lib = load()
     P, dP = np.ascontiguousarray(table.P, np.float64), np.ascontiguousarray(table.dP, np.float64)
     nH = np.ascontiguousarray(n_H, np.float32)
@@ -122,7 +123,7 @@ def raytrace_grad(N, cell_cm, sigma0, table, n_H, x_HI, ijk, Q, R, gbar, tau_w=0
     if layers:
         st = lib.hc_raytrace_layer_grad(N, cell_cm, sigma0, len(P), table.lg_lo, table.lg_hi, _p(P),
                                         _p(dP), float(tau_w), reading, _p(nH), _p(xH), len(Q), _p(ijk),
-                                        _p(Q), _p(R), _p(gb), _p(nbar), _p(qbar))
+                                        _p(Q), _p(R), _p(gb), _p(nbar), _p(qbar), 1 if split else 0)
     else:
         st = lib.hc_raytrace_grad(N, cell_cm, sigma0, len(P), table.lg_lo, table.lg_hi, _p(P), _p(dP),
                                   float(tau_w), reading, _p(nH), _p(xH), len(Q), _p(ijk), _p(Q), _p(R),

@@ -29,10 +29,16 @@ def _loss_grad(g, wt):
     return wt / ((g + 1e-20) * math.log(10))
 
 
-def _gpu_backward(asora, w, table, gbar, sweep=3, **kw):
-    """sweep: 3 = large sources as layer pyramids (the default), 2 = shell pyramids."""
+# large sources as layer pyramids, their adjoint's rate terms split between
+# the gathering and the reverse pass (the default) or all gathered; or as
+# shell pyramids
+SWEEPS = [(3, 2), (3, 1), (2, 0)]
+SWEEP_IDS = ["layers", "layers-gathered", "shells"]
+
+
+def _gpu_backward(asora, w, table, gbar, sweep=(3, 2), **kw):
     ctx = asora.Asora(w.N, w.cell_cm, table.P, table.dP, table.lg_lo, table.lg_hi, **kw)
-    ctx.set_tuning(pyramid_sweep=sweep)
+    ctx.set_tuning(pyramid_sweep=sweep[0], adj_rate=sweep[1])
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     dn, dx, dq = ctx.backward(t(w.n_H), t(w.x_HI), t(w.src.ijk), t(w.src.Q), t(w.src.R), t(gbar))
     ctx.check()
@@ -48,7 +54,7 @@ def _case(name, **kw):
     return w, g, wt
 
 
-@pytest.mark.parametrize("sweep", [3, 2], ids=["layers", "shells"])
+@pytest.mark.parametrize("sweep", SWEEPS, ids=SWEEP_IDS)
 def test_c4_against_oracle_reverse(asora, bb, sweep):
     print("case c4 adjoint vs oracle sweep", sweep, flush=True)
     w, g, wt = _case("c4")
@@ -61,7 +67,7 @@ def test_c4_against_oracle_reverse(asora, bb, sweep):
     np.testing.assert_allclose(gq, oq, rtol=1e-5)
 
 
-@pytest.mark.parametrize("sweep", [3, 2], ids=["layers", "shells"])
+@pytest.mark.parametrize("sweep", SWEEPS, ids=SWEEP_IDS)
 @pytest.mark.parametrize("tau_w,scalar", [(math.inf, False), (0.6, True)])
 def test_uneven_radii_all_piece_kinds(asora, bb, tau_w, scalar, sweep):
     print("case adjoint uneven", tau_w, scalar, "sweep", sweep, flush=True)
@@ -152,17 +158,19 @@ def test_autograd_function(asora, bb):
     torch.testing.assert_close(Q.grad, dq, rtol=1e-6, atol=0)
 
 
-def test_kept_records_match_recompute_and_oracle(asora, bb):
+@pytest.mark.parametrize("adj_rate", [2, 1], ids=["split", "gathered"])
+def test_kept_records_match_recompute_and_oracle(asora, bb, adj_rate):
     """Forward with ASORA_STORE keeps the pyramids' column records; the
     backward that reads them gives the recomputing backward's gradients and
     the oracle's.  Uneven radii cover whole-source and octant pieces (always
     recomputed) next to the pyramids."""
-    print("case kept records c4", flush=True)
+    print("case kept records c4 adj_rate", adj_rate, flush=True)
     w, g, wt = _case("c4")
     gbar = _loss_grad(g, wt)
     on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
                                       w.src.R, gbar)
     ctx = asora.Asora(w.N, w.cell_cm, bb.P, bb.dP, bb.lg_lo, bb.lg_hi)
+    ctx.set_tuning(adj_rate=adj_rate)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     nH, xH, ijk, Q, R, gb = t(w.n_H), t(w.x_HI), t(w.src.ijk), t(w.src.Q), t(w.src.R), t(gbar)
     ctx.raytrace(nH, xH, ijk, Q, R, store=True)
@@ -185,6 +193,7 @@ def test_kept_records_match_recompute_and_oracle(asora, bb):
     on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
                                       w.src.R, gbar)
     ctx = asora.Asora(w.N, w.cell_cm, bb.P, bb.dP, bb.lg_lo, bb.lg_hi)
+    ctx.set_tuning(adj_rate=adj_rate, adj_waves=12 if adj_rate == 1 else 2)
     nH, xH, ijk, Q, R, gb = t(w.n_H), t(w.x_HI), t(w.src.ijk), t(w.src.Q), t(w.src.R), t(gbar)
     ctx.raytrace(nH, xH, ijk, Q, R, store=True)
     assert ctx.store_info()[0]
