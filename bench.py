@@ -169,6 +169,21 @@ def cpu_baseline(w, budget_s: float = 12.0):
                       f"workload ({t:.1f} s, one thread, FP64)"}
 
 
+def parse_tuning(text):
+    """'R_oct=10,table_place=lds,adj_rate=gathered' -> keyword arguments of
+    Asora.set_tuning (the named values are those the JSON line prints)."""
+    named = {"table_place": {"lds": 1, "caches": 2}, "adj_rate": {"gathered": 1, "split": 2}}
+    out = {}
+    for item in filter(None, text.split(",")):
+        k, v = item.split("=")
+        k = k.strip()
+        if k in named and v in named[k]:
+            out[k] = named[k][v]
+        else:
+            out[k] = float(v) if k in ("R_whole", "R_oct") else int(v)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +193,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-source form")
     ap.add_argument("--no-tune", action="store_true", help="keep the default scheduling parameters")
+    ap.add_argument("--tuning", metavar="K=V,...",
+                    help="set these scheduling parameters instead of autotuning (keys as in the "
+                         "JSON line's tuning object, e.g. R_oct=10,adj_rate=gathered)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--reduce-pmc", metavar="DIR", help="reduce rocprofv3 counter CSVs and exit")
@@ -242,7 +260,9 @@ def main():
     # ---- scheduling parameters: the library's autotuner on this workload
     # (forward with kept records + adjoint), before anything is timed
     tuning = {"autotuned": False}
-    if not args.no_tune:
+    if args.tuning:
+        ctx.set_tuning(**parse_tuning(args.tuning))
+    elif not args.no_tune:
         print("[bench] autotune", file=sys.stderr, flush=True)
         best, rep = ctx.autotune(nH, xH, ijk, Q, R, R_max=R_max, passes=2)
         tuning = {"autotuned": True, "candidates": len(rep), "best_ms": best}
