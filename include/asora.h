@@ -64,17 +64,22 @@ typedef enum {
                                   piece (sources above R_oct, swept in layers) in
                                   library-owned device memory, if it fits the store
                                   budget (asora_set_store_budget); otherwise nothing
-                                  is kept (asora_store_info tells which).  backward:
-                                  take the columns and the cells with a rate from
-                                  those records instead of re-sweeping the pyramids
-                                  forward, provided the most recent forward call with
+                                  is kept (asora_store_info tells which); the records
+                                  also hold the rate's FP64 derivatives for every cell
+                                  with a rate.  backward: take the columns, the cells
+                                  with a rate and those derivatives from the records
+                                  instead of re-sweeping the pyramids forward and
+                                  re-evaluating the rate, provided the most recent
+                                  forward call with
                                   ASORA_STORE kept them for the same n_H, x_HI,
                                   src_ijk, src_Q, src_R pointers, n_src and R_max and
                                   the tuning has not changed since; otherwise the
                                   adjoint recomputes them.  The caller guarantees that
                                   the contents of those buffers did not change in
-                                  between.  Whole-source and octant pieces are always
-                                  recomputed.  Results are the same either way.      */
+                                  between (if they did, the gradients are wrong, but
+                                  every access stays inside the records).  Whole-source
+                                  and octant pieces are always recomputed.  Results
+                                  are the same either way up to rounding.            */
 #define ASORA_PLAIN      0x2u  /* one kernel launch per source, in input order: the
                                   unbatched baseline form (Section 3.3, one block per
                                   source).  Default: all sources in one persistent
@@ -224,8 +229,9 @@ asora_status asora_store_info(const asora_ctx *ctx, int32_t *valid, uint64_t *by
 
 /*
  * asora_set_store_budget -- largest number of bytes of device memory the kept
- * column records may take (n_src x 24 x one pyramid's record, about 8 bytes
- * per cell of the largest pyramid).  0 (the default) means half of the free
+ * column records may take (n_src x 24 x one pyramid's record, about 32 bytes
+ * per cell of the largest pyramid: its entry and room for the rate's three
+ * derivatives).  0 (the default) means half of the free
  * device memory at the time of the forward call, plus what is already held.
  * A forward call with ASORA_STORE that needs more keeps nothing.
  */
@@ -248,7 +254,9 @@ asora_status asora_set_store_budget(asora_ctx *ctx, uint64_t bytes);
  * gathered into full waves before the reverse pass (fewer registers: suits
  * sources whose rate reaches few cells), 2 = those of chunks where at least
  * half the cells have a rate evaluated in the reverse pass itself (the
- * default: suits sources that ionise most of their sphere).  Values <= 0
+ * default: suits sources that ionise most of their sphere); it applies when
+ * the adjoint re-sweeps the pyramids (records kept with ASORA_STORE carry the
+ * rate's derivatives).  Values <= 0
  * keep the current setting.  ASORA_EINVAL if R_oct < R_whole, max_waves > 16,
  * pyramid_sweep is not 0, 2 or 3, table_place not 0, 1 or 2, adj_waves > 12
  * or adj_rate not 0, 1 or 2; ASORA_ESTATE while a recorded graph of the

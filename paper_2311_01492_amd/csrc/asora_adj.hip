@@ -52,6 +52,7 @@ struct AdjArgs {
     int Mcap, lay_S;         // largest layer index, row stride of the layer buffers
     const char *kept;        // column records kept by the forward (per source and pyramid), or NULL
     size_t rec_piece_bytes;  // bytes of one pyramid's column record
+    size_t rec_rk_off;       // kept records: offset of the rate coefficients
     long rec_cap;            // cells (and listed cells) per pyramid record
 };
 
@@ -303,8 +304,9 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
     const double coef = Q * A.coef_unit;
     const int S = A.lay_S;
     const LayerRecord rec = layer_record_at(
-        KEPT ? (char *)A.kept + ((size_t)src * 24 + p) * A.rec_piece_bytes : scratch, A.rec_cap);
-    double *gin = (double *)(scratch + A.rec_piece_bytes);   // g_in by record cell
+        KEPT ? (char *)A.kept + ((size_t)src * 24 + p) * A.rec_piece_bytes : scratch, A.rec_cap,
+        KEPT ? A.rec_rk_off : 0);
+    double *gin = KEPT ? nullptr : (double *)(scratch + A.rec_piece_bytes);   // g_in by record cell
     const int Mx = min(isqrt_floor(Rsq), L.ext_d);
     constexpr int dense_at = SPLIT ? kDenseChunk : 65;   // popcount of a dense chunk
 
@@ -348,9 +350,16 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
         wave_sync_global();
     }
 
-    // ---- (G)
+    // ---- (G), unless the forward kept the rate's coefficients
     double nb_src = 0.0, qb = 0.0;
-    {
+    long off = 0, choff = 0;
+    if (KEPT) {
+        for (int m = 1; m <= Mx; ++m) {
+            const int t = layer_rect(L.ext_u, L.ext_v, Rsq, m).total;
+            off += t;
+            choff += (t + 63) / 64;
+        }
+    } else {
         int head = 0, tail = 0;
         auto batch = [&](int count) {
             if (lane < count) {
@@ -363,7 +372,7 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
                 const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m >= 2 ? m - 1 : 1);
                 const double *Hprev = rec.h + (m >= 2 ? k - g - rp.total : 0);
                 LayerInterp I;
-                layer_interp(L, X, m, w.u, w.v, Hprev, rp.wv, I);
+                layer_interp(L, X, m, w.u, w.v, Hprev, rp, I);
                 const double gb = gbar[I.cp];
                 double gi = 0.0;
                 if (gb != 0.0) {
@@ -375,7 +384,6 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
                 gin[k] = gi;
             }
         };
-        long off = 0, choff = 0;
         for (int m = 1; m <= Mx; ++m) {
             const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
             const int nch = (r.total + 63) / 64;
@@ -409,10 +417,16 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
             batch(tail - head);
             wave_sync();
         }
-        for (int k = lane; k < S * S; k += 64) buf[k] = 0.0;   // the adjoint slots
-        wave_sync_global();
+    }
+    for (int k = lane; k < S * S; k += 64) buf[k] = 0.0;   // the adjoint slots
+    wave_sync_global();
 
-        // ---- (R)
+    // ---- (R)
+    {
+        // kept records: the cells with a rate were evaluated layer by layer
+        // from the first, a layer's chunks from the last, a chunk's lanes in
+        // order; lit_end counts those of layers <= m
+        long lit_end = KEPT ? (long)((const uint64_t *)rec.rk)[3 * A.rec_cap] : 0;
         for (int m = Mx; m >= 1; --m) {
             const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
             const int nch = (r.total + 63) / 64;
@@ -420,11 +434,11 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
             choff -= nch;      // its first chunk
             // entries of layer m - 1 (its rectangle precedes layer m's)
             const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m >= 2 ? m - 1 : 1);
-            const int wvp = rp.wv;
             const double *Hprev = rec.h + (m >= 2 ? off - rp.total : 0);
             RectWalk w;
             w.init(r, lane);
             uint64_t masks = 0;
+            long run = 0;   // cells with a rate in chunks 0 .. c of this layer
             for (int c = 0; c < nch; ++c, w.up()) {
                 if ((c & 63) == 0) masks = load_masks(rec, choff, c, nch, lane);
                 const int g = c * 64 + lane;
@@ -432,18 +446,52 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
                 const bool act = g < r.total && mul24(u, u) + mul24(v, v) <= r.rem;
                 const uint64_t litmask = mask_of_chunk(masks, c);
                 const bool lit = (litmask >> lane) & 1;
+                run += __popcll(litmask);
                 double Tin = 0.0;
                 if (act) {
                     Tin = buf[mul24(u, S) + v];
                     buf[mul24(u, S) + v] = 0.0;
                 }
                 wave_sync();
-                if (__ballot(Tin != 0.0) | litmask) {
+                if (KEPT && (__ballot(Tin != 0.0) | litmask)) {
+                    if (Tin != 0.0 || lit) {
+                        // the rate's coefficients and dL/dGamma, read with the entries
+                        double k0 = 0.0, k1 = 0.0, k2 = 0.0, gbc = 0.0;
+                        if (lit) {
+                            long q = lit_end - run +
+                                     (long)__builtin_amdgcn_mbcnt_hi((uint32_t)(litmask >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)litmask, 0u));
+                            // in range for any record contents (records of inputs changed since the
+                            // forward give wrong gradients, never reads outside the record)
+                            q = q < 0 ? 0 : (q >= A.rec_cap ? A.rec_cap - 1 : q);
+                            k0 = rec.rk[q];
+                            k1 = rec.rk[A.rec_cap + q];
+                            k2 = rec.rk[2 * A.rec_cap + q];
+                            gbc = gbar[layer_cp(L, N, m, u, v)] * coef;
+                        }
+                        LayerInterp I;
+                        layer_interp(L, X, m, u, v, Hprev, rp, I);
+                        Tin += gbc * k0;
+                        qb += gbc * k2;
+                        LayerRev lr;
+                        layer_cell_reverse(X, m, I, Tin, lr);
+                        if (m >= 2) {
+#pragma unroll
+                            for (int n = 0; n < 4; ++n)
+                                if (lr.Mbar[n] != 0.0)
+                                    atomicAdd(&buf[mul24(u - (n & 1), S) + (v - (n >> 1))], lr.Mbar[n]);
+                        }
+                        const double nb = lr.nbar + gbc * k1 * X.alpha * I.ds;
+                        if (nb != 0.0) unsafeAtomicAdd(&nbar[lr.cp], nb);
+                        nb_src += lr.nbar_src;
+                    }
+                    wave_sync();
+                } else if (!KEPT && (__ballot(Tin != 0.0) | litmask)) {
                     const bool dense = __popcll(litmask) >= dense_at;
                     if (lit && !dense) Tin += gin[off + g];
                     if (Tin != 0.0 || (lit && dense)) {
                         LayerInterp I;
-                        layer_interp(L, X, m, u, v, Hprev, wvp, I);
+                        layer_interp(L, X, m, u, v, Hprev, rp, I);
                         double extra = 0.0;
                         if (lit && dense) {
                             const double gb = gbar[I.cp];
@@ -470,6 +518,7 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
                     wave_sync();
                 }
             }
+            lit_end -= run;
         }
     }
     if (p == 3 * 0 + 2 && lane == 0) {   // the source cell, once per source
@@ -627,7 +676,7 @@ hipError_t adj_configure(size_t max_lds)
     for (int t = 0; t < 3; ++t)
         (void)hipFuncSetAttribute(adj_fn(t), hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     for (const void *f : {(const void *)adj_layer<false, false>, (const void *)adj_layer<false, true>,
-                          (const void *)adj_layer<true, false>, (const void *)adj_layer<true, true>})
+                          (const void *)adj_layer<true, false>})
         (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipGetLastError();
     return hipSuccess;
@@ -685,6 +734,7 @@ static AdjArgs make_adj_args(const AdjLaunch &L)
     A.lay_S = 0;
     A.kept = L.kept;
     A.rec_piece_bytes = L.rec_piece_bytes;
+    A.rec_rk_off = L.rec_rk_off;
     A.rec_cap = L.rec_cap;
     return A;
 }
@@ -711,7 +761,8 @@ size_t adj_layer_region_bytes(int S)
 
 hipError_t adj_layer_occupancy(bool kept, bool split, int waves, size_t lds, int *blocks_per_cu)
 {
-    const void *f = kept ? (split ? (const void *)adj_layer<true, true> : (const void *)adj_layer<true, false>)
+    // kept records carry the rate's coefficients: no rate terms to split
+    const void *f = kept ? (const void *)adj_layer<true, false>
                          : (split ? (const void *)adj_layer<false, true> : (const void *)adj_layer<false, false>);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, waves * 64, lds);
 }
@@ -724,8 +775,7 @@ hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int Mcap, int S)
     A.region_bytes = (int)adj_layer_region_bytes(S);
     const size_t lds = (size_t)L.waves * A.region_bytes;
     const dim3 grid(L.grid), block(64 * L.waves);
-    if (A.kept && L.split) hipLaunchKernelGGL((adj_layer<true, true>), grid, block, lds, st, A);
-    else if (A.kept) hipLaunchKernelGGL((adj_layer<true, false>), grid, block, lds, st, A);
+    if (A.kept) hipLaunchKernelGGL((adj_layer<true, false>), grid, block, lds, st, A);
     else if (L.split) hipLaunchKernelGGL((adj_layer<false, true>), grid, block, lds, st, A);
     else hipLaunchKernelGGL((adj_layer<false, false>), grid, block, lds, st, A);
     return hipGetLastError();

@@ -29,7 +29,8 @@ struct Plan {
     long scratch;       // adjoint: doubles of scratch per wave
     int Mcap;           // layer pieces: largest layer index
     long rec_cap;       // layer pieces: cells per pyramid record
-    size_t rec_bytes;   // layer pieces: bytes of one pyramid record
+    size_t rec_bytes;   // layer pieces: bytes of one pyramid record (the adjoint's own)
+    size_t keep_bytes;  // layer pieces: bytes of one record kept by the forward (with rate coefficients)
     int wave_mode;   // 1: one wave per piece (waves per work-group below); 0: one work-group per piece
     int waves;
     size_t lds;
@@ -382,7 +383,8 @@ static asora_status get_layer_plan(asora_ctx *c, float R_cap, Plan *out)
     P.S = layer_buffer_side(Rsq, ex);
     P.rec_cap = layer_piece_capacity(Rsq, ex);
     if (P.rec_cap < 1) P.rec_cap = 1;
-    P.rec_bytes = layer_record_bytes(P.rec_cap, P.Mcap);
+    P.rec_bytes = layer_record_bytes(P.rec_cap, P.Mcap, false);
+    P.keep_bytes = layer_record_bytes(P.rec_cap, P.Mcap, true);
     P.wave_mode = 1;
     const size_t tab = c->tab_lds ? (size_t)c->tp.n * sizeof(TabNode) : 0;
     const size_t region = layer_region_bytes(P.S);
@@ -533,7 +535,7 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     bool keep = false;
     if (flags & ASORA_STORE) {
         c->keep_valid = false;
-        c->keep_need = layers ? (size_t)n_src * 24 * plans[3].rec_bytes : 0;
+        c->keep_need = layers ? (size_t)n_src * 24 * plans[3].keep_bytes : 0;
         if ((st = reserve_keep(c, c->keep_need, &keep))) return st;
     }
 
@@ -557,8 +559,10 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     F.nHI_T = c->d_nhi_T;
     F.gacc_T = c->d_gacc_T;
     F.keep = keep ? c->d_keep : nullptr;
-    F.keep_piece_bytes = layers ? plans[3].rec_bytes : 0;
+    F.keep_piece_bytes = layers ? plans[3].keep_bytes : 0;
     F.keep_cap = layers ? plans[3].rec_cap : 0;
+    F.keep_rk_off = layers ? plans[3].rec_bytes : 0;
+    F.m64 = c->d_m64;
     F.tab_lds = c->tab_lds;
 
     if (prof) HIPCHK(c, hipEventRecord(ev[0], s));
@@ -767,7 +771,10 @@ static asora_status get_adj_layer_plan(asora_ctx *c, float R_cap, bool kept, Pla
     HIPCHK(c, adj_layer_occupancy(kept, c->adj_split != 0, P.waves, P.lds, &bpc));
     P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
     P.piece_cells = P.rec_cap;
-    P.scratch = (long)(P.rec_bytes / sizeof(double)) + P.rec_cap;   // record, then g_in per cell
+    // the record, then g_in per cell (unused when the forward kept the records,
+    // but sized alike, so that both forms run on the same buffers: a recorded
+    // graph of one leaves room for eager calls of the other)
+    P.scratch = (long)(P.rec_bytes / sizeof(double)) + P.rec_cap;
     c->adj_plans[key] = P;
     *out = P;
     return ASORA_OK;
@@ -822,7 +829,13 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
         const float cap = t == tmax ? R_max : (t == 0 ? c->R_whole : c->R_oct);
         if ((st = t == 3 ? get_adj_layer_plan(c, cap, kept, &plans[t]) : get_adj_plan(c, t, cap, &plans[t])))
             return st;
-        const size_t need = (size_t)plans[t].grid * plans[t].waves * (size_t)plans[t].scratch;
+        size_t need = (size_t)plans[t].grid * plans[t].waves * (size_t)plans[t].scratch;
+        if (t == 3) {   // room for the other form too (kept records or not): see get_adj_layer_plan
+            Plan o;
+            if ((st = get_adj_layer_plan(c, cap, !kept, &o))) return st;
+            const size_t n2 = (size_t)o.grid * o.waves * (size_t)o.scratch;
+            need = n2 > need ? n2 : need;
+        }
         store_need = need > store_need ? need : store_need;
     }
     if ((st = ensure_src_cap(c, n_src))) return st;
@@ -872,7 +885,8 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
         L.gbar_T = c->d_gbar_T;
         L.nbar_T = c->d_nbar_T;
         L.kept = kept ? c->d_keep : nullptr;
-        L.rec_piece_bytes = layers ? plans[3].rec_bytes : 0;
+        L.rec_piece_bytes = layers ? (kept ? plans[3].keep_bytes : plans[3].rec_bytes) : 0;
+        L.rec_rk_off = kept ? plans[3].rec_bytes : 0;
         L.rec_cap = layers ? plans[3].rec_cap : 0;
         L.split = c->adj_split != 0;
         for (int t = tmax; t >= 0; --t) {

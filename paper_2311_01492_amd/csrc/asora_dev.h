@@ -890,22 +890,34 @@ __host__ __device__ inline long layer_piece_capacity(int Rsq, const Extent &ex)
 // (owned, entry optical depth inside the table).  Written by the forward
 // sweep when the columns are kept, or by the adjoint's own forward pass; read
 // by the adjoint's reverse pass.  `cap` bounds the cells of one pyramid.
+// A record kept by the forward also holds, for the cells with a rate in the
+// order the forward evaluated them, the rate's coefficients for the adjoint
+// (layer_rate_coefs) in three arrays of cap entries, followed by the number
+// of such cells.
 struct LayerRecord {
     double *h;        // [cap] layer-buffer entries of the cells
     uint64_t *lit;    // [cap / 64 + Mcap + 1] rate masks, one per chunk
+    double *rk;       // kept records: [3][cap] rate coefficients, then the count; else NULL
 };
 
-__host__ __device__ __forceinline__ size_t layer_record_bytes(long cap, int Mcap)
+// Bytes of a record of cap cells, with (coefs) or without the rate
+// coefficients; the coefficients start at layer_record_bytes(cap, Mcap, false).
+__host__ __device__ __forceinline__ size_t layer_record_bytes(long cap, int Mcap, bool coefs)
 {
-    const size_t b = (size_t)cap * sizeof(double) + ((size_t)cap / 64 + Mcap + 1) * sizeof(uint64_t);
-    return (b + 255) & ~(size_t)255;
+    size_t b = (size_t)cap * sizeof(double) + ((size_t)cap / 64 + Mcap + 1) * sizeof(uint64_t);
+    b = (b + 255) & ~(size_t)255;
+    if (coefs) b += ((3 * (size_t)cap + 1) * sizeof(double) + 255) & ~(size_t)255;
+    return b;
 }
 
-__host__ __device__ __forceinline__ LayerRecord layer_record_at(char *base, long cap)
+// rk_off: layer_record_bytes(cap, Mcap, false) for a record with the
+// coefficients, 0 for one without.
+__host__ __device__ __forceinline__ LayerRecord layer_record_at(char *base, long cap, size_t rk_off)
 {
     LayerRecord s;
     s.h = (double *)base;
     s.lit = (uint64_t *)(s.h + cap);
+    s.rk = rk_off ? (double *)(base + rk_off) : nullptr;
     return s;
 }
 
@@ -1182,8 +1194,14 @@ struct LayerInterp {
     bool thick[4];
 };
 
+// The interpolation of cell (u, v) of layer m from its four neighbours in
+// layer m - 1, whose entries Hprev holds in layer m - 1's rectangle rp (for
+// m = 1 the only neighbour of non-zero weight is the source: N_in is its
+// column).  Neighbours of zero weight may lie outside layer m - 1 and are not
+// read.
 __host__ __device__ __forceinline__ void layer_interp(const LayerPiece &L, const LayerX &X, int m, int u,
-                                                      int v, const double *Hprev, int wvp, LayerInterp &I)
+                                                      int v, const double *Hprev, const LayerRect &rp,
+                                                      LayerInterp &I)
 {
     I.cp = layer_cp(L, X.N, m, u, v);
     const double inv_m = rcp_f64((double)m);
@@ -1196,19 +1214,16 @@ __host__ __device__ __forceinline__ void layer_interp(const LayerPiece &L, const
     I.sw[2] = (1.0 - a) * b;
     I.sw[3] = a * b;
     I.iW = 1.0;
-    if (m == 1) {   // the only neighbour of non-zero weight is the source: N_in = its column
+    if (m == 1) {
         I.Nin = X.reading == 0 ? X.half_col * I.ds : X.half_col;
 #pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            I.f[n] = 0.0;
-            I.thick[n] = false;
-        }
+        for (int n = 0; n < 4; ++n) { I.f[n] = 0.0; I.thick[n] = false; }
         return;
     }
     double num = 0.0, W = 0.0;
 #pragma unroll
-    for (int n = 0; n < 4; ++n) {   // zero-weight neighbours may lie outside layer m - 1: not read
-        const double h = I.sw[n] > 0.0 ? Hprev[(u - (n & 1)) * wvp + (v - (n >> 1))] : 0.0;
+    for (int n = 0; n < 4; ++n) {
+        const double h = I.sw[n] > 0.0 ? Hprev[(u - (n & 1)) * rp.wv + (v - (n >> 1))] : 0.0;
         I.thick[n] = h > 0.0;
         I.f[n] = I.thick[n] ? h : X.inv_tw;
         const double g = I.thick[n] ? X.inv_s0 : -h * X.inv_tw;
@@ -1240,6 +1255,25 @@ __host__ __device__ __forceinline__ void layer_rate_adjoint(const TabNode *T, co
     *g_in = gi;
     *nbar_extra = (gd - gi) * X.alpha * I.ds;
     *gG = gbar * k * D;
+}
+
+// The rate's coefficients of a cell with a rate for the adjoint, from its
+// entry and in-cell optical depths (a = sigma0 N_in, dt = sigma0 dN) and r2:
+// with k = -1 / r2 (the source's Q coef factored out), dGamma/dN_in =
+// coef c[0], dGamma/d(dN) - dGamma/dN_in = coef c[1] and Gamma = coef c[2].
+// The same FP64 derivatives as layer_rate_adjoint, taken once in the forward
+// when the columns are kept, so that the adjoint only scales them by
+// coef dL/dGamma.
+__host__ __device__ __forceinline__ void layer_rate_coefs(const TabNode *T, const double *m64,
+                                                          const TabParams &tp, double sigma0, double a,
+                                                          double dt, int r2, double c[3])
+{
+    double D, Da, Ddt;
+    rate_derivs64(T, m64, tp, a, dt, &D, &Da, &Ddt);
+    const double k = -rcp_f64((double)r2);
+    c[0] = k * Da * sigma0;
+    c[1] = k * (Ddt - Da) * sigma0;
+    c[2] = k * D;
 }
 
 // Reverse-mode update of layer cell (u, v) of layer m through the

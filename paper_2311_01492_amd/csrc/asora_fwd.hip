@@ -43,6 +43,8 @@ struct FwdArgs {
     char *keep;             // layer pieces: column records, per (source, pyramid); NULL = none
     size_t keep_piece_bytes;
     long keep_cap;          // cells (and listed cells) per pyramid record
+    size_t keep_rk_off;     // offset of the rate coefficients in a kept record
+    const double *m64;      // FP64 node slopes of the table (rate coefficients of kept records)
 };
 
 struct Lds {
@@ -333,9 +335,45 @@ __global__ __launch_bounds__(1024) void fwd_wave(FwdArgs A)
 // through the same per-wave queue as the shell sweep.  With KEEP the sweep
 // also writes the pyramid's column record (the cells' layer-buffer entries and
 // the chunks' masks of cells with a rate) for a later adjoint.
+// The rate queue of the layer kernel: as RateQueue, with the in-cell optical
+// depth in FP64 (the rate coefficients of kept records are FP64 derivatives
+// taken at the same point as the adjoint's).
+struct LayerQueue {
+    double *ta;     // entry optical depth
+    double *dt;     // in-cell optical depth
+    uint32_t *cp;   // cell index
+    int *r2;        // squared distance (cells)
+};
+
+// One batch of queued cells: the rate added to Gamma and, with KEEP, the
+// rate's coefficients for the adjoint stored in the record at the cells'
+// places in the order of evaluation (head + lane).
+template <bool KEEP>
+__device__ __forceinline__ void layer_rate_batch(const FwdArgs &A, const TabNode *T, const LayerQueue &Qa,
+                                                 int head, int lane, double coef, double *acc,
+                                                 const LayerRecord &rec)
+{
+    const int pos = (head + lane) & (kQueue - 1);
+    const double ta = Qa.ta[pos], dt = Qa.dt[pos];
+    const int r2 = Qa.r2[pos];
+    const float nd = neg_divdiff(T, A.tp, ta, dt);
+    if (nd > 0.f) {
+        const double G = coef * (double)(nd * rcp_approx((float)r2));
+        unsafeAtomicAdd(&acc[Qa.cp[pos]], G);
+    }
+    if (KEEP) {
+        double c[3];
+        layer_rate_coefs(T, A.m64, A.tp, A.sigma0, ta, dt, r2, c);
+        const long q = head + lane;
+        rec.rk[q] = c[0];
+        rec.rk[A.keep_cap + q] = c[1];
+        rec.rk[2 * A.keep_cap + q] = c[2];
+    }
+}
+
 template <bool KEEP>
 __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *lay,
-                                  const RateQueue &Qa, int src, int p, int lane)
+                                  const LayerQueue &Qa, int src, int p, int lane)
 {
     const int N = A.N;
     const int si = A.ijk[3 * src], sj = A.ijk[3 * src + 1], sk = A.ijk[3 * src + 2];
@@ -363,7 +401,9 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
     const double coef = Q * A.coef_unit;
     const int S = A.lay_S;
     LayerRecord rec;
-    if (KEEP) rec = layer_record_at(A.keep + ((size_t)src * 24 + p) * A.keep_piece_bytes, A.keep_cap);
+    if (KEEP)
+        rec = layer_record_at(A.keep + ((size_t)src * 24 + p) * A.keep_piece_bytes, A.keep_cap,
+                              A.keep_rk_off);
 
     if (p == 3 * 0 + 2 && lane == 0) {   // the source cell, once per source
         const double G = source_cell_rate(T, A.tp, A.sigma0, A.alpha, Q, n_s);
@@ -418,7 +458,7 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
             tail += __popcll(mask);
             if (tail - head >= 64) {
                 wave_sync();
-                rate_batch(A, T, Qa, head, lane, coef, acc);
+                layer_rate_batch<KEEP>(A, T, Qa, head, lane, coef, acc, rec);
                 head += 64;
             }
             wave_sync();
@@ -428,9 +468,10 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
     }
     if (tail > head) {
         wave_sync();
-        if (lane < tail - head) rate_batch(A, T, Qa, head, lane, coef, acc);
+        if (lane < tail - head) layer_rate_batch<KEEP>(A, T, Qa, head, lane, coef, acc, rec);
         wave_sync();
     }
+    if (KEEP && lane == 0) ((uint64_t *)rec.rk)[3 * A.keep_cap] = (uint64_t)tail;   // cells with a rate
 }
 
 // TLDS: the table is copied to LDS once per work-group; otherwise the rate
@@ -451,9 +492,9 @@ __global__ __launch_bounds__(1024) void fwd_layer(FwdArgs A)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
     char *region = smem + (TLDS ? (size_t)A.tp.n * sizeof(TabNode) : 0) + (size_t)wave * A.region_bytes;
-    RateQueue Qa;
+    LayerQueue Qa;
     Qa.ta = (double *)region;
-    Qa.dt = (float *)(Qa.ta + kQueue);
+    Qa.dt = Qa.ta + kQueue;
     Qa.cp = (uint32_t *)(Qa.dt + kQueue);
     Qa.r2 = (int *)(Qa.cp + kQueue);
     double *lay = (double *)(Qa.r2 + kQueue);
@@ -478,7 +519,7 @@ __global__ __launch_bounds__(1024) void fwd_layer(FwdArgs A)
 // buffer.
 size_t layer_region_bytes(int S)
 {
-    const size_t b = (size_t)kQueue * (sizeof(double) + sizeof(float) + sizeof(uint32_t) + sizeof(int)) +
+    const size_t b = (size_t)kQueue * (2 * sizeof(double) + sizeof(uint32_t) + sizeof(int)) +
                      (size_t)S * S * sizeof(double);
     return (b + 15) & ~(size_t)15;
 }
@@ -814,6 +855,8 @@ static FwdArgs make_args(const FwdLaunch &F)
     A.keep = F.keep;
     A.keep_piece_bytes = F.keep_piece_bytes;
     A.keep_cap = F.keep_cap;
+    A.keep_rk_off = F.keep_rk_off;
+    A.m64 = F.m64;
     A.ijk = F.ijk;
     A.Q = F.Q;
     A.R = F.R;

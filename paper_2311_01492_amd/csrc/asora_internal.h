@@ -42,6 +42,8 @@ struct FwdLaunch {
     char *keep;             // layer pieces: column records per (source, pyramid), or NULL
     size_t keep_piece_bytes;
     long keep_cap;
+    size_t keep_rk_off;     // offset of the rate coefficients in a kept record
+    const double *m64;      // FP64 node slopes of the table
     int tab_lds;            // layer pieces: table in LDS (1) or read through the caches (0)
 };
 
@@ -98,6 +100,7 @@ struct AdjLaunch {
     double *nbar_T;
     const char *kept;      // layer pieces: column records kept by the forward, or NULL
     size_t rec_piece_bytes;   // bytes of one pyramid's column record
+    size_t rec_rk_off;        // kept records: offset of the rate coefficients
     long rec_cap;             // cells (and listed cells) per pyramid record
     bool split;               // layer pieces: rate terms of dense chunks in the reverse pass
 };

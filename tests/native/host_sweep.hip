@@ -172,13 +172,16 @@ extern "C" int hc_raytrace(int N, double alpha, double sigma0, int n, double lg_
 // first, every chunk reading layer m - 1 from the in-place buffer before it
 // writes layer m.  Adds the rates to acc (when acc != NULL) and, when rec is
 // given, fills the column record as the kernels do (exit columns in rectangle
-// order, listed cells in chunk and lane order).  Returns -6 if a neighbour of
-// non-zero weight is read from a slot that does not hold layer m - 1, -8 if a
-// cell falls outside the S x S layer buffer.
+// order, listed cells in chunk and lane order; with rec->rk the rate
+// coefficients of the cells with a rate in this order of evaluation, and
+// their number after the three arrays of cap entries).  Returns -6 if a
+// neighbour of non-zero weight is read from a slot that does not hold layer
+// m - 1, -8 if a cell falls outside the S x S layer buffer.
 static int layer_forward_piece(const LayerPiece &L, const LayerX &X, int Rsq, const TabNode *T,
-                               const TabParams &tp, double coef, int S, double *lay, int *lay_id,
-                               double *acc, double *coldens, int N, LayerRecord *rec)
+                               const double *m64, const TabParams &tp, double coef, int S, double *lay,
+                               int *lay_id, double *acc, double *coldens, int N, LayerRecord *rec, long cap)
 {
+    long nlit = 0;
     const int Mx = std::min(isqrt_floor(Rsq), L.ext_d);
     long off = 0, choff = 0;
     for (int m = 1; m <= Mx; ++m) {
@@ -218,16 +221,24 @@ static int layer_forward_piece(const LayerPiece &L, const LayerX &X, int Rsq, co
                 const double ta = X.sigma0 * lc[lane].Nin;
                 if (ta >= tp.tau_hi) continue;
                 mask |= 1ull << lane;
+                const double dt = X.sigma0 * lc[lane].dN;
                 if (acc) {
-                    const float nd = neg_divdiff(T, tp, ta, (double)(float)(X.sigma0 * lc[lane].dN));
+                    const float nd = neg_divdiff(T, tp, ta, dt);
                     if (nd > 0.f) acc[lc[lane].cp] += coef * (double)(nd * rcp_approx((float)lc[lane].r2));
                 }
+                if (rec && rec->rk) {
+                    double k[3];
+                    layer_rate_coefs(T, m64, tp, X.sigma0, ta, dt, lc[lane].r2, k);
+                    for (int i = 0; i < 3; ++i) rec->rk[i * cap + nlit] = k[i];
+                }
+                ++nlit;
             }
             if (rec) rec->lit[choff + c] = mask;
         }
         off += r.total;
         choff += nch;
     }
+    if (rec && rec->rk) ((uint64_t *)rec->rk)[3 * cap] = (uint64_t)nlit;
     return 0;
 }
 
@@ -303,9 +314,9 @@ extern "C" int hc_raytrace_layer(int N, double alpha, double sigma0, int n, doub
             const LayerX X = host_layer_x(H, L, N, alpha, sigma0, tau_w, reading, cs);
             std::fill(lay.begin(), lay.end(), 0.0);
             std::fill(lay_id.begin(), lay_id.end(), -1);
-            const int st = layer_forward_piece(L, X, Rsq, H.T.data(), H.tp, Q[s] * coef_unit, H.S, lay.data(),
-                                               lay_id.data(), L.transposed ? gT.data() : gacc, coldens, N,
-                                               nullptr);
+            const int st = layer_forward_piece(L, X, Rsq, H.T.data(), H.m64.data(), H.tp, Q[s] * coef_unit,
+                                               H.S, lay.data(), lay_id.data(), L.transposed ? gT.data() : gacc,
+                                               coldens, N, nullptr, H.cap);
             if (st) return st;
         }
     }
@@ -324,17 +335,21 @@ extern "C" int hc_raytrace_layer(int N, double alpha, double sigma0, int n, doub
 // terms of its cells with a rate, and pushing to its layer m - 1 neighbours,
 // whose entries it reads from the record.  dL/dn_HI of pyramids
 // with dominant axis k goes through a [k][i][j] buffer as on the GPU.
-// split != 0: chunks with at least kDenseChunk cells with a rate evaluate
-// them in (R), as the kernel's split form; else all are gathered in (G).
+// mode 1: chunks with at least kDenseChunk cells with a rate evaluate them in
+// (R), as the kernel's split form; 0: all are gathered in (G); 2: the forward
+// pass keeps the rate coefficients in the record, as a forward with kept
+// records does, and (R) reads them (no (G)).
 // Returns -6 if a neighbour of non-zero weight is not an active cell of layer
-// m - 1, -7 if a chunk mask marks an inactive lane.
+// m - 1, -7 if a chunk mask marks an inactive lane, -9 if (mode 2) the count
+// of cells with a rate disagrees with the chunk masks.
 extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n, double lg_lo,
                                       double lg_hi, const double *P, const double *dP, double tau_w,
                                       int reading, const float *nH, const float *xHI, long nsrc,
                                       const int32_t *ijk, const double *Q, const float *R,
-                                      const double *gbar, double *nbar, double *qbar, int split)
+                                      const double *gbar, double *nbar, double *qbar, int mode)
 {
-    const int dense_at = split ? kDenseChunk : 65;
+    const int dense_at = mode == 1 ? kDenseChunk : 65;
+    const bool kept = mode == 2;
     HostLayerSetup H;
     host_layer_setup(H, N, n, lg_lo, lg_hi, P, dP, nH, xHI, nsrc, R);
     const long n3 = (long)N * N * N;
@@ -346,8 +361,8 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
     const size_t SS = (size_t)S * S;
     std::vector<double> cols(SS), abar(SS), gin(H.cap);
     std::vector<int> cols_id(SS);
-    std::vector<char> recmem(layer_record_bytes(H.cap, H.Mcap));
-    LayerRecord rec = layer_record_at(recmem.data(), H.cap);
+    std::vector<char> recmem(layer_record_bytes(H.cap, H.Mcap, kept));
+    LayerRecord rec = layer_record_at(recmem.data(), H.cap, kept ? layer_record_bytes(H.cap, H.Mcap, false) : 0);
     const double coef_unit = sigma0 / (4.0 * M_PI * alpha * alpha);
     for (long s = 0; s < nsrc; ++s) {
         qbar[s] = 0.0;
@@ -365,8 +380,8 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
             // (F)
             std::fill(cols.begin(), cols.end(), 0.0);
             std::fill(cols_id.begin(), cols_id.end(), -1);
-            int st = layer_forward_piece(L, X, Rsq, H.T.data(), H.tp, coef, S, cols.data(), cols_id.data(),
-                                         nullptr, nullptr, N, &rec);
+            int st = layer_forward_piece(L, X, Rsq, H.T.data(), H.m64.data(), H.tp, coef, S, cols.data(),
+                                         cols_id.data(), nullptr, nullptr, N, &rec, H.cap);
             if (st) return st;
             // (G)
             long off = 0, choff = 0;
@@ -376,7 +391,7 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
                 const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m >= 2 ? m - 1 : 1);
                 for (int c = 0; c < nch; ++c) {
                     const uint64_t litmask = rec.lit[choff + c];
-                    if (__builtin_popcountll(litmask) >= dense_at) continue;   // left to (R)
+                    if (kept || __builtin_popcountll(litmask) >= dense_at) continue;   // left to (R)
                     for (int lane = 0; lane < 64; ++lane) {
                         if (!((litmask >> lane) & 1)) continue;
                         const int g = c * 64 + lane;
@@ -385,7 +400,7 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
                         if (g >= r.total || w.u * w.u + w.v * w.v > r.rem) return -7;
                         const double *Hprev = rec.h + (m >= 2 ? off - rp.total : 0);
                         LayerInterp I;
-                        layer_interp(L, X, m, w.u, w.v, Hprev, rp.wv, I);
+                        layer_interp(L, X, m, w.u, w.v, Hprev, rp, I);
                         double gi = 0.0;
                         const double g_ = gb[I.cp];
                         if (g_ != 0.0) {
@@ -403,7 +418,9 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
             }
             // (R)
             std::fill(abar.begin(), abar.end(), 0.0);
+            long lit_end = kept ? (long)((const uint64_t *)rec.rk)[3 * H.cap] : 0;   // with a rate, layers <= m
             for (int m = Mx; m >= 1; --m) {
+                long run = 0;
                 const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
                 const int nch = (r.total + 63) / 64;
                 off -= r.total;   // first cell of layer m
@@ -418,6 +435,7 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
                     int uu[64], vv[64];
                     double Tin[64];
                     const uint64_t litmask = rec.lit[choff + c];
+                    run += __builtin_popcountll(litmask);
                     for (int lane = 0; lane < 64; ++lane) {
                         uu[lane] = wk[lane].u;
                         vv[lane] = wk[lane].v;
@@ -427,11 +445,11 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
                     }
                     for (int lane = 0; lane < 64; ++lane)
                         if (act[lane]) abar[(size_t)uu[lane] * S + vv[lane]] = 0.0;
-                    const bool dense = __builtin_popcountll(litmask) >= dense_at;
+                    const bool dense = !kept && __builtin_popcountll(litmask) >= dense_at;
                     for (int lane = 0; lane < 64; ++lane) {
                         const bool lit = (litmask >> lane) & 1;
-                        if (lit && !dense) Tin[lane] += gin[off + c * 64 + lane];
-                        if (!act[lane] || (Tin[lane] == 0.0 && !(lit && dense))) continue;
+                        if (lit && !dense && !kept) Tin[lane] += gin[off + c * 64 + lane];
+                        if (!act[lane] || (Tin[lane] == 0.0 && !(lit && (dense || kept)))) continue;
                         const int u = uu[lane], v = vv[lane];
                         if (m > 1) {   // neighbours of non-zero weight: active cells of layer m - 1
                             const bool a0 = u > 0, a1 = u < m, b0 = v > 0, b1 = v < m;
@@ -443,8 +461,15 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
                             }
                         }
                         LayerInterp I;
-                        layer_interp(L, X, m, u, v, Hprev, rp.wv, I);
+                        layer_interp(L, X, m, u, v, Hprev, rp, I);
                         double extra = 0.0;
+                        if (lit && kept) {   // the coefficients at the cell's place in the forward's order
+                            const long q = lit_end - run + __builtin_popcountll(litmask & ((1ull << lane) - 1));
+                            const double gbc = gb[I.cp] * coef;
+                            Tin[lane] += gbc * rec.rk[q];
+                            extra = gbc * rec.rk[H.cap + q] * X.alpha * I.ds;
+                            qb += gbc * rec.rk[2 * H.cap + q];
+                        }
                         if (lit && dense && gb[I.cp] != 0.0) {
                             double gi, gG;
                             layer_rate_adjoint(H.T.data(), H.m64.data(), H.tp, X, coef, I, X.nHI[I.cp], gb[I.cp],
@@ -460,7 +485,9 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
                         nb_src += lr[lane].nbar_src;
                     }
                 }
+                lit_end -= run;
             }
+            if (kept && lit_end != 0) return -9;   // the count of cells with a rate does not add up
         }
         double nb1, q1;
         source_cell_adjoint(H.T.data(), H.m64.data(), H.tp, sigma0, alpha, Q[s], H.nhi[cs], gbar[cs], &nb1, &q1);

@@ -106,10 +106,11 @@ def rows(N, type_, piece, Rsq, q):
 
 
 def raytrace_grad(N, cell_cm, sigma0, table, n_H, x_HI, ijk, Q, R, gbar, tau_w=0.6, reading=0,
-                  type_force=-1, R_whole=10.0, R_oct=30.0, layers=False, split=True):
+                  type_force=-1, R_whole=10.0, R_oct=30.0, layers=False, split=True, kept=False):
     """(dL/dn_H, dL/dx_HI, dL/dQ) for dL/dGamma = gbar (FP64); layers: every
     source as layer pyramids, the rate terms of dense chunks in the reverse
-    pass (split) or all gathered first."""
+    pass (split) or all gathered first, or (kept) taken from coefficients the
+    forward pass stored, as with records kept by the forward."""
     lib = load()
     P, dP = np.ascontiguousarray(table.P, np.float64), np.ascontiguousarray(table.dP, np.float64)
     nH = np.ascontiguousarray(n_H, np.float32)
@@ -123,7 +124,8 @@ def raytrace_grad(N, cell_cm, sigma0, table, n_H, x_HI, ijk, Q, R, gbar, tau_w=0
     if layers:
         st = lib.hc_raytrace_layer_grad(N, cell_cm, sigma0, len(P), table.lg_lo, table.lg_hi, _p(P),
                                         _p(dP), float(tau_w), reading, _p(nH), _p(xH), len(Q), _p(ijk),
-                                        _p(Q), _p(R), _p(gb), _p(nbar), _p(qbar), 1 if split else 0)
+                                        _p(Q), _p(R), _p(gb), _p(nbar), _p(qbar),
+                                        2 if kept else (1 if split else 0))
     else:
         st = lib.hc_raytrace_grad(N, cell_cm, sigma0, len(P), table.lg_lo, table.lg_hi, _p(P), _p(dP),
                                   float(tau_w), reading, _p(nH), _p(xH), len(Q), _p(ijk), _p(Q), _p(R),

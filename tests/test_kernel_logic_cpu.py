@@ -162,8 +162,9 @@ def test_row_enumeration_matches_brute_force(N):
                 assert set(got) == want          # ghosts duplicate cells, nothing missing or extra
 
 
-@pytest.mark.parametrize("kind", [dict(type_force=-1)] + KINDS + [dict(layers=True, split=False)],
-                         ids=["by-radius"] + KIND_IDS + ["layers-gathered"])
+@pytest.mark.parametrize("kind", [dict(type_force=-1)] + KINDS +
+                         [dict(layers=True, split=False), dict(layers=True, kept=True)],
+                         ids=["by-radius"] + KIND_IDS + ["layers-gathered", "layers-kept"])
 @pytest.mark.parametrize("tau_w,reading", [(0.6, 0), (math.inf, 0), (0.6, 1)])
 def test_adjoint_matches_oracle_reverse(bb, kind, tau_w, reading):
     """The library's per-cell adjoint, driven serially over the reversed
@@ -196,10 +197,10 @@ def test_layer_adjoint_extent_clip_and_wrap(bb):
         on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
                                           w.src.R, gbar)
         from tests.parity import assert_grad_parity
-        for split in (True, False):
+        for split, kept in ((True, False), (False, False), (False, True)):
             hn, hx, hq = hostsweep.raytrace_grad(w.N, w.cell_cm, oracle.SIGMA0, bb, w.n_H, w.x_HI,
                                                  w.src.ijk, w.src.Q, w.src.R, gbar, layers=True,
-                                                 split=split)
+                                                 split=split, kept=kept)
             assert_grad_parity(hn, on, 1e-5, what="dL/dn_H")
             assert_grad_parity(hx, ox, 1e-5, what="dL/dx_HI")
             np.testing.assert_allclose(hq, oq, rtol=1e-6)
