@@ -310,10 +310,17 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
     const int Mx = min(isqrt_floor(Rsq), L.ext_d);
     constexpr int dense_at = SPLIT ? kDenseChunk : 65;   // popcount of a dense chunk
 
-    // ---- (F)
-    if (!KEPT) {
+    // ---- (F), up to the first layer whose cells all leave opaque
+    // (layer_opaque): later layers have no rate and no adjoint.  With kept
+    // records the forward found that layer.
+    int Mt = Mx;   // the last layer (G) and (R) visit
+    if (KEPT) {
+        const int ml = (int)((const uint64_t *)rec.rk)[3 * A.rec_cap + 1];
+        Mt = ml < Mx ? ml : Mx;
+    } else {
         for (int k = lane; k < S * S; k += 64) buf[k] = 0.0;   // finite everywhere it is read
         wave_sync();
+        const double opaque = layer_opaque(A.tp.tau_hi);
         long off = 0, choff = 0;
         for (int m = 1; m <= Mx; ++m) {
             const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
@@ -321,6 +328,7 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
             const int nch = (r.total + 63) / 64;
             RectWalk w;
             w.init(r, (nch - 1) * 64 + lane);
+            bool opq = true;   // every cell of layer m so far leaves opaque
             for (int c = nch - 1; c >= 0; --c, w.down()) {
                 const int g = c * 64 + lane;
                 const int u = w.u, v = w.v;
@@ -328,6 +336,7 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
                 const int pos = mul24(u, S) + v;
                 LayerCell lc;
                 lc.Nin = 0.0;
+                lc.Nout = 0.0;
                 lc.owned = false;
                 if (act) {
                     const uint32_t cp = layer_cp(L, N, m, u, v);
@@ -342,10 +351,15 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
                 }
                 const uint64_t mask = __ballot(lit);
                 if (lane == 0) rec.lit[choff + c] = mask;
+                opq = opq && __ballot(act && !(A.sigma0 * lc.Nout >= opaque)) == 0;
                 wave_sync();
             }
             off += r.total;
             choff += nch;
+            if (opq) {
+                Mt = m;
+                break;
+            }
         }
         wave_sync_global();
     }
@@ -354,7 +368,7 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
     double nb_src = 0.0, qb = 0.0;
     long off = 0, choff = 0;
     if (KEPT) {
-        for (int m = 1; m <= Mx; ++m) {
+        for (int m = 1; m <= Mt; ++m) {
             const int t = layer_rect(L.ext_u, L.ext_v, Rsq, m).total;
             off += t;
             choff += (t + 63) / 64;
@@ -384,7 +398,7 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
                 gin[k] = gi;
             }
         };
-        for (int m = 1; m <= Mx; ++m) {
+        for (int m = 1; m <= Mt; ++m) {
             const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
             const int nch = (r.total + 63) / 64;
             uint64_t masks = 0;
@@ -427,7 +441,7 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
         // from the first, a layer's chunks from the last, a chunk's lanes in
         // order; lit_end counts those of layers <= m
         long lit_end = KEPT ? (long)((const uint64_t *)rec.rk)[3 * A.rec_cap] : 0;
-        for (int m = Mx; m >= 1; --m) {
+        for (int m = Mt; m >= 1; --m) {
             const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
             const int nch = (r.total + 63) / 64;
             off -= r.total;    // first cell of layer m in the record

@@ -893,7 +893,8 @@ __host__ __device__ inline long layer_piece_capacity(int Rsq, const Extent &ex)
 // A record kept by the forward also holds, for the cells with a rate in the
 // order the forward evaluated them, the rate's coefficients for the adjoint
 // (layer_rate_coefs) in three arrays of cap entries, followed by the number
-// of such cells.
+// of such cells and the last layer the adjoint has to visit (layer_opaque):
+// entries and masks of later layers are not written.
 struct LayerRecord {
     double *h;        // [cap] layer-buffer entries of the cells
     uint64_t *lit;    // [cap / 64 + Mcap + 1] rate masks, one per chunk
@@ -906,7 +907,7 @@ __host__ __device__ __forceinline__ size_t layer_record_bytes(long cap, int Mcap
 {
     size_t b = (size_t)cap * sizeof(double) + ((size_t)cap / 64 + Mcap + 1) * sizeof(uint64_t);
     b = (b + 255) & ~(size_t)255;
-    if (coefs) b += ((3 * (size_t)cap + 1) * sizeof(double) + 255) & ~(size_t)255;
+    if (coefs) b += ((3 * (size_t)cap + 2) * sizeof(double) + 255) & ~(size_t)255;
     return b;
 }
 
@@ -961,6 +962,18 @@ __host__ __device__ __forceinline__ double layer_entry(const LayerX &X, double M
 {
     const double t = X.sigma0 * M;
     return (X.tau_w > 0.f && t > (double)X.tau_w) ? rcp_f64(t) : -M;
+}
+
+// A layer whose every cell leaves with sigma0 N_out >= layer_opaque(tau_hi)
+// ends the pyramid's cells with a rate: a cell's entry column is a convex
+// combination of its neighbours' exit columns (weights s / max(sigma0 M,
+// tau_w) >= 0) and its exit column adds dN >= 0, so every later cell enters
+// with sigma0 N_in >= tau_hi (the margin covers the rounding of tens of
+// layers), has no rate, and receives no adjoint.  The forward still sweeps
+// those cells; the adjoint need not.
+__host__ __device__ __forceinline__ double layer_opaque(double tau_hi)
+{
+    return tau_hi * (1.0 + 1e-12);
 }
 
 struct LayerCell {

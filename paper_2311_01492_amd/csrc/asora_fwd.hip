@@ -345,9 +345,11 @@ struct LayerQueue {
     int *r2;        // squared distance (cells)
 };
 
-// One batch of queued cells: the rate added to Gamma and, with KEEP, the
-// rate's coefficients for the adjoint stored in the record at the cells'
-// places in the order of evaluation (head + lane).
+// One batch of queued cells: the rate added to Gamma.  Without KEEP the
+// rate comes from the FP32 divided difference; with KEEP from the FP64 one
+// that also gives the rate's coefficients for the adjoint (one evaluation
+// instead of two), which are stored in the record at the cells' places in
+// the order of evaluation (head + lane).
 template <bool KEEP>
 __device__ __forceinline__ void layer_rate_batch(const FwdArgs &A, const TabNode *T, const LayerQueue &Qa,
                                                  int head, int lane, double coef, double *acc,
@@ -356,14 +358,17 @@ __device__ __forceinline__ void layer_rate_batch(const FwdArgs &A, const TabNode
     const int pos = (head + lane) & (kQueue - 1);
     const double ta = Qa.ta[pos], dt = Qa.dt[pos];
     const int r2 = Qa.r2[pos];
-    const float nd = neg_divdiff(T, A.tp, ta, dt);
-    if (nd > 0.f) {
-        const double G = coef * (double)(nd * rcp_approx((float)r2));
-        unsafeAtomicAdd(&acc[Qa.cp[pos]], G);
-    }
-    if (KEEP) {
+    if (!KEEP) {
+        const float nd = neg_divdiff(T, A.tp, ta, dt);
+        if (nd > 0.f) {
+            const double G = coef * (double)(nd * rcp_approx((float)r2));
+            unsafeAtomicAdd(&acc[Qa.cp[pos]], G);
+        }
+    } else {
         double c[3];
         layer_rate_coefs(T, A.m64, A.tp, A.sigma0, ta, dt, r2, c);
+        const double G = coef * c[2];   // Gamma = coef (-D) / r2
+        if (G != 0.0) unsafeAtomicAdd(&acc[Qa.cp[pos]], G);
         const long q = head + lane;
         rec.rk[q] = c[0];
         rec.rk[A.keep_cap + q] = c[1];
@@ -416,12 +421,16 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
     int head = 0, tail = 0;
     long off = 0;     // first cell of layer m in the record
     long choff = 0;   // first chunk of layer m in the record
+    const double opaque = layer_opaque(A.tp.tau_hi);
+    bool rec_on = KEEP;   // the record is written up to the first opaque layer
+    int m_last = Mx;      // the last layer the adjoint visits
     for (int m = 1; m <= Mx; ++m) {
         const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
         const double inv_m = rcp_f64((double)m);
         const int nch = (r.total + 63) / 64;
         RectWalk w;
         w.init(r, (nch - 1) * 64 + lane);
+        bool opq = true;   // every cell of layer m so far leaves opaque
         for (int c = nch - 1; c >= 0; --c, w.down()) {
             const int g = c * 64 + lane;
             const int u = w.u, v = w.v;
@@ -438,14 +447,17 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
             bool want = false;
             if (act) {
                 lay[pos] = lc.h;
-                if (KEEP) rec.h[off + g] = lc.h;
+                if (KEEP && rec_on) rec.h[off + g] = lc.h;
                 if (lc.owned) {
                     if (A.coldens) A.coldens[layer_std_index(L, N, m, u, v)] = lc.Nin;
                     want = A.sigma0 * lc.Nin < A.tp.tau_hi;
                 }
             }
             const uint64_t mask = __ballot(want);
-            if (KEEP && lane == 0) rec.lit[choff + c] = mask;
+            if (KEEP && rec_on) {
+                if (lane == 0) rec.lit[choff + c] = mask;
+                opq = opq && __ballot(act && !(A.sigma0 * lc.Nout >= opaque)) == 0;
+            }
             if (want) {
                 const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -465,13 +477,20 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
         }
         off += r.total;
         choff += nch;
+        if (rec_on && opq) {
+            rec_on = false;
+            m_last = m;
+        }
     }
     if (tail > head) {
         wave_sync();
         if (lane < tail - head) layer_rate_batch<KEEP>(A, T, Qa, head, lane, coef, acc, rec);
         wave_sync();
     }
-    if (KEEP && lane == 0) ((uint64_t *)rec.rk)[3 * A.keep_cap] = (uint64_t)tail;   // cells with a rate
+    if (KEEP && lane == 0) {
+        ((uint64_t *)rec.rk)[3 * A.keep_cap] = (uint64_t)tail;   // cells with a rate
+        ((uint64_t *)rec.rk)[3 * A.keep_cap + 1] = (uint64_t)m_last;
+    }
 }
 
 // TLDS: the table is copied to LDS once per work-group; otherwise the rate

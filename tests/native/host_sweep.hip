@@ -174,21 +174,30 @@ extern "C" int hc_raytrace(int N, double alpha, double sigma0, int n, double lg_
 // given, fills the column record as the kernels do (exit columns in rectangle
 // order, listed cells in chunk and lane order; with rec->rk the rate
 // coefficients of the cells with a rate in this order of evaluation, and
-// their number after the three arrays of cap entries).  Returns -6 if a
-// neighbour of non-zero weight is read from a slot that does not hold layer
-// m - 1, -8 if a cell falls outside the S x S layer buffer.
+// their number after the three arrays of cap entries).  The record stops
+// after the first layer whose cells all leave opaque (layer_opaque), as in the
+// kernels; *m_last (may be NULL) receives that layer (Mx if none).  Returns -6
+// if a neighbour of non-zero weight is read from a slot that does not hold
+// layer m - 1, -8 if a cell falls outside the S x S layer buffer, -10 if a
+// cell after an opaque layer has a rate.
 static int layer_forward_piece(const LayerPiece &L, const LayerX &X, int Rsq, const TabNode *T,
                                const double *m64, const TabParams &tp, double coef, int S, double *lay,
-                               int *lay_id, double *acc, double *coldens, int N, LayerRecord *rec, long cap)
+                               int *lay_id, double *acc, double *coldens, int N, LayerRecord *rec, long cap,
+                               int *m_last = nullptr)
 {
     long nlit = 0;
+    bool rec_on = rec != nullptr;
+    bool past_opaque = false;
+    const double opaque = layer_opaque(tp.tau_hi);
     const int Mx = std::min(isqrt_floor(Rsq), L.ext_d);
+    if (m_last) *m_last = Mx;
     long off = 0, choff = 0;
     for (int m = 1; m <= Mx; ++m) {
         const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
         const int nch = (r.total + 63) / 64;
         RectWalk wk[64];
         for (int lane = 0; lane < 64; ++lane) wk[lane].init(r, (nch - 1) * 64 + lane);
+        bool opq = true;
         for (int c = nch - 1; c >= 0; --c) {
             LayerCell lc[64];
             bool act[64];
@@ -215,7 +224,8 @@ static int layer_forward_piece(const LayerPiece &L, const LayerX &X, int Rsq, co
                 const int u = uu[lane], v = vv[lane];
                 lay[(size_t)u * S + v] = lc[lane].h;
                 lay_id[(size_t)u * S + v] = m;
-                if (rec) rec->h[off + c * 64 + lane] = lc[lane].h;
+                if (!(X.sigma0 * lc[lane].Nout >= opaque)) opq = false;
+                if (rec_on) rec->h[off + c * 64 + lane] = lc[lane].h;
                 if (!lc[lane].owned) continue;
                 if (coldens) coldens[layer_std_index(L, N, m, u, v)] = lc[lane].Nin;
                 const double ta = X.sigma0 * lc[lane].Nin;
@@ -233,12 +243,24 @@ static int layer_forward_piece(const LayerPiece &L, const LayerX &X, int Rsq, co
                 }
                 ++nlit;
             }
-            if (rec) rec->lit[choff + c] = mask;
+            if (rec_on) rec->lit[choff + c] = mask;
+            if (past_opaque && mask) return -10;   // a rate after an opaque layer
         }
         off += r.total;
         choff += nch;
+        if (opq && !past_opaque) {
+            past_opaque = true;
+            if (m_last) *m_last = m;
+        }
+        if (rec_on && opq) {
+            rec_on = false;
+            if (rec->rk) ((uint64_t *)rec->rk)[3 * cap + 1] = (uint64_t)m;
+        }
     }
-    if (rec && rec->rk) ((uint64_t *)rec->rk)[3 * cap] = (uint64_t)nlit;
+    if (rec && rec->rk) {
+        ((uint64_t *)rec->rk)[3 * cap] = (uint64_t)nlit;
+        if (rec_on) ((uint64_t *)rec->rk)[3 * cap + 1] = (uint64_t)Mx;
+    }
     return 0;
 }
 
@@ -346,8 +368,10 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
                                       double lg_hi, const double *P, const double *dP, double tau_w,
                                       int reading, const float *nH, const float *xHI, long nsrc,
                                       const int32_t *ijk, const double *Q, const float *R,
-                                      const double *gbar, double *nbar, double *qbar, int mode)
+                                      const double *gbar, double *nbar, double *qbar, int mode,
+                                      long *n_stopped)
 {
+    if (n_stopped) *n_stopped = 0;   // pieces whose adjoint stops before their last layer
     const int dense_at = mode == 1 ? kDenseChunk : 65;
     const bool kept = mode == 2;
     HostLayerSetup H;
@@ -380,12 +404,16 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
             // (F)
             std::fill(cols.begin(), cols.end(), 0.0);
             std::fill(cols_id.begin(), cols_id.end(), -1);
+            // unwritten parts of the record read as NaN entries and all-set masks
+            std::memset(recmem.data(), 0xff, recmem.size());
+            int Mt = Mx;   // the last layer (G) and (R) visit
             int st = layer_forward_piece(L, X, Rsq, H.T.data(), H.m64.data(), H.tp, coef, S, cols.data(),
-                                         cols_id.data(), nullptr, nullptr, N, &rec, H.cap);
+                                         cols_id.data(), nullptr, nullptr, N, &rec, H.cap, &Mt);
             if (st) return st;
+            if (n_stopped && Mt < Mx) ++*n_stopped;
             // (G)
             long off = 0, choff = 0;
-            for (int m = 1; m <= Mx; ++m) {
+            for (int m = 1; m <= Mt; ++m) {
                 const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
                 const int nch = (r.total + 63) / 64;
                 const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m >= 2 ? m - 1 : 1);
@@ -419,7 +447,7 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
             // (R)
             std::fill(abar.begin(), abar.end(), 0.0);
             long lit_end = kept ? (long)((const uint64_t *)rec.rk)[3 * H.cap] : 0;   // with a rate, layers <= m
-            for (int m = Mx; m >= 1; --m) {
+            for (int m = Mt; m >= 1; --m) {
                 long run = 0;
                 const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
                 const int nch = (r.total + 63) / 64;

@@ -58,8 +58,9 @@ def test_recorded_step_replays_match_eager(asora, bb, store):
         Q.copy_(torch.from_numpy(w.src.Q * scale))
         graph.launch()
         torch.cuda.synchronize()
-        # eager calls on the same inputs between replays
-        ge = ctx.raytrace(nH, xH, ijk, Q, R)
+        # eager calls on the same inputs between replays (the forward in the
+        # recorded mode: keeping records takes the rate from its FP64 form)
+        ge = ctx.raytrace(nH, xH, ijk, Q, R, store=store)
         en, ex, eq = ctx.backward(nH, xH, ijk, Q, R, gb)
         ctx.check()
         torch.testing.assert_close(gamma.view_as(ge), ge, rtol=1e-6, atol=0)
