@@ -35,6 +35,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ns per source-voxel (ASORA fwd, fwd+adjoint), batched vs plain, at 1e-5 rel err"
 HBM_PEAK_GBS = 8000.0
+# VALU issue: each SIMD issues one wave64 instruction per 4 cycles (16 lanes);
+# 256 CUs x 4 SIMDs at 2.4 GHz
+VALU_PEAK_PER_S = 256 * 4 * 2.4e9 / 4
 # algorithmic HBM bytes per source-voxel
 FWD_BYTES_PER_SV = 16.0   # n_H + x_HI reads (2 x FP32), Gamma read-modify-write (2 x FP32)
 ADJ_BYTES_PER_SV = 32.0   # n_H + x_HI (2 x FP32), dL/dGamma (FP64), dL/dn_HI read-modify-write (2 x FP64)
@@ -65,6 +68,10 @@ def kernel_sha() -> str:
 
 def pmc_file(workload: str) -> str:
     return os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.json")
+
+
+def valu_file(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"valu_issue_{workload}.json")
 
 
 # ---------------------------------------------------------------------------
@@ -139,6 +146,36 @@ def reduce_pmc(directory: str, workload: str):
     print(json.dumps(res))
 
 
+def reduce_sq(directory: str, workload: str):
+    """Mean SQ_INSTS_VALU (wave instructions) and SQ_WAVES per dispatch of
+    every sweep kernel, from rocprofv3 --pmc runs (CSV) found under
+    `directory` (any run that collected SQ_INSTS_VALU)."""
+    files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
+    table = {}
+    for p in files:
+        for k, v in _read_counter_csv(p).items():
+            for c, vals in v.items():
+                table.setdefault(k, {}).setdefault(c, []).extend(vals)
+    res = {"kernel_sha": kernel_sha(), "workload": workload, "valu_peak_per_s": VALU_PEAK_PER_S,
+           "kernels": {}}
+    for name, c in table.items():
+        k = name.split("(")[0].replace("void ", "").replace("asora::", "")
+        if not any(k.startswith(sub) for subs in KERNELS.values() for sub in subs):
+            continue
+        if "SQ_INSTS_VALU" not in c:
+            continue
+        v = c["SQ_INSTS_VALU"]
+        res["kernels"][k] = {"valu_insts_per_dispatch": sum(v) / len(v), "dispatches": len(v)}
+        if "SQ_WAVES" in c:
+            res["kernels"][k]["waves_per_dispatch"] = sum(c["SQ_WAVES"]) / len(c["SQ_WAVES"])
+    if not res["kernels"]:
+        raise SystemExit(f"no SQ_INSTS_VALU of a sweep kernel under {directory}")
+    os.makedirs(os.path.dirname(valu_file(workload)), exist_ok=True)
+    with open(valu_file(workload), "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res))
+
+
 # ---------------------------------------------------------------------------
 def cpu_baseline(w, budget_s: float = 12.0):
     """The FP64 oracle as it stands (forward, then reverse for
@@ -199,9 +236,14 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--reduce-pmc", metavar="DIR", help="reduce rocprofv3 counter CSVs and exit")
+    ap.add_argument("--reduce-sq", metavar="DIR",
+                    help="reduce rocprofv3 SQ counter CSVs (VALU instructions) and exit")
     args = ap.parse_args()
     if args.reduce_pmc:
         reduce_pmc(args.reduce_pmc, args.workload)
+        return
+    if args.reduce_sq:
+        reduce_sq(args.reduce_sq, args.workload)
         return
     if args.gpus != 1:
         print(f"bench.py: one GPU only; --gpus {args.gpus} is not supported (sources would shard "
@@ -335,6 +377,11 @@ def main():
         pmc = json.load(open(pmc_file(args.workload)))
         if pmc.get("kernel_sha") == kernel_sha() and pmc.get("workload") == args.workload:
             traffic = {k: v.get("hbm_bytes_per_dispatch") for k, v in pmc.get("kernels", {}).items()}
+    valu = {}
+    if os.path.exists(valu_file(args.workload)):
+        vj = json.load(open(valu_file(args.workload)))
+        if vj.get("kernel_sha") == kernel_sha() and vj.get("workload") == args.workload:
+            valu = {k: v.get("valu_insts_per_dispatch") for k, v in vj.get("kernels", {}).items()}
 
     # the dominant sweep kernels: layer pyramids (sweep 3) or shell pyramids;
     # the step's adjoint reads kept records or recomputes; the forward alone
@@ -352,10 +399,17 @@ def main():
 
     def roof(bytes_per_sv, sweep_ms, kernel, key):
         achieved = bytes_per_sv * work / (sweep_ms * 1e-3) / 1e9
-        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic.get(kernel),
-                "kernel": kernel, "launch_ms": sweep_ms,
-                "alg_bytes_per_source_voxel": bytes_per_sv, "source_voxels_per_launch": work}
+        r = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic.get(kernel),
+             "kernel": kernel, "launch_ms": sweep_ms,
+             "alg_bytes_per_source_voxel": bytes_per_sv, "source_voxels_per_launch": work}
+        # the limit that binds: VALU issue, from the kernel's counted wave
+        # instructions per dispatch (null when the counters are stale)
+        vi = valu.get(kernel)
+        r["valu_issue"] = None if vi is None else {
+            "insts_per_launch": vi, "achieved_per_s": vi / (sweep_ms * 1e-3), "peak_per_s": VALU_PEAK_PER_S,
+            "frac": vi / (sweep_ms * 1e-3) / VALU_PEAK_PER_S}
+        return r
 
     out = {
         "metric": METRIC, "value": ms * 1e6 / work, "unit": "ns per source-voxel", "n_gpus": 1,

@@ -369,9 +369,11 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
                                       int reading, const float *nH, const float *xHI, long nsrc,
                                       const int32_t *ijk, const double *Q, const float *R,
                                       const double *gbar, double *nbar, double *qbar, int mode,
-                                      long *n_stopped)
+                                      long *stats)
 {
-    if (n_stopped) *n_stopped = 0;   // pieces whose adjoint stops before their last layer
+    // stats (may be NULL): pieces whose adjoint stops before their last
+    // layer, cells in the layers the adjoint visits, cells of all layers
+    if (stats) stats[0] = stats[1] = stats[2] = 0;
     const int dense_at = mode == 1 ? kDenseChunk : 65;
     const bool kept = mode == 2;
     HostLayerSetup H;
@@ -410,7 +412,14 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
             int st = layer_forward_piece(L, X, Rsq, H.T.data(), H.m64.data(), H.tp, coef, S, cols.data(),
                                          cols_id.data(), nullptr, nullptr, N, &rec, H.cap, &Mt);
             if (st) return st;
-            if (n_stopped && Mt < Mx) ++*n_stopped;
+            if (stats) {
+                stats[0] += Mt < Mx;
+                for (int m = 1; m <= Mx; ++m) {
+                    const long t = layer_rect(L.ext_u, L.ext_v, Rsq, m).total;
+                    stats[1] += m <= Mt ? t : 0;
+                    stats[2] += t;
+                }
+            }
             // (G)
             long off = 0, choff = 0;
             for (int m = 1; m <= Mt; ++m) {

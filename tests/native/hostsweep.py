@@ -45,7 +45,7 @@ def load():
         lib.hc_raytrace_layer.argtypes = [i, d, d, i, d, d, p, p, d, i, p, p, l, p, p, p, p, p]
         lib.hc_raytrace_layer_grad.restype = i
         lib.hc_raytrace_layer_grad.argtypes = [i, d, d, i, d, d, p, p, d, i, p, p, l, p, p, p, p, p, p, i,
-                                               ctypes.POINTER(ctypes.c_long)]
+                                               p]
         lib.hc_rows.restype = i
         lib.hc_rows.argtypes = [i, i, i, i, i, p, p]
         _lib = lib
@@ -114,7 +114,8 @@ def raytrace_grad(N, cell_cm, sigma0, table, n_H, x_HI, ijk, Q, R, gbar, tau_w=0
     pass (split) or all gathered first, or (kept) taken from coefficients the
     forward pass stored, as with records kept by the forward.  stats (a dict,
     layers only) receives n_stopped: the pyramids whose adjoint stopped at an
-    opaque layer before their last."""
+    opaque layer before their last, and visited / total: cells (rectangle
+    slots) in the layers the adjoint visits / in all layers."""
     lib = load()
     P, dP = np.ascontiguousarray(table.P, np.float64), np.ascontiguousarray(table.dP, np.float64)
     nH = np.ascontiguousarray(n_H, np.float32)
@@ -126,13 +127,13 @@ def raytrace_grad(N, cell_cm, sigma0, table, n_H, x_HI, ijk, Q, R, gbar, tau_w=0
     nbar = np.zeros(N ** 3)
     qbar = np.zeros(len(Q))
     if layers:
-        n_stopped = ctypes.c_long(0)
+        st3 = np.zeros(3, np.int64)
         st = lib.hc_raytrace_layer_grad(N, cell_cm, sigma0, len(P), table.lg_lo, table.lg_hi, _p(P),
                                         _p(dP), float(tau_w), reading, _p(nH), _p(xH), len(Q), _p(ijk),
                                         _p(Q), _p(R), _p(gb), _p(nbar), _p(qbar),
-                                        2 if kept else (1 if split else 0), ctypes.byref(n_stopped))
+                                        2 if kept else (1 if split else 0), _p(st3))
         if stats is not None:
-            stats["n_stopped"] = n_stopped.value
+            stats.update(n_stopped=int(st3[0]), visited=int(st3[1]), total=int(st3[2]))
     else:
         st = lib.hc_raytrace_grad(N, cell_cm, sigma0, len(P), table.lg_lo, table.lg_hi, _p(P), _p(dP),
                                   float(tau_w), reading, _p(nH), _p(xH), len(Q), _p(ijk), _p(Q), _p(R),
