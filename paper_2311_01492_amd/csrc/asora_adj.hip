@@ -275,7 +275,7 @@ __device__ __forceinline__ uint64_t mask_of_chunk(uint64_t masks, int c)
 
 template <bool KEPT, bool SPLIT>
 __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *buf, int *qk, int *qm,
-                                    char *scratch, int src, int p, int lane)
+                                    double *qT, char *scratch, int src, int p, int lane)
 {
     const int N = A.N;
     const int si = A.ijk[3 * src], sj = A.ijk[3 * src + 1], sk = A.ijk[3 * src + 2];
@@ -309,6 +309,9 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
     double *gin = KEPT ? nullptr : (double *)(scratch + A.rec_piece_bytes);   // g_in by record cell
     const int Mx = min(isqrt_floor(Rsq), L.ext_d);
     constexpr int dense_at = SPLIT ? kDenseChunk : 65;   // popcount of a dense chunk
+    // (R) queues the cells with work into full batches, except in the split
+    // form (most cells have a rate there, and most lanes work anyway)
+    constexpr bool QUEUE = KEPT || !SPLIT;
 
     // ---- (F), up to the first layer whose cells all leave opaque
     // (layer_opaque): later layers have no rate and no adjoint.  With kept
@@ -449,6 +452,39 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
             // entries of layer m - 1 (its rectangle precedes layer m's)
             const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m >= 2 ? m - 1 : 1);
             const double *Hprev = rec.h + (m >= 2 ? off - rp.total : 0);
+            // a batch of queued cells of layer m; every slot a cell pushes to
+            // precedes it in (u, v) order, so its chunk was taken before the
+            // cell was queued
+            int qh = 0, qt = 0;
+            auto rbatch = [&](int count) {
+                if (lane < count) {
+                    const int q = (qh + lane) & (kAdjQueue - 1);
+                    const int g = qk[q], li = qm[q];
+                    double Tin = qT[q];
+                    int u, v;
+                    rect_cell(r, g, u, v);
+                    LayerInterp I;
+                    layer_interp(L, X, m, u, v, Hprev, rp, I);
+                    double nbx = 0.0;
+                    if (KEPT && li >= 0) {   // the rate's terms, from its coefficients
+                        const double gbc = gbar[I.cp] * coef;
+                        Tin += gbc * rec.rk[li];
+                        nbx = gbc * rec.rk[A.rec_cap + li] * X.alpha * I.ds;
+                        qb += gbc * rec.rk[2 * A.rec_cap + li];
+                    }
+                    LayerRev lr;
+                    layer_cell_reverse(X, m, I, Tin, lr);
+                    if (m >= 2) {
+#pragma unroll
+                        for (int n = 0; n < 4; ++n)
+                            if (lr.Mbar[n] != 0.0)
+                                atomicAdd(&buf[mul24(u - (n & 1), S) + (v - (n >> 1))], lr.Mbar[n]);
+                    }
+                    const double nb = lr.nbar + nbx;
+                    if (nb != 0.0) unsafeAtomicAdd(&nbar[lr.cp], nb);
+                    nb_src += lr.nbar_src;
+                }
+            };
             RectWalk w;
             w.init(r, lane);
             uint64_t masks = 0;
@@ -467,40 +503,41 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
                     buf[mul24(u, S) + v] = 0.0;
                 }
                 wave_sync();
-                if (KEPT && (__ballot(Tin != 0.0) | litmask)) {
-                    if (Tin != 0.0 || lit) {
-                        // the rate's coefficients and dL/dGamma, read with the entries
-                        double k0 = 0.0, k1 = 0.0, k2 = 0.0, gbc = 0.0;
-                        if (lit) {
-                            long q = lit_end - run +
-                                     (long)__builtin_amdgcn_mbcnt_hi((uint32_t)(litmask >> 32),
-                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)litmask, 0u));
+                if (QUEUE) {
+                    // the cells with work go to the queue with their entry-column
+                    // adjoint (gathered form: with the rate's g_in from (G)) and,
+                    // with kept records, the place of their rate's coefficients;
+                    // full batches run with every lane busy
+                    if (!KEPT && lit) Tin += gin[off + g];
+                    const bool need = Tin != 0.0 || (KEPT && lit);
+                    const uint64_t nm = __ballot(need);
+                    if (need) {
+                        const int q = (qt + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(nm >> 32),
+                                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)nm, 0u))) &
+                                      (kAdjQueue - 1);
+                        long li = -1;
+                        if (KEPT && lit) {
+                            li = lit_end - run +
+                                 (long)__builtin_amdgcn_mbcnt_hi((uint32_t)(litmask >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)litmask, 0u));
                             // in range for any record contents (records of inputs changed since the
                             // forward give wrong gradients, never reads outside the record)
-                            q = q < 0 ? 0 : (q >= A.rec_cap ? A.rec_cap - 1 : q);
-                            k0 = rec.rk[q];
-                            k1 = rec.rk[A.rec_cap + q];
-                            k2 = rec.rk[2 * A.rec_cap + q];
-                            gbc = gbar[layer_cp(L, N, m, u, v)] * coef;
+                            li = li < 0 ? 0 : (li >= A.rec_cap ? A.rec_cap - 1 : li);
                         }
-                        LayerInterp I;
-                        layer_interp(L, X, m, u, v, Hprev, rp, I);
-                        Tin += gbc * k0;
-                        qb += gbc * k2;
-                        LayerRev lr;
-                        layer_cell_reverse(X, m, I, Tin, lr);
-                        if (m >= 2) {
-#pragma unroll
-                            for (int n = 0; n < 4; ++n)
-                                if (lr.Mbar[n] != 0.0)
-                                    atomicAdd(&buf[mul24(u - (n & 1), S) + (v - (n >> 1))], lr.Mbar[n]);
-                        }
-                        const double nb = lr.nbar + gbc * k1 * X.alpha * I.ds;
-                        if (nb != 0.0) unsafeAtomicAdd(&nbar[lr.cp], nb);
-                        nb_src += lr.nbar_src;
+                        qk[q] = g;
+                        qm[q] = (int)li;
+                        qT[q] = Tin;
                     }
-                    wave_sync();
-                } else if (!KEPT && (__ballot(Tin != 0.0) | litmask)) {
+                    qt += __popcll(nm);
+                    if (qt - qh >= 64) {
+                        wave_sync();
+                        rbatch(64);
+                        qh += 64;
+                        wave_sync();
+                    }
+                } else if (__ballot(Tin != 0.0) | litmask) {
+                    // the split form, where most cells have a rate: each chunk
+                    // in place (queueing would only add work)
                     const bool dense = __popcll(litmask) >= dense_at;
                     if (lit && !dense) Tin += gin[off + g];
                     if (Tin != 0.0 || (lit && dense)) {
@@ -531,6 +568,11 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
                     }
                     wave_sync();
                 }
+            }
+            if (QUEUE && qt > qh) {   // the layer's remaining cells, before layer m - 1 takes its slots
+                wave_sync();
+                rbatch(qt - qh);
+                wave_sync();
             }
             lit_end -= run;
         }
@@ -566,6 +608,7 @@ __global__ __launch_bounds__(kAdjLayerThreads) void adj_layer(AdjArgs A)
     double *buf = (double *)(smem + (size_t)wave * A.region_bytes);
     int *qk = (int *)(buf + (size_t)A.lay_S * A.lay_S);
     int *qm = qk + kAdjQueue;
+    double *qT = (double *)(qm + kAdjQueue);
     char *scratch = (char *)(A.store + (size_t)(blockIdx.x * waves + wave) * A.store_stride);
     const int base = A.seg[TYPE];
     const int nitems = (A.seg[TYPE + 1] - base) * npieces;
@@ -575,7 +618,7 @@ __global__ __launch_bounds__(kAdjLayerThreads) void adj_layer(AdjArgs A)
         const int item = next_item(A.counter, nitems, home, chunk, lane);
         if (item >= nitems) break;
         const int src = A.order[base + item / npieces];
-        adjoint_layer_piece<KEPT, SPLIT>(A, T, buf, qk, qm, scratch, src, item % npieces, lane);
+        adjoint_layer_piece<KEPT, SPLIT>(A, T, buf, qk, qm, qT, scratch, src, item % npieces, lane);
     }
 }
 
@@ -770,7 +813,8 @@ hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L)
 // adjoints) and the queue of cells with a rate.
 size_t adj_layer_region_bytes(int S)
 {
-    return ((size_t)S * S * sizeof(double) + 2 * kAdjQueue * sizeof(int) + 15) & ~(size_t)15;
+    return ((size_t)S * S * sizeof(double) + kAdjQueue * (2 * sizeof(int) + sizeof(double)) + 15) &
+           ~(size_t)15;
 }
 
 hipError_t adj_layer_occupancy(bool kept, bool split, int waves, size_t lds, int *blocks_per_cu)
