@@ -1094,99 +1094,6 @@ __host__ __device__ __forceinline__ uint32_t layer_std_index(const LayerPiece &L
     return ((uint32_t)ci * (uint32_t)N + (uint32_t)cj) * (uint32_t)N + (uint32_t)ck;
 }
 
-// Reverse-mode update of layer cell (u, v) of layer m (the layer form of
-// cell_adjoint, same arithmetic).  Nbar_out: total adjoint of the cell's
-// exit column from its consumers in layer m + 1; dN: its in-cell column as
-// the forward computed it; cols: exit columns of layer m - 1 (unused for
-// m = 1); gbar_grid: dL/dGamma in the piece's layout.  Returns the adjoints
-// to push to the four neighbours of layer m - 1 (Mbar[n], for neighbour
-// (u - (n & 1), v - (n >> 1)); zero where the weight is zero; for m = 1 the
-// source takes them through nbar_src), dL/dn_HI of the cell and gbar * Gamma.
-struct LayerAdj {
-    uint32_t cp;
-    double Mbar[4];
-    double nbar_src;
-    double nbar;
-    double qbar;
-};
-
-__host__ __device__ __forceinline__ void layer_cell_adjoint(const LayerPiece &L, const LayerX &X,
-                                                            const TabNode *T, const double *m64,
-                                                            const TabParams &tp, double coef, int m,
-                                                            int u, int v, const double *cols, int S,
-                                                            double Nbar_out, double dN,
-                                                            const double *gbar_grid, LayerAdj &out)
-{
-    const int N = X.N;
-    const uint32_t cp = (uint32_t)wrap(L.c_d + L.sd * m, N) * L.st_d +
-                        (uint32_t)wrap(L.c_u + L.su * u, N) * L.st_u +
-                        (uint32_t)wrap(L.c_v + L.sv * v, N);
-    const double inv_m = rcp_f64((double)m);
-    const double a = u == m ? 1.0 : (double)u * inv_m;
-    const double b = v == m ? 1.0 : (double)v * inv_m;
-    const int r2 = m * m + u * u + v * v;
-    const double ds = sqrt_fast((double)r2) * inv_m;
-    const double sw[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
-    double Mv[4], wv[4], dw[4];
-    double num = 0.0, W = 0.0;
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-        Mv[n] = 0.0;
-        wv[n] = 0.0;
-        dw[n] = 0.0;
-        if (!(sw[n] > 0.0)) continue;
-        const double M = m == 1 ? (X.reading == 0 ? X.half_col * ds : X.half_col)
-                                : cols[(u - (n & 1)) * S + (v - (n >> 1))];
-        double wn = sw[n];
-        if (X.tau_w > 0.f) {
-            const double tau = X.sigma0 * M;
-            if (tau > (double)X.tau_w) {
-                const double it = 1.0 / tau;
-                wn *= it;
-                dw[n] = -sw[n] * X.sigma0 * it * it;
-            } else {
-                wn *= 1.0 / (double)X.tau_w;
-            }
-        }
-        Mv[n] = M;
-        wv[n] = wn;
-        num += wn * M;
-        W += wn;
-    }
-    const double iW = 1.0 / W;
-    const double Nin = num * iW;
-    bool owned = !((((L.oct >> L.au) & 1) && u == 0) || (((L.oct >> L.av) & 1) && v == 0));
-    int canon = 0;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        const int t = ax == L.d ? m : (ax == L.au ? u : v);
-        if (t == m) canon = ax;
-    }
-    owned = owned && canon == L.d;
-    double Nin_bar = Nbar_out, dN_bar = Nbar_out, qb = 0.0;
-    const double ta = X.sigma0 * Nin;
-    // dL/dGamma is read only where the rate can be non-zero
-    const double gbar = (owned && ta < tp.tau_hi) ? gbar_grid[cp] : 0.0;
-    if (gbar != 0.0) {
-        double D, Da, Ddt;
-        rate_derivs64(T, m64, tp, ta, X.sigma0 * dN, &D, &Da, &Ddt);
-        const double k = -coef / (double)r2;          // Gamma = k D
-        Nin_bar += gbar * k * Da * X.sigma0;
-        dN_bar += gbar * k * Ddt * X.sigma0;
-        qb = gbar * k * D;                            // = gbar Gamma
-    }
-    out.cp = cp;
-    out.nbar = dN_bar * X.alpha * ds;                 // dN = n_HI alpha ds
-    out.qbar = qb;
-    out.nbar_src = 0.0;
-#pragma unroll
-    for (int n = 0; n < 4; ++n) {
-        const double mb = sw[n] > 0.0 ? Nin_bar * (wv[n] + (Mv[n] - Nin) * dw[n]) * iW : 0.0;
-        out.Mbar[n] = m == 1 ? 0.0 : mb;
-        if (m == 1) out.nbar_src += mb * (X.reading == 0 ? X.alpha * ds * 0.5 : X.alpha * 0.5);
-    }
-}
-
 // The entry column of layer cell (u, v) of layer m recomputed from the
 // layer-buffer entries (layer_entry) of layer m - 1, kept as Hprev[u' * wvp +
 // v'] (its rectangle), with what the adjoint needs: the geometric weights s,
