@@ -80,6 +80,17 @@ typedef enum {
                                   every access stays inside the records).  Whole-source
                                   and octant pieces are always recomputed.  Results
                                   are the same either way up to rounding.            */
+#define ASORA_EARLY_EXIT 0x10u /* forward: stop each layer pyramid (sources above
+                                  R_oct, swept in layers) after its first layer whose
+                                  cells all leave with sigma0 N_out >= tau_hi (a
+                                  relative margin of 1e-12): every later cell of the
+                                  pyramid enters at tau >= tau_hi, where the table is
+                                  constant, so its rate is exactly zero (Section 2.2,
+                                  the table's range; the photon-loss cut of Section
+                                  3.3, made exact).  Gamma is the same as without the
+                                  flag up to the order of floating-point sums; fewer
+                                  cells are swept than the ball holds.  Not with
+                                  coldens_in (later cells get no entry column).    */
 #define ASORA_PLAIN      0x2u  /* one kernel launch per source, in input order: the
                                   unbatched baseline form (Section 3.3, one block per
                                   source).  Default: all sources in one persistent

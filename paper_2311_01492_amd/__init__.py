@@ -24,7 +24,7 @@ __all__ = ["Asora", "AsoraError", "raytrace", "table_blackbody", "table_grey", "
            "SIGMA0", "ACCUMULATE", "PLAIN", "STORE", "HALFPATH_SCALAR"]
 
 SIGMA0 = 6.3e-18          # HI cross-section at 13.6 eV, cm^2
-ACCUMULATE, PLAIN, PROFILE, STORE = 0x1, 0x2, 0x4, 0x8
+ACCUMULATE, PLAIN, PROFILE, STORE, EARLY_EXIT = 0x1, 0x2, 0x4, 0x8, 0x10
 HALFPATH_SCALAR = 0x1
 # scheduling parameters, in the order asora_get_tuning returns them
 TUNING_KEYS = ("R_whole", "R_oct", "max_waves", "pyramid_sweep", "table_place", "adj_waves", "adj_rate")
@@ -182,16 +182,18 @@ class Asora:
         return ijk, Q, R, float(R_max), n
 
     def raytrace(self, n_H, x_HI, ijk, Q, R=None, R_max=None, plain=False, coldens=False,
-                 out=None, accumulate=False, profile=False, store=False, stream=None):
+                 out=None, accumulate=False, profile=False, store=False, early_exit=False, stream=None):
         """Gamma (float32 cuda, N^3) for the sources; with coldens=True (one
         source) also the entry column N_in (float64, N^3).  store=True keeps the
-        pyramids' column records for a following backward(store=True)."""
+        pyramids' column records for a following backward(store=True).
+        early_exit=True stops each pyramid after its first opaque layer (the
+        same Gamma; fewer cells swept)."""
         ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
         dev = n_H.device
         gamma = out if out is not None else torch.empty(self.N ** 3, dtype=torch.float32, device=dev)
         cd = torch.empty(self.N ** 3, dtype=torch.float64, device=dev) if coldens else None
         flags = (PLAIN if plain else 0) | (ACCUMULATE if accumulate else 0) | (PROFILE if profile else 0)
-        flags |= STORE if store else 0
+        flags |= (STORE if store else 0) | (EARLY_EXIT if early_exit else 0)
         st = _lib.asora_raytrace(self._h, _dptr(n_H), _dptr(x_HI), n, _dptr(ijk), _dptr(Q),
                                  _dptr(R), R_max, _dptr(gamma), _dptr(cd), flags,
                                  _stream_ptr(stream))

@@ -511,8 +511,10 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     if (st) return st;
     if (!gamma) return fail(c, ASORA_EINVAL, "gamma must not be NULL");
     if (coldens_in && n_src != 1) return fail(c, ASORA_EINVAL, "coldens_in requires n_src == 1");
-    if (flags & ~(ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_PROFILE | ASORA_STORE))
+    if (flags & ~(ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_PROFILE | ASORA_STORE | ASORA_EARLY_EXIT))
         return fail(c, ASORA_EINVAL, "unknown flags");
+    if (coldens_in && (flags & ASORA_EARLY_EXIT))
+        return fail(c, ASORA_EINVAL, "ASORA_EARLY_EXIT does not give entry columns (coldens_in)");
     const bool prof = (flags & ASORA_PROFILE) != 0;
     hipEvent_t *ev = c->pev[c->prof_count % kProfSlots];
     HIPCHK(c, hipSetDevice(c->device));
@@ -564,6 +566,7 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     F.keep_rk_off = layers ? plans[3].rec_bytes : 0;
     F.m64 = c->d_m64;
     F.tab_lds = c->tab_lds;
+    F.early_exit = (flags & ASORA_EARLY_EXIT) != 0;
 
     if (prof) HIPCHK(c, hipEventRecord(ev[0], s));
     HIPCHK(c, launch_prologue(s, n_H, x_HI, c->d_nhi, c->d_gacc, coldens_in, n3, c->d_ctl,
@@ -937,8 +940,8 @@ extern "C" asora_status asora_graph_create(asora_ctx *c, const float *n_H, const
     if (!ctx_ok(c)) return ASORA_ESTATE;
     if (!out) return fail(c, ASORA_EINVAL, "asora_graph_create: out is NULL");
     *out = nullptr;
-    if (flags & ~(ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_STORE))
-        return fail(c, ASORA_EINVAL, "asora_graph_create: flags may be ACCUMULATE, PLAIN, STORE");
+    if (flags & ~(ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_STORE | ASORA_EARLY_EXIT))
+        return fail(c, ASORA_EINVAL, "asora_graph_create: flags may be ACCUMULATE, PLAIN, STORE, EARLY_EXIT");
     const bool adj = dL_dgamma != nullptr;
     const uint32_t ff = flags, bf = flags & (ASORA_ACCUMULATE | ASORA_STORE);
     HIPCHK(c, hipSetDevice(c->device));

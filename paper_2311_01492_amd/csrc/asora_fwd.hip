@@ -45,6 +45,7 @@ struct FwdArgs {
     long keep_cap;          // cells (and listed cells) per pyramid record
     size_t keep_rk_off;     // offset of the rate coefficients in a kept record
     const double *m64;      // FP64 node slopes of the table (rate coefficients of kept records)
+    int early_exit;         // layer pieces: stop after the first opaque layer
 };
 
 struct Lds {
@@ -424,6 +425,8 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
     const double opaque = layer_opaque(A.tp.tau_hi);
     bool rec_on = KEEP;   // the record is written up to the first opaque layer
     int m_last = Mx;      // the last layer the adjoint visits
+    // the first opaque layer is watched for the record or to stop there
+    bool watch = KEEP || A.early_exit;
     for (int m = 1; m <= Mx; ++m) {
         const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
         const double inv_m = rcp_f64((double)m);
@@ -454,10 +457,8 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
                 }
             }
             const uint64_t mask = __ballot(want);
-            if (KEEP && rec_on) {
-                if (lane == 0) rec.lit[choff + c] = mask;
-                opq = opq && __ballot(act && !(A.sigma0 * lc.Nout >= opaque)) == 0;
-            }
+            if (KEEP && rec_on && lane == 0) rec.lit[choff + c] = mask;
+            if (watch) opq = opq && __ballot(act && !(A.sigma0 * lc.Nout >= opaque)) == 0;
             if (want) {
                 const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
@@ -477,9 +478,11 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
         }
         off += r.total;
         choff += nch;
-        if (rec_on && opq) {
+        if (watch && opq) {
             rec_on = false;
+            watch = false;
             m_last = m;
+            if (A.early_exit) break;   // every later cell has a zero rate
         }
     }
     if (tail > head) {
@@ -876,6 +879,7 @@ static FwdArgs make_args(const FwdLaunch &F)
     A.keep_cap = F.keep_cap;
     A.keep_rk_off = F.keep_rk_off;
     A.m64 = F.m64;
+    A.early_exit = F.early_exit ? 1 : 0;
     A.ijk = F.ijk;
     A.Q = F.Q;
     A.R = F.R;

@@ -44,6 +44,7 @@ struct FwdLaunch {
     long keep_cap;
     size_t keep_rk_off;     // offset of the rate coefficients in a kept record
     const double *m64;      // FP64 node slopes of the table
+    bool early_exit;        // layer pieces: stop after the first opaque layer
     int tab_lds;            // layer pieces: table in LDS (1) or read through the caches (0)
 };
 

@@ -232,3 +232,23 @@ def test_kept_records_fall_back_to_recompute(asora, bb):
     assert_grad_parity(gn, on, 1e-5, what="dL/dn_H")
     assert_grad_parity(gx, ox, 1e-5, what="dL/dx_HI")
     np.testing.assert_allclose(gq, oq, rtol=1e-5)
+
+
+def test_kept_records_of_an_early_exit_forward(asora, bb):
+    """A forward with ASORA_EARLY_EXIT and ASORA_STORE keeps records up to each
+    pyramid's first opaque layer; the backward that reads them gives the
+    recomputing backward's gradients."""
+    print("case kept records early exit", flush=True)
+    w, g, wt = _case("c2", N=48, n_src=24, R=(10.0, 22.0))
+    gbar = _loss_grad(g, wt)
+    ctx = asora.Asora(w.N, w.cell_cm, bb.P, bb.dP, bb.lg_lo, bb.lg_hi)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    nH, xH, ijk, Q, R, gb = t(w.n_H), t(w.x_HI), t(w.src.ijk), t(w.src.Q), t(w.src.R), t(gbar)
+    ctx.raytrace(nH, xH, ijk, Q, R, store=True, early_exit=True)
+    assert ctx.store_info()[0]
+    ks = ctx.backward(nH, xH, ijk, Q, R, gb, store=True)
+    rc = ctx.backward(nH, xH, ijk, Q, R, gb)
+    ctx.check()
+    for a, b, name in zip(ks, rc, ("dL/dn_H", "dL/dx_HI", "dL/dQ")):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-12 * np.abs(b).max(), err_msg=name)

@@ -181,3 +181,29 @@ def test_radius_above_bound_is_flagged(asora, bb):
     with pytest.raises(asora.AsoraError):
         ctx.raytrace(nH, xH, torch.from_numpy(w.src.ijk), torch.from_numpy(w.src.Q),
                      torch.from_numpy(w.src.R), coldens=True)
+
+
+@pytest.mark.parametrize("case", ["uneven", "c2-subset"])
+def test_early_exit_gives_the_full_sweeps_gamma(asora, bb, case):
+    """ASORA_EARLY_EXIT stops each layer pyramid after its first opaque layer:
+    Gamma equals the full sweep's (every later cell has a zero rate) and the
+    oracle's; radii 2..40 also cover the pieces it does not apply to."""
+    if case == "uneven":
+        w = make_workload("c2", N=48, n_src=40, R=(2.0, 40.0))
+        src = w.src
+    else:
+        w = make_workload("c2")
+        src = w.src.subset(np.arange(60))
+    print("case early exit", case, flush=True)
+    o = _orc(w, bb, src=src)
+    ctx = _ctx(asora, w, bb)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    nH, xH, ijk, Q, R = t(w.n_H), t(w.x_HI), t(src.ijk), t(src.Q), t(src.R)
+    full = ctx.raytrace(nH, xH, ijk, Q, R)
+    early = ctx.raytrace(nH, xH, ijk, Q, R, early_exit=True)
+    ctx.check()
+    f, e = full.cpu().numpy().astype(np.float64), early.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(e, f, rtol=1e-6, atol=1e-6 * np.abs(f).max())
+    assert_parity(e, o, TOL)
+    with pytest.raises(asora.AsoraError):
+        ctx.raytrace(nH, xH, ijk[:1], Q[:1], R[:1], coldens=True, early_exit=True)
