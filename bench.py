@@ -206,6 +206,47 @@ def cpu_baseline(w, budget_s: float = 12.0):
                       f"workload ({t:.1f} s, one thread, FP64)"}
 
 
+def test1_time_steps(asora, torch):
+    """Test 1 of Section 4.1 with the library's time step (asora_time_step):
+    one source of 1e48 photons/s in uniform gas (n_H = 1e-3 cm^-3, T = 1e4 K,
+    case-B alpha = 2.59e-13 cm^3/s, grey opacity) at the centre of a
+    (10 kpc)^3 box on 128^3 cells, ten coarse steps of 50 Myr, each iterated
+    to convergence.  Wall time per step and the I-front radius along x over
+    the analytic r_S (1 - exp(-t/t_rec))^(1/3)."""
+    import numpy as np
+    N, kpc, myr = 128, 3.0856775814913673e21, 3.15576e13
+    ndot, nh0, alpha = 1e48, 1e-3, 2.59e-13
+    cell = 10.0 * kpc / N
+    c = N // 2
+    P, dP = asora.table_grey()
+    ctx = asora.Asora(N, cell, P, dP, -20.0, math.log10(80.0))
+    dev = torch.device("cuda")
+    nH = torch.full((N ** 3,), nh0, dtype=torch.float32, device=dev)
+    ijk = torch.tensor([[c, c, c]], dtype=torch.int32, device=dev)
+    Q = torch.tensor([ndot], dtype=torch.float64, device=dev)
+    R = torch.tensor([N / 2 - 0.5], dtype=torch.float32, device=dev)
+    y = torch.ones(N ** 3, dtype=torch.float64, device=dev)
+    r_s = (3.0 * ndot / (4.0 * math.pi * alpha * nh0 ** 2)) ** (1.0 / 3.0)
+    t_rec = 1.0 / (alpha * nh0)
+    dt = 50.0 * myr
+    ms, passes, ratio = [], [], []
+    for k in range(10):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ye, ya, g, p = ctx.time_step(nH, y, ijk, Q, R, dt, alpha)
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1e3)
+        passes.append(p)
+        y = ye.reshape(-1).contiguous()
+        line = ye[c, c, c:].double().cpu().numpy()
+        k2 = int(np.argmax(line >= 0.5)) if (line >= 0.5).any() else len(line)
+        r_i = cell * ((k2 - 1) + (0.5 - line[k2 - 1]) / (line[k2] - line[k2 - 1])) if 0 < k2 < len(line) else 0.0
+        ratio.append(r_i / (r_s * (1.0 - math.exp(-(k + 1) * dt / t_rec)) ** (1.0 / 3.0)))
+    ctx.close()
+    return {"grid": N, "steps": 10, "dt_Myr": 50.0, "ms_per_step": ms, "passes": passes,
+            "rI_over_analytic": ratio}
+
+
 def parse_tuning(text):
     """'R_oct=10,table_place=lds,adj_rate=gathered' -> keyword arguments of
     Asora.set_tuning (the named values are those the JSON line prints)."""
@@ -230,6 +271,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-source form")
     ap.add_argument("--no-tune", action="store_true", help="keep the default scheduling parameters")
+    ap.add_argument("--no-test1", action="store_true", help="skip the Test 1 time steps (chemistry)")
     ap.add_argument("--tuning", metavar="K=V,...",
                     help="set these scheduling parameters instead of autotuning (keys as in the "
                          "JSON line's tuning object, e.g. R_oct=10,adj_rate=gathered)")
@@ -483,6 +525,30 @@ def main():
                 "balls, so not comparable with value",
         "fwd_ms_per_call": ee_fwd_ms, "fwd_speedup": fwd_ms / ee_fwd_ms,
         "step_ms": ee_step_ms, "step_speedup": ms / ee_step_ms}
+    # ---- the chemistry step on the same grid (asora_chemistry): elementwise,
+    # HBM-bound; 44 algorithmic bytes per cell (Gamma, n_H FP32, x_HI and the
+    # previous <x_HI> FP64 in; <x_HI>, x_HI(dt) FP64 and <x_HI> FP32 out)
+    print("[bench] chemistry step", file=sys.stderr, flush=True)
+    ctx.raytrace(nH, xH, ijk, Q, R, R_max=R_max, out=gamma)
+    y0 = xH.double()
+    n3 = w.N ** 3
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(args.warmup):
+        ctx.chemistry(gamma, nH, y0, 1.6e15, 2.59e-13, xHI_avg_prev=y0)
+    torch.cuda.synchronize()
+    reps = 20
+    ev0.record()
+    for _ in range(reps):
+        ctx.chemistry(gamma, nH, y0, 1.6e15, 2.59e-13)
+    ev1.record()
+    torch.cuda.synchronize()
+    chem_ms = ev0.elapsed_time(ev1) / reps
+    chem_gbs = 44.0 * n3 / (chem_ms * 1e-3) / 1e9
+    out["chemistry"] = {"ms_per_call": chem_ms, "cells": n3, "alg_bytes_per_cell": 44,
+                        "roofline": {"bound": "hbm", "achieved": chem_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": chem_gbs / HBM_PEAK_GBS}}
+    if not args.no_test1:
+        out["test1_time_steps"] = test1_time_steps(asora, torch)
     out["paper_context"] = {"value": 3.156, "unit": "ns per source-voxel (forward)",
                             "hardware": "1x NVIDIA Tesla P100, FP64 grid data",
                             "workload": "250^3, R in {10,30,50,100}, up to 1e6 sources (asymptote)"}

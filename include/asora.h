@@ -375,6 +375,69 @@ asora_status asora_profile(asora_ctx *ctx, double *sweep_ms, double *total_ms);
 asora_status asora_profile_read(asora_ctx *ctx, int32_t max_calls, int32_t *n_calls,
                                 double *sweep_ms, double *total_ms);
 
+/*
+ * asora_chemistry -- the hydrogen chemistry step (Section 2.1, eq. chemistry
+ * and eq. time_avrg_sol): for every cell, the time-averaged solution of
+ * dx/dt = (1 - x)(Gamma + n_e C_H) - x n_e alpha_H over a step dt with Gamma,
+ * n_e, C_H and alpha_H held fixed, the electron density iterated as
+ * n_e = n_H <x> (starting from n_H x0) until <x> changes by at most 1e-12
+ * relative (100 passes at most).  Everything is in the neutral fraction
+ * x_HI = 1 - x (y below): y_eq = n_e alpha_H t_i, t_i = 1 / (Gamma +
+ * n_e (C_H + alpha_H)), <y> = y_eq + (y0 - y_eq)(1 - e^(-dt/t_i)) t_i/dt,
+ * y(dt) = y_eq + (y0 - y_eq) e^(-dt/t_i), FP64.  With xHI_avg_prev the n_e
+ * iteration starts from it instead (the same fixed point, in fewer passes).
+ *
+ *   gamma        device, N^3 FP32: the time-averaged photoionization rate
+ *                (s^-1; what asora_raytrace returns).
+ *   n_H          device, N^3 FP32 (cm^-3).
+ *   xHI_0        device, N^3 FP64: the neutral fraction at the start of the step.
+ *   xHI_avg_prev device, N^3 FP64, may be NULL: the <y> of the previous pass of
+ *                the ray-tracing <-> chemistry iteration, for n_changed.
+ *   dt           the step (s); alpha_H, C_H: recombination and collisional
+ *                ionization coefficients (cm^3 s^-1), the same in every cell.
+ *   conv_rtol    a cell counts as changed when |<y> - prev| > conv_rtol <y>.
+ *   xHI_avg      device, N^3 FP64 out: <y>;  xHI_end: y(dt);  xHI_avg32:
+ *                <y> in FP32, the next ray tracing's x_HI.
+ *   n_changed    host, may be NULL (then nothing waits): the number of
+ *                changed cells; the call then waits for `stream`.
+ * All outputs are written on `stream`.  ASORA_EINVAL for NULL buffers,
+ * negative or non-finite dt / coefficients; ASORA_ERANGE if the n_e iteration
+ * of some cell did not converge (only reported when the call waits).
+ */
+asora_status asora_chemistry(asora_ctx *ctx, const float *gamma, const float *n_H, const double *xHI_0,
+                             const double *xHI_avg_prev, double dt, double alpha_H, double C_H,
+                             double conv_rtol, double *xHI_avg, double *xHI_end, float *xHI_avg32,
+                             uint64_t *n_changed, void *stream);
+
+/*
+ * asora_time_step -- one time step of the ray-tracing <-> chemistry
+ * iteration (Section 2.1, the flowchart): the ray tracing (asora_raytrace on
+ * the sources, no flags) runs on the time-averaged neutral fraction <y>
+ * (the start-of-step xHI_0 the first time), the chemistry step
+ * (asora_chemistry) turns the summed rate into a new <y>, and the two
+ * alternate.  With fixed_passes > 0 exactly that many passes run; otherwise
+ * until at most conv_frac N^3 cells changed <y> by more than conv_rtol
+ * relative, or max_passes passes.  The photoionization rate is assumed
+ * constant over the step (the paper's time-averaged rate).
+ *
+ *   n_H          device, N^3 FP32; xHI_0: device, N^3 FP64.
+ *   sources      as for asora_raytrace (device buffers; R_max bounds src_R).
+ *   dt, alpha_H, C_H, conv_rtol   as for asora_chemistry.
+ *   xHI_end      device, N^3 FP64 out: the neutral fraction at the end of the step.
+ *   xHI_avg      device, N^3 FP64 out, may be NULL: the converged <y>.
+ *   gamma        device, N^3 FP32 out: the last pass's rate.
+ *   passes       host, may be NULL: the passes made.
+ * Holds two FP64 and one FP32 grid of its own in the context.  Waits for
+ * `stream` after every pass (the convergence count) unless fixed_passes > 0.
+ * ASORA_EINVAL for bad arguments; ASORA_ESTATE while a recorded graph of the
+ * context exists; errors of asora_raytrace and asora_chemistry pass through.
+ */
+asora_status asora_time_step(asora_ctx *ctx, const float *n_H, const double *xHI_0, int64_t n_src,
+                             const int32_t *src_ijk, const double *src_Q, const float *src_R, float R_max,
+                             double dt, double alpha_H, double C_H, double conv_rtol, double conv_frac,
+                             int32_t max_passes, int32_t fixed_passes, double *xHI_end, double *xHI_avg,
+                             float *gamma, int32_t *passes, void *stream);
+
 /* asora_last_error -- text of the most recent error on ctx (or of the most
  * recent failed asora_init when ctx is NULL).  Owned by the library. */
 const char *asora_last_error(const asora_ctx *ctx);

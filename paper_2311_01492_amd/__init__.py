@@ -45,6 +45,13 @@ _lib.asora_init.argtypes = [ctypes.POINTER(_p), _c_int, _c_d, _c_d, _c_d, _c_d, 
                             _c_d, _c_u32, _c_int]
 _lib.asora_raytrace.restype = _c_int
 _lib.asora_raytrace.argtypes = [_p, _p, _p, _c_i64, _p, _p, _p, _c_f, _p, _p, _c_u32, _p]
+_lib.asora_chemistry.restype = _c_int
+_lib.asora_chemistry.argtypes = [_p, _p, _p, _p, _p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, _p, _p, _p, ctypes.POINTER(ctypes.c_uint64), _p]
+_lib.asora_time_step.restype = _c_int
+_lib.asora_time_step.argtypes = [_p, _p, _p, _c_i64, _p, _p, _p, _c_f, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, _c_int, _c_int, _p, _p, _p,
+                                 ctypes.POINTER(_c_int), _p]
 _lib.asora_raytrace_backward.restype = _c_int
 _lib.asora_raytrace_backward.argtypes = [_p, _p, _p, _c_i64, _p, _p, _p, _c_f, _p, _p, _p, _p,
                                          _c_u32, _p]
@@ -279,6 +286,50 @@ class Asora:
                                        _dptr(R), R_max, _dptr(gamma), _dptr(g), _dptr(dn), _dptr(dx),
                                        _dptr(dq), flags, ctypes.byref(h)), self._h)
         return StepGraph(self, h, (n_H, x_HI, ijk, Q, R, gamma, g, dn, dx, dq))
+
+    def chemistry(self, gamma, n_H, xHI_0, dt, alpha_H, C_H=0.0, xHI_avg_prev=None, conv_rtol=1e-3,
+                  stream=None):
+        """Hydrogen chemistry step (library's asora_chemistry): returns
+        (<x_HI>, x_HI(dt), <x_HI> as float32, n_changed or None) for the
+        time-averaged rate gamma (float32) over dt seconds."""
+        dev = n_H.device
+        n3 = self.N ** 3
+        for name, t_, dt_ in (("gamma", gamma, torch.float32), ("n_H", n_H, torch.float32),
+                              ("xHI_0", xHI_0, torch.float64)):
+            if t_.dtype != dt_ or not t_.is_contiguous() or t_.numel() != n3:
+                raise AsoraError(-1, f"{name} must be a contiguous {dt_} tensor of N^3 cells")
+        y_avg = torch.empty(n3, dtype=torch.float64, device=dev)
+        y_end = torch.empty_like(y_avg)
+        y32 = torch.empty(n3, dtype=torch.float32, device=dev)
+        cnt = ctypes.c_uint64(0)
+        _raise(_lib.asora_chemistry(self._h, _dptr(gamma), _dptr(n_H), _dptr(xHI_0), _dptr(xHI_avg_prev),
+                                    float(dt), float(alpha_H), float(C_H), float(conv_rtol), _dptr(y_avg),
+                                    _dptr(y_end), _dptr(y32),
+                                    ctypes.byref(cnt) if xHI_avg_prev is not None else None,
+                                    _stream_ptr(stream)), self._h)
+        shape = (self.N,) * 3
+        return (y_avg.view(shape), y_end.view(shape), y32.view(shape),
+                cnt.value if xHI_avg_prev is not None else None)
+
+    def time_step(self, n_H, xHI_0, ijk, Q, R, dt, alpha_H, C_H=0.0, R_max=None, conv_rtol=1e-3,
+                  conv_frac=1e-4, max_passes=50, fixed_passes=0, stream=None):
+        """One time step of the ray-tracing <-> chemistry iteration (library's
+        asora_time_step): returns (x_HI(dt), <x_HI>, gamma, passes)."""
+        ijk, Q, R, R_max, n = self._prep(n_H, n_H, ijk, Q, R, R_max)
+        n3 = self.N ** 3
+        if xHI_0.dtype != torch.float64 or not xHI_0.is_contiguous() or xHI_0.numel() != n3:
+            raise AsoraError(-1, "xHI_0 must be a contiguous float64 tensor of N^3 cells")
+        dev = n_H.device
+        y_end = torch.empty(n3, dtype=torch.float64, device=dev)
+        y_avg = torch.empty_like(y_end)
+        gamma = torch.empty(n3, dtype=torch.float32, device=dev)
+        passes = _c_int(0)
+        _raise(_lib.asora_time_step(self._h, _dptr(n_H), _dptr(xHI_0), n, _dptr(ijk), _dptr(Q), _dptr(R), R_max,
+                                    float(dt), float(alpha_H), float(C_H), float(conv_rtol), float(conv_frac),
+                                    int(max_passes), int(fixed_passes), _dptr(y_end), _dptr(y_avg),
+                                    _dptr(gamma), ctypes.byref(passes), _stream_ptr(stream)), self._h)
+        shape = (self.N,) * 3
+        return y_end.view(shape), y_avg.view(shape), gamma.view(shape), passes.value
 
     def store_info(self):
         """(kept, bytes_needed, bytes_allocated) of the column records."""

@@ -90,6 +90,11 @@ struct asora_ctx {
     int live_graphs;        // graphs recorded from this context and not yet freed: they
                             // hold its buffers' addresses, so no buffer may move
     std::map<std::string, std::vector<float>> tuned;   // autotune results by workload key
+    // chemistry: counters (cells changed, cells whose n_e iteration did not
+    // converge); the time step's <y> in two FP64 grids and one FP32 grid
+    unsigned long long *d_chem_cnt;
+    double *d_chem_y[2];
+    float *d_chem_y32;
     std::string err;
 };
 
@@ -260,6 +265,10 @@ extern "C" asora_status asora_free(asora_ctx *c)
     (void)hipFree(c->d_nbar);
     (void)hipFree(c->d_store);
     (void)hipFree(c->d_keep);
+    (void)hipFree(c->d_chem_cnt);
+    (void)hipFree(c->d_chem_y[0]);
+    (void)hipFree(c->d_chem_y[1]);
+    (void)hipFree(c->d_chem_y32);
     for (int sl = 0; sl < kProfSlots; ++sl)
         for (int k = 0; k < 4; ++k)
             if (c->pev[sl][k]) (void)hipEventDestroy(c->pev[sl][k]);
@@ -1165,5 +1174,141 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
     c->tuned[key] = {b.w, b.o, (float)b.waves, (float)b.sweep, (float)b.place, (float)b.aw, (float)b.ar, best};
     if (best_ms) *best_ms = best;
     if (n_report) *n_report = nrep < max_report ? nrep : max_report;
+    return ASORA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Hydrogen chemistry (Section 2.1) and one time step of the ray-tracing <->
+// chemistry iteration.
+
+static constexpr double kNeRtol = 1e-12;   // n_e iteration: relative change of <y>
+static constexpr int kNeMaxIter = 100;
+
+static asora_status ensure_chem_counters(asora_ctx *c)
+{
+    if (!c->d_chem_cnt) HIPCHK(c, hipMalloc(&c->d_chem_cnt, 2 * sizeof(unsigned long long)));
+    return ASORA_OK;
+}
+
+static asora_status chem_check(asora_ctx *c, double dt, double alpha_H, double C_H, double conv_rtol)
+{
+    if (!(dt >= 0.0) || !std::isfinite(dt) || !(alpha_H >= 0.0) || !std::isfinite(alpha_H) || !(C_H >= 0.0) ||
+        !std::isfinite(C_H) || !(conv_rtol >= 0.0))
+        return fail(c, ASORA_EINVAL, "chemistry: need dt, alpha_H, C_H, conv_rtol finite and >= 0");
+    return ASORA_OK;
+}
+
+static asora_status chem_launch(asora_ctx *c, hipStream_t s, const float *gamma, const float *n_H,
+                                const double *y0, const double *y_prev, double dt, double alpha_H, double C_H,
+                                double conv_rtol, double *y_avg, double *y_end, float *y_avg32)
+{
+    ChemLaunch L;
+    L.n = (long)c->N * c->N * c->N;
+    L.gamma = gamma;
+    L.nH = n_H;
+    L.y0 = y0;
+    L.y_prev = y_prev;
+    L.y_avg = y_avg;
+    L.y_end = y_end;
+    L.y_avg32 = y_avg32;
+    L.dt = dt;
+    L.alpha = alpha_H;
+    L.c_h = C_H;
+    L.ne_rtol = kNeRtol;
+    L.conv_rtol = conv_rtol;
+    L.max_iter = kNeMaxIter;
+    L.changed = c->d_chem_cnt;
+    L.unconverged = c->d_chem_cnt + 1;
+    L.n_cu = c->n_cu;
+    HIPCHK(c, launch_chemistry(s, L));
+    return ASORA_OK;
+}
+
+// the two counters, after waiting for the stream
+static asora_status chem_counts(asora_ctx *c, hipStream_t s, unsigned long long out[2])
+{
+    HIPCHK(c, hipMemcpyAsync(out, c->d_chem_cnt, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (out[1]) return fail(c, ASORA_ERANGE, "chemistry: the n_e iteration of %llu cells did not converge", out[1]);
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_chemistry(asora_ctx *c, const float *gamma, const float *n_H, const double *xHI_0,
+                                        const double *xHI_avg_prev, double dt, double alpha_H, double C_H,
+                                        double conv_rtol, double *xHI_avg, double *xHI_end, float *xHI_avg32,
+                                        uint64_t *n_changed, void *stream)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    if (!gamma || !n_H || !xHI_0 || !xHI_avg || !xHI_end || !xHI_avg32)
+        return fail(c, ASORA_EINVAL, "asora_chemistry: gamma, n_H, xHI_0 and the outputs must not be NULL");
+    if (n_changed && !xHI_avg_prev)
+        return fail(c, ASORA_EINVAL, "asora_chemistry: n_changed needs xHI_avg_prev");
+    asora_status st = chem_check(c, dt, alpha_H, C_H, conv_rtol);
+    if (st) return st;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    if ((st = ensure_chem_counters(c))) return st;
+    HIPCHK(c, launch_chem_clear(s, c->d_chem_cnt));
+    if ((st = chem_launch(c, s, gamma, n_H, xHI_0, xHI_avg_prev, dt, alpha_H, C_H, conv_rtol, xHI_avg, xHI_end,
+                          xHI_avg32)))
+        return st;
+    if (n_changed) {
+        unsigned long long cnt[2];
+        if ((st = chem_counts(c, s, cnt))) return st;
+        *n_changed = cnt[0];
+    }
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_time_step(asora_ctx *c, const float *n_H, const double *xHI_0, int64_t n_src,
+                                        const int32_t *src_ijk, const double *src_Q, const float *src_R,
+                                        float R_max, double dt, double alpha_H, double C_H, double conv_rtol,
+                                        double conv_frac, int32_t max_passes, int32_t fixed_passes,
+                                        double *xHI_end, double *xHI_avg, float *gamma, int32_t *passes,
+                                        void *stream)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    if (!n_H || !xHI_0 || !xHI_end || !gamma)
+        return fail(c, ASORA_EINVAL, "asora_time_step: n_H, xHI_0, xHI_end and gamma must not be NULL");
+    asora_status st = chem_check(c, dt, alpha_H, C_H, conv_rtol);
+    if (st) return st;
+    if (!(conv_frac >= 0.0) || max_passes < 1 || fixed_passes < 0)
+        return fail(c, ASORA_EINVAL, "asora_time_step: need conv_frac >= 0, max_passes >= 1, fixed_passes >= 0");
+    if (c->live_graphs) return pinned(c, "the time-step buffers");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const long n3 = (long)c->N * c->N * c->N;
+    if ((st = ensure_chem_counters(c))) return st;
+    for (int k = 0; k < 2; ++k)
+        if (!c->d_chem_y[k]) HIPCHK(c, hipMalloc(&c->d_chem_y[k], sizeof(double) * n3));
+    if (!c->d_chem_y32) HIPCHK(c, hipMalloc(&c->d_chem_y32, sizeof(float) * n3));
+    // <y> of the pass before: y0 at first; the ray tracing reads its FP32 copy
+    int cur = 0;
+    HIPCHK(c, launch_chem_prepare(s, n3, xHI_0, c->d_chem_y[cur], c->d_chem_y32, c->d_chem_cnt, c->n_cu));
+    int pass = 0;
+    for (;;) {
+        if ((st = asora_raytrace(c, n_H, c->d_chem_y32, n_src, src_ijk, src_Q, src_R, R_max, gamma, nullptr, 0,
+                                 stream)))
+            return st;
+        HIPCHK(c, launch_chem_clear(s, c->d_chem_cnt));
+        if ((st = chem_launch(c, s, gamma, n_H, xHI_0, c->d_chem_y[cur], dt, alpha_H, C_H, conv_rtol,
+                              c->d_chem_y[1 - cur], xHI_end, c->d_chem_y32)))
+            return st;
+        cur = 1 - cur;
+        ++pass;
+        if (fixed_passes > 0) {
+            if (pass >= fixed_passes) break;
+            continue;
+        }
+        unsigned long long cnt[2];
+        if ((st = chem_counts(c, s, cnt))) return st;
+        if ((double)cnt[0] <= conv_frac * (double)n3 || pass >= max_passes) break;
+    }
+    if (xHI_avg) HIPCHK(c, hipMemcpyAsync(xHI_avg, c->d_chem_y[cur], sizeof(double) * n3, hipMemcpyDeviceToDevice, s));
+    if (passes) *passes = pass;
+    if (fixed_passes > 0) {   // report a non-converged n_e iteration here too
+        unsigned long long cnt[2];
+        if ((st = chem_counts(c, s, cnt))) return st;
+    }
     return ASORA_OK;
 }

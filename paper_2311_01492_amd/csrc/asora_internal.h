@@ -59,6 +59,23 @@ hipError_t launch_transpose_finalize(hipStream_t st, const double *gacc, const d
                                      float *gamma, int N, int accumulate);
 size_t layer_region_bytes(int S);
 hipError_t layer_occupancy(bool tab_lds, int waves, size_t lds, int *blocks_per_cu);
+
+// hydrogen chemistry step (asora_chem.hip)
+struct ChemLaunch {
+    long n;
+    const float *gamma, *nH;
+    const double *y0, *y_prev;     // start-of-step neutral fraction; previous <y> (may be NULL)
+    double *y_avg, *y_end;
+    float *y_avg32;
+    double dt, alpha, c_h, ne_rtol, conv_rtol;
+    int max_iter;
+    unsigned long long *changed, *unconverged;
+    int n_cu;
+};
+hipError_t launch_chemistry(hipStream_t st, const ChemLaunch &L);
+hipError_t launch_chem_prepare(hipStream_t st, long n, const double *y0, double *y_avg, float *y_avg32,
+                               unsigned long long *cnt, int n_cu);
+hipError_t launch_chem_clear(hipStream_t st, unsigned long long *cnt);
 hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int S, int waves, int grid,
                             int plain_src);
 size_t fwd_lds_bytes(int n_tab, int ring_cap, int row_cap);
