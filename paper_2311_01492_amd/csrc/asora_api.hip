@@ -81,6 +81,11 @@ struct asora_ctx {
     const void *keep_sig[5];    // n_H, x_HI, src_ijk, src_Q, src_R of that call
     int64_t keep_nsrc;
     float keep_Rmax;
+    // the source order (bucketing) in d_order and the segment table: a
+    // generation counted at every bucketing, and the one the keeping forward
+    // made (-1: none), which a backward with its records may reuse
+    long order_gen;
+    long keep_order_gen;
     std::map<PlanKey, Plan> adj_plans;
     // profiling: a ring of event quadruples (call start, sweep start, sweep
     // stop, call stop), one per call made with ASORA_PROFILE
@@ -197,6 +202,7 @@ extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, d
     c->max_waves = 16;
     c->big_kind = 3;
     c->tab_lds = 1;
+    c->keep_order_gen = -1;
     c->adj_waves = 4;
     c->adj_split = 1;
 
@@ -581,9 +587,12 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     HIPCHK(c, launch_prologue(s, n_H, x_HI, c->d_nhi, c->d_gacc, coldens_in, n3, c->d_ctl,
                               kCtlSize, c->n_cu));
     if (layers) HIPCHK(c, launch_transpose_prologue(s, n_H, x_HI, c->d_nhi_T, c->d_gacc_T, c->N));
-    if (n_src > 0 && !(flags & ASORA_PLAIN))
+    const bool bucketed = n_src > 0 && !(flags & ASORA_PLAIN);
+    if (bucketed) {
         HIPCHK(c, launch_bucketing(s, src_R, src_ijk, n_src, c->N, R_max, c->R_whole, c->R_oct,
                                    tmax == 3 ? 3 : 2, c->d_keys, c->d_ctl, c->d_order, c->d_err));
+        ++c->order_gen;
+    }
     if (prof) HIPCHK(c, hipEventRecord(ev[1], s));
     if (n_src > 0) {
         if (flags & ASORA_PLAIN) {
@@ -629,6 +638,7 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     }
     if (keep) {
         c->keep_valid = true;
+        c->keep_order_gen = bucketed ? c->order_gen : -1;
         c->keep_sig[0] = n_H;
         c->keep_sig[1] = x_HI;
         c->keep_sig[2] = src_ijk;
@@ -862,15 +872,21 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
         c->store_cap = store_need;
     }
     if (prof) HIPCHK(c, hipEventRecord(ev[0], s));
+    // with the forward's records and its source order still in place (no
+    // bucketing since), only the work counters are cleared and the order is
+    // reused; otherwise the sources are bucketed again
+    const bool reuse_order = kept && n_src > 0 && c->keep_order_gen == c->order_gen;
     // dL/dQ accumulates over pieces: zero it unless the caller accumulates
     HIPCHK(c, launch_adj_prologue(s, n_H, x_HI, c->d_nhi, c->d_nbar, n3, dL_dQ, n_src, acc ? 0 : 1,
-                                  c->d_ctl, kCtlSize, c->n_cu));
+                                  c->d_ctl, reuse_order ? kCtlSeg : kCtlSize, c->n_cu));
     if (layers)
         HIPCHK(c, launch_adj_transpose_prologue(s, n_H, x_HI, dL_dgamma, c->d_nhi_T, c->d_gbar_T,
                                                 c->d_nbar_T, c->N));
-    if (n_src > 0)
+    if (n_src > 0 && !reuse_order) {
         HIPCHK(c, launch_bucketing(s, src_R, src_ijk, n_src, c->N, R_max, c->R_whole, c->R_oct,
                                    layers ? 3 : 2, c->d_keys, c->d_ctl, c->d_order, c->d_err));
+        ++c->order_gen;
+    }
     if (prof) HIPCHK(c, hipEventRecord(ev[1], s));
     if (n_src > 0) {
         AdjLaunch L;
