@@ -17,7 +17,7 @@ import subprocess
 
 import numpy as np
 
-from .tables import SIGMA0, Table, blackbody_table, grey_table  # noqa: F401
+from .tables import SIGMA0, Table, blackbody_heat_table, blackbody_table, grey_table  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "asora_oracle.c")
@@ -100,6 +100,20 @@ def raytrace(N, cell_cm, table: Table, n_H, x_HI, ijk, Q, R, sigma0=SIGMA0, tau_
     _check(st)
     gam = gam.reshape(N, N, N)
     return (gam, cd.reshape(N, N, N)) if coldens else gam
+
+
+def raytrace_heating(N, cell_cm, heat_table: Table, n_H, x_HI, ijk, Q, R, sigma0=SIGMA0, tau_w=0.6,
+                     reading=0):
+    """Photo-heating rate per HI atom (eV/s, FP64, N^3) summed over sources,
+    for the heating table H of the sources' spectrum (tables.blackbody_H).
+
+    The heating of a cell is the energy its HI absorbs, Q [H(tau_in) -
+    H(tau_out)], over n_HI V, as the rate is the photons it absorbs, Q
+    [P(tau_in) - P(tau_out)], over n_HI V (eq. sugg): the same sweep and the
+    same columns with H in place of P.  Both are linear in the table, so
+    this is the rate computation given the heating table."""
+    return raytrace(N, cell_cm, heat_table, n_H, x_HI, ijk, Q, R, sigma0=sigma0, tau_w=tau_w,
+                    reading=reading)
 
 
 def raytrace_grad(N, cell_cm, table: Table, n_H, x_HI, ijk, Q, R, gbar, sigma0=SIGMA0,

@@ -9,7 +9,17 @@ so that P(0) = 1, and its derivative dP/dtau, for
       P(tau)  =  int_x0^inf phi(x) exp(-tau (x/x0)^-alpha) dx / int_x0^inf phi(x) dx,
       P'(tau) = -int_x0^inf phi(x) (x/x0)^-alpha exp(-tau (x/x0)^-alpha) dx / (same),
   where phi(x) = x^2 / (e^x - 1) is the photon-number spectrum L_nu/(h nu);
-* grey opacity (sigma = sigma0), where P = exp(-tau) exactly.
+* grey opacity (sigma = sigma0), where P = exp(-tau) exactly;
+
+and the photo-heating table of the same black body (the energy analogue of
+eq. tables: the paper leaves heating out and names it as a planned
+extension, Sections 2 and 6), in eV per emitted photon,
+      H(tau)  =  k T int_x0^inf phi(x) (x - x0) exp(-tau (x/x0)^-alpha) dx / int_x0^inf phi(x) dx,
+      H'(tau) = -k T int_x0^inf phi(x) (x - x0) (x/x0)^-alpha exp(..) dx / (same):
+the energy above the threshold that the photons still carry after optical
+depth tau, so that Q [H(tau_in) - H(tau_out)] is what a cell absorbs as
+photo-electron energy, exactly as Q [P(tau_in) - P(tau_out)] counts its
+ionizations.
 
 The integrals use SciPy's adaptive QUADPACK quadrature over fixed sub-ranges
 (the paper's table build also used SciPy quad, Section 3.4).  The upper limit
@@ -64,6 +74,32 @@ def blackbody_P(tau: float, T: float = 5e4, alpha: float = 2.8):
     P = _integral(lambda x: phi(x) * math.exp(-tau * (x / x0) ** -alpha), x0) / norm
     dP = -_integral(lambda x: phi(x) * (x / x0) ** -alpha * math.exp(-tau * (x / x0) ** -alpha), x0) / norm
     return P, dP
+
+
+def blackbody_H(tau: float, T: float = 5e4, alpha: float = 2.8):
+    """(H(tau), H'(tau)) in eV for a black body of temperature T."""
+    kT = K_B_EV * T
+    x0 = E_TH_EV / kT
+    phi = lambda x: x * x * math.exp(-x) / -math.expm1(-x)
+    norm = _integral(phi, x0)
+    H = _integral(lambda x: phi(x) * (x - x0) * math.exp(-tau * (x / x0) ** -alpha), x0) / norm
+    dH = -_integral(lambda x: phi(x) * (x - x0) * (x / x0) ** -alpha * math.exp(-tau * (x / x0) ** -alpha),
+                    x0) / norm
+    return kT * H, kT * dH
+
+
+@functools.lru_cache(maxsize=8)
+def blackbody_heat_table(T: float = 5e4, alpha: float = 2.8, n: int = 2000,
+                         lg_lo: float = -20.0, lg_hi: float = 4.0) -> Table:
+    """H(tau) and H'(tau) (eV) on the node grid of blackbody_table."""
+    taus = 10.0 ** np.linspace(lg_lo, lg_hi, n)
+    H = np.empty(n)
+    dH = np.empty(n)
+    for k, t in enumerate(taus):
+        H[k], dH[k] = blackbody_H(float(t), T, alpha)
+    H.setflags(write=False)
+    dH.setflags(write=False)
+    return Table(lg_lo, lg_hi, H, dH)
 
 
 @functools.lru_cache(maxsize=8)

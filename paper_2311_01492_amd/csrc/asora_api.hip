@@ -1106,12 +1106,12 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
         return fail(c, ASORA_ENOMEM, "asora_autotune: scratch allocation failed");
     }
     const uint32_t sf = passes == 2 ? ASORA_STORE : 0;
-    auto one = [&]() -> asora_status {
+    auto one = [&](uint32_t f) -> asora_status {
         asora_status r = asora_raytrace(c, n_H, x_HI, n_src, src_ijk, src_Q, src_R, R_max, gamma, nullptr,
-                                        sf, s);
+                                        f, s);
         if (r || passes == 1) return r;
         return asora_raytrace_backward(c, n_H, x_HI, n_src, src_ijk, src_Q, src_R, R_max, gb, dn, dx, dq,
-                                       sf, s);
+                                       f, s);
     };
     int nrep = 0;
     struct Cand {
@@ -1126,20 +1126,22 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
     auto apply = [&](const Cand &k) {
         return asora_set_tuning(c, k.w, k.o, k.waves, k.sweep, k.place, k.aw, k.ar);
     };
-    auto trial = [&](const Cand &k, float *ms) -> asora_status {
+    // f: the step's flags; only steps of the tuned form (sf) enter the report
+    auto trial = [&](const Cand &k, float *ms, uint32_t f) -> asora_status {
         asora_status r = apply(k);
         if (r) return r;
-        if ((r = one())) return r;   // plans, buffers, warm caches
+        if ((r = one(f))) return r;   // plans, buffers, warm caches
         float t[3];
         for (int i = 0; i < 3; ++i) {
             HIPCHK(c, hipEventRecord(e0, s));
-            if ((r = one())) return r;
+            if ((r = one(f))) return r;
             HIPCHK(c, hipEventRecord(e1, s));
             HIPCHK(c, hipEventSynchronize(e1));
             HIPCHK(c, hipEventElapsedTime(&t[i], e0, e1));
         }
         std::sort(t, t + 3);
         *ms = t[1];
+        if (f != sf) return ASORA_OK;
         if (nrep < max_report) {
             float *row = report + kTuneRow * nrep;
             const float v[kTuneRow] = {k.w, k.o, (float)k.waves, (float)k.sweep, (float)k.place,
@@ -1152,11 +1154,11 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
     Cand b{c->R_whole, c->R_oct, c->max_waves, c->big_kind, c->tab_lds ? 1 : 2, c->adj_waves,
            c->adj_split ? 2 : 1};
     float best = 0.f;
-    st = trial(b, &best);
+    st = trial(b, &best, sf);
     auto consider = [&](Cand k) -> asora_status {
         if (!(k.o >= k.w) || k == b) return ASORA_OK;
         float ms = 0.f;
-        asora_status r = trial(k, &ms);
+        asora_status r = trial(k, &ms, sf);
         if (r) return r;
         if (ms < best) {
             best = ms;
@@ -1174,8 +1176,18 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
     for (int wv : {4, 8, 12, 16})
         if (!st) (k = b).waves = wv, st = consider(k);
     if (passes == 2 && R_max > b.o && b.sweep == 3) {   // the layer adjoint
-        for (int ar : {1, 2})
-            if (!st) (k = b).ar = ar, st = consider(k);
+        if (c->keep_valid) {
+            // Records kept: only the kept-record adjoint runs, whatever the
+            // rate form.  The form serves the steps that recompute the
+            // columns, so it is chosen on such steps, outside the search.
+            float t_ar[2] = {0.f, 0.f};
+            for (int ar : {1, 2})
+                if (!st) (k = b).ar = ar, st = trial(k, &t_ar[ar - 1], 0u);
+            if (!st) b.ar = t_ar[0] <= t_ar[1] ? 1 : 2;
+        } else {
+            for (int ar : {1, 2})
+                if (!st) (k = b).ar = ar, st = consider(k);
+        }
         for (int aw : {2, 4, 8, 12})
             if (!st) (k = b).aw = aw, st = consider(k);
     }

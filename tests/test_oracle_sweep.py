@@ -337,3 +337,40 @@ def test_radius_monotonicity():
     mask = g1 != 0
     assert mask.sum() > 400
     assert np.array_equal(g1[mask], g2[mask]) and np.array_equal(c1[mask], c2[mask])
+
+
+# ------------------------------------------------- photo-heating (H table) ---
+def test_heating_thin_limit_and_hardening():
+    """Photo-heating per HI atom from the heating table H (eV): in the thin
+    limit heating / Gamma -> H'(0) / P'(0) = kT [J(4-a)/J(3-a) - x0], the mean
+    excess energy of the photons absorbed at zero depth (J(s) = int_x0^inf
+    x^(s-1)/(e^x-1) dx as an incomplete-gamma series); in a thick uniform
+    medium the ratio grows along an axis (the spectrum hardens)."""
+    from scipy.special import gamma as Gamma, gammaincc
+    from oracle.tables import E_TH_EV, K_B_EV
+    tb, th = oracle.blackbody_table(), oracle.blackbody_heat_table()
+    T, a = 5e4, 2.8
+    x0 = E_TH_EV / (K_B_EV * T)
+    n = np.arange(1, 61, dtype=np.float64)
+    J = lambda s: float(np.sum(n ** -s * gammaincc(s, n * x0) * Gamma(s)))
+    exact = K_B_EV * T * (J(4 - a) / J(3 - a) - x0)
+    N, s, Q = 24, (12, 12, 12), 1e52
+    d = np.indices((N,) * 3).reshape(3, -1).T - np.array(s)
+    r2 = (d ** 2).sum(axis=1).reshape((N,) * 3).astype(float)
+    inside = (r2 > 0) & (r2 <= 100)
+    ijk = np.array([s], np.int32)
+    for xval, tol in [(0.0, 1e-10), (1e-9, 3e-4)]:
+        nH = np.full((N,) * 3, 1e-4, np.float32)
+        xHI = np.full((N,) * 3, xval, np.float32)
+        g = oracle.raytrace(N, ALPHA, tb, nH, xHI, ijk, [Q], [10.0])
+        h = oracle.raytrace_heating(N, ALPHA, th, nH, xHI, ijk, [Q], [10.0])
+        np.testing.assert_allclose(h[inside] / g[inside], exact, rtol=tol)
+        assert h[s] / g[s] == pytest.approx(exact, rel=tol)
+        assert np.all(h[~inside & (r2 > 0)] == 0)
+    # thick: neutral gas of tau ~ 2.7 per cell
+    nH = np.full((N,) * 3, 1e-7, np.float32)
+    xHI = np.ones((N,) * 3, np.float32)
+    g = oracle.raytrace(N, ALPHA, tb, nH, xHI, ijk, [Q], [10.0])
+    h = oracle.raytrace_heating(N, ALPHA, th, nH, xHI, ijk, [Q], [10.0])
+    line = h[12, 12, 12:23] / g[12, 12, 12:23]
+    assert np.all(np.diff(line) > 0) and line[0] > exact

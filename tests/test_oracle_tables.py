@@ -134,3 +134,84 @@ def test_interpolant_pieces():
     np.testing.assert_allclose(d1, (Pp - Pm) / (2 * h), rtol=1e-6)
     # (the second derivative divides by tau^2: only meaningful for tau >~ 1e-3)
     np.testing.assert_allclose(d2[1:], ((d1p - d1m) / (2 * h))[1:], rtol=1e-4)
+
+
+# ---- photo-heating table H(tau) (eV): the energy analogue of eq. tables ----
+
+KT_EV = K_B_EV * T_BB
+
+
+def _series_J(s, x0, nterms=60):
+    """int_x0^inf x^(s-1)/(e^x-1) dx = sum_n n^-s Gamma(s, n x0) (upper incomplete gamma)."""
+    n = np.arange(1, nterms + 1, dtype=np.float64)
+    return float(np.sum(n ** -s * gammaincc(s, n * x0) * Gamma(s)))
+
+
+def _gl_H(tau, x0=X0, alpha=ALPHA, panels=4000, upper=800.0):
+    """Independent quadrature of (H, H') in eV, as _gl_P with the weight (x - x0) kT."""
+    g, w = np.polynomial.legendre.leggauss(16)
+    u_hi = math.sqrt(upper - x0)
+    edges = np.linspace(0.0, u_hi, panels + 1)
+    a, b = edges[:-1, None], edges[1:, None]
+    u = 0.5 * (b - a) * g[None, :] + 0.5 * (a + b)
+    wu = 0.5 * (b - a) * w[None, :]
+    x = x0 + u * u
+    jac = 2 * u
+    phi = x * x * np.exp(-x) / -np.expm1(-x)
+    sig = (x / x0) ** -alpha
+    f = phi * (x - x0) * np.exp(-tau * sig)
+    norm = np.sum(phi * jac * wu)
+    kT = E_TH_EV / x0
+    return float(kT * np.sum(f * jac * wu) / norm), float(-kT * np.sum(f * sig * jac * wu) / norm)
+
+
+def test_heating_at_zero_depth_closed_form():
+    """H(0) = kT (I_3 - x0 I_2) / I_2, the mean energy above threshold of the
+    emitted ionizing photons, with I_n = int_x0^inf x^n/(e^x-1) dx from the
+    polylogarithm series (exact for integer n)."""
+    I2 = _series_norm(X0)
+    I3 = _series_J(4.0, X0)
+    n = np.arange(1, 61, dtype=np.float64)
+    I3_int = float(np.sum(np.exp(-n * X0) * (X0 ** 3 / n + 3 * X0 ** 2 / n ** 2 + 6 * X0 / n ** 3 + 6 / n ** 4)))
+    assert I3 == pytest.approx(I3_int, rel=1e-13)
+    H0, _ = oracle.tables.blackbody_H(0.0)
+    assert H0 == pytest.approx(KT_EV * (I3 - X0 * I2) / I2, rel=1e-11)
+
+
+@pytest.mark.parametrize("alpha", [2.8, 2.0])
+def test_heating_slope_at_zero_closed_form(alpha):
+    """-H'(0) = kT x0^alpha [J(4-alpha) - x0 J(3-alpha)] / I_2; for alpha = 2
+    J(1) = -ln(1 - e^-x0) and J(2) = sum e^{-n x0} (x0/n + 1/n^2)."""
+    _, dH0 = oracle.tables.blackbody_H(0.0, T_BB, alpha)
+    I2 = _series_norm(X0)
+    if alpha == 2.0:
+        n = np.arange(1, 61, dtype=np.float64)
+        J1 = -math.log(-math.expm1(-X0))
+        J2 = float(np.sum(np.exp(-n * X0) * (X0 / n + 1 / n ** 2)))
+    else:
+        J1, J2 = _series_J(3.0 - alpha, X0), _series_J(4.0 - alpha, X0)
+    exact = -KT_EV * X0 ** alpha * (J2 - X0 * J1) / I2
+    assert dH0 == pytest.approx(exact, rel=1e-10)
+
+
+@pytest.mark.parametrize("tau", [1e-6, 0.3, 1.0, 10.0, 100.0, 1e3, 1e4])
+def test_heating_table_against_independent_quadrature(tau):
+    H, dH = oracle.tables.blackbody_H(tau)
+    Hg, dHg = _gl_H(tau)
+    assert H == pytest.approx(Hg, rel=1e-10)
+    assert dH == pytest.approx(dHg, rel=1e-10)
+
+
+def test_heating_table_hardening():
+    """Behind more absorber the photons left are harder: the mean excess
+    energy of the transmitted photons (H/P) and of the absorbed ones (H'/P')
+    grow with tau; H itself falls."""
+    tb = oracle.blackbody_table(n=200)
+    th = oracle.blackbody_heat_table(n=200)
+    assert np.all(th.P > 0) and np.all(np.diff(th.P) <= 0) and np.all(th.dP < 0)
+    ok = tb.tau > 1e-6   # where 1 - P is resolved in FP64
+    mean_t = (th.P / tb.P)[ok]
+    mean_a = (th.dP / tb.dP)[ok]
+    assert np.all(np.diff(mean_t) > 0) and np.all(np.diff(mean_a) > 0)
+    # absorbed photons are softer than the transmitted ones (sigma falls with nu)
+    assert np.all(mean_a < mean_t)
