@@ -441,6 +441,25 @@ def main():
     torch.cuda.synchronize()
     ee_step_ms = (time.perf_counter() - t0) / args.steps * 1e3
 
+    # ---- the photo-heating sweep (asora_raytrace_heating): the rate and the
+    # heating of the same black body from one sweep, two table lookups per cell
+    print("[bench] heating forward", file=sys.stderr, flush=True)
+    Hh, dHh = asora.table_blackbody_heat(5e4, 2.8, 2000, -20.0, 4.0)
+    ctx.set_heating_table(Hh, dHh)
+    heat = torch.empty_like(gamma)
+
+    def fwd_heat():
+        ctx.raytrace_heating(nH, xH, ijk, Q, R, R_max=R_max, out=gamma, heating_out=heat)
+
+    for _ in range(args.warmup):
+        fwd_heat()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fwd_heat()
+    torch.cuda.synchronize()
+    heat_ms = (time.perf_counter() - t0) / args.steps * 1e3
+
     traffic = {}
     if os.path.exists(pmc_file(args.workload)):
         pmc = json.load(open(pmc_file(args.workload)))
@@ -525,6 +544,11 @@ def main():
                 "balls, so not comparable with value",
         "fwd_ms_per_call": ee_fwd_ms, "fwd_speedup": fwd_ms / ee_fwd_ms,
         "step_ms": ee_step_ms, "step_speedup": ms / ee_step_ms}
+    out["heating"] = {
+        "note": "asora_raytrace_heating: Gamma and the photo-heating rate from one sweep (two table "
+                "lookups per cell); ns per source-voxel of the same balls",
+        "fwd_ms_per_call": heat_ms, "ns_per_source_voxel": heat_ms * 1e6 / work,
+        "over_fwd_alone": heat_ms / fwd_ms}
     # ---- the chemistry step on the same grid (asora_chemistry): elementwise,
     # HBM-bound; 44 algorithmic bytes per cell (Gamma, n_H FP32, x_HI and the
     # previous <x_HI> FP64 in; <x_HI>, x_HI(dt) FP64 and <x_HI> FP32 out)

@@ -171,6 +171,48 @@ asora_status asora_raytrace(asora_ctx *ctx, const float *n_H, const float *x_HI,
                             void *stream);
 
 /*
+ * asora_set_heating_table -- give the context a photo-heating table: H(tau)
+ * and dH/dtau (host arrays of the context's n_tab doubles, copied) on the
+ * node grid of its photoionization table, for the same source spectrum, in
+ * the energy unit the heating rate is wanted in (asora_table_blackbody_heat
+ * builds it in eV).  H is the energy above the ionization threshold that the
+ * photons still carry after optical depth tau, per emitted photon: the
+ * energy analogue of the photon count P of eq. tables (Section 2.2).  The
+ * paper computes photoionization only and names photo-heating as the next
+ * extension (Sections 2 and 6).  Replaces an earlier heating table; waits for
+ * the device first.  EINVAL for a NULL pointer or a node that is not positive,
+ * >= 1.2e-38 and non-increasing with a finite slope <= 0.
+ */
+asora_status asora_set_heating_table(asora_ctx *ctx, const double *H, const double *dHdtau);
+
+/*
+ * asora_raytrace_heating -- asora_raytrace that also gives the photo-heating
+ * rate per HI atom, from the same sweep: every cell whose rate is evaluated
+ * also evaluates the heating table at the same optical depths,
+ *   heating_p = Q_s [H(sigma0 N_in) - H(sigma0 N_out)] / (n_HI V_shell),
+ * the energy its neutral hydrogen absorbs above threshold (eq. sugg with H in
+ * place of P; the source cell as for the rate).  Two table lookups per cell,
+ * one column computation.
+ *
+ *   n_H ... gamma, flags, stream: as for asora_raytrace (flags ASORA_ACCUMULATE
+ *                | ASORA_PLAIN | ASORA_PROFILE | ASORA_STORE | ASORA_EARLY_EXIT;
+ *                the kept records serve the rate's adjoint only; the early
+ *                exit is exact for the heating too, which is also zero beyond
+ *                the table's last node).
+ *   heating      device, N^3 floats, output (heating-table energy unit per
+ *                second per HI atom); overwritten unless ASORA_ACCUMULATE.
+ *                FP64 accumulation, rounded once.
+ * ESTATE without a heating table (asora_set_heating_table).  Scratch: 16 N^3
+ * bytes more than asora_raytrace (two heating accumulators), allocated by
+ * the first call.  Both tables are read through the caches by the layer
+ * pieces (the table placement of asora_set_tuning does not apply).
+ */
+asora_status asora_raytrace_heating(asora_ctx *ctx, const float *n_H, const float *x_HI, int64_t n_src,
+                                    const int32_t *src_ijk, const double *src_Q, const float *src_R,
+                                    float R_max, float *gamma, float *heating, uint32_t flags,
+                                    void *stream);
+
+/*
  * asora_raytrace_backward -- adjoint of asora_raytrace.
  *
  * Given dL/dgamma, computes dL/dn_H, dL/dx_HI and dL/dQ of the forward map
@@ -217,6 +259,16 @@ asora_status asora_raytrace_backward(asora_ctx *ctx, const float *n_H, const flo
  */
 asora_status asora_table_blackbody(double T_bb, double index, int32_t n, double lg_lo,
                                    double lg_hi, double *P, double *dPdtau);
+
+/*
+ * asora_table_blackbody_heat -- the photo-heating table of the same source:
+ *   H(tau)  =  k T_bb int_x0^inf phi(x) (x - x0) exp(-tau (x/x0)^-index) dx / int_x0^inf phi(x) dx
+ *   H'(tau) = -k T_bb int_x0^inf phi(x) (x - x0) (x/x0)^-index exp(..) dx / (same)
+ * in eV, on the nodes of asora_table_blackbody with the same arguments.  Host
+ * only; H, dHdtau are host arrays of n doubles.
+ */
+asora_status asora_table_blackbody_heat(double T_bb, double index, int32_t n, double lg_lo,
+                                        double lg_hi, double *H, double *dHdtau);
 
 /* asora_table_grey -- P = exp(-tau), dP/dtau = -exp(-tau) (grey opacity). */
 asora_status asora_table_grey(int32_t n, double lg_lo, double lg_hi, double *P, double *dPdtau);

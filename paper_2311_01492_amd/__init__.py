@@ -57,6 +57,12 @@ _lib.asora_raytrace_backward.argtypes = [_p, _p, _p, _c_i64, _p, _p, _p, _c_f, _
                                          _c_u32, _p]
 _lib.asora_table_blackbody.restype = _c_int
 _lib.asora_table_blackbody.argtypes = [_c_d, _c_d, _c_int, _c_d, _c_d, _p, _p]
+_lib.asora_table_blackbody_heat.restype = _c_int
+_lib.asora_table_blackbody_heat.argtypes = [_c_d, _c_d, _c_int, _c_d, _c_d, _p, _p]
+_lib.asora_set_heating_table.restype = _c_int
+_lib.asora_set_heating_table.argtypes = [_p, _p, _p]
+_lib.asora_raytrace_heating.restype = _c_int
+_lib.asora_raytrace_heating.argtypes = [_p, _p, _p, _c_i64, _p, _p, _p, _c_f, _p, _p, _c_u32, _p]
 _lib.asora_table_grey.restype = _c_int
 _lib.asora_table_grey.argtypes = [_c_int, _c_d, _c_d, _p, _p]
 _lib.asora_check.restype = _c_int
@@ -127,6 +133,15 @@ def table_blackbody(T_bb: float = 5e4, index: float = 2.8, n: int = 2000, lg_lo:
     return P, dP
 
 
+def table_blackbody_heat(T_bb: float = 5e4, index: float = 2.8, n: int = 2000, lg_lo: float = -20.0,
+                         lg_hi: float = 4.0):
+    """(H, dH/dtau) in eV: the photo-heating table of the same black body, on
+    the nodes of table_blackbody with the same arguments; built on the host."""
+    H, dH = np.empty(n), np.empty(n)
+    _raise(_lib.asora_table_blackbody_heat(T_bb, index, n, lg_lo, lg_hi, _np_ptr(H), _np_ptr(dH)))
+    return H, dH
+
+
 def table_grey(n: int = 2000, lg_lo: float = -20.0, lg_hi: float = math.log10(80.0)):
     P, dP = np.empty(n), np.empty(n)
     _raise(_lib.asora_table_grey(n, lg_lo, lg_hi, _np_ptr(P), _np_ptr(dP)))
@@ -150,6 +165,7 @@ class Asora:
         P = np.ascontiguousarray(P, dtype=np.float64)
         dP = np.ascontiguousarray(dPdtau, dtype=np.float64)
         self.N, self.cell_cm, self.sigma0 = int(N), float(cell_cm), float(sigma0)
+        self.n_tab = int(P.size)
         h = _p()
         st = _lib.asora_init(ctypes.byref(h), self.N, self.cell_cm, self.sigma0, float(lg_lo),
                              float(lg_hi), int(P.size), _np_ptr(P), _np_ptr(dP), float(tau_w),
@@ -207,6 +223,32 @@ class Asora:
         _raise(st, self._h)
         shape = (self.N,) * 3
         return (gamma.view(shape), cd.view(shape)) if coldens else gamma.view(shape)
+
+    def set_heating_table(self, H, dHdtau):
+        """Photo-heating table (host arrays on this context's table nodes)."""
+        H = np.ascontiguousarray(H, dtype=np.float64)
+        dH = np.ascontiguousarray(dHdtau, dtype=np.float64)
+        if H.shape != (self.n_tab,) or dH.shape != (self.n_tab,):
+            raise AsoraError(-1, f"H and dH/dtau must be 1-d arrays of the table's {self.n_tab} nodes")
+        _raise(_lib.asora_set_heating_table(self._h, _np_ptr(H), _np_ptr(dH)), self._h)
+
+    def raytrace_heating(self, n_H, x_HI, ijk, Q, R=None, R_max=None, plain=False, out=None,
+                         heating_out=None, accumulate=False, profile=False, store=False,
+                         early_exit=False, stream=None):
+        """(Gamma, heating) from one sweep: float32 cuda N^3 each, heating in
+        the heating table's energy unit per second per HI atom."""
+        ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
+        dev = n_H.device
+        gamma = out if out is not None else torch.empty(self.N ** 3, dtype=torch.float32, device=dev)
+        heat = heating_out if heating_out is not None else torch.empty_like(gamma)
+        flags = (PLAIN if plain else 0) | (ACCUMULATE if accumulate else 0) | (PROFILE if profile else 0)
+        flags |= (STORE if store else 0) | (EARLY_EXIT if early_exit else 0)
+        st = _lib.asora_raytrace_heating(self._h, _dptr(n_H), _dptr(x_HI), n, _dptr(ijk), _dptr(Q),
+                                         _dptr(R), R_max, _dptr(gamma), _dptr(heat), flags,
+                                         _stream_ptr(stream))
+        _raise(st, self._h)
+        shape = (self.N,) * 3
+        return gamma.view(shape), heat.view(shape)
 
     def backward(self, n_H, x_HI, ijk, Q, R, dL_dgamma, R_max=None, profile=False, stream=None,
                  out=None, store=False):

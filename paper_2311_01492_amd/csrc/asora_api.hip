@@ -49,6 +49,11 @@ struct asora_ctx {
     TabParams tp;
     TabNode *d_tab;
     double *d_m64;          // FP64 node slopes for the adjoint
+    double lg_lo, lg_hi;    // log10 of the first and last table node
+    TabNode *d_tab_h;       // photo-heating table on the same nodes (NULL until set)
+    float dP0_h;            // its slope at the first node
+    double *d_hacc;         // heating accumulators (allocated by the first heating forward)
+    double *d_hacc_T;
     double *d_nhi;
     double *d_gacc;
     int *d_ctl;
@@ -141,6 +146,14 @@ extern "C" asora_status asora_table_blackbody(double T_bb, double index, int32_t
     return ASORA_OK;
 }
 
+extern "C" asora_status asora_table_blackbody_heat(double T_bb, double index, int32_t n, double lg_lo,
+                                                   double lg_hi, double *H, double *dHdtau)
+{
+    if (table_blackbody_heat(T_bb, index, n, lg_lo, lg_hi, H, dHdtau) != 0)
+        return fail(nullptr, ASORA_EINVAL, "asora_table_blackbody_heat: invalid argument");
+    return ASORA_OK;
+}
+
 extern "C" asora_status asora_table_grey(int32_t n, double lg_lo, double lg_hi, double *P,
                                          double *dPdtau)
 {
@@ -155,6 +168,17 @@ extern "C" asora_status asora_table_grey(int32_t n, double lg_lo, double lg_hi, 
 }
 
 // ---------------------------------------------------------------------------
+// First node of a table that the kernels cannot take (values must be positive
+// normal FP32 numbers, non-increasing, slopes finite and <= 0), or -1.
+static int bad_table_node(int n, const double *P, const double *dP)
+{
+    for (int k = 0; k < n; ++k)
+        if (!std::isfinite(P[k]) || !(P[k] >= 1.2e-38) || !std::isfinite(dP[k]) || dP[k] > 0 ||
+            (k > 0 && P[k] > P[k - 1]))
+            return k;
+    return -1;
+}
+
 extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, double sigma0_cm2,
                                    double lg_tau_lo, double lg_tau_hi, int32_t n_tab,
                                    const double *P, const double *dPdtau,
@@ -172,13 +196,11 @@ extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, d
     if (n_tab < 2 || n_tab > 4096)
         return fail(nullptr, ASORA_EINVAL, "asora_init: n_tab=%d out of [2,4096]", n_tab);
     if (!P || !dPdtau) return fail(nullptr, ASORA_EINVAL, "asora_init: table pointer is NULL");
-    for (int k = 0; k < n_tab; ++k) {
-        if (!std::isfinite(P[k]) || !(P[k] >= 1.2e-38) || !std::isfinite(dPdtau[k]) ||
-            dPdtau[k] > 0 || (k > 0 && P[k] > P[k - 1]))
-            return fail(nullptr, ASORA_EINVAL,
-                        "asora_init: table node %d invalid (P must be positive, >= 1.2e-38, "
-                        "non-increasing; dP/dtau finite and <= 0)", k);
-    }
+    const int bad = bad_table_node(n_tab, P, dPdtau);
+    if (bad >= 0)
+        return fail(nullptr, ASORA_EINVAL,
+                    "asora_init: table node %d invalid (P must be positive, >= 1.2e-38, "
+                    "non-increasing; dP/dtau finite and <= 0)", bad);
     if (std::isnan(tau_weight_floor) || tau_weight_floor < 0)
         return fail(nullptr, ASORA_EINVAL, "asora_init: tau_weight_floor must be >= 0 or +inf");
     if (flags & ~ASORA_INIT_SOURCE_HALFPATH_SCALAR)
@@ -210,6 +232,8 @@ extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, d
     std::vector<TabNode> nodes(n_tab);
     std::vector<double> m64(n_tab);
     prepare_table(n_tab, lg_tau_lo, lg_tau_hi, P, dPdtau, &c->tp, nodes.data(), m64.data());
+    c->lg_lo = lg_tau_lo;
+    c->lg_hi = lg_tau_hi;
 
     auto bail = [&](asora_status st) {
         asora_free(c);
@@ -258,6 +282,9 @@ extern "C" asora_status asora_free(asora_ctx *c)
     (void)hipDeviceSynchronize();
     (void)hipFree(c->d_tab);
     (void)hipFree(c->d_m64);
+    (void)hipFree(c->d_tab_h);
+    (void)hipFree(c->d_hacc);
+    (void)hipFree(c->d_hacc_T);
     (void)hipFree(c->d_nhi);
     (void)hipFree(c->d_gacc);
     (void)hipFree(c->d_ctl);
@@ -516,10 +543,60 @@ static asora_status check_common(asora_ctx *c, const float *n_H, const float *x_
     return ASORA_OK;
 }
 
+extern "C" asora_status asora_set_heating_table(asora_ctx *c, const double *H, const double *dHdtau)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    if (!H || !dHdtau) return fail(c, ASORA_EINVAL, "asora_set_heating_table: table pointer is NULL");
+    const int n = c->tp.n;
+    const int bad = bad_table_node(n, H, dHdtau);
+    if (bad >= 0)
+        return fail(c, ASORA_EINVAL,
+                    "asora_set_heating_table: node %d invalid (H must be positive, >= 1.2e-38, "
+                    "non-increasing; dH/dtau finite and <= 0)", bad);
+    std::vector<TabNode> nodes(n);
+    TabParams tp;
+    prepare_table(n, c->lg_lo, c->lg_hi, H, dHdtau, &tp, nodes.data(), nullptr);
+    HIPCHK(c, hipSetDevice(c->device));
+    if (!c->d_tab_h) HIPCHK(c, hipMalloc(&c->d_tab_h, sizeof(TabNode) * n));
+    // ordered after the work already queued on the device: a sweep in flight
+    // reads the table it started with
+    HIPCHK(c, hipDeviceSynchronize());
+    HIPCHK(c, hipMemcpy(c->d_tab_h, nodes.data(), sizeof(TabNode) * n, hipMemcpyHostToDevice));
+    c->dP0_h = tp.dP0;
+    return ASORA_OK;
+}
+
+static asora_status forward(asora_ctx *c, const float *n_H, const float *x_HI, int64_t n_src,
+                            const int32_t *src_ijk, const double *src_Q, const float *src_R, float R_max,
+                            float *gamma, float *heating, double *coldens_in, uint32_t flags,
+                            void *stream);
+
 extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const float *x_HI,
                                        int64_t n_src, const int32_t *src_ijk, const double *src_Q,
                                        const float *src_R, float R_max, float *gamma,
                                        double *coldens_in, uint32_t flags, void *stream)
+{
+    return forward(c, n_H, x_HI, n_src, src_ijk, src_Q, src_R, R_max, gamma, nullptr, coldens_in, flags,
+                   stream);
+}
+
+extern "C" asora_status asora_raytrace_heating(asora_ctx *c, const float *n_H, const float *x_HI,
+                                               int64_t n_src, const int32_t *src_ijk, const double *src_Q,
+                                               const float *src_R, float R_max, float *gamma,
+                                               float *heating, uint32_t flags, void *stream)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    if (!heating) return fail(c, ASORA_EINVAL, "heating must not be NULL");
+    if (!c->d_tab_h)
+        return fail(c, ASORA_ESTATE, "asora_raytrace_heating: no heating table (asora_set_heating_table)");
+    return forward(c, n_H, x_HI, n_src, src_ijk, src_Q, src_R, R_max, gamma, heating, nullptr, flags,
+                   stream);
+}
+
+static asora_status forward(asora_ctx *c, const float *n_H, const float *x_HI, int64_t n_src,
+                            const int32_t *src_ijk, const double *src_Q, const float *src_R, float R_max,
+                            float *gamma, float *heating, double *coldens_in, uint32_t flags,
+                            void *stream)
 {
     if (!ctx_ok(c)) return ASORA_ESTATE;
     asora_status st = check_common(c, n_H, x_HI, n_src, src_ijk, src_Q, R_max);
@@ -547,6 +624,10 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     }
     if ((st = ensure_src_cap(c, n_src))) return st;
     if (layers && (st = ensure_layer_buffers(c))) return st;
+    if (heating) {
+        if (!c->d_hacc) HIPCHK(c, hipMalloc(&c->d_hacc, sizeof(double) * n3));
+        if (layers && !c->d_hacc_T) HIPCHK(c, hipMalloc(&c->d_hacc_T, sizeof(double) * n3));
+    }
     // ASORA_STORE: keep the pyramids' column records for the adjoint when
     // they fit the budget; any other forward with the flag replaces them
     bool keep = false;
@@ -582,11 +663,19 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
     F.m64 = c->d_m64;
     F.tab_lds = c->tab_lds;
     F.early_exit = (flags & ASORA_EARLY_EXIT) != 0;
+    F.tab_h = heating ? c->d_tab_h : nullptr;
+    F.hacc = heating ? c->d_hacc : nullptr;
+    F.hacc_T = heating && layers ? c->d_hacc_T : nullptr;
+    F.dP0_h = c->dP0_h;
 
     if (prof) HIPCHK(c, hipEventRecord(ev[0], s));
     HIPCHK(c, launch_prologue(s, n_H, x_HI, c->d_nhi, c->d_gacc, coldens_in, n3, c->d_ctl,
                               kCtlSize, c->n_cu));
     if (layers) HIPCHK(c, launch_transpose_prologue(s, n_H, x_HI, c->d_nhi_T, c->d_gacc_T, c->N));
+    if (heating) {
+        HIPCHK(c, launch_zero(s, c->d_hacc, n3, c->n_cu));
+        if (layers) HIPCHK(c, launch_zero(s, c->d_hacc_T, n3, c->n_cu));
+    }
     const bool bucketed = n_src > 0 && !(flags & ASORA_PLAIN);
     if (bucketed) {
         HIPCHK(c, launch_bucketing(s, src_R, src_ijk, n_src, c->N, R_max, c->R_whole, c->R_oct,
@@ -630,6 +719,12 @@ extern "C" asora_status asora_raytrace(asora_ctx *c, const float *n_H, const flo
                                             (flags & ASORA_ACCUMULATE) ? 1 : 0));
     else
         HIPCHK(c, launch_finalize(s, c->d_gacc, gamma, n3, (flags & ASORA_ACCUMULATE) ? 1 : 0,
+                                  c->n_cu));
+    if (heating && layers)
+        HIPCHK(c, launch_transpose_finalize(s, c->d_hacc, c->d_hacc_T, heating, c->N,
+                                            (flags & ASORA_ACCUMULATE) ? 1 : 0));
+    else if (heating)
+        HIPCHK(c, launch_finalize(s, c->d_hacc, heating, n3, (flags & ASORA_ACCUMULATE) ? 1 : 0,
                                   c->n_cu));
     if (prof) {
         HIPCHK(c, hipEventRecord(ev[3], s));
@@ -1153,8 +1248,23 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
     };
     Cand b{c->R_whole, c->R_oct, c->max_waves, c->big_kind, c->tab_lds ? 1 : 2, c->adj_waves,
            c->adj_split ? 2 : 1};
+    Cand k;
+    // With the records kept (they fit) the tuned step's adjoint reads them and
+    // does not use the rate form; the form serves the steps that recompute the
+    // columns, so it is chosen on such steps, once, before the search, and
+    // every candidate carries it.
+    bool ar_fixed = false;
+    if (passes == 2 && !(st = apply(b)) && !(st = one(sf)) && c->keep_valid) {
+        float t_ar[2] = {0.f, 0.f};
+        for (int ar : {1, 2})
+            if (!st) (k = b).ar = ar, st = trial(k, &t_ar[ar - 1], 0u);
+        if (!st) {
+            b.ar = t_ar[0] <= t_ar[1] ? 1 : 2;
+            ar_fixed = true;
+        }
+    }
     float best = 0.f;
-    st = trial(b, &best, sf);
+    if (!st) st = trial(b, &best, sf);
     auto consider = [&](Cand k) -> asora_status {
         if (!(k.o >= k.w) || k == b) return ASORA_OK;
         float ms = 0.f;
@@ -1166,7 +1276,6 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
         }
         return ASORA_OK;
     };
-    Cand k;
     if (!st && R_max > b.o)
         for (int sw : {3, 2})
             if (!st) (k = b).sweep = sw, st = consider(k);
@@ -1176,18 +1285,9 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
     for (int wv : {4, 8, 12, 16})
         if (!st) (k = b).waves = wv, st = consider(k);
     if (passes == 2 && R_max > b.o && b.sweep == 3) {   // the layer adjoint
-        if (c->keep_valid) {
-            // Records kept: only the kept-record adjoint runs, whatever the
-            // rate form.  The form serves the steps that recompute the
-            // columns, so it is chosen on such steps, outside the search.
-            float t_ar[2] = {0.f, 0.f};
-            for (int ar : {1, 2})
-                if (!st) (k = b).ar = ar, st = trial(k, &t_ar[ar - 1], 0u);
-            if (!st) b.ar = t_ar[0] <= t_ar[1] ? 1 : 2;
-        } else {
+        if (!ar_fixed)
             for (int ar : {1, 2})
                 if (!st) (k = b).ar = ar, st = consider(k);
-        }
         for (int aw : {2, 4, 8, 12})
             if (!st) (k = b).aw = aw, st = consider(k);
     }

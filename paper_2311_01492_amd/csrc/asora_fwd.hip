@@ -46,7 +46,29 @@ struct FwdArgs {
     size_t keep_rk_off;     // offset of the rate coefficients in a kept record
     const double *m64;      // FP64 node slopes of the table (rate coefficients of kept records)
     int early_exit;         // layer pieces: stop after the first opaque layer
+    const TabNode *tab_h;   // photo-heating table on the same node grid (read through the
+                            // caches), or NULL: no heating
+    double *hacc, *hacc_T;  // heating accumulators, in the layouts of gacc and gacc_T
+    float dP0_h;            // dH/dtau at the first node (slope of the heating table's continuation)
 };
+
+// The node grid's parameters with the heating table's end slope.
+__device__ __forceinline__ TabParams heat_params(const FwdArgs &A)
+{
+    TabParams t = A.tp;
+    t.dP0 = A.dP0_h;
+    return t;
+}
+
+// Heating of one cell, added to hacc: the heating table's divided difference
+// over the cell's optical depths, with the rate's coefficient (the same
+// formula with H in place of P).
+__device__ __forceinline__ void add_heating(const FwdArgs &A, double *hacc, uint32_t cp, double ta,
+                                            double dt, int r2, double coef)
+{
+    const float nd = neg_divdiff(A.tab_h, heat_params(A), ta, dt);
+    if (nd > 0.f) unsafeAtomicAdd(&hacc[cp], coef * (double)(nd * rcp_approx((float)r2)));
+}
 
 struct Lds {
     TabNode *tab;
@@ -100,6 +122,10 @@ __device__ void sweep_piece(const FwdArgs &A, const Lds &L, int src, int p, int 
         const double G = source_cell_rate(L.tab, A.tp, A.sigma0, A.alpha, Q, n_s);
         if (G != 0.0) unsafeAtomicAdd(&A.gacc[cs], G);
         if (A.coldens) A.coldens[cs] = 0.0;
+        if (A.hacc) {
+            const double H = source_cell_rate(A.tab_h, heat_params(A), A.sigma0, A.alpha, Q, n_s);
+            if (H != 0.0) unsafeAtomicAdd(&A.hacc[cs], H);
+        }
     }
 
     for (int q = 1; q <= Qmax; ++q) {
@@ -152,6 +178,8 @@ __device__ void sweep_piece(const FwdArgs &A, const Lds &L, int src, int p, int 
             if (co.owned) {
                 if (co.G != 0.0) unsafeAtomicAdd(&A.gacc[co.cp], co.G);
                 if (A.coldens) A.coldens[co.cp] = co.Nin;
+                if (A.hacc)
+                    add_heating(A, A.hacc, co.cp, A.sigma0 * co.Nin, A.sigma0 * co.dN, co.r2, X.coef);
             }
         }
         __syncthreads();
@@ -169,6 +197,7 @@ struct RateQueue {
     int *r2;        // squared distance (cells)
 };
 
+template <bool HEAT>
 __device__ __forceinline__ void rate_batch(const FwdArgs &A, const TabNode *T, const RateQueue &Qa,
                                            int head, int lane, double coef, double *acc)
 {
@@ -179,9 +208,10 @@ __device__ __forceinline__ void rate_batch(const FwdArgs &A, const TabNode *T, c
         const double G = coef * (double)(nd * rcp_approx((float)Qa.r2[pos]));
         unsafeAtomicAdd(&acc[Qa.cp[pos]], G);
     }
+    if (HEAT) add_heating(A, A.hacc, Qa.cp[pos], ta, (double)Qa.dt[pos], Qa.r2[pos], coef);
 }
 
-template <int TYPE>
+template <int TYPE, bool HEAT>
 __device__ void sweep_piece_wave(const FwdArgs &A, const TabNode *T, double *ring, int *rowbase,
                                  int *rowstart, const RateQueue &Qa, int src, int p, int lane)
 {
@@ -226,6 +256,10 @@ __device__ void sweep_piece_wave(const FwdArgs &A, const TabNode *T, double *rin
         const double G = source_cell_rate(T, A.tp, A.sigma0, A.alpha, Q, n_s);
         if (G != 0.0) unsafeAtomicAdd(&A.gacc[cs], G);
         if (A.coldens) A.coldens[cs] = 0.0;
+        if (HEAT) {
+            const double H = source_cell_rate(A.tab_h, heat_params(A), A.sigma0, A.alpha, Q, n_s);
+            if (H != 0.0) unsafeAtomicAdd(&A.hacc[cs], H);
+        }
     }
     int head = 0, tail = 0;   // rate queue positions (wave-uniform)
 
@@ -265,7 +299,7 @@ __device__ void sweep_piece_wave(const FwdArgs &A, const TabNode *T, double *rin
             tail += __popcll(mask);
             if (tail - head >= 64) {
                 wave_sync();
-                rate_batch(A, T, Qa, head, lane, X.coef, A.gacc);
+                rate_batch<HEAT>(A, T, Qa, head, lane, X.coef, A.gacc);
                 head += 64;
                 wave_sync();
             }
@@ -275,17 +309,16 @@ __device__ void sweep_piece_wave(const FwdArgs &A, const TabNode *T, double *rin
     // the rates still queued
     if (tail > head) {
         wave_sync();
-        if (lane < tail - head) rate_batch(A, T, Qa, head, lane, X.coef, A.gacc);
+        if (lane < tail - head) rate_batch<HEAT>(A, T, Qa, head, lane, X.coef, A.gacc);
         wave_sync();
     }
 }
 
 // One wave per piece; the work-group only shares the table.  Persistent
 // (items from the global counter) or plain (item = wave index).
-template <int TYPE>
-__global__ __launch_bounds__(1024) void fwd_wave(FwdArgs A)
+template <int TYPE, bool HEAT>
+__device__ __forceinline__ void fwd_wave_body(const FwdArgs &A, char *smem)
 {
-    extern __shared__ __align__(16) char smem[];
     constexpr int npieces0 = TYPE == 0 ? 1 : (TYPE == 1 ? 8 : 24);
     if (A.plain_src < 0 && A.seg[TYPE + 1] == A.seg[TYPE]) return;   // no sources of this kind
     (void)npieces0;
@@ -311,7 +344,7 @@ __global__ __launch_bounds__(1024) void fwd_wave(FwdArgs A)
     if (A.plain_src >= 0) {
         const int item = blockIdx.x * waves + wave;
         if (item < npieces)
-            sweep_piece_wave<TYPE>(A, T, ring, rowbase, rowstart, Qa, A.plain_src, item, lane);
+            sweep_piece_wave<TYPE, HEAT>(A, T, ring, rowbase, rowstart, Qa, A.plain_src, item, lane);
         return;
     }
     const int base = A.seg[TYPE];
@@ -322,8 +355,23 @@ __global__ __launch_bounds__(1024) void fwd_wave(FwdArgs A)
         const int item = next_item(A.counter, nitems, home, chunk, lane);
         if (item >= nitems) break;
         const int src = A.order[base + item / npieces];
-        sweep_piece_wave<TYPE>(A, T, ring, rowbase, rowstart, Qa, src, item % npieces, lane);
+        sweep_piece_wave<TYPE, HEAT>(A, T, ring, rowbase, rowstart, Qa, src, item % npieces, lane);
     }
+}
+
+template <int TYPE>
+__global__ __launch_bounds__(1024) void fwd_wave(FwdArgs A)
+{
+    extern __shared__ __align__(16) char smem[];
+    fwd_wave_body<TYPE, false>(A, smem);
+}
+
+// The same sweep, adding the photo-heating of every cell to hacc.
+template <int TYPE>
+__global__ __launch_bounds__(1024) void fwd_wave_heat(FwdArgs A)
+{
+    extern __shared__ __align__(16) char smem[];
+    fwd_wave_body<TYPE, true>(A, smem);
 }
 
 // ---- layer pieces --------------------------------------------------------
@@ -351,10 +399,10 @@ struct LayerQueue {
 // that also gives the rate's coefficients for the adjoint (one evaluation
 // instead of two), which are stored in the record at the cells' places in
 // the order of evaluation (head + lane).
-template <bool KEEP>
+template <bool KEEP, bool HEAT>
 __device__ __forceinline__ void layer_rate_batch(const FwdArgs &A, const TabNode *T, const LayerQueue &Qa,
                                                  int head, int lane, double coef, double *acc,
-                                                 const LayerRecord &rec)
+                                                 double *hacc, const LayerRecord &rec)
 {
     const int pos = (head + lane) & (kQueue - 1);
     const double ta = Qa.ta[pos], dt = Qa.dt[pos];
@@ -375,9 +423,10 @@ __device__ __forceinline__ void layer_rate_batch(const FwdArgs &A, const TabNode
         rec.rk[A.keep_cap + q] = c[1];
         rec.rk[2 * A.keep_cap + q] = c[2];
     }
+    if (HEAT) add_heating(A, hacc, Qa.cp[pos], ta, dt, r2, coef);
 }
 
-template <bool KEEP>
+template <bool KEEP, bool HEAT>
 __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *lay,
                                   const LayerQueue &Qa, int src, int p, int lane)
 {
@@ -404,6 +453,7 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
     X.nHI = L.transposed ? A.nHI_T : A.nHI;
     layer_x_weights(X);
     double *acc = L.transposed ? A.gacc_T : A.gacc;
+    double *hacc = HEAT ? (L.transposed ? A.hacc_T : A.hacc) : nullptr;
     const double coef = Q * A.coef_unit;
     const int S = A.lay_S;
     LayerRecord rec;
@@ -415,6 +465,10 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
         const double G = source_cell_rate(T, A.tp, A.sigma0, A.alpha, Q, n_s);
         if (G != 0.0) unsafeAtomicAdd(&A.gacc[cs], G);
         if (A.coldens) A.coldens[cs] = 0.0;
+        if (HEAT) {
+            const double H = source_cell_rate(A.tab_h, heat_params(A), A.sigma0, A.alpha, Q, n_s);
+            if (H != 0.0) unsafeAtomicAdd(&A.hacc[cs], H);
+        }
     }
     const int Mx = min(isqrt_floor(Rsq), L.ext_d);
     for (int k = lane; k < S * S; k += 64) lay[k] = 0.0;   // finite everywhere it is read
@@ -471,7 +525,7 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
             tail += __popcll(mask);
             if (tail - head >= 64) {
                 wave_sync();
-                layer_rate_batch<KEEP>(A, T, Qa, head, lane, coef, acc, rec);
+                layer_rate_batch<KEEP, HEAT>(A, T, Qa, head, lane, coef, acc, hacc, rec);
                 head += 64;
             }
             wave_sync();
@@ -487,7 +541,7 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
     }
     if (tail > head) {
         wave_sync();
-        if (lane < tail - head) layer_rate_batch<KEEP>(A, T, Qa, head, lane, coef, acc, rec);
+        if (lane < tail - head) layer_rate_batch<KEEP, HEAT>(A, T, Qa, head, lane, coef, acc, hacc, rec);
         wave_sync();
     }
     if (KEEP && lane == 0) {
@@ -498,10 +552,9 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
 
 // TLDS: the table is copied to LDS once per work-group; otherwise the rate
 // batches read it through the caches, which leaves the LDS to more waves.
-template <bool KEEP, bool TLDS>
-__global__ __launch_bounds__(1024) void fwd_layer(FwdArgs A)
+template <bool KEEP, bool TLDS, bool HEAT>
+__device__ __forceinline__ void fwd_layer_body(const FwdArgs &A, char *smem)
 {
-    extern __shared__ __align__(16) char smem[];
     constexpr int TYPE = 3, npieces = 24;
     if (A.plain_src < 0 && A.seg[TYPE + 1] == A.seg[TYPE]) return;   // no sources of this kind
     const TabNode *T = TLDS ? (const TabNode *)smem : A.tab;
@@ -522,7 +575,7 @@ __global__ __launch_bounds__(1024) void fwd_layer(FwdArgs A)
     double *lay = (double *)(Qa.r2 + kQueue);
     if (A.plain_src >= 0) {
         const int item = blockIdx.x * waves + wave;
-        if (item < npieces) sweep_layer_piece<KEEP>(A, T, lay, Qa, A.plain_src, item, lane);
+        if (item < npieces) sweep_layer_piece<KEEP, HEAT>(A, T, lay, Qa, A.plain_src, item, lane);
         return;
     }
     const int base = A.seg[TYPE];
@@ -533,8 +586,24 @@ __global__ __launch_bounds__(1024) void fwd_layer(FwdArgs A)
         const int item = next_item(A.counter, nitems, home, chunk, lane);
         if (item >= nitems) break;
         const int src = A.order[base + item / npieces];
-        sweep_layer_piece<KEEP>(A, T, lay, Qa, src, item % npieces, lane);
+        sweep_layer_piece<KEEP, HEAT>(A, T, lay, Qa, src, item % npieces, lane);
     }
+}
+
+template <bool KEEP, bool TLDS>
+__global__ __launch_bounds__(1024) void fwd_layer(FwdArgs A)
+{
+    extern __shared__ __align__(16) char smem[];
+    fwd_layer_body<KEEP, TLDS, false>(A, smem);
+}
+
+// The same sweep, adding the photo-heating of every cell to hacc / hacc_T
+// (both tables through the caches).
+template <bool KEEP>
+__global__ __launch_bounds__(1024) void fwd_layer_heat(FwdArgs A)
+{
+    extern __shared__ __align__(16) char smem[];
+    fwd_layer_body<KEEP, false, true>(A, smem);
 }
 
 // Per-wave LDS of the layer kernel: the rate queue, then the S x S layer
@@ -559,10 +628,13 @@ hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int S, int waves
     A.plain_src = plain_src;
     A.lay_S = S;
     A.region_bytes = (int)layer_region_bytes(S);
-    const size_t lds = (F.tab_lds ? (size_t)F.tp.n * sizeof(TabNode) : 0) + (size_t)waves * A.region_bytes;
+    const bool tab_lds = F.tab_lds && !F.hacc;   // the heating sweep reads both tables through the caches
+    const size_t lds = (tab_lds ? (size_t)F.tp.n * sizeof(TabNode) : 0) + (size_t)waves * A.region_bytes;
     if (plain_src >= 0) grid = (24 + waves - 1) / waves;
     const dim3 g(grid), b(64 * waves);
-    if (A.keep && F.tab_lds) hipLaunchKernelGGL((fwd_layer<true, true>), g, b, lds, st, A);
+    if (F.hacc && A.keep) hipLaunchKernelGGL((fwd_layer_heat<true>), g, b, lds, st, A);
+    else if (F.hacc) hipLaunchKernelGGL((fwd_layer_heat<false>), g, b, lds, st, A);
+    else if (A.keep && F.tab_lds) hipLaunchKernelGGL((fwd_layer<true, true>), g, b, lds, st, A);
     else if (A.keep) hipLaunchKernelGGL((fwd_layer<true, false>), g, b, lds, st, A);
     else if (F.tab_lds) hipLaunchKernelGGL((fwd_layer<false, true>), g, b, lds, st, A);
     else hipLaunchKernelGGL((fwd_layer<false, false>), g, b, lds, st, A);
@@ -590,6 +662,14 @@ hipError_t launch_fwd_wave(hipStream_t st, const FwdLaunch &F, int waves, int gr
     A.region_bytes = (int)wave_region_bytes(F.ring_cap, F.row_cap);
     const size_t lds = (size_t)F.tp.n * sizeof(TabNode) + (size_t)waves * A.region_bytes;
     if (plain_src >= 0) grid = (pieces_of_type(F.type) + waves - 1) / waves;
+    if (F.hacc) {
+        switch (F.type) {
+        case 0: hipLaunchKernelGGL(fwd_wave_heat<0>, dim3(grid), dim3(64 * waves), lds, st, A); break;
+        case 1: hipLaunchKernelGGL(fwd_wave_heat<1>, dim3(grid), dim3(64 * waves), lds, st, A); break;
+        default: hipLaunchKernelGGL(fwd_wave_heat<2>, dim3(grid), dim3(64 * waves), lds, st, A); break;
+        }
+        return hipGetLastError();
+    }
     switch (F.type) {
     case 0: hipLaunchKernelGGL(fwd_wave<0>, dim3(grid), dim3(64 * waves), lds, st, A); break;
     case 1: hipLaunchKernelGGL(fwd_wave<1>, dim3(grid), dim3(64 * waves), lds, st, A); break;
@@ -802,6 +882,14 @@ __global__ __launch_bounds__(256) void transpose_finalize_kernel(const double *_
     }
 }
 
+// Clears an accumulator (a kernel: no memset node where the caller records
+// the launch into a graph).
+__global__ void zero_kernel(double *__restrict__ p, long n)
+{
+    const long stride = (long)gridDim.x * blockDim.x;
+    for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < n; c += stride) p[c] = 0.0;
+}
+
 __global__ void finalize_kernel(const double *__restrict__ gacc, float *__restrict__ gamma, long n3,
                                 int accumulate)
 {
@@ -880,6 +968,10 @@ static FwdArgs make_args(const FwdLaunch &F)
     A.keep_rk_off = F.keep_rk_off;
     A.m64 = F.m64;
     A.early_exit = F.early_exit ? 1 : 0;
+    A.tab_h = F.tab_h;
+    A.hacc = F.hacc;
+    A.hacc_T = F.hacc_T;
+    A.dP0_h = F.dP0_h;
     A.ijk = F.ijk;
     A.Q = F.Q;
     A.R = F.R;
@@ -920,6 +1012,11 @@ hipError_t fwd_configure(size_t max_lds)
     (void)hipFuncSetAttribute((const void *)fwd_layer<true, true>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipFuncSetAttribute((const void *)fwd_layer<false, false>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipFuncSetAttribute((const void *)fwd_layer<true, false>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)fwd_wave_heat<0>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)fwd_wave_heat<1>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)fwd_wave_heat<2>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)fwd_layer_heat<false>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    (void)hipFuncSetAttribute((const void *)fwd_layer_heat<true>, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
     (void)hipGetLastError();
     return hipSuccess;
 }
@@ -944,6 +1041,12 @@ hipError_t launch_fwd_plain(hipStream_t st, const FwdLaunch &F, int src)
     A.plain_src = src;
     const size_t lds = fwd_lds_bytes(F.tp.n, F.ring_cap, F.row_cap);
     hipLaunchKernelGGL(fwd_plain, dim3(A.n_pieces), dim3(kWG), lds, st, A);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(hipStream_t st, double *p, long n, int n_cu)
+{
+    hipLaunchKernelGGL(zero_kernel, dim3(n_cu * 8), dim3(256), 0, st, p, n);
     return hipGetLastError();
 }
 

@@ -46,6 +46,9 @@ struct FwdLaunch {
     const double *m64;      // FP64 node slopes of the table
     bool early_exit;        // layer pieces: stop after the first opaque layer
     int tab_lds;            // layer pieces: table in LDS (1) or read through the caches (0)
+    const TabNode *tab_h;   // photo-heating table (same node grid), or NULL: no heating
+    double *hacc, *hacc_T;  // heating accumulators (layouts of gacc, gacc_T)
+    float dP0_h;            // dH/dtau at the first node
 };
 
 hipError_t launch_prologue(hipStream_t st, const float *nH, const float *xHI, double *nHI,
@@ -57,6 +60,7 @@ hipError_t launch_transpose_prologue(hipStream_t st, const float *nH, const floa
                                      double *gacc_T, int N);
 hipError_t launch_transpose_finalize(hipStream_t st, const double *gacc, const double *gacc_T,
                                      float *gamma, int N, int accumulate);
+hipError_t launch_zero(hipStream_t st, double *p, long n, int n_cu);
 size_t layer_region_bytes(int S);
 hipError_t layer_occupancy(bool tab_lds, int waves, size_t lds, int *blocks_per_cu);
 
@@ -146,6 +150,8 @@ hipError_t launch_adj_finalize(hipStream_t st, const double *nbar, const float *
 // host table builders (asora_tables.cpp)
 int table_blackbody(double T_bb, double index, int n, double lg_lo, double lg_hi, double *P,
                     double *dP);
+int table_blackbody_heat(double T_bb, double index, int n, double lg_lo, double lg_hi, double *H,
+                         double *dH);
 void prepare_table(int n, double lg_lo, double lg_hi, const double *P, const double *dP,
                    TabParams *tp, TabNode *nodes, double *m64);
 

@@ -1,6 +1,9 @@
 // asora_tables.cpp -- host construction of the photoionization tables
 // P(tau) = gamma(tau/sigma0)/gamma(0) and dP/dtau (eq. tables, Section 2.2)
-// for a black-body spectrum behind a power-law cross-section (Section 4.1).
+// for a black-body spectrum behind a power-law cross-section (Section 4.1),
+// and of the photo-heating table of the same spectrum: H(tau), the energy
+// above threshold (eV) that the photons still carry per emitted photon, the
+// photon count of P weighted by h nu - h nu_th.
 //
 // Integration: x = h nu / k T from x0 = 13.6 eV / kT to 800 (the integrand is
 // below e^-790 of its peak beyond), substituted x = x0 + u^2 so that panels
@@ -49,8 +52,9 @@ void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
 
 }  // namespace
 
-int table_blackbody(double T_bb, double index, int n, double lg_lo, double lg_hi, double *P,
-                    double *dP)
+// heat = false: P and dP/dtau; heat = true: H and dH/dtau (eV).
+static int blackbody(double T_bb, double index, int n, double lg_lo, double lg_hi, bool heat, double *P,
+                     double *dP)
 {
     if (!(T_bb > 0) || !(n >= 2) || !(lg_hi > lg_lo) || !P || !dP) return -1;
     const double x0 = kThresholdEv / (kBoltzmannEv * T_bb);
@@ -74,6 +78,7 @@ int table_blackbody(double T_bb, double index, int n, double lg_lo, double lg_hi
             wphi[i] = 0.5 * du * gw[k] * 2.0 * u * phi;
             shape[i] = std::pow(x / x0, -index);
             norm += wphi[i];
+            if (heat) wphi[i] *= (x - x0) * kBoltzmannEv * T_bb;   // energy above threshold
         }
     }
     for (int t = 0; t < n; ++t) {
@@ -88,6 +93,18 @@ int table_blackbody(double T_bb, double index, int n, double lg_lo, double lg_hi
         dP[t] = -s1 / norm;
     }
     return 0;
+}
+
+int table_blackbody(double T_bb, double index, int n, double lg_lo, double lg_hi, double *P,
+                    double *dP)
+{
+    return blackbody(T_bb, index, n, lg_lo, lg_hi, false, P, dP);
+}
+
+int table_blackbody_heat(double T_bb, double index, int n, double lg_lo, double lg_hi, double *H,
+                         double *dH)
+{
+    return blackbody(T_bb, index, n, lg_lo, lg_hi, true, H, dH);
 }
 
 // The table in the form the kernels read (see TabNode): node values ln P,

@@ -113,7 +113,12 @@ def test_autotune_keeps_results(asora, bb, passes):
     tun = ctx.get_tuning()
     assert tun == tuple(chosen[k] for k in asora.TUNING_KEYS)
     if passes == 2 and tun[3] == 3:   # layer pyramids won: their adjoint's parameters were timed
-        assert {r["adj_rate"] for r in rep} == {1.0, 2.0}
+        assert len({r["adj_waves"] for r in rep}) > 1
+        # with the records kept the rate form is chosen on recomputing steps
+        # before the search, and every timed candidate carries it
+        ctx.raytrace(nH, xH, ijk, Q, R, store=True)
+        kept = ctx.store_info()[0]
+        assert {r["adj_rate"] for r in rep} == ({tun[6]} if kept else {1.0, 2.0})
     ctx.set_tuning(R_whole=5.0, R_oct=9.0, max_waves=4, pyramid_sweep=2, table_place=2, adj_waves=8,
                    adj_rate=1)
     best2, rep2 = ctx.autotune(nH, xH, ijk, Q, R, passes=passes)   # cached: no timing

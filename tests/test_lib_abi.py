@@ -40,6 +40,18 @@ def test_table_blackbody_matches_oracle(pkg):
     np.testing.assert_allclose(dP, tb.dP, rtol=1e-10, atol=0)
 
 
+def test_table_blackbody_heat_matches_oracle(pkg):
+    """The photo-heating table (eV) against the oracle's quadrature, on a
+    coarser node grid (the oracle's adaptive quadrature takes ~0.3 s per
+    hundred nodes)."""
+    H, dH = pkg.table_blackbody_heat(5e4, 2.8, 200, -20.0, 4.0)
+    th = oracle.blackbody_heat_table(n=200)
+    np.testing.assert_allclose(H, th.P, rtol=1e-10, atol=0)
+    np.testing.assert_allclose(dH, th.dP, rtol=1e-10, atol=0)
+    with pytest.raises(pkg.AsoraError):
+        pkg.table_blackbody_heat(0.0)
+
+
 def test_table_grey(pkg):
     P, dP = pkg.table_grey(500, -20.0, math.log10(80.0))
     tau = 10 ** np.linspace(-20, math.log10(80.0), 500)
