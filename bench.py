@@ -272,6 +272,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-source form")
     ap.add_argument("--no-tune", action="store_true", help="keep the default scheduling parameters")
     ap.add_argument("--no-test1", action="store_true", help="skip the Test 1 time steps (chemistry)")
+    ap.add_argument("--no-early-exit", action="store_true",
+                    help="skip the early-exit timings (their sweeps share kernel names with the full ones)")
     ap.add_argument("--tuning", metavar="K=V,...",
                     help="set these scheduling parameters instead of autotuning (keys as in the "
                          "JSON line's tuning object, e.g. R_oct=10,adj_rate=gathered)")
@@ -417,29 +419,31 @@ def main():
     # ---- the exact early exit (ASORA_EARLY_EXIT): each pyramid stops after its
     # first opaque layer.  Same Gamma, fewer cells swept: not the graded
     # metric, which counts every cell of every ball.
-    print("[bench] early-exit forward and step", file=sys.stderr, flush=True)
+    ee_fwd_ms = ee_step_ms = None
+    if not args.no_early_exit:
+        print("[bench] early-exit forward and step", file=sys.stderr, flush=True)
 
-    def fwd_early(store=False):
-        ctx.raytrace(nH, xH, ijk, Q, R, R_max=R_max, out=gamma, store=store, early_exit=True)
+        def fwd_early(store=False):
+            ctx.raytrace(nH, xH, ijk, Q, R, R_max=R_max, out=gamma, store=store, early_exit=True)
 
-    for _ in range(args.warmup):
-        fwd_early()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        fwd_early()
-    torch.cuda.synchronize()
-    ee_fwd_ms = (time.perf_counter() - t0) / args.steps * 1e3
-    for _ in range(args.warmup):
-        fwd_early(store=True)
-        adj(store=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        fwd_early(store=True)
-        adj(store=True)
-    torch.cuda.synchronize()
-    ee_step_ms = (time.perf_counter() - t0) / args.steps * 1e3
+        for _ in range(args.warmup):
+            fwd_early()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fwd_early()
+        torch.cuda.synchronize()
+        ee_fwd_ms = (time.perf_counter() - t0) / args.steps * 1e3
+        for _ in range(args.warmup):
+            fwd_early(store=True)
+            adj(store=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fwd_early(store=True)
+            adj(store=True)
+        torch.cuda.synchronize()
+        ee_step_ms = (time.perf_counter() - t0) / args.steps * 1e3
 
     # ---- the photo-heating sweep (asora_raytrace_heating): the rate and the
     # heating of the same black body from one sweep, two table lookups per cell
@@ -539,11 +543,12 @@ def main():
         out["plain"] = {"ns_per_source_voxel": pms * 1e6 / sub_work, "sources": n,
                         "ms_per_call": pms,
                         "plain_over_batched_fwd": (pms * 1e6 / sub_work) / out["fwd"]["ns_per_source_voxel"]}
-    out["early_exit"] = {
-        "note": "ASORA_EARLY_EXIT: same Gamma, fewer cells swept; ns are per source-voxel of the full "
-                "balls, so not comparable with value",
-        "fwd_ms_per_call": ee_fwd_ms, "fwd_speedup": fwd_ms / ee_fwd_ms,
-        "step_ms": ee_step_ms, "step_speedup": ms / ee_step_ms}
+    if ee_fwd_ms is not None:
+        out["early_exit"] = {
+            "note": "ASORA_EARLY_EXIT: same Gamma, fewer cells swept; ns are per source-voxel of the full "
+                    "balls, so not comparable with value",
+            "fwd_ms_per_call": ee_fwd_ms, "fwd_speedup": fwd_ms / ee_fwd_ms,
+            "step_ms": ee_step_ms, "step_speedup": ms / ee_step_ms}
     out["heating"] = {
         "note": "asora_raytrace_heating: Gamma and the photo-heating rate from one sweep (two table "
                 "lookups per cell); ns per source-voxel of the same balls",
