@@ -150,3 +150,28 @@ def test_heating_requires_table_and_accumulates(asora, tabs):
     g0 = ctx.raytrace(*args)
     np.testing.assert_allclose(g0.cpu().numpy(), g1.cpu().numpy(), rtol=1e-6, atol=0)
     assert math.isfinite(float(h1.max())) and float(h1.max()) > 0
+
+
+@pytest.mark.parametrize("sweep", [3, 2], ids=["layers", "shells"])
+def test_heating_edges_and_scaled_table(asora, sweep):
+    """Odd grid, sources on faces and corners (periodic wrap), radii beyond
+    half the box (extent clip), a duplicate source, R = 0; with the heating
+    table E P (grey P = e^-tau), heating = E Gamma in every cell, whatever
+    piece or accumulator (standard or transposed) the cell goes through."""
+    gt = oracle.grey_table()
+    E = 3.75
+    w = make_workload("c2", N=19, n_src=6, R=(3.0, 17.0))
+    w.n_H = (w.n_H * 2e-3).astype(np.float32)
+    w.src.ijk[:] = [[0, 0, 0], [18, 18, 18], [0, 9, 18], [5, 5, 5], [5, 5, 5], [12, 0, 7]]
+    w.src.R[:] = [17.0, 9.5, 12.0, 4.0, 4.0, 0.0]
+    print("case heating edges sweep", sweep, flush=True)
+    ctx = asora.Asora(w.N, w.cell_cm, gt.P, gt.dP, gt.lg_lo, gt.lg_hi)
+    ctx.set_tuning(pyramid_sweep=sweep)
+    ctx.set_heating_table(E * gt.P, E * gt.dP)
+    g, h = _gpu(ctx, w)
+    og = oracle.raytrace(w.N, w.cell_cm, gt, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
+    assert_parity(g, og, TOL)
+    lit = og > 0
+    assert np.all((h > 0) == lit)
+    # both from FP32 divided differences of tables whose logs differ by ln E
+    np.testing.assert_allclose(h[lit] / g[lit], E, rtol=2e-6)
