@@ -171,7 +171,9 @@ def test_heating_edges_and_scaled_table(asora, sweep):
     g, h = _gpu(ctx, w)
     og = oracle.raytrace(w.N, w.cell_cm, gt, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
     assert_parity(g, og, TOL)
-    lit = og > 0
-    assert np.all((h > 0) == lit)
-    # both from FP32 divided differences of tables whose logs differ by ln E
-    np.testing.assert_allclose(h[lit] / g[lit], E, rtol=2e-6)
+    assert_parity(h, E * og, TOL, what="heating")
+    # both from FP32 divided differences of tables whose logs differ by ln E;
+    # far below the largest rate the FP32 products reach the denormal range
+    # (flushed to zero), where only the parity floor applies
+    big = og >= 1e-20 * og.max()
+    np.testing.assert_allclose(h[big] / g[big], E, rtol=2e-6)
