@@ -119,6 +119,19 @@ def test_c3_shape_subset(asora, bb):
     assert_parity(g, o, TOL)
 
 
+def test_c5_shape_subset(asora, bb):
+    """250^3 grid, x_HI from the smoothed threshold field (about half the
+    volume ionized), radii U[5,40]: a 60-source subset against the oracle,
+    with the autotuned scheduling of a small run."""
+    w = make_workload("c5", n_src=60)
+    print("case c5 subset 60", flush=True)
+    o = _orc(w, bb)
+    ctx = _ctx(asora, w, bb)
+    ctx.set_tuning(R_whole=8.0, R_oct=8.0, max_waves=16, table_place=2)
+    g = _gpu(ctx, w)
+    assert_parity(g, o, TOL)
+
+
 @pytest.mark.parametrize("tau_w,scalar", [(math.inf, False), (0.6, True)])
 def test_weighting_and_source_readings(asora, bb, tau_w, scalar):
     w = make_workload("c2", N=32, n_src=12, R=(3.0, 20.0))
