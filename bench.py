@@ -41,6 +41,7 @@ VALU_PEAK_PER_S = 256 * 4 * 2.4e9 / 4
 # algorithmic HBM bytes per source-voxel
 FWD_BYTES_PER_SV = 16.0   # n_H + x_HI reads (2 x FP32), Gamma read-modify-write (2 x FP32)
 ADJ_BYTES_PER_SV = 32.0   # n_H + x_HI (2 x FP32), dL/dGamma (FP64), dL/dn_HI read-modify-write (2 x FP64)
+KEEP_FWD_BYTES_PER_SV = FWD_BYTES_PER_SV + 8.0   # and the kept entry column of every cell (FP64)
 KERNEL_SOURCES = ["paper_2311_01492_amd/csrc/asora_dev.h", "paper_2311_01492_amd/csrc/asora_fwd.hip",
                   "paper_2311_01492_amd/csrc/asora_adj.hip"]
 # sweep kernels of each pass (one dispatch per piece kind up to the largest
@@ -488,6 +489,9 @@ def main():
              else "adj_wave<2>"}
     if not big:
         kname = {"fwd": "fwd_wave<1>", "adj": "adj_wave<1>"}
+    # the step's forward keeps the records when they fit (layer pieces only)
+    kname["fwd_step"] = f"fwd_layer<true, {tl}>" if (kept and layer) else kname["fwd"]
+    fwd_step_bytes = KEEP_FWD_BYTES_PER_SV if (kept and layer) else FWD_BYTES_PER_SV
 
     def roof(bytes_per_sv, sweep_ms, kernel, key):
         achieved = bytes_per_sv * work / (sweep_ms * 1e-3) / 1e9
@@ -511,8 +515,11 @@ def main():
                    "n_sources": len(w.src), "source_voxels": work, "seed": w.seed,
                    "step": "batched forward + adjoint" + (" (columns kept by the forward)" if kept
                                                           else " (columns recomputed by the adjoint)")},
-        # the adjoint sweep dominates the step
-        "roofline": roof(ADJ_BYTES_PER_SV, adj_sweep_ms, kname["adj"], "adj"),
+        # the step's longer sweep kernel (forward or adjoint)
+        "roofline": (roof(fwd_step_bytes, fwd_sweep_ms, kname["fwd_step"], "fwd") if fwd_sweep_ms >= adj_sweep_ms
+                     else roof(ADJ_BYTES_PER_SV, adj_sweep_ms, kname["adj"], "adj")),
+        "step_sweeps": {"fwd": roof(fwd_step_bytes, fwd_sweep_ms, kname["fwd_step"], "fwd"),
+                        "adj": roof(ADJ_BYTES_PER_SV, adj_sweep_ms, kname["adj"], "adj")},
         "fwd": {"ns_per_source_voxel": fwd_ms * 1e6 / work, "ms_per_call": fwd_ms,
                 "roofline": roof(FWD_BYTES_PER_SV, step_rc["fwd_sweep_ms"], kname["fwd"], "fwd")},
         "adjoint": {"ns_per_source_voxel": (ms - fwd_ms) * 1e6 / work,
