@@ -186,6 +186,16 @@ class Asora:
             pass
 
     # -- argument checks shared by forward and backward ----------------------
+    def _check(self, name, t, dtype, numel=None):
+        """A tensor handed to the library as a raw pointer: its dtype, device,
+        layout and size must be what the entry point reads or writes."""
+        numel = self.N ** 3 if numel is None else numel
+        if (not torch.is_tensor(t) or t.dtype != dtype or t.device != torch.device("cuda", self.device)
+                or not t.is_contiguous() or t.numel() != numel):
+            raise AsoraError(-1, f"{name} must be a contiguous {dtype} tensor of {numel} elements "
+                                 f"on cuda:{self.device}")
+        return t
+
     def _prep(self, n_H, x_HI, ijk, Q, R, R_max):
         dev = torch.device("cuda", self.device)
         for name, t, dt in (("n_H", n_H, torch.float32), ("x_HI", x_HI, torch.float32)):
@@ -213,7 +223,8 @@ class Asora:
         same Gamma; fewer cells swept)."""
         ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
         dev = n_H.device
-        gamma = out if out is not None else torch.empty(self.N ** 3, dtype=torch.float32, device=dev)
+        gamma = (self._check("out", out, torch.float32) if out is not None
+                 else torch.empty(self.N ** 3, dtype=torch.float32, device=dev))
         cd = torch.empty(self.N ** 3, dtype=torch.float64, device=dev) if coldens else None
         flags = (PLAIN if plain else 0) | (ACCUMULATE if accumulate else 0) | (PROFILE if profile else 0)
         flags |= (STORE if store else 0) | (EARLY_EXIT if early_exit else 0)
@@ -239,8 +250,10 @@ class Asora:
         the heating table's energy unit per second per HI atom."""
         ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
         dev = n_H.device
-        gamma = out if out is not None else torch.empty(self.N ** 3, dtype=torch.float32, device=dev)
-        heat = heating_out if heating_out is not None else torch.empty_like(gamma)
+        gamma = (self._check("out", out, torch.float32) if out is not None
+                 else torch.empty(self.N ** 3, dtype=torch.float32, device=dev))
+        heat = (self._check("heating_out", heating_out, torch.float32) if heating_out is not None
+                else torch.empty_like(gamma))
         flags = (PLAIN if plain else 0) | (ACCUMULATE if accumulate else 0) | (PROFILE if profile else 0)
         flags |= (STORE if store else 0) | (EARLY_EXIT if early_exit else 0)
         st = _lib.asora_raytrace_heating(self._h, _dptr(n_H), _dptr(x_HI), n, _dptr(ijk), _dptr(Q),
@@ -314,14 +327,16 @@ class Asora:
         into grads = (dn, dx, dq)) as a HIP graph: StepGraph.launch() replays it
         on the tensors' current contents.  Runs the step once while recording."""
         ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
-        if gamma.dtype != torch.float32 or not gamma.is_contiguous() or gamma.numel() != self.N ** 3:
-            raise AsoraError(-1, "gamma must be a contiguous float32 tensor of N^3 cells")
+        self._check("gamma", gamma, torch.float32)
         dn = dx = dq = g = None
         if dL_dgamma is not None:
-            g = dL_dgamma
-            if g.dtype != torch.float64 or not g.is_contiguous() or g.numel() != self.N ** 3:
-                raise AsoraError(-1, "dL_dgamma must be a contiguous float64 tensor of N^3 cells")
+            g = self._check("dL_dgamma", dL_dgamma, torch.float64)
+            if grads is None:
+                raise AsoraError(-1, "grads = (dL/dn_H, dL/dx_HI, dL/dQ) buffers are needed with dL_dgamma")
             dn, dx, dq = grads
+            self._check("dL/dn_H", dn, torch.float32)
+            self._check("dL/dx_HI", dx, torch.float32)
+            self._check("dL/dQ", dq, torch.float64, n)
         flags = (STORE if store else 0) | (ACCUMULATE if accumulate else 0) | (PLAIN if plain else 0)
         h = _p()
         _raise(_lib.asora_graph_create(self._h, _dptr(n_H), _dptr(x_HI), n, _dptr(ijk), _dptr(Q),
@@ -338,8 +353,9 @@ class Asora:
         n3 = self.N ** 3
         for name, t_, dt_ in (("gamma", gamma, torch.float32), ("n_H", n_H, torch.float32),
                               ("xHI_0", xHI_0, torch.float64)):
-            if t_.dtype != dt_ or not t_.is_contiguous() or t_.numel() != n3:
-                raise AsoraError(-1, f"{name} must be a contiguous {dt_} tensor of N^3 cells")
+            self._check(name, t_, dt_)
+        if xHI_avg_prev is not None:
+            self._check("xHI_avg_prev", xHI_avg_prev, torch.float64)
         y_avg = torch.empty(n3, dtype=torch.float64, device=dev)
         y_end = torch.empty_like(y_avg)
         y32 = torch.empty(n3, dtype=torch.float32, device=dev)
@@ -359,8 +375,7 @@ class Asora:
         asora_time_step): returns (x_HI(dt), <x_HI>, gamma, passes)."""
         ijk, Q, R, R_max, n = self._prep(n_H, n_H, ijk, Q, R, R_max)
         n3 = self.N ** 3
-        if xHI_0.dtype != torch.float64 or not xHI_0.is_contiguous() or xHI_0.numel() != n3:
-            raise AsoraError(-1, "xHI_0 must be a contiguous float64 tensor of N^3 cells")
+        self._check("xHI_0", xHI_0, torch.float64)
         dev = n_H.device
         y_end = torch.empty(n3, dtype=torch.float64, device=dev)
         y_avg = torch.empty_like(y_end)
