@@ -638,7 +638,7 @@ __global__ __launch_bounds__(256) void adj_transpose_prologue_kernel(
         const int j = j0 + jj, k = k0 + tx;
         if (j < N && k < N) {
             const size_t c = ((size_t)i * N + j) * N + k;
-            tn[jj][tx] = (double)nH[c] * (double)xHI[c];
+            if (nHI_T) tn[jj][tx] = (double)nH[c] * (double)xHI[c];
             tg[jj][tx] = gbar[c];
         }
     }
@@ -647,7 +647,7 @@ __global__ __launch_bounds__(256) void adj_transpose_prologue_kernel(
         const int k = k0 + kk, j = j0 + tx;
         if (j < N && k < N) {
             const size_t t = ((size_t)k * N + i) * N + j;
-            nHI_T[t] = tn[tx][kk];
+            if (nHI_T) nHI_T[t] = tn[tx][kk];   // NULL: still in place from the forward
             gbar_T[t] = tg[tx][kk];
             nbar_T[t] = 0.0;
         }
@@ -688,7 +688,7 @@ __global__ void adj_prologue_kernel(const float *__restrict__ nH, const float *_
 {
     const long stride = (long)gridDim.x * blockDim.x;
     for (long c = blockIdx.x * (long)blockDim.x + threadIdx.x; c < n3; c += stride) {
-        nHI[c] = (double)nH[c] * (double)xHI[c];
+        if (nHI) nHI[c] = (double)nH[c] * (double)xHI[c];   // NULL: still in place from the forward
         nbar[c] = 0.0;
     }
     if (zero_q)

@@ -91,6 +91,10 @@ struct asora_ctx {
     // made (-1: none), which a backward with its records may reuse
     long order_gen;
     long keep_order_gen;
+    // n_HI in d_nhi (and d_nhi_T): a generation counted at every write, and
+    // the one the keeping forward wrote (-1: none), which its backward reuses
+    long nhi_gen;
+    long keep_nhi_gen;
     std::map<PlanKey, Plan> adj_plans;
     // profiling: a ring of event quadruples (call start, sweep start, sweep
     // stop, call stop), one per call made with ASORA_PROFILE
@@ -225,6 +229,7 @@ extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, d
     c->big_kind = 3;
     c->tab_lds = 1;
     c->keep_order_gen = -1;
+    c->keep_nhi_gen = -1;
     c->adj_waves = 4;
     c->adj_split = 1;
 
@@ -672,6 +677,7 @@ static asora_status forward(asora_ctx *c, const float *n_H, const float *x_HI, i
     HIPCHK(c, launch_prologue(s, n_H, x_HI, c->d_nhi, c->d_gacc, coldens_in, n3, c->d_ctl,
                               kCtlSize, c->n_cu));
     if (layers) HIPCHK(c, launch_transpose_prologue(s, n_H, x_HI, c->d_nhi_T, c->d_gacc_T, c->N));
+    ++c->nhi_gen;
     if (heating) {
         HIPCHK(c, launch_zero(s, c->d_hacc, n3, c->n_cu));
         if (layers) HIPCHK(c, launch_zero(s, c->d_hacc_T, n3, c->n_cu));
@@ -734,6 +740,7 @@ static asora_status forward(asora_ctx *c, const float *n_H, const float *x_HI, i
     if (keep) {
         c->keep_valid = true;
         c->keep_order_gen = bucketed ? c->order_gen : -1;
+        c->keep_nhi_gen = c->nhi_gen;
         c->keep_sig[0] = n_H;
         c->keep_sig[1] = x_HI;
         c->keep_sig[2] = src_ijk;
@@ -971,12 +978,15 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
     // bucketing since), only the work counters are cleared and the order is
     // reused; otherwise the sources are bucketed again
     const bool reuse_order = kept && n_src > 0 && c->keep_order_gen == c->order_gen;
+    // n_HI (both layouts) as the keeping forward left it, if nothing wrote it since
+    const bool reuse_nhi = kept && c->keep_nhi_gen == c->nhi_gen;
     // dL/dQ accumulates over pieces: zero it unless the caller accumulates
-    HIPCHK(c, launch_adj_prologue(s, n_H, x_HI, c->d_nhi, c->d_nbar, n3, dL_dQ, n_src, acc ? 0 : 1,
-                                  c->d_ctl, reuse_order ? kCtlSeg : kCtlSize, c->n_cu));
+    HIPCHK(c, launch_adj_prologue(s, n_H, x_HI, reuse_nhi ? nullptr : c->d_nhi, c->d_nbar, n3, dL_dQ, n_src,
+                                  acc ? 0 : 1, c->d_ctl, reuse_order ? kCtlSeg : kCtlSize, c->n_cu));
     if (layers)
-        HIPCHK(c, launch_adj_transpose_prologue(s, n_H, x_HI, dL_dgamma, c->d_nhi_T, c->d_gbar_T,
-                                                c->d_nbar_T, c->N));
+        HIPCHK(c, launch_adj_transpose_prologue(s, n_H, x_HI, dL_dgamma, reuse_nhi ? nullptr : c->d_nhi_T,
+                                                c->d_gbar_T, c->d_nbar_T, c->N));
+    if (!reuse_nhi) ++c->nhi_gen;
     if (n_src > 0 && !reuse_order) {
         HIPCHK(c, launch_bucketing(s, src_R, src_ijk, n_src, c->N, R_max, c->R_whole, c->R_oct,
                                    layers ? 3 : 2, c->d_keys, c->d_ctl, c->d_order, c->d_err));
