@@ -3,9 +3,10 @@
 A step is one pass of the whole hot path over the workload's source list:
 the forward sweep (asora_raytrace: n_HI and accumulator set-up, scheduling
 sort, persistent sweep over all source pieces, FP32 conversion of Gamma)
-followed by the adjoint (asora_raytrace_backward: the same set-up, per-piece
-recomputation of the columns, reverse sweep, dL/dn_H and dL/dx_HI
-conversion) for a fixed dL/dGamma, all inputs resident in HBM.  The metric
+followed by the adjoint (asora_raytrace_backward: the same set-up, the
+columns from the records the forward kept when they fit in memory, else
+recomputed per piece, reverse sweep, dL/dn_H and dL/dx_HI conversion) for a
+fixed dL/dGamma, all inputs resident in HBM.  The metric
 is the paper's time per source per voxel, t / sum_s (4/3) pi R_s^3
 (Section 4.2), in ns: `value` is the forward+adjoint step; the batched
 forward alone and the plain form (one launch per source) are reported beside
@@ -15,8 +16,9 @@ Default workload: 128^3 grid, 1.4 Mpc cells, lognormal density with ionized
 bubbles, 1000 sources, R = 30 cells.  Prints one JSON line.
 
 `--reduce-pmc DIR` turns rocprofv3 counter runs (CSV output) of this script
-into the per-launch HBM traffic file read here (see the design doc for the
-commands).
+into the per-launch HBM traffic file read here, and `--reduce-sq DIR` the SQ
+instruction counters into the VALU-issue file (the commands that made them
+head the summaries under profiles/).
 """
 from __future__ import annotations
 
