@@ -275,6 +275,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the one-launch-per-source form")
     ap.add_argument("--no-tune", action="store_true", help="keep the default scheduling parameters")
     ap.add_argument("--no-test1", action="store_true", help="skip the Test 1 time steps (chemistry)")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="skip the recorded-graph timing (its sweeps share kernel names with the eager ones)")
     ap.add_argument("--no-early-exit", action="store_true",
                     help="skip the early-exit timings (their sweeps share kernel names with the full ones)")
     ap.add_argument("--tuning", metavar="K=V,...",
@@ -396,20 +398,22 @@ def main():
     fwd_call_ms, adj_call_ms = step["fwd_call_ms"], step["adj_call_ms"]
 
     # ---- the same step recorded once as a HIP graph and replayed
-    print("[bench] recorded step", file=sys.stderr, flush=True)
-    graph = ctx.record_step(nH, xH, ijk, Q, R, gamma, dL_dgamma=gbar, grads=(dn, dx, dq), R_max=R_max,
-                            store=kept)
-    for _ in range(args.warmup):
-        graph.launch()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    torch.cuda.synchronize()
-    ev[0].record()
-    for _ in range(args.steps):
-        graph.launch()
-    ev[1].record()
-    torch.cuda.synchronize()
-    graph_ms = ev[0].elapsed_time(ev[1]) / args.steps
-    graph.close()
+    graph_ms = None
+    if not args.no_graph:
+        print("[bench] recorded step", file=sys.stderr, flush=True)
+        graph = ctx.record_step(nH, xH, ijk, Q, R, gamma, dL_dgamma=gbar, grads=(dn, dx, dq), R_max=R_max,
+                                store=kept)
+        for _ in range(args.warmup):
+            graph.launch()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.cuda.synchronize()
+        ev[0].record()
+        for _ in range(args.steps):
+            graph.launch()
+        ev[1].record()
+        torch.cuda.synchronize()
+        graph_ms = ev[0].elapsed_time(ev[1]) / args.steps
+        graph.close()
 
     # ---- batched forward alone
     print("[bench] batched forward", file=sys.stderr, flush=True)
@@ -528,7 +532,8 @@ def main():
                     "sweep_ms": adj_sweep_ms, "call_ms": adj_call_ms},
         "fwd_call_ms_in_step": fwd_call_ms,
         "tuning": tuning,
-        "graph_step": {"ms_per_step": graph_ms, "ns_per_source_voxel": graph_ms * 1e6 / work},
+        "graph_step": (None if graph_ms is None else
+                       {"ms_per_step": graph_ms, "ns_per_source_voxel": graph_ms * 1e6 / work}),
         "steps_by_mode": {
             "kept": {"ns_per_source_voxel": step_kept["ms"] * 1e6 / work, "ms_per_step": step_kept["ms"],
                      "adj_sweep_ms": step_kept["adj_sweep_ms"], "fwd_sweep_ms": step_kept["fwd_sweep_ms"],
