@@ -90,12 +90,28 @@ typedef enum {
                                   3.3, made exact).  Gamma is the same as without the
                                   flag up to the order of floating-point sums; fewer
                                   cells are swept than the ball holds.  Not with
-                                  coldens_in (later cells get no entry column).    */
+                                  coldens_in (later cells get no entry column).
+                                  backward: the same stop in the adjoint's passes
+                                  (no adjoint reaches a cell past such a layer, so
+                                  the gradients are the same up to rounding).  Kept
+                                  records are used only by a backward with the same
+                                  choice as the forward that kept them.  Without
+                                  the flag both passes sweep every layer.          */
 #define ASORA_PLAIN      0x2u  /* one kernel launch per source, in input order: the
                                   unbatched baseline form (Section 3.3, one block per
                                   source).  Default: all sources in one persistent
                                   launch per piece kind, longest first.  Results are
                                   the same up to the order of floating-point sums.   */
+
+/*
+ * asora_max_sources -- the largest n_src one call accepts (host only, no GPU
+ * use).  The persistent sweep kernels number their work items (source, piece)
+ * in 32-bit integers with up to 24 pieces per source, so n_src is bounded by
+ * INT32_MAX / 24; a call with more sources returns ASORA_EINVAL before
+ * anything is enqueued (split the source list over several calls with
+ * ASORA_ACCUMULATE: Gamma is a sum over sources, Section 2.2).
+ */
+int64_t asora_max_sources(void);
 
 /*
  * asora_init -- create a context for one grid and one photoionization table.
@@ -151,7 +167,8 @@ asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, double sigma
  *
  *   n_H, x_HI    device, N^3 floats: total hydrogen density (cm^-3) and neutral
  *                fraction; n_HI = n_H x_HI.
- *   n_src        number of sources (>= 0; 0 writes zeros / leaves gamma).
+ *   n_src        number of sources, 0 <= n_src <= asora_max_sources() (0 writes
+ *                zeros / leaves gamma).
  *   src_ijk      device, n_src x 3 int32 cell indices in [0, N).
  *   src_Q        device, n_src doubles, ionizing photons per second (>= 0).
  *   src_R        device, n_src floats, radius in cells; NULL = R_max for all.
@@ -234,7 +251,9 @@ asora_status asora_raytrace_heating(asora_ctx *ctx, const float *n_H, const floa
  *                ASORA_ACCUMULATE).
  *   flags        ASORA_ACCUMULATE | ASORA_PROFILE (asora_profile then reports
  *                the reverse sweep as sweep_ms) | ASORA_STORE (use the column
- *                records kept by the forward, see ASORA_STORE).
+ *                records kept by the forward, see ASORA_STORE) |
+ *                ASORA_EARLY_EXIT (stop each layer pyramid at its first opaque
+ *                layer, see ASORA_EARLY_EXIT).
  * Scratch: about 16 N^3 bytes more than the forward, plus the stored columns
  * of the pieces in flight (allocated at the first call, grown on demand).
  * The derivative of the rate is taken on the interpolant as it is (a cubic
@@ -345,8 +364,12 @@ asora_status asora_set_tuning(asora_ctx *ctx, float R_whole, float R_oct, int32_
  * `stream`.  passes = 1 times the forward; passes = 2 the forward with
  * ASORA_STORE followed by the adjoint (with dL/dgamma = 1).  The best
  * candidate is kept in the context (asora_get_tuning reads it) and cached
- * per (n_src, R_max, passes): a later call for the same key sets the cached
- * parameters without timing, unless flags has ASORA_TUNE_RETUNE.
+ * under a key of the workload's shape: the device (name and compute-unit
+ * count), N, n_src, R_max, passes and a 64-bin histogram of the radii.  A
+ * later call with the same key sets the cached parameters without timing,
+ * unless flags has ASORA_TUNE_RETUNE; asora_tuning_load fills that cache from
+ * a file.  The key is formed on the host from a copy of src_R (the call
+ * waits for `stream` for it).
  *
  *   n_H .. R_max  as for asora_raytrace (device buffers; only read).
  *   passes        1 or 2.
@@ -364,6 +387,36 @@ asora_status asora_autotune(asora_ctx *ctx, const float *n_H, const float *x_HI,
                             const int32_t *src_ijk, const double *src_Q, const float *src_R,
                             float R_max, int32_t passes, uint32_t flags, void *stream,
                             float *best_ms, int32_t max_report, int32_t *n_report, float *report);
+
+/*
+ * asora_set_tune_progress -- a host function that asora_autotune calls after
+ * every candidate it has timed, on the calling thread: row = the candidate's
+ * R_whole, R_oct, max_waves, pyramid_sweep, table_place, adj_waves, adj_rate
+ * and its time in ms (host array of 8 floats, valid during the call);
+ * in_report = 1 if the candidate is of the tuned form (it enters the report),
+ * 0 for the preliminary choice of adj_rate.  fn = NULL removes it.  For
+ * callers that show the progress of a long tuning run.
+ */
+typedef void (*asora_tune_progress_fn)(const float *row, int32_t in_report, void *user);
+asora_status asora_set_tune_progress(asora_ctx *ctx, asora_tune_progress_fn fn, void *user);
+
+/*
+ * asora_tuning_save / asora_tuning_load -- keep autotuner results across
+ * processes (the survey's tuning cache; the search itself is asora_autotune).
+ * The file is text, one line per key: the key of asora_autotune and eight
+ * numbers (R_whole R_oct max_waves pyramid_sweep table_place adj_waves
+ * adj_rate best_ms); lines starting with '#' are comments.
+ *   save  writes every result the context holds into `path` (host string),
+ *         keeping the file's entries of other keys; written to path".tmp"
+ *         and renamed.  ASORA_EINVAL if the file cannot be written.
+ *   load  adds the file's entries to the context's cache (a missing file
+ *         adds nothing and is not an error); *n_loaded (may be NULL)
+ *         receives their number.  The tuning in force changes only when
+ *         asora_autotune later meets one of these keys.
+ * Host only (no GPU use).
+ */
+asora_status asora_tuning_save(asora_ctx *ctx, const char *path);
+asora_status asora_tuning_load(asora_ctx *ctx, const char *path, int32_t *n_loaded);
 
 /*
  * asora_graph_create -- record one ray-tracing step into a HIP graph owned

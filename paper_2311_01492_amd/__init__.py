@@ -31,6 +31,8 @@ TUNING_KEYS = ("R_whole", "R_oct", "max_waves", "pyramid_sweep", "table_place", 
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libasora.so")
+# autotuner results of the workloads measured here (asora_tuning_save format)
+TUNING_CACHE = os.path.join(_HERE, "tuning_cache.txt")
 
 if not os.path.exists(_LIB_PATH):
     raise ImportError(f"{_LIB_PATH} is not built; run `python __graft_entry__.py` or "
@@ -95,6 +97,15 @@ _lib.asora_last_error.restype = ctypes.c_char_p
 _lib.asora_last_error.argtypes = [_p]
 _lib.asora_free.restype = _c_int
 _lib.asora_free.argtypes = [_p]
+_lib.asora_max_sources.restype = _c_i64
+_lib.asora_max_sources.argtypes = []
+_lib.asora_tuning_save.restype = _c_int
+_lib.asora_tuning_save.argtypes = [_p, ctypes.c_char_p]
+_lib.asora_tuning_load.restype = _c_int
+_lib.asora_tuning_load.argtypes = [_p, ctypes.c_char_p, ctypes.POINTER(_c_int)]
+_TUNE_CB = ctypes.CFUNCTYPE(None, ctypes.POINTER(_c_f), _c_int, _p)
+_lib.asora_set_tune_progress.restype = _c_int
+_lib.asora_set_tune_progress.argtypes = [_p, _TUNE_CB, _p]
 
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ERANGE",
            -6: "ENOSYS"}
@@ -104,6 +115,11 @@ class AsoraError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"{_STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+def max_sources() -> int:
+    """The largest number of sources one call accepts (asora_max_sources)."""
+    return int(_lib.asora_max_sources())
 
 
 def lib_path() -> str:
@@ -264,11 +280,13 @@ class Asora:
         return gamma.view(shape), heat.view(shape)
 
     def backward(self, n_H, x_HI, ijk, Q, R, dL_dgamma, R_max=None, profile=False, stream=None,
-                 out=None, store=False):
+                 out=None, store=False, early_exit=False):
         """(dL/dn_H, dL/dx_HI, dL/dQ) for the given dL/dgamma (converted to FP64).
         out: optional (dn [N^3 float32], dx [N^3 float32], dq [n float64]) to fill.
         store=True: use the column records kept by raytrace(store=True) with the
-        same tensors (which must not have changed since), else recompute."""
+        same tensors (which must not have changed since), else recompute.
+        early_exit=True stops each pyramid at its first opaque layer (kept
+        records are used only if their forward made the same choice)."""
         ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
         dev = n_H.device
         g = dL_dgamma.to(dev, torch.float64).contiguous()
@@ -285,7 +303,8 @@ class Asora:
         st = _lib.asora_raytrace_backward(self._h, _dptr(n_H), _dptr(x_HI), n, _dptr(ijk),
                                           _dptr(Q), _dptr(R), R_max, _dptr(g), _dptr(dn),
                                           _dptr(dx), _dptr(dq),
-                                          (PROFILE if profile else 0) | (STORE if store else 0),
+                                          (PROFILE if profile else 0) | (STORE if store else 0) |
+                                          (EARLY_EXIT if early_exit else 0),
                                           _stream_ptr(stream))
         _raise(st, self._h)
         shape = (self.N,) * 3
@@ -320,6 +339,32 @@ class Asora:
                                    rep.ctypes.data_as(_p)), self._h)
         keys = TUNING_KEYS + ("ms",)
         return best.value, [dict(zip(keys, map(float, r))) for r in rep[:nrep.value]]
+
+    def set_tune_progress(self, fn):
+        """fn(row: dict, in_report: bool) is called after every candidate the
+        autotuner times (asora_set_tune_progress); None removes it."""
+        if fn is None:
+            self._tune_cb = None
+            _raise(_lib.asora_set_tune_progress(self._h, ctypes.cast(None, _TUNE_CB), None), self._h)
+            return
+        keys = TUNING_KEYS + ("ms",)
+
+        def cb(row, in_report, user):
+            fn(dict(zip(keys, (float(row[i]) for i in range(8)))), bool(in_report))
+
+        self._tune_cb = _TUNE_CB(cb)   # kept alive with the context
+        _raise(_lib.asora_set_tune_progress(self._h, self._tune_cb, None), self._h)
+
+    def save_tuning(self, path):
+        """Write the autotuner results of this context to `path` (asora_tuning_save)."""
+        _raise(_lib.asora_tuning_save(self._h, os.fsencode(path)), self._h)
+
+    def load_tuning(self, path) -> int:
+        """Add the autotuner results stored in `path` to this context's cache
+        (asora_tuning_load); returns how many were read."""
+        n = _c_int(0)
+        _raise(_lib.asora_tuning_load(self._h, os.fsencode(path), ctypes.byref(n)), self._h)
+        return n.value
 
     def record_step(self, n_H, x_HI, ijk, Q, R, gamma, dL_dgamma=None, grads=None, R_max=None,
                     store=False, accumulate=False, plain=False):

@@ -54,6 +54,7 @@ struct AdjArgs {
     size_t rec_piece_bytes;  // bytes of one pyramid's column record
     size_t rec_rk_off;       // kept records: offset of the rate coefficients
     long rec_cap;            // cells (and listed cells) per pyramid record
+    int early_exit;          // layer pieces: stop at the first opaque layer
 };
 
 template <int TYPE>
@@ -313,14 +314,15 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
     // form (most cells have a rate there, and most lanes work anyway)
     constexpr bool QUEUE = KEPT || !SPLIT;
 
-    // ---- (F), up to the first layer whose cells all leave opaque
-    // (layer_opaque): later layers have no rate and no adjoint.  With kept
-    // records the forward found that layer.
+    // ---- (F), every layer; with the early exit only up to the first layer
+    // whose cells all leave opaque (layer_opaque): later layers have no rate
+    // and no adjoint.  Kept records hold the layers their forward swept.
     int Mt = Mx;   // the last layer (G) and (R) visit
     if (KEPT) {
         const int ml = (int)((const uint64_t *)rec.rk)[3 * A.rec_cap + 1];
         Mt = ml < Mx ? ml : Mx;
     } else {
+        const bool watch = A.early_exit != 0;
         for (int k = lane; k < S * S; k += 64) buf[k] = 0.0;   // finite everywhere it is read
         wave_sync();
         const double opaque = layer_opaque(A.tp.tau_hi);
@@ -354,12 +356,12 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
                 }
                 const uint64_t mask = __ballot(lit);
                 if (lane == 0) rec.lit[choff + c] = mask;
-                opq = opq && __ballot(act && !(A.sigma0 * lc.Nout >= opaque)) == 0;
+                if (watch) opq = opq && __ballot(act && !(A.sigma0 * lc.Nout >= opaque)) == 0;
                 wave_sync();
             }
             off += r.total;
             choff += nch;
-            if (opq) {
+            if (watch && opq) {
                 Mt = m;
                 break;
             }
@@ -793,6 +795,7 @@ static AdjArgs make_adj_args(const AdjLaunch &L)
     A.rec_piece_bytes = L.rec_piece_bytes;
     A.rec_rk_off = L.rec_rk_off;
     A.rec_cap = L.rec_cap;
+    A.early_exit = L.early_exit ? 1 : 0;
     return A;
 }
 

@@ -86,6 +86,7 @@ struct asora_ctx {
     const void *keep_sig[5];    // n_H, x_HI, src_ijk, src_Q, src_R of that call
     int64_t keep_nsrc;
     float keep_Rmax;
+    bool keep_early;        // that call stopped its pyramids at their first opaque layer
     // the source order (bucketing) in d_order and the segment table: a
     // generation counted at every bucketing, and the one the keeping forward
     // made (-1: none), which a backward with its records may reuse
@@ -104,6 +105,9 @@ struct asora_ctx {
     int live_graphs;        // graphs recorded from this context and not yet freed: they
                             // hold its buffers' addresses, so no buffer may move
     std::map<std::string, std::vector<float>> tuned;   // autotune results by workload key
+    std::string dev_tag;    // device name and compute-unit count (part of the tuning keys)
+    asora_tune_progress_fn tune_cb;   // called after every timed autotune candidate (may be NULL)
+    void *tune_cb_user;
     // chemistry: counters (cells changed, cells whose n_e iteration did not
     // converge); the time step's <y> in two FP64 grids and one FP32 grid
     unsigned long long *d_chem_cnt;
@@ -251,6 +255,13 @@ extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, d
         return bail(fail(nullptr, ASORA_EHIP, "asora_init: hipGetDeviceProperties failed"));
     c->n_cu = prop.multiProcessorCount;
     c->max_lds = prop.sharedMemPerBlock;
+    {
+        char tag[96];
+        snprintf(tag, sizeof tag, "%s:%d", prop.gcnArchName, c->n_cu);
+        c->dev_tag = tag;
+        for (char &ch : c->dev_tag)
+            if (ch == ' ' || ch == '/') ch = '_';
+    }
     const long n3 = (long)N * N * N;
     if (hipMalloc(&c->d_tab, sizeof(TabNode) * n_tab) != hipSuccess ||
         hipMalloc(&c->d_m64, sizeof(double) * n_tab) != hipSuccess ||
@@ -347,11 +358,13 @@ static int type_of(const asora_ctx *c, float R)
     return R <= c->R_whole ? 0 : (R <= c->R_oct ? 1 : 2);
 }
 
-static asora_status get_layer_plan(asora_ctx *c, float R_cap, Plan *out);
+static asora_status get_layer_plan(asora_ctx *c, float R_cap, Plan *out, bool store = true);
 
-static asora_status get_plan(asora_ctx *c, int type, float R_cap, Plan *out)
+// store = false: the plan is not added to the context's table (no host
+// allocation; the allocation-free entry point plans every call)
+static asora_status get_plan(asora_ctx *c, int type, float R_cap, Plan *out, bool store = true)
 {
-    if (type == 3) return get_layer_plan(c, R_cap, out);
+    if (type == 3) return get_layer_plan(c, R_cap, out, store);
     const int Rsq = (int)std::floor((double)R_cap * (double)R_cap);
     const PlanKey key{type, Rsq};
     auto it = c->plans.find(key);
@@ -405,13 +418,13 @@ static asora_status get_plan(asora_ctx *c, int type, float R_cap, Plan *out)
         HIPCHK(c, fwd_occupancy(P.lds, &bpc));
     }
     P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
-    c->plans[key] = P;
+    if (store) c->plans[key] = P;
     *out = P;
     return ASORA_OK;
 }
 
 // Layer pieces: one wave per pyramid, the wave's LDS holds one layer.
-static asora_status get_layer_plan(asora_ctx *c, float R_cap, Plan *out)
+static asora_status get_layer_plan(asora_ctx *c, float R_cap, Plan *out, bool store)
 {
     const int Rsq = (int)std::floor((double)R_cap * (double)R_cap);
     const PlanKey key{c->tab_lds ? 3 : 5, Rsq};
@@ -445,7 +458,7 @@ static asora_status get_layer_plan(asora_ctx *c, float R_cap, Plan *out)
     int bpc = 0;
     HIPCHK(c, layer_occupancy(c->tab_lds != 0, P.waves, P.lds, &bpc));
     P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
-    c->plans[key] = P;
+    if (store) c->plans[key] = P;
     *out = P;
     return ASORA_OK;
 }
@@ -537,11 +550,18 @@ extern "C" asora_status asora_set_store_budget(asora_ctx *c, uint64_t bytes)
     return ASORA_OK;
 }
 
+// Largest source list of one call: the persistent kernels number their work
+// items (source, piece) in 32-bit integers, up to 24 pieces per source.
+static const int64_t kMaxSources = (int64_t)INT32_MAX / 24;
+
+extern "C" int64_t asora_max_sources(void) { return kMaxSources; }
+
 static asora_status check_common(asora_ctx *c, const float *n_H, const float *x_HI, int64_t n_src,
                                  const int32_t *ijk, const double *Q, float R_max)
 {
     if (!n_H || !x_HI) return fail(c, ASORA_EINVAL, "n_H and x_HI must not be NULL");
-    if (n_src < 0 || n_src > (int64_t)1 << 30) return fail(c, ASORA_EINVAL, "n_src out of range");
+    if (n_src < 0 || n_src > kMaxSources)
+        return fail(c, ASORA_EINVAL, "n_src=%lld out of [0, %lld]", (long long)n_src, (long long)kMaxSources);
     if (n_src > 0 && (!ijk || !Q)) return fail(c, ASORA_EINVAL, "source arrays must not be NULL");
     if (!(R_max >= 0.f) || !(R_max <= 4096.f))
         return fail(c, ASORA_EINVAL, "R_max must be in [0, 4096]");
@@ -598,50 +618,41 @@ extern "C" asora_status asora_raytrace_heating(asora_ctx *c, const float *n_H, c
                    stream);
 }
 
-static asora_status forward(asora_ctx *c, const float *n_H, const float *x_HI, int64_t n_src,
-                            const int32_t *src_ijk, const double *src_Q, const float *src_R, float R_max,
-                            float *gamma, float *heating, double *coldens_in, uint32_t flags,
-                            void *stream)
+// Device buffers of one forward call: n_HI and the rate accumulator in both
+// layouts, the control block (work counters, segment table, histogram), the
+// source keys and the scheduling order.
+struct FwdBufs {
+    double *nhi, *gacc, *nhi_T, *gacc_T;
+    int *ctl, *keys, *order;
+};
+
+// Plans of the piece kinds a forward up to R_max uses (plans[t], t <= *tmax;
+// kind 2 is skipped when the large kind is 3).
+static asora_status forward_plans(asora_ctx *c, float R_max, bool store, Plan plans[4], int *tmax_out)
 {
-    if (!ctx_ok(c)) return ASORA_ESTATE;
-    asora_status st = check_common(c, n_H, x_HI, n_src, src_ijk, src_Q, R_max);
-    if (st) return st;
-    if (!gamma) return fail(c, ASORA_EINVAL, "gamma must not be NULL");
-    if (coldens_in && n_src != 1) return fail(c, ASORA_EINVAL, "coldens_in requires n_src == 1");
-    if (flags & ~(ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_PROFILE | ASORA_STORE | ASORA_EARLY_EXIT))
-        return fail(c, ASORA_EINVAL, "unknown flags");
-    if (coldens_in && (flags & ASORA_EARLY_EXIT))
-        return fail(c, ASORA_EINVAL, "ASORA_EARLY_EXIT does not give entry columns (coldens_in)");
-    const bool prof = (flags & ASORA_PROFILE) != 0;
-    hipEvent_t *ev = c->pev[c->prof_count % kProfSlots];
-    HIPCHK(c, hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
-    const long n3 = (long)c->N * c->N * c->N;
-    // piece kinds in use: 0 and 1 up to R_oct, then the large kind (2 or 3)
     const int tbig = type_of(c, R_max);
     const int tmax = tbig == 2 ? c->big_kind : tbig;
-    const bool layers = tmax == 3;
-    Plan plans[4];
     for (int t = 0; t <= tmax; ++t) {
         if (t == 2 && tmax == 3) continue;
         const float cap = t == tmax ? R_max : (t == 0 ? c->R_whole : c->R_oct);
-        if ((st = get_plan(c, t, cap, &plans[t]))) return st;
+        asora_status st = get_plan(c, t, cap, &plans[t], store);
+        if (st) return st;
     }
-    if ((st = ensure_src_cap(c, n_src))) return st;
-    if (layers && (st = ensure_layer_buffers(c))) return st;
-    if (heating) {
-        if (!c->d_hacc) HIPCHK(c, hipMalloc(&c->d_hacc, sizeof(double) * n3));
-        if (layers && !c->d_hacc_T) HIPCHK(c, hipMalloc(&c->d_hacc_T, sizeof(double) * n3));
-    }
-    // ASORA_STORE: keep the pyramids' column records for the adjoint when
-    // they fit the budget; any other forward with the flag replaces them
-    bool keep = false;
-    if (flags & ASORA_STORE) {
-        c->keep_valid = false;
-        c->keep_need = layers ? (size_t)n_src * 24 * plans[3].keep_bytes : 0;
-        if ((st = reserve_keep(c, c->keep_need, &keep))) return st;
-    }
+    *tmax_out = tmax;
+    return ASORA_OK;
+}
 
+// The launches of one forward call on buffers B (no allocation).
+static asora_status forward_launch(asora_ctx *c, const FwdBufs &B, const Plan plans[4], int tmax,
+                                   const float *n_H, const float *x_HI, int64_t n_src, const int32_t *src_ijk,
+                                   const double *src_Q, const float *src_R, float R_max, float *gamma,
+                                   float *heating, double *coldens_in, uint32_t flags, bool keep,
+                                   hipStream_t s)
+{
+    const bool prof = (flags & ASORA_PROFILE) != 0;
+    hipEvent_t *ev = c->pev[c->prof_count % kProfSlots];
+    const long n3 = (long)c->N * c->N * c->N;
+    const bool layers = tmax == 3;
     FwdLaunch F;
     F.N = c->N;
     F.alpha = c->alpha;
@@ -650,17 +661,17 @@ static asora_status forward(asora_ctx *c, const float *n_H, const float *x_HI, i
     F.reading = c->reading;
     F.tp = c->tp;
     F.tab = c->d_tab;
-    F.nHI = c->d_nhi;
-    F.gacc = c->d_gacc;
+    F.nHI = B.nhi;
+    F.gacc = B.gacc;
     F.coldens = coldens_in;
     F.ijk = src_ijk;
     F.Q = src_Q;
     F.R = src_R;
-    F.order = c->d_order;
-    F.ctl = c->d_ctl;
+    F.order = B.order;
+    F.ctl = B.ctl;
     F.err = c->d_err;
-    F.nHI_T = c->d_nhi_T;
-    F.gacc_T = c->d_gacc_T;
+    F.nHI_T = B.nhi_T;
+    F.gacc_T = B.gacc_T;
     F.keep = keep ? c->d_keep : nullptr;
     F.keep_piece_bytes = layers ? plans[3].keep_bytes : 0;
     F.keep_cap = layers ? plans[3].rec_cap : 0;
@@ -674,20 +685,16 @@ static asora_status forward(asora_ctx *c, const float *n_H, const float *x_HI, i
     F.dP0_h = c->dP0_h;
 
     if (prof) HIPCHK(c, hipEventRecord(ev[0], s));
-    HIPCHK(c, launch_prologue(s, n_H, x_HI, c->d_nhi, c->d_gacc, coldens_in, n3, c->d_ctl,
-                              kCtlSize, c->n_cu));
-    if (layers) HIPCHK(c, launch_transpose_prologue(s, n_H, x_HI, c->d_nhi_T, c->d_gacc_T, c->N));
-    ++c->nhi_gen;
+    HIPCHK(c, launch_prologue(s, n_H, x_HI, B.nhi, B.gacc, coldens_in, n3, B.ctl, kCtlSize, c->n_cu));
+    if (layers) HIPCHK(c, launch_transpose_prologue(s, n_H, x_HI, B.nhi_T, B.gacc_T, c->N));
     if (heating) {
         HIPCHK(c, launch_zero(s, c->d_hacc, n3, c->n_cu));
         if (layers) HIPCHK(c, launch_zero(s, c->d_hacc_T, n3, c->n_cu));
     }
     const bool bucketed = n_src > 0 && !(flags & ASORA_PLAIN);
-    if (bucketed) {
+    if (bucketed)
         HIPCHK(c, launch_bucketing(s, src_R, src_ijk, n_src, c->N, R_max, c->R_whole, c->R_oct,
-                                   tmax == 3 ? 3 : 2, c->d_keys, c->d_ctl, c->d_order, c->d_err));
-        ++c->order_gen;
-    }
+                                   tmax == 3 ? 3 : 2, B.keys, B.ctl, B.order, c->d_err));
     if (prof) HIPCHK(c, hipEventRecord(ev[1], s));
     if (n_src > 0) {
         if (flags & ASORA_PLAIN) {
@@ -721,22 +728,65 @@ static asora_status forward(asora_ctx *c, const float *n_H, const float *x_HI, i
     }
     if (prof) HIPCHK(c, hipEventRecord(ev[2], s));
     if (layers)
-        HIPCHK(c, launch_transpose_finalize(s, c->d_gacc, c->d_gacc_T, gamma, c->N,
-                                            (flags & ASORA_ACCUMULATE) ? 1 : 0));
+        HIPCHK(c, launch_transpose_finalize(s, B.gacc, B.gacc_T, gamma, c->N, (flags & ASORA_ACCUMULATE) ? 1 : 0));
     else
-        HIPCHK(c, launch_finalize(s, c->d_gacc, gamma, n3, (flags & ASORA_ACCUMULATE) ? 1 : 0,
-                                  c->n_cu));
+        HIPCHK(c, launch_finalize(s, B.gacc, gamma, n3, (flags & ASORA_ACCUMULATE) ? 1 : 0, c->n_cu));
     if (heating && layers)
         HIPCHK(c, launch_transpose_finalize(s, c->d_hacc, c->d_hacc_T, heating, c->N,
                                             (flags & ASORA_ACCUMULATE) ? 1 : 0));
     else if (heating)
-        HIPCHK(c, launch_finalize(s, c->d_hacc, heating, n3, (flags & ASORA_ACCUMULATE) ? 1 : 0,
-                                  c->n_cu));
+        HIPCHK(c, launch_finalize(s, c->d_hacc, heating, n3, (flags & ASORA_ACCUMULATE) ? 1 : 0, c->n_cu));
     if (prof) {
         HIPCHK(c, hipEventRecord(ev[3], s));
         c->prof_count++;
         if (c->prof_pending < kProfSlots) c->prof_pending++;
     }
+    return ASORA_OK;
+}
+
+static asora_status forward(asora_ctx *c, const float *n_H, const float *x_HI, int64_t n_src,
+                            const int32_t *src_ijk, const double *src_Q, const float *src_R, float R_max,
+                            float *gamma, float *heating, double *coldens_in, uint32_t flags,
+                            void *stream)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    asora_status st = check_common(c, n_H, x_HI, n_src, src_ijk, src_Q, R_max);
+    if (st) return st;
+    if (!gamma) return fail(c, ASORA_EINVAL, "gamma must not be NULL");
+    if (coldens_in && n_src != 1) return fail(c, ASORA_EINVAL, "coldens_in requires n_src == 1");
+    if (flags & ~(ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_PROFILE | ASORA_STORE | ASORA_EARLY_EXIT))
+        return fail(c, ASORA_EINVAL, "unknown flags");
+    if (coldens_in && (flags & ASORA_EARLY_EXIT))
+        return fail(c, ASORA_EINVAL, "ASORA_EARLY_EXIT does not give entry columns (coldens_in)");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const long n3 = (long)c->N * c->N * c->N;
+    Plan plans[4];
+    int tmax = 0;
+    if ((st = forward_plans(c, R_max, true, plans, &tmax))) return st;
+    const bool layers = tmax == 3;
+    if ((st = ensure_src_cap(c, n_src))) return st;
+    if (layers && (st = ensure_layer_buffers(c))) return st;
+    if (heating) {
+        if (!c->d_hacc) HIPCHK(c, hipMalloc(&c->d_hacc, sizeof(double) * n3));
+        if (layers && !c->d_hacc_T) HIPCHK(c, hipMalloc(&c->d_hacc_T, sizeof(double) * n3));
+    }
+    // ASORA_STORE: keep the pyramids' column records for the adjoint when
+    // they fit the budget; any other forward with the flag replaces them
+    bool keep = false;
+    if (flags & ASORA_STORE) {
+        c->keep_valid = false;
+        c->keep_need = layers ? (size_t)n_src * 24 * plans[3].keep_bytes : 0;
+        if ((st = reserve_keep(c, c->keep_need, &keep))) return st;
+    }
+    // n_HI and the source order are rewritten from here on (even if a launch fails)
+    ++c->nhi_gen;
+    const bool bucketed = n_src > 0 && !(flags & ASORA_PLAIN);
+    if (bucketed) ++c->order_gen;
+    const FwdBufs B{c->d_nhi, c->d_gacc, c->d_nhi_T, c->d_gacc_T, c->d_ctl, c->d_keys, c->d_order};
+    if ((st = forward_launch(c, B, plans, tmax, n_H, x_HI, n_src, src_ijk, src_Q, src_R, R_max, gamma, heating,
+                             coldens_in, flags, keep, s)))
+        return st;
     if (keep) {
         c->keep_valid = true;
         c->keep_order_gen = bucketed ? c->order_gen : -1;
@@ -748,6 +798,7 @@ static asora_status forward(asora_ctx *c, const float *n_H, const float *x_HI, i
         c->keep_sig[4] = src_R;
         c->keep_nsrc = n_src;
         c->keep_Rmax = R_max;
+        c->keep_early = (flags & ASORA_EARLY_EXIT) != 0;
     }
     return ASORA_OK;
 }
@@ -931,10 +982,11 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
     if (st) return st;
     if (!dL_dgamma || !dL_dnH || !dL_dxHI || (n_src > 0 && !dL_dQ))
         return fail(c, ASORA_EINVAL, "gradient buffers must not be NULL");
-    if (flags & ~(ASORA_ACCUMULATE | ASORA_PROFILE | ASORA_STORE))
+    if (flags & ~(ASORA_ACCUMULATE | ASORA_PROFILE | ASORA_STORE | ASORA_EARLY_EXIT))
         return fail(c, ASORA_EINVAL, "unknown flags");
     const bool prof = (flags & ASORA_PROFILE) != 0;
     const bool acc = (flags & ASORA_ACCUMULATE) != 0;
+    const bool early = (flags & ASORA_EARLY_EXIT) != 0;
     hipEvent_t *ev = c->pev[c->prof_count % kProfSlots];
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
@@ -943,9 +995,12 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
     const int tmax = tbig == 2 ? c->big_kind : tbig;
     const bool layers = tmax == 3;
     // ASORA_STORE: the records kept by the forward call with these inputs
+    // (and the same early-exit choice: records of an early-exit forward end at
+    // the opaque layers)
     const bool kept = (flags & ASORA_STORE) && layers && c->keep_valid && c->keep_nsrc == n_src &&
                       c->keep_Rmax == R_max && c->keep_sig[0] == n_H && c->keep_sig[1] == x_HI &&
-                      c->keep_sig[2] == src_ijk && c->keep_sig[3] == src_Q && c->keep_sig[4] == src_R;
+                      c->keep_sig[2] == src_ijk && c->keep_sig[3] == src_Q && c->keep_sig[4] == src_R &&
+                      c->keep_early == early;
     Plan plans[4];
     size_t store_need = 0;
     for (int t = 0; t <= tmax; ++t) {
@@ -1022,6 +1077,7 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
         L.rec_rk_off = kept ? plans[3].rec_bytes : 0;
         L.rec_cap = layers ? plans[3].rec_cap : 0;
         L.split = c->adj_split != 0;
+        L.early_exit = early;
         for (int t = tmax; t >= 0; --t) {
             if (t == 2 && layers) continue;
             L.type = t;
@@ -1073,7 +1129,7 @@ extern "C" asora_status asora_graph_create(asora_ctx *c, const float *n_H, const
     if (flags & ~(ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_STORE | ASORA_EARLY_EXIT))
         return fail(c, ASORA_EINVAL, "asora_graph_create: flags may be ACCUMULATE, PLAIN, STORE, EARLY_EXIT");
     const bool adj = dL_dgamma != nullptr;
-    const uint32_t ff = flags, bf = flags & (ASORA_ACCUMULATE | ASORA_STORE);
+    const uint32_t ff = flags, bf = flags & (ASORA_ACCUMULATE | ASORA_STORE | ASORA_EARLY_EXIT);
     HIPCHK(c, hipSetDevice(c->device));
     // the inputs may still be in production on other streams
     HIPCHK(c, hipDeviceSynchronize());
@@ -1148,6 +1204,106 @@ extern "C" asora_status asora_graph_free(asora_graph *g)
 }
 
 // ---------------------------------------------------------------------------
+// Tuning keys: the device, the grid, the number of sources, R_max, the pass
+// count and a 64-bin histogram of the radii (FNV-1a hash of the counts), so
+// that a tuning found once is reused for workloads of the same shape, in this
+// process (the context's table) or across processes (asora_tuning_save /
+// asora_tuning_load).
+static asora_status tuning_key(asora_ctx *c, const float *src_R, int64_t n_src, float R_max, int passes,
+                               void *stream, std::string *key)
+{
+    constexpr int kBins = 64;
+    uint64_t cnt[kBins] = {};
+    if (src_R && n_src > 0) {
+        std::vector<float> R((size_t)n_src);
+        HIPCHK(c, hipMemcpyAsync(R.data(), src_R, sizeof(float) * (size_t)n_src, hipMemcpyDeviceToHost,
+                                 (hipStream_t)stream));
+        HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+        for (float r : R) {
+            int b = R_max > 0.f ? (int)((double)r / (double)R_max * kBins) : 0;
+            b = b < 0 ? 0 : (b >= kBins ? kBins - 1 : b);
+            cnt[b]++;
+        }
+    } else {
+        cnt[kBins - 1] = (uint64_t)n_src;
+    }
+    uint64_t h = 1469598103934665603ull;
+    for (int b = 0; b < kBins; ++b)
+        for (int k = 0; k < 8; ++k) {
+            h ^= (cnt[b] >> (8 * k)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s/N%d/n%lld/R%.4f/h%016llx/p%d", c->dev_tag.c_str(), c->N, (long long)n_src,
+             (double)R_max, (unsigned long long)h, passes);
+    *key = buf;
+    return ASORA_OK;
+}
+
+static const int kTuneVals = 8;   // the seven tuning values and the best time (ms)
+
+// Entries of a tuning file: one per line, the key and kTuneVals numbers.
+static bool read_tuning_file(const char *path, std::map<std::string, std::vector<float>> *out)
+{
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        char key[300];
+        float v[kTuneVals];
+        if (sscanf(line, "%299s %f %f %f %f %f %f %f %f", key, &v[0], &v[1], &v[2], &v[3], &v[4], &v[5],
+                   &v[6], &v[7]) == 1 + kTuneVals)
+            (*out)[key] = std::vector<float>(v, v + kTuneVals);
+    }
+    fclose(f);
+    return true;
+}
+
+extern "C" asora_status asora_set_tune_progress(asora_ctx *c, asora_tune_progress_fn fn, void *user)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    c->tune_cb = fn;
+    c->tune_cb_user = user;
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_tuning_load(asora_ctx *c, const char *path, int32_t *n_loaded)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    if (!path) return fail(c, ASORA_EINVAL, "asora_tuning_load: path is NULL");
+    std::map<std::string, std::vector<float>> m;
+    if (n_loaded) *n_loaded = 0;
+    if (!read_tuning_file(path, &m)) return ASORA_OK;   // no file yet: nothing known
+    for (auto &kv : m) c->tuned[kv.first] = kv.second;
+    if (n_loaded) *n_loaded = (int32_t)m.size();
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_tuning_save(asora_ctx *c, const char *path)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    if (!path) return fail(c, ASORA_EINVAL, "asora_tuning_save: path is NULL");
+    std::map<std::string, std::vector<float>> m;
+    read_tuning_file(path, &m);   // entries of other workloads and devices stay
+    for (auto &kv : c->tuned) m[kv.first] = kv.second;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return fail(c, ASORA_EINVAL, "asora_tuning_save: cannot write %s", tmp.c_str());
+    fprintf(f, "# ASORA autotuner results: key (device:CUs/N/n_src/R_max/radius histogram/passes), "
+               "R_whole R_oct max_waves pyramid_sweep table_place adj_waves adj_rate best_ms\n");
+    for (auto &kv : m) {
+        fprintf(f, "%s", kv.first.c_str());
+        for (float v : kv.second) fprintf(f, " %.9g", (double)v);
+        fprintf(f, "\n");
+    }
+    const bool ok = fclose(f) == 0;
+    if (!ok || rename(tmp.c_str(), path) != 0)
+        return fail(c, ASORA_EINVAL, "asora_tuning_save: cannot write %s", path);
+    return ASORA_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Autotuner: times candidate scheduling parameters on the caller's inputs and
 // keeps the fastest.  Coordinate descent over the large-source sweep (layers,
 // shells), the table's place, the waves per work-group, the layer adjoint's
@@ -1169,9 +1325,9 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
         return fail(c, ASORA_EINVAL, "asora_autotune: need max_report >= 0 and a report array");
     if (c->live_graphs) return pinned(c, "the tuning");
     if (n_report) *n_report = 0;
-    char keybuf[96];
-    snprintf(keybuf, sizeof keybuf, "%lld/%.4f/%d", (long long)n_src, (double)R_max, passes);
-    const std::string key(keybuf);
+    HIPCHK(c, hipSetDevice(c->device));
+    std::string key;
+    if ((st = tuning_key(c, src_R, n_src, R_max, passes, stream, &key))) return st;
     auto hit = c->tuned.find(key);
     if (hit != c->tuned.end() && !(flags & ASORA_TUNE_RETUNE)) {
         const std::vector<float> &v = hit->second;
@@ -1179,7 +1335,6 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
         if (!st && best_ms) *best_ms = v[7];
         return st;
     }
-    HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     const size_t n3 = (size_t)c->N * c->N * c->N;
     float *gamma = nullptr, *dn = nullptr, *dx = nullptr;
@@ -1246,13 +1401,11 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
         }
         std::sort(t, t + 3);
         *ms = t[1];
+        const float v[kTuneRow] = {k.w, k.o, (float)k.waves, (float)k.sweep, (float)k.place,
+                                   (float)k.aw, (float)k.ar, *ms};
+        if (c->tune_cb) c->tune_cb(v, f == sf ? 1 : 0, c->tune_cb_user);
         if (f != sf) return ASORA_OK;
-        if (nrep < max_report) {
-            float *row = report + kTuneRow * nrep;
-            const float v[kTuneRow] = {k.w, k.o, (float)k.waves, (float)k.sweep, (float)k.place,
-                                       (float)k.aw, (float)k.ar, *ms};
-            std::copy(v, v + kTuneRow, row);
-        }
+        if (nrep < max_report) std::copy(v, v + kTuneRow, report + kTuneRow * nrep);
         ++nrep;
         return ASORA_OK;
     };

@@ -477,10 +477,10 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
     long off = 0;     // first cell of layer m in the record
     long choff = 0;   // first chunk of layer m in the record
     const double opaque = layer_opaque(A.tp.tau_hi);
-    bool rec_on = KEEP;   // the record is written up to the first opaque layer
-    int m_last = Mx;      // the last layer the adjoint visits
-    // the first opaque layer is watched for the record or to stop there
-    bool watch = KEEP || A.early_exit;
+    // the last layer swept, recorded and visited by the adjoint: every layer,
+    // unless the early exit stops the pyramid at its first opaque layer
+    int m_last = Mx;
+    const bool watch = A.early_exit;
     for (int m = 1; m <= Mx; ++m) {
         const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
         const double inv_m = rcp_f64((double)m);
@@ -504,14 +504,14 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
             bool want = false;
             if (act) {
                 lay[pos] = lc.h;
-                if (KEEP && rec_on) rec.h[off + g] = lc.h;
+                if (KEEP) rec.h[off + g] = lc.h;
                 if (lc.owned) {
                     if (A.coldens) A.coldens[layer_std_index(L, N, m, u, v)] = lc.Nin;
                     want = A.sigma0 * lc.Nin < A.tp.tau_hi;
                 }
             }
             const uint64_t mask = __ballot(want);
-            if (KEEP && rec_on && lane == 0) rec.lit[choff + c] = mask;
+            if (KEEP && lane == 0) rec.lit[choff + c] = mask;
             if (watch) opq = opq && __ballot(act && !(A.sigma0 * lc.Nout >= opaque)) == 0;
             if (want) {
                 const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -533,10 +533,8 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
         off += r.total;
         choff += nch;
         if (watch && opq) {
-            rec_on = false;
-            watch = false;
             m_last = m;
-            if (A.early_exit) break;   // every later cell has a zero rate
+            break;   // every later cell has a zero rate
         }
     }
     if (tail > head) {

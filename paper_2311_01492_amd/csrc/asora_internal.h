@@ -125,6 +125,7 @@ struct AdjLaunch {
     size_t rec_rk_off;        // kept records: offset of the rate coefficients
     long rec_cap;             // cells (and listed cells) per pyramid record
     bool split;               // layer pieces: rate terms of dense chunks in the reverse pass
+    bool early_exit;          // layer pieces: stop at the first opaque layer
 };
 
 size_t adj_region_bytes(int ring_cap, int row_cap, int shell_cap);

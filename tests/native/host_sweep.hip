@@ -174,16 +174,17 @@ extern "C" int hc_raytrace(int N, double alpha, double sigma0, int n, double lg_
 // given, fills the column record as the kernels do (exit columns in rectangle
 // order, listed cells in chunk and lane order; with rec->rk the rate
 // coefficients of the cells with a rate in this order of evaluation, and
-// their number after the three arrays of cap entries).  The record stops
-// after the first layer whose cells all leave opaque (layer_opaque), as in the
-// kernels; *m_last (may be NULL) receives that layer (Mx if none).  Returns -6
-// if a neighbour of non-zero weight is read from a slot that does not hold
-// layer m - 1, -8 if a cell falls outside the S x S layer buffer, -10 if a
-// cell after an opaque layer has a rate.
+// their number after the three arrays of cap entries).  With `early` the
+// record stops after the first layer whose cells all leave opaque
+// (layer_opaque), as in the kernels with the early exit; *m_last (may be
+// NULL) receives that layer (Mx without `early` or if there is none).  Every
+// layer is swept either way.  Returns -6 if a neighbour of non-zero weight is
+// read from a slot that does not hold layer m - 1, -8 if a cell falls outside
+// the S x S layer buffer, -10 if a cell after an opaque layer has a rate.
 static int layer_forward_piece(const LayerPiece &L, const LayerX &X, int Rsq, const TabNode *T,
                                const double *m64, const TabParams &tp, double coef, int S, double *lay,
                                int *lay_id, double *acc, double *coldens, int N, LayerRecord *rec, long cap,
-                               int *m_last = nullptr)
+                               int *m_last = nullptr, bool early = false)
 {
     long nlit = 0;
     bool rec_on = rec != nullptr;
@@ -250,9 +251,9 @@ static int layer_forward_piece(const LayerPiece &L, const LayerX &X, int Rsq, co
         choff += nch;
         if (opq && !past_opaque) {
             past_opaque = true;
-            if (m_last) *m_last = m;
+            if (m_last && early) *m_last = m;
         }
-        if (rec_on && opq) {
+        if (rec_on && opq && early) {
             rec_on = false;
             if (rec->rk) ((uint64_t *)rec->rk)[3 * cap + 1] = (uint64_t)m;
         }
@@ -360,7 +361,8 @@ extern "C" int hc_raytrace_layer(int N, double alpha, double sigma0, int n, doub
 // mode 1: chunks with at least kDenseChunk cells with a rate evaluate them in
 // (R), as the kernel's split form; 0: all are gathered in (G); 2: the forward
 // pass keeps the rate coefficients in the record, as a forward with kept
-// records does, and (R) reads them (no (G)).
+// records does, and (R) reads them (no (G)).  mode | 4: the early exit (every
+// pass stops at the pyramid's first opaque layer); otherwise all layers.
 // Returns -6 if a neighbour of non-zero weight is not an active cell of layer
 // m - 1, -7 if a chunk mask marks an inactive lane, -9 if (mode 2) the count
 // of cells with a rate disagrees with the chunk masks.
@@ -374,6 +376,8 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
     // stats (may be NULL): pieces whose adjoint stops before their last
     // layer, cells in the layers the adjoint visits, cells of all layers
     if (stats) stats[0] = stats[1] = stats[2] = 0;
+    const bool early = (mode & 4) != 0;
+    mode &= 3;
     const int dense_at = mode == 1 ? kDenseChunk : 65;
     const bool kept = mode == 2;
     HostLayerSetup H;
@@ -410,7 +414,7 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
             std::memset(recmem.data(), 0xff, recmem.size());
             int Mt = Mx;   // the last layer (G) and (R) visit
             int st = layer_forward_piece(L, X, Rsq, H.T.data(), H.m64.data(), H.tp, coef, S, cols.data(),
-                                         cols_id.data(), nullptr, nullptr, N, &rec, H.cap, &Mt);
+                                         cols_id.data(), nullptr, nullptr, N, &rec, H.cap, &Mt, early);
             if (st) return st;
             if (stats) {
                 stats[0] += Mt < Mx;

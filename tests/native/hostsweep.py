@@ -108,14 +108,16 @@ def rows(N, type_, piece, Rsq, q):
 
 def raytrace_grad(N, cell_cm, sigma0, table, n_H, x_HI, ijk, Q, R, gbar, tau_w=0.6, reading=0,
                   type_force=-1, R_whole=10.0, R_oct=30.0, layers=False, split=True, kept=False,
-                  stats=None):
+                  stats=None, early_exit=False):
     """(dL/dn_H, dL/dx_HI, dL/dQ) for dL/dGamma = gbar (FP64); layers: every
     source as layer pyramids, the rate terms of dense chunks in the reverse
     pass (split) or all gathered first, or (kept) taken from coefficients the
     forward pass stored, as with records kept by the forward.  stats (a dict,
     layers only) receives n_stopped: the pyramids whose adjoint stopped at an
     opaque layer before their last, and visited / total: cells (rectangle
-    slots) in the layers the adjoint visits / in all layers."""
+    slots) in the layers the adjoint visits / in all layers.  early_exit: every
+    pass of a pyramid stops at its first opaque layer (otherwise all layers
+    are visited)."""
     lib = load()
     P, dP = np.ascontiguousarray(table.P, np.float64), np.ascontiguousarray(table.dP, np.float64)
     nH = np.ascontiguousarray(n_H, np.float32)
@@ -131,7 +133,8 @@ def raytrace_grad(N, cell_cm, sigma0, table, n_H, x_HI, ijk, Q, R, gbar, tau_w=0
         st = lib.hc_raytrace_layer_grad(N, cell_cm, sigma0, len(P), table.lg_lo, table.lg_hi, _p(P),
                                         _p(dP), float(tau_w), reading, _p(nH), _p(xH), len(Q), _p(ijk),
                                         _p(Q), _p(R), _p(gb), _p(nbar), _p(qbar),
-                                        2 if kept else (1 if split else 0), _p(st3))
+                                        (2 if kept else (1 if split else 0)) | (4 if early_exit else 0),
+                                        _p(st3))
         if stats is not None:
             stats.update(n_stopped=int(st3[0]), visited=int(st3[1]), total=int(st3[2]))
     else:

@@ -236,19 +236,30 @@ def test_kept_records_fall_back_to_recompute(asora, bb):
 
 def test_kept_records_of_an_early_exit_forward(asora, bb):
     """A forward with ASORA_EARLY_EXIT and ASORA_STORE keeps records up to each
-    pyramid's first opaque layer; the backward that reads them gives the
-    recomputing backward's gradients."""
+    pyramid's first opaque layer; the early-exit backward that reads them, the
+    early-exit backward that recomputes and the full backward (every layer)
+    give the same gradients, and the oracle's.  A backward without the flag
+    does not read those records (it recomputes every layer)."""
     print("case kept records early exit", flush=True)
     w, g, wt = _case("c2", N=48, n_src=24, R=(10.0, 22.0))
     gbar = _loss_grad(g, wt)
+    on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
+                                      w.src.R, gbar)
     ctx = asora.Asora(w.N, w.cell_cm, bb.P, bb.dP, bb.lg_lo, bb.lg_hi)
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
     nH, xH, ijk, Q, R, gb = t(w.n_H), t(w.x_HI), t(w.src.ijk), t(w.src.Q), t(w.src.R), t(gbar)
     ctx.raytrace(nH, xH, ijk, Q, R, store=True, early_exit=True)
     assert ctx.store_info()[0]
-    ks = ctx.backward(nH, xH, ijk, Q, R, gb, store=True)
+    ks = ctx.backward(nH, xH, ijk, Q, R, gb, store=True, early_exit=True)
+    re = ctx.backward(nH, xH, ijk, Q, R, gb, early_exit=True)
     rc = ctx.backward(nH, xH, ijk, Q, R, gb)
+    rs = ctx.backward(nH, xH, ijk, Q, R, gb, store=True)   # flags differ: recomputes
     ctx.check()
-    for a, b, name in zip(ks, rc, ("dL/dn_H", "dL/dx_HI", "dL/dQ")):
-        a, b = a.cpu().numpy(), b.cpu().numpy()
-        np.testing.assert_allclose(a, b, rtol=1e-9, atol=1e-12 * np.abs(b).max(), err_msg=name)
+    for a, b, c, d, o, name in zip(ks, re, rc, rs, (on, ox, oq), ("dL/dn_H", "dL/dx_HI", "dL/dQ")):
+        a, b, c, d = a.cpu().numpy(), b.cpu().numpy(), c.cpu().numpy(), d.cpu().numpy()
+        for x in (b, c, d):
+            np.testing.assert_allclose(a, x, rtol=1e-9, atol=1e-12 * np.abs(x).max(), err_msg=name)
+        if name == "dL/dQ":
+            np.testing.assert_allclose(a, o, rtol=1e-5)
+        else:
+            assert_grad_parity(a, o, 1e-5, what=name)

@@ -220,3 +220,31 @@ def test_early_exit_gives_the_full_sweeps_gamma(asora, bb, case):
     assert_parity(e, o, TOL)
     with pytest.raises(asora.AsoraError):
         ctx.raytrace(nH, xH, ijk[:1], Q[:1], R[:1], coldens=True, early_exit=True)
+
+
+def test_block_level_octant_kernels(asora, bb):
+    """Octant pieces whose four-shell ring does not fit several waves' LDS
+    regions (R up to 44 on 96^3: about 47 KB per wave next to the 32 KB table,
+    two per work-group) run one work-group per piece: the persistent block
+    kernel for the batched call and the block kernel per source for the
+    plain one.  Both against the oracle, and the adjoint of the same pieces
+    (one wave per work-group) against the oracle's reverse mode."""
+    print("case block-level octant kernels", flush=True)
+    w = make_workload("c2", N=96, n_src=6, R=(30.0, 44.0))
+    ctx = _ctx(asora, w, bb)
+    ctx.set_tuning(R_oct=45.0)   # every source is swept as eight octants
+    o = _orc(w, bb)
+    for plain in (False, True):
+        assert_parity(_gpu(ctx, w, plain=plain), o, TOL, what=f"gamma (plain={plain})")
+    wt = np.random.default_rng(5).standard_normal(o.shape)
+    gbar = wt / ((o + 1e-20) * math.log(10))
+    on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R,
+                                      gbar)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    nH, xH = _dev(w)
+    dn, dx, dq = ctx.backward(nH, xH, t(w.src.ijk), t(w.src.Q), t(w.src.R), t(gbar))
+    ctx.check()
+    from tests.parity import assert_grad_parity
+    assert_grad_parity(dn.cpu().numpy(), on, 1e-5, what="dL/dn_H")
+    assert_grad_parity(dx.cpu().numpy(), ox, 1e-5, what="dL/dx_HI")
+    np.testing.assert_allclose(dq.cpu().numpy(), oq, rtol=1e-5)

@@ -99,7 +99,7 @@ def test_recorded_step_pins_buffers(asora, bb):
 
 
 @pytest.mark.parametrize("passes", [1, 2])
-def test_autotune_keeps_results(asora, bb, passes):
+def test_autotune_keeps_results(asora, bb, passes, tmp_path):
     """The autotuner times candidates, keeps the fastest, caches it per
     workload, and the tuned context still matches the oracle."""
     print("case autotune passes", passes, flush=True)
@@ -123,6 +123,20 @@ def test_autotune_keeps_results(asora, bb, passes):
                    adj_rate=1)
     best2, rep2 = ctx.autotune(nH, xH, ijk, Q, R, passes=passes)   # cached: no timing
     assert rep2 == [] and best2 == best and ctx.get_tuning() == tun
+    # across processes: saved to a file, loaded by a fresh context, found by
+    # the autotuner's key without timing; other radii make another key
+    path = tmp_path / "tuning.txt"
+    ctx.save_tuning(str(path))
+    assert len([l for l in path.read_text().splitlines() if not l.startswith("#")]) == 1
+    fresh = asora.Asora(w.N, w.cell_cm, bb.P, bb.dP, bb.lg_lo, bb.lg_hi)
+    assert fresh.load_tuning(str(tmp_path / "missing.txt")) == 0
+    assert fresh.load_tuning(str(path)) == 1
+    best3, rep3 = fresh.autotune(nH, xH, ijk, Q, R, passes=passes)
+    assert rep3 == [] and best3 == pytest.approx(best, rel=1e-6) and fresh.get_tuning() == tun
+    R_other = (R * 0.5).contiguous()
+    _, rep4 = fresh.autotune(nH, xH, ijk, Q, R_other, passes=passes)
+    assert len(rep4) >= 8
+    fresh.close()
     o = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
     g = ctx.raytrace(nH, xH, ijk, Q, R)
     ctx.check()

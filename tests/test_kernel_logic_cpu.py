@@ -163,8 +163,10 @@ def test_row_enumeration_matches_brute_force(N):
 
 
 @pytest.mark.parametrize("kind", [dict(type_force=-1)] + KINDS +
-                         [dict(layers=True, split=False), dict(layers=True, kept=True)],
-                         ids=["by-radius"] + KIND_IDS + ["layers-gathered", "layers-kept"])
+                         [dict(layers=True, split=False), dict(layers=True, kept=True),
+                          dict(layers=True, early_exit=True), dict(layers=True, kept=True, early_exit=True)],
+                         ids=["by-radius"] + KIND_IDS + ["layers-gathered", "layers-kept", "layers-early",
+                                                         "layers-kept-early"])
 @pytest.mark.parametrize("tau_w,reading", [(0.6, 0), (math.inf, 0), (0.6, 1)])
 def test_adjoint_matches_oracle_reverse(bb, kind, tau_w, reading):
     """The library's per-cell adjoint, driven serially over the reversed
@@ -181,9 +183,14 @@ def test_adjoint_matches_oracle_reverse(bb, kind, tau_w, reading):
                                          w.src.ijk, w.src.Q, w.src.R, gbar, tau_w=tau_w,
                                          reading=reading, **kind, **({"stats": st} if "layers" in kind else {}))
     if "layers" in kind:
-        # some pyramids end their adjoint at an opaque layer (the record beyond
-        # it is left unwritten and poisoned in the emulation)
-        assert st["n_stopped"] > 0
+        if kind.get("early_exit"):
+            # some pyramids end their adjoint at an opaque layer (the record
+            # beyond it is left unwritten and poisoned in the emulation)
+            assert st["n_stopped"] > 0
+            assert st["visited"] < st["total"]
+        else:   # without the early exit every layer is visited
+            assert st["n_stopped"] == 0
+            assert st["visited"] == st["total"]
     from tests.parity import assert_grad_parity
     assert_grad_parity(hn, on, 1e-5, what="dL/dn_H")
     assert_grad_parity(hx, ox, 1e-5, what="dL/dx_HI")

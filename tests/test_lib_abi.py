@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     txt = open(os.path.join(ROOT, "include", "asora.h")).read()
-    return sorted(set(re.findall(r"^(?:asora_status|const char \*)\s*(asora_\w+)\(", txt, re.M)))
+    return sorted(set(re.findall(r"^(?:asora_status|const char \*|int64_t)\s*(asora_\w+)\(", txt, re.M)))
 
 
 @pytest.fixture(scope="module")
@@ -31,6 +31,15 @@ def test_exports_every_declared_symbol(pkg):
     lib = ctypes.CDLL(pkg.lib_path())
     for n in names:
         assert hasattr(lib, n), n
+
+
+def test_max_sources_fits_the_work_item_numbering(pkg):
+    """The kernels number (source, piece) work items in 32-bit integers, up to
+    24 pieces per source: the accepted source count keeps them in range."""
+    n = pkg.max_sources()
+    assert n * 24 <= 2 ** 31 - 1 < (n + 1) * 24
+    assert n >= 1_000_000   # the million-source workload fits one call
+    assert "asora_max_sources" in _declared()
 
 
 def test_table_blackbody_matches_oracle(pkg):
