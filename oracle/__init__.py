@@ -17,7 +17,8 @@ import subprocess
 
 import numpy as np
 
-from .tables import SIGMA0, Table, blackbody_heat_table, blackbody_table, grey_table  # noqa: F401
+from .tables import (SIGMA0, Table, blackbody_band_table, blackbody_heat_table,  # noqa: F401
+                     blackbody_table, grey_table)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "asora_oracle.c")
@@ -55,6 +56,9 @@ def _load():
         lib.oracle_shell_order.argtypes = [i, d, p, p, l]
         lib.oracle_neighbours.restype = i
         lib.oracle_neighbours.argtypes = [p, p, p]
+        lib.oracle_raytrace_he.restype = i
+        lib.oracle_raytrace_he.argtypes = [i, d, d, i, i, p, p, p, p, p, p, d, i, p, p, l, p, p, p, p, p, p,
+                                           p]
         _lib = lib
     return _lib
 
@@ -100,6 +104,45 @@ def raytrace(N, cell_cm, table: Table, n_H, x_HI, ijk, Q, R, sigma0=SIGMA0, tau_
     _check(st)
     gam = gam.reshape(N, N, N)
     return (gam, cd.reshape(N, N, N)) if coldens else gam
+
+
+def raytrace_helium(N, cell_cm, bands, n_H, x_HI, n_He, x_HeI, ijk, Q, R, sigma0=SIGMA0, tau_w=0.6,
+                    reading=0, coldens=False):
+    """Photoionization rates of HI and HeI (FP64, N^3 each) summed over
+    sources, for a spectrum in bands: `bands` is a sequence of (Table,
+    sigma_HI, sigma_HeI), each band's table P_b on its own nodes (the
+    photons of the band that survive an optical depth measured at its lower
+    edge) and the two cross-sections (cm^2) there.  n_HI = n_H x_HI and
+    n_HeI = n_He x_HeI are formed in FP64.  With coldens=True (single source)
+    also the entry columns of HI and HeI.  The readings are those listed in
+    asora_oracle.c above oracle_raytrace_he."""
+    lib = _load()
+    nhi = n_HI(n_H, x_HI).reshape(-1)
+    nhe = (_f64(n_He) * _f64(x_HeI)).reshape(-1)
+    assert nhi.size == N ** 3 and nhe.size == N ** 3
+    nb = len(bands)
+    ntab = bands[0][0].n
+    assert all(t.n == ntab for t, _, _ in bands)
+    lg_lo = _f64([t.lg_lo for t, _, _ in bands])
+    lg_hi = _f64([t.lg_hi for t, _, _ in bands])
+    P = _f64(np.concatenate([t.P for t, _, _ in bands]))
+    dP = _f64(np.concatenate([t.dP for t, _, _ in bands]))
+    sH = _f64([b[1] for b in bands])
+    sHe = _f64([b[2] for b in bands])
+    ijk = np.ascontiguousarray(ijk, dtype=np.int32).reshape(-1, 3)
+    Qa, Ra = _f64(Q).reshape(-1), _f64(R).reshape(-1)
+    gH, gHe = np.zeros(N ** 3), np.zeros(N ** 3)
+    cH = np.zeros(N ** 3) if coldens else None
+    cHe = np.zeros(N ** 3) if coldens else None
+    st = lib.oracle_raytrace_he(N, cell_cm, sigma0, nb, ntab, _ptr(lg_lo), _ptr(lg_hi), _ptr(P), _ptr(dP),
+                                _ptr(sH), _ptr(sHe), float(tau_w), int(reading), _ptr(nhi), _ptr(nhe),
+                                ijk.shape[0], _ptr(ijk), _ptr(Qa), _ptr(Ra), _ptr(gH), _ptr(gHe), _ptr(cH),
+                                _ptr(cHe))
+    _check(st)
+    shape = (N, N, N)
+    if coldens:
+        return gH.reshape(shape), gHe.reshape(shape), cH.reshape(shape), cHe.reshape(shape)
+    return gH.reshape(shape), gHe.reshape(shape)
 
 
 def raytrace_heating(N, cell_cm, heat_table: Table, n_H, x_HI, ijk, Q, R, sigma0=SIGMA0, tau_w=0.6,

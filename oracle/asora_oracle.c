@@ -550,3 +550,197 @@ int oracle_neighbours(const int32_t d[3], int32_t off_out[12], double s_out[4])
     }
     return nb.nn;
 }
+
+/* ------------------------------------------------------------------ */
+/* Hydrogen and helium: two absorbers (the extension the paper plans,   */
+/* Sections 2 and 6).  Readings where the paper is silent:              */
+/*  - the spectrum above 13.6 eV is split into bands at photon energies; */
+/*    band b has a table P_b(T): the photons of the band that survive an */
+/*    optical depth T measured at the band's lower edge, per photon      */
+/*    emitted above 13.6 eV, and the cross-sections sH[b], sHe[b] of HI  */
+/*    and HeI at that edge; within a band both cross-sections are taken  */
+/*    to follow the band's frequency shape, so the band's optical depth  */
+/*    is T_b = sH[b] N_HI + sHe[b] N_HeI;                                */
+/*  - a cell absorbs Q [P_b(T_in) - P_b(T_out)] photons of band b (eq.   */
+/*    sugg for the band), shared between the species in proportion to   */
+/*    their in-cell optical depths; a species' rate is its share over    */
+/*    n_i V (the limit sH[b] (-P_b') / (4 pi alpha^2 r^2) where the cell */
+/*    holds none of it or nothing absorbs);                              */
+/*  - both columns N_HI and N_HeI are carried by the same short          */
+/*    characteristics with the hydrogen method's weights, the optical-   */
+/*    depth factor taken on the HI column at the HI threshold            */
+/*    (sigma0 N_HI): helium does not absorb at 13.6 eV;                  */
+/*  - the source cell and its neighbours as for hydrogen, for each       */
+/*    column (reading A: the exit column n alpha ds / 2 in the           */
+/*    neighbour's direction).                                            */
+/* ------------------------------------------------------------------ */
+#define ORC_MAX_BANDS 8
+
+typedef struct {
+    int nb;
+    otab tab[ORC_MAX_BANDS];
+    double sH[ORC_MAX_BANDS], sHe[ORC_MAX_BANDS];
+} oband;
+
+/* Rates of one cell from its columns: n (species densities), Nin and dN
+ * (entry and in-cell columns of HI and HeI), the volume factor 4 pi (alpha
+ * r)^2 (alpha ds) as V, and the band loop.  Adds to *GH, *GHe. */
+static void he_cell_rates(const oband *bd, double Q, const double n[2], const double Nin[2],
+                          const double dN[2], double V, double area, double *GH, double *GHe)
+{
+    for (int b = 0; b < bd->nb; ++b) {
+        const double s[2] = {bd->sH[b], bd->sHe[b]};
+        double Tin = s[0] * Nin[0] + s[1] * Nin[1];
+        double dT = s[0] * dN[0] + s[1] * dN[1];
+        double dPin;
+        double Pin = tab_eval(&bd->tab[b], Tin, &dPin, NULL);
+        double Pout = tab_eval(&bd->tab[b], Tin + dT, NULL, NULL);
+        double A = Q * (Pin - Pout);          /* photons of band b absorbed in the cell */
+        double G[2];
+        for (int i = 0; i < 2; ++i) {
+            if (n[i] > 0 && dT > 0) {
+                double share = s[i] * dN[i] / dT;
+                G[i] = A * share / (n[i] * V);
+            } else if (dT > 0) {
+                G[i] = A * s[i] / (dT * area);   /* the same expression as n_i -> 0 */
+            } else {
+                G[i] = Q * s[i] * (-dPin) / area;
+            }
+        }
+        *GH += G[0];
+        *GHe += G[1];
+    }
+}
+
+static int sweep_source_he(const octx *c, const oband *bd, const double *nH, const double *nHe, int sid,
+                           const int s[3], double Q, double R, owork *w, double *NoutHe, double *gH,
+                           double *gHe, double *cdH, double *cdHe)
+{
+    const int N = c->N;
+    const double alpha = c->alpha, sig = c->sigma0;
+    const double four_pi = 4.0 * M_PI;
+    const double R2 = R * R;
+    long is = cell_index(N, s, (int[3]){0, 0, 0});
+    const double ns[2] = {nH[is], nHe[is]};
+    int Qmax = (int)ceil(sqrt(3.0) * R);
+
+    /* shell 0: the source cell, path half a cell, volume alpha^3 */
+    {
+        const double Nin[2] = {0, 0}, dN[2] = {ns[0] * alpha / 2, ns[1] * alpha / 2};
+        double GH = 0, GHe = 0;
+        /* area: the limit form with path half a cell, (alpha^3)/(alpha/2) */
+        he_cell_rates(bd, Q, ns, Nin, dN, alpha * alpha * alpha, 2 * alpha * alpha, &GH, &GHe);
+        gH[is] += GH;
+        gHe[is] += GHe;
+        w->Nout[is] = ns[0] * alpha / 2;
+        NoutHe[is] = ns[1] * alpha / 2;
+        w->stamp[is] = sid + 1;
+        w->shell[is] = 0;
+        if (cdH) cdH[is] = 0;
+        if (cdHe) cdHe[is] = 0;
+    }
+
+    for (int q = 1; q <= Qmax; ++q) {
+        for (int di = -q; di <= q; ++di) {
+            int rj = q - iabs_(di);
+            for (int dj = -rj; dj <= rj; ++dj) {
+                int rk = rj - iabs_(dj);
+                for (int t = 0; t < (rk == 0 ? 1 : 2); ++t) {
+                    int dk = (rk == 0) ? 0 : (t == 0 ? -rk : rk);
+                    int d[3] = {di, dj, dk};
+                    if (di < c->lo || di > c->hi || dj < c->lo || dj > c->hi ||
+                        dk < c->lo || dk > c->hi)
+                        continue;
+                    double r2 = (double)di * di + (double)dj * dj + (double)dk * dk;
+                    if (r2 > R2) continue;
+                    long ip = cell_index(N, s, d);
+                    int m = iabs_(di);
+                    if (iabs_(dj) > m) m = iabs_(dj);
+                    if (iabs_(dk) > m) m = iabs_(dk);
+                    double r = sqrt(r2);
+                    double ds = r / (double)m;
+                    onbr nb;
+                    neighbours(d, &nb);
+                    double numH = 0, numHe = 0, den = 0;
+                    for (int n = 0; n < nb.nn; ++n) {
+                        int *e = nb.off[n];
+                        double MH, MHe;
+                        if (e[0] == 0 && e[1] == 0 && e[2] == 0) {
+                            double path = (c->reading == 0) ? alpha * ds / 2 : alpha / 2;
+                            MH = ns[0] * path;
+                            MHe = ns[1] * path;
+                        } else {
+                            long ie = cell_index(N, s, e);
+                            if (w->stamp[ie] != sid + 1 || w->shell[ie] >= q) return ORC_ECAUSAL;
+                            MH = w->Nout[ie];
+                            MHe = NoutHe[ie];
+                        }
+                        /* the hydrogen method's weights, on the HI column */
+                        double wn = isfinite(c->tau_w) ? nb.s[n] / fmax(sig * MH, c->tau_w) : nb.s[n];
+                        numH += wn * MH;
+                        numHe += wn * MHe;
+                        den += wn;
+                    }
+                    const double Nin[2] = {numH / den, numHe / den};
+                    const double np[2] = {nH[ip], nHe[ip]};
+                    const double dN[2] = {np[0] * alpha * ds, np[1] * alpha * ds};
+                    double V = four_pi * (alpha * r) * (alpha * r) * (alpha * ds);
+                    double GH = 0, GHe = 0;
+                    he_cell_rates(bd, Q, np, Nin, dN, V, four_pi * alpha * alpha * r2, &GH, &GHe);
+                    gH[ip] += GH;
+                    gHe[ip] += GHe;
+                    if (cdH) cdH[ip] = Nin[0];
+                    if (cdHe) cdHe[ip] = Nin[1];
+                    w->Nout[ip] = Nin[0] + dN[0];
+                    NoutHe[ip] = Nin[1] + dN[1];
+                    w->stamp[ip] = sid + 1;
+                    w->shell[ip] = q;
+                }
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* Rates of HI and HeI (N^3 each, accumulated, caller zeroes) for nb bands:
+ * tables P, dP as nb x ntab (band b on its own nodes, uniform in log10 tau
+ * from lg_lo[b] to lg_hi[b]), cross-sections sH, sHe per band.  nH, nHe:
+ * n_HI and n_HeI.  Single source: the entry columns of both species
+ * (coldens_H, coldens_He, may be NULL). */
+int oracle_raytrace_he(int N, double alpha, double sigma0, int nb, int ntab, const double *lg_lo,
+                       const double *lg_hi, const double *P, const double *dP, const double *sH,
+                       const double *sHe, double tau_w, int reading, const double *nH, const double *nHe,
+                       long nsrc, const int32_t *ijk, const double *Q, const double *R, double *gH,
+                       double *gHe, double *coldens_H, double *coldens_He)
+{
+    if (nb < 1 || nb > ORC_MAX_BANDS) return ORC_EINVAL;
+    octx c;
+    int st = make_ctx(&c, N, alpha, sigma0, ntab, lg_lo[0], lg_hi[0], P, dP, tau_w, reading);
+    if (st) return st;
+    if ((coldens_H || coldens_He) && nsrc != 1) return ORC_EINVAL;
+    oband bd;
+    bd.nb = nb;
+    for (int b = 0; b < nb; ++b) {
+        if (!(lg_hi[b] > lg_lo[b]) || !(sH[b] >= 0) || !(sHe[b] >= 0)) return ORC_EINVAL;
+        for (int k = 0; k < ntab; ++k)
+            if (!(P[b * ntab + k] > 0) || !isfinite(P[b * ntab + k]) || !isfinite(dP[b * ntab + k]))
+                return ORC_EINVAL;
+        bd.tab[b] = (otab){ntab, lg_lo[b], lg_hi[b], P + (long)b * ntab, dP + (long)b * ntab};
+        bd.sH[b] = sH[b];
+        bd.sHe[b] = sHe[b];
+    }
+    long n3 = (long)N * N * N;
+    owork w;
+    double *NoutHe = (double *)malloc(sizeof(double) * n3);
+    if (!NoutHe || alloc_work(&w, n3)) { free(NoutHe); free_work(&w); return ORC_ENOMEM; }
+    for (long sI = 0; sI < nsrc; ++sI) {
+        if (!(R[sI] >= 0)) { st = ORC_EINVAL; break; }
+        int s[3] = {ijk[3 * sI], ijk[3 * sI + 1], ijk[3 * sI + 2]};
+        st = sweep_source_he(&c, &bd, nH, nHe, (int)sI, s, Q[sI], R[sI], &w, NoutHe, gH, gHe, coldens_H,
+                             coldens_He);
+        if (st) break;
+    }
+    free(NoutHe);
+    free_work(&w);
+    return st;
+}

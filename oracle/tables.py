@@ -11,6 +11,13 @@ so that P(0) = 1, and its derivative dP/dtau, for
   where phi(x) = x^2 / (e^x - 1) is the photon-number spectrum L_nu/(h nu);
 * grey opacity (sigma = sigma0), where P = exp(-tau) exactly;
 
+the band tables of the same black body split at photon energies (several
+absorbers, hydrogen and helium): with a band [x_a, x_b) and its optical depth
+tau measured at the lower edge x_a,
+      P_b(tau)  =  int_xa^xb phi(x) exp(-tau (x/x_a)^-alpha) dx / int_x0^inf phi(x) dx,
+so that the bands of a spectrum with tau_b = tau (x_a/x0)^-alpha add up to
+P(tau);
+
 and the photo-heating table of the same black body (the energy analogue of
 eq. tables: the paper leaves heating out and names it as a planned
 extension, Sections 2 and 6), in eV per emitted photon,
@@ -74,6 +81,38 @@ def blackbody_P(tau: float, T: float = 5e4, alpha: float = 2.8):
     P = _integral(lambda x: phi(x) * math.exp(-tau * (x / x0) ** -alpha), x0) / norm
     dP = -_integral(lambda x: phi(x) * (x / x0) ** -alpha * math.exp(-tau * (x / x0) ** -alpha), x0) / norm
     return P, dP
+
+
+def blackbody_band_P(tau: float, e_lo: float, e_hi: float, T: float = 5e4, alpha: float = 2.8):
+    """(P_b(tau), P_b'(tau)) of the band [e_lo, e_hi) eV (e_hi = inf: open),
+    tau measured at e_lo, per photon emitted above 13.6 eV."""
+    kT = K_B_EV * T
+    x0, xa = E_TH_EV / kT, e_lo / kT
+    xb = e_hi / kT if math.isfinite(e_hi) else _BREAKS[-1]
+    phi = lambda x: x * x * math.exp(-x) / -math.expm1(-x)
+    norm = _integral(phi, x0)
+
+    def band(f):
+        pts = [xa] + [b for b in _BREAKS if xa + 1e-9 < b < xb] + [xb]
+        return sum(quad(f, a, b, epsabs=0.0, epsrel=1e-13, limit=400)[0] for a, b in zip(pts[:-1], pts[1:]))
+
+    P = band(lambda x: phi(x) * math.exp(-tau * (x / xa) ** -alpha)) / norm
+    dP = -band(lambda x: phi(x) * (x / xa) ** -alpha * math.exp(-tau * (x / xa) ** -alpha)) / norm
+    return P, dP
+
+
+@functools.lru_cache(maxsize=16)
+def blackbody_band_table(e_lo: float, e_hi: float, T: float = 5e4, alpha: float = 2.8, n: int = 2000,
+                         lg_lo: float = -20.0, lg_hi: float = 2.5) -> Table:
+    """P_b and P_b' of one band on n nodes uniform in log10 tau."""
+    taus = 10.0 ** np.linspace(lg_lo, lg_hi, n)
+    P = np.empty(n)
+    dP = np.empty(n)
+    for k, t in enumerate(taus):
+        P[k], dP[k] = blackbody_band_P(float(t), e_lo, e_hi, T, alpha)
+    P.setflags(write=False)
+    dP.setflags(write=False)
+    return Table(lg_lo, lg_hi, P, dP)
 
 
 def blackbody_H(tau: float, T: float = 5e4, alpha: float = 2.8):

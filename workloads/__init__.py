@@ -24,7 +24,7 @@ MPC_CM = 3.0856775814913673e24
 __all__ = [
     "Sources", "Workload", "gaussian_field", "lognormal_density",
     "bubble_xhi", "smoothed_threshold_xhi", "random_sources", "make_workload",
-    "CONFIGS",
+    "CONFIGS", "HE_BAND_EDGES_EV", "HE_BAND_LG_HI", "HE_ABUNDANCE", "helium_cross_sections",
 ]
 
 
@@ -139,6 +139,31 @@ def random_sources(N: int, n: int, rng, lgQ=(51.0, 55.0), R=(30.0, 30.0)) -> Sou
     else:
         Rv = rng.uniform(R[0], R[1], size=n).astype(np.float32)
     return Sources(ijk, Q.astype(np.float64), Rv)
+
+
+# Helium as a second absorber (inputs of the two-species sweep).  The
+# spectrum above 13.6 eV is split into bands at 24.59 eV (the HeI threshold),
+# 35 eV and 54.42 eV (the HeII threshold, kept as a band edge only); per band
+# the upper end of its table in log10 of the optical depth at its lower edge
+# (its photons are absorbed to below about 1e-30 there), and the
+# cross-sections of HI (the paper's law, 6.3e-18 cm^2 (E/13.6 eV)^-2.8) and
+# HeI (the measured cross-section's fit 7.42e-18 cm^2 [1.66 (E/24.59 eV)^-2.05
+# - 0.66 (E/24.59 eV)^-3.05]) at the band's lower edge E.  Helium by number
+# n_He = 0.0789 n_H (mass fraction 0.24); x_HeI follows x_HI (helium singly
+# ionized where hydrogen is ionized).
+HE_BAND_EDGES_EV = (13.6, 24.59, 35.0, 54.42, math.inf)
+HE_BAND_LG_HI = (2.5, 2.2, 2.3, 3.3)
+HE_ABUNDANCE = 0.0789
+
+
+def helium_cross_sections():
+    """(sigma_HI, sigma_HeI) in cm^2 at the lower edge of every band."""
+    sH, sHe = [], []
+    for e in HE_BAND_EDGES_EV[:-1]:
+        sH.append(6.3e-18 * (e / 13.6) ** -2.8)
+        r = e / 24.59
+        sHe.append(7.42e-18 * (1.66 * r ** -2.05 - 0.66 * r ** -3.05) if e >= 24.59 else 0.0)
+    return np.array(sH), np.array(sHe)
 
 
 # The five workloads, with their recipe.  Cell sizes: 1.4 Mpc is rounded to
