@@ -230,6 +230,50 @@ asora_status asora_raytrace_heating(asora_ctx *ctx, const float *n_H, const floa
                                     void *stream);
 
 /*
+ * asora_set_helium / asora_raytrace_helium -- the sweep with two absorbers,
+ * HI and HeI (the extension the paper plans, Sections 2 and 6).
+ *
+ * The spectrum above 13.6 eV is split into bands (asora_table_blackbody_band
+ * builds a black body's).  Band b has its own table P_b(T): the photons of the
+ * band that survive an optical depth T measured at the band's lower edge, per
+ * photon emitted above 13.6 eV, on n_tab nodes uniform in log10 T from
+ * lg_lo[b] to lg_hi[b] (interpolated as the hydrogen table; constant beyond
+ * the last node), and the cross-sections sigma_HI[b], sigma_HeI[b] (cm^2) of
+ * the two species at that edge; inside a band both follow the band's
+ * frequency shape, so its optical depth is sigma_HI[b] N_HI + sigma_HeI[b] N_HeI.
+ * Both column densities are carried by the same short characteristics
+ * (Section 3.1) with the weights of the hydrogen sweep (their optical-depth
+ * factor on sigma0 N_HI: helium does not absorb at 13.6 eV).  A cell absorbs
+ * Q [P_b(T_in) - P_b(T_out)] photons of band b, shared between the species in
+ * proportion to their in-cell optical depths; a species' rate is its share
+ * over n_i V (eq. sugg for each band), i.e. Q sum_b sigma_i[b] (-D_b) /
+ * (4 pi alpha^2 r^2) with D_b the divided difference of P_b over the cell.
+ *
+ * asora_set_helium: n_bands in [1, 8]; lg_lo, lg_hi, sigma_HI, sigma_HeI host
+ * arrays of n_bands; P, dPdtau host arrays of n_bands x n_tab (band-major),
+ * with the rules of asora_init's table per band; copied (waits for the
+ * device).  sigma_HI[b], sigma_HeI[b] >= 0, not both 0.  ASORA_EINVAL on
+ * invalid input, ASORA_ESTATE while a recorded graph exists.
+ *
+ * asora_raytrace_helium: as asora_raytrace with, in addition, n_He (total
+ * helium density, cm^-3) and x_HeI (its neutral fraction), device N^3 floats
+ * (n_HeI = n_He x_HeI formed exactly in FP64), and two outputs gamma_HI,
+ * gamma_HeI (device N^3 floats, s^-1, overwritten unless ASORA_ACCUMULATE;
+ * FP64 accumulation).  Every source is swept as layer pyramids (no whole or
+ * octant pieces); flags ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_PROFILE.
+ * ESTATE without band tables.  Scratch: 32 N^3 bytes more than
+ * asora_raytrace (n_HeI and the HeI accumulator in both layouts), allocated
+ * by the first call.
+ */
+asora_status asora_set_helium(asora_ctx *ctx, int32_t n_bands, int32_t n_tab, const double *lg_lo,
+                              const double *lg_hi, const double *P, const double *dPdtau,
+                              const double *sigma_HI, const double *sigma_HeI);
+asora_status asora_raytrace_helium(asora_ctx *ctx, const float *n_H, const float *x_HI, const float *n_He,
+                                   const float *x_HeI, int64_t n_src, const int32_t *src_ijk,
+                                   const double *src_Q, const float *src_R, float R_max, float *gamma_HI,
+                                   float *gamma_HeI, uint32_t flags, void *stream);
+
+/*
  * asora_raytrace_backward -- adjoint of asora_raytrace.
  *
  * Given dL/dgamma, computes dL/dn_H, dL/dx_HI and dL/dQ of the forward map
@@ -288,6 +332,21 @@ asora_status asora_table_blackbody(double T_bb, double index, int32_t n, double 
  */
 asora_status asora_table_blackbody_heat(double T_bb, double index, int32_t n, double lg_lo,
                                         double lg_hi, double *H, double *dHdtau);
+
+/*
+ * asora_table_blackbody_band -- one band [e_lo_eV, e_hi_eV) of the black body
+ * of asora_table_blackbody, for several absorbers: the photons of the band
+ * that survive an optical depth tau measured at the band's lower edge, with
+ * the cross-section shape (nu / nu_lo)^-index inside the band, per photon
+ * emitted above 13.6 eV, and its derivative:
+ *   P_b(tau) = int_{x_lo}^{x_hi} phi(x) exp(-tau (x/x_lo)^-index) dx / int_x0^inf phi(x) dx.
+ * The bands of a spectrum with tau_b = tau (e_b / 13.6 eV)^-index add up to
+ * asora_table_blackbody's P(tau).  e_hi_eV = +INFINITY: an open band.  Host
+ * only; P, dPdtau host arrays of n doubles.  ASORA_EINVAL unless
+ * 13.6 <= e_lo_eV < e_hi_eV.
+ */
+asora_status asora_table_blackbody_band(double T_bb, double index, double e_lo_eV, double e_hi_eV, int32_t n,
+                                        double lg_lo, double lg_hi, double *P, double *dPdtau);
 
 /* asora_table_grey -- P = exp(-tau), dP/dtau = -exp(-tau) (grey opacity). */
 asora_status asora_table_grey(int32_t n, double lg_lo, double lg_hi, double *P, double *dPdtau);

@@ -65,6 +65,12 @@ _lib.asora_set_heating_table.restype = _c_int
 _lib.asora_set_heating_table.argtypes = [_p, _p, _p]
 _lib.asora_raytrace_heating.restype = _c_int
 _lib.asora_raytrace_heating.argtypes = [_p, _p, _p, _c_i64, _p, _p, _p, _c_f, _p, _p, _c_u32, _p]
+_lib.asora_table_blackbody_band.restype = _c_int
+_lib.asora_table_blackbody_band.argtypes = [_c_d, _c_d, _c_d, _c_d, _c_int, _c_d, _c_d, _p, _p]
+_lib.asora_set_helium.restype = _c_int
+_lib.asora_set_helium.argtypes = [_p, _c_int, _c_int, _p, _p, _p, _p, _p, _p]
+_lib.asora_raytrace_helium.restype = _c_int
+_lib.asora_raytrace_helium.argtypes = [_p, _p, _p, _p, _p, _c_i64, _p, _p, _p, _c_f, _p, _p, _c_u32, _p]
 _lib.asora_table_grey.restype = _c_int
 _lib.asora_table_grey.argtypes = [_c_int, _c_d, _c_d, _p, _p]
 _lib.asora_check.restype = _c_int
@@ -156,6 +162,16 @@ def table_blackbody_heat(T_bb: float = 5e4, index: float = 2.8, n: int = 2000, l
     H, dH = np.empty(n), np.empty(n)
     _raise(_lib.asora_table_blackbody_heat(T_bb, index, n, lg_lo, lg_hi, _np_ptr(H), _np_ptr(dH)))
     return H, dH
+
+
+def table_blackbody_band(e_lo_eV: float, e_hi_eV: float, T_bb: float = 5e4, index: float = 2.8, n: int = 2000,
+                         lg_lo: float = -20.0, lg_hi: float = 2.5):
+    """(P_b, dP_b/dtau) of one band [e_lo_eV, e_hi_eV) of the black body
+    (asora_table_blackbody_band; e_hi_eV = inf for an open band)."""
+    P = np.empty(n)
+    dP = np.empty(n)
+    _raise(_lib.asora_table_blackbody_band(T_bb, index, e_lo_eV, e_hi_eV, n, lg_lo, lg_hi, _np_ptr(P), _np_ptr(dP)))
+    return P, dP
 
 
 def table_grey(n: int = 2000, lg_lo: float = -20.0, lg_hi: float = math.log10(80.0)):
@@ -250,6 +266,44 @@ class Asora:
         _raise(st, self._h)
         shape = (self.N,) * 3
         return (gamma.view(shape), cd.view(shape)) if coldens else gamma.view(shape)
+
+    def set_helium(self, bands):
+        """Band tables of the two-absorber sweep (asora_set_helium): `bands` is a
+        sequence of (P, dP/dtau, lg_lo, lg_hi, sigma_HI, sigma_HeI), every
+        band's table on n nodes uniform in log10 tau from lg_lo to lg_hi."""
+        nb = len(bands)
+        n = len(bands[0][0])
+        P = np.ascontiguousarray(np.concatenate([b[0] for b in bands]), dtype=np.float64)
+        dP = np.ascontiguousarray(np.concatenate([b[1] for b in bands]), dtype=np.float64)
+        if P.size != nb * n or dP.size != nb * n:
+            raise AsoraError(-1, "every band's table must have the same number of nodes")
+        col = lambda k: np.ascontiguousarray([float(b[k]) for b in bands], dtype=np.float64)
+        lo, hi, sH, sHe = col(2), col(3), col(4), col(5)
+        _raise(_lib.asora_set_helium(self._h, nb, n, _np_ptr(lo), _np_ptr(hi), _np_ptr(P), _np_ptr(dP),
+                                     _np_ptr(sH), _np_ptr(sHe)), self._h)
+
+    def raytrace_helium(self, n_H, x_HI, n_He, x_HeI, ijk, Q, R=None, R_max=None, plain=False, out=None,
+                        accumulate=False, profile=False, stream=None):
+        """(Gamma_HI, Gamma_HeI), float32 cuda N^3 each, from one two-absorber
+        sweep (asora_raytrace_helium); out = (gamma_HI, gamma_HeI) to fill."""
+        ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
+        for name, t in (("n_He", n_He), ("x_HeI", x_HeI)):
+            self._check(name, t, torch.float32)
+        dev = n_H.device
+        if out is not None:
+            gH, gHe = out
+            self._check("gamma_HI", gH, torch.float32)
+            self._check("gamma_HeI", gHe, torch.float32)
+        else:
+            gH = torch.empty(self.N ** 3, dtype=torch.float32, device=dev)
+            gHe = torch.empty_like(gH)
+        flags = (PLAIN if plain else 0) | (ACCUMULATE if accumulate else 0) | (PROFILE if profile else 0)
+        st = _lib.asora_raytrace_helium(self._h, _dptr(n_H), _dptr(x_HI), _dptr(n_He), _dptr(x_HeI), n, _dptr(ijk),
+                                        _dptr(Q), _dptr(R), R_max, _dptr(gH), _dptr(gHe), flags,
+                                        _stream_ptr(stream))
+        _raise(st, self._h)
+        shape = (self.N,) * 3
+        return gH.view(shape), gHe.view(shape)
 
     def set_heating_table(self, H, dHdtau):
         """Photo-heating table (host arrays on this context's table nodes)."""

@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libasora.so")
-SOURCES = ["asora_api.hip", "asora_fwd.hip", "asora_adj.hip", "asora_chem.hip", "asora_tables.cpp"]
+SOURCES = ["asora_api.hip", "asora_fwd.hip", "asora_adj.hip", "asora_he.hip", "asora_chem.hip",
+           "asora_tables.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -55,6 +55,7 @@ struct AdjArgs {
     size_t rec_rk_off;       // kept records: offset of the rate coefficients
     long rec_cap;            // cells (and listed cells) per pyramid record
     int early_exit;          // layer pieces: stop at the first opaque layer
+    int sq_n;                // layer pieces: entries of the work-group's LDS table of sqrt(r^2); 0: none
 };
 
 template <int TYPE>
@@ -275,8 +276,9 @@ __device__ __forceinline__ uint64_t mask_of_chunk(uint64_t masks, int c)
 }
 
 template <bool KEPT, bool SPLIT>
-__device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *buf, int *qk, int *qm,
-                                    double *qT, char *scratch, int src, int p, int lane)
+__device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, const double *sq, double *buf, Geo *geo,
+                                    uint32_t *iu, uint32_t *iv, int *qk, int *qm, double *qT, char *scratch, int src,
+                                    int p, int lane)
 {
     const int N = A.N;
     const int si = A.ijk[3 * src], sj = A.ijk[3 * src + 1], sk = A.ijk[3 * src + 2];
@@ -323,7 +325,12 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
         Mt = ml < Mx ? ml : Mx;
     } else {
         const bool watch = A.early_exit != 0;
-        for (int k = lane; k < S * S; k += 64) buf[k] = 0.0;   // finite everywhere it is read
+        const int P = S + 1;   // row stride of the padded layer buffer
+        for (int k = lane; k < P * P; k += 64) buf[k] = 0.0;   // finite everywhere it is read
+        for (int k = lane; k < S; k += 64) {                   // the pyramid's index terms
+            iu[k] = layer_idx_u(L, N, k);
+            iv[k] = layer_idx_v(L, N, k);
+        }
         wave_sync();
         const double opaque = layer_opaque(A.tp.tau_hi);
         long off = 0, choff = 0;
@@ -331,21 +338,29 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, double *
             const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
             const double inv_m = rcp_f64((double)m);
             const int nch = (r.total + 63) / 64;
+            for (int k = lane; k < S; k += 64) geo[k] = layer_geo(m, inv_m, k);
+            wave_sync();
             RectWalk w;
             w.init(r, (nch - 1) * 64 + lane);
             bool opq = true;   // every cell of layer m so far leaves opaque
+            const int m2 = mul24(m, m);
+            const uint32_t idx_d = layer_idx_d(L, N, m);
             for (int c = nch - 1; c >= 0; --c, w.down()) {
                 const int g = c * 64 + lane;
                 const int u = w.u, v = w.v;
-                const bool act = g < r.total && mul24(u, u) + mul24(v, v) <= r.rem;
-                const int pos = mul24(u, S) + v;
+                const int uv2 = mul24(u, u) + mul24(v, v);
+                const bool act = g < r.total && uv2 <= r.rem;
+                const int pos = layer_slot(u, v, P);
                 LayerCell lc;
                 lc.Nin = 0.0;
                 lc.Nout = 0.0;
                 lc.owned = false;
                 if (act) {
-                    const uint32_t cp = layer_cp(L, N, m, u, v);
-                    layer_cell_at(L, X, m, inv_m, u, v, cp, X.nHI[cp], buf, pos, S, lc);
+                    const uint32_t cp = idx_d + iu[u] + iv[v];
+                    const int r2 = m2 + uv2;   // <= Rsq < sq_n when the table is there
+                    const double rt = A.sq_n ? sq[r2] : sqrt_fast((double)r2);
+                    layer_cell_core(L, X, m, u, v, geo[u], geo[v], rt * inv_m, r2, cp, X.nHI[cp], buf[pos],
+                                    buf[pos - P], buf[pos - 1], buf[pos - P - 1], lc);
                 }
                 wave_sync();
                 bool lit = false;
@@ -603,14 +618,21 @@ __global__ __launch_bounds__(kAdjLayerThreads) void adj_layer(AdjArgs A)
     constexpr int TYPE = 3, npieces = 24;
     if (A.seg[TYPE + 1] == A.seg[TYPE]) return;   // no sources of this kind
     const TabNode *T = A.tab;
+    // the work-group's table of square roots (used by (F))
+    double *sq = (double *)smem;
+    for (int k = threadIdx.x; k < A.sq_n; k += blockDim.x) sq[k] = sqrt((double)k);
+    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
-    // per wave: one S x S buffer, the columns in (F) and the adjoints in (R),
-    // then the (G) queue
-    double *buf = (double *)(smem + (size_t)wave * A.region_bytes);
-    int *qk = (int *)(buf + (size_t)A.lay_S * A.lay_S);
+    // per wave: one buffer, the columns in (F) and the adjoints in (R), the
+    // queue, the tables of (F)
+    double *buf = (double *)(smem + (A.sq_n ? layer_sqrt_bytes(A.sq_n - 1) : 0) + (size_t)wave * A.region_bytes);
+    int *qk = (int *)(buf + (size_t)(A.lay_S + 1) * (A.lay_S + 1));
     int *qm = qk + kAdjQueue;
     double *qT = (double *)(qm + kAdjQueue);
+    Geo *geo = (Geo *)(qT + kAdjQueue);
+    uint32_t *iu = (uint32_t *)(geo + A.lay_S);
+    uint32_t *iv = iu + A.lay_S;
     char *scratch = (char *)(A.store + (size_t)(blockIdx.x * waves + wave) * A.store_stride);
     const int base = A.seg[TYPE];
     const int nitems = (A.seg[TYPE + 1] - base) * npieces;
@@ -620,7 +642,8 @@ __global__ __launch_bounds__(kAdjLayerThreads) void adj_layer(AdjArgs A)
         const int item = next_item(A.counter, nitems, home, chunk, lane);
         if (item >= nitems) break;
         const int src = A.order[base + item / npieces];
-        adjoint_layer_piece<KEPT, SPLIT>(A, T, buf, qk, qm, qT, scratch, src, item % npieces, lane);
+        adjoint_layer_piece<KEPT, SPLIT>(A, T, sq, buf, geo, iu, iv, qk, qm, qT, scratch, src, item % npieces,
+                                         lane);
     }
 }
 
@@ -796,6 +819,7 @@ static AdjArgs make_adj_args(const AdjLaunch &L)
     A.rec_rk_off = L.rec_rk_off;
     A.rec_cap = L.rec_cap;
     A.early_exit = L.early_exit ? 1 : 0;
+    A.sq_n = 0;
     return A;
 }
 
@@ -812,11 +836,13 @@ hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L)
     return hipGetLastError();
 }
 
-// Per-wave LDS of the layer adjoint: the S x S buffer (columns, then
-// adjoints) and the queue of cells with a rate.
+// Per-wave LDS of the layer adjoint: the buffer (the padded (S + 1) x (S + 1)
+// layer buffer in (F), the S x S adjoint slots in (R)), the queue of cells
+// with work and the table of bilinear factors of (F).
 size_t adj_layer_region_bytes(int S)
 {
-    return ((size_t)S * S * sizeof(double) + kAdjQueue * (2 * sizeof(int) + sizeof(double)) + 15) &
+    return ((size_t)(S + 1) * (S + 1) * sizeof(double) + kAdjQueue * (2 * sizeof(int) + sizeof(double)) +
+            (size_t)S * sizeof(Geo) + 2 * (size_t)S * sizeof(uint32_t) + 15) &
            ~(size_t)15;
 }
 
@@ -834,7 +860,10 @@ hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int Mcap, int S)
     A.Mcap = Mcap;
     A.lay_S = S;
     A.region_bytes = (int)adj_layer_region_bytes(S);
-    const size_t lds = (size_t)L.waves * A.region_bytes;
+    const int Rsq = (int)floor((double)L.R_cap * (double)L.R_cap);
+    const size_t sqb = layer_sqrt_bytes(Rsq);
+    A.sq_n = sqb ? Rsq + 1 : 0;
+    const size_t lds = sqb + (size_t)L.waves * A.region_bytes;
     const dim3 grid(L.grid), block(64 * L.waves);
     if (A.kept) hipLaunchKernelGGL((adj_layer<true, false>), grid, block, lds, st, A);
     else if (L.split) hipLaunchKernelGGL((adj_layer<false, true>), grid, block, lds, st, A);

@@ -54,6 +54,13 @@ struct asora_ctx {
     float dP0_h;            // its slope at the first node
     double *d_hacc;         // heating accumulators (allocated by the first heating forward)
     double *d_hacc_T;
+    // two absorbers (asora_set_helium): band tables, cross-sections; n_HeI and
+    // the HeI rate accumulator in both layouts (allocated by the first call)
+    int he_nb, he_ntab;
+    TabNode *d_tab_he;
+    TabParams he_tp[kMaxBands];
+    double he_sH[kMaxBands], he_sHe[kMaxBands];
+    double *d_nhe, *d_nhe_T, *d_ghe, *d_ghe_T;
     double *d_nhi;
     double *d_gacc;
     int *d_ctl;
@@ -159,6 +166,14 @@ extern "C" asora_status asora_table_blackbody_heat(double T_bb, double index, in
 {
     if (table_blackbody_heat(T_bb, index, n, lg_lo, lg_hi, H, dHdtau) != 0)
         return fail(nullptr, ASORA_EINVAL, "asora_table_blackbody_heat: invalid argument");
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_table_blackbody_band(double T_bb, double index, double e_lo_eV, double e_hi_eV,
+                                                   int32_t n, double lg_lo, double lg_hi, double *P, double *dPdtau)
+{
+    if (table_blackbody_band(T_bb, index, e_lo_eV, e_hi_eV, n, lg_lo, lg_hi, P, dPdtau) != 0)
+        return fail(nullptr, ASORA_EINVAL, "asora_table_blackbody_band: invalid argument");
     return ASORA_OK;
 }
 
@@ -281,7 +296,8 @@ extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, d
         for (int k = 0; k < 4; ++k)
             if (hipEventCreate(&c->pev[sl][k]) != hipSuccess)
                 return bail(fail(nullptr, ASORA_EHIP, "asora_init: hipEventCreate failed"));
-    if (fwd_configure(c->max_lds) != hipSuccess || adj_configure(c->max_lds) != hipSuccess)
+    if (fwd_configure(c->max_lds) != hipSuccess || adj_configure(c->max_lds) != hipSuccess ||
+        he_configure(c->max_lds) != hipSuccess)
         return bail(fail(nullptr, ASORA_EHIP, "asora_init: kernel attribute setup failed"));
     *out = c;
     return ASORA_OK;
@@ -301,6 +317,11 @@ extern "C" asora_status asora_free(asora_ctx *c)
     (void)hipFree(c->d_tab_h);
     (void)hipFree(c->d_hacc);
     (void)hipFree(c->d_hacc_T);
+    (void)hipFree(c->d_tab_he);
+    (void)hipFree(c->d_nhe);
+    (void)hipFree(c->d_nhe_T);
+    (void)hipFree(c->d_ghe);
+    (void)hipFree(c->d_ghe_T);
     (void)hipFree(c->d_nhi);
     (void)hipFree(c->d_gacc);
     (void)hipFree(c->d_ctl);
@@ -446,7 +467,9 @@ static asora_status get_layer_plan(asora_ctx *c, float R_cap, Plan *out, bool st
     P.rec_bytes = layer_record_bytes(P.rec_cap, P.Mcap, false);
     P.keep_bytes = layer_record_bytes(P.rec_cap, P.Mcap, true);
     P.wave_mode = 1;
-    const size_t tab = c->tab_lds ? (size_t)c->tp.n * sizeof(TabNode) : 0;
+    // the work-group's LDS: the table (if placed there), the table of square
+    // roots, one region per wave
+    const size_t tab = (c->tab_lds ? (size_t)c->tp.n * sizeof(TabNode) : 0) + layer_sqrt_bytes(Rsq);
     const size_t region = layer_region_bytes(P.S);
     const long fit = c->max_lds > tab + 64 ? (long)((c->max_lds - tab - 64) / region) : 0;
     if (fit < 1)
@@ -803,6 +826,176 @@ static asora_status forward(asora_ctx *c, const float *n_H, const float *x_HI, i
     return ASORA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Two absorbers: hydrogen and helium.
+extern "C" asora_status asora_set_helium(asora_ctx *c, int32_t n_bands, int32_t n_tab, const double *lg_lo,
+                                         const double *lg_hi, const double *P, const double *dPdtau,
+                                         const double *sigma_HI, const double *sigma_HeI)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    if (n_bands < 1 || n_bands > kMaxBands || n_tab < 2 || n_tab > 4096)
+        return fail(c, ASORA_EINVAL, "asora_set_helium: need 1 <= n_bands <= %d and 2 <= n_tab <= 4096",
+                    kMaxBands);
+    if (!lg_lo || !lg_hi || !P || !dPdtau || !sigma_HI || !sigma_HeI)
+        return fail(c, ASORA_EINVAL, "asora_set_helium: NULL argument");
+    std::vector<TabNode> nodes((size_t)n_bands * n_tab);
+    TabParams tp[kMaxBands];
+    for (int b = 0; b < n_bands; ++b) {
+        if (!(lg_hi[b] > lg_lo[b]) || !std::isfinite(lg_lo[b]) || !std::isfinite(lg_hi[b]))
+            return fail(c, ASORA_EINVAL, "asora_set_helium: band %d: table range must satisfy lo < hi", b);
+        if (!(sigma_HI[b] >= 0) || !(sigma_HeI[b] >= 0) || !std::isfinite(sigma_HI[b]) ||
+            !std::isfinite(sigma_HeI[b]) || !(sigma_HI[b] + sigma_HeI[b] > 0))
+            return fail(c, ASORA_EINVAL, "asora_set_helium: band %d: cross-sections must be >= 0, finite, "
+                                         "not both 0", b);
+        const int bad = bad_table_node(n_tab, P + (size_t)b * n_tab, dPdtau + (size_t)b * n_tab);
+        if (bad >= 0)
+            return fail(c, ASORA_EINVAL, "asora_set_helium: band %d: table node %d invalid (P must be positive, "
+                                         ">= 1.2e-38, non-increasing; dP/dtau finite and <= 0)", b, bad);
+        prepare_table(n_tab, lg_lo[b], lg_hi[b], P + (size_t)b * n_tab, dPdtau + (size_t)b * n_tab, &tp[b],
+                      nodes.data() + (size_t)b * n_tab, nullptr);
+    }
+    HIPCHK(c, hipSetDevice(c->device));
+    if (c->live_graphs) return pinned(c, "the helium tables");
+    // ordered after the work already queued: a sweep in flight reads its tables
+    HIPCHK(c, hipDeviceSynchronize());
+    if (c->d_tab_he && (c->he_nb != n_bands || c->he_ntab != n_tab)) {
+        (void)hipFree(c->d_tab_he);
+        c->d_tab_he = nullptr;
+    }
+    if (!c->d_tab_he) HIPCHK(c, hipMalloc(&c->d_tab_he, sizeof(TabNode) * nodes.size()));
+    HIPCHK(c, hipMemcpy(c->d_tab_he, nodes.data(), sizeof(TabNode) * nodes.size(), hipMemcpyHostToDevice));
+    c->he_nb = n_bands;
+    c->he_ntab = n_tab;
+    for (int b = 0; b < n_bands; ++b) {
+        c->he_tp[b] = tp[b];
+        c->he_sH[b] = sigma_HI[b];
+        c->he_sHe[b] = sigma_HeI[b];
+    }
+    return ASORA_OK;
+}
+
+// The two-absorber sweep's plan: layer pyramids, one wave each, the
+// work-group's table of square roots and one region per wave.
+static asora_status get_he_plan(asora_ctx *c, float R_cap, Plan *out)
+{
+    const int Rsq = (int)std::floor((double)R_cap * (double)R_cap);
+    const PlanKey key{6, Rsq};
+    auto it = c->plans.find(key);
+    if (it != c->plans.end()) {
+        *out = it->second;
+        return ASORA_OK;
+    }
+    const Extent ex = make_extent(c->N);
+    Plan P = Plan();
+    P.S = layer_buffer_side(Rsq, ex);
+    P.wave_mode = 1;
+    const size_t wg = layer_sqrt_bytes(Rsq);
+    const size_t region = he_region_bytes(P.S);
+    const long fit = c->max_lds > wg + 64 ? (long)((c->max_lds - wg - 64) / region) : 0;
+    if (fit < 1)
+        return fail(c, ASORA_ENOSYS, "asora_raytrace_helium: R_max=%.1f needs %zu bytes of LDS per wave (limit %zu)",
+                    R_cap, region + wg, c->max_lds);
+    P.waves = (int)(fit < c->max_waves ? fit : c->max_waves);
+    P.lds = wg + (size_t)P.waves * region;
+    int bpc = 0;
+    HIPCHK(c, he_occupancy(P.waves, P.lds, &bpc));
+    P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
+    c->plans[key] = P;
+    *out = P;
+    return ASORA_OK;
+}
+
+extern "C" asora_status asora_raytrace_helium(asora_ctx *c, const float *n_H, const float *x_HI, const float *n_He,
+                                              const float *x_HeI, int64_t n_src, const int32_t *src_ijk,
+                                              const double *src_Q, const float *src_R, float R_max,
+                                              float *gamma_HI, float *gamma_HeI, uint32_t flags, void *stream)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    asora_status st = check_common(c, n_H, x_HI, n_src, src_ijk, src_Q, R_max);
+    if (st) return st;
+    if (!n_He || !x_HeI || !gamma_HI || !gamma_HeI)
+        return fail(c, ASORA_EINVAL, "asora_raytrace_helium: n_He, x_HeI and both outputs must not be NULL");
+    if (flags & ~(ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_PROFILE))
+        return fail(c, ASORA_EINVAL, "asora_raytrace_helium: flags may be ACCUMULATE, PLAIN, PROFILE");
+    if (!c->d_tab_he) return fail(c, ASORA_ESTATE, "asora_raytrace_helium: no band tables (asora_set_helium)");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    const long n3 = (long)c->N * c->N * c->N;
+    Plan plan;
+    if ((st = get_he_plan(c, R_max, &plan))) return st;
+    if ((st = ensure_src_cap(c, n_src))) return st;
+    if ((st = ensure_layer_buffers(c))) return st;
+    double **grids[4] = {&c->d_nhe, &c->d_nhe_T, &c->d_ghe, &c->d_ghe_T};
+    for (double **g : grids)
+        if (!*g) {
+            if (c->live_graphs) return pinned(c, "the helium grids");
+            HIPCHK(c, hipMalloc(g, sizeof(double) * n3));
+        }
+    const bool prof = (flags & ASORA_PROFILE) != 0;
+    hipEvent_t *ev = c->pev[c->prof_count % kProfSlots];
+    const int acc = (flags & ASORA_ACCUMULATE) ? 1 : 0;
+    // n_HI, n_HeI and zeroed accumulators in both layouts; every source as layer pyramids
+    ++c->nhi_gen;
+    if (prof) HIPCHK(c, hipEventRecord(ev[0], s));
+    HIPCHK(c, launch_prologue(s, n_H, x_HI, c->d_nhi, c->d_gacc, nullptr, n3, c->d_ctl, kCtlSize, c->n_cu));
+    HIPCHK(c, launch_prologue(s, n_He, x_HeI, c->d_nhe, c->d_ghe, nullptr, n3, c->d_ctl, 0, c->n_cu));
+    HIPCHK(c, launch_transpose_prologue(s, n_H, x_HI, c->d_nhi_T, c->d_gacc_T, c->N));
+    HIPCHK(c, launch_transpose_prologue(s, n_He, x_HeI, c->d_nhe_T, c->d_ghe_T, c->N));
+    const bool bucketed = n_src > 0 && !(flags & ASORA_PLAIN);
+    if (bucketed) {
+        HIPCHK(c, launch_bucketing(s, src_R, src_ijk, n_src, c->N, R_max, -1.f, -1.f, 3, c->d_keys, c->d_ctl,
+                                   c->d_order, c->d_err));
+        ++c->order_gen;
+    }
+    if (prof) HIPCHK(c, hipEventRecord(ev[1], s));
+    if (n_src > 0) {
+        HeLaunch H;
+        H.N = c->N;
+        H.alpha = c->alpha;
+        H.sigma0 = c->sigma0;
+        H.tau_w = (float)c->tau_w;
+        H.reading = c->reading;
+        H.nb = c->he_nb;
+        H.n_tab = c->he_ntab;
+        H.tab = c->d_tab_he;
+        for (int b = 0; b < kMaxBands; ++b) {
+            H.tp[b] = c->he_tp[b < c->he_nb ? b : 0];
+            H.sH[b] = b < c->he_nb ? c->he_sH[b] : 0.0;
+            H.sHe[b] = b < c->he_nb ? c->he_sHe[b] : 0.0;
+        }
+        H.nHI = c->d_nhi;
+        H.nHeI = c->d_nhe;
+        H.nHI_T = c->d_nhi_T;
+        H.nHeI_T = c->d_nhe_T;
+        H.gH = c->d_gacc;
+        H.gHe = c->d_ghe;
+        H.gH_T = c->d_gacc_T;
+        H.gHe_T = c->d_ghe_T;
+        H.ijk = src_ijk;
+        H.Q = src_Q;
+        H.R = src_R;
+        H.R_cap = R_max;
+        H.order = c->d_order;
+        H.ctl = c->d_ctl;
+        H.err = c->d_err;
+        if (flags & ASORA_PLAIN) {
+            for (long k = 0; k < n_src; ++k)
+                HIPCHK(c, launch_fwd_layer_he(s, H, plan.S, plan.waves, 0, (int)k));
+        } else {
+            HIPCHK(c, launch_fwd_layer_he(s, H, plan.S, plan.waves, plan.grid, -1));
+        }
+    }
+    if (prof) HIPCHK(c, hipEventRecord(ev[2], s));
+    HIPCHK(c, launch_transpose_finalize(s, c->d_gacc, c->d_gacc_T, gamma_HI, c->N, acc));
+    HIPCHK(c, launch_transpose_finalize(s, c->d_ghe, c->d_ghe_T, gamma_HeI, c->N, acc));
+    if (prof) {
+        HIPCHK(c, hipEventRecord(ev[3], s));
+        c->prof_count++;
+        if (c->prof_pending < kProfSlots) c->prof_pending++;
+    }
+    return ASORA_OK;
+}
+
 extern "C" asora_status asora_set_tuning(asora_ctx *c, float R_whole, float R_oct, int32_t max_waves,
                                          int32_t pyramid_sweep, int32_t table_place, int32_t adj_waves,
                                          int32_t adj_rate)
@@ -935,13 +1128,14 @@ static asora_status get_adj_layer_plan(asora_ctx *c, float R_cap, bool kept, Pla
     asora_status st = get_layer_plan(c, R_cap, &P);   // Mcap, record sizes
     if (st) return st;
     const size_t region = adj_layer_region_bytes(P.S);
-    const long fit = c->max_lds > 64 ? (long)((c->max_lds - 64) / region) : 0;
+    const size_t wg = layer_sqrt_bytes(Rsq);   // the work-group's table of square roots
+    const long fit = c->max_lds > wg + 64 ? (long)((c->max_lds - wg - 64) / region) : 0;
     if (fit < 1)
         return fail(c, ASORA_ENOSYS,
                     "asora_raytrace_backward: R_max=%.1f needs %zu bytes of LDS per wave (limit %zu)",
-                    R_cap, region, c->max_lds);
+                    R_cap, region + wg, c->max_lds);
     P.waves = (int)(fit < c->adj_waves ? fit : c->adj_waves);
-    P.lds = (size_t)P.waves * region;
+    P.lds = wg + (size_t)P.waves * region;
     int bpc = 0;
     HIPCHK(c, adj_layer_occupancy(kept, c->adj_split != 0, P.waves, P.lds, &bpc));
     P.grid = c->n_cu * (bpc > 0 ? bpc : 1);

@@ -112,6 +112,35 @@ __host__ __device__ __forceinline__ double log_fast(double a)
     return 2.0 * s * p + (double)e * 0.69314718055994530942;
 }
 
+// ln(a) in FP64 for normal a > 0 to about 1e-14 absolute: the reduction of
+// log_fast with the series summed to s^19 (the next term is below 1e-16).
+// The rate's derivatives for the adjoint take difference quotients over
+// in-cell optical depths down to 1e-4 of the entry one, which multiply an
+// error of the table position by up to 1e4: log_fast's 2e-11 would reach
+// 1e-5 in the gradients.
+__host__ __device__ __forceinline__ double log_f64(double a)
+{
+    int e;
+    double m = frexp(a, &e);
+    if (m < 0.70710678118654752) {
+        m *= 2.0;
+        e -= 1;
+    }
+    const double s = (m - 1.0) * rcp_f64(m + 1.0);
+    const double s2 = s * s;
+    double p = 1.0 / 19.0;
+    p = p * s2 + 1.0 / 17.0;
+    p = p * s2 + 1.0 / 15.0;
+    p = p * s2 + 1.0 / 13.0;
+    p = p * s2 + 1.0 / 11.0;
+    p = p * s2 + 1.0 / 9.0;
+    p = p * s2 + 1.0 / 7.0;
+    p = p * s2 + 1.0 / 5.0;
+    p = p * s2 + 1.0 / 3.0;
+    p = p * s2 + 1.0;
+    return 2.0 * s * p + (double)e * 0.69314718055994530942;
+}
+
 // --------------------------------------------------------------------------
 // Photoionization table P(tau) (eq. tables, Section 2.2, normalised to P(0)=1)
 // in the form the kernels read it.  Node k sits at x_k = x_lo + k h, x = ln tau.
@@ -540,7 +569,7 @@ __host__ __device__ __forceinline__ void tab_eval64(const TabNode *T, const doub
         *d2 = 0.0;
         return;
     }
-    const double t = (log_fast(tau) - tp.x_lo) * tp.inv_h;
+    const double t = (log_f64(tau) - tp.x_lo) * tp.inv_h;
     int j = (int)floor(t);
     j = j < 0 ? 0 : (j > tp.n - 2 ? tp.n - 2 : j);
     const double f = t - (double)j;
@@ -1015,44 +1044,90 @@ struct RectWalk {
     }
 };
 
-// The short-characteristics update of cell (u, v) of layer m of a pyramid:
-// entry column interpolated from the four neighbours in layer m - 1 (eqs.
-// 11-12; for m = 1 the only neighbour of non-zero weight is the source),
-// in-cell column (eqs. 9-10), ownership.  lay holds layer m - 1 as
-// lay[u * S + v].  The arithmetic is the same as cell_update's.
-// Index of layer cell (u, v) of layer m in the piece's field layout.
-__host__ __device__ __forceinline__ uint32_t layer_cp(const LayerPiece &L, int N, int m, int u, int v)
+// Index of layer cell (u, v) of layer m in the piece's field layout, as the
+// sum of one term per axis: layer_idx_d(m) + layer_idx_u(u) + layer_idx_v(v)
+// (a sweep keeps the u and v terms of its pyramid in per-wave tables).
+// Strides are N or N^2 (< 2^22); the N^2 stride is applied with a full product.
+__host__ __device__ __forceinline__ uint32_t layer_idx_d(const LayerPiece &L, int N, int m)
 {
-    // strides are N or N^2 (< 2^22); the N^2 stride is applied with a full product
-    const uint32_t cd = (uint32_t)wrap(L.c_d + L.sd * m, N), cu = (uint32_t)wrap(L.c_u + L.su * u, N);
-    return cd * L.st_d + cu * L.st_u + (uint32_t)wrap(L.c_v + L.sv * v, N);
+    return (uint32_t)wrap(L.c_d + L.sd * m, N) * L.st_d;
 }
 
-// The short-characteristics update of cell (u, v) of layer m (inv_m = 1/m)
-// with its index cp, its n_HI and its buffer slot pos = u * S + v at hand:
-// entry column interpolated from the four neighbours in layer m - 1 (eqs.
-// 11-12; for m = 1 the only neighbour of non-zero weight is the source),
-// in-cell column (eqs. 9-10), ownership.  lay holds layer m - 1's entries
-// (layer_entry) at u * S + v.  Neighbours of zero weight are read from a
-// clamped slot and contribute exactly zero, so the lanes do not branch; the
-// buffer must hold finite values wherever it is read.
-__host__ __device__ __forceinline__ void layer_cell_at(const LayerPiece &L, const LayerX &X, int m,
-                                                       double inv_m, int u, int v, uint32_t cp, double nhi,
-                                                       const double *lay, int pos, int S, LayerCell &out)
+__host__ __device__ __forceinline__ uint32_t layer_idx_u(const LayerPiece &L, int N, int u)
 {
-    // a = 1 (b = 1) must be exact: the weights of neighbours that leave the
-    // pyramid then vanish exactly
-    const double a = u == m ? 1.0 : (double)u * inv_m;
-    const double b = v == m ? 1.0 : (double)v * inv_m;
-    const int r2 = mul24(m, m) + mul24(u, u) + mul24(v, v);
-    const double ds = sqrt_fast((double)r2) * inv_m;
+    return (uint32_t)wrap(L.c_u + L.su * u, N) * L.st_u;
+}
+
+__host__ __device__ __forceinline__ uint32_t layer_idx_v(const LayerPiece &L, int N, int v)
+{
+    return (uint32_t)wrap(L.c_v + L.sv * v, N);
+}
+
+__host__ __device__ __forceinline__ uint32_t layer_cp(const LayerPiece &L, int N, int m, int u, int v)
+{
+    return layer_idx_d(L, N, m) + layer_idx_u(L, N, u) + layer_idx_v(L, N, v);
+}
+
+// Largest number of spectral bands of the two-absorber sweep.
+constexpr int kMaxBands = 8;
+
+// Largest r^2 with an entry in a sweep's table of square roots (r^2 up to the
+// squared radius of the call); beyond it the root is computed per cell.
+constexpr int kSqrtTable = 4096;
+
+// Bytes of a layer sweep's table of square roots (sqrt of every r^2 up to
+// the squared radius Rsq of the call), or 0 when it would exceed kSqrtTable
+// entries (the roots are then computed per cell).
+__host__ __device__ inline size_t layer_sqrt_bytes(int Rsq)
+{
+    return Rsq < kSqrtTable ? (((size_t)(Rsq + 1) * sizeof(double) + 15) & ~(size_t)15) : 0;
+}
+
+// The layer buffer of a sweep: (S + 1) x (S + 1) doubles, cell (u, v) at
+// slot (u + 1)(S + 1) + v + 1.  Row 0 and column 0 stay zero: a cell on a
+// zero plane (u = 0 or v = 0) reads its neighbours (u - 1, .) or (., v - 1),
+// whose weights vanish, from those finite slots, so the four reads need no
+// clamp and come in two adjacent pairs.
+__host__ __device__ __forceinline__ int layer_slot(int u, int v, int P)
+{
+    return mul24(u + 1, P) + v + 1;
+}
+
+// Bilinear factors of an offset u (or v) of layer m: (1 - a, a), a = u / m.
+// a = 1 exactly at u = m: the weights of neighbours that leave the pyramid
+// then vanish exactly.  A sweep keeps them for u = 0 .. S - 1 in a per-layer
+// table.
+struct Geo {
+    double om, a;
+};
+
+__host__ __device__ __forceinline__ Geo layer_geo(int m, double inv_m, int u)
+{
+    Geo g;
+    g.a = u == m ? 1.0 : (double)u * inv_m;
+    g.om = 1.0 - g.a;
+    return g;
+}
+
+// The short-characteristics update of cell (u, v) of layer m of a pyramid
+// (eqs. 9-12): entry column interpolated from the layer-buffer entries
+// (layer_entry) h0 .. h3 of its four neighbours in layer m - 1, (u, v),
+// (u - 1, v), (u, v - 1), (u - 1, v - 1), with bilinear geometric weights
+// from gu = layer_geo(u), gv = layer_geo(v) times the optical-depth factors
+// (for m = 1 the only neighbour of non-zero weight is the source, whose
+// column the cell sees directly); in-cell column n_HI alpha ds with
+// ds = r / m; ownership.  The weights must be finite wherever they are zero.
+__host__ __device__ __forceinline__ void layer_cell_core(const LayerPiece &L, const LayerX &X, int m, int u,
+                                                         int v, const Geo &gu, const Geo &gv, double ds, int r2,
+                                                         uint32_t cp, double nhi, double h0, double h1,
+                                                         double h2, double h3, LayerCell &out)
+{
     double Nin;
     if (m == 1) {
         Nin = X.reading == 0 ? X.half_col * ds : X.half_col;
     } else {
-        const int du = u > 0 ? S : 0, dv = v > 0 ? 1 : 0;
-        const double h[4] = {lay[pos], lay[pos - du], lay[pos - dv], lay[pos - du - dv]};
-        const double sw[4] = {(1.0 - a) * (1.0 - b), a * (1.0 - b), (1.0 - a) * b, a * b};
+        const double h[4] = {h0, h1, h2, h3};
+        const double sw[4] = {gu.om * gv.om, gu.a * gv.om, gu.om * gv.a, gu.a * gv.a};
         double num = 0.0, W = 0.0;
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
@@ -1074,12 +1149,19 @@ __host__ __device__ __forceinline__ void layer_cell_at(const LayerPiece &L, cons
     out.owned = !(L.neg_u && u == 0) && !(L.neg_v && v == 0) && !(L.tie_u && u == m) && !(L.tie_v && v == m);
 }
 
-__host__ __device__ __forceinline__ void layer_cell(const LayerPiece &L, const LayerX &X, int m,
-                                                    int u, int v, const double *lay, int S,
-                                                    LayerCell &out)
+// The same update from the padded layer buffer lay (row stride P = S + 1) of
+// layer m - 1, with the geometry computed in place: the reference form of
+// what the sweep kernels do with their per-layer tables.
+__host__ __device__ __forceinline__ void layer_cell(const LayerPiece &L, const LayerX &X, int m, int u, int v,
+                                                    const double *lay, int P, LayerCell &out)
 {
     const uint32_t cp = layer_cp(L, X.N, m, u, v);
-    layer_cell_at(L, X, m, rcp_f64((double)m), u, v, cp, X.nHI[cp], lay, u * S + v, S, out);
+    const double inv_m = rcp_f64((double)m);
+    const int r2 = mul24(m, m) + mul24(u, u) + mul24(v, v);
+    const int pos = layer_slot(u, v, P);
+    layer_cell_core(L, X, m, u, v, layer_geo(m, inv_m, u), layer_geo(m, inv_m, v),
+                    sqrt_fast((double)r2) * inv_m, r2, cp, X.nHI[cp], lay[pos], lay[pos - P], lay[pos - 1],
+                    lay[pos - P - 1], out);
 }
 
 // Cell (i, j, k) of layer cell (m, u, v), in the standard layout.

@@ -50,6 +50,8 @@ struct FwdArgs {
                             // caches), or NULL: no heating
     double *hacc, *hacc_T;  // heating accumulators, in the layouts of gacc and gacc_T
     float dP0_h;            // dH/dtau at the first node (slope of the heating table's continuation)
+    int sq_n;               // layer pieces: entries of the work-group's LDS table of sqrt(r^2)
+                            // (r^2 < sq_n); 0: roots computed per cell
 };
 
 // The node grid's parameters with the heating table's end slope.
@@ -427,8 +429,8 @@ __device__ __forceinline__ void layer_rate_batch(const FwdArgs &A, const TabNode
 }
 
 template <bool KEEP, bool HEAT>
-__device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *lay,
-                                  const LayerQueue &Qa, int src, int p, int lane)
+__device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, const double *sq, double *lay, Geo *geo,
+                                  uint32_t *iu, uint32_t *iv, const LayerQueue &Qa, int src, int p, int lane)
 {
     const int N = A.N;
     const int si = A.ijk[3 * src], sj = A.ijk[3 * src + 1], sk = A.ijk[3 * src + 2];
@@ -471,7 +473,12 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
         }
     }
     const int Mx = min(isqrt_floor(Rsq), L.ext_d);
-    for (int k = lane; k < S * S; k += 64) lay[k] = 0.0;   // finite everywhere it is read
+    const int P = S + 1;   // row stride of the padded layer buffer
+    for (int k = lane; k < P * P; k += 64) lay[k] = 0.0;   // finite everywhere it is read
+    for (int k = lane; k < S; k += 64) {                   // the pyramid's index terms
+        iu[k] = layer_idx_u(L, N, k);
+        iv[k] = layer_idx_v(L, N, k);
+    }
     wave_sync();
     int head = 0, tail = 0;
     long off = 0;     // first cell of layer m in the record
@@ -485,20 +492,30 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
         const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
         const double inv_m = rcp_f64((double)m);
         const int nch = (r.total + 63) / 64;
+        // the bilinear factors of this layer's offsets (the previous layer's
+        // readers are done: every chunk ends with a wave barrier)
+        for (int k = lane; k < S; k += 64) geo[k] = layer_geo(m, inv_m, k);
+        wave_sync();
         RectWalk w;
         w.init(r, (nch - 1) * 64 + lane);
         bool opq = true;   // every cell of layer m so far leaves opaque
+        const int m2 = mul24(m, m);
+        const uint32_t idx_d = layer_idx_d(L, N, m);
         for (int c = nch - 1; c >= 0; --c, w.down()) {
             const int g = c * 64 + lane;
             const int u = w.u, v = w.v;
-            const bool act = g < r.total && mul24(u, u) + mul24(v, v) <= r.rem;
-            const int pos = mul24(u, S) + v;
+            const int uv2 = mul24(u, u) + mul24(v, v);
+            const bool act = g < r.total && uv2 <= r.rem;
+            const int pos = layer_slot(u, v, P);
             LayerCell lc;
             lc.Nin = 0.0;
             lc.owned = false;
             if (act) {
-                const uint32_t cp = layer_cp(L, N, m, u, v);
-                layer_cell_at(L, X, m, inv_m, u, v, cp, X.nHI[cp], lay, pos, S, lc);
+                const uint32_t cp = idx_d + iu[u] + iv[v];
+                const int r2 = m2 + uv2;   // <= Rsq < sq_n when the table is there
+                const double rt = A.sq_n ? sq[r2] : sqrt_fast((double)r2);
+                layer_cell_core(L, X, m, u, v, geo[u], geo[v], rt * inv_m, r2, cp, X.nHI[cp], lay[pos],
+                                lay[pos - P], lay[pos - 1], lay[pos - P - 1], lc);
             }
             wave_sync();   // every read of layer m - 1 before the writes below
             bool want = false;
@@ -550,6 +567,8 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, double *la
 
 // TLDS: the table is copied to LDS once per work-group; otherwise the rate
 // batches read it through the caches, which leaves the LDS to more waves.
+// The work-group also holds the table of square roots; every wave its own
+// region (rate queue, layer buffer, per-layer and per-pyramid tables).
 template <bool KEEP, bool TLDS, bool HEAT>
 __device__ __forceinline__ void fwd_layer_body(const FwdArgs &A, char *smem)
 {
@@ -560,20 +579,26 @@ __device__ __forceinline__ void fwd_layer_body(const FwdArgs &A, char *smem)
         const int4 *s = (const int4 *)A.tab;
         int4 *d = (int4 *)smem;
         for (int k = threadIdx.x; k < A.tp.n; k += blockDim.x) d[k] = s[k];
-        __syncthreads();
     }
+    char *wg = smem + (TLDS ? (size_t)A.tp.n * sizeof(TabNode) : 0);
+    double *sq = (double *)wg;
+    for (int k = threadIdx.x; k < A.sq_n; k += blockDim.x) sq[k] = sqrt((double)k);
+    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
-    char *region = smem + (TLDS ? (size_t)A.tp.n * sizeof(TabNode) : 0) + (size_t)wave * A.region_bytes;
+    char *region = wg + (A.sq_n ? layer_sqrt_bytes(A.sq_n - 1) : 0) + (size_t)wave * A.region_bytes;
     LayerQueue Qa;
     Qa.ta = (double *)region;
     Qa.dt = Qa.ta + kQueue;
     Qa.cp = (uint32_t *)(Qa.dt + kQueue);
     Qa.r2 = (int *)(Qa.cp + kQueue);
     double *lay = (double *)(Qa.r2 + kQueue);
+    Geo *geo = (Geo *)(lay + (size_t)(A.lay_S + 1) * (A.lay_S + 1));
+    uint32_t *iu = (uint32_t *)(geo + A.lay_S);
+    uint32_t *iv = iu + A.lay_S;
     if (A.plain_src >= 0) {
         const int item = blockIdx.x * waves + wave;
-        if (item < npieces) sweep_layer_piece<KEEP, HEAT>(A, T, lay, Qa, A.plain_src, item, lane);
+        if (item < npieces) sweep_layer_piece<KEEP, HEAT>(A, T, sq, lay, geo, iu, iv, Qa, A.plain_src, item, lane);
         return;
     }
     const int base = A.seg[TYPE];
@@ -584,7 +609,7 @@ __device__ __forceinline__ void fwd_layer_body(const FwdArgs &A, char *smem)
         const int item = next_item(A.counter, nitems, home, chunk, lane);
         if (item >= nitems) break;
         const int src = A.order[base + item / npieces];
-        sweep_layer_piece<KEEP, HEAT>(A, T, lay, Qa, src, item % npieces, lane);
+        sweep_layer_piece<KEEP, HEAT>(A, T, sq, lay, geo, iu, iv, Qa, src, item % npieces, lane);
     }
 }
 
@@ -604,12 +629,14 @@ __global__ __launch_bounds__(1024) void fwd_layer_heat(FwdArgs A)
     fwd_layer_body<KEEP, false, true>(A, smem);
 }
 
-// Per-wave LDS of the layer kernel: the rate queue, then the S x S layer
-// buffer.
+// Per-wave LDS of the layer kernel: the rate queue, the (S + 1) x (S + 1)
+// padded layer buffer, the layer's table of bilinear factors and the
+// pyramid's index terms along u and v.
 size_t layer_region_bytes(int S)
 {
     const size_t b = (size_t)kQueue * (2 * sizeof(double) + sizeof(uint32_t) + sizeof(int)) +
-                     (size_t)S * S * sizeof(double);
+                     (size_t)(S + 1) * (S + 1) * sizeof(double) + (size_t)S * sizeof(Geo) +
+                     2 * (size_t)S * sizeof(uint32_t);
     return (b + 15) & ~(size_t)15;
 }
 
@@ -626,8 +653,11 @@ hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int S, int waves
     A.plain_src = plain_src;
     A.lay_S = S;
     A.region_bytes = (int)layer_region_bytes(S);
+    const int Rsq = (int)floor((double)F.R_cap * (double)F.R_cap);
+    const size_t sqb = layer_sqrt_bytes(Rsq);
+    A.sq_n = sqb ? Rsq + 1 : 0;
     const bool tab_lds = F.tab_lds && !F.hacc;   // the heating sweep reads both tables through the caches
-    const size_t lds = (tab_lds ? (size_t)F.tp.n * sizeof(TabNode) : 0) + (size_t)waves * A.region_bytes;
+    const size_t lds = (tab_lds ? (size_t)F.tp.n * sizeof(TabNode) : 0) + sqb + (size_t)waves * A.region_bytes;
     if (plain_src >= 0) grid = (24 + waves - 1) / waves;
     const dim3 g(grid), b(64 * waves);
     if (F.hacc && A.keep) hipLaunchKernelGGL((fwd_layer_heat<true>), g, b, lds, st, A);
@@ -985,6 +1015,7 @@ static FwdArgs make_args(const FwdLaunch &F)
     A.plain_src = -1;
     A.region_bytes = 0;
     A.coef_unit = F.sigma0 / (4.0 * M_PI * F.alpha * F.alpha);
+    A.sq_n = 0;
     return A;
 }
 

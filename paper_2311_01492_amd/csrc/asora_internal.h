@@ -148,11 +148,38 @@ hipError_t launch_adj_transpose_finalize(hipStream_t st, const double *nbar, con
 hipError_t launch_adj_finalize(hipStream_t st, const double *nbar, const float *nH, const float *xHI,
                                float *dnH, float *dxHI, long n3, int accumulate, int n_cu);
 
+// two absorbers, hydrogen and helium (asora_he.hip)
+struct HeLaunch {
+    int N;
+    double alpha, sigma0;
+    float tau_w;
+    int reading;
+    int nb, n_tab;
+    const TabNode *tab;               // nb x n_tab
+    TabParams tp[kMaxBands];
+    double sH[kMaxBands], sHe[kMaxBands];
+    const double *nHI, *nHeI, *nHI_T, *nHeI_T;
+    double *gH, *gHe, *gH_T, *gHe_T;
+    const int32_t *ijk;
+    const double *Q;
+    const float *R;
+    float R_cap;
+    const int *order;
+    int *ctl;
+    int *err;
+};
+size_t he_region_bytes(int S);
+hipError_t he_configure(size_t max_lds);
+hipError_t he_occupancy(int waves, size_t lds, int *blocks_per_cu);
+hipError_t launch_fwd_layer_he(hipStream_t st, const HeLaunch &H, int S, int waves, int grid, int plain_src);
+
 // host table builders (asora_tables.cpp)
 int table_blackbody(double T_bb, double index, int n, double lg_lo, double lg_hi, double *P,
                     double *dP);
 int table_blackbody_heat(double T_bb, double index, int n, double lg_lo, double lg_hi, double *H,
                          double *dH);
+int table_blackbody_band(double T_bb, double index, double e_lo_ev, double e_hi_ev, int n, double lg_lo,
+                         double lg_hi, double *P, double *dP);
 void prepare_table(int n, double lg_lo, double lg_hi, const double *P, const double *dP,
                    TabParams *tp, TabNode *nodes, double *m64);
 

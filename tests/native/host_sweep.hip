@@ -215,16 +215,16 @@ static int layer_forward_piece(const LayerPiece &L, const LayerX &X, int Rsq, co
                     const bool a0 = u > 0, a1 = u < m, b0 = v > 0, b1 = v < m;
                     const bool need[4] = {a1 && b1, a0 && b1, a1 && b0, a0 && b0};
                     for (int k = 0; k < 4; ++k)
-                        if (need[k] && lay_id[(size_t)(u - (k & 1)) * S + v - (k >> 1)] != m - 1) return -6;
+                        if (need[k] && lay_id[layer_slot(u - (k & 1), v - (k >> 1), S + 1)] != m - 1) return -6;
                 }
-                layer_cell(L, X, m, u, v, lay, S, lc[lane]);
+                layer_cell(L, X, m, u, v, lay, S + 1, lc[lane]);
             }
             uint64_t mask = 0;
             for (int lane = 0; lane < 64; ++lane) {
                 if (!act[lane]) continue;
                 const int u = uu[lane], v = vv[lane];
-                lay[(size_t)u * S + v] = lc[lane].h;
-                lay_id[(size_t)u * S + v] = m;
+                lay[layer_slot(u, v, S + 1)] = lc[lane].h;
+                lay_id[layer_slot(u, v, S + 1)] = m;
                 if (!(X.sigma0 * lc[lane].Nout >= opaque)) opq = false;
                 if (rec_on) rec->h[off + c * 64 + lane] = lc[lane].h;
                 if (!lc[lane].owned) continue;
@@ -323,8 +323,8 @@ extern "C" int hc_raytrace_layer(int N, double alpha, double sigma0, int n, doub
     host_layer_setup(H, N, n, lg_lo, lg_hi, P, dP, nH, xHI, nsrc, R);
     const long n3 = (long)N * N * N;
     std::vector<double> gT(n3, 0.0);
-    std::vector<double> lay((size_t)H.S * H.S);
-    std::vector<int> lay_id((size_t)H.S * H.S);
+    std::vector<double> lay((size_t)(H.S + 1) * (H.S + 1));   // padded, as in the kernels
+    std::vector<int> lay_id((size_t)(H.S + 1) * (H.S + 1));
     const double coef_unit = sigma0 / (4.0 * M_PI * alpha * alpha);
     for (long s = 0; s < nsrc; ++s) {
         const int si = ijk[3 * s], sj = ijk[3 * s + 1], sk = ijk[3 * s + 2];
@@ -388,9 +388,9 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
         for (long j = 0; j < N; ++j)
             for (long k = 0; k < N; ++k) gbT[(k * N + i) * N + j] = gbar[(i * N + j) * N + k];
     const int S = H.S;
-    const size_t SS = (size_t)S * S;
-    std::vector<double> cols(SS), abar(SS), gin(H.cap);
-    std::vector<int> cols_id(SS);
+    const size_t SS = (size_t)S * S, PP = (size_t)(S + 1) * (S + 1);
+    std::vector<double> cols(PP), abar(SS), gin(H.cap);
+    std::vector<int> cols_id(PP);
     std::vector<char> recmem(layer_record_bytes(H.cap, H.Mcap, kept));
     LayerRecord rec = layer_record_at(recmem.data(), H.cap, kept ? layer_record_bytes(H.cap, H.Mcap, false) : 0);
     const double coef_unit = sigma0 / (4.0 * M_PI * alpha * alpha);
@@ -653,3 +653,7 @@ extern "C" int hc_raytrace_grad(int N, double alpha, double sigma0, int n, doubl
     }
     return 0;
 }
+
+// The kernels' FP64 logarithms (unit access for their accuracy pins).
+extern "C" double hc_log_fast(double a) { return log_fast(a); }
+extern "C" double hc_log_f64(double a) { return log_f64(a); }

@@ -145,3 +145,17 @@ def raytrace_grad(N, cell_cm, sigma0, table, n_H, x_HI, ijk, Q, R, gbar, tau_w=0
         raise RuntimeError(f"host grad failed: {st}")
     nbar = nbar.reshape((N,) * 3)
     return xH.astype(np.float64) * nbar, nH.astype(np.float64) * nbar, qbar
+
+
+def log_fast(a):
+    lib = load()
+    lib.hc_log_fast.restype = ctypes.c_double
+    lib.hc_log_fast.argtypes = [ctypes.c_double]
+    return lib.hc_log_fast(float(a))
+
+
+def log_f64(a):
+    lib = load()
+    lib.hc_log_f64.restype = ctypes.c_double
+    lib.hc_log_f64.argtypes = [ctypes.c_double]
+    return lib.hc_log_f64(float(a))

@@ -216,3 +216,35 @@ def test_layer_adjoint_extent_clip_and_wrap(bb):
             assert_grad_parity(hn, on, 1e-5, what="dL/dn_H")
             assert_grad_parity(hx, ox, 1e-5, what="dL/dx_HI")
             np.testing.assert_allclose(hq, oq, rtol=1e-6)
+
+
+def test_kernel_logarithms():
+    """The kernels' FP64 logarithms: log_fast (the rate's table position,
+    2e-11 absolute) and log_f64 (the FP64 derivatives of the adjoint, 1e-14)."""
+    rng = np.random.default_rng(11)
+    for a in 10.0 ** rng.uniform(-20, 4.5, 3000):
+        assert abs(hostsweep.log_fast(a) - math.log(a)) < 2.5e-11
+        assert abs(hostsweep.log_f64(a) - math.log(a)) < 1e-14
+
+
+def test_layer_adjoint_at_full_radii_of_the_250_grid(bb):
+    """The kernels' per-cell adjoint code, emulated on the CPU, on sources of
+    R in [40, 50] of the 1e5-source 250^3 workload (unclipped), against the
+    oracle's reverse mode: the long columns and deep optical depths of these
+    radii are where the rate derivatives' difference quotients magnify an
+    error of the table position (the case that needs log_f64)."""
+    w = make_workload("c3")
+    cand = np.nonzero((w.src.R >= 40) & (w.src.R <= 50))[0]
+    idx = np.sort(np.random.default_rng(31).choice(cand, size=4, replace=False))
+    sub = w.src.subset(idx)
+    g = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, sub.ijk, sub.Q, sub.R)
+    wt = np.random.default_rng(32).standard_normal(g.shape)
+    gbar = wt / ((g + 1e-20) * math.log(10))
+    on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, sub.ijk, sub.Q, sub.R, gbar)
+    from tests.parity import assert_grad_parity
+    for split, kept in ((False, False), (True, False), (False, True)):
+        hn, hx, hq = hostsweep.raytrace_grad(w.N, w.cell_cm, oracle.SIGMA0, bb, w.n_H, w.x_HI, sub.ijk, sub.Q,
+                                             sub.R, gbar, layers=True, split=split, kept=kept)
+        assert_grad_parity(hn, on, 1e-6, what="dL/dn_H")
+        assert_grad_parity(hx, ox, 1e-6, what="dL/dx_HI")
+        np.testing.assert_allclose(hq, oq, rtol=1e-8)

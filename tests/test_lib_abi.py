@@ -61,6 +61,18 @@ def test_table_blackbody_heat_matches_oracle(pkg):
         pkg.table_blackbody_heat(0.0)
 
 
+def test_table_blackbody_band_matches_oracle(pkg):
+    """The band tables of the two-absorber sweep against the oracle's
+    quadrature (coarse node grids: the oracle's adaptive quadrature is slow)."""
+    for lo, hi, lg_hi in ((13.6, 24.59, 2.5), (35.0, 54.42, 2.3), (54.42, math.inf, 3.3)):
+        P, dP = pkg.table_blackbody_band(lo, hi, n=120, lg_hi=lg_hi)
+        t = oracle.blackbody_band_table(lo, hi, n=120, lg_hi=lg_hi)
+        np.testing.assert_allclose(P, t.P, rtol=1e-10, atol=0)
+        np.testing.assert_allclose(dP, t.dP, rtol=1e-10, atol=0)
+    with pytest.raises(pkg.AsoraError):
+        pkg.table_blackbody_band(10.0, 20.0)
+
+
 def test_table_grey(pkg):
     P, dP = pkg.table_grey(500, -20.0, math.log10(80.0))
     tau = 10 ** np.linspace(-20, math.log10(80.0), 500)
