@@ -316,6 +316,13 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, const do
     // form (most cells have a rate there, and most lanes work anyway)
     constexpr bool QUEUE = KEPT || !SPLIT;
 
+    // the pyramid's index terms along u and v (every pass)
+    for (int k = lane; k < S; k += 64) {
+        iu[k] = layer_idx_u(L, N, k);
+        iv[k] = layer_idx_v(L, N, k);
+    }
+    wave_sync();
+
     // ---- (F), every layer; with the early exit only up to the first layer
     // whose cells all leave opaque (layer_opaque): later layers have no rate
     // and no adjoint.  Kept records hold the layers their forward swept.
@@ -327,10 +334,6 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, const do
         const bool watch = A.early_exit != 0;
         const int P = S + 1;   // row stride of the padded layer buffer
         for (int k = lane; k < P * P; k += 64) buf[k] = 0.0;   // finite everywhere it is read
-        for (int k = lane; k < S; k += 64) {                   // the pyramid's index terms
-            iu[k] = layer_idx_u(L, N, k);
-            iv[k] = layer_idx_v(L, N, k);
-        }
         wave_sync();
         const double opaque = layer_opaque(A.tp.tau_hi);
         long off = 0, choff = 0;
@@ -405,8 +408,13 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, const do
                 w.init(r, g);
                 const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m >= 2 ? m - 1 : 1);
                 const double *Hprev = rec.h + (m >= 2 ? k - g - rp.total : 0);
+                const int u = w.u, v = w.v;
+                const double inv_m = rcp_f64((double)m);
+                const int r2 = mul24(m, m) + mul24(u, u) + mul24(v, v);
+                const double rt = A.sq_n ? sq[r2] : sqrt_fast((double)r2);
                 LayerInterp I;
-                layer_interp(L, X, m, w.u, w.v, Hprev, rp, I);
+                layer_interp_core(X, m, u, v, layer_idx_d(L, N, m) + iu[u] + iv[v], r2, rt * inv_m,
+                                  layer_geo(m, inv_m, u), layer_geo(m, inv_m, v), Hprev, rp, I);
                 const double gb = gbar[I.cp];
                 double gi = 0.0;
                 if (gb != 0.0) {
@@ -469,6 +477,17 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, const do
             // entries of layer m - 1 (its rectangle precedes layer m's)
             const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m >= 2 ? m - 1 : 1);
             const double *Hprev = rec.h + (m >= 2 ? off - rp.total : 0);
+            // this layer's geometry (the previous layer's readers are done)
+            const double inv_m = rcp_f64((double)m);
+            const int m2 = mul24(m, m);
+            const uint32_t idx_d = layer_idx_d(L, N, m);
+            for (int k = lane; k < S; k += 64) geo[k] = layer_geo(m, inv_m, k);
+            wave_sync();
+            auto interp = [&](int u, int v, LayerInterp &I) {
+                const int r2 = m2 + mul24(u, u) + mul24(v, v);
+                const double rt = A.sq_n ? sq[r2] : sqrt_fast((double)r2);
+                layer_interp_core(X, m, u, v, idx_d + iu[u] + iv[v], r2, rt * inv_m, geo[u], geo[v], Hprev, rp, I);
+            };
             // a batch of queued cells of layer m; every slot a cell pushes to
             // precedes it in (u, v) order, so its chunk was taken before the
             // cell was queued
@@ -481,7 +500,7 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, const do
                     int u, v;
                     rect_cell(r, g, u, v);
                     LayerInterp I;
-                    layer_interp(L, X, m, u, v, Hprev, rp, I);
+                    interp(u, v, I);
                     double nbx = 0.0;
                     if (KEPT && li >= 0) {   // the rate's terms, from its coefficients
                         const double gbc = gbar[I.cp] * coef;
@@ -559,7 +578,7 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, const do
                     if (lit && !dense) Tin += gin[off + g];
                     if (Tin != 0.0 || (lit && dense)) {
                         LayerInterp I;
-                        layer_interp(L, X, m, u, v, Hprev, rp, I);
+                        interp(u, v, I);
                         double extra = 0.0;
                         if (lit && dense) {
                             const double gb = gbar[I.cp];

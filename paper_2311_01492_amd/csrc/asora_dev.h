@@ -1199,22 +1199,21 @@ struct LayerInterp {
 // The interpolation of cell (u, v) of layer m from its four neighbours in
 // layer m - 1, whose entries Hprev holds in layer m - 1's rectangle rp (for
 // m = 1 the only neighbour of non-zero weight is the source: N_in is its
-// column).  Neighbours of zero weight may lie outside layer m - 1 and are not
-// read.
-__host__ __device__ __forceinline__ void layer_interp(const LayerPiece &L, const LayerX &X, int m, int u,
-                                                      int v, const double *Hprev, const LayerRect &rp,
-                                                      LayerInterp &I)
+// column), given the cell's index cp, r2, ds and bilinear factors gu, gv
+// (layer_geo).  Neighbours of zero weight may lie outside layer m - 1 and
+// are not read.
+__host__ __device__ __forceinline__ void layer_interp_core(const LayerX &X, int m, int u, int v, uint32_t cp,
+                                                           int r2, double ds, const Geo &gu, const Geo &gv,
+                                                           const double *Hprev, const LayerRect &rp,
+                                                           LayerInterp &I)
 {
-    I.cp = layer_cp(L, X.N, m, u, v);
-    const double inv_m = rcp_f64((double)m);
-    I.r2 = mul24(m, m) + mul24(u, u) + mul24(v, v);
-    I.ds = sqrt_fast((double)I.r2) * inv_m;
-    const double a = u == m ? 1.0 : (double)u * inv_m;
-    const double b = v == m ? 1.0 : (double)v * inv_m;
-    I.sw[0] = (1.0 - a) * (1.0 - b);
-    I.sw[1] = a * (1.0 - b);
-    I.sw[2] = (1.0 - a) * b;
-    I.sw[3] = a * b;
+    I.cp = cp;
+    I.r2 = r2;
+    I.ds = ds;
+    I.sw[0] = gu.om * gv.om;
+    I.sw[1] = gu.a * gv.om;
+    I.sw[2] = gu.om * gv.a;
+    I.sw[3] = gu.a * gv.a;
     I.iW = 1.0;
     if (m == 1) {
         I.Nin = X.reading == 0 ? X.half_col * I.ds : X.half_col;
@@ -1234,6 +1233,17 @@ __host__ __device__ __forceinline__ void layer_interp(const LayerPiece &L, const
     }
     I.iW = rcp_f64(W);
     I.Nin = num * I.iW;
+}
+
+// The same with the cell's geometry computed in place (the reference form of
+// what the adjoint kernel does with its tables).
+__host__ __device__ __forceinline__ void layer_interp(const LayerPiece &L, const LayerX &X, int m, int u, int v,
+                                                      const double *Hprev, const LayerRect &rp, LayerInterp &I)
+{
+    const double inv_m = rcp_f64((double)m);
+    const int r2 = mul24(m, m) + mul24(u, u) + mul24(v, v);
+    layer_interp_core(X, m, u, v, layer_cp(L, X.N, m, u, v), r2, sqrt_fast((double)r2) * inv_m,
+                      layer_geo(m, inv_m, u), layer_geo(m, inv_m, v), Hprev, rp, I);
 }
 
 // The rate's share of the adjoint of a cell with a rate (owned, entry optical
