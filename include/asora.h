@@ -188,6 +188,30 @@ asora_status asora_raytrace(asora_ctx *ctx, const float *n_H, const float *x_HI,
                             void *stream);
 
 /*
+ * asora_raytrace_static -- asora_raytrace for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc): the call allocates nothing.  Its scratch (n_HI and
+ * the FP64 rate accumulator in both layouts, work counters, source keys and
+ * scheduling order) lives in a fixed-size device array of the library, about
+ * 8.6 MiB, which every device the library runs on holds until the process
+ * ends; the tables and parameters come from the context as asora_init made
+ * them.  Limits: N <= 64 and n_src <= 65536; larger calls return ASORA_EINVAL
+ * before anything is enqueued.  The caller passes every input and output as
+ * for asora_raytrace (same arguments and meaning).
+ *   flags        ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_PROFILE |
+ *                ASORA_EARLY_EXIT (not ASORA_STORE: kept records need memory).
+ * Every call on a device uses that device's one array and leaves its contents
+ * there; the call clears what must start at zero itself.  Calls that overlap
+ * on one device (several streams, threads or contexts) race on the array and
+ * give wrong results; serialise them.  Results equal asora_raytrace's up to
+ * the order of floating-point sums.
+ */
+asora_status asora_raytrace_static(asora_ctx *ctx, const float *n_H, const float *x_HI, int64_t n_src,
+                                   const int32_t *src_ijk, const double *src_Q, const float *src_R,
+                                   float R_max, float *gamma, double *coldens_in, uint32_t flags,
+                                   void *stream);
+
+/*
  * asora_set_heating_table -- give the context a photo-heating table: H(tau)
  * and dH/dtau (host arrays of the context's n_tab doubles, copied) on the
  * node grid of its photoionization table, for the same source spectrum, in

@@ -47,6 +47,8 @@ _lib.asora_init.argtypes = [ctypes.POINTER(_p), _c_int, _c_d, _c_d, _c_d, _c_d, 
                             _c_d, _c_u32, _c_int]
 _lib.asora_raytrace.restype = _c_int
 _lib.asora_raytrace.argtypes = [_p, _p, _p, _c_i64, _p, _p, _p, _c_f, _p, _p, _c_u32, _p]
+_lib.asora_raytrace_static.restype = _c_int
+_lib.asora_raytrace_static.argtypes = [_p, _p, _p, _c_i64, _p, _p, _p, _c_f, _p, _p, _c_u32, _p]
 _lib.asora_chemistry.restype = _c_int
 _lib.asora_chemistry.argtypes = [_p, _p, _p, _p, _p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_double, _p, _p, _p, ctypes.POINTER(ctypes.c_uint64), _p]
@@ -266,6 +268,24 @@ class Asora:
         _raise(st, self._h)
         shape = (self.N,) * 3
         return (gamma.view(shape), cd.view(shape)) if coldens else gamma.view(shape)
+
+    def raytrace_static(self, n_H, x_HI, ijk, Q, R=None, R_max=None, out=None, coldens=None,
+                        plain=False, accumulate=False, early_exit=False, stream=None):
+        """Gamma into `out` (float32 cuda, N^3) through asora_raytrace_static,
+        the entry point that allocates no device memory (N <= 64, up to 65536
+        sources); `coldens` (float64 cuda N^3, one source) receives the entry
+        column.  The caller provides every buffer."""
+        ijk, Q, R, R_max, n = self._prep(n_H, x_HI, ijk, Q, R, R_max)
+        if out is None:
+            raise AsoraError(-1, "raytrace_static needs the output buffer `out`")
+        self._check("out", out, torch.float32)
+        if coldens is not None:
+            self._check("coldens", coldens, torch.float64)
+        flags = (PLAIN if plain else 0) | (ACCUMULATE if accumulate else 0) | (EARLY_EXIT if early_exit else 0)
+        st = _lib.asora_raytrace_static(self._h, _dptr(n_H), _dptr(x_HI), n, _dptr(ijk), _dptr(Q), _dptr(R),
+                                        R_max, _dptr(out), _dptr(coldens), flags, _stream_ptr(stream))
+        _raise(st, self._h)
+        return out.view((self.N,) * 3)
 
     def set_helium(self, bands):
         """Band tables of the two-absorber sweep (asora_set_helium): `bands` is a

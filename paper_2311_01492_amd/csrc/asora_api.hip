@@ -113,6 +113,7 @@ struct asora_ctx {
                             // hold its buffers' addresses, so no buffer may move
     std::map<std::string, std::vector<float>> tuned;   // autotune results by workload key
     std::string dev_tag;    // device name and compute-unit count (part of the tuning keys)
+    char *d_static;         // this device's `scratch` array (asora_raytrace_static), or NULL
     asora_tune_progress_fn tune_cb;   // called after every timed autotune candidate (may be NULL)
     void *tune_cb_user;
     // chemistry: counters (cells changed, cells whose n_e iteration did not
@@ -200,6 +201,48 @@ static int bad_table_node(int n, const double *P, const double *dP)
             (k > 0 && P[k] > P[k - 1]))
             return k;
     return -1;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free forward (asora_raytrace_static): a file-scope
+// device array of fixed size, of which every device holds its own copy for
+// the life of the process.  Host code never uses the array's name as an
+// address: asora_init looks up each device's copy once with
+// hipGetSymbolAddress and every later use goes through that pointer.
+// Layout: n_HI, the rate accumulator and their [k][i][j] copies (FP64, up to
+// kStaticMaxN^3 cells each), the control block, the source keys and the
+// scheduling order (up to kStaticMaxSources each).
+constexpr int kStaticMaxN = 64;
+constexpr long kStaticMaxSources = 1L << 16;
+constexpr size_t kStaticCells = (size_t)kStaticMaxN * kStaticMaxN * kStaticMaxN;
+constexpr size_t pad256(size_t b) { return (b + 255) & ~(size_t)255; }
+constexpr size_t kStaticGrid = pad256(kStaticCells * sizeof(double));
+constexpr size_t kStaticOffCtl = 4 * kStaticGrid;
+constexpr size_t kStaticOffKeys = kStaticOffCtl + pad256((size_t)kCtlSize * sizeof(int));
+constexpr size_t kStaticOffOrder = kStaticOffKeys + pad256((size_t)kStaticMaxSources * sizeof(int));
+constexpr size_t kStaticBytes = kStaticOffOrder + pad256((size_t)kStaticMaxSources * sizeof(int));
+
+static __device__ __align__(256) char scratch[kStaticBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static char *g_scratch_ptr[kMaxDevices];   // each device's copy of `scratch` (NULL: not looked up yet)
+
+// This device's copy of `scratch` (the device must be current), looked up
+// once per device.
+static hipError_t device_scratch(int device, char **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = (char *)p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
 }
 
 extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, double sigma0_cm2,
@@ -299,6 +342,12 @@ extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, d
     if (fwd_configure(c->max_lds) != hipSuccess || adj_configure(c->max_lds) != hipSuccess ||
         he_configure(c->max_lds) != hipSuccess)
         return bail(fail(nullptr, ASORA_EHIP, "asora_init: kernel attribute setup failed"));
+    {
+        const hipError_t e = device_scratch(device, &c->d_static);
+        if (e != hipSuccess)
+            return bail(fail(nullptr, ASORA_EHIP, "asora_init: hipGetSymbolAddress of the static scratch: %s",
+                             hipGetErrorString(e)));
+    }
     *out = c;
     return ASORA_OK;
 }
@@ -994,6 +1043,39 @@ extern "C" asora_status asora_raytrace_helium(asora_ctx *c, const float *n_H, co
         if (c->prof_pending < kProfSlots) c->prof_pending++;
     }
     return ASORA_OK;
+}
+
+extern "C" asora_status asora_raytrace_static(asora_ctx *c, const float *n_H, const float *x_HI, int64_t n_src,
+                                              const int32_t *src_ijk, const double *src_Q, const float *src_R,
+                                              float R_max, float *gamma, double *coldens_in, uint32_t flags,
+                                              void *stream)
+{
+    if (!ctx_ok(c)) return ASORA_ESTATE;
+    asora_status st = check_common(c, n_H, x_HI, n_src, src_ijk, src_Q, R_max);
+    if (st) return st;
+    if (!gamma) return fail(c, ASORA_EINVAL, "gamma must not be NULL");
+    if (coldens_in && n_src != 1) return fail(c, ASORA_EINVAL, "coldens_in requires n_src == 1");
+    if (flags & ~(ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_PROFILE | ASORA_EARLY_EXIT))
+        return fail(c, ASORA_EINVAL, "asora_raytrace_static: flags may be ACCUMULATE, PLAIN, PROFILE, EARLY_EXIT");
+    if (coldens_in && (flags & ASORA_EARLY_EXIT))
+        return fail(c, ASORA_EINVAL, "ASORA_EARLY_EXIT does not give entry columns (coldens_in)");
+    if (c->N > kStaticMaxN)
+        return fail(c, ASORA_EINVAL, "asora_raytrace_static: N=%d exceeds the static scratch (N <= %d)", c->N,
+                    kStaticMaxN);
+    if (n_src > kStaticMaxSources)
+        return fail(c, ASORA_EINVAL, "asora_raytrace_static: n_src=%lld exceeds the static scratch (<= %ld)",
+                    (long long)n_src, kStaticMaxSources);
+    if (!c->d_static) return fail(c, ASORA_ESTATE, "asora_raytrace_static: no static scratch on this device");
+    HIPCHK(c, hipSetDevice(c->device));
+    Plan plans[4];
+    int tmax = 0;
+    if ((st = forward_plans(c, R_max, false, plans, &tmax))) return st;
+    char *base = c->d_static;
+    const FwdBufs B{(double *)base, (double *)(base + kStaticGrid), (double *)(base + 2 * kStaticGrid),
+                    (double *)(base + 3 * kStaticGrid), (int *)(base + kStaticOffCtl), (int *)(base + kStaticOffKeys),
+                    (int *)(base + kStaticOffOrder)};
+    return forward_launch(c, B, plans, tmax, n_H, x_HI, n_src, src_ijk, src_Q, src_R, R_max, gamma, nullptr,
+                          coldens_in, flags, false, (hipStream_t)stream);
 }
 
 extern "C" asora_status asora_set_tuning(asora_ctx *c, float R_whole, float R_oct, int32_t max_waves,
