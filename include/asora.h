@@ -414,8 +414,9 @@ asora_status asora_set_store_budget(asora_ctx *ctx, uint64_t bytes);
  * in the adjoint.  table_place: where the layer forward reads the table, 1 =
  * a copy in LDS per work-group (the default), 2 = through the caches (which
  * leaves the LDS to more waves).  max_waves (1..16) caps the waves per
- * work-group.  The adjoint of layer pyramids: adj_waves (1..12, default 4)
- * waves per work-group; adj_rate 1 = the rate terms of every cell with a rate
+ * work-group.  The adjoint of layer pyramids: adj_waves (1..16, default 4)
+ * waves per work-group (above 12 a build held to four waves per SIMD, which
+ * may spill registers); adj_rate 1 = the rate terms of every cell with a rate
  * gathered into full waves before the reverse pass (fewer registers: suits
  * sources whose rate reaches few cells), 2 = those of chunks where at least
  * half the cells have a rate evaluated in the reverse pass itself (the
@@ -423,7 +424,7 @@ asora_status asora_set_store_budget(asora_ctx *ctx, uint64_t bytes);
  * the adjoint re-sweeps the pyramids (records kept with ASORA_STORE carry the
  * rate's derivatives).  Values <= 0
  * keep the current setting.  ASORA_EINVAL if R_oct < R_whole, max_waves > 16,
- * pyramid_sweep is not 0, 2 or 3, table_place not 0, 1 or 2, adj_waves > 12
+ * pyramid_sweep is not 0, 2 or 3, table_place not 0, 1 or 2, adj_waves > 16
  * or adj_rate not 0, 1 or 2; ASORA_ESTATE while a recorded graph of the
  * context exists.
  */
@@ -441,7 +442,7 @@ asora_status asora_set_tuning(asora_ctx *ctx, float R_whole, float R_oct, int32_
  * measurement, not by rule).  Coordinate descent over: the sweep of pyramid
  * pieces (layers, shells), the place of the table (LDS, caches), the waves
  * per work-group (4, 8, 12, 16), for passes = 2 with layer pyramids the
- * layer adjoint's adj_rate (1, 2) and adj_waves (2, 4, 8, 12), R_oct (8, 10,
+ * layer adjoint's adj_rate (1, 2) and adj_waves (2, 4, 8, 12, 16), R_oct (8, 10,
  * 12, 15, 20) and R_whole (3, 4, 6, 8); every candidate is one
  * warm-up call and the median of three calls timed with HIP events on
  * `stream`.  passes = 1 times the forward; passes = 2 the forward with

@@ -18,7 +18,11 @@
 
 namespace asora {
 
-constexpr int kAdjLayerThreads = 64 * kAdjLayerWaves;   // layer adjoint work-groups
+// Layer adjoint work-groups: up to kAdjLayerNarrow waves the kernel may hold
+// 168 VGPRs per lane (three waves per SIMD); the wide build, up to
+// kAdjLayerWaves waves, is held to 128 (four per SIMD) and spills the rest.
+// Which wins depends on the workload: the work-group size is tuned.
+constexpr int kAdjLayerNarrow = 12;
 
 struct AdjArgs {
     int N;
@@ -630,8 +634,8 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, const do
     }
 }
 
-template <bool KEPT, bool SPLIT>
-__global__ __launch_bounds__(kAdjLayerThreads) void adj_layer(AdjArgs A)
+template <bool KEPT, bool SPLIT, int MAXW>
+__global__ __launch_bounds__(64 * MAXW) void adj_layer(AdjArgs A)
 {
     extern __shared__ __align__(16) char smem[];
     constexpr int TYPE = 3, npieces = 24;
@@ -771,14 +775,28 @@ static const void *adj_fn(int type)
                      : (type == 1 ? (const void *)adj_wave<1> : (const void *)adj_wave<2>);
 }
 
+// The layer adjoint's instantiation: kept records (no rate terms to split),
+// split rate terms or gathered ones; the wide build above kAdjLayerNarrow waves.
+static const void *adj_layer_fn(bool kept, bool split, bool wide)
+{
+    if (wide)
+        return kept ? (const void *)adj_layer<true, false, kAdjLayerWaves>
+                    : (split ? (const void *)adj_layer<false, true, kAdjLayerWaves>
+                             : (const void *)adj_layer<false, false, kAdjLayerWaves>);
+    return kept ? (const void *)adj_layer<true, false, kAdjLayerNarrow>
+                : (split ? (const void *)adj_layer<false, true, kAdjLayerNarrow>
+                         : (const void *)adj_layer<false, false, kAdjLayerNarrow>);
+}
+
 hipError_t adj_configure(size_t max_lds)
 {
     const int dyn = (int)max_lds - 64;
     for (int t = 0; t < 3; ++t)
         (void)hipFuncSetAttribute(adj_fn(t), hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
-    for (const void *f : {(const void *)adj_layer<false, false>, (const void *)adj_layer<false, true>,
-                          (const void *)adj_layer<true, false>})
-        (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
+    for (bool wide : {false, true})
+        for (int v = 0; v < 3; ++v)
+            (void)hipFuncSetAttribute(adj_layer_fn(v == 2, v == 1, wide), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      dyn);
     (void)hipGetLastError();
     return hipSuccess;
 }
@@ -868,8 +886,7 @@ size_t adj_layer_region_bytes(int S)
 hipError_t adj_layer_occupancy(bool kept, bool split, int waves, size_t lds, int *blocks_per_cu)
 {
     // kept records carry the rate's coefficients: no rate terms to split
-    const void *f = kept ? (const void *)adj_layer<true, false>
-                         : (split ? (const void *)adj_layer<false, true> : (const void *)adj_layer<false, false>);
+    const void *f = adj_layer_fn(kept, !kept && split, waves > kAdjLayerNarrow);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, waves * 64, lds);
 }
 
@@ -880,13 +897,20 @@ hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int Mcap, int S)
     A.lay_S = S;
     A.region_bytes = (int)adj_layer_region_bytes(S);
     const int Rsq = (int)floor((double)L.R_cap * (double)L.R_cap);
-    const size_t sqb = layer_sqrt_bytes(Rsq);
+    const size_t sqb = L.sq_table ? layer_sqrt_bytes(Rsq) : 0;
     A.sq_n = sqb ? Rsq + 1 : 0;
     const size_t lds = sqb + (size_t)L.waves * A.region_bytes;
     const dim3 grid(L.grid), block(64 * L.waves);
-    if (A.kept) hipLaunchKernelGGL((adj_layer<true, false>), grid, block, lds, st, A);
-    else if (L.split) hipLaunchKernelGGL((adj_layer<false, true>), grid, block, lds, st, A);
-    else hipLaunchKernelGGL((adj_layer<false, false>), grid, block, lds, st, A);
+    constexpr int W = kAdjLayerWaves, Wn = kAdjLayerNarrow;
+    if (L.waves > Wn) {
+        if (A.kept) hipLaunchKernelGGL((adj_layer<true, false, W>), grid, block, lds, st, A);
+        else if (L.split) hipLaunchKernelGGL((adj_layer<false, true, W>), grid, block, lds, st, A);
+        else hipLaunchKernelGGL((adj_layer<false, false, W>), grid, block, lds, st, A);
+    } else {
+        if (A.kept) hipLaunchKernelGGL((adj_layer<true, false, Wn>), grid, block, lds, st, A);
+        else if (L.split) hipLaunchKernelGGL((adj_layer<false, true, Wn>), grid, block, lds, st, A);
+        else hipLaunchKernelGGL((adj_layer<false, false, Wn>), grid, block, lds, st, A);
+    }
     return hipGetLastError();
 }
 

@@ -35,6 +35,10 @@ struct Plan {
     int waves;
     size_t lds;
     int grid;
+    bool sq_table;      // layer pieces: the work-group holds the table of sqrt(r^2)
+    // layer forward that keeps the column records (a larger rate queue)
+    int kwaves, kgrid;
+    bool ksq_table;
 };
 
 static const int kProfSlots = 64;
@@ -493,6 +497,22 @@ static asora_status get_plan(asora_ctx *c, int type, float R_cap, Plan *out, boo
     return ASORA_OK;
 }
 
+// Waves of a layer sweep's work-group: as many per-wave regions as fit in the
+// LDS next to the work-group's own bytes (wg), up to cap.  The table of square
+// roots (sqb bytes) is added only when it costs no wave: a wave more hides
+// more latency than the table saves (a root is a handful of instructions per
+// cell).  0 when not even one region fits.
+static int layer_waves(const asora_ctx *c, size_t wg, size_t sqb, size_t region, int cap, bool *sq_table)
+{
+    auto fit = [&](size_t b) -> long {
+        const long f = c->max_lds > b + 64 ? (long)((c->max_lds - b - 64) / region) : 0;
+        return f < cap ? f : cap;
+    };
+    const long with = sqb ? fit(wg + sqb) : 0, without = fit(wg);
+    *sq_table = sqb && with >= without;
+    return (int)(*sq_table ? with : without);
+}
+
 // Layer pieces: one wave per pyramid, the wave's LDS holds one layer.
 static asora_status get_layer_plan(asora_ctx *c, float R_cap, Plan *out, bool store)
 {
@@ -517,19 +537,28 @@ static asora_status get_layer_plan(asora_ctx *c, float R_cap, Plan *out, bool st
     P.keep_bytes = layer_record_bytes(P.rec_cap, P.Mcap, true);
     P.wave_mode = 1;
     // the work-group's LDS: the table (if placed there), the table of square
-    // roots, one region per wave
-    const size_t tab = (c->tab_lds ? (size_t)c->tp.n * sizeof(TabNode) : 0) + layer_sqrt_bytes(Rsq);
-    const size_t region = layer_region_bytes(P.S);
-    const long fit = c->max_lds > tab + 64 ? (long)((c->max_lds - tab - 64) / region) : 0;
-    if (fit < 1)
-        return fail(c, ASORA_ENOSYS,
-                    "R_max=%.1f needs %zu bytes of LDS per wave (limit %zu) for this table and grid",
-                    R_cap, region + tab, c->max_lds);
-    P.waves = (int)(fit < c->max_waves ? fit : c->max_waves);
-    P.lds = tab + (size_t)P.waves * region;
-    int bpc = 0;
-    HIPCHK(c, layer_occupancy(c->tab_lds != 0, P.waves, P.lds, &bpc));
-    P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
+    // roots (if it costs no wave), one region per wave
+    const size_t tab = c->tab_lds ? (size_t)c->tp.n * sizeof(TabNode) : 0;
+    const size_t sqb = layer_sqrt_bytes(Rsq);
+    for (bool keep : {false, true}) {
+        const size_t region = layer_region_bytes(P.S, keep);
+        bool sq = false;
+        const int waves = layer_waves(c, tab, sqb, region, c->max_waves, &sq);
+        if (waves < 1 || Rsq > 65535)   // the rate queue holds r^2 in 16 bits
+            return fail(c, ASORA_ENOSYS,
+                        "R_max=%.1f needs %zu bytes of LDS per wave (limit %zu) for this table and grid",
+                        R_cap, region + tab, c->max_lds);
+        const size_t lds = tab + (sq ? sqb : 0) + (size_t)waves * region;
+        int bpc = 0;
+        HIPCHK(c, layer_occupancy(keep, c->tab_lds != 0, waves, lds, &bpc));
+        const int grid = c->n_cu * (bpc > 0 ? bpc : 1);
+        if (keep) {
+            P.kwaves = waves, P.kgrid = grid, P.ksq_table = sq;
+        } else {
+            P.waves = waves, P.grid = grid, P.sq_table = sq;
+            P.lds = lds;
+        }
+    }
     if (store) c->plans[key] = P;
     *out = P;
     return ASORA_OK;
@@ -750,6 +779,7 @@ static asora_status forward_launch(asora_ctx *c, const FwdBufs &B, const Plan pl
     F.keep_rk_off = layers ? plans[3].rec_bytes : 0;
     F.m64 = c->d_m64;
     F.tab_lds = c->tab_lds;
+    F.sq_table = layers && (keep ? plans[3].ksq_table : plans[3].sq_table);
     F.early_exit = (flags & ASORA_EARLY_EXIT) != 0;
     F.tab_h = heating ? c->d_tab_h : nullptr;
     F.hacc = heating ? c->d_hacc : nullptr;
@@ -776,7 +806,8 @@ static asora_status forward_launch(asora_ctx *c, const FwdBufs &B, const Plan pl
             F.row_cap = plans[tmax].row_cap;
             for (long k = 0; k < n_src; ++k) {
                 if (tmax == 3)
-                    HIPCHK(c, launch_fwd_layer(s, F, plans[3].S, plans[3].waves, 0, (int)k));
+                    HIPCHK(c, launch_fwd_layer(s, F, plans[3].S, keep ? plans[3].kwaves : plans[3].waves, 0,
+                                               (int)k));
                 else if (plans[tmax].wave_mode)
                     HIPCHK(c, launch_fwd_wave(s, F, plans[tmax].waves, 0, (int)k));
                 else
@@ -790,7 +821,8 @@ static asora_status forward_launch(asora_ctx *c, const FwdBufs &B, const Plan pl
                 F.ring_cap = plans[t].ring_cap;
                 F.row_cap = plans[t].row_cap;
                 if (t == 3)
-                    HIPCHK(c, launch_fwd_layer(s, F, plans[3].S, plans[3].waves, plans[3].grid, -1));
+                    HIPCHK(c, launch_fwd_layer(s, F, plans[3].S, keep ? plans[3].kwaves : plans[3].waves,
+                                               keep ? plans[3].kgrid : plans[3].grid, -1));
                 else if (plans[t].wave_mode)
                     HIPCHK(c, launch_fwd_wave(s, F, plans[t].waves, plans[t].grid, -1));
                 else
@@ -938,14 +970,13 @@ static asora_status get_he_plan(asora_ctx *c, float R_cap, Plan *out)
     Plan P = Plan();
     P.S = layer_buffer_side(Rsq, ex);
     P.wave_mode = 1;
-    const size_t wg = layer_sqrt_bytes(Rsq);
+    const size_t sqb = layer_sqrt_bytes(Rsq);
     const size_t region = he_region_bytes(P.S);
-    const long fit = c->max_lds > wg + 64 ? (long)((c->max_lds - wg - 64) / region) : 0;
-    if (fit < 1)
+    P.waves = layer_waves(c, 0, sqb, region, c->max_waves, &P.sq_table);
+    if (P.waves < 1)
         return fail(c, ASORA_ENOSYS, "asora_raytrace_helium: R_max=%.1f needs %zu bytes of LDS per wave (limit %zu)",
-                    R_cap, region + wg, c->max_lds);
-    P.waves = (int)(fit < c->max_waves ? fit : c->max_waves);
-    P.lds = wg + (size_t)P.waves * region;
+                    R_cap, region, c->max_lds);
+    P.lds = (P.sq_table ? sqb : 0) + (size_t)P.waves * region;
     int bpc = 0;
     HIPCHK(c, he_occupancy(P.waves, P.lds, &bpc));
     P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
@@ -1027,6 +1058,7 @@ extern "C" asora_status asora_raytrace_helium(asora_ctx *c, const float *n_H, co
         H.order = c->d_order;
         H.ctl = c->d_ctl;
         H.err = c->d_err;
+        H.sq_table = plan.sq_table;
         if (flags & ASORA_PLAIN) {
             for (long k = 0; k < n_src; ++k)
                 HIPCHK(c, launch_fwd_layer_he(s, H, plan.S, plan.waves, 0, (int)k));
@@ -1210,14 +1242,13 @@ static asora_status get_adj_layer_plan(asora_ctx *c, float R_cap, bool kept, Pla
     asora_status st = get_layer_plan(c, R_cap, &P);   // Mcap, record sizes
     if (st) return st;
     const size_t region = adj_layer_region_bytes(P.S);
-    const size_t wg = layer_sqrt_bytes(Rsq);   // the work-group's table of square roots
-    const long fit = c->max_lds > wg + 64 ? (long)((c->max_lds - wg - 64) / region) : 0;
-    if (fit < 1)
+    const size_t sqb = layer_sqrt_bytes(Rsq);   // the work-group's table of square roots
+    P.waves = layer_waves(c, 0, sqb, region, c->adj_waves, &P.sq_table);
+    if (P.waves < 1)
         return fail(c, ASORA_ENOSYS,
                     "asora_raytrace_backward: R_max=%.1f needs %zu bytes of LDS per wave (limit %zu)",
-                    R_cap, region + wg, c->max_lds);
-    P.waves = (int)(fit < c->adj_waves ? fit : c->adj_waves);
-    P.lds = wg + (size_t)P.waves * region;
+                    R_cap, region, c->max_lds);
+    P.lds = (P.sq_table ? sqb : 0) + (size_t)P.waves * region;
     int bpc = 0;
     HIPCHK(c, adj_layer_occupancy(kept, c->adj_split != 0, P.waves, P.lds, &bpc));
     P.grid = c->n_cu * (bpc > 0 ? bpc : 1);
@@ -1354,6 +1385,7 @@ extern "C" asora_status asora_raytrace_backward(asora_ctx *c, const float *n_H, 
         L.rec_cap = layers ? plans[3].rec_cap : 0;
         L.split = c->adj_split != 0;
         L.early_exit = early;
+        L.sq_table = layers && plans[3].sq_table;
         for (int t = tmax; t >= 0; --t) {
             if (t == 2 && layers) continue;
             L.type = t;
@@ -1727,7 +1759,7 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
         if (!ar_fixed)
             for (int ar : {1, 2})
                 if (!st) (k = b).ar = ar, st = consider(k);
-        for (int aw : {2, 4, 8, 12})
+        for (int aw : {2, 4, 8, 12, 16})
             if (!st) (k = b).aw = aw, st = consider(k);
     }
     if (R_max > 8.f)

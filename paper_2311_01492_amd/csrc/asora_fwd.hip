@@ -6,6 +6,8 @@
 // the rate of every owned cell added to an FP64 N^3 accumulator with one
 // hardware atomic per source-cell.  The persistent kernel pulls
 // (source, piece) items from a global counter, largest radius first.
+#include <type_traits>
+
 #include "asora_dev.h"
 #include "asora_internal.h"
 
@@ -386,14 +388,20 @@ __global__ __launch_bounds__(1024) void fwd_wave_heat(FwdArgs A)
 // through the same per-wave queue as the shell sweep.  With KEEP the sweep
 // also writes the pyramid's column record (the cells' layer-buffer entries and
 // the chunks' masks of cells with a rate) for a later adjoint.
-// The rate queue of the layer kernel: as RateQueue, with the in-cell optical
-// depth in FP64 (the rate coefficients of kept records are FP64 derivatives
-// taken at the same point as the adjoint's).
+// The rate queue of the layer kernel: as RateQueue, with the squared distance
+// in 16 bits (a layer buffer that fits the LDS bounds the radius: R^2 stays
+// below 2^16, which the plan checks).  The in-cell optical depth is rounded to
+// FP32 as in RateQueue (a relative change of 6e-8 in one argument of the
+// rate), except with KEEP: the rate coefficients of kept records are FP64
+// derivatives that the adjoint combines with cancellation, so they are taken
+// at the same point as the adjoint's own.
+template <bool KEEP>
 struct LayerQueue {
+    using dt_t = typename std::conditional<KEEP, double, float>::type;
     double *ta;     // entry optical depth
-    double *dt;     // in-cell optical depth
+    dt_t *dt;       // in-cell optical depth
     uint32_t *cp;   // cell index
-    int *r2;        // squared distance (cells)
+    uint16_t *r2;   // squared distance (cells)
 };
 
 // One batch of queued cells: the rate added to Gamma.  Without KEEP the
@@ -402,12 +410,12 @@ struct LayerQueue {
 // instead of two), which are stored in the record at the cells' places in
 // the order of evaluation (head + lane).
 template <bool KEEP, bool HEAT>
-__device__ __forceinline__ void layer_rate_batch(const FwdArgs &A, const TabNode *T, const LayerQueue &Qa,
+__device__ __forceinline__ void layer_rate_batch(const FwdArgs &A, const TabNode *T, const LayerQueue<KEEP> &Qa,
                                                  int head, int lane, double coef, double *acc,
                                                  double *hacc, const LayerRecord &rec)
 {
     const int pos = (head + lane) & (kQueue - 1);
-    const double ta = Qa.ta[pos], dt = Qa.dt[pos];
+    const double ta = Qa.ta[pos], dt = (double)Qa.dt[pos];
     const int r2 = Qa.r2[pos];
     if (!KEEP) {
         const float nd = neg_divdiff(T, A.tp, ta, dt);
@@ -430,7 +438,7 @@ __device__ __forceinline__ void layer_rate_batch(const FwdArgs &A, const TabNode
 
 template <bool KEEP, bool HEAT>
 __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, const double *sq, double *lay, Geo *geo,
-                                  uint32_t *iu, uint32_t *iv, const LayerQueue &Qa, int src, int p, int lane)
+                                  uint32_t *iu, uint32_t *iv, const LayerQueue<KEEP> &Qa, int src, int p, int lane)
 {
     const int N = A.N;
     const int si = A.ijk[3 * src], sj = A.ijk[3 * src + 1], sk = A.ijk[3 * src + 2];
@@ -535,9 +543,9 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, const doub
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
                 const int qpos = (tail + rank) & (kQueue - 1);
                 Qa.ta[qpos] = A.sigma0 * lc.Nin;
-                Qa.dt[qpos] = A.sigma0 * lc.dN;
+                Qa.dt[qpos] = (typename LayerQueue<KEEP>::dt_t)(A.sigma0 * lc.dN);
                 Qa.cp[qpos] = lc.cp;
-                Qa.r2[qpos] = lc.r2;
+                Qa.r2[qpos] = (uint16_t)lc.r2;
             }
             tail += __popcll(mask);
             if (tail - head >= 64) {
@@ -587,12 +595,12 @@ __device__ __forceinline__ void fwd_layer_body(const FwdArgs &A, char *smem)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int waves = blockDim.x >> 6;
     char *region = wg + (A.sq_n ? layer_sqrt_bytes(A.sq_n - 1) : 0) + (size_t)wave * A.region_bytes;
-    LayerQueue Qa;
+    LayerQueue<KEEP> Qa;
     Qa.ta = (double *)region;
-    Qa.dt = Qa.ta + kQueue;
+    Qa.dt = (typename LayerQueue<KEEP>::dt_t *)(Qa.ta + kQueue);
     Qa.cp = (uint32_t *)(Qa.dt + kQueue);
-    Qa.r2 = (int *)(Qa.cp + kQueue);
-    double *lay = (double *)(Qa.r2 + kQueue);
+    Qa.r2 = (uint16_t *)(Qa.cp + kQueue);
+    double *lay = (double *)(Qa.r2 + kQueue);   // kQueue is a multiple of 4: aligned
     Geo *geo = (Geo *)(lay + (size_t)(A.lay_S + 1) * (A.lay_S + 1));
     uint32_t *iu = (uint32_t *)(geo + A.lay_S);
     uint32_t *iv = iu + A.lay_S;
@@ -629,20 +637,22 @@ __global__ __launch_bounds__(1024) void fwd_layer_heat(FwdArgs A)
     fwd_layer_body<KEEP, false, true>(A, smem);
 }
 
-// Per-wave LDS of the layer kernel: the rate queue, the (S + 1) x (S + 1)
-// padded layer buffer, the layer's table of bilinear factors and the
-// pyramid's index terms along u and v.
-size_t layer_region_bytes(int S)
+// Per-wave LDS of the layer kernel: the rate queue (its in-cell optical depths
+// in FP64 with keep), the (S + 1) x (S + 1) padded layer buffer, the layer's
+// table of bilinear factors and the pyramid's index terms along u and v.
+size_t layer_region_bytes(int S, bool keep)
 {
-    const size_t b = (size_t)kQueue * (2 * sizeof(double) + sizeof(uint32_t) + sizeof(int)) +
+    const size_t dt = keep ? sizeof(double) : sizeof(float);
+    const size_t b = (size_t)kQueue * (sizeof(double) + dt + sizeof(uint32_t) + sizeof(uint16_t)) +
                      (size_t)(S + 1) * (S + 1) * sizeof(double) + (size_t)S * sizeof(Geo) +
                      2 * (size_t)S * sizeof(uint32_t);
     return (b + 15) & ~(size_t)15;
 }
 
-hipError_t layer_occupancy(bool tab_lds, int waves, size_t lds, int *blocks_per_cu)
+hipError_t layer_occupancy(bool keep, bool tab_lds, int waves, size_t lds, int *blocks_per_cu)
 {
-    const void *f = tab_lds ? (const void *)fwd_layer<false, true> : (const void *)fwd_layer<false, false>;
+    const void *f = keep ? (tab_lds ? (const void *)fwd_layer<true, true> : (const void *)fwd_layer<true, false>)
+                         : (tab_lds ? (const void *)fwd_layer<false, true> : (const void *)fwd_layer<false, false>);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, waves * 64, lds);
 }
 
@@ -652,9 +662,9 @@ hipError_t launch_fwd_layer(hipStream_t st, const FwdLaunch &F, int S, int waves
     FwdArgs A = make_args(F);
     A.plain_src = plain_src;
     A.lay_S = S;
-    A.region_bytes = (int)layer_region_bytes(S);
+    A.region_bytes = (int)layer_region_bytes(S, A.keep != nullptr);
     const int Rsq = (int)floor((double)F.R_cap * (double)F.R_cap);
-    const size_t sqb = layer_sqrt_bytes(Rsq);
+    const size_t sqb = F.sq_table ? layer_sqrt_bytes(Rsq) : 0;
     A.sq_n = sqb ? Rsq + 1 : 0;
     const bool tab_lds = F.tab_lds && !F.hacc;   // the heating sweep reads both tables through the caches
     const size_t lds = (tab_lds ? (size_t)F.tp.n * sizeof(TabNode) : 0) + sqb + (size_t)waves * A.region_bytes;

@@ -315,7 +315,7 @@ hipError_t launch_fwd_layer_he(hipStream_t st, const HeLaunch &H, int S, int wav
     A.lay_S = S;
     A.region_bytes = (int)he_region_bytes(S);
     const int Rsq = (int)floor((double)H.R_cap * (double)H.R_cap);
-    const size_t sqb = layer_sqrt_bytes(Rsq);
+    const size_t sqb = H.sq_table ? layer_sqrt_bytes(Rsq) : 0;
     A.sq_n = sqb ? Rsq + 1 : 0;
     A.coef_unit = 1.0 / (4.0 * M_PI * H.alpha * H.alpha);
     const size_t lds = sqb + (size_t)waves * A.region_bytes;

@@ -46,6 +46,7 @@ struct FwdLaunch {
     const double *m64;      // FP64 node slopes of the table
     bool early_exit;        // layer pieces: stop after the first opaque layer
     int tab_lds;            // layer pieces: table in LDS (1) or read through the caches (0)
+    bool sq_table;          // layer pieces: the work-group's LDS table of sqrt(r^2) (else per cell)
     const TabNode *tab_h;   // photo-heating table (same node grid), or NULL: no heating
     double *hacc, *hacc_T;  // heating accumulators (layouts of gacc, gacc_T)
     float dP0_h;            // dH/dtau at the first node
@@ -61,8 +62,8 @@ hipError_t launch_transpose_prologue(hipStream_t st, const float *nH, const floa
 hipError_t launch_transpose_finalize(hipStream_t st, const double *gacc, const double *gacc_T,
                                      float *gamma, int N, int accumulate);
 hipError_t launch_zero(hipStream_t st, double *p, long n, int n_cu);
-size_t layer_region_bytes(int S);
-hipError_t layer_occupancy(bool tab_lds, int waves, size_t lds, int *blocks_per_cu);
+size_t layer_region_bytes(int S, bool keep);
+hipError_t layer_occupancy(bool keep, bool tab_lds, int waves, size_t lds, int *blocks_per_cu);
 
 // hydrogen chemistry step (asora_chem.hip)
 struct ChemLaunch {
@@ -126,6 +127,7 @@ struct AdjLaunch {
     long rec_cap;             // cells (and listed cells) per pyramid record
     bool split;               // layer pieces: rate terms of dense chunks in the reverse pass
     bool early_exit;          // layer pieces: stop at the first opaque layer
+    bool sq_table;            // layer pieces: the work-group's LDS table of sqrt(r^2) (else per cell)
 };
 
 size_t adj_region_bytes(int ring_cap, int row_cap, int shell_cap);
@@ -135,7 +137,7 @@ hipError_t launch_adj_prologue(hipStream_t st, const float *nH, const float *xHI
                                double *nbar, long n3, double *qbar, long nsrc, int zero_q, int *ctl,
                                int nctl, int n_cu);
 hipError_t launch_adj_wave(hipStream_t st, const AdjLaunch &L);
-constexpr int kAdjLayerWaves = 12;   // largest work-group of the layer adjoint (waves)
+constexpr int kAdjLayerWaves = 16;   // largest work-group of the layer adjoint (waves)
 size_t adj_layer_region_bytes(int S);
 hipError_t adj_layer_occupancy(bool kept, bool split, int waves, size_t lds, int *blocks_per_cu);
 hipError_t launch_adj_layer(hipStream_t st, const AdjLaunch &L, int Mcap, int S);
@@ -167,6 +169,7 @@ struct HeLaunch {
     const int *order;
     int *ctl;
     int *err;
+    bool sq_table;                    // the work-group's LDS table of sqrt(r^2) (else per cell)
 };
 size_t he_region_bytes(int S);
 hipError_t he_configure(size_t max_lds);

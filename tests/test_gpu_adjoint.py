@@ -204,6 +204,32 @@ def test_kept_records_match_recompute_and_oracle(asora, bb, adj_rate):
     np.testing.assert_allclose(gq, oq, rtol=1e-5)
 
 
+@pytest.mark.parametrize("adj_rate", [1, 2])
+def test_wide_work_groups(asora, bb, adj_rate):
+    """The layer adjoint's 16-wave build (held to four waves per SIMD) in all
+    three forms: recomputed columns with gathered or split rate terms, and
+    kept records; uneven radii, so every piece kind runs."""
+    print(f"case wide adjoint adj_rate={adj_rate}", flush=True)
+    w, g, wt = _case("c2", N=40, n_src=24, R=(2.0, 38.0))
+    gbar = _loss_grad(g, wt)
+    on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
+                                      w.src.R, gbar)
+    ctx = asora.Asora(w.N, w.cell_cm, bb.P, bb.dP, bb.lg_lo, bb.lg_hi)
+    ctx.set_tuning(adj_rate=adj_rate, adj_waves=16)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    nH, xH, ijk, Q, R, gb = t(w.n_H), t(w.x_HI), t(w.src.ijk), t(w.src.Q), t(w.src.R), t(gbar)
+    for store in (False, True):
+        if store:
+            ctx.raytrace(nH, xH, ijk, Q, R, store=True)
+            assert ctx.store_info()[0]
+        gn, gx, gq = (a.cpu().numpy() for a in ctx.backward(nH, xH, ijk, Q, R, gb, store=store))
+        ctx.check()
+        assert_grad_parity(gn, on, 1e-5, what=f"dL/dn_H (store={store})")
+        assert_grad_parity(gx, ox, 1e-5, what=f"dL/dx_HI (store={store})")
+        np.testing.assert_allclose(gq, oq, rtol=1e-5)
+    ctx.close()
+
+
 def test_kept_records_fall_back_to_recompute(asora, bb):
     """Records that do not fit the budget are not kept; records kept for other
     input buffers are not used: both backwards recompute."""
