@@ -442,7 +442,7 @@ asora_status asora_set_tuning(asora_ctx *ctx, float R_whole, float R_oct, int32_
  * measurement, not by rule).  Coordinate descent over: the sweep of pyramid
  * pieces (layers, shells), the place of the table (LDS, caches), the waves
  * per work-group (4, 8, 12, 16), for passes = 2 with layer pyramids the
- * layer adjoint's adj_rate (1, 2) and adj_waves (2, 4, 8, 12, 16), R_oct (8, 10,
+ * layer adjoint's adj_rate (1, 2) jointly with adj_waves (2, 4, 8, 12, 16), R_oct (8, 10,
  * 12, 15, 20) and R_whole (3, 4, 6, 8); every candidate is one
  * warm-up call and the median of three calls timed with HIP events on
  * `stream`.  passes = 1 times the forward; passes = 2 the forward with

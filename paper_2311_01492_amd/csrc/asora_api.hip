@@ -1756,11 +1756,14 @@ extern "C" asora_status asora_autotune(asora_ctx *c, const float *n_H, const flo
     for (int wv : {4, 8, 12, 16})
         if (!st) (k = b).waves = wv, st = consider(k);
     if (passes == 2 && R_max > b.o && b.sweep == 3) {   // the layer adjoint
-        if (!ar_fixed)
-            for (int ar : {1, 2})
-                if (!st) (k = b).ar = ar, st = consider(k);
+        // the rate form and the work-group size jointly: the wide build's
+        // register limit suits the gathered form and not the split one
+        const Cand b0 = b;
         for (int aw : {2, 4, 8, 12, 16})
-            if (!st) (k = b).aw = aw, st = consider(k);
+            for (int ar : {1, 2}) {
+                if (st || (ar_fixed && ar != b0.ar)) continue;
+                (k = b0).aw = aw, k.ar = ar, st = consider(k);
+            }
     }
     if (R_max > 8.f)
         for (float o : {8.f, 10.f, 12.f, 15.f, 20.f})

@@ -552,10 +552,11 @@ __host__ __device__ __forceinline__ double exp_f64(double x)
 }
 
 // P(tau), dP/dtau and d2P/dtau2 of the interpolant in FP64 (node slopes m64
-// in FP64: gradients can be sums of large terms of both signs).
-__host__ __device__ __forceinline__ void tab_eval64(const TabNode *T, const double *m64,
-                                                    const TabParams &tp, double tau, double *P,
-                                                    double *d1, double *d2)
+// in FP64: gradients can be sums of large terms of both signs), given
+// x = ln tau (used only inside the table).
+__host__ __device__ __forceinline__ void tab_eval64_x(const TabNode *T, const double *m64,
+                                                      const TabParams &tp, double tau, double x, double *P,
+                                                      double *d1, double *d2)
 {
     if (tau < tp.tau_lo) {
         *P = exp_f64(T[0].y) + (double)tp.dP0 * (tau - tp.tau_lo);
@@ -569,7 +570,7 @@ __host__ __device__ __forceinline__ void tab_eval64(const TabNode *T, const doub
         *d2 = 0.0;
         return;
     }
-    const double t = (log_f64(tau) - tp.x_lo) * tp.inv_h;
+    const double t = (x - tp.x_lo) * tp.inv_h;
     int j = (int)floor(t);
     j = j < 0 ? 0 : (j > tp.n - 2 ? tp.n - 2 : j);
     const double f = t - (double)j;
@@ -587,6 +588,19 @@ __host__ __device__ __forceinline__ void tab_eval64(const TabNode *T, const doub
     *d2 = p * (yx * yx + yxx - yx) * it * it;
 }
 
+__host__ __device__ __forceinline__ void tab_eval64(const TabNode *T, const double *m64,
+                                                    const TabParams &tp, double tau, double *P,
+                                                    double *d1, double *d2)
+{
+    tab_eval64_x(T, m64, tp, tau, tau >= tp.tau_lo ? log_f64(tau) : 0.0, P, d1, d2);
+}
+
+// ln(1 + e) for |e| <= 1e-4 to 3e-17 absolute (the series to e^3).
+__host__ __device__ __forceinline__ double log1p_small(double e)
+{
+    return e * (1.0 + e * (-0.5 + e * (1.0 / 3.0)));
+}
+
 // D = [P(a+dt) - P(a)] / dt and its partial derivatives dD/da (dt fixed) and
 // dD/d(dt) (a fixed), FP64.  For dt > 1e-4 a the difference quotients are
 // formed directly (their FP64 cancellation costs at most ~1e-8); below that
@@ -597,8 +611,10 @@ __host__ __device__ __forceinline__ void rate_derivs64(const TabNode *T, const d
                                                        const TabParams &tp, double a, double dt,
                                                        double *D, double *dDda, double *dDddt)
 {
+    const bool in = a >= tp.tau_lo;   // then a > 0
+    const double xa = in ? log_f64(a) : 0.0;
     double Pa, Pa1, Pa2;
-    tab_eval64(T, m64, tp, a, &Pa, &Pa1, &Pa2);
+    tab_eval64_x(T, m64, tp, a, xa, &Pa, &Pa1, &Pa2);
     if (dt > 1e-4 * a && dt > 0.0) {
         double Pb, Pb1, Pb2;
         tab_eval64(T, m64, tp, a + dt, &Pb, &Pb1, &Pb2);
@@ -613,11 +629,17 @@ __host__ __device__ __forceinline__ void rate_derivs64(const TabNode *T, const d
     const double g1 = 0.21132486540518711, g2 = 0.78867513459481289;
     const double j1 = 0.35505102572168219, j2 = 0.84494897427831781;   // (6 -+ sqrt6)/10
     const double w1 = (9.0 + 2.449489742783178) / 36.0, w2 = (9.0 - 2.449489742783178) / 36.0;
-    double P_, d1_, q1, q2, r1, r2;
-    tab_eval64(T, m64, tp, a + g1 * dt, &P_, &d1_, &q1);
-    tab_eval64(T, m64, tp, a + g2 * dt, &P_, &d1_, &q2);
-    tab_eval64(T, m64, tp, a + j1 * dt, &P_, &d1_, &r1);
-    tab_eval64(T, m64, tp, a + j2 * dt, &P_, &d1_, &r2);
+    // the nodes lie within a relative 1e-4 of a: inside the table their
+    // logarithms are ln a + ln(1 + g dt / a) (a node can enter the table only
+    // from an a just below its start: it takes its own logarithm)
+    const double ea = in ? dt * rcp_f64(a) : 0.0;
+    auto d2_at = [&](double g) {
+        double P_, d1_, d2_;
+        if (in) tab_eval64_x(T, m64, tp, a + g * dt, xa + log1p_small(g * ea), &P_, &d1_, &d2_);
+        else tab_eval64(T, m64, tp, a + g * dt, &P_, &d1_, &d2_);
+        return d2_;
+    };
+    const double q1 = d2_at(g1), q2 = d2_at(g2), r1 = d2_at(j1), r2 = d2_at(j2);
     *dDda = 0.5 * (q1 + q2);
     *dDddt = w1 * r1 + w2 * r2;
     *D = Pa1 + 0.5 * dt * (*dDda);

@@ -35,6 +35,32 @@ extern "C" void hc_neg_divdiff_batch(int n, double lg_lo, double lg_hi, const do
     for (long i = 0; i < m; ++i) out[i] = neg_divdiff(T.data(), tp, a[i], dt[i]);
 }
 
+// The adjoint's FP64 divided difference and its partial derivatives
+// (rate_derivs64) at m points (a, dt): out is D, dD/da, dD/d(dt) per point.
+extern "C" void hc_rate_derivs64_batch(int n, double lg_lo, double lg_hi, const double *P, const double *dP,
+                                       long m, const double *a, const double *dt, double *out)
+{
+    TabParams tp;
+    std::vector<TabNode> T(n);
+    std::vector<double> m64(n);
+    prepare_table(n, lg_lo, lg_hi, P, dP, &tp, T.data(), m64.data());
+    for (long i = 0; i < m; ++i) rate_derivs64(T.data(), m64.data(), tp, a[i], dt[i], out + 3 * i,
+                                               out + 3 * i + 1, out + 3 * i + 2);
+}
+
+// The library's FP64 interpolant (tab_eval64: P, dP/dtau, d2P/dtau2, each
+// point's own logarithm) at m points: out is [m, 3].
+extern "C" void hc_tab_eval64_batch(int n, double lg_lo, double lg_hi, const double *P, const double *dP,
+                                    long m, const double *tau, double *out)
+{
+    TabParams tp;
+    std::vector<TabNode> T(n);
+    std::vector<double> m64(n);
+    prepare_table(n, lg_lo, lg_hi, P, dP, &tp, T.data(), m64.data());
+    for (long i = 0; i < m; ++i) tab_eval64(T.data(), m64.data(), tp, tau[i], out + 3 * i, out + 3 * i + 1,
+                                            out + 3 * i + 2);
+}
+
 // The chunk walk of the layer kernels against plain division: for every row
 // width wv in [1, wv_max] and every cell g of rectangles up to 40 rows, the
 // lanes' (u, v) after init, down() and up() equal (g / wv, g % wv).  Returns 0

@@ -39,6 +39,10 @@ def load():
         lib.hc_raytrace.argtypes = [i, d, d, i, d, d, p, p, d, i, p, p, l, p, p, p, f, f, i, p, p]
         lib.hc_neg_divdiff_batch.restype = None
         lib.hc_neg_divdiff_batch.argtypes = [i, d, d, p, p, l, p, p, p]
+        lib.hc_rate_derivs64_batch.restype = None
+        lib.hc_rate_derivs64_batch.argtypes = [i, d, d, p, p, l, p, p, p]
+        lib.hc_tab_eval64_batch.restype = None
+        lib.hc_tab_eval64_batch.argtypes = [i, d, d, p, p, l, p, p]
         lib.hc_raytrace_grad.restype = i
         lib.hc_raytrace_grad.argtypes = [i, d, d, i, d, d, p, p, d, i, p, p, l, p, p, p, f, f, i, p, p, p]
         lib.hc_raytrace_layer.restype = i
@@ -94,6 +98,28 @@ def neg_divdiff(table, a, dt):
     out = np.empty(a.shape, np.float32)
     P, dP = np.ascontiguousarray(table.P, np.float64), np.ascontiguousarray(table.dP, np.float64)
     lib.hc_neg_divdiff_batch(len(P), table.lg_lo, table.lg_hi, _p(P), _p(dP), a.size, _p(a), _p(dt), _p(out))
+    return out
+
+
+def rate_derivs64(table, a, dt):
+    """(D, dD/da, dD/d(dt)) of the adjoint's FP64 rate derivatives, [m, 3]."""
+    lib = load()
+    a = np.ascontiguousarray(a, np.float64)
+    dt = np.ascontiguousarray(dt, np.float64)
+    out = np.empty((a.size, 3), np.float64)
+    P, dP = np.ascontiguousarray(table.P, np.float64), np.ascontiguousarray(table.dP, np.float64)
+    lib.hc_rate_derivs64_batch(len(P), table.lg_lo, table.lg_hi, _p(P), _p(dP), a.size, _p(a), _p(dt),
+                               _p(out))
+    return out
+
+
+def tab_eval64(table, tau):
+    """The library's FP64 interpolant (P, dP/dtau, d2P/dtau2) at tau, [m, 3]."""
+    lib = load()
+    tau = np.ascontiguousarray(tau, np.float64)
+    out = np.empty((tau.size, 3), np.float64)
+    P, dP = np.ascontiguousarray(table.P, np.float64), np.ascontiguousarray(table.dP, np.float64)
+    lib.hc_tab_eval64_batch(len(P), table.lg_lo, table.lg_hi, _p(P), _p(dP), tau.size, _p(tau), _p(out))
     return out
 
 

@@ -218,6 +218,48 @@ def test_layer_adjoint_extent_clip_and_wrap(bb):
             np.testing.assert_allclose(hq, oq, rtol=1e-6)
 
 
+def test_rate_derivatives_of_thin_cells(bb):
+    """The adjoint's rate derivatives where the in-cell depth is below 1e-4 of
+    the entry one: Gauss rules over [a, a + dt] whose nodes share the
+    logarithm of a (ln a + ln(1 + g dt / a)).  Against the same rules on the
+    library's interpolant with every node's own logarithm, and D against its
+    definition P'(a) + dt/2 dD/da; inside the table, across its first node
+    (a just below it) and at zero width.  Then against the oracle's own
+    interpolant inside the table (its second derivative, to the agreement of
+    the two interpolants)."""
+    rng = np.random.default_rng(5)
+    a = 10 ** rng.uniform(-19.5, 3.9, 3000)
+    dt = a * 10 ** rng.uniform(-9, -4, 3000)
+    a = np.concatenate([a, [1e-20 * (1 - 3e-5), 1e-20 * (1 - 1e-9), 7.0]])
+    # (the first node: some quadrature nodes of the last two points lie above it)
+    dt = np.concatenate([dt, [0.99e-24, 5e-29, 0.0]])
+    assert np.all(dt <= 1e-4 * a)
+    got = hostsweep.rate_derivs64(bb, a, dt)
+    g1, g2 = 0.5 - 0.5 / math.sqrt(3), 0.5 + 0.5 / math.sqrt(3)
+    j1, j2 = (6 - math.sqrt(6)) / 10, (6 + math.sqrt(6)) / 10
+    w1, w2 = (9 + math.sqrt(6)) / 36, (9 - math.sqrt(6)) / 36
+    for lib, d2 in ((True, lambda x: hostsweep.tab_eval64(bb, x)[:, 2]),
+                    (False, lambda x: oracle.table_eval(bb, x)[2])):
+        Da = 0.5 * (d2(a + g1 * dt) + d2(a + g2 * dt))
+        Ddt = w1 * d2(a + j1 * dt) + w2 * d2(a + j2 * dt)
+        if lib:
+            # the per-node logarithms (1e-14 absolute) move a node's second
+            # derivative by up to ~1e-10 where its terms nearly cancel
+            d1a = hostsweep.tab_eval64(bb, a)[:, 1]
+            D = d1a + 0.5 * dt * Da
+            assert np.all(np.abs(got[:, 1] - Da) <= 1e-9 * np.abs(Da))
+            assert np.all(np.abs(got[:, 2] - Ddt) <= 1e-9 * np.abs(Ddt))
+            assert np.all(np.abs(got[:, 0] - D) <= 1e-12 * np.abs(D))
+        else:
+            # the two interpolants agree to ~1e-8 in ln P; a second derivative
+            # is held to that on the scale |P'| / tau of its own size (it
+            # crosses zero)
+            inside = a >= 1.001e-20
+            sc = 1e-6 * (np.abs(Da) + np.abs(hostsweep.tab_eval64(bb, a)[:, 1]) / a)
+            assert np.all(np.abs(got[inside, 1] - Da[inside]) <= sc[inside])
+            assert np.all(np.abs(got[inside, 2] - Ddt[inside]) <= sc[inside])
+
+
 def test_kernel_logarithms():
     """The kernels' FP64 logarithms: log_fast (the rate's table position,
     2e-11 absolute) and log_f64 (the FP64 derivatives of the adjoint, 1e-14)."""
