@@ -220,23 +220,22 @@ __global__ __launch_bounds__(512) void adj_wave(AdjArgs A)
 }
 
 // ---- layer pieces --------------------------------------------------------
-// One wave per pyramid, in three passes.
+// One wave per pyramid, in two passes.
 //  (F) Unless the forward kept the pyramid's column record: the columns layer
 //      by layer, in place in the LDS buffer as in the forward kernel, every
 //      cell's layer-buffer entry written to the record in the wave's scratch
-//      together with each chunk's mask of cells with a rate.
-//  (G) The cells with a rate (SPLIT: only those in sparse chunks, fewer than
-//      kDenseChunk of them), found from the chunk masks and compacted into an
-//      LDS queue, 64 at a time with every lane busy: their entry columns from the record,
-//      the FP64 rate derivatives, the rate's in-cell term of dL/dn_HI, its
-//      share of dL/dQ, and its entry-column term g_in, kept per cell in the
-//      wave's scratch.  With SPLIT, dense chunks leave theirs to (R), which
-//      has the interpolation at hand; without, the kernel holds fewer
-//      registers (more waves per SIMD), which pays when few cells have a rate.
+//      together with each chunk's mask of cells with a rate.  The cells with
+//      a rate (SPLIT: only those in sparse chunks, fewer than kDenseChunk of
+//      them) go to an LDS queue with their entry optical depth, and 64 at a
+//      time, with every lane busy, get the FP64 rate derivatives, the rate's
+//      in-cell term of dL/dn_HI, its share of dL/dQ, and its entry-column
+//      term g_in, kept per cell in the wave's scratch.  With SPLIT, dense
+//      chunks leave theirs to (R), which has the interpolation at hand;
+//      without, the kernel holds fewer registers (more waves per SIMD).
 //  (R) Layers from the outermost inward, each layer's rectangle in chunks
 //      from the first to the last: every cell takes and clears its slot in
 //      the LDS adjoint buffer (the adjoint of its exit column, pushed by its
-//      consumers), adds its g_in if it has a rate (from (G), or evaluated
+//      consumers), adds its g_in if it has a rate (from (F), or evaluated
 //      here in a dense chunk), adds alpha ds times the sum (and, in a dense
 //      chunk, the rate's in-cell term) to dL/dn_HI with one atomic and pushes
 //      it through the interpolation weights, read
@@ -255,7 +254,7 @@ __device__ __forceinline__ void wave_sync_global()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-constexpr int kAdjQueue = 128;   // (G) queue entries per wave
+constexpr int kAdjQueue = 128;   // queue entries per wave ((F) rate terms, (R) batches)
 
 // The rate masks of chunks c0 .. c0 + 63 of a layer (first chunk at choff),
 // one per lane, held in registers.
@@ -330,17 +329,57 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, const do
     // ---- (F), every layer; with the early exit only up to the first layer
     // whose cells all leave opaque (layer_opaque): later layers have no rate
     // and no adjoint.  Kept records hold the layers their forward swept.
-    int Mt = Mx;   // the last layer (G) and (R) visit
+    // Unless the forward kept the rate's coefficients, (F) also evaluates the
+    // rate's terms (g_in by record cell, dL/dn_HI and dL/dQ shares) of the
+    // cells with a rate that (R) does not take in place (all of them in the
+    // gathered form, those of sparse chunks in the split one): such cells go
+    // to the wave's queue with their entry optical depth and place (m, g),
+    // and every full 64 are evaluated by all lanes together.
+    double nb_src = 0.0, qb = 0.0;
+    long off = 0, choff = 0;   // the record's cells and chunks of layers 1 .. Mt
+    int Mt = Mx;   // the last layer (R) visits
     if (KEPT) {
         const int ml = (int)((const uint64_t *)rec.rk)[3 * A.rec_cap + 1];
         Mt = ml < Mx ? ml : Mx;
+        for (int m = 1; m <= Mt; ++m) {
+            const int t = layer_rect(L.ext_u, L.ext_v, Rsq, m).total;
+            off += t;
+            choff += (t + 63) / 64;
+        }
     } else {
         const bool watch = A.early_exit != 0;
         const int P = S + 1;   // row stride of the padded layer buffer
         for (int k = lane; k < P * P; k += 64) buf[k] = 0.0;   // finite everywhere it is read
         wave_sync();
         const double opaque = layer_opaque(A.tp.tau_hi);
-        long off = 0, choff = 0;
+        // the queue: record cell (qk), (m << 16) | g (qm), entry optical depth (qT)
+        int head = 0, tail = 0;
+        auto batch = [&](int count) {
+            if (lane < count) {
+                const int q = (head + lane) & (kAdjQueue - 1);
+                const int k = qk[q], mg = qm[q];
+                const double ta = qT[q];
+                const int m = mg >> 16, g = mg & 0xffff;
+                int u, v;
+                rect_cell(layer_rect(L.ext_u, L.ext_v, Rsq, m), g, u, v);
+                // the cell's index, distance and in-cell column as (F) formed them
+                const uint32_t cp = layer_idx_d(L, N, m) + iu[u] + iv[v];
+                const int r2 = mul24(m, m) + mul24(u, u) + mul24(v, v);
+                const double rt = A.sq_n ? sq[r2] : sqrt_fast((double)r2);
+                const double ds = rt * rcp_f64((double)m);
+                const double gb = gbar[cp];
+                double gi = 0.0;
+                if (gb != 0.0) {
+                    const double dN = X.nHI[cp] * X.alpha * ds;
+                    double ne, gG;
+                    layer_rate_adjoint_t(T, A.m64, A.tp, A.sigma0, coef, ta, A.sigma0 * dN, X.alpha * ds, r2, gb,
+                                         &gi, &ne, &gG);
+                    if (ne != 0.0) unsafeAtomicAdd(&nbar[cp], ne);
+                    qb += gG;
+                }
+                gin[k] = gi;
+            }
+        };
         for (int m = 1; m <= Mx; ++m) {
             const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
             const double inv_m = rcp_f64((double)m);
@@ -379,6 +418,23 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, const do
                 const uint64_t mask = __ballot(lit);
                 if (lane == 0) rec.lit[choff + c] = mask;
                 if (watch) opq = opq && __ballot(act && !(A.sigma0 * lc.Nout >= opaque)) == 0;
+                if (mask && __popcll(mask) < dense_at) {   // (R) does not take these in place
+                    if (lit) {
+                        const int q = (tail + (int)__builtin_amdgcn_mbcnt_hi(
+                                                  (uint32_t)(mask >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u))) &
+                                      (kAdjQueue - 1);
+                        qk[q] = (int)(off + g);
+                        qm[q] = (m << 16) | g;
+                        qT[q] = A.sigma0 * lc.Nin;
+                    }
+                    tail += __popcll(mask);
+                    if (tail - head >= 64) {
+                        wave_sync();
+                        batch(64);
+                        head += 64;
+                    }
+                }
                 wave_sync();
             }
             off += r.total;
@@ -388,81 +444,12 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, const do
                 break;
             }
         }
-        wave_sync_global();
-    }
-
-    // ---- (G), unless the forward kept the rate's coefficients
-    double nb_src = 0.0, qb = 0.0;
-    long off = 0, choff = 0;
-    if (KEPT) {
-        for (int m = 1; m <= Mt; ++m) {
-            const int t = layer_rect(L.ext_u, L.ext_v, Rsq, m).total;
-            off += t;
-            choff += (t + 63) / 64;
-        }
-    } else {
-        int head = 0, tail = 0;
-        auto batch = [&](int count) {
-            if (lane < count) {
-                const int q = (head + lane) & (kAdjQueue - 1);
-                const int k = qk[q], mg = qm[q];
-                const int m = mg >> 16, g = mg & 0xffff;
-                const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
-                RectWalk w;
-                w.init(r, g);
-                const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m >= 2 ? m - 1 : 1);
-                const double *Hprev = rec.h + (m >= 2 ? k - g - rp.total : 0);
-                const int u = w.u, v = w.v;
-                const double inv_m = rcp_f64((double)m);
-                const int r2 = mul24(m, m) + mul24(u, u) + mul24(v, v);
-                const double rt = A.sq_n ? sq[r2] : sqrt_fast((double)r2);
-                LayerInterp I;
-                layer_interp_core(X, m, u, v, layer_idx_d(L, N, m) + iu[u] + iv[v], r2, rt * inv_m,
-                                  layer_geo(m, inv_m, u), layer_geo(m, inv_m, v), Hprev, rp, I);
-                const double gb = gbar[I.cp];
-                double gi = 0.0;
-                if (gb != 0.0) {
-                    double ne, gG;
-                    layer_rate_adjoint(T, A.m64, A.tp, X, coef, I, X.nHI[I.cp], gb, &gi, &ne, &gG);
-                    if (ne != 0.0) unsafeAtomicAdd(&nbar[I.cp], ne);
-                    qb += gG;
-                }
-                gin[k] = gi;
-            }
-        };
-        for (int m = 1; m <= Mt; ++m) {
-            const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
-            const int nch = (r.total + 63) / 64;
-            uint64_t masks = 0;
-            for (int c = 0; c < nch; ++c) {
-                if ((c & 63) == 0) masks = load_masks(rec, choff, c, nch, lane);
-                const uint64_t litmask = mask_of_chunk(masks, c);
-                if (litmask && __popcll(litmask) < dense_at) {
-                    if ((litmask >> lane) & 1) {
-                        const int q = (tail + (int)__builtin_amdgcn_mbcnt_hi(
-                                                  (uint32_t)(litmask >> 32),
-                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)litmask, 0u))) &
-                                      (kAdjQueue - 1);
-                        qk[q] = (int)(off + c * 64 + lane);
-                        qm[q] = (m << 16) | (c * 64 + lane);
-                    }
-                    tail += __popcll(litmask);
-                    if (tail - head >= 64) {
-                        wave_sync();
-                        batch(64);
-                        head += 64;
-                        wave_sync();
-                    }
-                }
-            }
-            off += r.total;
-            choff += nch;
-        }
         if (tail > head) {
             wave_sync();
             batch(tail - head);
             wave_sync();
         }
+        wave_sync_global();
     }
     for (int k = lane; k < S * S; k += 64) buf[k] = 0.0;   // the adjoint slots
     wave_sync_global();
@@ -545,7 +532,7 @@ __device__ void adjoint_layer_piece(const AdjArgs &A, const TabNode *T, const do
                 wave_sync();
                 if (QUEUE) {
                     // the cells with work go to the queue with their entry-column
-                    // adjoint (gathered form: with the rate's g_in from (G)) and,
+                    // adjoint (gathered form: with the rate's g_in from (F)) and,
                     // with kept records, the place of their rate's coefficients;
                     // full batches run with every lane busy
                     if (!KEPT && lit) Tin += gin[off + g];

@@ -1274,21 +1274,35 @@ __host__ __device__ __forceinline__ void layer_interp(const LayerPiece &L, const
 // derivatives of the divided difference.  Returns g_in (added to the cell's
 // exit-column adjoint before the interpolation is reversed), the part of
 // dL/dn_HI of the cell that the reverse does not produce,
-// (g_dN - g_in) alpha ds, and gbar Gamma.
+// (g_dN - g_in) alpha ds, and gbar Gamma.  Given the cell's entry and
+// in-cell optical depths ta = sigma0 N_in and dt = sigma0 dN, alpha ds (ads)
+// and r2.
+__host__ __device__ __forceinline__ void layer_rate_adjoint_t(const TabNode *T, const double *m64,
+                                                              const TabParams &tp, double sigma0, double coef,
+                                                              double ta, double dt, double ads, int r2,
+                                                              double gbar, double *g_in, double *nbar_extra,
+                                                              double *gG)
+{
+    double D, Da, Ddt;
+    rate_derivs64(T, m64, tp, ta, dt, &D, &Da, &Ddt);
+    const double k = -coef * rcp_f64((double)r2);
+    const double gi = gbar * k * Da * sigma0;
+    const double gd = gbar * k * Ddt * sigma0;
+    *g_in = gi;
+    *nbar_extra = (gd - gi) * ads;
+    *gG = gbar * k * D;
+}
+
 __host__ __device__ __forceinline__ void layer_rate_adjoint(const TabNode *T, const double *m64,
                                                             const TabParams &tp, const LayerX &X,
                                                             double coef, const LayerInterp &I, double nhi,
                                                             double gbar, double *g_in, double *nbar_extra,
                                                             double *gG)
 {
-    double D, Da, Ddt;
-    rate_derivs64(T, m64, tp, X.sigma0 * I.Nin, X.sigma0 * nhi * X.alpha * I.ds, &D, &Da, &Ddt);
-    const double k = -coef * rcp_f64((double)I.r2);
-    const double gi = gbar * k * Da * X.sigma0;
-    const double gd = gbar * k * Ddt * X.sigma0;
-    *g_in = gi;
-    *nbar_extra = (gd - gi) * X.alpha * I.ds;
-    *gG = gbar * k * D;
+    // the same from the cell's interpolation I and n_HI, dt formed as the
+    // column sweep forms it: sigma0 (n_HI alpha ds)
+    layer_rate_adjoint_t(T, m64, tp, X.sigma0, coef, X.sigma0 * I.Nin, X.sigma0 * (nhi * X.alpha * I.ds),
+                         X.alpha * I.ds, I.r2, gbar, g_in, nbar_extra, gG);
 }
 
 // The rate's coefficients of a cell with a rate for the adjoint, from its

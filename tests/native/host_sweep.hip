@@ -210,7 +210,7 @@ extern "C" int hc_raytrace(int N, double alpha, double sigma0, int n, double lg_
 static int layer_forward_piece(const LayerPiece &L, const LayerX &X, int Rsq, const TabNode *T,
                                const double *m64, const TabParams &tp, double coef, int S, double *lay,
                                int *lay_id, double *acc, double *coldens, int N, LayerRecord *rec, long cap,
-                               int *m_last = nullptr, bool early = false)
+                               int *m_last = nullptr, bool early = false, double *ta_out = nullptr)
 {
     long nlit = 0;
     bool rec_on = rec != nullptr;
@@ -258,6 +258,7 @@ static int layer_forward_piece(const LayerPiece &L, const LayerX &X, int Rsq, co
                 const double ta = X.sigma0 * lc[lane].Nin;
                 if (ta >= tp.tau_hi) continue;
                 mask |= 1ull << lane;
+                if (ta_out && rec_on) ta_out[off + c * 64 + lane] = ta;
                 const double dt = X.sigma0 * lc[lane].dN;
                 if (acc) {
                     const float nd = neg_divdiff(T, tp, ta, dt);
@@ -377,17 +378,18 @@ extern "C" int hc_raytrace_layer(int N, double alpha, double sigma0, int n, doub
 
 // Reverse mode on the CPU through the layer pieces, in the adjoint kernel's
 // order, per pyramid: (F) the forward pass fills the column record (the
-// cells' layer-buffer entries, each chunk's mask of cells with a rate); (G)
-// the rate terms of the cells with a rate; (R) layers from the outermost
+// cells' layer-buffer entries, each chunk's mask of cells with a rate, and
+// the rate terms of the cells with a rate from their entry optical depths);
+// (R) layers from the outermost
 // inward, each layer's rectangle in chunks from the first to the last, each
 // chunk reading its slots and clearing them, adding the rate's entry-column
 // terms of its cells with a rate, and pushing to its layer m - 1 neighbours,
 // whose entries it reads from the record.  dL/dn_HI of pyramids
 // with dominant axis k goes through a [k][i][j] buffer as on the GPU.
 // mode 1: chunks with at least kDenseChunk cells with a rate evaluate them in
-// (R), as the kernel's split form; 0: all are gathered in (G); 2: the forward
+// (R), as the kernel's split form; 0: all are taken in (F); 2: the forward
 // pass keeps the rate coefficients in the record, as a forward with kept
-// records does, and (R) reads them (no (G)).  mode | 4: the early exit (every
+// records does, and (R) reads them (no rate terms in (F)).  mode | 4: the early exit (every
 // pass stops at the pyramid's first opaque layer); otherwise all layers.
 // Returns -6 if a neighbour of non-zero weight is not an active cell of layer
 // m - 1, -7 if a chunk mask marks an inactive lane, -9 if (mode 2) the count
@@ -415,7 +417,7 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
             for (long k = 0; k < N; ++k) gbT[(k * N + i) * N + j] = gbar[(i * N + j) * N + k];
     const int S = H.S;
     const size_t SS = (size_t)S * S, PP = (size_t)(S + 1) * (S + 1);
-    std::vector<double> cols(PP), abar(SS), gin(H.cap);
+    std::vector<double> cols(PP), abar(SS), gin(H.cap), ta(H.cap);
     std::vector<int> cols_id(PP);
     std::vector<char> recmem(layer_record_bytes(H.cap, H.Mcap, kept));
     LayerRecord rec = layer_record_at(recmem.data(), H.cap, kept ? layer_record_bytes(H.cap, H.Mcap, false) : 0);
@@ -438,9 +440,10 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
             std::fill(cols_id.begin(), cols_id.end(), -1);
             // unwritten parts of the record read as NaN entries and all-set masks
             std::memset(recmem.data(), 0xff, recmem.size());
-            int Mt = Mx;   // the last layer (G) and (R) visit
+            int Mt = Mx;   // the last layer (R) visits
             int st = layer_forward_piece(L, X, Rsq, H.T.data(), H.m64.data(), H.tp, coef, S, cols.data(),
-                                         cols_id.data(), nullptr, nullptr, N, &rec, H.cap, &Mt, early);
+                                         cols_id.data(), nullptr, nullptr, N, &rec, H.cap, &Mt, early,
+                                         kept ? nullptr : ta.data());
             if (st) return st;
             if (stats) {
                 stats[0] += Mt < Mx;
@@ -450,31 +453,33 @@ extern "C" int hc_raytrace_layer_grad(int N, double alpha, double sigma0, int n,
                     stats[2] += t;
                 }
             }
-            // (G)
+            // the rate terms (F) evaluates from its queue: cells with a rate that
+            // (R) does not take in place, from their entry optical depth and
+            // place (m, g), the rest recomputed as (F) formed it
             long off = 0, choff = 0;
             for (int m = 1; m <= Mt; ++m) {
                 const LayerRect r = layer_rect(L.ext_u, L.ext_v, Rsq, m);
                 const int nch = (r.total + 63) / 64;
-                const LayerRect rp = layer_rect(L.ext_u, L.ext_v, Rsq, m >= 2 ? m - 1 : 1);
                 for (int c = 0; c < nch; ++c) {
                     const uint64_t litmask = rec.lit[choff + c];
                     if (kept || __builtin_popcountll(litmask) >= dense_at) continue;   // left to (R)
                     for (int lane = 0; lane < 64; ++lane) {
                         if (!((litmask >> lane) & 1)) continue;
                         const int g = c * 64 + lane;
-                        RectWalk w;
-                        w.init(r, g);
-                        if (g >= r.total || w.u * w.u + w.v * w.v > r.rem) return -7;
-                        const double *Hprev = rec.h + (m >= 2 ? off - rp.total : 0);
-                        LayerInterp I;
-                        layer_interp(L, X, m, w.u, w.v, Hprev, rp, I);
+                        int u, v;
+                        rect_cell(r, g, u, v);
+                        if (g >= r.total || u * u + v * v > r.rem) return -7;
+                        const uint32_t cp = layer_cp(L, N, m, u, v);
+                        const int r2 = m * m + u * u + v * v;
+                        const double ds = sqrt_fast((double)r2) * rcp_f64((double)m);
                         double gi = 0.0;
-                        const double g_ = gb[I.cp];
+                        const double g_ = gb[cp];
                         if (g_ != 0.0) {
+                            const double dN = X.nHI[cp] * X.alpha * ds;
                             double ne, gG;
-                            layer_rate_adjoint(H.T.data(), H.m64.data(), H.tp, X, coef, I, X.nHI[I.cp], g_, &gi,
-                                               &ne, &gG);
-                            nb[I.cp] += ne;
+                            layer_rate_adjoint_t(H.T.data(), H.m64.data(), H.tp, sigma0, coef, ta[off + g],
+                                                 sigma0 * dN, X.alpha * ds, r2, g_, &gi, &ne, &gG);
+                            nb[cp] += ne;
                             qb += gG;
                         }
                         gin[off + g] = gi;
