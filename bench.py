@@ -624,10 +624,10 @@ def main():
     big = R_max > tun["R_oct"]
     layer = big and tun["pyramid_sweep"] == 3
     tl = "true" if tun["table_place"] == 1 else "false"
-    sp = "true" if tun["adj_rate"] == 2 else "false"
+    sp = "true" if tun["adj_rate"] == 2 and not kept else "false"
+    aw = 16 if tun["adj_waves"] > 12 else 12   # the layer adjoint's build (wide above 12 waves)
     kname = {"fwd": f"fwd_layer<false, {tl}>" if layer else "fwd_wave<2>",
-             "adj": ("adj_layer<true, false>" if kept else f"adj_layer<false, {sp}>") if layer
-             else "adj_wave<2>"}
+             "adj": f"adj_layer<{'true' if kept else 'false'}, {sp}, {aw}>" if layer else "adj_wave<2>"}
     if not big:
         kname = {"fwd": "fwd_wave<1>", "adj": "adj_wave<1>"}
     # the step's forward keeps the records when they fit (layer pieces only)
