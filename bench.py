@@ -408,6 +408,7 @@ def main():
     ap.add_argument("--no-early-exit", action="store_true",
                     help="skip the early-exit timings (their sweeps share kernel names with the full ones)")
     ap.add_argument("--no-heating", action="store_true", help="skip the photo-heating forward")
+    ap.add_argument("--no-helium", action="store_true", help="skip the two-absorber (HI, HeI) forward")
     ap.add_argument("--tuning", metavar="K=V,...",
                     help="set these scheduling parameters instead of autotuning (keys as in the "
                          "JSON line's tuning object, e.g. R_oct=10,adj_rate=gathered)")
@@ -605,6 +606,25 @@ def main():
                                                     heating_out=heat), side)
         del heat
 
+    # ---- the two-absorber sweep (asora_raytrace_helium): HI and HeI columns
+    # per cell, a black body in four bands with a table each, on the same
+    # balls (n_He = 0.0789 n_H, x_HeI = x_HI)
+    he_ms = None
+    if not args.no_helium:
+        say("helium forward")
+        from workloads import HE_ABUNDANCE, HE_BAND_EDGES_EV, HE_BAND_LG_HI, helium_cross_sections
+        sH, sHe = helium_cross_sections()
+        bands = []
+        for b in range(len(sH)):
+            Pb, dPb = asora.table_blackbody_band(HE_BAND_EDGES_EV[b], HE_BAND_EDGES_EV[b + 1], 5e4, 2.8, 2000,
+                                                 -20.0, HE_BAND_LG_HI[b])
+            bands.append((Pb, dPb, -20.0, HE_BAND_LG_HI[b], sH[b], sHe[b]))
+        ctx.set_helium(bands)
+        nHe = (nH * HE_ABUNDANCE).contiguous()
+        gH, gHe = torch.empty_like(gamma), torch.empty_like(gamma)
+        he_ms = wall(lambda: ctx.raytrace_helium(nH, xH, nHe, xH, ijk, Q, R, R_max=R_max, out=(gH, gHe)), side)
+        del gH, gHe, nHe
+
     def counters(path):
         if not os.path.exists(path):
             return {}
@@ -709,6 +729,12 @@ def main():
                     "lookups per cell); ns per source-voxel of the same balls",
             "fwd_ms_per_call": heat_ms, "ns_per_source_voxel": heat_ms * 1e6 / work,
             "over_fwd_alone": heat_ms / fwd_ms}
+    if he_ms is not None:
+        out["helium"] = {
+            "note": "asora_raytrace_helium: Gamma_HI and Gamma_HeI from one sweep carrying the HI and HeI "
+                    "columns, four spectral bands (two tables per band and cell); ns per source-voxel of the "
+                    "same balls",
+            "fwd_ms_per_call": he_ms, "ns_per_source_voxel": he_ms * 1e6 / work, "over_fwd_alone": he_ms / fwd_ms}
     # ---- the chemistry step on the same grid (asora_chemistry): elementwise,
     # HBM-bound; 44 algorithmic bytes per cell (Gamma, n_H FP32, x_HI and the
     # previous <x_HI> FP64 in; <x_HI>, x_HI(dt) FP64 and <x_HI> FP32 out)

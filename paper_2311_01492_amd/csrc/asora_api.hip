@@ -973,7 +973,7 @@ static asora_status get_he_plan(asora_ctx *c, float R_cap, Plan *out)
     const size_t sqb = layer_sqrt_bytes(Rsq);
     const size_t region = he_region_bytes(P.S);
     P.waves = layer_waves(c, 0, sqb, region, c->max_waves, &P.sq_table);
-    if (P.waves < 1)
+    if (P.waves < 1 || Rsq > 65535)   // the rate queue holds r^2 in 16 bits
         return fail(c, ASORA_ENOSYS, "asora_raytrace_helium: R_max=%.1f needs %zu bytes of LDS per wave (limit %zu)",
                     R_cap, region, c->max_lds);
     P.lds = (P.sq_table ? sqb : 0) + (size_t)P.waves * region;

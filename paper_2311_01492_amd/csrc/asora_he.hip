@@ -49,20 +49,28 @@ struct HeArgs {
     double coef_unit;   // 1 / (4 pi alpha^2)
 };
 
-// Per-wave queue of cells with a rate: both entry and in-cell columns.
+// Per-wave queue of cells with a rate: both entry columns, the cell index
+// and (m << 16) | r^2 (r^2 < 2^16: the plan checks it).  The in-cell columns
+// are recomputed by the batch exactly as the sweep formed them, which keeps
+// the queue, and so the LDS per wave, small.
 constexpr int kHeQueue = 128;
 struct HeQueue {
-    double *NinH, *NinHe, *dNH, *dNHe;
+    double *NinH, *NinHe;
     uint32_t *cp;
-    int *r2;
+    uint32_t *mr;
 };
 
 // Rates of one queued cell (one lane): every band's divided difference,
-// shared between the species by their cross-sections.
-__device__ __forceinline__ void he_rate(const HeArgs &A, const HeQueue &Qa, int pos, double coef, double *gH,
-                                        double *gHe)
+// shared between the species by their cross-sections.  nH, nHe: the fields
+// in the piece's layout.
+__device__ __forceinline__ void he_rate(const HeArgs &A, const HeQueue &Qa, int pos, double coef, const double *sq,
+                                        const double *nH, const double *nHe, double *gH, double *gHe)
 {
-    const double NH = Qa.NinH[pos], NHe = Qa.NinHe[pos], dH = Qa.dNH[pos], dHe = Qa.dNHe[pos];
+    const double NH = Qa.NinH[pos], NHe = Qa.NinHe[pos];
+    const uint32_t cp = Qa.cp[pos], mr = Qa.mr[pos];
+    const int r2 = (int)(mr & 0xffffu), m = (int)(mr >> 16);
+    const double ds = (A.sq_n ? sq[r2] : sqrt_fast((double)r2)) * rcp_f64((double)m);
+    const double dH = nH[cp] * A.alpha * ds, dHe = nHe[cp] * A.alpha * ds;
     double sumH = 0.0, sumHe = 0.0;
     for (int b = 0; b < A.nb; ++b) {
         const double T = A.sH[b] * NH + A.sHe[b] * NHe;
@@ -71,8 +79,7 @@ __device__ __forceinline__ void he_rate(const HeArgs &A, const HeQueue &Qa, int 
         sumH += A.sH[b] * nd;
         sumHe += A.sHe[b] * nd;
     }
-    const double k = coef * (double)rcp_approx((float)Qa.r2[pos]);
-    const uint32_t cp = Qa.cp[pos];
+    const double k = coef * (double)rcp_approx((float)r2);
     if (sumH > 0.0) unsafeAtomicAdd(&gH[cp], k * sumH);
     if (sumHe > 0.0) unsafeAtomicAdd(&gHe[cp], k * sumHe);
 }
@@ -195,15 +202,13 @@ __device__ void sweep_layer_piece_he(const HeArgs &A, const double *sq, double *
                 const int q = (tail + rank) & (kHeQueue - 1);
                 Qa.NinH[q] = lc.Nin;
                 Qa.NinHe[q] = NinHe;
-                Qa.dNH[q] = lc.dN;
-                Qa.dNHe[q] = dNHe;
                 Qa.cp[q] = lc.cp;
-                Qa.r2[q] = lc.r2;
+                Qa.mr[q] = ((uint32_t)m << 16) | (uint32_t)lc.r2;
             }
             tail += __popcll(mask);
             if (tail - head >= 64) {
                 wave_sync();
-                he_rate(A, Qa, (head + lane) & (kHeQueue - 1), coef, gH, gHe);
+                he_rate(A, Qa, (head + lane) & (kHeQueue - 1), coef, sq, X.nHI, nHe, gH, gHe);
                 head += 64;
             }
             wave_sync();
@@ -211,7 +216,7 @@ __device__ void sweep_layer_piece_he(const HeArgs &A, const double *sq, double *
     }
     if (tail > head) {
         wave_sync();
-        if (lane < tail - head) he_rate(A, Qa, (head + lane) & (kHeQueue - 1), coef, gH, gHe);
+        if (lane < tail - head) he_rate(A, Qa, (head + lane) & (kHeQueue - 1), coef, sq, X.nHI, nHe, gH, gHe);
         wave_sync();
     }
 }
@@ -230,12 +235,10 @@ __global__ __launch_bounds__(1024) void fwd_layer_he(HeArgs A)
     HeQueue Qa;
     Qa.NinH = (double *)region;
     Qa.NinHe = Qa.NinH + kHeQueue;
-    Qa.dNH = Qa.NinHe + kHeQueue;
-    Qa.dNHe = Qa.dNH + kHeQueue;
-    Qa.cp = (uint32_t *)(Qa.dNHe + kHeQueue);
-    Qa.r2 = (int *)(Qa.cp + kHeQueue);
+    Qa.cp = (uint32_t *)(Qa.NinHe + kHeQueue);
+    Qa.mr = Qa.cp + kHeQueue;
     const size_t PP = (size_t)(A.lay_S + 1) * (A.lay_S + 1);
-    double *lay = (double *)(Qa.r2 + kHeQueue);
+    double *lay = (double *)(Qa.mr + kHeQueue);   // kHeQueue is even: aligned
     double *layHe = lay + PP;
     Geo *geo = (Geo *)(layHe + PP);
     uint32_t *iu = (uint32_t *)(geo + A.lay_S);
@@ -259,7 +262,7 @@ __global__ __launch_bounds__(1024) void fwd_layer_he(HeArgs A)
 
 size_t he_region_bytes(int S)
 {
-    const size_t b = (size_t)kHeQueue * (4 * sizeof(double) + sizeof(uint32_t) + sizeof(int)) +
+    const size_t b = (size_t)kHeQueue * (2 * sizeof(double) + 2 * sizeof(uint32_t)) +
                      2 * (size_t)(S + 1) * (S + 1) * sizeof(double) + (size_t)S * sizeof(Geo) +
                      2 * (size_t)S * sizeof(uint32_t);
     return (b + 15) & ~(size_t)15;
