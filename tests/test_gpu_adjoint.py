@@ -83,6 +83,36 @@ def test_uneven_radii_all_piece_kinds(asora, bb, tau_w, scalar, sweep):
     np.testing.assert_allclose(gq, oq, rtol=1e-5)
 
 
+@pytest.mark.parametrize("sweep", SWEEPS, ids=SWEEP_IDS)
+def test_edges_odd_grid_wrap_clip_and_empty(asora, bb, sweep):
+    """The adjoint on the forward's edge cases: odd N with sources on faces and
+    corners (periodic wrap), radii beyond half the box (extent clip), a
+    duplicate source and R = 0; an even grid with a radius beyond the box;
+    and an empty source list (all gradients zero)."""
+    print("case adjoint edges sweep", sweep, flush=True)
+    for N, ijk, R in ((19, [[0, 0, 0], [18, 18, 18], [0, 9, 18], [5, 5, 5], [5, 5, 5], [12, 0, 7]],
+                       [17.0, 9.5, 12.0, 4.0, 4.0, 0.0]),
+                      (20, [[19, 0, 19], [3, 12, 8], [10, 10, 10]], [26.0, 12.0, 30.0])):
+        w, _, wt = _case("c2", N=N, n_src=len(R), R=(1.0, 2.0))
+        w.src.ijk[:] = ijk
+        w.src.R[:] = R
+        g = oracle.raytrace(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q, w.src.R)
+        gbar = _loss_grad(g, wt)
+        on, ox, oq = oracle.raytrace_grad(w.N, w.cell_cm, bb, w.n_H, w.x_HI, w.src.ijk, w.src.Q,
+                                          w.src.R, gbar)
+        gn, gx, gq = _gpu_backward(asora, w, bb, gbar, sweep=sweep)
+        assert_grad_parity(gn, on, 1e-5, what=f"dL/dn_H N={N}")
+        assert_grad_parity(gx, ox, 1e-5, what=f"dL/dx_HI N={N}")
+        np.testing.assert_allclose(gq, oq, rtol=1e-5)
+    ctx = asora.Asora(w.N, w.cell_cm, bb.P, bb.dP, bb.lg_lo, bb.lg_hi)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    dn, dx, dq = ctx.backward(t(w.n_H), t(w.x_HI), torch.empty(0, 3, dtype=torch.int32, device="cuda"),
+                              torch.empty(0, dtype=torch.float64, device="cuda"),
+                              torch.empty(0, dtype=torch.float32, device="cuda"), t(gbar), R_max=0.0)
+    ctx.check()
+    assert float(dn.abs().max()) == 0.0 and float(dx.abs().max()) == 0.0 and dq.numel() == 0
+
+
 def _covering(w, c):
     d = (np.asarray(c)[None, :] - w.src.ijk + w.N // 2) % w.N - w.N // 2
     return np.nonzero((d ** 2).sum(axis=1) <= w.src.R.astype(np.float64) ** 2)[0]

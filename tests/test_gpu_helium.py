@@ -65,6 +65,16 @@ def test_helium_small_grid_all_radii(asora, bands):
     _check(asora, w, bands)
 
 
+def test_helium_edges_odd_grid_wrap_and_clip(asora, bands):
+    """Odd N, sources on faces and corners (periodic wrap), radii beyond half
+    the box (extent clip), a duplicate source and R = 0."""
+    print("case helium edges N=19", flush=True)
+    w = make_workload("c2", N=19, n_src=6, R=(3.0, 17.0))
+    w.src.ijk[:] = [[0, 0, 0], [18, 18, 18], [0, 9, 18], [5, 5, 5], [5, 5, 5], [12, 0, 7]]
+    w.src.R[:] = [17.0, 9.5, 12.0, 4.0, 4.0, 0.0]
+    _check(asora, w, bands)
+
+
 def test_helium_c2_subset(asora, bands):
     print("case helium 128^3 subset of 12 sources, R=30", flush=True)
     w = make_workload("c2")
