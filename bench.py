@@ -54,8 +54,11 @@ ADJ_BYTES_PER_SV = 32.0   # n_H + x_HI (2 x FP32), dL/dGamma (FP64), dL/dn_HI re
 # coefficients per cell with a rate come on top; their count depends on the
 # field)
 REC_BYTES_PER_CELL = 8.0
+# the sweep kernels' sources and the plans that size their launches (waves,
+# LDS, the table of square roots): counters taken on other versions are not used
 KERNEL_SOURCES = ["paper_2311_01492_amd/csrc/asora_dev.h", "paper_2311_01492_amd/csrc/asora_fwd.hip",
-                  "paper_2311_01492_amd/csrc/asora_adj.hip"]
+                  "paper_2311_01492_amd/csrc/asora_adj.hip", "paper_2311_01492_amd/csrc/asora_internal.h",
+                  "paper_2311_01492_amd/csrc/asora_api.hip"]
 # sweep kernels of each pass (one dispatch per piece kind up to the largest
 # radius; the kinds without sources return at once)
 KERNELS = {"fwd": ("fwd_wave", "fwd_layer"), "adj": ("adj_wave", "adj_layer")}
