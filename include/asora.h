@@ -486,7 +486,8 @@ asora_status asora_set_tune_progress(asora_ctx *ctx, asora_tune_progress_fn fn, 
 
 /*
  * asora_tuning_save / asora_tuning_load -- keep autotuner results across
- * processes (the survey's tuning cache; the search itself is asora_autotune).
+ * processes, so that a workload tuned once is not searched again (the search
+ * itself is asora_autotune).
  * The file is text, one line per key: the key of asora_autotune and eight
  * numbers (R_whole R_oct max_waves pyramid_sweep table_place adj_waves
  * adj_rate best_ms); lines starting with '#' are comments.
