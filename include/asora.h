@@ -196,7 +196,9 @@ asora_status asora_raytrace(asora_ctx *ctx, const float *n_H, const float *x_HI,
  * 8.6 MiB, which every device the library runs on holds until the process
  * ends; the tables and parameters come from the context as asora_init made
  * them.  Limits: N <= 64 and n_src <= 65536; larger calls return ASORA_EINVAL
- * before anything is enqueued.  The caller passes every input and output as
+ * before anything is enqueued; on devices numbered 64 and above the call
+ * returns ASORA_ESTATE (the library keeps the array's address for devices
+ * 0 to 63).  The caller passes every input and output as
  * for asora_raytrace (same arguments and meaning).
  *   flags        ASORA_ACCUMULATE | ASORA_PLAIN | ASORA_PROFILE |
  *                ASORA_EARLY_EXIT (not ASORA_STORE: kept records need memory).

@@ -346,7 +346,7 @@ extern "C" asora_status asora_init(asora_ctx **out, int32_t N, double cell_cm, d
     if (fwd_configure(c->max_lds) != hipSuccess || adj_configure(c->max_lds) != hipSuccess ||
         he_configure(c->max_lds) != hipSuccess)
         return bail(fail(nullptr, ASORA_EHIP, "asora_init: kernel attribute setup failed"));
-    {
+    if (device < kMaxDevices) {   // beyond, the context works without asora_raytrace_static
         const hipError_t e = device_scratch(device, &c->d_static);
         if (e != hipSuccess)
             return bail(fail(nullptr, ASORA_EHIP, "asora_init: hipGetSymbolAddress of the static scratch: %s",
