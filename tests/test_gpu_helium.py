@@ -75,6 +75,31 @@ def test_helium_edges_odd_grid_wrap_and_clip(asora, bands):
     _check(asora, w, bands)
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_helium_random_cases(asora, bands, seed):
+    """Seeded random small cases: grid size (odd and even), source positions,
+    radii up to beyond half the box, helium abundance and ionization drawn
+    per cell (x_HeI independent of x_HI), batched and plain."""
+    rng = np.random.default_rng(8000 + seed)
+    N = int(rng.integers(9, 37))
+    n_src = int(rng.integers(1, 7))
+    w = make_workload("c2", N=N, n_src=n_src, R=(0.5, 1.0), seed=8100 + seed)
+    w.src.ijk[:] = rng.integers(0, N, size=(n_src, 3)).astype(np.int32)
+    w.src.R[:] = rng.uniform(0.0, 0.75 * N, size=n_src).astype(np.float32)
+    n_He = (w.n_H * rng.uniform(0.05, 0.12, size=w.n_H.shape)).astype(np.float32)
+    x_He = rng.uniform(1e-4, 1.0, size=w.x_HI.shape).astype(np.float32)
+    print(f"case helium random seed={seed} N={N} n_src={n_src}", flush=True)
+    ctx = _ctx(asora, w, bands)
+    oH, oHe = oracle.raytrace_helium(w.N, w.cell_cm, bands, w.n_H, w.x_HI, n_He, x_He, w.src.ijk, w.src.Q,
+                                     w.src.R)
+    gH, gHe = ctx.raytrace_helium(_t(w.n_H), _t(w.x_HI), _t(n_He), _t(x_He), _t(w.src.ijk), _t(w.src.Q),
+                                  _t(w.src.R), plain=bool(seed & 1))
+    ctx.check()
+    assert_parity(gH.cpu().numpy(), oH, TOL, what=f"Gamma_HI seed={seed}")
+    assert_parity(gHe.cpu().numpy(), oHe, TOL, what=f"Gamma_HeI seed={seed}")
+    ctx.close()
+
+
 def test_helium_c2_subset(asora, bands):
     print("case helium 128^3 subset of 12 sources, R=30", flush=True)
     w = make_workload("c2")
