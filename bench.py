@@ -78,10 +78,35 @@ WORKLOADS = {
 PLAIN_FRACTION, PLAIN_MIN = 0.01, 1000
 
 
-def kernel_sha() -> str:
+def _code_only(text: str) -> str:
+    """C++ source without comments and whitespace: what the compiler sees,
+    so that edits of the prose alone keep the profiles' hash."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if text.startswith("//", i):
+            i = text.find("\n", i)
+            i = n if i < 0 else i
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        elif c in "\"'":   # string or character literal, kept as written
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            if not c.isspace():
+                out.append(c)
+            i += 1
+    return "".join(out)
+
+
+def kernel_sha(root: str = ROOT) -> str:
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, f), "rb").read())
+        h.update(_code_only(open(os.path.join(root, f), encoding="utf-8").read()).encode())
     return h.hexdigest()[:16]
 
 

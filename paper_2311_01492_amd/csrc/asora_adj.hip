@@ -628,7 +628,8 @@ __global__ __launch_bounds__(64 * MAXW) void adj_layer(AdjArgs A)
     constexpr int TYPE = 3, npieces = 24;
     if (A.seg[TYPE + 1] == A.seg[TYPE]) return;   // no sources of this kind
     const TabNode *T = A.tab;
-    // the work-group's table of square roots (used by (F))
+    // the work-group's table of square roots, when the launch gives one
+    // (every pass takes a cell's root from it)
     double *sq = (double *)smem;
     for (int k = threadIdx.x; k < A.sq_n; k += blockDim.x) sq[k] = sqrt((double)k);
     __syncthreads();

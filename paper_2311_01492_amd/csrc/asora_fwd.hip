@@ -575,8 +575,9 @@ __device__ void sweep_layer_piece(const FwdArgs &A, const TabNode *T, const doub
 
 // TLDS: the table is copied to LDS once per work-group; otherwise the rate
 // batches read it through the caches, which leaves the LDS to more waves.
-// The work-group also holds the table of square roots; every wave its own
-// region (rate queue, layer buffer, per-layer and per-pyramid tables).
+// The work-group also holds the table of square roots when the launch gives
+// one (sq_n > 0: the plan adds it only where it costs no wave); every wave
+// its own region (rate queue, layer buffer, per-layer and per-pyramid tables).
 template <bool KEEP, bool TLDS, bool HEAT>
 __device__ __forceinline__ void fwd_layer_body(const FwdArgs &A, char *smem)
 {

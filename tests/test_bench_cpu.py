@@ -26,3 +26,14 @@ def test_lattice_counts_clipped_by_the_periodic_extent(N):
     radii = np.array([0.0, 1.0, 2.5, 3.9, 6.0, 11.5, 40.0], np.float32)
     assert bench.lattice_voxels(radii, N) == sum(_brute(r, N) for r in radii)
     assert bench.lattice_voxels(np.array([], np.float32), N) == 0
+
+
+def test_kernel_hash_ignores_comments_only():
+    """The profiles' kernel hash covers what the compiler sees: comments and
+    whitespace do not change it, code and string literals do."""
+    import bench
+    a = "int f(int x) { return x + 1; } // one\n/* two */"
+    b = "int  f(int x)\n{\n  // other words\n  return x + 1;   /* c */\n}"
+    assert bench._code_only(a) == bench._code_only(b)
+    assert bench._code_only(a) != bench._code_only(a.replace("+ 1", "+ 2"))
+    assert bench._code_only('s = "// not a comment";') == 's="//notacomment";'.replace("notacomment", "not a comment")
