@@ -36,4 +36,4 @@ def test_kernel_hash_ignores_comments_only():
     b = "int  f(int x)\n{\n  // other words\n  return x + 1;   /* c */\n}"
     assert bench._code_only(a) == bench._code_only(b)
     assert bench._code_only(a) != bench._code_only(a.replace("+ 1", "+ 2"))
-    assert bench._code_only('s = "// not a comment";') == 's="//notacomment";'.replace("notacomment", "not a comment")
+    assert bench._code_only('s = "// not a comment";') == 's="// not a comment";'
